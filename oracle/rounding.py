@@ -1,0 +1,82 @@
+"""Bit-level rounding emulators for the reduced storage formats.
+
+TEST INFRASTRUCTURE ONLY (see ofrr_oracle.py).  Written from the IEEE-754 /
+OCP format definitions; round-to-nearest, ties to even, for every
+conversion (the paper does not name a rounding mode; RNE is the IEEE
+default).
+
+* bfloat16: the upper 16 bits of an FP32 word (8 exponent bits, 7 stored
+  mantissa bits).
+* float16: IEEE binary16 (numpy's own conversion is RNE).
+* float8 e4m3fn (OCP 8-bit floating point): 1 sign, 4 exponent (bias 7),
+  3 mantissa bits, no infinities, S.1111.111 is NaN, largest finite 448,
+  subnormals m/8 * 2^-6; out-of-range values saturate to +-448.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def f32_to_bf16_bits(x) -> np.ndarray:
+    """FP32 -> bfloat16 bit patterns (uint16), round to nearest even."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    nan = np.isnan(f)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) & 0xFFFF
+    r = np.where(nan, (u >> 16) | 0x0040, r)  # keep NaN quiet
+    return r.astype(np.uint16)
+
+
+def bf16_bits_to_f32(bits) -> np.ndarray:
+    b = np.ascontiguousarray(bits, dtype=np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32)
+
+
+def round_bf16(x) -> np.ndarray:
+    """Round to bfloat16 and return the value as FP32 (shape kept)."""
+    x = np.asarray(x, dtype=np.float32)
+    return bf16_bits_to_f32(f32_to_bf16_bits(x).ravel(order="K")).reshape(x.shape)
+
+
+def round_f16(x) -> np.ndarray:
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float32)
+
+
+def _e4m3_table():
+    """All 127 non-negative finite e4m3fn values, ascending, with codes."""
+    codes = np.arange(0, 0x7F, dtype=np.int64)  # 0x7F is NaN
+    e = codes >> 3
+    m = codes & 7
+    val = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * 2.0 ** (e - 7.0))
+    return val, codes
+
+
+_E4M3_VAL, _E4M3_CODE = _e4m3_table()
+E4M3_MAX = float(_E4M3_VAL[-1])  # 448
+
+
+def f32_to_e4m3_bits(x) -> np.ndarray:
+    """FP32 -> e4m3fn codes (uint8), nearest value, ties to the even code,
+    saturating to +-448; NaN -> 0x7F."""
+    f = np.asarray(x, dtype=np.float64)
+    a = np.abs(f)
+    sign = (np.signbit(f)).astype(np.uint8) << 7
+    a_sat = np.minimum(a, E4M3_MAX)
+    hi = np.searchsorted(_E4M3_VAL, a_sat, side="left")
+    hi = np.clip(hi, 0, _E4M3_VAL.size - 1)
+    lo = np.clip(hi - 1, 0, _E4M3_VAL.size - 1)
+    dlo = a_sat - _E4M3_VAL[lo]
+    dhi = _E4M3_VAL[hi] - a_sat
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (_E4M3_CODE[hi] % 2 == 0))
+    code = np.where(pick_hi, _E4M3_CODE[hi], _E4M3_CODE[lo]).astype(np.uint8)
+    code = np.where(np.isnan(f), np.uint8(0x7F), code | sign)
+    return code.astype(np.uint8)
+
+
+def e4m3_bits_to_f32(bits) -> np.ndarray:
+    b = np.asarray(bits, dtype=np.uint8).astype(np.int64)
+    mag = b & 0x7F
+    out = np.where(mag == 0x7F, np.nan, _E4M3_VAL[np.minimum(mag, 0x7E)])
+    out = np.where(b & 0x80, -out, out)
+    return out.astype(np.float32)

@@ -1,0 +1,346 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix:
+closed forms, textbook/library special cases, invariants, brute force and
+hand-worked fixtures.  A plausible slip anywhere in the oracle (a wrong
+rotation sign, a dropped re-orthogonalisation, a transposed factor, a wrong
+pivot rule) fails at least one of these."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_sym(n, seed):
+    g = np.random.default_rng(seed).standard_normal((n, n))
+    return g + g.T
+
+
+def _prescribed(lam, seed):
+    return W.dense_symmetric_prescribed(lam, seed).numpy()
+
+
+# --------------------------------------------------------------- Jacobi ----
+
+def test_jacobi_2x2_closed_form(oracle):
+    a, b, d = 3.0, -1.25, 0.5
+    w, Z = oracle.jacobi_eig([[a, b], [b, d]])
+    m, r = (a + d) / 2, math.hypot((a - d) / 2, b)
+    np.testing.assert_allclose(w, [m - r, m + r], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Z.T @ Z, np.eye(2), atol=1e-15)
+
+
+def test_jacobi_prescribed_spectrum(oracle):
+    lam = 0.95 ** np.arange(1, 65)
+    A = _prescribed(lam, 7)
+    w, Z = oracle.jacobi_eig(A)
+    np.testing.assert_allclose(w, np.sort(lam), rtol=0, atol=2e-15 * 64)
+    np.testing.assert_allclose(A @ Z, Z * w, atol=1e-14)
+    np.testing.assert_allclose(Z.T @ Z, np.eye(64), atol=1e-14)
+
+
+def test_jacobi_matches_lapack(oracle):
+    S = _rand_sym(80, 3)
+    w, Z = oracle.jacobi_eig(S)
+    np.testing.assert_allclose(w, np.linalg.eigvalsh(S), rtol=0, atol=1e-13 * np.abs(w).max())
+
+
+def test_jacobi_laplacian_closed_form(oracle):
+    rp, ci, v = W.laplacian_2d_csr(8, dtype=np.float64)
+    n = 64
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    w, _ = oracle.jacobi_eig(A)
+    np.testing.assert_allclose(w, W.laplacian_2d_eigenvalues(8), rtol=0, atol=1e-13)
+
+
+def test_jacobi_degenerate(oracle):
+    w, Z = oracle.jacobi_eig(np.diag([3.0, -1.0, 2.0]))
+    np.testing.assert_array_equal(w, [-1.0, 2.0, 3.0])
+    np.testing.assert_array_equal(np.abs(Z), np.eye(3)[:, [1, 2, 0]])
+    w, Z = oracle.jacobi_eig(np.zeros((4, 4)))
+    np.testing.assert_array_equal(w, 0.0)
+
+
+# ----------------------------------------------------- Cholesky / MGS2 ----
+
+def test_cholesky_matches_lapack(oracle):
+    g = np.random.default_rng(1).standard_normal((30, 30))
+    G = g @ g.T + 30 * np.eye(30)
+    np.testing.assert_allclose(oracle.cholesky(G), np.linalg.cholesky(G), atol=1e-13)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(-np.eye(3))
+
+
+def test_mgs2_qr(oracle):
+    X = np.random.default_rng(2).standard_normal((300, 12))
+    Q, R = oracle.mgs2(X)
+    np.testing.assert_allclose(Q @ R, X, atol=1e-13)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(12), atol=1e-14)
+    # same factor as Householder QR up to column signs
+    Qh, Rh = np.linalg.qr(X)
+    np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(Rh)), rtol=1e-12)
+    assert np.all(np.diag(R) > 0)
+
+
+def test_mgs2_reorthogonalises_ill_conditioned(oracle):
+    # columns of a Vandermonde-type matrix: kappa ~ 1e12; one MGS pass would
+    # lose orthogonality to ~1e-4, the sqrt(2)/2 re-orthogonalisation keeps it
+    t = np.linspace(0, 1, 400)
+    X = np.stack([t ** j for j in range(10)], axis=1)
+    Q, R = oracle.mgs2(X)
+    assert np.abs(Q.T @ Q - np.eye(10)).max() < 1e-13
+    np.testing.assert_allclose(Q @ R, X, atol=1e-13)
+
+
+# ----------------------------------------------------------- Hessenberg ----
+
+def _read_golden_hess():
+    rows = [l.strip() for l in open(os.path.join(GOLDEN, "hessenberg_4x3.txt"))
+            if l.strip() and not l.startswith("#")]
+    i = rows.index("Q")
+    Q = np.array([[float(x) for x in r.split()] for r in rows[i + 1:i + 5]])
+    piv = np.array([int(x) for x in rows[rows.index("piv") + 1].split()])
+    j = rows.index("U")
+    U = np.array([[float(x) for x in r.split()] for r in rows[j + 1:j + 4]])
+    return Q, piv, U
+
+
+def test_hessenberg_hand_worked_example(oracle):
+    Y = np.array([[1, 2, 1], [4, 2, 0], [2, 4, 1], [-2, 0, 3]], dtype=float)
+    Qe, pe, Ue = _read_golden_hess()
+    for prec in ("f64", "f32"):
+        Q, piv, keep, U = oracle.hessenberg(Y, 1e-12, prec, want_u=True)
+        np.testing.assert_array_equal(piv, pe)
+        np.testing.assert_array_equal(keep, 1)
+        tol = 1e-15 if prec == "f64" else 1e-7
+        np.testing.assert_allclose(Q, Qe, atol=tol)
+        np.testing.assert_allclose(U, Ue, atol=tol * 4)
+
+
+def test_hessenberg_equals_row_pivoted_lu(oracle):
+    # Sec. 4.2: the Hessenberg output is P^T L of PA = LU with row pivoting
+    X = np.random.default_rng(5).random((500, 24))
+    Q, piv, keep = oracle.hessenberg(X, 2.2e-16)
+    P, L, U = sla.lu(X)
+    np.testing.assert_allclose(Q, P @ L, atol=1e-13)
+    # pivot rows are where the permutation puts rows 0..k-1
+    perm = np.argmax(P, axis=0)
+    np.testing.assert_array_equal(piv, perm[:24])
+
+
+def test_hessenberg_structure(oracle):
+    X = np.random.default_rng(6).standard_normal((300, 16))
+    Q, piv, keep, U = oracle.hessenberg(X, 1e-12, want_u=True)
+    assert keep.all()
+    for j in range(16):
+        assert Q[piv[j], j] == 1.0
+        assert np.all(Q[piv[:j], j] == 0.0)
+    assert np.abs(Q).max() <= 1.0
+    np.testing.assert_allclose(Q @ U, X, atol=1e-13)
+    assert np.allclose(np.tril(U, -1), 0)
+
+
+def test_hessenberg_drops_dependent_columns(oracle):
+    X = np.random.default_rng(8).standard_normal((200, 5))
+    X[:, 2] = X[:, 0] - 2 * X[:, 1]
+    X[:, 4] = 0.0
+    Xs = X / np.abs(X).max(axis=0, initial=0, where=np.ones_like(X, bool)).clip(1e-300)
+    Q, piv, keep = oracle.hessenberg(Xs, 2.2e-16 * 64)
+    np.testing.assert_array_equal(keep, [1, 1, 0, 1, 0])
+    np.testing.assert_array_equal(piv[[2, 4]], -1)
+    Qk = Q[:, keep == 1]
+    assert oracle.subspace_sin(Qk, X[:, [0, 1, 3]]) < 1e-12
+
+
+def test_hessenberg_tie_takes_first_index(oracle):
+    Y = np.array([[1.0, 0.3], [-2.0, 1.0], [2.0, 5.0]])
+    _, piv, _ = oracle.hessenberg(Y, 1e-12)
+    assert piv[0] == 1
+
+
+def test_hessenberg_f32_agrees_with_f64(oracle):
+    X = np.random.default_rng(9).random((2000, 32)).astype(np.float32)
+    Q64, p64, _ = oracle.hessenberg(X.astype(np.float64), 1e-7)
+    Q32, p32, _ = oracle.hessenberg(X, 1e-7, "f32")
+    np.testing.assert_array_equal(p32, p64)
+    np.testing.assert_allclose(Q32, Q64, atol=2e-4)
+
+
+# --------------------------------------------------------------- pencils ---
+
+def test_sym_pencil_matches_lapack_and_basis_invariance(oracle):
+    rng = np.random.default_rng(11)
+    A = _rand_sym(120, 12)
+    Qo, _ = np.linalg.qr(rng.standard_normal((120, 10)))
+    R = np.triu(rng.standard_normal((10, 10))) + 5 * np.eye(10)
+    V = Qo @ R  # non-orthogonal basis of the same subspace
+    H, G = V.T @ A @ V, V.T @ V
+    theta, Y = oracle.sym_pencil_eig(H, G)
+    np.testing.assert_allclose(theta, sla.eigh(H, G, eigvals_only=True), rtol=1e-11, atol=1e-12)
+    # Galerkin condition depends only on the subspace (eq. (geig))
+    np.testing.assert_allclose(theta, np.linalg.eigvalsh(Qo.T @ A @ Qo), atol=1e-11)
+    np.testing.assert_allclose(Y.T @ G @ Y, np.eye(10), atol=1e-11)
+    np.testing.assert_allclose(H @ Y, G @ Y * theta, atol=1e-10)
+
+
+def test_svd_pencil_theorem(oracle):
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((90, 40))
+    Uo, _ = np.linalg.qr(rng.standard_normal((90, 8)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((40, 6)))
+    U = Uo @ (np.triu(rng.standard_normal((8, 8))) + 3 * np.eye(8))
+    V = Vo @ (np.triu(rng.standard_normal((6, 6))) + 3 * np.eye(6))
+    B, MU, MV = U.T @ A @ V, U.T @ U, V.T @ V
+    s, Y, Z = oracle.svd_pencil(B, MU, MV)
+    # k1 + k2 = 14 eigenvalues: 6 positive, 6 negative (pairs), 2 zero
+    K = np.block([[np.zeros((8, 8)), B], [B.T, np.zeros((6, 6))]])
+    M = sla.block_diag(MU, MV)
+    ev = sla.eigh(K, M, eigvals_only=True)
+    np.testing.assert_allclose(np.sort(ev[ev > 1e-9])[::-1], s, rtol=1e-11)
+    np.testing.assert_allclose(np.sort(-ev[ev < -1e-9])[::-1], s, rtol=1e-11)
+    assert np.sum(np.abs(ev) <= 1e-9) == 2
+    # Theorem: sqrt(2) U Y and sqrt(2) V Z are orthonormal
+    Ut, Vt = np.sqrt(2) * U @ Y, np.sqrt(2) * V @ Z
+    np.testing.assert_allclose(Ut.T @ Ut, np.eye(6), atol=1e-11)
+    np.testing.assert_allclose(Vt.T @ Vt, np.eye(6), atol=1e-11)
+    # equals the classical two-sided projection on orthonormal bases
+    np.testing.assert_allclose(s, np.linalg.svd(Uo.T @ A @ Vo, compute_uv=False), rtol=1e-11)
+
+
+# ------------------------------------------------------------- filters -----
+
+def _cheb_T(d, x):
+    x = np.asarray(x, dtype=float)
+    return np.where(np.abs(x) <= 1, np.cos(d * np.arccos(np.clip(x, -1, 1))),
+                    np.sign(x) ** d * np.cosh(d * np.arccosh(np.abs(x))))
+
+
+def _cheb_plain(A, X, d, lo, hi):
+    c, e = (lo + hi) / 2, (hi - lo) / 2
+    Y0 = X
+    Y1 = (A @ Y0 - c * Y0) / e
+    for _ in range(2, d + 1):
+        Y0, Y1 = Y1, 2 * (A @ Y1 - c * Y1) / e - Y0
+    return Y1
+
+
+def test_chebyshev_scales_eigenvectors_by_T_d(oracle):
+    lam = np.linspace(-1, 3, 40)
+    A = _prescribed(lam, 21)
+    w, Z = np.linalg.eigh(A)
+    lo, hi = -1.0, 1.5
+    for d in (1, 4, 7):
+        Y = _cheb_plain(A, Z, d, lo, hi)
+        gains = np.linalg.norm(Y, axis=0)
+        x = (w - (lo + hi) / 2) / ((hi - lo) / 2)
+        np.testing.assert_allclose(gains, np.abs(_cheb_T(d, x)), rtol=1e-10, atol=1e-12)
+
+
+def test_stabilised_filter_spans_plain_recurrence(oracle):
+    lam = 0.8 ** np.arange(60)
+    A = _prescribed(lam, 22)
+    X = W.uniform_start(60, 6, 3)
+    for basis in ("mgs2", "hessenberg"):
+        Q = oracle.filter_block(oracle.DenseOp(A), X, "chebyshev", 5, 0.0, 0.3, basis=basis)
+        assert oracle.subspace_sin(Q, _cheb_plain(A, X, 5, 0.0, 0.3)) < 1e-10
+        Q = oracle.filter_block(oracle.DenseOp(A), X, "power", 3, basis=basis)
+        assert oracle.subspace_sin(Q, A @ A @ A @ X) < 1e-10
+
+
+def test_csr_product_matches_dense(oracle):
+    rp, ci, v = W.laplacian_2d_csr(12, dtype=np.float64)
+    n = 144
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    assert np.array_equal(A, A.T) and np.all(np.diag(A) == 4)
+    X = np.random.default_rng(4).standard_normal((n, 5))
+    np.testing.assert_allclose(oracle.csr_matmul(rp, ci, v, X), A @ X, atol=1e-14)
+
+
+# ---------------------------------------------------- subspace iteration ---
+
+def test_subspace_eig_prescribed_spectrum_converged(oracle):
+    n = 512
+    lam = 0.95 ** np.arange(1, n + 1)
+    A = _prescribed(lam, 1001)
+    X0 = W.uniform_start(n, 16, 1101)
+    r = oracle.subspace_eig(A, X0, 8, tol=1e-13, anorm=0.95, max_outer=2000)
+    np.testing.assert_allclose(r.theta, lam[:8], rtol=1e-12)
+    assert np.all(r.resid <= 1e-13)
+    # eigenvectors match brute force up to sign
+    w, Z = oracle.jacobi_eig(A)
+    Zt = oracle.normalize_signs(Z[:, ::-1][:, :8])
+    np.testing.assert_allclose(r.X, Zt, atol=1e-10)
+
+
+def test_subspace_eig_basis_invariance_same_step(oracle):
+    # the Hessenberg basis and the orthonormal basis span the same subspace,
+    # so the Ritz values after the same number of steps agree
+    n = 300
+    lam = 0.9 ** np.arange(n)
+    A = _prescribed(lam, 31)
+    X0 = W.uniform_start(n, 10, 32)
+    a = oracle.subspace_eig(A, X0, 5, outer=6)
+    b = oracle.subspace_eig(A, X0, 5, outer=6, basis="hessenberg")
+    np.testing.assert_allclose(a.theta_all, b.theta_all, rtol=1e-12)
+    a = oracle.subspace_eig(A, X0, 5, filt="chebyshev", degree=3, lo=-0.1, hi=0.4, outer=4)
+    b = oracle.subspace_eig(A, X0, 5, filt="chebyshev", degree=3, lo=-0.1, hi=0.4, outer=4,
+                            basis="hessenberg")
+    np.testing.assert_allclose(a.theta_all, b.theta_all, rtol=1e-12)
+
+
+def test_subspace_eig_laplacian_smallest(oracle):
+    N = 20
+    rp, ci, v = W.laplacian_2d_csr(N, dtype=np.float64)
+    ev = W.laplacian_2d_eigenvalues(N)
+    X0 = W.uniform_start(N * N, 16, 5)
+    r = oracle.subspace_eig((rp, ci, v), X0, 6, which="smallest", filt="chebyshev",
+                            degree=10, lo=ev[16], hi=8.0, tol=1e-11, anorm=8.0, max_outer=5000)
+    np.testing.assert_allclose(r.theta, ev[:6], rtol=1e-9)
+
+
+def test_subspace_svd_prescribed(oracle):
+    m, n = 600, 150
+    sig = np.exp(-np.arange(1, n + 1) / 20.0)
+    A = W.svd_prescribed(m, n, sig, 41, dtype=np.float64 and __import__("torch").float64).numpy()
+    V0 = W.uniform_start(n, 12, 42)
+    r = oracle.subspace_svd(A, V0, 6, tol=1e-12, max_outer=500)
+    np.testing.assert_allclose(r.sigma, sig[:6], rtol=1e-11)
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)
+    Vr, Ur = oracle.normalize_signs(Vt[:6].T, U[:, :6])
+    np.testing.assert_allclose(r.V, Vr, atol=1e-8)
+    np.testing.assert_allclose(r.U, Ur, atol=1e-8)
+
+
+# ------------------------------------------------------------- rounding ----
+
+def test_rounding_bit_patterns():
+    from oracle import rounding as R
+    for line in open(os.path.join(GOLDEN, "e4m3_bf16_bits.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        fmt, val, hexv = line.split()
+        if fmt == "bf16":
+            got = int(R.f32_to_bf16_bits(np.float32(val)).ravel()[0])
+        else:
+            got = int(R.f32_to_e4m3_bits(np.float32(val)).ravel()[0])
+        assert got == int(hexv, 16), (fmt, val, hex(got), hexv)
+
+
+def test_rounding_roundtrip_exhaustive_e4m3():
+    from oracle import rounding as R
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], dtype=np.uint8)
+    vals = R.e4m3_bits_to_f32(codes)
+    back = R.f32_to_e4m3_bits(vals)
+    # +0 and -0 are distinct codes with the same value
+    np.testing.assert_array_equal(back, codes)
+    x = np.random.default_rng(0).standard_normal(10000).astype(np.float32) * 10
+    bf = R.round_bf16(x)
+    assert np.all(np.abs(bf - x) <= np.abs(x) * 2.0 ** -8)

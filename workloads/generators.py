@@ -1,0 +1,156 @@
+"""Seeded generators for the synthetic test and benchmark matrices.
+
+Random draws always come from numpy's PCG64 with an explicit seed, so the
+same seed gives the same bits on every machine; the heavy assembly (QR of a
+Gaussian matrix, Q diag(lam) Q^T) runs through torch on the requested
+device, which is plain input preparation and no part of the eigensolver.
+
+Dense matrices are returned as torch tensors in column-major layout
+(stride (1, rows)); for symmetric matrices that is the same memory as
+row-major.  Start blocks are U(0,1) drawn in FP64, as in the paper's
+experiments (Sec. 5.2: random initial blocks drawn from U(0,1) in FP64 and
+cast to the working precision).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _normal(shape, seed: int) -> np.ndarray:
+    return rng(seed).standard_normal(size=shape, dtype=np.float64)
+
+
+def haar_orthogonal(n: int, seed: int, cols: int | None = None,
+                    device: str | torch.device = "cpu") -> torch.Tensor:
+    """Q from the QR factorisation of a seeded N(0,1) n x cols matrix, with
+    the column signs fixed so that diag(R) > 0 (this makes Q Haar
+    distributed).  Returned as an FP64 tensor on `device`."""
+    cols = n if cols is None else cols
+    g = torch.from_numpy(_normal((n, cols), seed)).to(device)
+    q, r = torch.linalg.qr(g, mode="reduced")
+    d = torch.sign(torch.diagonal(r))
+    d[d == 0] = 1.0
+    return q * d.unsqueeze(0)
+
+
+def goe_noise(n: int, scale: float, seed: int,
+              device: str | torch.device = "cpu") -> torch.Tensor:
+    """Symmetric Gaussian noise E = scale * (G + G^T) / sqrt(2), G ~ N(0,1)."""
+    g = torch.from_numpy(_normal((n, n), seed)).to(device)
+    return (g + g.T) * (scale / math.sqrt(2.0))
+
+
+def dense_symmetric_prescribed(lam, seed: int, noise_scale: float = 0.0,
+                               noise_seed: int | None = None,
+                               dtype=torch.float64,
+                               device: str | torch.device = "cpu") -> torch.Tensor:
+    """A = Q diag(lam) Q^T (+ optional symmetric noise), assembled in FP64 and
+    stored in `dtype` (the stored array is the matrix of record)."""
+    lam = torch.as_tensor(np.asarray(lam, dtype=np.float64), device=device)
+    n = lam.numel()
+    q = haar_orthogonal(n, seed, device=device)
+    a = (q * lam.unsqueeze(0)) @ q.T
+    del q
+    a = (a + a.T) * 0.5
+    if noise_scale:
+        a += goe_noise(n, noise_scale, seed if noise_seed is None else noise_seed,
+                       device=device)
+    return a.to(dtype).contiguous()
+
+
+def svd_prescribed(m: int, n: int, sigma, seed: int, dtype=torch.float32,
+                   device: str | torch.device = "cpu") -> torch.Tensor:
+    """A = U diag(sigma) V^T with U (m x n) and V (n x n) Haar orthonormal,
+    assembled in FP64 and stored column-major in `dtype`."""
+    sigma = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    u = haar_orthogonal(m, seed, cols=n, device=device)
+    v = haar_orthogonal(n, seed + 7, device=device)
+    # A^T = V diag(sigma) U^T stored row-major is A stored column-major.
+    at = (v * sigma.unsqueeze(0)) @ u.T
+    del u, v
+    return at.to(dtype).contiguous().T
+
+
+def laplacian_2d_csr(N: int, dtype=np.float32):
+    """Dirichlet 5-point Laplacian on an N x N grid, lexicographic ordering
+    (row = x + N*y), diagonal 4 and -1 to every existing neighbour, CSR with
+    sorted int32 column indices.  Returns (row_ptr, col_idx, values)."""
+    n = N * N
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % N
+    y = idx // N
+    cols = []
+    vals = []
+    # neighbours in increasing column order: y-1, x-1, self, x+1, y+1
+    for dc, ok, v in ((-N, y > 0, -1.0), (-1, x > 0, -1.0), (0, np.ones(n, bool), 4.0),
+                      (1, x < N - 1, -1.0), (N, y < N - 1, -1.0)):
+        c = np.where(ok, idx + dc, -1)
+        cols.append(c)
+        vals.append(np.where(ok, v, 0.0))
+    cols = np.stack(cols, axis=1)
+    vals = np.stack(vals, axis=1)
+    mask = cols >= 0
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col_idx = cols[mask].astype(np.int32)
+    values = vals[mask].astype(dtype)
+    return row_ptr.astype(np.int32), col_idx, values
+
+
+def laplacian_2d_eigenvalues(N: int) -> np.ndarray:
+    """All eigenvalues of the N x N-grid Dirichlet 5-point Laplacian
+    (textbook closed form 4 - 2 cos(p pi/(N+1)) - 2 cos(q pi/(N+1))),
+    sorted ascending."""
+    t = 2.0 - 2.0 * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    return np.sort((t[:, None] + t[None, :]).ravel())
+
+
+def uniform_start(n: int, b: int, seed: int) -> np.ndarray:
+    """U(0,1) start block in FP64, column-major (Fortran order)."""
+    return np.asfortranarray(rng(seed).random(size=(n, b), dtype=np.float64))
+
+
+def batched_sizes(seed: int, count: int = 512, lo: int = 256, hi: int = 4096) -> np.ndarray:
+    return rng(seed).integers(lo, hi + 1, size=count)
+
+
+@dataclass
+class Workload:
+    name: str
+    kind: str
+    params: dict = field(default_factory=dict)
+
+
+# The five benchmark/parity configurations (seed = 1000 + index, start
+# block seed = 1100 + index).
+WORKLOADS = {
+    "dense_sym_n512_power": Workload(
+        "dense_sym_n512_power", "eig_dense",
+        dict(n=512, lam="0.95**i (i=1..n)", k=8, basis=16, degree=1, filter="power",
+             outer=20, seed=1001, x0_seed=1101, dtype="f64")),
+    "dense_sym_n16384_cheb4": Workload(
+        "dense_sym_n16384_cheb4", "eig_dense",
+        dict(n=16384, lam="i**-1.5 (i=1..n)", noise=1e-3, k=64, basis=128, degree=4,
+             filter="chebyshev", seed=1002, x0_seed=1102, dtype="f32")),
+    "dense_svd_65536x8192": Workload(
+        "dense_svd_65536x8192", "svd_dense",
+        dict(m=65536, n=8192, sigma="exp(-i/200)", k=100, basis=200, seed=1003,
+             x0_seed=1103, dtype="f32")),
+    "laplacian2d_1024": Workload(
+        "laplacian2d_1024", "eig_csr",
+        dict(N=1024, k=32, basis=64, degree=20, filter="chebyshev", which="smallest",
+             seed=1004, x0_seed=1104)),
+    "batched_512": Workload(
+        "batched_512", "eig_batched",
+        dict(count=512, nlo=256, nhi=4096, lam="0.9**i", k=8, basis=16, seed=1005,
+             x0_seed=1105)),
+}
