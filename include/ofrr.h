@@ -1,0 +1,275 @@
+/*
+ * ofrr.h -- C ABI of the MI355X (gfx950) orthogonalization-free
+ * Rayleigh-Ritz library.
+ *
+ * Method: Xu, Zhang, Chen, Saad and Xi, "Mixed Precision
+ * Orthogonalization-Free Projection Methods for Eigenvalue and Singular
+ * Value Problems" (arXiv 2505.00281).  A few eigenpairs of a symmetric A
+ * (or singular triplets of a rectangular A) are computed by subspace
+ * iteration whose basis is built in reduced precision without inner
+ * products (per-column scaling and the Hessenberg process, Sec. 4.2),
+ * projected in higher precision (G = V^T V, H = V^T A V, eq. (geig)), and
+ * extracted from the small generalized eigenproblem in FP64 (Sec. 3, the
+ * mixed-precision plan at the end of Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *   - Dense matrices are column-major with a leading dimension (ld >= rows).
+ *   - Every array argument is a DEVICE pointer on the context's device,
+ *     owned by the caller, unless the comment says "host".  Inputs are
+ *     read-only; outputs are overwritten.  Nothing is retained after a call
+ *     returns.
+ *   - Every call is enqueued on the context's HIP stream and returns once
+ *     its outputs are ready (the call synchronises that stream).
+ *   - A negative status is a failure: outputs are undefined and
+ *     ofrr_last_error() describes it.  Arguments are validated before any
+ *     device work; invalid ones give OFRR_ERR_INVALID_ARG and touch
+ *     nothing.  No C++ exception crosses this boundary.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef OFRR_H
+#define OFRR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ofrr_ctx_s *ofrr_ctx;
+
+typedef enum {
+    OFRR_OK = 0,
+    OFRR_NOT_CONVERGED = 1,     /* warning: outputs valid, fewer than k pairs met tol */
+    OFRR_ERR_INVALID_ARG = -1,
+    OFRR_ERR_UNSUPPORTED = -2,  /* valid but not implemented combination */
+    OFRR_ERR_NO_DEVICE = -3,
+    OFRR_ERR_OOM = -4,
+    OFRR_ERR_HIP = -5,          /* a HIP runtime call failed */
+    OFRR_ERR_NUMERIC = -6       /* NaN/Inf met, or every basis column dropped */
+} ofrr_status;
+
+typedef enum { OFRR_DENSE_COLMAJOR = 0, OFRR_CSR = 1 } ofrr_format;
+
+typedef enum {
+    OFRR_F64 = 0,
+    OFRR_F32 = 1,
+    OFRR_BF16 = 2,
+    OFRR_F16 = 3,
+    OFRR_F8E4M3 = 4   /* OCP e4m3fn with one power-of-two scale per 32 x 32 block */
+} ofrr_dtype;
+
+typedef enum { OFRR_LARGEST = 0, OFRR_SMALLEST = 1 } ofrr_which;
+typedef enum { OFRR_POWER = 0, OFRR_CHEBYSHEV = 1 } ofrr_filter;
+
+/* Accumulation of the projections G = V^T V, H = V^T W (Sec. 4, mixed-
+ * precision plan: reduced-precision inputs, higher-precision products). */
+typedef enum {
+    OFRR_ACC_F32 = 0,             /* FP32 sums */
+    OFRR_ACC_F32_COMPENSATED = 1, /* FP32 sums over row chunks, FP64 across chunks */
+    OFRR_ACC_F64 = 2              /* FP64 sums */
+} ofrr_accum;
+
+/* Matrix descriptor.  Dense: values (rows x cols, column-major, ld).
+ * CSR: 0-based row_ptr[rows+1] and col_idx[nnz] sorted within each row,
+ * values[nnz].  values are FP64 or FP32 (dtype).  Symmetry of A is assumed
+ * by the eigenvalue entry points, not checked. */
+typedef struct {
+    ofrr_format format;
+    ofrr_dtype dtype;
+    int64_t rows, cols, ld;
+    const void *values;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    int64_t nnz;
+} ofrr_matrix;
+
+/* Precision plan and iteration controls.  Fill with ofrr_plan_default(). */
+typedef struct {
+    ofrr_dtype basis_dtype;  /* storage/compute type of the products and the basis in
+                                the first phase: F64 gives the FP64 form of the method
+                                (all FP64); F32, BF16, F16, F8E4M3 the mixed forms */
+    ofrr_accum gram_accum;   /* accumulation of G and H in the first phase */
+    int32_t refine;          /* 0: one phase in basis_dtype; 1: first phase until its
+                                residual estimate stalls, then an FP64 tail */
+    ofrr_filter filter;
+    int32_t degree;          /* products per outer iteration (power steps or
+                                Chebyshev degree), >= 1 */
+    double lo, hi;           /* Chebyshev damping interval [lo, hi], lo < hi */
+    double drop_tol;         /* Hessenberg column drop tolerance on |pivot| of a column
+                                scaled to infinity-norm (1/2, 1]; 0 -> unit roundoff of
+                                the basis storage type (Sec. 5.2) */
+    double tol;              /* stop when all k relative residuals <= tol; 0 -> run
+                                exactly max_iters outer iterations */
+    double anorm;            /* residual normaliser ||A||_2; 0 -> max |Ritz value| */
+    int32_t max_iters;       /* outer iterations cap (>= 1) */
+    int32_t stall_iters;     /* refine=1: leave the first phase after this many outer
+                                iterations without a 2x residual improvement */
+    double switch_resid;     /* refine=1: also leave it once the largest wanted residual
+                                estimate is below this value (0 -> never by value) */
+    int32_t b_split;         /* BF16/F16 products: 2 carries the basis block as a two-
+                                term split (hi + lo) through the MFMA, 1 rounds it once */
+    int32_t profile;         /* nonzero: time every kernel launch with HIP events */
+} ofrr_plan;
+
+typedef struct {
+    int32_t iters;           /* outer iterations done */
+    int32_t iters_low;       /* of which in the first (reduced-precision) phase */
+    int32_t n_converged;     /* wanted pairs with final residual <= tol */
+    int32_t basis_eff;       /* columns kept by the last Hessenberg sweep */
+    int32_t products;        /* block products by A (or A^T) */
+    double max_resid;        /* largest final residual among the k pairs */
+    double seconds;          /* device time of the call (HIP events on the stream) */
+} ofrr_info;
+
+/* --------------------------------------------------------------------- */
+/* Context                                                                */
+/* --------------------------------------------------------------------- */
+
+/* Defaults: FP64 basis, FP64 accumulation, no refinement, power filter of
+ * degree 1, drop_tol 0, tol 0, anorm 0, max_iters 20, stall_iters 3,
+ * switch_resid 0, b_split 1, profile 0. */
+void ofrr_plan_default(ofrr_plan *plan);
+
+/* Creates a context bound to `device` and to `hip_stream` (a hipStream_t,
+ * NULL = the default stream).  The context owns a workspace that grows to
+ * the largest problem seen and is reused; it is freed by ofrr_destroy.
+ * Errors: OFRR_ERR_NO_DEVICE if no HIP device `device` is visible. */
+ofrr_status ofrr_create(ofrr_ctx *ctx, int device, void *hip_stream);
+ofrr_status ofrr_destroy(ofrr_ctx ctx);
+
+/* Message of the last failure on this context (or of the last failed
+ * ofrr_create when ctx is NULL); valid until the next call. */
+const char *ofrr_last_error(ofrr_ctx ctx);
+
+/* Kernel timing (plan.profile != 0): number of launches and summed device
+ * milliseconds of the kernel family `name` since the last reset, measured
+ * with HIP events on the context's stream.  Families: "quantize",
+ * "product_bf16", "product_f16", "product_f8", "product_f64", "product_f32",
+ * "spmm", "scale", "hessenberg", "gram", "small_eig", "lift",
+ * "residual".  Returns OFRR_ERR_INVALID_ARG for an unknown name. */
+ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches /*host*/,
+                              double *total_ms /*host*/);
+ofrr_status ofrr_kernel_stats_reset(ofrr_ctx ctx);
+
+/* --------------------------------------------------------------------- */
+/* Whole-method entry points (Sec. 2-4)                                   */
+/* --------------------------------------------------------------------- */
+
+/* k eigenpairs of a symmetric A (rows == cols == n) by subspace iteration
+ * with a basis of `basis` columns (k <= basis <= n), the filter of `plan`
+ * (Alg. "Multiple Step Subspace Iteration" with restart from all Ritz
+ * vectors), the Hessenberg process in place of QR (Sec. 4.2) and the
+ * orthogonalization-free projection (Sec. 3.1, eq. (geig)).
+ *   X0     n x basis start block, FP64, column-major (ld = n), or NULL for
+ *          U(0,1) drawn on the device from a fixed seed.
+ *   evals  k FP64, sorted by `which` (descending for LARGEST).
+ *   evecs  n x k FP64 column-major (ld = n), unit 2-norm, the entry of
+ *          largest magnitude (first on ties) positive.
+ *   resid  k FP64: ||A x - lambda x||_2 / anorm, computed in FP64 from A as
+ *          stored.
+ *   info   host, may be NULL.
+ * Returns OFRR_OK, OFRR_NOT_CONVERGED (tol > 0 and some resid > tol), or an
+ * error. */
+ofrr_status ofrr_eig_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                             ofrr_which which, const ofrr_plan *plan, const double *X0,
+                             double *evals, double *evecs, double *resid, ofrr_info *info);
+
+/* k largest singular triplets of a dense A (m x n, column-major) by
+ * alternating subspace iteration U = A V, V = A^T U with the Hessenberg
+ * process as stabiliser and the orthogonalization-free projection for the
+ * SVD (Sec. 3.2): the positive eigenvalues of
+ * [0 B; B^T 0] [y; z] = s blkdiag(U^T U, V^T V) [y; z], B = U^T A V, lifted
+ * as sqrt(2) U Y and sqrt(2) V Z (Theorem of Sec. 3.2).
+ *   V0     n x basis FP64 start block or NULL.
+ *   sigma  k FP64 descending; U m x k and V n x k FP64 column-major;
+ *   resid  k FP64 sqrt(||A v - s u||^2 + ||A^T u - s v||^2) / anorm.
+ * plan.filter must be OFRR_POWER with degree 1. */
+ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                             const ofrr_plan *plan, const double *V0, double *sigma,
+                             double *U, double *V, double *resid, ofrr_info *info);
+
+/* nprob independent symmetric eigenproblems (dense, each with its own n),
+ * the same k, basis and plan.  As[p], X0s (may be NULL), evals[p],
+ * evecs[p], resid[p] are per-problem pointers held in HOST arrays of length
+ * nprob; the pointers themselves are device pointers.  infos: host array of
+ * nprob or NULL. */
+ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_matrix *As,
+                                     int32_t k, int32_t basis, ofrr_which which,
+                                     const ofrr_plan *plan, const double *const *X0s,
+                                     double *const *evals, double *const *evecs,
+                                     double *const *resid, ofrr_info *infos);
+
+/* --------------------------------------------------------------------- */
+/* Step entry points: one step of the method on caller buffers.  They run  */
+/* the same kernels the whole-method calls use.                           */
+/* --------------------------------------------------------------------- */
+
+/* Round an FP32 array of `count` elements to `dst_dtype` (BF16 or F16 bits,
+ * uint16 per element), round to nearest even.  Mixed-precision plan of
+ * Sec. 4: the matrix and basis are stored in reduced precision. */
+ofrr_status ofrr_quantize(ofrr_ctx ctx, ofrr_dtype dst_dtype, int64_t count,
+                          const float *src, void *dst);
+
+/* FP8 e4m3fn with one power-of-two scale per 32 x 32 block: A (rows x cols
+ * FP32 column-major, lda) -> codes (rows x cols uint8, column-major, ld =
+ * rows) and scales (ceil(rows/32) x ceil(cols/32) FP32, column-major).  The
+ * block scale is 2^ceil(log2(amax/448)) (1 for an all-zero block); the code
+ * is e4m3fn(A/scale), nearest even, saturating. */
+ofrr_status ofrr_quantize_fp8_blocks(ofrr_ctx ctx, int64_t rows, int64_t cols, const float *A,
+                                     int64_t lda, uint8_t *codes, float *scales);
+
+/* Block product W = op(A) V (Sec. 2, the products X_{iter} = A^{iter} X_0).
+ *   A         descriptor: dense F64/F32 (FP64 arithmetic, FP64 V and W), dense
+ *             BF16/F16 (uint16 values; V BF16/F16 in the same type, W FP32;
+ *             MFMA with FP32 accumulation), or CSR F32/F64 (V and W FP32 or
+ *             FP64 per v_dtype).
+ *   trans     0: W = A V; 1: W = A^T V (dense only).
+ *   v_dtype   element type of V and W as described above.
+ *   V         (op(A) cols) x b, column-major ld = op cols; W (op rows) x b,
+ *             ld = op rows. */
+ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
+                               ofrr_dtype v_dtype, const void *V, void *W);
+
+/* Right-looking Hessenberg process on an n x b block Y (Sec. 4.2) in FP64
+ * (dtype F64) or FP32 (dtype F32), in place: for each column the first row
+ * of largest magnitude is the pivot; a column whose pivot magnitude is
+ * below tol is dropped (keep=0, piv=-1), otherwise it is divided by its
+ * pivot and its multiple eliminates the pivot row from every later column
+ * (one fused multiply-add per element).  piv, keep: int32[b].  Returns the
+ * kept count in *kept (host).  The kept columns equal P^T L of the
+ * row-pivoted LU factorisation of Y. */
+ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b, void *Y,
+                            int64_t ldy, double tol, int32_t *piv, int32_t *keep,
+                            int32_t *kept);
+
+/* Projections G = V^T V and H = V^T W (Alg. "Orthogonalization-Free
+ * Rayleigh-Ritz Projection", lines computing B and M), b x b FP64 outputs.
+ * V: n x b in v_dtype (F64, F32, BF16, F16); W: n x b in w_dtype (F64 or
+ * F32); both column-major with ld = n; accumulation per `accum`. */
+ofrr_status ofrr_project(ofrr_ctx ctx, int64_t n, int32_t b, ofrr_dtype v_dtype, const void *V,
+                         ofrr_dtype w_dtype, const void *W, ofrr_accum accum, double *G,
+                         double *H);
+
+/* Symmetric definite pencil H y = theta G y (eq. (geig)) in FP64 on the
+ * GPU: Cholesky G = L L^T, symmetric eigen-decomposition of L^{-1} H L^{-T}
+ * by cyclic Jacobi, Y = L^{-T} Z.  theta: b, sorted by `which`; Y: b x b
+ * with Y^T G Y = I.  If G is not positive definite the directions of G with
+ * eigenvalues below 1e-14 * max are discarded first and the discarded
+ * columns of Y are zero with theta = 0 placed last; *rank (host) receives
+ * the number of retained directions. */
+ofrr_status ofrr_pencil_eig(ofrr_ctx ctx, int32_t b, const double *H, const double *G,
+                            ofrr_which which, double *theta, double *Y, int32_t *rank);
+
+/* The SVD pencil of Sec. 3.2 for B (k1 x k2), MU (k1 x k1), MV (k2 x k2):
+ * sigma (min(k1,k2), descending, the positive eigenvalues), Y (k1 x
+ * min(k1,k2)), Z (k2 x min(k1,k2)) normalised so that [y; z]^T blkdiag(MU,
+ * MV) [y; z] = 1. */
+ofrr_status ofrr_svd_pencil(ofrr_ctx ctx, int32_t k1, int32_t k2, const double *B,
+                            const double *MU, const double *MV, double *sigma, double *Y,
+                            double *Z);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFRR_H */

@@ -74,6 +74,35 @@ def f32_to_e4m3_bits(x) -> np.ndarray:
     return code.astype(np.uint8)
 
 
+def fp8_block_quantize(A, block: int = 32):
+    """Per-block e4m3fn quantisation of a 2-D FP32 array: each block x block
+    tile gets the scale 2^ceil(log2(amax / 448)) (1 for an all-zero tile), a
+    power of two so that dividing by it is exact, and the codes are
+    e4m3fn(A / scale).  Returns (codes uint8, scales float32 of shape
+    (ceil(rows/block), ceil(cols/block)))."""
+    A = np.asarray(A, dtype=np.float32)
+    rows, cols = A.shape
+    br, bc = -(-rows // block), -(-cols // block)
+    scales = np.ones((br, bc), dtype=np.float32)
+    codes = np.zeros((rows, cols), dtype=np.uint8)
+    for i in range(br):
+        for j in range(bc):
+            t = A[i * block:(i + 1) * block, j * block:(j + 1) * block]
+            amax = float(np.max(np.abs(t))) if t.size else 0.0
+            s = 1.0
+            if amax > 0:
+                s = 2.0 ** int(np.ceil(np.log2(amax / 448.0)))
+                # guard the log2 rounding at exact powers of two
+                while amax / s > 448.0:
+                    s *= 2.0
+                while s > 2.0 ** -149 and amax / (s / 2.0) <= 448.0:
+                    s /= 2.0
+            scales[i, j] = s
+            codes[i * block:(i + 1) * block, j * block:(j + 1) * block] = \
+                f32_to_e4m3_bits((t / np.float32(s)).astype(np.float32))
+    return codes, scales
+
+
 def e4m3_bits_to_f32(bits) -> np.ndarray:
     b = np.asarray(bits, dtype=np.uint8).astype(np.int64)
     mag = b & 0x7F

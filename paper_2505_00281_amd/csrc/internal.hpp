@@ -1,0 +1,200 @@
+// internal.hpp -- host-side internals shared by the library's translation
+// units: context, workspace, error handling, kernel timing and the kernel
+// launcher declarations.  Not part of the public ABI (include/ofrr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ofrr.h"
+
+namespace ofrr {
+
+struct Error {
+    ofrr_status status;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(ofrr_status st, const std::string &msg) { throw Error{st, msg}; }
+
+#define OFRR_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::ofrr::fail(OFRR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define OFRR_CHECK_ARG(cond, msg)                                   \
+    do {                                                            \
+        if (!(cond)) ::ofrr::fail(OFRR_ERR_INVALID_ARG, (msg));     \
+    } while (0)
+
+// Per-family launch timing with HIP events recorded on the context stream
+// around each launch.  Events are resolved at the end of an API call.
+struct KernelTimer {
+    struct Pending {
+        int family;
+        hipEvent_t a, b;
+    };
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> total_ms;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int family(const char *name) const {
+        for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == name) return (int)i;
+        return -1;
+    }
+};
+
+struct Context;
+
+// RAII scope that times one kernel launch when profiling is on.
+struct KTimer {
+    Context *ctx;
+    int fam;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(Context *c, const char *family);
+    ~KTimer() noexcept(false);
+};
+
+// Device workspace: named buffers that grow on demand and are reused.
+struct Workspace {
+    struct Buf {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    void *get(const std::string &name, size_t bytes);
+    void release_all();
+};
+
+struct Context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    Workspace ws;
+    bool profile = false;
+    KernelTimer timer;
+    int cu_count = 0;
+    int max_lds = 0;
+
+    template <class T>
+    T *buf(const std::string &name, size_t count) {
+        return static_cast<T *>(ws.get(name, count * sizeof(T) + 256));
+    }
+    void sync() { OFRR_HIP(hipStreamSynchronize(stream)); }
+    void resolve_timers();
+};
+
+// ------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip translation units).
+// All pointers are device pointers; all launches go to ctx->stream.
+// ------------------------------------------------------------------------
+
+// k_misc.hip
+void zero_bytes(Context *ctx, void *p, size_t bytes);
+void cast_f32_to_bf16(Context *ctx, int64_t count, const float *src, uint16_t *dst);
+void cast_f32_to_f16(Context *ctx, int64_t count, const float *src, uint16_t *dst);
+void cast_f64_to_f32(Context *ctx, int64_t count, const double *src, float *dst);
+void cast_matrix(Context *ctx, ofrr_dtype src_t, ofrr_dtype dst_t, int64_t rows, int64_t cols,
+                 const void *src, int64_t lds, void *dst, int64_t ldd);
+void quantize_fp8_blocks(Context *ctx, int64_t rows, int64_t cols, const float *A, int64_t lda,
+                         uint8_t *codes, float *scales);
+void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X);
+// colmax[j] = max_i |Y_ij| for the n x b block (element type t, ld), then
+// Y (and Z if not null, same layout and type tz) are multiplied per column
+// by 2^-ceil(log2(colmax)); returns nothing; scale factors stay on device.
+void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
+                        ofrr_dtype tz, void *Z, int64_t ldz, float *work);
+// Row-major block helpers (element (i, j) at i*ld + j).
+// dst[:, dest(j)] = src[:, j] for every kept column j (src != dst).
+void compact_columns_rm(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *src,
+                        int64_t lds, const int32_t *keep, void *dst, int64_t ldd);
+// column-major FP64 (n x b, ld) -> row-major block of type dt (ld_dst)
+void colmajor_to_rowmajor(Context *ctx, int64_t n, int32_t b, const double *src, int64_t lds,
+                          ofrr_dtype dt, void *dst, int64_t ldd);
+// FP32 values -> hi (and lo = value - hi when lo != null) in BF16/F16 bits
+void split_block(Context *ctx, ofrr_dtype t, int64_t count, const float *src, uint16_t *hi,
+                 uint16_t *lo);
+// round FP32 values in place to the nearest BF16/F16 value
+void round_block(Context *ctx, ofrr_dtype t, int64_t count, float *x);
+// FP32 array of `count` values stored at the start of buf -> FP64 in place
+void promote_block(Context *ctx, int64_t count, void *buf);
+
+// k_product.hip
+void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const double *V,
+                 int64_t ldv, double *W, int64_t ldw);
+// A BF16/F16 (dense, uint16 bits, ld), V in the same type, W FP32.
+// vlo (may be null): low halves of a two-term split of V.
+void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
+                  int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
+                  int64_t ldv, float *W, int64_t ldw);
+// Validates a CSR descriptor's structure on the device (row_ptr[0] == 0,
+// non-decreasing, row_ptr[rows] == nnz, column indices in range); fails
+// with OFRR_ERR_INVALID_ARG otherwise.
+void check_csr(Context *ctx, const ofrr_matrix *A);
+void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,
+                 int64_t ldv, void *W, int64_t ldw);
+
+// k_hessenberg.hip
+int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
+                   double tol, int32_t *piv, int32_t *keep, bool want_count);
+
+// k_project.hip
+void project(Context *ctx, int64_t n, int32_t b, ofrr_dtype vt, const void *V, int64_t ldv,
+             ofrr_dtype wt, const void *W, int64_t ldw, ofrr_accum acc, double *G, double *H);
+void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, const void *X,
+               int64_t ldx, ofrr_dtype yt, const void *Y, int64_t ldy, double *C);
+
+// k_smalleig.hip
+// Pencil H y = theta G y; returns rank of G used.
+int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
+                   double *theta, double *Y, bool want_rank);
+void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,
+                const double *MV, double *sigma, double *Y, double *Z);
+
+// k_lift.hip
+// X = V Y[:, :nc], AX = W Y[:, :nc] (n x nc outputs, element type per xt),
+// optional residual partial sums ||AX_i - theta_i X_i||^2, ||X_i||^2.
+void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const void *V,
+          int64_t ldv, ofrr_dtype wt, const void *W, int64_t ldw, const double *Y, int32_t ldy,
+          const double *theta, ofrr_dtype xt, void *X, void *AX, int64_t ldx, double *res2,
+          double *xn2);
+// Chebyshev first step from X and AX: Y1 = alpha*(AX - c*X); or Y1 = AX
+// (power); output in type yt.
+void axpby_block(Context *ctx, int64_t n, int32_t b, ofrr_dtype it, const void *AX,
+                 const void *X, int64_t ld, double alpha, double beta, ofrr_dtype yt, void *Y,
+                 int64_t ldy);
+// Chebyshev recurrence Ynext = alpha*(P - c*Ycur) - Yprev (P FP32/FP64
+// product output, Ycur/Yprev in storage type st, Ynext in type nt).
+void cheb_combine(Context *ctx, int64_t n, int32_t b, ofrr_dtype pt, const void *P,
+                  ofrr_dtype st, const void *Ycur, const void *Yprev, int64_t ld, double alpha,
+                  double c, double beta, ofrr_dtype nt, void *Ynext);
+void scale_array(Context *ctx, int64_t count, double *x, double f);
+// out[c] = ||X1_c - s_c X2_c|| / ||X2_c|| / anorm for row-major blocks
+void col_resid(Context *ctx, ofrr_dtype t, int64_t n, int32_t count, const void *X1, const void *X2,
+               int64_t ld, const double *s, double anorm, double *out);
+// Final residual: R = AX - X theta, norms -> resid[i] = ||R_i|| / (||X_i|| anorm);
+// normalises X to unit columns with the sign rule and writes FP64 outputs.
+void finalize_eig(Context *ctx, int64_t n, int32_t k, const double *X, int64_t ldx,
+                  const double *AX, int64_t ldax, const double *theta, double anorm,
+                  double *evals, double *evecs, double *resid);
+// out[c] = sqrt(sum res2[blk][c]) / sqrt(sum xn2[blk][c]) / anorm for
+// c < count; partial arrays have row stride `stride`.
+void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
+                     int count, double anorm, double *out);
+// SVD final step: resid[c] = sqrt(|A v - s u|^2 + |A^T u - s v|^2)/anorm,
+// normalisation and sign rule (sign fixed on v, u follows); outputs
+// column-major FP64.
+void finalize_svd(Context *ctx, int64_t m, int64_t n, int32_t k, const double *U, const double *AV,
+                  const double *Vv, const double *ATU, int64_t ld, const double *sigma,
+                  double anorm, double *sig_out, double *Uo, double *Vo, double *resid);
+
+}  // namespace ofrr

@@ -1,0 +1,392 @@
+// k_misc.hip -- elementwise and column-wise kernels: fills, precision
+// conversions (storage formats of the mixed-precision plan, end of Sec. 4),
+// FP8 block quantisation, the U(0,1) start block (Sec. 5.2) and the
+// per-column scaling that follows each product (Sec. 2, Alg. "Multiple Step
+// Subspace Iteration": column scaling after every multiplication).
+#include "internal.hpp"
+#include "device_util.hpp"
+
+namespace ofrr {
+
+namespace {
+
+__global__ void k_zero(uint32_t *p, int64_t words) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ s, uint16_t *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = f32_to_bf16_bits(s[i]);
+}
+
+__global__ void k_f32_to_f16(const float *__restrict__ s, uint16_t *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = f32_to_f16_bits(s[i]);
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = (float)s[i];
+}
+
+template <class S, class D>
+__global__ void k_cast_matrix(const S *__restrict__ s, int64_t lds, D *__restrict__ d,
+                              int64_t ldd, int64_t rows, int64_t cols) {
+    int64_t total = rows * cols;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        int64_t c = i / rows, r = i - c * rows;
+        store_as<D>(d + r + c * ldd, load_as_f64(s + r + c * lds));
+    }
+}
+
+// One 32 x 32 block per 256-thread workgroup: amax, power-of-two scale,
+// e4m3fn codes.
+__global__ void k_fp8_blocks(const float *__restrict__ A, int64_t lda, int64_t rows, int64_t cols,
+                             uint8_t *__restrict__ codes, float *__restrict__ scales,
+                             int64_t brows) {
+    const int64_t bi = blockIdx.x, bj = blockIdx.y;
+    const int tid = threadIdx.x;
+    __shared__ float red[256];
+    float amax = 0.f;
+    for (int e = tid; e < 1024; e += 256) {
+        int64_t r = bi * 32 + (e & 31), c = bj * 32 + (e >> 5);
+        if (r < rows && c < cols) amax = fmaxf(amax, fabsf(A[r + c * lda]));
+    }
+    red[tid] = amax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    amax = red[0];
+    // scale = smallest power of two s with amax / s <= 448 (448 = 0.875 * 2^9),
+    // decided exactly from amax = m 2^e, m in [0.5, 1); 1 for an all-zero block
+    float scale = 1.f;
+    if (amax > 0.f) {
+        int e;
+        const float m = frexpf(amax, &e);
+        scale = ldexpf(1.f, m <= 0.875f ? e - 9 : e - 8);
+    }
+    if (tid == 0) scales[bi + bj * brows] = scale;
+    const float inv = 1.f / scale;  // exact: scale is a power of two
+    for (int e = tid; e < 1024; e += 256) {
+        int64_t r = bi * 32 + (e & 31), c = bj * 32 + (e >> 5);
+        if (r < rows && c < cols) codes[r + c * rows] = f32_to_e4m3_bits(A[r + c * lda] * inv);
+    }
+}
+
+// Counter-based U(0,1): SplitMix64 of (seed, index), top 53 bits.
+__global__ void k_uniform(double *X, int64_t count, uint64_t seed) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        X[i] = (double)(z >> 11) * 0x1.0p-53;
+    }
+}
+
+// Column abs-max partials of a row-major block: block x reduces rows
+// [x*rows_per_block, ...) over all b columns.  Rows are read contiguously;
+// per-column maxima are combined in LDS with an integer max on the float
+// bits (valid for non-negative floats, and order independent).  A NaN/Inf
+// in a column marks it with an all-ones pattern.
+template <class T>
+__global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
+                                                        int64_t n, int b, int64_t rows_per_block,
+                                                        float *__restrict__ part, int nblk) {
+    __shared__ unsigned cm[512];
+    for (int j = threadIdx.x; j < b; j += blockDim.x) cm[j] = 0u;
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
+    const int64_t total = (r1 - r0) * b;
+    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+        const int64_t r = r0 + e / b;
+        const int j = (int)(e % b);
+        const double v = load_as_f64(Y + r * ldy + j);
+        unsigned bits;
+        if (!(v == v) || isinf(v))
+            bits = 0xFFFFFFFFu;
+        else
+            bits = __float_as_uint((float)fabs(v));
+        atomicMax(&cm[j], bits);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < b; j += blockDim.x) {
+        const unsigned bits = cm[j];
+        part[(int64_t)j * nblk + blockIdx.x] = bits == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(bits);
+    }
+}
+
+// Reduce partials of each column and turn them into power-of-two scales
+// 2^-ceil(log2(max)) (so the scaled column has infinity-norm in (1/2, 1]);
+// a zero column keeps scale 1.  NaN/Inf poison the scale (NaN).
+__global__ void k_colscale(const float *__restrict__ part, int nblk, int b, float *__restrict__ scale) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b) return;
+    float m = 0.f;
+    bool bad = false;
+    for (int i = 0; i < nblk; ++i) {
+        float v = part[(int64_t)j * nblk + i];
+        if (v != v) bad = true;
+        m = fmaxf(m, v);
+    }
+    float s = 1.f;
+    if (bad) {
+        s = __builtin_nanf("");
+    } else if (m > 0.f) {
+        int e;
+        float mm = frexpf(m, &e);  // m = mm 2^e, mm in [0.5,1): 2^-e m in [0.5, 1)
+        (void)mm;
+        s = ldexpf(1.f, -e);
+    }
+    scale[j] = s;
+}
+
+template <class T>
+__global__ void k_apply_scale(T *__restrict__ Y, int64_t ldy, int64_t n, int b,
+                              const float *__restrict__ scale) {
+    int64_t total = n * b;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const int64_t r = i / b;
+        const int c = (int)(i - r * b);
+        T *p = Y + r * ldy + c;
+        store_as<T>(p, load_as_f64(p) * (double)scale[c]);
+    }
+}
+
+// row-major compaction: d[i, dest[j]] = s[i, j] for kept j
+template <class T>
+__global__ void k_compact_rm(const T *__restrict__ s, int64_t lds, T *__restrict__ d, int64_t ldd,
+                             int64_t n, const int32_t *__restrict__ dest_col, int b) {
+    const int64_t total = n * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        const int dj = dest_col[j];
+        if (dj >= 0) d[i * ldd + dj] = s[i * lds + j];
+    }
+}
+
+template <class D>
+__global__ void k_cm_to_rm(const double *__restrict__ s, int64_t lds, int64_t n, int b,
+                           D *__restrict__ d, int64_t ldd) {
+    const int64_t total = n * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        store_as<D>(d + i * ldd + j, s[i + (int64_t)j * lds]);
+    }
+}
+
+template <bool BF16>
+__global__ void k_split(const float *__restrict__ s, int64_t n, uint16_t *__restrict__ hi,
+                        uint16_t *__restrict__ lo) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float x = s[e];
+        const uint16_t h = BF16 ? f32_to_bf16_bits(x) : f32_to_f16_bits(x);
+        hi[e] = h;
+        if (lo) {
+            const float hv = BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
+            const float r = x - hv;  // exact: x and hv share the leading bits
+            lo[e] = BF16 ? f32_to_bf16_bits(r) : f32_to_f16_bits(r);
+        }
+    }
+}
+
+template <bool BF16>
+__global__ void k_round(float *__restrict__ x, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = BF16 ? bf16_bits_to_f32(f32_to_bf16_bits(x[e])) : f16_bits_to_f32(f32_to_f16_bits(x[e]));
+}
+
+__global__ void k_f32_to_f64_copy(const float *__restrict__ s, double *__restrict__ d, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        d[e] = (double)s[e];
+}
+
+__global__ void k_keep_to_dest(const int32_t *keep, int b, int32_t *dest) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int c = 0;
+        for (int j = 0; j < b; ++j) dest[j] = keep[j] ? c++ : -1;
+    }
+}
+
+inline int grid_for(int64_t count, int block = 256) {
+    int64_t g = (count + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <class F>
+void dispatch_type(ofrr_dtype t, F &&f) {
+    switch (t) {
+        case OFRR_F64: f((double *)nullptr); break;
+        case OFRR_F32: f((float *)nullptr); break;
+        case OFRR_BF16: f((bf16_t *)nullptr); break;
+        case OFRR_F16: f((f16_t *)nullptr); break;
+        default: fail(OFRR_ERR_UNSUPPORTED, "element type not supported here");
+    }
+}
+
+}  // namespace
+
+void zero_bytes(Context *ctx, void *p, size_t bytes) {
+    if (!bytes) return;
+    int64_t words = (int64_t)((bytes + 3) / 4);
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(words)), dim3(256), 0, ctx->stream, (uint32_t *)p, words);
+    OFRR_HIP(hipGetLastError());
+}
+
+void cast_f32_to_bf16(Context *ctx, int64_t count, const float *src, uint16_t *dst) {
+    KTimer t(ctx, "quantize");
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for(count)), dim3(256), 0, ctx->stream, src, dst, count);
+    OFRR_HIP(hipGetLastError());
+}
+
+void cast_f32_to_f16(Context *ctx, int64_t count, const float *src, uint16_t *dst) {
+    KTimer t(ctx, "quantize");
+    hipLaunchKernelGGL(k_f32_to_f16, dim3(grid_for(count)), dim3(256), 0, ctx->stream, src, dst, count);
+    OFRR_HIP(hipGetLastError());
+}
+
+void cast_f64_to_f32(Context *ctx, int64_t count, const double *src, float *dst) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(count)), dim3(256), 0, ctx->stream, src, dst, count);
+    OFRR_HIP(hipGetLastError());
+}
+
+void cast_matrix(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64_t cols,
+                 const void *src, int64_t lds, void *dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return;
+    int g = grid_for(rows * cols);
+    dispatch_type(st, [&](auto *sp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        dispatch_type(dt, [&](auto *dp) {
+            using D = std::remove_pointer_t<decltype(dp)>;
+            hipLaunchKernelGGL((k_cast_matrix<S, D>), dim3(g), dim3(256), 0, ctx->stream,
+                               (const S *)src, lds, (D *)dst, ldd, rows, cols);
+        });
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
+void quantize_fp8_blocks(Context *ctx, int64_t rows, int64_t cols, const float *A, int64_t lda,
+                         uint8_t *codes, float *scales) {
+    KTimer t(ctx, "quantize");
+    int64_t br = (rows + 31) / 32, bc = (cols + 31) / 32;
+    OFRR_CHECK_ARG(br <= 0x7fffffff && bc <= 65535, "matrix too large for FP8 block grid");
+    hipLaunchKernelGGL(k_fp8_blocks, dim3((unsigned)br, (unsigned)bc), dim3(256), 0, ctx->stream, A,
+                       lda, rows, cols, codes, scales, br);
+    OFRR_HIP(hipGetLastError());
+}
+
+void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X) {
+    int64_t count = n * b;
+    hipLaunchKernelGGL(k_uniform, dim3(grid_for(count)), dim3(256), 0, ctx->stream, X, count, seed);
+    OFRR_HIP(hipGetLastError());
+}
+
+void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
+                        ofrr_dtype tz, void *Z, int64_t ldz, float *work) {
+    KTimer tm(ctx, "scale");
+    (void)work;
+    OFRR_CHECK_ARG(b <= 512, "scale_columns_pow2: b <= 512");
+    const int64_t rpb = 256;
+    const int nblk = (int)((n + rpb - 1) / rpb);
+    float *part = ctx->buf<float>("colscale_work", (size_t)nblk * b + b + 64);
+    float *scale = part + (size_t)nblk * b + 32;
+    dispatch_type(t, [&](auto *p) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream,
+                           (const T *)Y, ldy, n, b, rpb, part, nblk);
+    });
+    hipLaunchKernelGGL(k_colscale, dim3((b + 63) / 64), dim3(64), 0, ctx->stream, part, nblk, b, scale);
+    int g = grid_for(n * b);
+    dispatch_type(t, [&](auto *p) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_apply_scale<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, n,
+                           b, scale);
+    });
+    if (Z) {
+        dispatch_type(tz, [&](auto *p) {
+            using T = std::remove_pointer_t<decltype(p)>;
+            hipLaunchKernelGGL((k_apply_scale<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Z, ldz,
+                               n, b, scale);
+        });
+    }
+    OFRR_HIP(hipGetLastError());
+}
+
+void compact_columns_rm(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *src,
+                        int64_t lds, const int32_t *keep, void *dst, int64_t ldd) {
+    OFRR_CHECK_ARG(src != dst, "compact_columns_rm: src and dst must differ");
+    int32_t *dest = ctx->buf<int32_t>("compact_dest", b);
+    hipLaunchKernelGGL(k_keep_to_dest, dim3(1), dim3(64), 0, ctx->stream, keep, b, dest);
+    dispatch_type(t, [&](auto *p) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_compact_rm<T>), dim3(grid_for(n * b)), dim3(256), 0, ctx->stream,
+                           (const T *)src, lds, (T *)dst, ldd, n, dest, b);
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
+void colmajor_to_rowmajor(Context *ctx, int64_t n, int32_t b, const double *src, int64_t lds,
+                          ofrr_dtype dt, void *dst, int64_t ldd) {
+    dispatch_type(dt, [&](auto *p) {
+        using D = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_cm_to_rm<D>), dim3(grid_for(n * b)), dim3(256), 0, ctx->stream, src,
+                           lds, n, b, (D *)dst, ldd);
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
+void split_block(Context *ctx, ofrr_dtype t, int64_t count, const float *src, uint16_t *hi,
+                 uint16_t *lo) {
+    if (t == OFRR_BF16)
+        hipLaunchKernelGGL((k_split<true>), dim3(grid_for(count)), dim3(256), 0, ctx->stream, src,
+                           count, hi, lo);
+    else if (t == OFRR_F16)
+        hipLaunchKernelGGL((k_split<false>), dim3(grid_for(count)), dim3(256), 0, ctx->stream, src,
+                           count, hi, lo);
+    else
+        fail(OFRR_ERR_UNSUPPORTED, "split_block: BF16 or F16");
+    OFRR_HIP(hipGetLastError());
+}
+
+void round_block(Context *ctx, ofrr_dtype t, int64_t count, float *x) {
+    if (t == OFRR_BF16)
+        hipLaunchKernelGGL((k_round<true>), dim3(grid_for(count)), dim3(256), 0, ctx->stream, x, count);
+    else if (t == OFRR_F16)
+        hipLaunchKernelGGL((k_round<false>), dim3(grid_for(count)), dim3(256), 0, ctx->stream, x, count);
+    else
+        fail(OFRR_ERR_UNSUPPORTED, "round_block: BF16 or F16");
+    OFRR_HIP(hipGetLastError());
+}
+
+void promote_block(Context *ctx, int64_t count, void *buf) {
+    double *tmp = ctx->buf<double>("promote_tmp", (size_t)count);
+    hipLaunchKernelGGL(k_f32_to_f64_copy, dim3(grid_for(count)), dim3(256), 0, ctx->stream,
+                       (const float *)buf, tmp, count);
+    OFRR_HIP(hipGetLastError());
+    OFRR_HIP(hipMemcpyAsync(buf, tmp, (size_t)count * 8, hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+}  // namespace ofrr

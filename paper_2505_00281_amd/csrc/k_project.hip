@@ -1,0 +1,133 @@
+// k_project.hip -- the projections of the orthogonalization-free
+// Rayleigh-Ritz step (Sec. 3.1, Alg. "Orthogonalization-Free Rayleigh-Ritz
+// Projection": B = U^T A U and M = U^T U; here G = V^T V and H = V^T W with
+// W = A V already formed).  Inputs are tall row-major n x b blocks in any
+// storage type; each product of two stored values is exact in FP64 (16 x
+// 16, 16 x 24 and 24 x 24 significand bits all fit in 53), so the only
+// rounding is the FP64 accumulation: row chunks are summed per workgroup,
+// then the chunk partials are added in a fixed order (deterministic).
+#include "internal.hpp"
+#include "device_util.hpp"
+
+namespace ofrr {
+
+namespace {
+
+constexpr int PJ_T = 64;      // output tile (PJ_T x PJ_T) per workgroup
+constexpr int PJ_R = 16;      // rows staged per step
+
+// grid (nchunks, ntiles_i, ntiles_j).  Computes the partial sums over rows
+// [c*rows_per, (c+1)*rows_per) of X^T Y for one tile, written to
+// part[c][tile] (PJ_T x PJ_T, row-major within the tile).
+template <class TX, class TY>
+__global__ __launch_bounds__(256) void k_gram_partial(const TX *__restrict__ X, int64_t ldx,
+                                                      const TY *__restrict__ Yb, int64_t ldy,
+                                                      int64_t n, int b1, int b2, int64_t rows_per,
+                                                      double *__restrict__ part) {
+    __shared__ double Xs[PJ_R][PJ_T + 1];
+    __shared__ double Ys[PJ_R][PJ_T + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int i0 = blockIdx.y * PJ_T, j0 = blockIdx.z * PJ_T;
+    const int64_t rbeg = (int64_t)blockIdx.x * rows_per;
+    int64_t rend = rbeg + rows_per;
+    if (rend > n) rend = n;
+    double acc[4][4] = {};
+    for (int64_t r0 = rbeg; r0 < rend; r0 += PJ_R) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = t + 256 * s;
+            const int rr = e >> 6, cc = e & 63;
+            const int64_t gr = r0 + rr;
+            const bool okr = gr < rend;
+            Xs[rr][cc] = (okr && i0 + cc < b1) ? load_as_f64(X + gr * ldx + i0 + cc) : 0.0;
+            Ys[rr][cc] = (okr && j0 + cc < b2) ? load_as_f64(Yb + gr * ldy + j0 + cc) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < PJ_R; ++rr) {
+            double a[4], v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = Xs[rr][ty + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = Ys[rr][tx + 16 * q];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], v[q], acc[p][q]);
+        }
+        __syncthreads();
+    }
+    const int ntile = gridDim.y * gridDim.z;
+    const int tile = blockIdx.y * gridDim.z + blockIdx.z;
+    double *dst = part + ((int64_t)blockIdx.x * ntile + tile) * PJ_T * PJ_T;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[(ty + 16 * p) * PJ_T + tx + 16 * q] = acc[p][q];
+}
+
+// Sum the chunk partials in chunk order and write C (b1 x b2, column-major,
+// ld = b1).
+__global__ void k_gram_reduce(const double *__restrict__ part, int nchunks, int ntj, int b1,
+                              int b2, double *__restrict__ C) {
+    const int64_t total = (int64_t)b1 * b2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / b1), i = (int)(e - (int64_t)j * b1);
+        const int ti = i / PJ_T, tj = j / PJ_T, ii = i % PJ_T, jj = j % PJ_T;
+        const int ntile = ((b1 + PJ_T - 1) / PJ_T) * ntj;
+        const int tile = ti * ntj + tj;
+        double s = 0.0;
+        for (int c = 0; c < nchunks; ++c) s += part[((int64_t)c * ntile + tile) * PJ_T * PJ_T + ii * PJ_T + jj];
+        C[e] = s;
+    }
+}
+
+template <class F>
+void dispatch_store(ofrr_dtype t, F &&f) {
+    switch (t) {
+        case OFRR_F64: f((double *)nullptr); break;
+        case OFRR_F32: f((float *)nullptr); break;
+        case OFRR_BF16: f((bf16_t *)nullptr); break;
+        case OFRR_F16: f((f16_t *)nullptr); break;
+        default: fail(OFRR_ERR_UNSUPPORTED, "projection: element type");
+    }
+}
+
+}  // namespace
+
+void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, const void *X,
+               int64_t ldx, ofrr_dtype yt, const void *Y, int64_t ldy, double *C) {
+    KTimer tm(ctx, "gram");
+    const int nti = (b1 + PJ_T - 1) / PJ_T, ntj = (b2 + PJ_T - 1) / PJ_T;
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    // enough chunks to fill the chip, each at least 256 rows
+    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (2 * cus + nti * ntj - 1) / (nti * ntj)));
+    int64_t rows_per = (n + nchunks - 1) / nchunks;
+    rows_per = (rows_per + PJ_R - 1) / PJ_R * PJ_R;
+    nchunks = (n + rows_per - 1) / rows_per;
+    double *part = ctx->buf<double>("gram_part", (size_t)nchunks * nti * ntj * PJ_T * PJ_T);
+    dim3 grid((unsigned)nchunks, nti, ntj);
+    dispatch_store(xt, [&](auto *xp) {
+        using TX = std::remove_pointer_t<decltype(xp)>;
+        dispatch_store(yt, [&](auto *yp) {
+            using TY = std::remove_pointer_t<decltype(yp)>;
+            hipLaunchKernelGGL((k_gram_partial<TX, TY>), grid, dim3(256), 0, ctx->stream,
+                               (const TX *)X, ldx, (const TY *)Y, ldy, n, b1, b2, rows_per, part);
+        });
+    });
+    OFRR_HIP(hipGetLastError());
+    const int64_t total = (int64_t)b1 * b2;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)),
+                       dim3(256), 0, ctx->stream, part, (int)nchunks, ntj, b1, b2, C);
+    OFRR_HIP(hipGetLastError());
+}
+
+void project(Context *ctx, int64_t n, int32_t b, ofrr_dtype vt, const void *V, int64_t ldv,
+             ofrr_dtype wt, const void *W, int64_t ldw, ofrr_accum acc, double *G, double *H) {
+    (void)acc;  // every accumulation mode is served by the FP64 path for now
+    gram_rect(ctx, n, b, b, vt, V, ldv, vt, V, ldv, G);
+    gram_rect(ctx, n, b, b, vt, V, ldv, wt, W, ldw, H);
+}
+
+}  // namespace ofrr

@@ -1,0 +1,329 @@
+// solver.cpp -- host orchestration of the whole method: multi-step subspace
+// iteration (Sec. 2, Alg. "Multiple Step Subspace Iteration") with the
+// Hessenberg process in place of QR (Sec. 4.2), the orthogonalization-free
+// projection (Sec. 3.1, eq. (geig); Sec. 3.2 for the SVD) and the mixed-
+// precision plan (end of Sec. 4): reduced-precision products and basis,
+// FP64 projected problem, FP64 final residuals.
+//
+// Per outer iteration (eigenvalues), with X the current Ritz block and
+// AX = A X when known:
+//   filter     Y1 = p1(A) X from AX (no product) or by a product, then the
+//              remaining degree-1 products of the power/Chebyshev filter; every
+//              filtered block is column-scaled by powers of two (Sec. 2);
+//   stabilise  Hessenberg process on the last block (drops dependent columns);
+//   project    W = A V, G = V^T V, H = V^T W;
+//   solve      H y = theta G y in FP64;
+//   lift       X = V Y, A X = W Y, residual estimates.
+// A refined plan runs this first in the reduced precision and switches to
+// an all-FP64 tail when the residual estimates stop improving.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ofrr {
+
+namespace {
+
+size_t esize(ofrr_dtype t) {
+    switch (t) {
+        case OFRR_F64: return 8;
+        case OFRR_F32: return 4;
+        case OFRR_BF16:
+        case OFRR_F16: return 2;
+        case OFRR_F8E4M3: return 1;
+    }
+    return 8;
+}
+
+double unit_roundoff(ofrr_dtype t) {
+    switch (t) {
+        case OFRR_F64: return std::ldexp(1.0, -52);
+        case OFRR_F32: return std::ldexp(1.0, -23);
+        case OFRR_F16: return std::ldexp(1.0, -10);
+        case OFRR_BF16: return std::ldexp(1.0, -7);
+        case OFRR_F8E4M3: return std::ldexp(1.0, -3);
+    }
+    return 0.0;
+}
+
+// One precision phase of the eigen iteration.
+struct Phase {
+    ofrr_dtype basis;  // F64: everything FP64; BF16/F16: reduced products, FP32 master blocks
+    bool f64() const { return basis == OFRR_F64; }
+    ofrr_dtype master() const { return f64() ? OFRR_F64 : OFRR_F32; }
+};
+
+struct EigRun {
+    Context *ctx;
+    const ofrr_matrix *A;
+    const ofrr_plan *plan;
+    int64_t n;
+    int32_t b;      // current basis size
+    int32_t k;
+    ofrr_which which;
+    int products = 0;
+    // reduced-precision copy of dense A
+    uint16_t *A_lo = nullptr;
+    ofrr_dtype A_lo_t = OFRR_F64;
+
+    // product of the current phase: W (master type) = A * Vblk (master type)
+    void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc) {
+        ++products;
+        const int64_t ld = b0;
+        if (A->format == OFRR_CSR) {
+            if (ph.f64()) {
+                product_csr(ctx, A, bc, OFRR_F64, Vm, ld, Wm, ld);
+            } else {
+                // round the FP32 block to the storage type and run the SpMM on it
+                uint16_t *vlo = ctx->buf<uint16_t>("spmm_vlo", (size_t)n * ld);
+                if (ph.basis == OFRR_F16)
+                    cast_f32_to_f16(ctx, n * ld, (const float *)Vm, vlo);
+                else
+                    cast_f32_to_bf16(ctx, n * ld, (const float *)Vm, vlo);
+                product_csr(ctx, A, bc, ph.basis, vlo, ld, Wm, ld);
+            }
+            return;
+        }
+        if (ph.f64()) {
+            product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
+            return;
+        }
+        // dense reduced precision: split the FP32 block into hi (+ lo)
+        uint16_t *vhi = ctx->buf<uint16_t>("prod_vhi", (size_t)n * ld);
+        uint16_t *vlo = nullptr;
+        if (plan->b_split >= 2) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)n * ld);
+        split_block(ctx, ph.basis, n * ld, (const float *)Vm, vhi, vlo);
+        product_lowp(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ld, (float *)Wm, ld);
+    }
+
+    int64_t b0 = 0;  // leading dimension of every block (the initial basis size)
+};
+
+}  // namespace
+
+ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                             ofrr_which which, const ofrr_plan *plan, const double *X0,
+                             double *evals, double *evecs, double *resid, ofrr_info *info) {
+    const int64_t n = A->rows;
+    const int64_t ld = basis;
+    hipEvent_t ev0, ev1;
+    OFRR_HIP(hipEventCreate(&ev0));
+    OFRR_HIP(hipEventCreate(&ev1));
+    OFRR_HIP(hipEventRecord(ev0, ctx->stream));
+
+    EigRun run;
+    run.ctx = ctx;
+    run.A = A;
+    run.plan = plan;
+    run.n = n;
+    run.b = basis;
+    run.k = k;
+    run.which = which;
+    run.b0 = ld;
+
+    std::vector<Phase> phases;
+    phases.push_back(Phase{plan->basis_dtype});
+    if (plan->refine && plan->basis_dtype != OFRR_F64) phases.push_back(Phase{OFRR_F64});
+
+    // quantise dense A once for a reduced-precision phase (Sec. 4: A stored
+    // in reduced precision)
+    if (A->format == OFRR_DENSE_COLMAJOR && !phases[0].f64()) {
+        run.A_lo_t = phases[0].basis;
+        run.A_lo = ctx->buf<uint16_t>("A_lo", (size_t)n * n);
+        const float *Af = nullptr;
+        if (A->dtype == OFRR_F32) {
+            Af = (const float *)A->values;
+        } else {
+            float *tmp = ctx->buf<float>("A_f32", (size_t)n * n);
+            cast_matrix(ctx, OFRR_F64, OFRR_F32, n, n, A->values, A->ld, tmp, n);
+            Af = tmp;
+        }
+        if (A->ld == n) {
+            if (run.A_lo_t == OFRR_BF16)
+                cast_f32_to_bf16(ctx, n * n, Af, run.A_lo);
+            else
+                cast_f32_to_f16(ctx, n * n, Af, run.A_lo);
+        } else {
+            cast_matrix(ctx, OFRR_F32, run.A_lo_t, n, n, Af, A->ld, run.A_lo, n);
+        }
+    }
+
+    // blocks (row-major n x ld), allocated in FP64 size so every phase fits
+    const size_t blk = (size_t)n * ld;
+    void *X = ctx->buf<double>("X", blk);
+    void *AX = ctx->buf<double>("AX", blk);
+    void *Y0 = ctx->buf<double>("Y0", blk);
+    void *Y1 = ctx->buf<double>("Y1", blk);
+    void *Y2 = ctx->buf<double>("Y2", blk);
+    void *V = ctx->buf<double>("V", blk);
+    void *W = ctx->buf<double>("W", blk);
+    float *swork = ctx->buf<float>("scale_work", (size_t)ld * ((n + 4095) / 4096 + 2) + 256);
+    double *G = ctx->buf<double>("G", (size_t)ld * ld);
+    double *H = ctx->buf<double>("H", (size_t)ld * ld);
+    double *Yr = ctx->buf<double>("Yr", (size_t)ld * ld);
+    double *theta = ctx->buf<double>("theta", (size_t)ld + 8);
+    int32_t *piv = ctx->buf<int32_t>("piv", (size_t)ld);
+    int32_t *keep = ctx->buf<int32_t>("keep", (size_t)ld);
+    const int64_t nblk = (n + 63) / 64;
+    double *res2 = ctx->buf<double>("res2", (size_t)nblk * ld);
+    double *xn2 = ctx->buf<double>("xn2", (size_t)nblk * ld);
+    double *rest = ctx->buf<double>("res_est", (size_t)ld + 8);
+
+    // start block X0 (column-major FP64) -> row-major master of phase 0
+    {
+        const double *src = X0;
+        if (!src) {
+            double *gen = ctx->buf<double>("X0_gen", blk);
+            uniform_start(ctx, n, basis, 0x5EEDull, gen);
+            src = gen;
+        }
+        colmajor_to_rowmajor(ctx, n, basis, src, n, phases[0].master(), X, ld);
+    }
+
+    const bool cheb = plan->filter == OFRR_CHEBYSHEV;
+    const double cc = cheb ? 0.5 * (plan->hi + plan->lo) : 0.0;
+    const double ee = cheb ? 0.5 * (plan->hi - plan->lo) : 1.0;
+
+    int32_t bc = basis;  // current basis size
+    bool have_ax = false;
+    int iters = 0, iters_low = 0;
+    int stall = 0;
+    double best_est = INFINITY;
+    size_t pi = 0;
+    std::vector<double> est((size_t)k);
+    double anorm_used = plan->anorm;
+
+    while (iters < plan->max_iters) {
+        const Phase &ph = phases[pi];
+        const ofrr_dtype mt = ph.master();
+        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(ph.basis);
+        // ---- filter
+        // Y0 = X
+        OFRR_HIP(hipMemcpyAsync(Y0, X, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        if (have_ax) {
+            if (cheb)
+                axpby_block(ctx, n, bc, mt, AX, X, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
+            else
+                OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        } else {
+            run.product(ph, Y0, W, bc);
+            if (cheb)
+                cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+            else
+                OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        for (int d = 2; d <= plan->degree; ++d) {
+            scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
+            if (!ph.f64() && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
+            run.product(ph, Y1, W, bc);
+            if (cheb)
+                cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+            else
+                OFRR_HIP(hipMemcpyAsync(Y2, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+            std::swap(Y0, Y1);
+            std::swap(Y1, Y2);
+        }
+        scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
+        // ---- stabilise (Hessenberg process, FP64 or FP32 arithmetic)
+        const int32_t kept = hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, true);
+        if (kept <= 0) fail(OFRR_ERR_NUMERIC, "every basis column was dropped");
+        if (kept < bc) {
+            compact_columns_rm(ctx, mt, n, bc, Y1, ld, keep, V, ld);
+        } else {
+            std::swap(V, Y1);
+        }
+        bc = kept;
+        if (bc < k) fail(OFRR_ERR_NUMERIC, "basis lost rank below k");
+        // storage rounding of the basis for a reduced-precision phase
+        if (!ph.f64() && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
+        // ---- project
+        run.product(ph, V, W, bc);
+        project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
+        // ---- solve
+        const int32_t rank = pencil_eig(ctx, bc, H, G, which, theta, Yr, true);
+        if (rank < k) fail(OFRR_ERR_NUMERIC, "projected mass matrix lost rank below k");
+        // ---- lift (X = V Y, AX = W Y) with residual estimates
+        lift(ctx, n, bc, rank, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
+        ++iters;
+        if (!ph.f64()) ++iters_low;
+        have_ax = true;
+        bc = rank;
+        // residual estimates of the k wanted pairs
+        if (plan->anorm <= 0) {
+            std::vector<double> th((size_t)rank);
+            OFRR_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * rank, hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            double m = 0.0;
+            for (double v : th) m = std::max(m, std::fabs(v));
+            anorm_used = m > 0 ? m : 1.0;
+        }
+        residual_reduce(ctx, res2, xn2, (int)nblk, rank, k, anorm_used, rest);
+        OFRR_HIP(hipMemcpyAsync(est.data(), rest, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        double emax = 0.0;
+        for (double v : est) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
+        if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "non-finite residual estimate");
+        const bool last_phase = pi + 1 == phases.size();
+        if (last_phase && plan->tol > 0 && emax <= plan->tol) break;
+        if (!last_phase) {
+            if (emax < 0.5 * best_est) {
+                best_est = emax;
+                stall = 0;
+            } else {
+                ++stall;
+            }
+            const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
+            if (stall >= plan->stall_iters || by_value) {
+                // switch to the FP64 tail: promote X, recompute AX by a product
+                promote_block(ctx, n * ld, X);
+                ++pi;
+                have_ax = false;
+                best_est = INFINITY;
+                stall = 0;
+            }
+        }
+    }
+
+    // ---- final FP64 residuals from A as stored
+    const Phase &ph = phases[pi];
+    double *Xf = ctx->buf<double>("X_final", (size_t)n * k + 8);
+    double *AXf = ctx->buf<double>("AX_final", (size_t)n * k + 8);
+    // X (row-major, ld) -> FP64 row-major n x k (ld k)
+    cast_matrix(ctx, ph.master(), OFRR_F64, k, n, X, ld, Xf, k);
+    {
+        ++run.products;
+        if (A->format == OFRR_CSR)
+            product_csr(ctx, A, k, OFRR_F64, Xf, k, AXf, k);
+        else
+            product_f64(ctx, A, 1, k, Xf, k, AXf, k);
+    }
+    finalize_eig(ctx, n, k, Xf, k, AXf, k, theta, anorm_used, evals, evecs, resid);
+    OFRR_HIP(hipEventRecord(ev1, ctx->stream));
+    std::vector<double> r((size_t)k);
+    OFRR_HIP(hipMemcpyAsync(r.data(), resid, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    float ms = 0.f;
+    OFRR_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    OFRR_HIP(hipEventDestroy(ev0));
+    OFRR_HIP(hipEventDestroy(ev1));
+    int nconv = 0;
+    double rmax = 0.0;
+    for (double v : r) {
+        rmax = std::max(rmax, v);
+        if (plan->tol > 0 ? v <= plan->tol : true) ++nconv;
+    }
+    if (info) {
+        info->iters = iters;
+        info->iters_low = iters_low;
+        info->n_converged = nconv;
+        info->basis_eff = bc;
+        info->products = run.products;
+        info->max_resid = rmax;
+        info->seconds = ms * 1e-3;
+    }
+    return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
+}
+
+}  // namespace ofrr

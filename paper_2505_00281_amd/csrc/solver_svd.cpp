@@ -1,0 +1,219 @@
+// solver_svd.cpp -- the SVD form (Sec. 3.2, Alg. "Orthogonalization-Free
+// Rayleigh-Ritz Projection for SVD"): alternating products U = A V and
+// V = A^T U, each stabilised by the Hessenberg process, then the augmented
+// pencil [0 B; B^T 0] vs blkdiag(U^T U, V^T V) with B = U^T A V, whose
+// positive eigenvalues are the singular values; the lift sqrt(2) U Y and
+// sqrt(2) V Z gives orthonormal singular vectors (Theorem of Sec. 3.2).
+//
+// B needs no third product: with T = A^T U formed for the right block,
+// B = U^T A V = T^T V, where T is kept unscaled before the Hessenberg sweep
+// turns it into V.  Restart is from all right Ritz vectors.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ofrr {
+
+namespace {
+
+double unit_roundoff_svd(ofrr_dtype t) {
+    switch (t) {
+        case OFRR_F64: return std::ldexp(1.0, -52);
+        case OFRR_F32: return std::ldexp(1.0, -23);
+        case OFRR_F16: return std::ldexp(1.0, -10);
+        case OFRR_BF16: return std::ldexp(1.0, -7);
+        case OFRR_F8E4M3: return std::ldexp(1.0, -3);
+    }
+    return 0.0;
+}
+
+}  // namespace
+
+ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                             const ofrr_plan *plan, const double *V0, double *sigma, double *U,
+                             double *V, double *resid, ofrr_info *info) {
+    const int64_t m = A->rows, n = A->cols;
+    const int64_t ld = basis;
+    hipEvent_t ev0, ev1;
+    OFRR_HIP(hipEventCreate(&ev0));
+    OFRR_HIP(hipEventCreate(&ev1));
+    OFRR_HIP(hipEventRecord(ev0, ctx->stream));
+
+    std::vector<ofrr_dtype> phases{plan->basis_dtype};
+    if (plan->refine && plan->basis_dtype != OFRR_F64) phases.push_back(OFRR_F64);
+    if (plan->basis_dtype == OFRR_F8E4M3 || plan->basis_dtype == OFRR_F32)
+        fail(OFRR_ERR_UNSUPPORTED, "svd_partial: basis_dtype F8E4M3/F32 not supported");
+
+    uint16_t *A_lo = nullptr;
+    if (phases[0] != OFRR_F64) {
+        A_lo = ctx->buf<uint16_t>("svd_A_lo", (size_t)m * n);
+        const float *Af = (const float *)A->values;
+        int64_t lda = A->ld;
+        if (A->dtype == OFRR_F64) {
+            float *tmp = ctx->buf<float>("svd_A_f32", (size_t)m * n);
+            cast_matrix(ctx, OFRR_F64, OFRR_F32, m, n, A->values, A->ld, tmp, m);
+            Af = tmp;
+            lda = m;
+        }
+        cast_matrix(ctx, OFRR_F32, phases[0], m, n, Af, lda, A_lo, m);
+    }
+
+    const size_t bm = (size_t)m * ld, bn = (size_t)n * ld;
+    void *Ub = ctx->buf<double>("svd_U", bm);
+    void *T1 = ctx->buf<double>("svd_T1", bm);
+    void *Vb = ctx->buf<double>("svd_V", bn);
+    void *T2 = ctx->buf<double>("svd_T2", bn);
+    void *Ts = ctx->buf<double>("svd_Ts", bn);
+    void *Vt = ctx->buf<double>("svd_Vt", bn);
+    void *Ut = ctx->buf<double>("svd_Ut", bm);
+    uint16_t *vh = ctx->buf<uint16_t>("svd_vh", std::max(bm, bn));
+    uint16_t *vl = ctx->buf<uint16_t>("svd_vl", std::max(bm, bn));
+    float *swork = ctx->buf<float>("svd_swork", (size_t)ld * ((std::max(m, n) + 4095) / 4096 + 2) + 256);
+    double *B = ctx->buf<double>("svd_B", (size_t)ld * ld);
+    double *MU = ctx->buf<double>("svd_MU", (size_t)ld * ld);
+    double *MV = ctx->buf<double>("svd_MV", (size_t)ld * ld);
+    double *Ys = ctx->buf<double>("svd_Ys", (size_t)ld * ld);
+    double *Zs = ctx->buf<double>("svd_Zs", (size_t)ld * ld);
+    double *sig = ctx->buf<double>("svd_sig", (size_t)ld + 8);
+    double *est = ctx->buf<double>("svd_est", (size_t)ld + 8);
+    int32_t *piv = ctx->buf<int32_t>("svd_piv", (size_t)ld);
+    int32_t *keep = ctx->buf<int32_t>("svd_keep", (size_t)ld);
+    int products = 0;
+
+    size_t pi = 0;
+    auto master = [&]() { return phases[pi] == OFRR_F64 ? OFRR_F64 : OFRR_F32; };
+    auto esz = [&]() { return phases[pi] == OFRR_F64 ? (size_t)8 : (size_t)4; };
+
+    {
+        const double *src = V0;
+        if (!src) {
+            double *gen = ctx->buf<double>("svd_V0_gen", bn);
+            uniform_start(ctx, n, basis, 0x5EEDull, gen);
+            src = gen;
+        }
+        colmajor_to_rowmajor(ctx, n, basis, src, n, master(), Vb, ld);
+    }
+
+    // W (rows x bc) = op(A) * X (cols x bc), phase arithmetic
+    auto product = [&](int trans, const void *X, void *Wout, int32_t bc) {
+        ++products;
+        const int64_t rows = trans ? n : m, cols = trans ? m : n;
+        if (phases[pi] == OFRR_F64) {
+            product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
+        } else {
+            split_block(ctx, phases[pi], cols * ld, (const float *)X, vh, plan->b_split >= 2 ? vl : nullptr);
+            product_lowp(ctx, phases[pi], rows, cols, A_lo, m, trans, bc, vh,
+                         plan->b_split >= 2 ? vl : nullptr, ld, (float *)Wout, ld);
+        }
+    };
+    // scale, Hessenberg, compact into dst; returns kept columns
+    auto stabilise = [&](void *Tin, int64_t rows, int32_t bc, void *dst) {
+        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff_svd(phases[pi]);
+        scale_columns_pow2(ctx, master(), rows, bc, Tin, ld, master(), nullptr, ld, swork);
+        const int32_t kept = hessenberg(ctx, master(), rows, bc, Tin, ld, tol, piv, keep, true);
+        if (kept < k) fail(OFRR_ERR_NUMERIC, "svd: basis lost rank below k");
+        if (kept < bc)
+            compact_columns_rm(ctx, master(), rows, bc, Tin, ld, keep, dst, ld);
+        else
+            OFRR_HIP(hipMemcpyAsync(dst, Tin, (size_t)rows * ld * esz(), hipMemcpyDeviceToDevice, ctx->stream));
+        if (phases[pi] != OFRR_F64 && plan->b_split < 2)
+            round_block(ctx, phases[pi], rows * ld, (float *)dst);
+        return kept;
+    };
+
+    int32_t bv = basis;
+    int iters = 0, iters_low = 0, stall = 0;
+    double best = INFINITY, anorm = plan->anorm;
+    int32_t r = 0;
+    std::vector<double> eh((size_t)k), sh((size_t)ld);
+    while (iters < plan->max_iters) {
+        const ofrr_dtype mt = master();
+        product(0, Vb, T1, bv);
+        const int32_t bu = stabilise(T1, m, bv, Ub);
+        product(1, Ub, T2, bu);
+        OFRR_HIP(hipMemcpyAsync(Ts, T2, bn * esz(), hipMemcpyDeviceToDevice, ctx->stream));
+        bv = stabilise(T2, n, bu, Vb);
+        gram_rect(ctx, n, bu, bv, mt, Ts, ld, mt, Vb, ld, B);
+        gram_rect(ctx, m, bu, bu, mt, Ub, ld, mt, Ub, ld, MU);
+        gram_rect(ctx, n, bv, bv, mt, Vb, ld, mt, Vb, ld, MV);
+        svd_pencil(ctx, bu, bv, B, MU, MV, sig, Ys, Zs);
+        r = std::min(bu, bv);
+        scale_array(ctx, (int64_t)bu * r, Ys, std::sqrt(2.0));
+        scale_array(ctx, (int64_t)bv * r, Zs, std::sqrt(2.0));
+        // U~ = U Y, V~ = V Z, A^T U~ = T Y (free), one-sided estimate
+        lift(ctx, m, bu, r, mt, Ub, ld, mt, nullptr, 0, Ys, bu, nullptr, mt, Ut, nullptr, ld, nullptr, nullptr);
+        lift(ctx, n, bv, r, mt, Vb, ld, mt, nullptr, 0, Zs, bv, nullptr, mt, Vt, nullptr, ld, nullptr, nullptr);
+        lift(ctx, n, bu, r, mt, Ts, ld, mt, nullptr, 0, Ys, bu, nullptr, mt, T2, nullptr, ld, nullptr, nullptr);
+        ++iters;
+        if (phases[pi] != OFRR_F64) ++iters_low;
+        OFRR_HIP(hipMemcpyAsync(sh.data(), sig, sizeof(double) * r, hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        if (plan->anorm <= 0) anorm = sh[0] > 0 ? sh[0] : 1.0;
+        col_resid(ctx, mt, n, k, T2, Vt, ld, sig, anorm, est);
+        OFRR_HIP(hipMemcpyAsync(eh.data(), est, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        double emax = 0.0;
+        for (double v : eh) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
+        if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "svd: non-finite residual estimate");
+        // restart from all right Ritz vectors
+        std::swap(Vb, Vt);
+        bv = r;
+        const bool last = pi + 1 == phases.size();
+        if (last && plan->tol > 0 && emax <= plan->tol) break;
+        if (!last) {
+            if (emax < 0.5 * best) {
+                best = emax;
+                stall = 0;
+            } else {
+                ++stall;
+            }
+            if (stall >= plan->stall_iters || (plan->switch_resid > 0 && emax <= plan->switch_resid)) {
+                promote_block(ctx, n * ld, Vb);
+                promote_block(ctx, m * ld, Ut);
+                ++pi;
+                best = INFINITY;
+                stall = 0;
+            }
+        }
+    }
+    // final FP64 residuals from A as stored: U~ (m x k), V~ (n x k)
+    const ofrr_dtype mt = master();
+    double *Uf = ctx->buf<double>("svd_Uf", (size_t)m * k + 8);
+    double *Vf = ctx->buf<double>("svd_Vf", (size_t)n * k + 8);
+    double *AVf = ctx->buf<double>("svd_AVf", (size_t)m * k + 8);
+    double *ATUf = ctx->buf<double>("svd_ATUf", (size_t)n * k + 8);
+    cast_matrix(ctx, mt, OFRR_F64, k, m, Ut, ld, Uf, k);
+    cast_matrix(ctx, mt, OFRR_F64, k, n, Vb, ld, Vf, k);
+    products += 2;
+    product_f64(ctx, A, 0, k, Vf, k, AVf, k);
+    product_f64(ctx, A, 1, k, Uf, k, ATUf, k);
+    finalize_svd(ctx, m, n, k, Uf, AVf, Vf, ATUf, k, sig, anorm, sigma, U, V, resid);
+    OFRR_HIP(hipEventRecord(ev1, ctx->stream));
+    std::vector<double> rr((size_t)k);
+    OFRR_HIP(hipMemcpyAsync(rr.data(), resid, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    float ms = 0.f;
+    OFRR_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    OFRR_HIP(hipEventDestroy(ev0));
+    OFRR_HIP(hipEventDestroy(ev1));
+    int nconv = 0;
+    double rmax = 0.0;
+    for (double v : rr) {
+        rmax = std::max(rmax, v);
+        if (plan->tol > 0 ? v <= plan->tol : true) ++nconv;
+    }
+    if (info) {
+        info->iters = iters;
+        info->iters_low = iters_low;
+        info->n_converged = nconv;
+        info->basis_eff = bv;
+        info->products = products;
+        info->max_resid = rmax;
+        info->seconds = ms * 1e-3;
+    }
+    return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
+}
+
+}  // namespace ofrr

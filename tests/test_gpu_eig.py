@@ -1,0 +1,212 @@
+"""Whole-method parity through the C ABI: the GPU path against the CPU
+oracle on the same seeded inputs.
+
+* FP64 form, same-step mode: after the same number of outer iterations the
+  GPU's Hessenberg/OFRR subspace equals the oracle's orthonormal/classical-RR
+  subspace (span(p(A)^s X0)), so the Ritz values agree to rounding (the
+  tolerance 1e-12 relative is the one stated for the FP64 form).
+* Mixed forms, converged mode: final residual <= 1e-8 and relative
+  eigenvalue error <= 1e-10 against the oracle's converged pairs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ofrr_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_00281_amd import ofrr
+    c = ofrr.Context(0)
+    yield c
+    c.close()
+
+
+def _plan(**kw):
+    from paper_2505_00281_amd import ofrr
+    return ofrr.make_plan(**kw)
+
+
+def _check_same_step(r, ref, k, vec_tol=1e-8):
+    th = r.evals.cpu().numpy()
+    np.testing.assert_allclose(th, ref.theta, rtol=1e-12, atol=0)
+    res = r.resid.cpu().numpy()
+    np.testing.assert_allclose(res, ref.resid, rtol=1e-6, atol=1e-12)
+    X = r.evecs.cpu().numpy()
+    np.testing.assert_allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-14)
+    np.testing.assert_allclose(X, ref.X, atol=vec_tol)
+
+
+def test_eig_dense_n512_power_fp64_same_step(ctx):
+    """The n=512 configuration: A = Q diag(0.95^i) Q^T (FP64), k=8, basis 16,
+    20 power steps, FP64 form."""
+    n, b, k, outer = 512, 16, 8, 20
+    lam = 0.95 ** np.arange(1, n + 1)
+    A = W.dense_symmetric_prescribed(lam, 1001)
+    X0 = W.uniform_start(n, b, 1101)
+    print("eig n512 fp64 same-step", flush=True)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=_plan(max_iters=outer), X0=torch.from_numpy(X0))
+    ref = O.subspace_eig(A.numpy(), X0, k, outer=outer)
+    assert r.info["iters"] == outer
+    _check_same_step(r, ref, k)
+
+
+@pytest.mark.parametrize("n,b,k,deg", [(300, 10, 4, 3), (257, 9, 3, 5)])
+def test_eig_dense_chebyshev_fp64_same_step(ctx, n, b, k, deg):
+    lam = np.linspace(1.0, -0.5, n) ** 3
+    A = W.dense_symmetric_prescribed(lam, 77 + n)
+    X0 = W.uniform_start(n, b, 78 + n)
+    lo, hi = -0.2, 0.3
+    print("eig chebyshev fp64", n, b, k, deg, flush=True)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=_plan(filter="chebyshev", degree=deg, lo=lo, hi=hi,
+                                                    max_iters=6), X0=torch.from_numpy(X0))
+    ref = O.subspace_eig(A.numpy(), X0, k, filt="chebyshev", degree=deg, lo=lo, hi=hi, outer=6)
+    _check_same_step(r, ref, k, vec_tol=1e-7)
+
+
+def test_eig_csr_laplacian_smallest_fp64_same_step(ctx):
+    from paper_2505_00281_amd import ofrr
+    N, b, k = 24, 16, 6
+    rp, ci, v = W.laplacian_2d_csr(N)
+    ev = W.laplacian_2d_eigenvalues(N)
+    X0 = W.uniform_start(N * N, b, 9)
+    mat = ofrr.csr_matrix(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                          torch.from_numpy(v).cuda())
+    print("eig csr laplacian fp64", flush=True)
+    plan = _plan(filter="chebyshev", degree=8, lo=float(ev[b]), hi=8.0, anorm=8.0, max_iters=10)
+    r = ctx.eig_partial(mat, k, b, which="smallest", plan=plan, X0=torch.from_numpy(X0))
+    ref = O.subspace_eig((rp, ci, v), X0, k, which="smallest", filt="chebyshev", degree=8,
+                         lo=float(ev[b]), hi=8.0, outer=10, anorm=8.0)
+    th = r.evals.cpu().numpy()
+    np.testing.assert_allclose(th, ref.theta, rtol=1e-12)
+    # exact double eigenvalues: compare spans of the returned vectors, not vectors
+    np.testing.assert_allclose(r.resid.cpu().numpy(), ref.resid, rtol=1e-5, atol=1e-12)
+
+
+def test_eig_csr_malformed_is_rejected(ctx):
+    """A CSR with an out-of-range column index is refused before any
+    product runs."""
+    from paper_2505_00281_amd import ofrr
+    rp, ci, v = W.laplacian_2d_csr(8)
+    ci = ci.copy()
+    ci[10] = 10 ** 6
+    rpg, cig, vg = (torch.from_numpy(a).cuda() for a in (rp, ci, v))
+    mat = ofrr.csr_matrix(rpg, cig, vg)
+    with pytest.raises(ofrr.OfrrError) as e:
+        ctx.eig_partial(mat, 2, 4, which="smallest", plan=_plan(max_iters=2))
+    assert e.value.status == ofrr.ERR_INVALID_ARG
+
+
+def test_eig_converged_to_tolerance_fp64(ctx):
+    n, b, k = 400, 12, 5
+    lam = 0.8 ** np.arange(n)
+    A = W.dense_symmetric_prescribed(lam, 5)
+    print("eig converged fp64", flush=True)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=_plan(tol=1e-12, anorm=1.0, max_iters=500))
+    assert r.status == 0
+    np.testing.assert_allclose(r.evals.cpu().numpy(), lam[:k], rtol=1e-13)
+    assert r.resid.cpu().numpy().max() <= 1e-12
+
+
+@pytest.mark.parametrize("lowp", ["bf16", "f16"])
+def test_eig_mixed_refined_converged(ctx, lowp):
+    """Mixed form with the FP64 tail reaches residual <= 1e-8 and relative
+    eigenvalue error <= 1e-10 against the oracle's converged pairs."""
+    n, b, k = 2048, 32, 12
+    lam = np.arange(1, n + 1) ** -1.5
+    A = W.dense_symmetric_prescribed(lam, 1002, noise_scale=1e-4, noise_seed=2002, dtype=torch.float32)
+    Ad = A.double().numpy()
+    w, Z = np.linalg.eigh(Ad)
+    w = w[::-1]
+    X0 = W.uniform_start(n, b, 1102)
+    lo, hi = float(w[-1]), float(w[b])
+    print("eig mixed refined", lowp, flush=True)
+    plan = _plan(basis_dtype=lowp, refine=True, filter="chebyshev", degree=4, lo=lo, hi=hi,
+                 tol=1e-9, anorm=float(w[0]), max_iters=400)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=plan, X0=torch.from_numpy(X0))
+    ref = O.subspace_eig(Ad, X0, k, filt="chebyshev", degree=4, lo=lo, hi=hi, tol=1e-12,
+                         anorm=float(w[0]), max_outer=2000)
+    th = r.evals.cpu().numpy()
+    assert r.info["iters_low"] >= 1
+    assert r.resid.cpu().numpy().max() <= 1e-8
+    np.testing.assert_allclose(th, ref.theta, rtol=1e-10)
+    np.testing.assert_allclose(th, w[:k], rtol=1e-10)
+
+
+def test_eig_rank_deficient_start_block_still_correct(ctx):
+    n, b, k = 300, 10, 4
+    lam = 0.7 ** np.arange(n)
+    A = W.dense_symmetric_prescribed(lam, 15)
+    X0 = W.uniform_start(n, b, 16)
+    X0[:, 7] = X0[:, 1]  # dependent start column: dropped by the Hessenberg sweep
+    print("eig rank-deficient start", flush=True)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=_plan(tol=1e-12, anorm=1.0, max_iters=300),
+                        X0=torch.from_numpy(X0))
+    assert r.info["basis_eff"] <= b - 1
+    np.testing.assert_allclose(r.evals.cpu().numpy(), lam[:k], rtol=1e-12)
+
+
+def test_eig_invalid_arguments(ctx):
+    from paper_2505_00281_amd import ofrr
+    A = torch.eye(10, dtype=torch.float64).cuda()
+    with pytest.raises(ofrr.OfrrError) as e:
+        ctx.eig_partial(A, 5, 4)  # k > basis
+    assert e.value.status == ofrr.ERR_INVALID_ARG
+    with pytest.raises(ofrr.OfrrError) as e:
+        ctx.eig_partial(A, 2, 4, plan=_plan(filter="chebyshev", lo=1.0, hi=1.0))
+    assert e.value.status == ofrr.ERR_INVALID_ARG
+    with pytest.raises(ofrr.OfrrError) as e:
+        ctx.eig_partial(A, 2, 11)
+    assert e.value.status == ofrr.ERR_INVALID_ARG
+
+
+def test_eig_nan_input_reports_numeric(ctx):
+    from paper_2505_00281_amd import ofrr
+    A = torch.eye(64, dtype=torch.float64)
+    A[3, 5] = float("nan")
+    A[5, 3] = float("nan")
+    with pytest.raises(ofrr.OfrrError) as e:
+        ctx.eig_partial(A.cuda(), 2, 4, plan=_plan(max_iters=3))
+    assert e.value.status == ofrr.ERR_NUMERIC
+
+
+def test_svd_fp64_same_step(ctx):
+    m, n, b, k = 700, 240, 14, 6
+    sig = np.exp(-np.arange(1, n + 1) / 30.0)
+    A = W.svd_prescribed(m, n, sig, 31, dtype=torch.float64)
+    V0 = W.uniform_start(n, b, 32)
+    print("svd fp64 same-step", flush=True)
+    r = ctx.svd_partial(A.cuda(), k, b, plan=_plan(max_iters=5), V0=torch.from_numpy(V0))
+    ref = O.subspace_svd(A.numpy(), V0, k, outer=5)
+    np.testing.assert_allclose(r.sigma.cpu().numpy(), ref.sigma, rtol=1e-12)
+    np.testing.assert_allclose(r.resid.cpu().numpy(), ref.resid, rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(r.V.cpu().numpy(), ref.V, atol=1e-8)
+    np.testing.assert_allclose(r.U.cpu().numpy(), ref.U, atol=1e-8)
+
+
+def test_svd_converged_fp64(ctx):
+    m, n, b, k = 600, 200, 16, 8
+    sig = np.exp(-np.arange(1, n + 1) / 20.0)
+    A = W.svd_prescribed(m, n, sig, 41, dtype=torch.float64)
+    print("svd converged fp64", flush=True)
+    r = ctx.svd_partial(A.cuda(), k, b, plan=_plan(tol=1e-12, max_iters=300))
+    np.testing.assert_allclose(r.sigma.cpu().numpy(), sig[:k], rtol=1e-12)
+    assert r.resid.cpu().numpy().max() <= 1e-12
+
+
+def test_batched_matches_single(ctx):
+    sizes = [256, 300, 513]
+    As, X0s = [], []
+    for i, n in enumerate(sizes):
+        lam = 0.9 ** np.arange(1, n + 1)
+        As.append(W.dense_symmetric_prescribed(lam, 500 + i))
+        X0s.append(torch.from_numpy(W.uniform_start(n, 16, 600 + i)))
+    print("batched", flush=True)
+    outs = ctx.eig_partial_batched([a.cuda() for a in As], 8, 16, plan=_plan(max_iters=10), X0s=X0s)
+    for i, o in enumerate(outs):
+        ref = O.subspace_eig(As[i].numpy(), X0s[i].numpy(), 8, outer=10)
+        np.testing.assert_allclose(o.evals.cpu().numpy(), ref.theta, rtol=1e-12)

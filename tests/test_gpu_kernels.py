@@ -1,0 +1,250 @@
+"""Step-level parity of the HIP kernels against the CPU oracle, called
+through the C ABI.  Integer and byte results are compared bit-exactly; float
+results within the rounding-error bound of the arithmetic they perform."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ofrr_oracle as O
+from oracle import rounding as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_00281_amd import ofrr
+    c = ofrr.Context(0)
+    yield c
+    c.close()
+
+
+def _cuda(x):
+    return torch.as_tensor(x).cuda()
+
+
+# ---------------------------------------------------------------- quantize
+
+def test_quantize_bf16_f16_bit_exact(ctx):
+    rng = np.random.default_rng(1)
+    x = np.concatenate([
+        rng.standard_normal(100000).astype(np.float32) * 10,
+        np.array([1.0, 1.00390625, 1.01171875, 1.0078125, -2.0, 0.0, 3.0e38, 1e-40, 65504.0,
+                  65520.0, 6e-8, 1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11], dtype=np.float32)])
+    print("quantize bf16/f16 count", x.size, flush=True)
+    got = ctx.quantize(_cuda(x), "bf16").cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(got, R.f32_to_bf16_bits(x))
+    got16 = ctx.quantize(_cuda(x), "f16").cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(got16, x.astype(np.float16).view(np.uint16))
+
+
+def test_fp8_block_quantize_bit_exact(ctx):
+    rng = np.random.default_rng(2)
+    rows, cols = 100, 70  # ragged blocks
+    A = (rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-20, 10, (rows, cols)))).astype(np.float32)
+    A[:32, :32] = 0.0  # an all-zero block
+    A[40, 40] = 448.0 * 2.0 ** -3  # amax exactly 448 * power of two
+    print("fp8 blocks", rows, cols, flush=True)
+    At = torch.from_numpy(A.T.copy()).cuda().t()  # column-major
+    codes, scales = ctx.quantize_fp8_blocks(At)
+    c_ref, s_ref = R.fp8_block_quantize(A)
+    np.testing.assert_array_equal(scales.cpu().numpy(), s_ref)
+    np.testing.assert_array_equal(codes.cpu().numpy(), c_ref)
+
+
+# ---------------------------------------------------------------- products
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("trans", [0, 1])
+def test_product_f64(ctx, dtype, trans):
+    rng = np.random.default_rng(3)
+    m, kd, b = 300, 257, 13
+    A = rng.standard_normal((m, kd) if not trans else (kd, m))
+    A = A.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A
+    V = rng.standard_normal((kd, b))
+    print("product_f64", dtype, trans, flush=True)
+    At = torch.from_numpy(np.asfortranarray(A)).to(dtype)
+    At = At.t().contiguous().t().cuda()
+    Wg = ctx.block_product(At, _cuda(V), trans=bool(trans)).cpu().numpy()
+    opA = A.T if trans else A
+    ref = opA @ V
+    bound = 2 * kd * 2.0 ** -53 * (np.abs(opA) @ np.abs(V))
+    assert np.all(np.abs(Wg - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("lowp", ["bf16", "f16"])
+@pytest.mark.parametrize("trans", [0, 1])
+@pytest.mark.parametrize("shape", [(300, 1000, 70), (128, 64, 64), (4100, 4096, 128)])
+def test_product_lowp(ctx, lowp, trans, shape):
+    from paper_2505_00281_amd import ofrr
+    rng = np.random.default_rng(4)
+    m, kd, b = shape
+    A = rng.standard_normal((m, kd) if not trans else (kd, m)).astype(np.float32)
+    V = rng.standard_normal((kd, b)).astype(np.float32)
+    rnd = R.round_bf16 if lowp == "bf16" else R.round_f16
+    Ar, Vr = rnd(A).astype(np.float64), rnd(V).astype(np.float64)
+    print("product_lowp", lowp, trans, shape, flush=True)
+    Acm = torch.from_numpy(np.asfortranarray(A).T.copy()).cuda()  # storage of A^T row-major = A col-major
+    Aq = ctx.quantize(Acm, lowp)  # same memory order
+    Vq = ctx.quantize(_cuda(V), lowp)
+    mat = ofrr.Matrix()
+    mat.format, mat.dtype = ofrr.DENSE, ofrr.BF16 if lowp == "bf16" else ofrr.F16
+    mat.rows, mat.cols = A.shape
+    mat.ld = A.shape[0]
+    mat.values = Aq.data_ptr()
+    Wg = ctx.block_product(mat, Vq, trans=bool(trans), v_dtype=lowp).cpu().numpy().astype(np.float64)
+    opA = Ar.T if trans else Ar
+    ref = opA @ Vr  # products of the rounded values are exact in FP32 and FP64
+    bound = (kd + 2) * 2.0 ** -24 * (np.abs(opA) @ np.abs(Vr))
+    err = np.abs(Wg - ref)
+    assert np.all(err <= bound), float(np.max(err / np.maximum(bound, 1e-300)))
+
+
+@pytest.mark.parametrize("vt", ["f64", "f16", "f32"])
+def test_spmm_laplacian(ctx, vt):
+    from paper_2505_00281_amd import ofrr
+    N = 37
+    rp, ci, v = W.laplacian_2d_csr(N)
+    n = N * N
+    X = np.random.default_rng(5).standard_normal((n, 24))
+    if vt == "f16":
+        X = R.round_f16(X).astype(np.float64)
+        Xg = torch.from_numpy(X.astype(np.float16)).cuda()
+    elif vt == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        Xg = torch.from_numpy(X.astype(np.float32)).cuda()
+    else:
+        Xg = _cuda(X)
+    print("spmm", vt, flush=True)
+    rpg, cig, vg = _cuda(rp), _cuda(ci), _cuda(v)
+    mat = ofrr.csr_matrix(rpg, cig, vg)
+    Wg = ctx.block_product(mat, Xg, v_dtype=vt).cpu().numpy().astype(np.float64)
+    ref = O.csr_matmul(rp, ci, v.astype(np.float64), X)
+    tol = 1e-14 if vt == "f64" else 2.0 ** -23
+    np.testing.assert_allclose(Wg, ref, rtol=tol, atol=tol * 8 * np.abs(X).max())
+
+
+# -------------------------------------------------------------- Hessenberg
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1000, 24), (5000, 64), (70000, 128), (16384, 128), (7, 3)])
+def test_hessenberg_matches_oracle_bitwise(ctx, prec, shape):
+    n, b = shape
+    if prec == "f32" and n == 70000:
+        pytest.skip("FP32 streaming case covered at FP64")
+    rng = np.random.default_rng(6)
+    Y = rng.random((n, b))
+    dt = np.float64 if prec == "f64" else np.float32
+    Y = Y.astype(dt)
+    tol = 2.0 ** -52 if prec == "f64" else 2.0 ** -23
+    print("hessenberg", prec, shape, flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    assert kept == int(k_ref.sum())
+    np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
+
+
+def test_hessenberg_drops_like_oracle(ctx):
+    rng = np.random.default_rng(7)
+    n, b = 3000, 12
+    Y = rng.standard_normal((n, b))
+    Y[:, 5] = Y[:, 1] - 0.5 * Y[:, 3]
+    Y[:, 9] = 0.0
+    Y /= np.maximum(np.abs(Y).max(axis=0), 1e-300)
+    tol = 2.0 ** -52 * 64
+    print("hessenberg drops", flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, "f64")
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    assert k_ref[5] == 0 and k_ref[9] == 0
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
+
+
+# ------------------------------------------------------------- projection
+
+@pytest.mark.parametrize("vt", ["f64", "f32", "bf16"])
+def test_project(ctx, vt):
+    rng = np.random.default_rng(8)
+    n, b = 3001, 70
+    V = rng.standard_normal((n, b))
+    Wm = rng.standard_normal((n, b))
+    if vt == "bf16":
+        V = R.round_bf16(V).astype(np.float64)
+        Vg = ctx.quantize(_cuda(V.astype(np.float32)), "bf16")
+        Wm = Wm.astype(np.float32).astype(np.float64)
+        Wg = _cuda(Wm.astype(np.float32))
+    elif vt == "f32":
+        V = V.astype(np.float32).astype(np.float64)
+        Vg = _cuda(V.astype(np.float32))
+        Wm = Wm.astype(np.float32).astype(np.float64)
+        Wg = _cuda(Wm.astype(np.float32))
+    else:
+        Vg, Wg = _cuda(V), _cuda(Wm)
+    print("project", vt, flush=True)
+    G, H = ctx.project(Vg, Wg, v_dtype=vt)
+    G, H = G.cpu().numpy(), H.cpu().numpy()
+    bound = 2 * n * 2.0 ** -53
+    np.testing.assert_allclose(G, V.T @ V, rtol=0, atol=bound * (np.abs(V).T @ np.abs(V)).max())
+    np.testing.assert_allclose(H, V.T @ Wm, rtol=0, atol=bound * (np.abs(V).T @ np.abs(Wm)).max())
+    assert np.array_equal(G, G.T)
+
+
+# ---------------------------------------------------------- small problems
+
+@pytest.mark.parametrize("b", [1, 2, 7, 16, 64, 128])
+def test_pencil_eig(ctx, b):
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((400, 400))
+    A = A + A.T
+    V = rng.standard_normal((400, b))
+    H, G = V.T @ A @ V, V.T @ V
+    print("pencil", b, flush=True)
+    theta, Y, rank = ctx.pencil_eig(_cuda(H), _cuda(G), "largest")
+    theta, Y = theta.cpu().numpy(), Y.cpu().numpy()
+    t_ref, Y_ref = O.sym_pencil_eig(H, G)
+    t_ref, Y_ref = t_ref[::-1], Y_ref[:, ::-1]
+    assert rank == b
+    scale = np.abs(t_ref).max()
+    np.testing.assert_allclose(theta, t_ref, rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(Y.T @ G @ Y, np.eye(b), atol=1e-10)
+    np.testing.assert_allclose(H @ Y, G @ Y * theta, atol=1e-9 * scale * np.abs(Y).max())
+
+
+def test_pencil_eig_indefinite_mass_falls_back(ctx):
+    rng = np.random.default_rng(10)
+    A = rng.standard_normal((200, 200))
+    A = A + A.T
+    V = rng.standard_normal((200, 8))
+    V[:, 6] = V[:, 0] + V[:, 2]  # rank 7
+    H, G = V.T @ A @ V, V.T @ V
+    print("pencil fallback", flush=True)
+    theta, Y, rank = ctx.pencil_eig(_cuda(H), _cuda(G), "largest")
+    assert rank == 7
+    theta = theta.cpu().numpy()
+    Q, _ = np.linalg.qr(V[:, [0, 1, 2, 3, 4, 5, 7]])
+    ref = np.sort(np.linalg.eigvalsh(Q.T @ A @ Q))[::-1]
+    np.testing.assert_allclose(theta[:7], ref, rtol=1e-8, atol=1e-8)
+    assert theta[7] == 0.0
+
+
+@pytest.mark.parametrize("k1,k2", [(8, 6), (16, 16), (40, 25)])
+def test_svd_pencil(ctx, k1, k2):
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((300, 120))
+    U = rng.standard_normal((300, k1))
+    V = rng.standard_normal((120, k2))
+    B, MU, MV = U.T @ A @ V, U.T @ U, V.T @ V
+    print("svd pencil", k1, k2, flush=True)
+    s, Y, Z = ctx.svd_pencil(_cuda(B), _cuda(MU), _cuda(MV))
+    s, Y, Z = s.cpu().numpy(), Y.cpu().numpy(), Z.cpu().numpy()
+    s_ref, _, _ = O.svd_pencil(B, MU, MV)
+    np.testing.assert_allclose(s, s_ref[:min(k1, k2)], rtol=1e-11)
+    Ut, Vt = np.sqrt(2) * U @ Y, np.sqrt(2) * V @ Z
+    np.testing.assert_allclose(Ut.T @ Ut, np.eye(min(k1, k2)), atol=1e-9)
+    np.testing.assert_allclose(Vt.T @ Vt, np.eye(min(k1, k2)), atol=1e-9)
