@@ -96,8 +96,11 @@ typedef struct {
                                 Chebyshev degree), >= 1 */
     double lo, hi;           /* Chebyshev damping interval [lo, hi], lo < hi */
     double drop_tol;         /* Hessenberg column drop tolerance on |pivot| of a column
-                                scaled to infinity-norm (1/2, 1]; 0 -> unit roundoff of
-                                the basis storage type (Sec. 5.2) */
+                                scaled to infinity-norm (1/2, 1]; 0 -> machine epsilon of
+                                the arithmetic the sweep runs in (FP64 for the FP64 form,
+                                FP32 for reduced-precision phases, whose sweep works on
+                                the FP32 product before rounding; Sec. 5.2 ties the
+                                tolerance to the working precision) */
     double tol;              /* stop when all k relative residuals <= tol; 0 -> run
                                 exactly max_iters outer iterations */
     double anorm;            /* residual normaliser ||A||_2; 0 -> max |Ritz value| */
@@ -145,8 +148,9 @@ const char *ofrr_last_error(ofrr_ctx ctx);
  * milliseconds of the kernel family `name` since the last reset, measured
  * with HIP events on the context's stream.  Families: "quantize",
  * "product_bf16", "product_f16", "product_f8", "product_f64", "product_f32",
- * "spmm", "scale", "hessenberg", "gram", "small_eig", "lift",
- * "residual".  Returns OFRR_ERR_INVALID_ARG for an unknown name. */
+ * "product_reduce" (the fixed-order sum of split-K partials), "spmm",
+ * "scale", "hessenberg", "gram", "small_eig", "lift", "residual".
+ * Returns OFRR_ERR_INVALID_ARG for an unknown name. */
 ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches /*host*/,
                               double *total_ms /*host*/);
 ofrr_status ofrr_kernel_stats_reset(ofrr_ctx ctx);

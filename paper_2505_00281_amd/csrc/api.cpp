@@ -18,7 +18,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                              double *V, double *resid, ofrr_info *info);
 
 static const char *kFamilies[] = {"quantize", "product_bf16", "product_f16", "product_f8",
-                                  "product_f64", "product_f32", "spmm", "scale",
+                                  "product_f64", "product_f32", "product_reduce", "spmm", "scale",
                                   "hessenberg", "gram", "small_eig", "lift", "residual"};
 
 void *Workspace::get(const std::string &name, size_t bytes) {

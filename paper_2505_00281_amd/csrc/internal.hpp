@@ -34,6 +34,19 @@ struct Error {
         if (!(cond)) ::ofrr::fail(OFRR_ERR_INVALID_ARG, (msg));     \
     } while (0)
 
+// Phase switch test of the refined plans: a phase has stalled when its
+// residual estimate has not halved over the last `window` outer iterations.
+struct StallDetector {
+    int window;
+    std::vector<double> h;
+    bool push(double e) {
+        h.push_back(e);
+        const size_t w = (size_t)(window > 0 ? window : 1);
+        return h.size() > w && !(e <= 0.5 * h[h.size() - 1 - w]);
+    }
+    void reset() { h.clear(); }
+};
+
 // Per-family launch timing with HIP events recorded on the context stream
 // around each launch.  Events are resolved at the end of an API call.
 struct KernelTimer {

@@ -102,26 +102,30 @@ __device__ __forceinline__ f32x16_t mfma32x32x16(u32x4_t a, u32x4_t b, f32x16_t 
 // Operand layout of v_mfma_f32_32x32x16: lane l holds A[l%32][8(l/32)..+8]
 // and B[8(l/32)..+8][l%32]; the accumulator register r of lane l is
 // D[(r/4)*8 + 4(l/32) + r%4][l%32].
-constexpr int LP_BM = 128, LP_BN = 64, LP_BK = 32, LP_PAD = 40;
+constexpr int LP_BM = 128, LP_BK = 32, LP_PAD = 40;
 
-template <bool IS_BF16>
+// NB 32-column blocks per wave: the workgroup tile is 128 x (32*NB).
+template <bool IS_BF16, int NB>
 __global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t *__restrict__ A, int64_t lda,
                                                    int trans, int64_t m, int64_t kdim, int b,
                                                    const uint16_t *__restrict__ V,
                                                    const uint16_t *__restrict__ Vlo, int64_t ldv,
                                                    float *__restrict__ W, int64_t ldw,
                                                    int64_t k_per_split) {
+    constexpr int BN = 32 * NB;
     __shared__ __attribute__((aligned(16))) uint16_t As[LP_BM][LP_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[LP_BN][LP_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bls[LP_BN][LP_PAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LP_PAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bls[BN][LP_PAD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * LP_BM;
-    const int j0 = blockIdx.y * LP_BN;
+    const int j0 = blockIdx.y * BN;
     const int64_t kbeg = (int64_t)blockIdx.z * k_per_split;
     int64_t kend = kbeg + k_per_split;
     if (kend > kdim) kend = kdim;
     const bool split = Vlo != nullptr;
-    f32x16_t acc0 = {}, acc1 = {};
+    f32x16_t acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16_t{};
 
     for (int64_t k0 = kbeg; k0 < kend; k0 += LP_BK) {
         // ---- A tile: 128 rows x 32 k
@@ -170,9 +174,10 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t *__restrict__ 
                 for (int q = 0; q < 8; ++q) As[rc + q][kk] = tmp[q];
             }
         }
-        // ---- B tile: 32 k x 64 n, V row-major -> Bs[n][k]
-        {
-            const int kk = t >> 3, nc = (t & 7) * 8;
+        // ---- B tile: 32 k x (32*NB) n, V row-major -> Bs[n][k]
+#pragma unroll
+        for (int s = 0; s < NB / 2; ++s) {
+            const int kk = t >> 3, nc = (t & 7) * 8 + 64 * s;
             const int64_t gk = k0 + kk;
             uint16_t tmp[8], tmpl[8];
 #pragma unroll
@@ -192,15 +197,14 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t *__restrict__ 
         for (int kk = 0; kk < LP_BK; kk += 16) {
             const int kq = kk + 8 * (lane >> 5);
             const u32x4_t a = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq];
-            const u32x4_t b0 = *(const u32x4_t *)&Bs[(lane & 31)][kq];
-            const u32x4_t b1 = *(const u32x4_t *)&Bs[32 + (lane & 31)][kq];
-            acc0 = mfma32x32x16<IS_BF16>(a, b0, acc0);
-            acc1 = mfma32x32x16<IS_BF16>(a, b1, acc1);
-            if (split) {
-                const u32x4_t c0 = *(const u32x4_t *)&Bls[(lane & 31)][kq];
-                const u32x4_t c1 = *(const u32x4_t *)&Bls[32 + (lane & 31)][kq];
-                acc0 = mfma32x32x16<IS_BF16>(a, c0, acc0);
-                acc1 = mfma32x32x16<IS_BF16>(a, c1, acc1);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const u32x4_t bv = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq];
+                acc[nb] = mfma32x32x16<IS_BF16>(a, bv, acc[nb]);
+                if (split) {
+                    const u32x4_t cv = *(const u32x4_t *)&Bls[32 * nb + (lane & 31)][kq];
+                    acc[nb] = mfma32x32x16<IS_BF16>(a, cv, acc[nb]);
+                }
             }
         }
         __syncthreads();
@@ -211,9 +215,11 @@ __global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t *__restrict__ 
         const int i = (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
         const int64_t gi = i0 + 32 * wave + i;
         if (gi >= m) continue;
-        const int gj0 = j0 + (lane & 31), gj1 = gj0 + 32;
-        if (gj0 < b) Wz[gi * ldw + gj0] = acc0[r];
-        if (gj1 < b) Wz[gi * ldw + gj1] = acc1[r];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int gj = j0 + 32 * nb + (lane & 31);
+            if (gj < b) Wz[gi * ldw + gj] = acc[nb][r];
+        }
     }
 }
 
@@ -296,8 +302,10 @@ void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const
 void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                   int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
                   int64_t ldv, float *W, int64_t ldw) {
-    KTimer tm(ctx, t == OFRR_BF16 ? "product_bf16" : "product_f16");
-    const unsigned gx = (unsigned)((m + LP_BM - 1) / LP_BM), gy = (unsigned)((b + LP_BN - 1) / LP_BN);
+    // whole basis in one tile column when b > 64 (A is then streamed once)
+    const int NB = b > 64 ? 4 : 2;
+    const int BN = 32 * NB;
+    const unsigned gx = (unsigned)((m + LP_BM - 1) / LP_BM), gy = (unsigned)((b + BN - 1) / BN);
     // split K so that the launch has at least ~2 workgroups per CU
     int nsplit = 1;
     const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
@@ -307,14 +315,20 @@ void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uin
     float *dst = W;
     if (nsplit > 1) dst = ctx->buf<float>("lowp_slabs", (size_t)nsplit * m * ldw);
     dim3 grid(gx, gy, nsplit);
-    if (t == OFRR_BF16)
-        hipLaunchKernelGGL((k_gemm_lowp<true>), grid, dim3(256), 0, ctx->stream, A, lda, trans, m,
-                           kdim, b, V, Vlo, ldv, dst, ldw, kps);
-    else
-        hipLaunchKernelGGL((k_gemm_lowp<false>), grid, dim3(256), 0, ctx->stream, A, lda, trans, m,
-                           kdim, b, V, Vlo, ldv, dst, ldw, kps);
-    OFRR_HIP(hipGetLastError());
+    {
+        KTimer tm(ctx, t == OFRR_BF16 ? "product_bf16" : "product_f16");
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(256), 0, ctx->stream, A, lda, trans, m, kdim, b, V,
+                               Vlo, ldv, dst, ldw, kps);
+        };
+        if (t == OFRR_BF16)
+            NB == 4 ? go(k_gemm_lowp<true, 4>) : go(k_gemm_lowp<true, 2>);
+        else
+            NB == 4 ? go(k_gemm_lowp<false, 4>) : go(k_gemm_lowp<false, 2>);
+        OFRR_HIP(hipGetLastError());
+    }
     if (nsplit > 1) {
+        KTimer tm(ctx, "product_reduce");
         int64_t total = m * b;
         int g = (int)std::min<int64_t>((total + 255) / 256, 65536);
         hipLaunchKernelGGL(k_sum_slabs, dim3(g), dim3(256), 0, ctx->stream, dst, nsplit, m, b, ldw, W);

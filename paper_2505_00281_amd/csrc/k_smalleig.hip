@@ -374,8 +374,12 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
         LV[e] = 0.5 * (MV[i + j * k2] + MV[j + i * k2]);
     }
     __syncthreads();
-    if (!cholesky(LU, k1, w.flag) || !cholesky(LV, k2, w.flag)) {
+    if (!cholesky(LU, k1, w.flag)) {
         if (t == 0) *status = 3;
+        return;
+    }
+    if (!cholesky(LV, k2, w.flag)) {
+        if (t == 0) *status = 4;
         return;
     }
     // Cm = LU^{-1} B LV^{-T}  (k1 x k2): T = B^T (k2 x k1), T <- LV^{-1} T,
@@ -482,7 +486,8 @@ void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const dou
     int host = 0;
     OFRR_HIP(hipMemcpyAsync(&host, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
-    if (host == 3) fail(OFRR_ERR_NUMERIC, "svd pencil: mass matrix not positive definite");
+    if (host == 3) fail(OFRR_ERR_NUMERIC, "svd pencil: U^T U not positive definite");
+    if (host == 4) fail(OFRR_ERR_NUMERIC, "svd pencil: V^T V not positive definite");
     if (host == 2) fail(OFRR_ERR_NUMERIC, "svd pencil: Jacobi did not converge");
 }
 

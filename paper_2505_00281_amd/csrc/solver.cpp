@@ -189,8 +189,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     int32_t bc = basis;  // current basis size
     bool have_ax = false;
     int iters = 0, iters_low = 0;
-    int stall = 0;
-    double best_est = INFINITY;
+    StallDetector stall_det{plan->stall_iters};
     size_t pi = 0;
     std::vector<double> est((size_t)k);
     double anorm_used = plan->anorm;
@@ -198,7 +197,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     while (iters < plan->max_iters) {
         const Phase &ph = phases[pi];
         const ofrr_dtype mt = ph.master();
-        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(ph.basis);
+        // default drop tolerance: machine epsilon of the arithmetic the
+        // Hessenberg sweep runs in (FP32 for reduced-precision phases: it
+        // works on the FP32 product output before the basis is rounded to
+        // its storage type)
+        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(mt);
         // ---- filter
         // Y0 = X
         OFRR_HIP(hipMemcpyAsync(Y0, X, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
@@ -268,20 +271,14 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         const bool last_phase = pi + 1 == phases.size();
         if (last_phase && plan->tol > 0 && emax <= plan->tol) break;
         if (!last_phase) {
-            if (emax < 0.5 * best_est) {
-                best_est = emax;
-                stall = 0;
-            } else {
-                ++stall;
-            }
+            const bool stalled = stall_det.push(emax);
             const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
-            if (stall >= plan->stall_iters || by_value) {
+            if (stalled || by_value) {
                 // switch to the FP64 tail: promote X, recompute AX by a product
                 promote_block(ctx, n * ld, X);
                 ++pi;
                 have_ax = false;
-                best_est = INFINITY;
-                stall = 0;
+                stall_det.reset();
             }
         }
     }

@@ -10,6 +10,8 @@
 // turns it into V.  Restart is from all right Ritz vectors.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.hpp"
@@ -110,7 +112,8 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     };
     // scale, Hessenberg, compact into dst; returns kept columns
     auto stabilise = [&](void *Tin, int64_t rows, int32_t bc, void *dst) {
-        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff_svd(phases[pi]);
+        // machine epsilon of the sweep's arithmetic (FP32 in reduced phases)
+        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff_svd(master());
         scale_columns_pow2(ctx, master(), rows, bc, Tin, ld, master(), nullptr, ld, swork);
         const int32_t kept = hessenberg(ctx, master(), rows, bc, Tin, ld, tol, piv, keep, true);
         if (kept < k) fail(OFRR_ERR_NUMERIC, "svd: basis lost rank below k");
@@ -124,13 +127,43 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     };
 
     int32_t bv = basis;
-    int iters = 0, iters_low = 0, stall = 0;
-    double best = INFINITY, anorm = plan->anorm;
+    int iters = 0, iters_low = 0;
+    double anorm = plan->anorm;
+    StallDetector stall_det{plan->stall_iters};
     int32_t r = 0;
     std::vector<double> eh((size_t)k), sh((size_t)ld);
-    while (iters < plan->max_iters) {
-        const ofrr_dtype mt = master();
+    // Convergence test of the triplets of the previous iteration: the first
+    // product of an iteration is T1 = A V~ with V~ the previous right Ritz
+    // vectors, so ||A v~ - s u~|| comes for free.  (The other side,
+    // A^T u~ - s v~, lies in span(V) and is orthogonal to it by the Galerkin
+    // condition, i.e. it vanishes and tells nothing.)
+    bool have_prev = false;
+    const bool debug = std::getenv("OFRR_DEBUG") != nullptr;
+    while (true) {
+        ofrr_dtype mt = master();  // refreshed below if the phase changes
         product(0, Vb, T1, bv);
+        if (have_prev) {
+            col_resid(ctx, mt, m, k, T1, Ut, ld, sig, anorm, est);
+            OFRR_HIP(hipMemcpyAsync(eh.data(), est, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            double emax = 0.0;
+            for (double v : eh) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
+            if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "svd: non-finite residual estimate");
+            const bool last = pi + 1 == phases.size();
+            if (last && plan->tol > 0 && emax <= plan->tol) break;
+            if (!last) {
+                const bool stalled = stall_det.push(emax);
+                if (stalled || (plan->switch_resid > 0 && emax <= plan->switch_resid)) {
+                    // FP64 tail: promote the right block, redo its product in FP64
+                    promote_block(ctx, n * ld, Vb);
+                    ++pi;
+                    stall_det.reset();
+                    mt = master();
+                    product(0, Vb, T1, bv);
+                }
+            }
+        }
+        if (iters >= plan->max_iters) break;
         const int32_t bu = stabilise(T1, m, bv, Ub);
         product(1, Ub, T2, bu);
         OFRR_HIP(hipMemcpyAsync(Ts, T2, bn * esz(), hipMemcpyDeviceToDevice, ctx->stream));
@@ -138,45 +171,41 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         gram_rect(ctx, n, bu, bv, mt, Ts, ld, mt, Vb, ld, B);
         gram_rect(ctx, m, bu, bu, mt, Ub, ld, mt, Ub, ld, MU);
         gram_rect(ctx, n, bv, bv, mt, Vb, ld, mt, Vb, ld, MV);
+        if (debug) {
+            std::vector<double> mu((size_t)bu * bu), mv((size_t)bv * bv);
+            OFRR_HIP(hipMemcpyAsync(mu.data(), MU, sizeof(double) * bu * bu, hipMemcpyDeviceToHost, ctx->stream));
+            OFRR_HIP(hipMemcpyAsync(mv.data(), MV, sizeof(double) * bv * bv, hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            double dmin_u = INFINITY, dmin_v = INFINITY, dmax_u = 0, dmax_v = 0;
+            for (int i = 0; i < bu; ++i) {
+                dmin_u = std::min(dmin_u, mu[(size_t)i * bu + i]);
+                dmax_u = std::max(dmax_u, mu[(size_t)i * bu + i]);
+            }
+            for (int i = 0; i < bv; ++i) {
+                dmin_v = std::min(dmin_v, mv[(size_t)i * bv + i]);
+                dmax_v = std::max(dmax_v, mv[(size_t)i * bv + i]);
+            }
+            std::fprintf(stderr, "[ofrr svd] iter %d phase %zu bu %d bv %d diag(MU) [%g, %g] diag(MV) [%g, %g]\n",
+                         iters, pi, bu, bv, dmin_u, dmax_u, dmin_v, dmax_v);
+        }
         svd_pencil(ctx, bu, bv, B, MU, MV, sig, Ys, Zs);
         r = std::min(bu, bv);
         scale_array(ctx, (int64_t)bu * r, Ys, std::sqrt(2.0));
         scale_array(ctx, (int64_t)bv * r, Zs, std::sqrt(2.0));
-        // U~ = U Y, V~ = V Z, A^T U~ = T Y (free), one-sided estimate
+        // U~ = U Y, V~ = V Z (orthonormal by the Theorem of Sec. 3.2)
         lift(ctx, m, bu, r, mt, Ub, ld, mt, nullptr, 0, Ys, bu, nullptr, mt, Ut, nullptr, ld, nullptr, nullptr);
         lift(ctx, n, bv, r, mt, Vb, ld, mt, nullptr, 0, Zs, bv, nullptr, mt, Vt, nullptr, ld, nullptr, nullptr);
-        lift(ctx, n, bu, r, mt, Ts, ld, mt, nullptr, 0, Ys, bu, nullptr, mt, T2, nullptr, ld, nullptr, nullptr);
         ++iters;
         if (phases[pi] != OFRR_F64) ++iters_low;
         OFRR_HIP(hipMemcpyAsync(sh.data(), sig, sizeof(double) * r, hipMemcpyDeviceToHost, ctx->stream));
         ctx->sync();
         if (plan->anorm <= 0) anorm = sh[0] > 0 ? sh[0] : 1.0;
-        col_resid(ctx, mt, n, k, T2, Vt, ld, sig, anorm, est);
-        OFRR_HIP(hipMemcpyAsync(eh.data(), est, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-        ctx->sync();
-        double emax = 0.0;
-        for (double v : eh) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
-        if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "svd: non-finite residual estimate");
         // restart from all right Ritz vectors
         std::swap(Vb, Vt);
         bv = r;
-        const bool last = pi + 1 == phases.size();
-        if (last && plan->tol > 0 && emax <= plan->tol) break;
-        if (!last) {
-            if (emax < 0.5 * best) {
-                best = emax;
-                stall = 0;
-            } else {
-                ++stall;
-            }
-            if (stall >= plan->stall_iters || (plan->switch_resid > 0 && emax <= plan->switch_resid)) {
-                promote_block(ctx, n * ld, Vb);
-                promote_block(ctx, m * ld, Ut);
-                ++pi;
-                best = INFINITY;
-                stall = 0;
-            }
-        }
+        have_prev = true;
+        // a same-step run (tol = 0) ends after max_iters projections
+        if (plan->tol <= 0 && iters >= plan->max_iters) break;
     }
     // final FP64 residuals from A as stored: U~ (m x k), V~ (n x k)
     const ofrr_dtype mt = master();

@@ -83,8 +83,22 @@ def test_eig_csr_laplacian_smallest_fp64_same_step(ctx):
                          lo=float(ev[b]), hi=8.0, outer=10, anorm=8.0)
     th = r.evals.cpu().numpy()
     np.testing.assert_allclose(th, ref.theta, rtol=1e-12)
-    # exact double eigenvalues: compare spans of the returned vectors, not vectors
-    np.testing.assert_allclose(r.resid.cpu().numpy(), ref.resid, rtol=1e-5, atol=1e-12)
+    # the Laplacian has exact double eigenvalues: inside such a cluster the
+    # individual Ritz vectors (and their residuals) are not unique, but the
+    # cluster's residual norm sqrt(sum r_i^2) and its span are
+    res, rres = r.resid.cpu().numpy(), ref.resid
+    X = r.evecs.cpu().numpy()
+    i = 0
+    while i < k:
+        j = i + 1
+        while j < k and abs(ref.theta[j] - ref.theta[i]) <= 1e-9 * abs(ref.theta[i]):
+            j += 1
+        np.testing.assert_allclose(np.linalg.norm(res[i:j]), np.linalg.norm(rres[i:j]), rtol=1e-3,
+                                   atol=1e-11)
+        if j == k and j - i > 1:
+            break  # the cluster may continue past k: its span within the first k is not unique
+        assert O.subspace_sin(X[:, i:j], ref.X[:, i:j]) < 1e-6
+        i = j
 
 
 def test_eig_csr_malformed_is_rejected(ctx):
@@ -194,8 +208,26 @@ def test_svd_converged_fp64(ctx):
     A = W.svd_prescribed(m, n, sig, 41, dtype=torch.float64)
     print("svd converged fp64", flush=True)
     r = ctx.svd_partial(A.cuda(), k, b, plan=_plan(tol=1e-12, max_iters=300))
+    print("info", r.info, flush=True)
+    assert r.info["iters"] > 5
     np.testing.assert_allclose(r.sigma.cpu().numpy(), sig[:k], rtol=1e-12)
-    assert r.resid.cpu().numpy().max() <= 1e-12
+    assert r.resid.cpu().numpy().max() <= 2e-12
+
+
+@pytest.mark.parametrize("lowp", ["bf16", "f16"])
+def test_svd_mixed_refined_converged(ctx, lowp):
+    m, n, b, k = 1500, 400, 24, 10
+    sig = np.exp(-np.arange(1, n + 1) / 40.0)
+    A = W.svd_prescribed(m, n, sig, 43, dtype=torch.float32)
+    Ad = A.double().numpy()
+    s_ref = np.linalg.svd(Ad, compute_uv=False)
+    print("svd mixed", lowp, flush=True)
+    r = ctx.svd_partial(A.cuda(), k, b, plan=_plan(basis_dtype=lowp, refine=True, tol=1e-9,
+                                                    max_iters=400))
+    print("info", r.info, flush=True)
+    assert r.info["iters_low"] >= 1
+    assert r.resid.cpu().numpy().max() <= 1e-8
+    np.testing.assert_allclose(r.sigma.cpu().numpy(), s_ref[:k], rtol=1e-10)
 
 
 def test_batched_matches_single(ctx):
