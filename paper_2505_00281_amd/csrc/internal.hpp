@@ -144,11 +144,22 @@ void promote_block(Context *ctx, int64_t count, void *buf);
 // k_product.hip
 void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const double *V,
                  int64_t ldv, double *W, int64_t ldw);
-// A BF16/F16 (dense, uint16 bits, ld), V in the same type, W FP32.
-// vlo (may be null): low halves of a two-term split of V.
+// k_gemm_lp.hip.  A BF16/F16 (dense, uint16 bits, column-major, lda), W FP32
+// row-major.  product_lowp takes a row-major basis V (vlo, may be null: low
+// halves of a two-term split); product_lowp_t takes it K-contiguous per
+// column (Vt[j*ldvt + k]) as written by split_block_t.
 void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                   int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
                   int64_t ldv, float *W, int64_t ldw);
+void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
+                    int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
+                    int64_t ldvt, float *W, int64_t ldw);
+// leading dimension of the K-contiguous basis copy for `rows` rows
+int64_t lowp_ldt(int64_t rows);
+// FP32 row-major block (rows x b, ld) -> hi (and lo) BF16/F16 bits in the
+// K-contiguous layout (b x rows, ldt)
+void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const float *src,
+                   int64_t ld, uint16_t *hi, uint16_t *lo, int64_t ldt);
 // Validates a CSR descriptor's structure on the device (row_ptr[0] == 0,
 // non-decreasing, row_ptr[rows] == nnz, column indices in range); fails
 // with OFRR_ERR_INVALID_ARG otherwise.

@@ -1,0 +1,321 @@
+// k_gemm_lp.hip -- the reduced-precision block product W = op(A) V of the
+// basis build (Sec. 2: X_{iter} = A^{iter} X_0; Sec. 4: A and the basis in
+// reduced precision, products accumulated in FP32), on BF16/F16 MFMA.
+//
+// The product is bound by streaming A from HBM (2 n^2 bytes against
+// 2 n^2 b flops: about b flop per byte, below the BF16 ridge), so the kernel
+// is organised around keeping HBM busy:
+//   * the basis operand arrives K-contiguous per column (the split kernel
+//     writes it that way), so both operands load as 16-byte vectors and are
+//     stored to LDS without transposition (for K-contiguous A);
+//   * 64-deep K slices, the next slice prefetched into registers while the
+//     MFMAs consume the current one;
+//   * one 128-row x (32 NB)-column tile per workgroup covers the whole basis
+//     (NB = 4 for b <= 128), so A is read exactly once;
+//   * split-K fills the chip; the workgroup -> (tile, split) map sends all
+//     workgroups of one K range to the same XCD(s), so that range of the
+//     basis stays in one L2; the FP32 partials are summed in a fixed order.
+// MFMA v_mfma_f32_32x32x16: lane l holds A[l%32][8(l/32)..+8] and
+// B[8(l/32)..+8][l%32]; accumulator register r of lane l is
+// D[(r/4)*8 + 4(l/32) + r%4][l%32].
+#include "internal.hpp"
+#include "device_util.hpp"
+
+namespace ofrr {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4_t;
+
+template <bool IS_BF16>
+__device__ __forceinline__ f32x16_t mfma_32x32x16(u32x4_t a, u32x4_t b, f32x16_t c) {
+    if constexpr (IS_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                       __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a),
+                                                      __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
+}
+
+constexpr int GL_BM = 128;  // rows per workgroup tile
+constexpr int GL_BK = 64;   // K depth per slice
+constexpr int GL_LD = 72;   // LDS row stride in halves (144 B, 16-byte aligned)
+
+// 8 halves starting at p, zero beyond `valid` (and for misaligned p).
+__device__ __forceinline__ u32x4_t load8(const uint16_t *p, int64_t valid) {
+    if (valid >= 8 && (((uintptr_t)p) & 15) == 0) return *(const u32x4_t *)p;
+    uint16_t tmp[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tmp[q] = (q < valid) ? p[q] : (uint16_t)0;
+    return __builtin_bit_cast(u32x4_t, tmp);
+}
+
+// ATRANS: op(A)[i][k] = A[k + i*lda] (K-contiguous); else A[i + k*lda].
+template <bool IS_BF16, int NB, bool ATRANS, bool SPLITV>
+__global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A, int64_t lda,
+                                                 int64_t m, int64_t kdim, int b,
+                                                 const uint16_t *__restrict__ Vt,
+                                                 const uint16_t *__restrict__ Vtlo, int64_t ldvt,
+                                                 float *__restrict__ W, int64_t ldw,
+                                                 int64_t k_per_split, int ntiles, int nsplit,
+                                                 int xcd_map) {
+    constexpr int BN = 32 * NB;
+    __shared__ __attribute__((aligned(16))) uint16_t As[GL_BM][GL_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][GL_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bls[SPLITV ? BN : 1][GL_LD];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+
+    // workgroup -> (tile, split)
+    int tile, z;
+    const int L = blockIdx.x;
+    if (xcd_map) {
+        const int xcd = L & 7, slot = L >> 3, per = 8 / nsplit;
+        z = xcd % nsplit;
+        tile = slot * per + xcd / nsplit;
+    } else {
+        tile = L % ntiles;
+        z = L / ntiles;
+    }
+    if (tile >= ntiles) return;
+    const int gy = (b + BN - 1) / BN;
+    const int64_t i0 = (int64_t)(tile / gy) * GL_BM;
+    const int j0 = (tile % gy) * BN;
+    const int64_t kbeg = (int64_t)z * k_per_split;
+    const int64_t kend = kbeg + k_per_split < kdim ? kbeg + k_per_split : kdim;
+
+    f32x16_t acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16_t{};
+
+    // register staging of one K slice: A 4 chunks, B NB chunks (+NB lo)
+    u32x4_t ra[4], rb[NB], rl[SPLITV ? NB : 1];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int c = t + 256 * s;
+            if (ATRANS) {
+                const int row = c >> 3, kc = (c & 7) * 8;
+                const int64_t gi = i0 + row, gk = k0 + kc;
+                ra[s] = (gi < m) ? load8(A + gk + gi * lda, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
+            } else {
+                const int kk = c >> 4, rc = (c & 15) * 8;
+                const int64_t gk = k0 + kk, gi = i0 + rc;
+                ra[s] = (gk < kend) ? load8(A + gi + gk * lda, m - gi) : u32x4_t{0u, 0u, 0u, 0u};
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            const int c = t + 256 * s;
+            const int col = c >> 3, kc = (c & 7) * 8;
+            const int64_t gk = k0 + kc;
+            const bool ok = j0 + col < b;
+            rb[s] = ok ? load8(Vt + (int64_t)(j0 + col) * ldvt + gk, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
+            if constexpr (SPLITV)
+                rl[s] = ok ? load8(Vtlo + (int64_t)(j0 + col) * ldvt + gk, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int c = t + 256 * s;
+            if (ATRANS) {
+                *(u32x4_t *)&As[c >> 3][(c & 7) * 8] = ra[s];
+            } else {
+                const int kk = c >> 4, rc = (c & 15) * 8;
+                uint16_t tmp[8];
+                __builtin_memcpy(tmp, &ra[s], 16);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) As[rc + q][kk] = tmp[q];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            const int c = t + 256 * s;
+            *(u32x4_t *)&Bs[c >> 3][(c & 7) * 8] = rb[s];
+            if constexpr (SPLITV) *(u32x4_t *)&Bls[c >> 3][(c & 7) * 8] = rl[s];
+        }
+    };
+
+    if (kbeg < kend) fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += GL_BK) {
+        stash();
+        __syncthreads();
+        if (k0 + GL_BK < kend) fetch(k0 + GL_BK);
+#pragma unroll
+        for (int kk = 0; kk < GL_BK; kk += 16) {
+            const int kq = kk + 8 * (lane >> 5);
+            const u32x4_t a = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const u32x4_t bv = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq];
+                acc[nb] = mfma_32x32x16<IS_BF16>(a, bv, acc[nb]);
+                if constexpr (SPLITV) {
+                    const u32x4_t cv = *(const u32x4_t *)&Bls[32 * nb + (lane & 31)][kq];
+                    acc[nb] = mfma_32x32x16<IS_BF16>(a, cv, acc[nb]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *Wz = W + (int64_t)z * m * ldw;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
+        const int64_t gi = i0 + 32 * wave + i;
+        if (gi >= m) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int gj = j0 + 32 * nb + (lane & 31);
+            if (gj < b) Wz[gi * ldw + gj] = acc[nb][r];
+        }
+    }
+}
+
+// Sum of split-K partial slabs in fixed order (deterministic).
+__global__ void k_sum_slabs(const float *__restrict__ P, int nsplit, int64_t m, int b, int64_t ld,
+                            float *__restrict__ W) {
+    const int64_t total = m * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        float s = 0.f;
+        for (int zz = 0; zz < nsplit; ++zz) s += P[(int64_t)zz * m * ld + i * ld + j];
+        W[i * ld + j] = s;
+    }
+}
+
+// row-major (rows x b, ld) 16-bit block -> column-major (b x rows, ldt)
+__global__ void k_transpose_u16(const uint16_t *__restrict__ s, int64_t rows, int b, int64_t ld,
+                                uint16_t *__restrict__ d, int64_t ldt) {
+    const int64_t total = rows * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / rows);
+        const int64_t i = e - (int64_t)j * rows;
+        d[(int64_t)j * ldt + i] = s[i * ld + j];
+    }
+}
+
+template <bool BF16>
+__global__ void k_split_t(const float *__restrict__ s, int64_t rows, int b, int64_t ld,
+                          uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldt) {
+    const int64_t total = rows * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        const float x = s[i * ld + j];
+        const uint16_t h = BF16 ? f32_to_bf16_bits(x) : f32_to_f16_bits(x);
+        hi[(int64_t)j * ldt + i] = h;
+        if (lo) {
+            const float hv = BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
+            const float r = x - hv;  // exact: x and hv share their leading bits
+            lo[(int64_t)j * ldt + i] = BF16 ? f32_to_bf16_bits(r) : f32_to_f16_bits(r);
+        }
+    }
+}
+
+inline int grid1(int64_t total) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+}
+
+}  // namespace
+
+int64_t lowp_ldt(int64_t rows) { return (rows + 7) / 8 * 8; }
+
+void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const float *src,
+                   int64_t ld, uint16_t *hi, uint16_t *lo, int64_t ldt) {
+    if (t == OFRR_BF16)
+        hipLaunchKernelGGL((k_split_t<true>), dim3(grid1(rows * b)), dim3(256), 0, ctx->stream, src,
+                           rows, b, ld, hi, lo, ldt);
+    else if (t == OFRR_F16)
+        hipLaunchKernelGGL((k_split_t<false>), dim3(grid1(rows * b)), dim3(256), 0, ctx->stream, src,
+                           rows, b, ld, hi, lo, ldt);
+    else
+        fail(OFRR_ERR_UNSUPPORTED, "split_block_t: BF16 or F16");
+    OFRR_HIP(hipGetLastError());
+}
+
+void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
+                    int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
+                    int64_t ldvt, float *W, int64_t ldw) {
+    OFRR_CHECK_ARG(b >= 1 && b <= 4096, "product: 1 <= b <= 4096");
+    const int NB = b > 64 ? 4 : 2;
+    const int BN = 32 * NB;
+    const int gx = (int)((m + GL_BM - 1) / GL_BM), gy = (b + BN - 1) / BN;
+    const int ntiles = gx * gy;
+    // split K so that the launch has at least ~2 workgroups per CU
+    int nsplit = 1;
+    const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
+    while ((int64_t)ntiles * nsplit < want && kdim / (nsplit * 2) >= 2048 && nsplit < 8) nsplit *= 2;
+    int64_t kps = (kdim + nsplit - 1) / nsplit;
+    kps = (kps + GL_BK - 1) / GL_BK * GL_BK;
+    nsplit = (int)((kdim + kps - 1) / kps);
+    // XCD-aware map when the splits divide the 8 XCDs evenly
+    const int xcd_map = (nsplit >= 2 && 8 % nsplit == 0) ? 1 : 0;
+    int64_t nwg = (int64_t)ntiles * nsplit;
+    if (xcd_map) {
+        const int per = 8 / nsplit;
+        nwg = (int64_t)((ntiles + per - 1) / per) * 8;
+    }
+    float *dst = W;
+    if (nsplit > 1) dst = ctx->buf<float>("lowp_slabs", (size_t)nsplit * m * ldw);
+    const bool splitv = Vtlo != nullptr;
+    {
+        KTimer tm(ctx, t == OFRR_BF16 ? "product_bf16" : "product_f16");
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, A, lda, m, kdim, b,
+                               Vt, Vtlo, ldvt, dst, ldw, kps, ntiles, nsplit, xcd_map);
+        };
+#define OFRR_GO(BFV, NBV, TR, SP) go(k_gemm_lp<BFV, NBV, TR, SP>)
+        const bool bf = t == OFRR_BF16;
+        const bool tr = trans != 0;
+        if (bf) {
+            if (NB == 4) {
+                if (tr) { if (splitv) OFRR_GO(true, 4, true, true); else OFRR_GO(true, 4, true, false); }
+                else { if (splitv) OFRR_GO(true, 4, false, true); else OFRR_GO(true, 4, false, false); }
+            } else {
+                if (tr) { if (splitv) OFRR_GO(true, 2, true, true); else OFRR_GO(true, 2, true, false); }
+                else { if (splitv) OFRR_GO(true, 2, false, true); else OFRR_GO(true, 2, false, false); }
+            }
+        } else {
+            if (NB == 4) {
+                if (tr) { if (splitv) OFRR_GO(false, 4, true, true); else OFRR_GO(false, 4, true, false); }
+                else { if (splitv) OFRR_GO(false, 4, false, true); else OFRR_GO(false, 4, false, false); }
+            } else {
+                if (tr) { if (splitv) OFRR_GO(false, 2, true, true); else OFRR_GO(false, 2, true, false); }
+                else { if (splitv) OFRR_GO(false, 2, false, true); else OFRR_GO(false, 2, false, false); }
+            }
+        }
+#undef OFRR_GO
+        OFRR_HIP(hipGetLastError());
+    }
+    if (nsplit > 1) {
+        KTimer tm(ctx, "product_reduce");
+        hipLaunchKernelGGL(k_sum_slabs, dim3(grid1(m * b)), dim3(256), 0, ctx->stream, dst, nsplit, m, b,
+                           ldw, W);
+        OFRR_HIP(hipGetLastError());
+    }
+}
+
+void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
+                  int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
+                  int64_t ldv, float *W, int64_t ldw) {
+    // row-major basis -> the K-contiguous layout the kernel streams
+    const int64_t ldt = lowp_ldt(kdim);
+    uint16_t *Vt = ctx->buf<uint16_t>("lowp_vt", (size_t)b * ldt);
+    uint16_t *Vtl = Vlo ? ctx->buf<uint16_t>("lowp_vtlo", (size_t)b * ldt) : nullptr;
+    hipLaunchKernelGGL(k_transpose_u16, dim3(grid1(kdim * b)), dim3(256), 0, ctx->stream, V, kdim, b,
+                       ldv, Vt, ldt);
+    if (Vlo)
+        hipLaunchKernelGGL(k_transpose_u16, dim3(grid1(kdim * b)), dim3(256), 0, ctx->stream, Vlo, kdim,
+                           b, ldv, Vtl, ldt);
+    OFRR_HIP(hipGetLastError());
+    product_lowp_t(ctx, t, m, kdim, A, lda, trans, b, Vt, Vtl, ldt, W, ldw);
+}
+
+}  // namespace ofrr

@@ -3,9 +3,7 @@
 // with FP32 accumulation).
 //
 //   product_f64   FP64 arithmetic, A dense FP64 or FP32 (promoted exactly).
-//   product_lowp  A and V in BF16 or F16, MFMA 32x32x16 with FP32
-//                 accumulation; optional two-term split of V (V = Vhi + Vlo)
-//                 carried through a second MFMA on the same A fragment.
+//   (the BF16/F16 MFMA product is in k_gemm_lp.hip)
 //   product_csr   CSR A (FP32/FP64 values), one wavefront per row.
 //
 // Blocks V and W are row-major (element (i, j) at i*ld + j); A is the
@@ -18,223 +16,93 @@ namespace ofrr {
 namespace {
 
 // ------------------------------------------------------------------ FP64 --
-// W (m x b) = op(A) (m x kdim) * V (kdim x b).  64 x 64 output tile per
-// 256-thread workgroup, 16-deep K slices staged in LDS, 4 x 4 outputs per
-// thread.
+// W (m x b) = op(A) (m x kdim) * V (kdim x b) on FP64 MFMA
+// (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16];
+// accumulator register r of lane l is D[4(l/16) + r][l%16]).  64 x 64
+// output tile per 256-thread workgroup (2 x 2 waves, each 2 x 2 MFMA
+// blocks), 16-deep K slices staged in LDS; the next slice is loaded into
+// registers while the current one is multiplied.
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4_t;
+
+template <class TA>
+__device__ __forceinline__ void f64_tile_load(const TA *__restrict__ A, int64_t lda, int trans,
+                                              int64_t m, int64_t kdim, int b,
+                                              const double *__restrict__ V, int64_t ldv,
+                                              int64_t i0, int j0, int64_t k0, int t, double (&ra)[4],
+                                              double (&rv)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        int ii, kk;
+        if (trans) {  // contiguous in k: 4 consecutive k per thread
+            ii = t >> 2;
+            kk = (t & 3) * 4 + s;
+        } else {  // contiguous in i: 4 consecutive i per thread
+            kk = t >> 4;
+            ii = (t & 15) * 4 + s;
+        }
+        const int64_t gi = i0 + ii, gk = k0 + kk;
+        ra[s] = (gi < m && gk < kdim) ? (double)(trans ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
+        const int vk = t >> 4, vj = (t & 15) * 4 + s;
+        const int64_t gvk = k0 + vk;
+        rv[s] = (gvk < kdim && j0 + vj < b) ? V[gvk * ldv + j0 + vj] : 0.0;
+    }
+}
+
 template <class TA>
 __global__ __launch_bounds__(256) void k_gemm_f64(const TA *__restrict__ A, int64_t lda, int trans,
                                                   int64_t m, int64_t kdim, int b,
                                                   const double *__restrict__ V, int64_t ldv,
                                                   double *__restrict__ W, int64_t ldw) {
-    __shared__ double As[16][64 + 1];
-    __shared__ double Vs[16][64 + 1];
-    const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
+    __shared__ double As[16][64 + 2];
+    __shared__ double Vs[16][64 + 2];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
     const int64_t i0 = (int64_t)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
-    double acc[4][4] = {};
+    f64x4_t acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    double ra[4], rv[4];
+    f64_tile_load(A, lda, trans, m, kdim, b, V, ldv, i0, j0, 0, t, ra, rv);
     for (int64_t k0 = 0; k0 < kdim; k0 += 16) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int e = t + 256 * s;
-            int ii, kk;
-            if (!trans) {
-                ii = e & 63;
-                kk = e >> 6;
-            } else {
-                kk = e & 15;
-                ii = e >> 4;
-            }
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            double v = 0.0;
-            if (gi < m && gk < kdim) v = (double)(trans ? A[gk + gi * lda] : A[gi + gk * lda]);
-            As[kk][ii] = v;
-            const int vk = e >> 6, vj = e & 63;
-            const int64_t gvk = k0 + vk;
-            Vs[vk][vj] = (gvk < kdim && j0 + vj < b) ? V[gvk * ldv + j0 + vj] : 0.0;
+            if (trans)
+                As[(t & 3) * 4 + s][t >> 2] = ra[s];
+            else
+                As[t >> 4][(t & 15) * 4 + s] = ra[s];
+            Vs[t >> 4][(t & 15) * 4 + s] = rv[s];
         }
         __syncthreads();
+        if (k0 + 16 < kdim) f64_tile_load(A, lda, trans, m, kdim, b, V, ldv, i0, j0, k0 + 16, t, ra, rv);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], v[4];
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            double a[2], bb[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
+            for (int p = 0; p < 2; ++p) a[p] = As[kr][32 * wr + 16 * p + (lane & 15)];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = Vs[kk][tx + 16 * c];
+            for (int q = 0; q < 2; ++q) bb[q] = Vs[kr][32 * wc + 16 * q + (lane & 15)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], v[c], acc[r][c]);
+                for (int q = 0; q < 2; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], bb[q], acc[p][q], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + ty + 16 * r;
-        if (gi >= m) continue;
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int gj = j0 + tx + 16 * c;
-            if (gj < b) W[gi * ldw + gj] = acc[r][c];
-        }
-    }
-}
-
-// ------------------------------------------------------- BF16 / F16 MFMA --
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
-typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4_t;
-
-template <bool IS_BF16>
-__device__ __forceinline__ f32x16_t mfma32x32x16(u32x4_t a, u32x4_t b, f32x16_t c) {
-    if constexpr (IS_BF16)
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
-                                                       __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
-    else
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a),
-                                                      __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
-}
-
-// Tile: 128 rows x 64 cols of W per 256-thread workgroup (each wave 32 rows x
-// 64 cols = two 32x32 MFMA blocks), 32-deep K slices.  LDS rows are padded
-// (40 halves = 80 B) to spread the 16-byte fragment reads over the banks.
-// Operand layout of v_mfma_f32_32x32x16: lane l holds A[l%32][8(l/32)..+8]
-// and B[8(l/32)..+8][l%32]; the accumulator register r of lane l is
-// D[(r/4)*8 + 4(l/32) + r%4][l%32].
-constexpr int LP_BM = 128, LP_BK = 32, LP_PAD = 40;
-
-// NB 32-column blocks per wave: the workgroup tile is 128 x (32*NB).
-template <bool IS_BF16, int NB>
-__global__ __launch_bounds__(256) void k_gemm_lowp(const uint16_t *__restrict__ A, int64_t lda,
-                                                   int trans, int64_t m, int64_t kdim, int b,
-                                                   const uint16_t *__restrict__ V,
-                                                   const uint16_t *__restrict__ Vlo, int64_t ldv,
-                                                   float *__restrict__ W, int64_t ldw,
-                                                   int64_t k_per_split) {
-    constexpr int BN = 32 * NB;
-    __shared__ __attribute__((aligned(16))) uint16_t As[LP_BM][LP_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LP_PAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bls[BN][LP_PAD];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * LP_BM;
-    const int j0 = blockIdx.y * BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * k_per_split;
-    int64_t kend = kbeg + k_per_split;
-    if (kend > kdim) kend = kdim;
-    const bool split = Vlo != nullptr;
-    f32x16_t acc[NB];
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16_t{};
-
-    for (int64_t k0 = kbeg; k0 < kend; k0 += LP_BK) {
-        // ---- A tile: 128 rows x 32 k
-        if (trans) {
-            // op(A)[i][k] = A[k + i*lda]: contiguous in k; 4 threads per row
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int row = (t >> 2) + 64 * s, kc = (t & 3) * 8;
-                const int64_t gi = i0 + row, gk = k0 + kc;
-                u32x4_t v = {0u, 0u, 0u, 0u};
-                if (gi < m) {
-                    const uint16_t *p = A + gk + gi * lda;
-                    if (gk + 8 <= kend && (((uintptr_t)p) & 15) == 0) {
-                        v = *(const u32x4_t *)p;
-                    } else {
-                        uint16_t tmp[8];
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) tmp[q] = (gk + q < kend) ? p[q] : (uint16_t)0;
-                        v = __builtin_bit_cast(u32x4_t, tmp);
-                    }
-                }
-                *(u32x4_t *)&As[row][kc] = v;
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = i0 + 32 * wr + 16 * p + 4 * (lane >> 4) + r;
+                const int gj = j0 + 32 * wc + 16 * q + (lane & 15);
+                if (gi < m && gj < b) W[gi * ldw + gj] = acc[p][q][r];
             }
-        } else {
-            // op(A)[i][k] = A[i + k*lda]: contiguous in i; 16 threads per k column
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int e = t + 256 * s;
-                const int kk = e >> 4, rc = (e & 15) * 8;
-                const int64_t gk = k0 + kk, gi = i0 + rc;
-                uint16_t tmp[8];
-                if (gk < kend) {
-                    const uint16_t *p = A + gi + gk * lda;
-                    if (gi + 8 <= m && (((uintptr_t)p) & 15) == 0) {
-                        u32x4_t v = *(const u32x4_t *)p;
-                        __builtin_memcpy(tmp, &v, 16);
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) tmp[q] = (gi + q < m) ? p[q] : (uint16_t)0;
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) tmp[q] = 0;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) As[rc + q][kk] = tmp[q];
-            }
-        }
-        // ---- B tile: 32 k x (32*NB) n, V row-major -> Bs[n][k]
-#pragma unroll
-        for (int s = 0; s < NB / 2; ++s) {
-            const int kk = t >> 3, nc = (t & 7) * 8 + 64 * s;
-            const int64_t gk = k0 + kk;
-            uint16_t tmp[8], tmpl[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const bool ok = gk < kend && j0 + nc + q < b;
-                tmp[q] = ok ? V[gk * ldv + j0 + nc + q] : (uint16_t)0;
-                tmpl[q] = (ok && split) ? Vlo[gk * ldv + j0 + nc + q] : (uint16_t)0;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                Bs[nc + q][kk] = tmp[q];
-                Bls[nc + q][kk] = tmpl[q];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < LP_BK; kk += 16) {
-            const int kq = kk + 8 * (lane >> 5);
-            const u32x4_t a = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const u32x4_t bv = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq];
-                acc[nb] = mfma32x32x16<IS_BF16>(a, bv, acc[nb]);
-                if (split) {
-                    const u32x4_t cv = *(const u32x4_t *)&Bls[32 * nb + (lane & 31)][kq];
-                    acc[nb] = mfma32x32x16<IS_BF16>(a, cv, acc[nb]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    float *Wz = W + (int64_t)blockIdx.z * m * ldw;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
-        const int64_t gi = i0 + 32 * wave + i;
-        if (gi >= m) continue;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int gj = j0 + 32 * nb + (lane & 31);
-            if (gj < b) Wz[gi * ldw + gj] = acc[nb][r];
-        }
-    }
-}
-
-// Sum of split-K partial slabs in fixed order (deterministic).
-__global__ void k_sum_slabs(const float *__restrict__ P, int nsplit, int64_t m, int b, int64_t ld,
-                            float *__restrict__ W) {
-    const int64_t total = m * b;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / b;
-        const int j = (int)(e - i * b);
-        float s = 0.f;
-        for (int z = 0; z < nsplit; ++z) s += P[(int64_t)z * m * ld + i * ld + j];
-        W[i * ld + j] = s;
-    }
 }
 
 // -------------------------------------------------------------- CSR SpMM --
@@ -297,43 +165,6 @@ void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const
     else
         fail(OFRR_ERR_UNSUPPORTED, "product_f64: A must be F64 or F32");
     OFRR_HIP(hipGetLastError());
-}
-
-void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
-                  int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
-                  int64_t ldv, float *W, int64_t ldw) {
-    // whole basis in one tile column when b > 64 (A is then streamed once)
-    const int NB = b > 64 ? 4 : 2;
-    const int BN = 32 * NB;
-    const unsigned gx = (unsigned)((m + LP_BM - 1) / LP_BM), gy = (unsigned)((b + BN - 1) / BN);
-    // split K so that the launch has at least ~2 workgroups per CU
-    int nsplit = 1;
-    const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
-    while ((int64_t)gx * gy * nsplit < want && kdim / (nsplit * 2) >= 1024) nsplit *= 2;
-    int64_t kps = (kdim + nsplit - 1) / nsplit;
-    kps = (kps + LP_BK - 1) / LP_BK * LP_BK;
-    float *dst = W;
-    if (nsplit > 1) dst = ctx->buf<float>("lowp_slabs", (size_t)nsplit * m * ldw);
-    dim3 grid(gx, gy, nsplit);
-    {
-        KTimer tm(ctx, t == OFRR_BF16 ? "product_bf16" : "product_f16");
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, grid, dim3(256), 0, ctx->stream, A, lda, trans, m, kdim, b, V,
-                               Vlo, ldv, dst, ldw, kps);
-        };
-        if (t == OFRR_BF16)
-            NB == 4 ? go(k_gemm_lowp<true, 4>) : go(k_gemm_lowp<true, 2>);
-        else
-            NB == 4 ? go(k_gemm_lowp<false, 4>) : go(k_gemm_lowp<false, 2>);
-        OFRR_HIP(hipGetLastError());
-    }
-    if (nsplit > 1) {
-        KTimer tm(ctx, "product_reduce");
-        int64_t total = m * b;
-        int g = (int)std::min<int64_t>((total + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_sum_slabs, dim3(g), dim3(256), 0, ctx->stream, dst, nsplit, m, b, ldw, W);
-        OFRR_HIP(hipGetLastError());
-    }
 }
 
 void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,

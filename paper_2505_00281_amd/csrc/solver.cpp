@@ -90,12 +90,14 @@ struct EigRun {
             product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
             return;
         }
-        // dense reduced precision: split the FP32 block into hi (+ lo)
-        uint16_t *vhi = ctx->buf<uint16_t>("prod_vhi", (size_t)n * ld);
+        // dense reduced precision: split the FP32 block into hi (+ lo), written
+        // K-contiguous per column for the MFMA product
+        const int64_t ldt = lowp_ldt(n);
+        uint16_t *vhi = ctx->buf<uint16_t>("prod_vhi", (size_t)ld * ldt);
         uint16_t *vlo = nullptr;
-        if (plan->b_split >= 2) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)n * ld);
-        split_block(ctx, ph.basis, n * ld, (const float *)Vm, vhi, vlo);
-        product_lowp(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ld, (float *)Wm, ld);
+        if (plan->b_split >= 2) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
+        split_block_t(ctx, ph.basis, n, bc, (const float *)Vm, ld, vhi, vlo, ldt);
+        product_lowp_t(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ldt, (float *)Wm, ld);
     }
 
     int64_t b0 = 0;  // leading dimension of every block (the initial basis size)

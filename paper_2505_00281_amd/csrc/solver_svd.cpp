@@ -70,8 +70,9 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     void *Ts = ctx->buf<double>("svd_Ts", bn);
     void *Vt = ctx->buf<double>("svd_Vt", bn);
     void *Ut = ctx->buf<double>("svd_Ut", bm);
-    uint16_t *vh = ctx->buf<uint16_t>("svd_vh", std::max(bm, bn));
-    uint16_t *vl = ctx->buf<uint16_t>("svd_vl", std::max(bm, bn));
+    const size_t bt = (size_t)ld * lowp_ldt(std::max(m, n));
+    uint16_t *vh = ctx->buf<uint16_t>("svd_vh", bt);
+    uint16_t *vl = ctx->buf<uint16_t>("svd_vl", bt);
     float *swork = ctx->buf<float>("svd_swork", (size_t)ld * ((std::max(m, n) + 4095) / 4096 + 2) + 256);
     double *B = ctx->buf<double>("svd_B", (size_t)ld * ld);
     double *MU = ctx->buf<double>("svd_MU", (size_t)ld * ld);
@@ -105,9 +106,11 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         if (phases[pi] == OFRR_F64) {
             product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
         } else {
-            split_block(ctx, phases[pi], cols * ld, (const float *)X, vh, plan->b_split >= 2 ? vl : nullptr);
-            product_lowp(ctx, phases[pi], rows, cols, A_lo, m, trans, bc, vh,
-                         plan->b_split >= 2 ? vl : nullptr, ld, (float *)Wout, ld);
+            const int64_t ldt = lowp_ldt(cols);
+            split_block_t(ctx, phases[pi], cols, bc, (const float *)X, ld, vh,
+                          plan->b_split >= 2 ? vl : nullptr, ldt);
+            product_lowp_t(ctx, phases[pi], rows, cols, A_lo, m, trans, bc, vh,
+                           plan->b_split >= 2 ? vl : nullptr, ldt, (float *)Wout, ld);
         }
     };
     // scale, Hessenberg, compact into dst; returns kept columns
