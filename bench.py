@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--b-split", type=int, default=1)
+    ap.add_argument("--refine", type=int, default=2,
+                    help="1: BF16 then FP64 tail; 2: BF16, split-BF16, FP64 tail")
+    ap.add_argument("--stall-iters", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -130,7 +133,8 @@ def main():
 
     common = dict(filter="chebyshev", degree=DEGREE, lo=lo, hi=hi, tol=TOL * 0.5, anorm=anorm,
                   max_iters=400)
-    mixed = ofrr.make_plan(basis_dtype="bf16", refine=True, stall_iters=2, b_split=args.b_split,
+    mixed = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
+                           b_split=args.b_split,
                            **common)
     f64 = ofrr.make_plan(basis_dtype="f64", **common)
 
@@ -151,12 +155,14 @@ def main():
                    "n_converged": fconv, "max_rel_eval_diff_mixed_vs_fp64": ev_diff}
 
     # dominant kernel: the BF16 block product, timed per launch with HIP events
-    prof = ofrr.make_plan(basis_dtype="bf16", refine=True, stall_iters=2, b_split=args.b_split,
+    prof = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
+                          b_split=args.b_split,
                           profile=True, **common)
     ctx.kernel_stats_reset()
     ctx.eig_partial(A, K_WANT, BASIS, plan=prof, X0=X0)
     torch.cuda.synchronize()
-    fams = ["product_bf16", "product_f64", "hessenberg", "small_eig", "gram", "lift", "scale",
+    fams = ["product_bf16", "product_bf16x2", "product_reduce", "product_f64", "hessenberg",
+            "small_eig", "gram", "lift", "scale",
             "quantize", "residual"]
     stats = {f: ctx.kernel_stats(f) for f in fams}
     launches, tot = stats["product_bf16"]

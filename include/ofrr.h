@@ -90,7 +90,10 @@ typedef struct {
                                 (all FP64); F32, BF16, F16, F8E4M3 the mixed forms */
     ofrr_accum gram_accum;   /* accumulation of G and H in the first phase */
     int32_t refine;          /* 0: one phase in basis_dtype; 1: first phase until its
-                                residual estimate stalls, then an FP64 tail */
+                                residual estimate stalls, then an FP64 tail; 2 (dense,
+                                BF16): BF16 phase, then a phase with A and the basis as
+                                two-term BF16 splits (about 16 significant bits each,
+                                three MFMAs per fragment), then the FP64 tail */
     ofrr_filter filter;
     int32_t degree;          /* products per outer iteration (power steps or
                                 Chebyshev degree), >= 1 */
@@ -147,7 +150,7 @@ const char *ofrr_last_error(ofrr_ctx ctx);
 /* Kernel timing (plan.profile != 0): number of launches and summed device
  * milliseconds of the kernel family `name` since the last reset, measured
  * with HIP events on the context's stream.  Families: "quantize",
- * "product_bf16", "product_f16", "product_f8", "product_f64", "product_f32",
+ * "product_bf16", "product_bf16x2", "product_f16", "product_f8", "product_f64", "product_f32",
  * "product_reduce" (the fixed-order sum of split-K partials), "spmm",
  * "scale", "hessenberg", "gram", "small_eig", "lift", "residual".
  * Returns OFRR_ERR_INVALID_ARG for an unknown name. */

@@ -17,7 +17,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                              const ofrr_plan *plan, const double *V0, double *sigma, double *U,
                              double *V, double *resid, ofrr_info *info);
 
-static const char *kFamilies[] = {"quantize", "product_bf16", "product_f16", "product_f8",
+static const char *kFamilies[] = {"quantize", "product_bf16", "product_bf16x2", "product_f16", "product_f8",
                                   "product_f64", "product_f32", "product_reduce", "spmm", "scale",
                                   "hessenberg", "gram", "small_eig", "lift", "residual"};
 

@@ -151,9 +151,15 @@ void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const
 void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                   int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
                   int64_t ldv, float *W, int64_t ldw);
+// Alo (may be null): low halves of a two-term BF16 split of A (then Vtlo is
+// required): W = Ahi Vhi + Ahi Vlo + Alo Vhi.
 void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                     int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
-                    int64_t ldvt, float *W, int64_t ldw);
+                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo);
+// FP32 column-major (rows x cols, lds) -> hi = bf16(x), lo = bf16(x - hi),
+// both column-major with ld = rows
+void cast_f32_to_bf16x2(Context *ctx, int64_t rows, int64_t cols, const float *src, int64_t lds,
+                        uint16_t *hi, uint16_t *lo);
 // leading dimension of the K-contiguous basis copy for `rows` rows
 int64_t lowp_ldt(int64_t rows);
 // FP32 row-major block (rows x b, ld) -> hi (and lo) BF16/F16 bits in the

@@ -54,8 +54,12 @@ __device__ __forceinline__ u32x4_t load8(const uint16_t *p, int64_t valid) {
 }
 
 // ATRANS: op(A)[i][k] = A[k + i*lda] (K-contiguous); else A[i + k*lda].
-template <bool IS_BF16, int NB, bool ATRANS, bool SPLITV>
-__global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A, int64_t lda,
+// SPLITV: the basis is a two-term split Vhi + Vlo (two MFMAs per fragment).
+// SPLITA: A is also a two-term split Ahi + Alo (same layout); the product is
+// Ahi Vhi + Ahi Vlo + Alo Vhi, i.e. about 16 significant bits on each side.
+template <bool IS_BF16, int NB, bool ATRANS, bool SPLITV, bool SPLITA>
+__global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
+                                                 const uint16_t *__restrict__ Alo, int64_t lda,
                                                  int64_t m, int64_t kdim, int b,
                                                  const uint16_t *__restrict__ Vt,
                                                  const uint16_t *__restrict__ Vtlo, int64_t ldvt,
@@ -64,6 +68,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
                                                  int xcd_map) {
     constexpr int BN = 32 * NB;
     __shared__ __attribute__((aligned(16))) uint16_t As[GL_BM][GL_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Als[SPLITA ? GL_BM : 1][GL_LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][GL_LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bls[SPLITV ? BN : 1][GL_LD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16_t{};
 
     // register staging of one K slice: A 4 chunks, B NB chunks (+NB lo)
-    u32x4_t ra[4], rb[NB], rl[SPLITV ? NB : 1];
+    u32x4_t ra[4], ral[SPLITA ? 4 : 1], rb[NB], rl[SPLITV ? NB : 1];
     auto fetch = [&](int64_t k0) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -100,10 +105,14 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
                 const int row = c >> 3, kc = (c & 7) * 8;
                 const int64_t gi = i0 + row, gk = k0 + kc;
                 ra[s] = (gi < m) ? load8(A + gk + gi * lda, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
+                if constexpr (SPLITA)
+                    ral[s] = (gi < m) ? load8(Alo + gk + gi * lda, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
             } else {
                 const int kk = c >> 4, rc = (c & 15) * 8;
                 const int64_t gk = k0 + kk, gi = i0 + rc;
                 ra[s] = (gk < kend) ? load8(A + gi + gk * lda, m - gi) : u32x4_t{0u, 0u, 0u, 0u};
+                if constexpr (SPLITA)
+                    ral[s] = (gk < kend) ? load8(Alo + gi + gk * lda, m - gi) : u32x4_t{0u, 0u, 0u, 0u};
             }
         }
 #pragma unroll
@@ -123,12 +132,18 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
             const int c = t + 256 * s;
             if (ATRANS) {
                 *(u32x4_t *)&As[c >> 3][(c & 7) * 8] = ra[s];
+                if constexpr (SPLITA) *(u32x4_t *)&Als[c >> 3][(c & 7) * 8] = ral[s];
             } else {
                 const int kk = c >> 4, rc = (c & 15) * 8;
                 uint16_t tmp[8];
                 __builtin_memcpy(tmp, &ra[s], 16);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) As[rc + q][kk] = tmp[q];
+                if constexpr (SPLITA) {
+                    __builtin_memcpy(tmp, &ral[s], 16);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) Als[rc + q][kk] = tmp[q];
+                }
             }
         }
 #pragma unroll
@@ -148,6 +163,8 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
         for (int kk = 0; kk < GL_BK; kk += 16) {
             const int kq = kk + 8 * (lane >> 5);
             const u32x4_t a = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq];
+            u32x4_t al = a;
+            if constexpr (SPLITA) al = *(const u32x4_t *)&Als[32 * wave + (lane & 31)][kq];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const u32x4_t bv = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq];
@@ -156,6 +173,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
                     const u32x4_t cv = *(const u32x4_t *)&Bls[32 * nb + (lane & 31)][kq];
                     acc[nb] = mfma_32x32x16<IS_BF16>(a, cv, acc[nb]);
                 }
+                if constexpr (SPLITA) acc[nb] = mfma_32x32x16<IS_BF16>(al, bv, acc[nb]);
             }
         }
         __syncthreads();
@@ -242,8 +260,10 @@ void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const fl
 
 void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                     int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
-                    int64_t ldvt, float *W, int64_t ldw) {
+                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo) {
     OFRR_CHECK_ARG(b >= 1 && b <= 4096, "product: 1 <= b <= 4096");
+    OFRR_CHECK_ARG(Alo == nullptr || (Vtlo != nullptr && t == OFRR_BF16),
+                   "product: a split A needs a split BF16 basis");
     const int NB = b > 64 ? 4 : 2;
     const int BN = 32 * NB;
     const int gx = (int)((m + GL_BM - 1) / GL_BM), gy = (b + BN - 1) / BN;
@@ -266,15 +286,21 @@ void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const u
     if (nsplit > 1) dst = ctx->buf<float>("lowp_slabs", (size_t)nsplit * m * ldw);
     const bool splitv = Vtlo != nullptr;
     {
-        KTimer tm(ctx, t == OFRR_BF16 ? "product_bf16" : "product_f16");
+        KTimer tm(ctx, Alo ? "product_bf16x2" : (t == OFRR_BF16 ? "product_bf16" : "product_f16"));
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, A, lda, m, kdim, b,
-                               Vt, Vtlo, ldvt, dst, ldw, kps, ntiles, nsplit, xcd_map);
+            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, A, Alo, lda, m, kdim,
+                               b, Vt, Vtlo, ldvt, dst, ldw, kps, ntiles, nsplit, xcd_map);
         };
-#define OFRR_GO(BFV, NBV, TR, SP) go(k_gemm_lp<BFV, NBV, TR, SP>)
+#define OFRR_GO(BFV, NBV, TR, SP) go(k_gemm_lp<BFV, NBV, TR, SP, false>)
         const bool bf = t == OFRR_BF16;
         const bool tr = trans != 0;
-        if (bf) {
+        if (Alo) {
+            if (NB == 4) {
+                if (tr) go(k_gemm_lp<true, 4, true, true, true>); else go(k_gemm_lp<true, 4, false, true, true>);
+            } else {
+                if (tr) go(k_gemm_lp<true, 2, true, true, true>); else go(k_gemm_lp<true, 2, false, true, true>);
+            }
+        } else if (bf) {
             if (NB == 4) {
                 if (tr) { if (splitv) OFRR_GO(true, 4, true, true); else OFRR_GO(true, 4, true, false); }
                 else { if (splitv) OFRR_GO(true, 4, false, true); else OFRR_GO(true, 4, false, false); }
@@ -315,7 +341,30 @@ void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uin
         hipLaunchKernelGGL(k_transpose_u16, dim3(grid1(kdim * b)), dim3(256), 0, ctx->stream, Vlo, kdim,
                            b, ldv, Vtl, ldt);
     OFRR_HIP(hipGetLastError());
-    product_lowp_t(ctx, t, m, kdim, A, lda, trans, b, Vt, Vtl, ldt, W, ldw);
+    product_lowp_t(ctx, t, m, kdim, A, lda, trans, b, Vt, Vtl, ldt, W, ldw, nullptr);
+}
+
+namespace {
+__global__ void k_f32_to_bf16x2(const float *__restrict__ s, int64_t rows, int64_t cols, int64_t lds,
+                                uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / rows, r = e - c * rows;
+        const float x = s[r + c * lds];
+        const uint16_t h = f32_to_bf16_bits(x);
+        hi[e] = h;
+        lo[e] = f32_to_bf16_bits(x - bf16_bits_to_f32(h));  // the difference is exact
+    }
+}
+}  // namespace
+
+void cast_f32_to_bf16x2(Context *ctx, int64_t rows, int64_t cols, const float *src, int64_t lds,
+                        uint16_t *hi, uint16_t *lo) {
+    KTimer tm(ctx, "quantize");
+    hipLaunchKernelGGL(k_f32_to_bf16x2, dim3(grid1(rows * cols)), dim3(256), 0, ctx->stream, src, rows,
+                       cols, lds, hi, lo);
+    OFRR_HIP(hipGetLastError());
 }
 
 }  // namespace ofrr

@@ -7,11 +7,13 @@
 //
 // MI355X design.  One cooperative launch; workgroup g owns a contiguous
 // slice of rows for the whole sweep (in LDS when the slice fits, otherwise
-// in place in HBM/L2).  Per column there is exactly one grid barrier:
+// in place in HBM/L2).  Per column there is exactly one grid-wide exchange:
 //   1. every workgroup publishes its local pivot candidate (value, row) and
 //      a copy of that candidate row's trailing entries into a double-
-//      buffered slot;
-//   2. barrier;
+//      buffered slot, then raises the slot's sequence flag to j+1;
+//   2. every workgroup waits for all G flags (one thread per flag, polled in
+//      parallel: the barrier and the candidate exchange are one round trip,
+//      with no contended atomic counter);
 //   3. every workgroup picks the global winner (largest magnitude, smallest
 //      row on ties -- the same rule in every workgroup, so no broadcast is
 //      needed), reads the winner's published row as the multipliers, and
@@ -21,6 +23,8 @@
 // The slot copy is what makes one barrier enough: the pivot row's owner may
 // already be overwriting that row while others still need its old values.
 // Each update is one fused multiply-add, as in the reference process.
+#include <cstdlib>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
                                                     T *__restrict__ slot_rows,
                                                     typename MagT<T>::type *__restrict__ slot_mag,
                                                     int32_t *__restrict__ slot_idx,
-                                                    unsigned *__restrict__ counter,
+                                                    int32_t *__restrict__ slot_seq,
                                                     int *__restrict__ err,
                                                     int32_t *__restrict__ kept_out) {
     using M = typename MagT<T>::type;
@@ -94,7 +98,6 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     const int ldl = b;  // leading dimension of the LDS copy
     T *rows = RESIDENT ? reinterpret_cast<T *>(smem_raw) : Y + r0 * ldy;
     const int64_t ldr = RESIDENT ? ldl : ldy;
-    unsigned epoch = 0;
 
     if (RESIDENT) {
         for (int64_t e = t; e < nrows * b; e += 256) {
@@ -154,13 +157,31 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             __hip_atomic_store(slot_idx + buf * G + g, ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __threadfence();
-        // 2. one grid barrier per column
-        if (!grid_barrier(counter, (unsigned)G, epoch, err)) break;
+        __syncthreads();
+        // 2. the slot's sequence flag (column j+1) is the only grid-wide signal:
+        // readers poll every workgroup's flag in parallel (one thread each), so
+        // the barrier and the candidate exchange are one round trip and there
+        // is no contended counter
+        if (t == 0)
+            __hip_atomic_store(slot_seq + buf * G + g, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // 3. global winner, same rule everywhere
         {
             M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
+            int ok = 1;
             for (int h = t; h < G; h += 256) {
+                unsigned long long spins = 0;
+                while (__hip_atomic_load(slot_seq + buf * G + h, __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < j + 1) {
+                    if (++spins > (1ull << 24) ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (!ok) break;
                 const M m2 = __hip_atomic_load(slot_mag + buf * G + h, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                 const int i2 = __hip_atomic_load(slot_idx + buf * G + h, __ATOMIC_RELAXED,
@@ -171,6 +192,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
                     bg = h;
                 }
             }
+            if (!__syncthreads_and(ok)) break;
             // reduce (bm, bi) and carry the owning workgroup along with the row
             for (int o = 32; o > 0; o >>= 1) {
                 M m2 = __shfl_xor(bm, o, 64);
@@ -271,11 +293,10 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     if (g == 0 && t == 0 && kept_out) *kept_out = kept;
 }
 
-__global__ void k_zero_small(unsigned *c, int *e) {
-    if (threadIdx.x == 0) {
-        *c = 0u;
-        *e = 0;
-    }
+// clears the error flag, the kept count and the 2*G sequence flags (a
+// kernel, not a memset, so the sweep can be captured in a graph)
+__global__ void k_hess_reset(int *flags, int nflags) {
+    for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
 }
 
 template <class T>
@@ -286,7 +307,14 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     OFRR_CHECK_ARG(ldy >= b, "hessenberg: ld >= b");
     using M = typename MagT<T>::type;
     // rows per workgroup: LDS-resident when the slice fits in 64 KiB
-    const size_t lds_budget = 64 * 1024;
+    // LDS per workgroup for its row slice (OFRR_HESS_LDS_KB overrides, for
+    // tuning sweeps): a bigger slice means fewer workgroups meeting at each
+    // per-column grid barrier
+    size_t lds_budget = 64 * 1024;
+    if (const char *s = std::getenv("OFRR_HESS_LDS_KB")) {
+        const long kb = std::strtol(s, nullptr, 10);
+        if (kb >= 8 && kb <= 150) lds_budget = (size_t)kb * 1024;
+    }
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     int64_t rows_res = (int64_t)(lds_budget / ((size_t)b * sizeof(T)));
     bool resident = false;
@@ -309,10 +337,12 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     T *slot_rows = ctx->buf<T>("hess_slot_rows", (size_t)2 * G * b);
     M *slot_mag = ctx->buf<M>("hess_slot_mag", (size_t)2 * G);
     int32_t *slot_idx = ctx->buf<int32_t>("hess_slot_idx", (size_t)2 * G);
-    unsigned *counter = ctx->buf<unsigned>("hess_counter", 4);
-    int *err = reinterpret_cast<int *>(counter + 1);
-    int32_t *kept_d = reinterpret_cast<int32_t *>(counter + 2);
-    hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, ctx->stream, counter, err);
+    // flags: [0] error, [1] kept count, [2..2+2G) per-slot sequence numbers
+    int *flags = ctx->buf<int>("hess_flags", 2 + (size_t)2 * G);
+    int *err = flags;
+    int32_t *kept_d = flags + 1;
+    int32_t *slot_seq = flags + 2;
+    hipLaunchKernelGGL(k_hess_reset, dim3(1), dim3(256), 0, ctx->stream, flags, 2 + 2 * G);
     OFRR_HIP(hipGetLastError());
 
     auto kern = resident ? (void *)k_hessenberg<T, true> : (void *)k_hessenberg<T, false>;
@@ -322,7 +352,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     if ((int64_t)per_cu * cus < G)
         fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &rows_per, &slot_rows, &slot_mag,
-                    &slot_idx, &counter, &err, &kept_d};
+                    &slot_idx, &slot_seq, &err, &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
         OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, (unsigned)shmem, ctx->stream));
@@ -330,7 +360,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     int32_t host[2] = {0, 0};
     OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
-    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: grid barrier timed out");
+    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
     (void)want_count;
     return host[1];
 }

@@ -50,7 +50,8 @@ double unit_roundoff(ofrr_dtype t) {
 
 // One precision phase of the eigen iteration.
 struct Phase {
-    ofrr_dtype basis;  // F64: everything FP64; BF16/F16: reduced products, FP32 master blocks
+    ofrr_dtype basis;    // F64: everything FP64; BF16/F16: reduced products, FP32 master blocks
+    bool split = false;  // BF16 with A and the basis as two-term (hi + lo) splits
     bool f64() const { return basis == OFRR_F64; }
     ofrr_dtype master() const { return f64() ? OFRR_F64 : OFRR_F32; }
 };
@@ -64,8 +65,9 @@ struct EigRun {
     int32_t k;
     ofrr_which which;
     int products = 0;
-    // reduced-precision copy of dense A
+    // reduced-precision copy of dense A (and the low half of its BF16 split)
     uint16_t *A_lo = nullptr;
+    uint16_t *A_lo2 = nullptr;
     ofrr_dtype A_lo_t = OFRR_F64;
 
     // product of the current phase: W (master type) = A * Vblk (master type)
@@ -95,9 +97,10 @@ struct EigRun {
         const int64_t ldt = lowp_ldt(n);
         uint16_t *vhi = ctx->buf<uint16_t>("prod_vhi", (size_t)ld * ldt);
         uint16_t *vlo = nullptr;
-        if (plan->b_split >= 2) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
+        if (plan->b_split >= 2 || ph.split) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
         split_block_t(ctx, ph.basis, n, bc, (const float *)Vm, ld, vhi, vlo, ldt);
-        product_lowp_t(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ldt, (float *)Wm, ld);
+        product_lowp_t(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ldt, (float *)Wm, ld,
+                       ph.split ? A_lo2 : nullptr);
     }
 
     int64_t b0 = 0;  // leading dimension of every block (the initial basis size)
@@ -127,28 +130,41 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
 
     std::vector<Phase> phases;
     phases.push_back(Phase{plan->basis_dtype});
+    const bool dense = A->format == OFRR_DENSE_COLMAJOR;
+    if (plan->refine >= 2 && dense && plan->basis_dtype == OFRR_BF16) {
+        Phase mid{OFRR_BF16};
+        mid.split = true;
+        phases.push_back(mid);
+    }
     if (plan->refine && plan->basis_dtype != OFRR_F64) phases.push_back(Phase{OFRR_F64});
+    bool any_split = false;
+    for (auto &p : phases) any_split = any_split || p.split;
 
-    // quantise dense A once for a reduced-precision phase (Sec. 4: A stored
-    // in reduced precision)
-    if (A->format == OFRR_DENSE_COLMAJOR && !phases[0].f64()) {
+    // quantise dense A once for the reduced-precision phases (Sec. 4: A
+    // stored in reduced precision; a split phase also keeps A - bf16(A))
+    if (dense && !phases[0].f64()) {
         run.A_lo_t = phases[0].basis;
         run.A_lo = ctx->buf<uint16_t>("A_lo", (size_t)n * n);
         const float *Af = nullptr;
+        int64_t lda = A->ld;
         if (A->dtype == OFRR_F32) {
             Af = (const float *)A->values;
         } else {
             float *tmp = ctx->buf<float>("A_f32", (size_t)n * n);
             cast_matrix(ctx, OFRR_F64, OFRR_F32, n, n, A->values, A->ld, tmp, n);
             Af = tmp;
+            lda = n;
         }
-        if (A->ld == n) {
+        if (any_split) {
+            run.A_lo2 = ctx->buf<uint16_t>("A_lo2", (size_t)n * n);
+            cast_f32_to_bf16x2(ctx, n, n, Af, lda, run.A_lo, run.A_lo2);
+        } else if (lda == n) {
             if (run.A_lo_t == OFRR_BF16)
                 cast_f32_to_bf16(ctx, n * n, Af, run.A_lo);
             else
                 cast_f32_to_f16(ctx, n * n, Af, run.A_lo);
         } else {
-            cast_matrix(ctx, OFRR_F32, run.A_lo_t, n, n, Af, A->ld, run.A_lo, n);
+            cast_matrix(ctx, OFRR_F32, run.A_lo_t, n, n, Af, lda, run.A_lo, n);
         }
     }
 
@@ -221,7 +237,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         }
         for (int d = 2; d <= plan->degree; ++d) {
             scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
-            if (!ph.f64() && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
+            if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
             run.product(ph, Y1, W, bc);
             if (cheb)
                 cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
@@ -242,7 +258,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         bc = kept;
         if (bc < k) fail(OFRR_ERR_NUMERIC, "basis lost rank below k");
         // storage rounding of the basis for a reduced-precision phase
-        if (!ph.f64() && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
+        if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
         // ---- project
         run.product(ph, V, W, bc);
         project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
@@ -276,8 +292,9 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             const bool stalled = stall_det.push(emax);
             const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
             if (stalled || by_value) {
-                // switch to the FP64 tail: promote X, recompute AX by a product
-                promote_block(ctx, n * ld, X);
+                // next phase: promote X for the FP64 tail; AX is recomputed by a
+                // product of the new phase in every case
+                if (phases[pi + 1].f64() && !ph.f64()) promote_block(ctx, n * ld, X);
                 ++pi;
                 have_ax = false;
                 stall_det.reset();

@@ -110,7 +110,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             split_block_t(ctx, phases[pi], cols, bc, (const float *)X, ld, vh,
                           plan->b_split >= 2 ? vl : nullptr, ldt);
             product_lowp_t(ctx, phases[pi], rows, cols, A_lo, m, trans, bc, vh,
-                           plan->b_split >= 2 ? vl : nullptr, ldt, (float *)Wout, ld);
+                           plan->b_split >= 2 ? vl : nullptr, ldt, (float *)Wout, ld, nullptr);
         }
     };
     // scale, Hessenberg, compact into dst; returns kept columns

@@ -122,7 +122,7 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
     load_library().ofrr_plan_default(ctypes.byref(p))
     p.basis_dtype = _DTYPES[basis_dtype] if isinstance(basis_dtype, str) else basis_dtype
     p.gram_accum = _ACCUM[gram_accum] if isinstance(gram_accum, str) else gram_accum
-    p.refine = int(bool(refine))
+    p.refine = int(refine)  # False/True/0/1/2
     p.filter = _FILTER[filter] if isinstance(filter, str) else filter
     p.degree = degree
     p.lo, p.hi = float(lo), float(hi)
