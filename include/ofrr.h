@@ -237,6 +237,18 @@ ofrr_status ofrr_quantize_fp8_blocks(ofrr_ctx ctx, int64_t rows, int64_t cols, c
 ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
                                ofrr_dtype v_dtype, const void *V, void *W);
 
+/* FP8 block product W = op(A) V (trans 0: A V; 1: A^T V) for A given as
+ * e4m3fn codes (rows x cols, column-major, ld = rows) with 32 x 32 block
+ * scales as produced by ofrr_quantize_fp8_blocks.  V: FP32 row-major
+ * (op(A) cols x b), quantised inside the call to e4m3fn with one
+ * power-of-two scale per 32 consecutive rows of each column (the smallest
+ * 2^k with amax / 2^k <= 448).  W: FP32 row-major (op(A) rows x b); both
+ * operands' scales are applied inside the block-scaled MFMA, accumulation
+ * in FP32. */
+ofrr_status ofrr_block_product_fp8(ofrr_ctx ctx, int64_t rows, int64_t cols, const uint8_t *codes,
+                                   const float *scales, int32_t trans, int32_t b, const float *V,
+                                   float *W);
+
 /* Right-looking Hessenberg process on an n x b block Y (Sec. 4.2) in FP64
  * (dtype F64) or FP32 (dtype F32), in place: for each column the first row
  * of largest magnitude is the pivot; a column whose pivot magnitude is

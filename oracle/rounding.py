@@ -103,6 +103,30 @@ def fp8_block_quantize(A, block: int = 32):
     return codes, scales
 
 
+def fp8_colblock_quantize(V, block: int = 32):
+    """e4m3fn quantisation of a 2-D FP32 array with one power-of-two scale per
+    `block` consecutive rows of each column (the smallest 2^k with
+    amax / 2^k <= 448; 1 for an all-zero segment).  Returns the dequantised
+    values (codes * scale) as float64."""
+    V = np.asarray(V, dtype=np.float32)
+    out = np.zeros(V.shape, dtype=np.float64)
+    rows, cols = V.shape
+    for j in range(cols):
+        for r0 in range(0, rows, block):
+            seg = V[r0:r0 + block, j]
+            amax = float(np.max(np.abs(seg))) if seg.size else 0.0
+            s = 1.0
+            if amax > 0:
+                s = 2.0 ** int(np.ceil(np.log2(amax / 448.0)))
+                while amax / s > 448.0:
+                    s *= 2.0
+                while amax / (s / 2.0) <= 448.0:
+                    s /= 2.0
+            codes = f32_to_e4m3_bits((seg / np.float32(s)).astype(np.float32))
+            out[r0:r0 + block, j] = e4m3_bits_to_f32(codes).astype(np.float64) * s
+    return out
+
+
 def e4m3_bits_to_f32(bits) -> np.ndarray:
     b = np.asarray(bits, dtype=np.uint8).astype(np.int64)
     mag = b & 0x7F

@@ -383,6 +383,26 @@ ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans
     });
 }
 
+ofrr_status ofrr_block_product_fp8(ofrr_ctx ctx, int64_t rows, int64_t cols, const uint8_t *codes,
+                                   const float *scales, int32_t trans, int32_t b, const float *V,
+                                   float *W) {
+    return guarded(ctx, [&](Context *c) {
+        OFRR_CHECK_ARG(rows >= 1 && cols >= 1 && codes && scales && V && W && b >= 1 && b <= 4096,
+                       "block_product_fp8: bad arguments");
+        OFRR_CHECK_ARG(trans == 0 || trans == 1, "trans must be 0 or 1");
+        OFRR_HIP(hipSetDevice(c->device));
+        const int64_t kdim = trans ? rows : cols, m = trans ? cols : rows;
+        const int64_t ldt = f8_ldt(kdim);
+        uint8_t *vc = c->buf<uint8_t>("f8_vcodes", (size_t)b * ldt);
+        uint8_t *vs = c->buf<uint8_t>("f8_vscales", (size_t)b * (ldt / 32));
+        quant_basis_f8(c, kdim, b, V, b, vc, vs);
+        product_f8(c, rows, cols, codes, scales, trans, b, vc, vs, W, b);
+        (void)m;
+        c->sync();
+        return OFRR_OK;
+    });
+}
+
 ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b, void *Y,
                             int64_t ldy, double tol, int32_t *piv, int32_t *keep, int32_t *kept) {
     return guarded(ctx, [&](Context *c) {

@@ -156,6 +156,14 @@ void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uin
 void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                     int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
                     int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo);
+// k_gemm_f8.hip.  FP8 e4m3fn product with 32 x 32 block scales on A and
+// per-(column, 32 rows) E8M0 scales on the basis.
+int64_t f8_ldt(int64_t rows);
+void quant_basis_f8(Context *ctx, int64_t rows, int32_t b, const float *src, int64_t ld,
+                    uint8_t *codes, uint8_t *scales);
+void product_f8(Context *ctx, int64_t arows, int64_t acols, const uint8_t *Acodes,
+                const float *Ascale, int trans, int32_t b, const uint8_t *Vt, const uint8_t *Vsc,
+                float *W, int64_t ldw);
 // FP32 column-major (rows x cols, lds) -> hi = bf16(x), lo = bf16(x - hi),
 // both column-major with ld = rows
 void cast_f32_to_bf16x2(Context *ctx, int64_t rows, int64_t cols, const float *src, int64_t lds,

@@ -45,12 +45,16 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
 
     std::vector<ofrr_dtype> phases{plan->basis_dtype};
     if (plan->refine && plan->basis_dtype != OFRR_F64) phases.push_back(OFRR_F64);
-    if (plan->basis_dtype == OFRR_F8E4M3 || plan->basis_dtype == OFRR_F32)
-        fail(OFRR_ERR_UNSUPPORTED, "svd_partial: basis_dtype F8E4M3/F32 not supported");
+    if (plan->basis_dtype == OFRR_F32)
+        fail(OFRR_ERR_UNSUPPORTED, "svd_partial: basis_dtype F32 not supported");
 
+    // quantise A once for the reduced phase: BF16/F16 elementwise, or FP8
+    // e4m3fn with one power-of-two scale per 32 x 32 block (square blocks,
+    // so the one copy serves both A V and A^T U)
     uint16_t *A_lo = nullptr;
+    uint8_t *A_f8 = nullptr;
+    float *A_f8s = nullptr;
     if (phases[0] != OFRR_F64) {
-        A_lo = ctx->buf<uint16_t>("svd_A_lo", (size_t)m * n);
         const float *Af = (const float *)A->values;
         int64_t lda = A->ld;
         if (A->dtype == OFRR_F64) {
@@ -59,7 +63,14 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             Af = tmp;
             lda = m;
         }
-        cast_matrix(ctx, OFRR_F32, phases[0], m, n, Af, lda, A_lo, m);
+        if (phases[0] == OFRR_F8E4M3) {
+            A_f8 = ctx->buf<uint8_t>("svd_A_f8", (size_t)m * n);
+            A_f8s = ctx->buf<float>("svd_A_f8s", (size_t)((m + 31) / 32) * ((n + 31) / 32));
+            quantize_fp8_blocks(ctx, m, n, Af, lda, A_f8, A_f8s);
+        } else {
+            A_lo = ctx->buf<uint16_t>("svd_A_lo", (size_t)m * n);
+            cast_matrix(ctx, OFRR_F32, phases[0], m, n, Af, lda, A_lo, m);
+        }
     }
 
     const size_t bm = (size_t)m * ld, bn = (size_t)n * ld;
@@ -70,7 +81,9 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     void *Ts = ctx->buf<double>("svd_Ts", bn);
     void *Vt = ctx->buf<double>("svd_Vt", bn);
     void *Ut = ctx->buf<double>("svd_Ut", bm);
-    const size_t bt = (size_t)ld * lowp_ldt(std::max(m, n));
+    // staging of the product's basis operand: 16-bit codes (hi, lo) or, for
+    // FP8, codes in vh and per-32-row scales in vl (both fit in bt halves)
+    const size_t bt = (size_t)ld * std::max(lowp_ldt(std::max(m, n)), f8_ldt(std::max(m, n)));
     uint16_t *vh = ctx->buf<uint16_t>("svd_vh", bt);
     uint16_t *vl = ctx->buf<uint16_t>("svd_vl", bt);
     float *swork = ctx->buf<float>("svd_swork", (size_t)ld * ((std::max(m, n) + 4095) / 4096 + 2) + 256);
@@ -105,6 +118,12 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         const int64_t rows = trans ? n : m, cols = trans ? m : n;
         if (phases[pi] == OFRR_F64) {
             product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
+        } else if (phases[pi] == OFRR_F8E4M3) {
+            // basis quantised per product: one scale per 32 rows of each column
+            uint8_t *vc = reinterpret_cast<uint8_t *>(vh);
+            uint8_t *vs = reinterpret_cast<uint8_t *>(vl);
+            quant_basis_f8(ctx, cols, bc, (const float *)X, ld, vc, vs);
+            product_f8(ctx, m, n, A_f8, A_f8s, trans, bc, vc, vs, (float *)Wout, ld);
         } else {
             const int64_t ldt = lowp_ldt(cols);
             split_block_t(ctx, phases[pi], cols, bc, (const float *)X, ld, vh,
@@ -124,7 +143,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             compact_columns_rm(ctx, master(), rows, bc, Tin, ld, keep, dst, ld);
         else
             OFRR_HIP(hipMemcpyAsync(dst, Tin, (size_t)rows * ld * esz(), hipMemcpyDeviceToDevice, ctx->stream));
-        if (phases[pi] != OFRR_F64 && plan->b_split < 2)
+        if ((phases[pi] == OFRR_BF16 || phases[pi] == OFRR_F16) && plan->b_split < 2)
             round_block(ctx, phases[pi], rows * ld, (float *)dst);
         return kept;
     };

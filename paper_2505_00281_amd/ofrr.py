@@ -36,7 +36,8 @@ _FILTER = {"power": POWER, "chebyshev": CHEBYSHEV}
 EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error",
             "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_eig_partial",
             "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_quantize",
-            "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_hessenberg",
+            "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_fp8",
+            "ofrr_hessenberg",
             "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
 
 
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_quantize.argtypes = [vp, ctypes.c_int, i64, vp, vp]
     lib.ofrr_quantize_fp8_blocks.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     lib.ofrr_block_product.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, vp, vp]
+    lib.ofrr_block_product_fp8.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, vp]
     lib.ofrr_hessenberg.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
     lib.ofrr_project.argtypes = [vp, i64, i32, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                  vp, vp]
@@ -337,6 +339,19 @@ class Context:
         W = torch.empty((rows, b), dtype=wdt, device=self.device)
         self._check(self.lib.ofrr_block_product(self.h, ctypes.byref(mat), int(trans), b,
                                                 _DTYPES[v_dtype], _ptr(V), _ptr(W)))
+        return W
+
+    def block_product_fp8(self, codes: torch.Tensor, scales: torch.Tensor, V: torch.Tensor,
+                          trans: bool = False):
+        """W = op(A) V for FP8 block-quantised A (codes, scales from
+        quantize_fp8_blocks, column-major) and an FP32 row-major V."""
+        rows, cols = codes.shape
+        assert codes.stride(0) == 1 and scales.stride(0) == 1
+        V = V.to(torch.float32).contiguous()
+        b = V.shape[1]
+        W = torch.empty((cols if trans else rows, b), dtype=torch.float32, device=self.device)
+        self._check(self.lib.ofrr_block_product_fp8(self.h, rows, cols, _ptr(codes), _ptr(scales),
+                                                    int(trans), b, _ptr(V), _ptr(W)))
         return W
 
     def hessenberg(self, Y: torch.Tensor, tol: float):

@@ -216,7 +216,7 @@ def test_svd_converged_fp64(ctx):
     assert r.resid.cpu().numpy().max() <= 2e-12
 
 
-@pytest.mark.parametrize("lowp", ["bf16", "f16"])
+@pytest.mark.parametrize("lowp", ["bf16", "f16", "f8e4m3"])
 def test_svd_mixed_refined_converged(ctx, lowp):
     m, n, b, k = 1500, 400, 24, 10
     sig = np.exp(-np.arange(1, n + 1) / 40.0)

@@ -101,6 +101,32 @@ def test_product_lowp(ctx, lowp, trans, shape):
     assert np.all(err <= bound), float(np.max(err / np.maximum(bound, 1e-300)))
 
 
+@pytest.mark.parametrize("trans", [0, 1])
+@pytest.mark.parametrize("shape", [(300, 1000, 70), (4100, 2080, 128)])
+def test_product_fp8_block_scaled(ctx, trans, shape):
+    """FP8 e4m3fn product with 32x32 block scales on A and per-(column, 32
+    rows) scales on V: equal to the FP64 product of the dequantised operands
+    within the FP32 accumulation bound (scaled FP8 products are exact)."""
+    rng = np.random.default_rng(12)
+    m, kd, b = shape
+    ar, ac = (m, kd) if not trans else (kd, m)
+    A = (rng.standard_normal((ar, ac)) * np.exp(rng.uniform(-6, 2, (ar, ac)))).astype(np.float32)
+    V = rng.standard_normal((kd, b)).astype(np.float32)
+    codes_ref, scales_ref = R.fp8_block_quantize(A)
+    Adq = R.e4m3_bits_to_f32(codes_ref).astype(np.float64) * np.kron(
+        scales_ref.astype(np.float64), np.ones((32, 32)))[:ar, :ac]
+    Vdq = R.fp8_colblock_quantize(V)
+    print("product_fp8", trans, shape, flush=True)
+    At = torch.from_numpy(A.T.copy()).cuda().t()
+    codes, scales = ctx.quantize_fp8_blocks(At)
+    Wg = ctx.block_product_fp8(codes, scales, _cuda(V), trans=bool(trans)).cpu().numpy().astype(np.float64)
+    opA = Adq.T if trans else Adq
+    ref = opA @ Vdq
+    bound = (kd + 2) * 2.0 ** -24 * (np.abs(opA) @ np.abs(Vdq))
+    err = np.abs(Wg - ref)
+    assert np.all(err <= bound + 1e-30), float(np.max(err / np.maximum(bound, 1e-300)))
+
+
 @pytest.mark.parametrize("vt", ["f64", "f16", "f32"])
 def test_spmm_laplacian(ctx, vt):
     from paper_2505_00281_amd import ofrr
