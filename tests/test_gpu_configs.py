@@ -1,0 +1,155 @@
+"""The benchmark/parity configurations at full size, checked where the CPU
+oracle can still reach: closed-form spectra, and sampled outputs computed one
+by one in FP64 on the host (Rayleigh quotients and residuals of returned
+vectors from A as stored).
+
+* dense n=512, lambda_i = 0.95^i, FP64 form, 20 power steps: same-step parity
+  (tests/test_gpu_eig.py);
+* dense n=16384, lambda_i = i^-1.5 + 1e-3 symmetric noise, FP32 storage,
+  refined BF16 plan as timed by bench.py: final residuals <= 1e-8 and
+  eigenvalues equal to the oracle's Rayleigh quotients of sampled vectors;
+* dense SVD 65536 x 8192, sigma_i = exp(-i/200), FP8 e4m3 basis build with
+  block scales, FP64 tail: singular values against the closed form (up to
+  the FP32 storage error of A) and sampled residuals;
+* 2-D Laplacian 1024 x 1024 (CSR), 32 smallest, degree-20 Chebyshev, FP16
+  vectors with an FP64 tail: eigenvalues against the closed form;
+* 512 problems n in [256, 4096], lambda_i = 0.9^i, BF16 basis, power
+  filter: every problem's eigenvalues against the closed form.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2505_00281_amd import ofrr
+    c = ofrr.Context(0)
+    yield c
+    c.close()
+
+
+def _plan(**kw):
+    from paper_2505_00281_amd import ofrr
+    return ofrr.make_plan(**kw)
+
+
+def _sampled_checks(A_host64, evals, evecs, idx, anorm):
+    """Oracle-side FP64 Rayleigh quotient and residual of sampled vectors."""
+    X = evecs[:, idx]
+    AX = A_host64 @ X
+    rq = np.sum(X * AX, axis=0) / np.sum(X * X, axis=0)
+    res = np.linalg.norm(AX - X * evals[idx], axis=0) / anorm
+    return rq, res
+
+
+def test_dense_n16384_refined_bf16(ctx):
+    n, k, b = 16384, 64, 128
+    lam = np.arange(1, n + 1, dtype=np.float64) ** -1.5
+    print("config dense n=16384 generate", flush=True)
+    A = W.dense_symmetric_prescribed(lam, 1002, noise_scale=1e-3, noise_seed=2002,
+                                     dtype=torch.float32, device="cuda")
+    X0 = torch.from_numpy(W.uniform_start(n, b, 1102))
+    w = torch.linalg.eigvalsh(A).double().cpu().numpy()[::-1]
+    lo, hi, anorm = float(w[-1]) * 1.001, float(w[b]), float(max(abs(w[0]), abs(w[-1])))
+    print("config dense n=16384 run", flush=True)
+    plan = _plan(basis_dtype="bf16", refine=2, filter="chebyshev", degree=4, lo=lo, hi=hi,
+                 tol=5e-9, anorm=anorm, max_iters=400, stall_iters=3)
+    r = ctx.eig_partial(A, k, b, plan=plan, X0=X0)
+    print("info", r.info, flush=True)
+    ev, X, res = r.evals.cpu().numpy(), r.evecs.cpu().numpy(), r.resid.cpu().numpy()
+    assert r.status == 0 and np.all(res <= 1e-8)
+    A64 = A.double().cpu().numpy()
+    idx = np.array([0, 1, 2, 31, 62, 63])
+    rq, rr = _sampled_checks(A64, ev, X, idx, anorm)
+    np.testing.assert_allclose(ev[idx], rq, rtol=1e-10)
+    assert np.all(rr <= 1e-8)
+    np.testing.assert_allclose(rr, res[idx], rtol=1e-3, atol=1e-12)
+
+
+def test_dense_svd_65536x8192_fp8(ctx):
+    m, n, k, b = 65536, 8192, 100, 200
+    sig = np.exp(-np.arange(1, n + 1) / 200.0)
+    print("config svd generate", flush=True)
+    A = W.svd_prescribed(m, n, sig, 1003, dtype=torch.float32, device="cuda")
+    V0 = torch.from_numpy(W.uniform_start(n, b, 1103))
+    print("config svd run", flush=True)
+    r = ctx.svd_partial(A, k, b, plan=_plan(basis_dtype="f8e4m3", refine=1, tol=5e-9,
+                                            max_iters=300, stall_iters=3), V0=V0)
+    print("info", r.info, flush=True)
+    s = r.sigma.cpu().numpy()
+    assert np.all(r.resid.cpu().numpy() <= 1e-8)
+    # closed form holds up to the FP32 storage of A (||A_stored - A|| ~ 1e-8)
+    np.testing.assert_allclose(s, sig[:k], rtol=5e-8)
+    # sampled residuals in FP64 on the host, from A as stored
+    A64 = A.cpu().numpy().astype(np.float64)
+    idx = [0, 50, 99]
+    U = r.U[:, idx].cpu().numpy()
+    V = r.V[:, idx].cpu().numpy()
+    r1 = np.linalg.norm(A64 @ V - U * s[idx], axis=0)
+    r2 = np.linalg.norm(A64.T @ U - V * s[idx], axis=0)
+    assert np.all(np.sqrt(r1 ** 2 + r2 ** 2) / s[0] <= 1e-8)
+
+
+def test_laplacian_1024_smallest_fp16(ctx):
+    from paper_2505_00281_amd import ofrr
+    N, k, b = 1024, 32, 64
+    rp, ci, v = W.laplacian_2d_csr(N)
+    ev = W.laplacian_2d_eigenvalues(N)
+    X0 = torch.from_numpy(W.uniform_start(N * N, b, 1104))
+    mat = ofrr.csr_matrix(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                          torch.from_numpy(v).cuda())
+    print("config laplacian run", flush=True)
+    plan = _plan(basis_dtype="f16", refine=1, filter="chebyshev", degree=20, lo=float(ev[b]),
+                 hi=8.0, tol=5e-9, anorm=8.0, max_iters=2000, stall_iters=10)
+    r = ctx.eig_partial(mat, k, b, which="smallest", plan=plan, X0=X0)
+    print("info", r.info, flush=True)
+    th = r.evals.cpu().numpy()
+    res = r.resid.cpu().numpy() * 8.0
+    assert np.all(res <= 8e-8)
+    # Ritz values of a subspace bound the smallest eigenvalues from above
+    # (A is exact in FP32: integer entries), and each lies within
+    # min(|r|, |r|^2 / gap) of its eigenvalue, gap measured in the closed
+    # form to the nearest eigenvalue of a different value.
+    assert np.all(th >= ev[:k] - 1e-13)
+    for i in range(k):
+        d = np.abs(ev[:4 * k] - ev[i])
+        gap = d[d > 1e-13].min()
+        assert abs(th[i] - ev[i]) <= min(res.max(), res.max() ** 2 / gap) + 1e-13, i
+    # sampled Rayleigh quotients and residuals on the host (FP64 CSR product)
+    idx = [0, 15, 31]
+    Xs = r.evecs[:, idx].cpu().numpy()
+    Xg = np.ascontiguousarray(Xs).reshape(N, N, len(idx))  # [y, x, col], row = x + N*y
+    AXg = 4.0 * Xg
+    AXg[1:] -= Xg[:-1]
+    AXg[:-1] -= Xg[1:]
+    AXg[:, 1:] -= Xg[:, :-1]
+    AXg[:, :-1] -= Xg[:, 1:]
+    AX = AXg.reshape(N * N, len(idx))
+    rq = np.sum(Xs * AX, axis=0) / np.sum(Xs * Xs, axis=0)
+    np.testing.assert_allclose(th[idx], rq, rtol=1e-9)
+    assert np.all(np.linalg.norm(AX - Xs * th[idx], axis=0) <= 8e-8)
+
+
+@pytest.mark.timeout(400)
+def test_batched_512_bf16(ctx):
+    sizes = W.batched_sizes(1005)
+    print("config batched generate", flush=True)
+    As, X0s = [], []
+    for p, n in enumerate(sizes):
+        lam = 0.9 ** np.arange(1, n + 1)
+        As.append(W.dense_symmetric_prescribed(lam, 1005000 + p, dtype=torch.float32, device="cuda"))
+        X0s.append(torch.from_numpy(W.uniform_start(int(n), 16, 1105000 + p)))
+    print("config batched run", flush=True)
+    plan = _plan(basis_dtype="bf16", refine=1, tol=5e-9, anorm=0.9, max_iters=200, stall_iters=3)
+    outs = ctx.eig_partial_batched(As, 8, 16, plan=plan, X0s=X0s)
+    ref = 0.9 ** np.arange(1, 9)
+    for p, o in enumerate(outs):
+        assert np.all(o.resid.cpu().numpy() <= 1e-8), p
+        # FP32 storage moves each eigenvalue by at most ||A_stored - A||_2,
+        # about 2^-24 * 2 sqrt(n) * rms entry < 2e-8 for these spectra
+        np.testing.assert_allclose(o.evals.cpu().numpy(), ref, rtol=0, atol=5e-8)
