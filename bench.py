@@ -119,13 +119,26 @@ def main():
     ap.add_argument("--refine", type=int, default=2,
                     help="1: BF16 then FP64 tail; 2: BF16, split-BF16, FP64 tail")
     ap.add_argument("--stall-iters", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (read + write) three times; "
+                         "used to scale rocprofv3 FETCH_SIZE/WRITE_SIZE readings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the sharded design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
+              "row partition is a design, not an implemented path", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": 3}))
+        return
     from paper_2505_00281_amd import ofrr
     device = torch.device("cuda", 0)
     A, X0, lo, hi, anorm = make_problem(device)
@@ -165,16 +178,35 @@ def main():
             "small_eig", "gram", "lift", "scale",
             "quantize", "residual"]
     stats = {f: ctx.kernel_stats(f) for f in fams}
-    launches, tot = stats["product_bf16"]
-    avg_ms = tot / max(launches, 1)
+    # dominant kernel: the block-product family with the largest total time
+    # in one call; algorithmic bytes per launch = A read once in its stored
+    # format + the basis block read once + the FP32/FP64 product written once
     vb = 2 if args.b_split >= 2 else 1
-    alg_bytes = N * N * 2 + vb * N * BASIS * 2 + N * BASIS * 4  # A + V (+Vlo) + W
+    alg = {
+        "product_bf16": (N * N * 2 + vb * N * BASIS * 2 + N * BASIS * 4,
+                         "k_gemm_lp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)"),
+        "product_bf16x2": (N * N * 4 + N * BASIS * 4 + N * BASIS * 4,
+                           "k_gemm_lp<bf16, split A and V> (3 BF16 MFMAs per tile step)"),
+        "product_f64": (N * N * 4 + N * BASIS * 8 + N * BASIS * 8,
+                        "k_gemm_f64 (A FP32 promoted, FP64 MFMA 16x16x4)"),
+    }
+    dom = max(alg, key=lambda f: stats[f][1])
+    launches, tot = stats[dom]
+    avg_ms = tot / max(launches, 1)
+    alg_bytes, kname = alg[dom]
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_gemm_lowp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)",
+                "kernel": kname, "family": dom,
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "algorithmic_bytes_per_launch": alg_bytes}
+    others = {}
+    for f, (ab, _) in alg.items():
+        n_l, t_l = stats[f]
+        if n_l:
+            others[f] = {"avg_launch_ms": t_l / n_l,
+                         "achieved_GBps": round(ab / (t_l / n_l * 1e-3) / 1e9, 1)}
+    roofline["per_family"] = others
     kernel_ms = {f: {"launches": n, "total_ms": round(t, 3)} for f, (n, t) in stats.items()}
 
     cpu = None

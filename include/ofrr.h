@@ -108,9 +108,11 @@ typedef struct {
                                 exactly max_iters outer iterations */
     double anorm;            /* residual normaliser ||A||_2; 0 -> max |Ritz value| */
     int32_t max_iters;       /* outer iterations cap (>= 1) */
-    int32_t stall_iters;     /* refine=1: leave the first phase after this many outer
-                                iterations without a 2x residual improvement */
-    double switch_resid;     /* refine=1: also leave it once the largest wanted residual
+    int32_t stall_iters;     /* refine>=1: leave a reduced-precision phase once the
+                                smallest largest-wanted-residual estimate of the last
+                                stall_iters outer iterations is not 10% below the
+                                smallest one before them */
+    double switch_resid;     /* refine>=1: also leave it once the largest wanted residual
                                 estimate is below this value (0 -> never by value) */
     int32_t b_split;         /* BF16/F16 products: 2 carries the basis block as a two-
                                 term split (hi + lo) through the MFMA, 1 rounds it once */

@@ -9,6 +9,8 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "../../include/ofrr.h"
@@ -36,13 +38,21 @@ struct Error {
 
 // Phase switch test of the refined plans: a phase has stalled when its
 // residual estimate has not halved over the last `window` outer iterations.
+// A precision phase has stalled when the smallest residual estimate seen in
+// the last `window` outer iterations is not 10% below the smallest one seen
+// before them: slow but steady convergence keeps setting new minima, while
+// an estimate that has reached the phase's rounding floor only fluctuates.
 struct StallDetector {
     int window;
     std::vector<double> h;
     bool push(double e) {
         h.push_back(e);
         const size_t w = (size_t)(window > 0 ? window : 1);
-        return h.size() > w && !(e <= 0.5 * h[h.size() - 1 - w]);
+        if (h.size() <= w) return false;
+        double before = INFINITY, recent = INFINITY;
+        for (size_t i = 0; i + w < h.size(); ++i) before = std::min(before, h[i]);
+        for (size_t i = h.size() - w; i < h.size(); ++i) recent = std::min(recent, h[i]);
+        return !(recent < 0.9 * before);
     }
     void reset() { h.clear(); }
 };

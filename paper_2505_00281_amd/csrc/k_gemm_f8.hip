@@ -9,9 +9,14 @@
 // are applied inside the instruction and the FP32 accumulation sees the
 // true products.
 //
-// Operand layout of the 32x32x64 FP8 MFMA (eight dwords per lane): lane l
-// holds row l%32 of A and K values 32(l/32)..+32; B likewise for column
-// l%32; the accumulator is laid out as for the other 32x32 MFMAs.
+// Operand layout of the 32x32x64 FP8 MFMA (eight dwords per lane, row
+// l%32 of A, column l%32 of B): bytes 0..15 of a lane belong to the first
+// 32-deep K block and bytes 16..31 to the second; the two lane halves
+// (l/32 = 0, 1) each supply 16 values of both blocks, and the E8M0 scale
+// of lane l applies to K block l/32 of its row (column).  Lane half h
+// therefore carries K = 16h..16h+15 and 32+16h..32+16h+15 of the 64-deep
+// step, and its scale is that of block h.  The accumulator is laid out as
+// for the other 32x32 MFMAs.
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -132,10 +137,12 @@ __global__ __launch_bounds__(256) void k_gemm_f8(const uint8_t *__restrict__ A, 
                 const float s = ATRANS ? Ascale[kblk + rb_ * lds_blk] : Ascale[rb_ + kblk * lds_blk];
                 sa = e8m0_of(s);
             }
+            // this lane's 16 values of each 32-deep block of the step
+            const int kb0 = kk + 16 * (lane >> 5), kb1 = kb0 + 32;
             i32x8_t a;
             {
-                const u32x4_t lo = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq];
-                const u32x4_t hi = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kq + 16];
+                const u32x4_t lo = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kb0];
+                const u32x4_t hi = *(const u32x4_t *)&As[32 * wave + (lane & 31)][kb1];
                 a = i32x8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
                             (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
             }
@@ -144,8 +151,8 @@ __global__ __launch_bounds__(256) void k_gemm_f8(const uint8_t *__restrict__ A, 
                 const int col = j0 + 32 * nb + (lane & 31);
                 int sb = 127;
                 if (col < b && k0 + kq < kend) sb = Vsc[(int64_t)col * ldvs + kblk];
-                const u32x4_t lo = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq];
-                const u32x4_t hi = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kq + 16];
+                const u32x4_t lo = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kb0];
+                const u32x4_t hi = *(const u32x4_t *)&Bs[32 * nb + (lane & 31)][kb1];
                 const i32x8_t bv = i32x8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
                                            (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
                 acc[nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, bv, acc[nb], 0, 0, 0, sa, 0,

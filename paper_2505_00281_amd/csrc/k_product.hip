@@ -18,7 +18,7 @@ namespace {
 // ------------------------------------------------------------------ FP64 --
 // W (m x b) = op(A) (m x kdim) * V (kdim x b) on FP64 MFMA
 // (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16];
-// accumulator register r of lane l is D[4(l/16) + r][l%16]).  64 x 64
+// accumulator register r of lane l is D[4r + l/16][l%16]).  64 x 64
 // output tile per 256-thread workgroup (2 x 2 waves, each 2 x 2 MFMA
 // blocks), 16-deep K slices staged in LDS; the next slice is loaded into
 // registers while the current one is multiplied.
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const TA *__restrict__ A, int6
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gi = i0 + 32 * wr + 16 * p + 4 * (lane >> 4) + r;
+                const int64_t gi = i0 + 32 * wr + 16 * p + 4 * r + (lane >> 4);
                 const int gj = j0 + 32 * wc + 16 * q + (lane & 15);
                 if (gi < m && gj < b) W[gi * ldw + gj] = acc[p][q][r];
             }

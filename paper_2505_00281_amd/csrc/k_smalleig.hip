@@ -150,16 +150,17 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
     return c;
 }
 
-__device__ void bisect_all(int n, EigWork &wk, double *red) {
+__device__ void bisect_ptr(int n, const double *dg, const double *eo, const double *eo2,
+                           double *lamo) {
     const int t = threadIdx.x, T = blockDim.x;
     const int lane = t & 63, grp = lane >> 3, sub = lane & 7;
     // Gershgorin interval and the pivot floor
     double lo = INFINITY, hi = -INFINITY, emax = 0.0;
     for (int k = t; k < n; k += T) {
-        const double off = (k > 0 ? fabs(wk.e[k - 1]) : 0.0) + (k + 1 < n ? fabs(wk.e[k]) : 0.0);
-        lo = fmin(lo, wk.d[k] - off);
-        hi = fmax(hi, wk.d[k] + off);
-        if (k + 1 < n) emax = fmax(emax, wk.e2[k]);
+        const double off = (k > 0 ? fabs(eo[k - 1]) : 0.0) + (k + 1 < n ? fabs(eo[k]) : 0.0);
+        lo = fmin(lo, dg[k] - off);
+        hi = fmax(hi, dg[k] + off);
+        if (k + 1 < n) emax = fmax(emax, eo2[k]);
     }
     __shared__ double s_lo[16], s_hi[16], s_em[16];
     for (int o = 32; o > 0; o >>= 1) {
@@ -194,7 +195,7 @@ __device__ void bisect_all(int n, EigWork &wk, double *red) {
         for (int it = 0; it < 26; ++it) {
             const double x = a + (b - a) * (double)(sub + 1) * 0.125;
             int c = 0;
-            if (active && sub < 7) c = sturm_count(wk.d, wk.e2, n, x, pivmin);
+            if (active && sub < 7) c = sturm_count(dg, eo2, n, x, pivmin);
             const bool flag = active && sub < 7 && c > idx;
             const unsigned long long bal = __ballot(flag);
             const unsigned bits = (unsigned)((bal >> (grp * 8)) & 0x7Full);
@@ -205,9 +206,14 @@ __device__ void bisect_all(int n, EigWork &wk, double *red) {
             a = na;
             b = nb;
         }
-        if (active && sub == 0) wk.lam[idx] = 0.5 * (a + b);
+        if (active && sub == 0) lamo[idx] = 0.5 * (a + b);
     }
     __syncthreads();
+}
+
+__device__ void bisect_all(int n, EigWork &wk, double *red) {
+    (void)red;
+    bisect_ptr(n, wk.d, wk.e, wk.e2, wk.lam);
 }
 
 // ---------------------------------------------------------------- step 3
@@ -638,6 +644,425 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
     trsm_lower_t(LV, k2, Zo, r);
 }
 
+// ------------------------------------------------------------ fast path --
+// n <= 128.  One 1024-thread workgroup keeps the active n x n matrix in LDS
+// (leading dimension n + 1, so row and column walks are both free of bank
+// conflicts) and a second n x n matrix in registers: thread t holds column
+// c = t % 128, rows r = t / 128 + 8 q, q = 0..15.  Every phase then works
+// out of LDS and registers; global memory only carries the Cholesky factor
+// while LDS holds the tridiagonal reduction, one transpose, and the
+// eigenvectors of T between their computation and the back-transform.
+//
+// Eigenvectors of T: for an eigenvalue separated from its neighbours by
+// more than 1e-7 |T| the twisted factorisation gives the vector in one pass
+// (forward pivots D+ of T - lam I = L+ D+ L+^T, backward pivots D- of the
+// U D- U^T factorisation, gamma_k = D+_k + D-_k - (a_k - lam), twist
+// r = argmin |gamma_k|, then z_r = 1 and the two one-term recurrences away
+// from r); clusters of closer eigenvalues go through inverse iteration with
+// Gram-Schmidt inside the cluster.
+constexpr int FP_NMAX = 128;
+
+struct FastWork {
+    double *Lg;   // n x n, the Cholesky factor (column-major)
+    double *Tg;   // n x n, transpose scratch
+    double *Zt;   // n x n, eigenvectors of T (column-major)
+    double *dpm;  // 2 n x n, twisted-factorisation pivots, [k][i]
+    double *scr;  // 6 n per eigenvector (inverse iteration inside clusters)
+    int *cstart;  // n
+};
+
+// one-sync block sum over 1024 threads (red: 16 doubles, alternate buffers
+// between consecutive calls)
+__device__ __forceinline__ double bsum1(double v, double *red) {
+    v = wave_sum_f64(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r += red[i];
+    return r;
+}
+
+__device__ bool chol_lds(double *S, int ld, int n) {
+    const int t = threadIdx.x;
+    for (int j = 0; j < n; ++j) {
+        const double dj = S[j + j * ld];
+        if (!(dj > 0.0)) return false;  // every thread read the same value
+        const double l = sqrt(dj), il = 1.0 / l;
+        __syncthreads();
+        for (int i = j + t; i < n; i += SE_THREADS) S[i + j * ld] = (i == j) ? l : S[i + j * ld] * il;
+        __syncthreads();
+        const int rem = n - j - 1;
+        for (int e = t; e < rem * rem; e += SE_THREADS) {
+            const int ii = j + 1 + e % rem, kk = j + 1 + e / rem;
+            if (kk <= ii) S[ii + kk * ld] -= S[ii + j * ld] * S[kk + j * ld];
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// X <- L^{-1} X, L lower triangular in LDS (S, ld), X in registers.  The
+// register holding row i is selected by predication over the unrolled q
+// loop, so x[] is never indexed dynamically.
+__device__ void fwd_solve_reg(const double *S, int ld, int n, double (&x)[16], double *rowbuf) {
+    const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
+    for (int i = 0; i < n; ++i) {
+        double *rb = rowbuf + (i & 1) * 128;
+        const double lii = S[i + i * ld];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (g + 8 * q == i) {
+                x[q] /= lii;
+                rb[c] = x[q];
+            }
+        __syncthreads();
+        const double xi = rb[c];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = g + 8 * q;
+            if (r > i && r < n) x[q] -= S[r + i * ld] * xi;
+        }
+    }
+}
+
+// X <- L^{-T} X, L lower triangular in LDS (S, ld), X in registers.
+__device__ void bwd_solve_reg(const double *S, int ld, int n, double (&x)[16], double *rowbuf) {
+    const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
+    for (int i = n - 1; i >= 0; --i) {
+        double *rb = rowbuf + (i & 1) * 128;
+        const double lii = S[i + i * ld];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (g + 8 * q == i) {
+                x[q] /= lii;
+                rb[c] = x[q];
+            }
+        __syncthreads();
+        const double xi = rb[c];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = g + 8 * q;
+            if (r < i) x[q] -= S[i + r * ld] * xi;
+        }
+    }
+}
+
+// Householder reduction of the symmetric matrix in S (LDS, ld) to
+// tridiagonal form; reflector j is left in S rows j+1..n-1 of column j.
+__device__ void tridiag_lds(double *S, int ld, int n, double *d, double *e, double *beta,
+                            double *pv, double *red2) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int rb = 0;
+    for (int j = 0; j + 2 < n; ++j) {
+        const int m = n - j - 1;
+        double s = 0.0;
+        for (int i = j + 1 + t; i < n; i += SE_THREADS) s += S[i + j * ld] * S[i + j * ld];
+        s = bsum1(s, red2 + 16 * rb);
+        rb ^= 1;
+        const double x0 = S[(j + 1) + j * ld];
+        const double alpha = (s > 0.0) ? -copysign(sqrt(s), x0) : 0.0;
+        const double bt = (s > 0.0) ? 1.0 / (alpha * (alpha - x0)) : 0.0;
+        const double vj1 = x0 - alpha;
+        if (t == 0) {
+            d[j] = S[j + j * ld];
+            e[j] = (s > 0.0) ? alpha : x0;
+            beta[j] = bt;
+        }
+        if (bt == 0.0) continue;  // column already reduced; S untouched
+        // p = beta C22 v, one wavefront per row (column r of the symmetric C22)
+        double vp = 0.0;
+        for (int r = j + 1 + wave; r < n; r += 16) {
+            double acc = 0.0;
+            for (int cc = j + 1 + lane; cc < n; cc += 64) {
+                const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
+                acc += S[cc + r * ld] * vc;
+            }
+            acc = wave_sum_f64(acc) * bt;
+            if (lane == 0) {
+                pv[r] = acc;
+                vp += ((r == j + 1) ? vj1 : S[r + j * ld]) * acc;
+            }
+        }
+        vp = bsum1(vp, red2 + 16 * rb);  // also publishes pv
+        rb ^= 1;
+        const double K = 0.5 * bt * vp;
+        // C22 -= v w^T + w v^T, w = p - K v (lower triangle, mirrored)
+        for (int el = t; el < m * m; el += SE_THREADS) {
+            const int r = j + 1 + el % m, cc = j + 1 + el / m;
+            if (r >= cc) {
+                const double vr = (r == j + 1) ? vj1 : S[r + j * ld];
+                const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
+                const double wr = pv[r] - K * vr, wc = pv[cc] - K * vc;
+                const double val = S[r + cc * ld] - (vr * wc + wr * vc);
+                S[r + cc * ld] = val;
+                S[cc + r * ld] = val;
+            }
+        }
+        if (t == 0) S[(j + 1) + j * ld] = vj1;
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (n >= 2) {
+            d[n - 2] = S[(n - 2) + (n - 2) * ld];
+            e[n - 2] = S[(n - 1) + (n - 2) * ld];
+            beta[n - 2] = 0.0;
+        }
+        d[n - 1] = S[(n - 1) + (n - 1) * ld];
+        beta[n - 1] = 0.0;
+        e[n - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Eigenvector of the symmetric tridiagonal (d, e) for the isolated
+// eigenvalue lam by the twisted factorisation; pivots go to dp/dm (stride
+// `st` between consecutive k).  Writes the unit vector to z (stride 1).
+__device__ void twisted_vector(const double *d, const double *e, int n, double lam, double tiny,
+                               double *dp, double *dm, int64_t st, double *z) {
+    double q = d[0] - lam;
+    if (q == 0.0) q = tiny;
+    dp[0] = q;
+    for (int k = 1; k < n; ++k) {
+        q = (d[k] - lam) - e[k - 1] * e[k - 1] / q;
+        if (q == 0.0) q = tiny;
+        dp[(int64_t)k * st] = q;
+    }
+    q = d[n - 1] - lam;
+    if (q == 0.0) q = tiny;
+    dm[(int64_t)(n - 1) * st] = q;
+    double gbest = fabs(dp[(int64_t)(n - 1) * st]);  // gamma_{n-1} = D+_{n-1}
+    int r = n - 1;
+    for (int k = n - 2; k >= 0; --k) {
+        q = (d[k] - lam) - e[k] * e[k] / q;
+        if (q == 0.0) q = tiny;
+        dm[(int64_t)k * st] = q;
+        const double gk = fabs(dp[(int64_t)k * st] + q - (d[k] - lam));
+        if (gk < gbest) {  // first minimum from the top; ties keep the larger k
+            gbest = gk;
+            r = k;
+        }
+    }
+    z[r] = 1.0;
+    double nn = 1.0;
+    double zk = 1.0;
+    for (int k = r - 1; k >= 0; --k) {
+        zk = -(e[k] / dp[(int64_t)k * st]) * zk;
+        z[k] = zk;
+        nn += zk * zk;
+    }
+    zk = 1.0;
+    for (int k = r + 1; k < n; ++k) {
+        zk = -(e[k - 1] / dm[(int64_t)k * st]) * zk;
+        z[k] = zk;
+        nn += zk * zk;
+    }
+    const double inv = 1.0 / sqrt(nn);
+    for (int k = 0; k < n; ++k) z[k] *= inv;
+}
+
+// Inverse iteration for the eigenvalues lam[i0..i1) of one cluster, with
+// Gram-Schmidt against the earlier members; vectors to Zt columns.
+__device__ void cluster_vectors(const double *d, const double *e, int n, const double *lam, int i0,
+                                int i1, double tiny, double *f, double *Zt) {
+    for (int i = i0; i < i1; ++i) {
+        double *x = Zt + (int64_t)i * n;
+        const double lm = lam[i] + (double)(i - i0) * 4.0 * tiny;
+        tri_factor(d, e, n, lm, tiny, f);
+        for (int k = 0; k < n; ++k) {
+            uint32_t h = (uint32_t)(k * 2654435761u) ^ (uint32_t)(i * 40503u + 0x9E37u);
+            h ^= h >> 15;
+            h *= 0x2C1B3C6Du;
+            h ^= h >> 12;
+            x[k] = 0.5 + (double)(h & 0xFFFF) * (1.0 / 65536.0);
+        }
+        for (int it = 0; it < 3; ++it) {
+            tri_solve(f, n, x);
+            for (int qv = i0; qv < i; ++qv) {
+                const double *y = Zt + (int64_t)qv * n;
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += y[k] * x[k];
+                for (int k = 0; k < n; ++k) x[k] -= s * y[k];
+            }
+            double mx = 0.0;
+            for (int k = 0; k < n; ++k) mx = fmax(mx, fabs(x[k]));
+            const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+            double nn = 0.0;
+            for (int k = 0; k < n; ++k) {
+                x[k] *= inv;
+                nn += x[k] * x[k];
+            }
+            const double rr = 1.0 / sqrt(nn);
+            for (int k = 0; k < n; ++k) x[k] *= rr;
+        }
+    }
+}
+
+// status[0]: 0 solved, 1 G not positive definite (nothing written);
+// status[1]: rank (= n when solved).
+__global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__restrict__ H,
+                                                            const double *__restrict__ G, int n,
+                                                            int which_smallest,
+                                                            double *__restrict__ theta,
+                                                            double *__restrict__ Y, FastWork fw,
+                                                            int *status) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    __shared__ double red2[32];
+    const int ld = n + 1;
+    double *S = smem;
+    double *rowbuf = S + (size_t)n * ld;  // 2 x 128
+    double *part = rowbuf + 256;          // 2 x 8 x 128
+    double *dd = part + 2048;             // d, e, e2, lam, beta, p: 128 each
+    double *ee = dd + 128, *e2 = ee + 128, *lam = e2 + 128, *beta = lam + 128, *pv = beta + 128;
+    const int t = threadIdx.x;
+    const int c = t & 127, g = t >> 7;
+    const bool cin = c < n;
+
+    // A. Cholesky of sym(G) in LDS
+    for (int el = t; el < n * n; el += SE_THREADS) {
+        const int i = el % n, j = el / n;
+        S[i + j * ld] = 0.5 * (G[i + j * n] + G[j + i * n]);
+    }
+    __syncthreads();
+    if (!chol_lds(S, ld, n)) {
+        if (t == 0) {
+            status[0] = 1;
+            status[1] = 0;
+        }
+        return;
+    }
+    // B. keep L in global memory
+    for (int el = t; el < n * n; el += SE_THREADS) {
+        const int i = el % n, j = el / n;
+        fw.Lg[el] = (i >= j) ? S[i + j * ld] : 0.0;
+    }
+    // C. X = sym(H) in registers; X <- L^{-1} X
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        x[q] = (r < n && cin) ? 0.5 * (H[r + c * n] + H[c + r * n]) : 0.0;
+    }
+    fwd_solve_reg(S, ld, n, x, rowbuf);
+    // D. transpose through global memory, X <- L^{-1} X^T = L^{-1} H L^{-T}
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        if (r < n && cin) fw.Tg[c + r * n] = x[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        x[q] = (r < n && cin) ? fw.Tg[r + c * n] : 0.0;
+    }
+    fwd_solve_reg(S, ld, n, x, rowbuf);
+    __syncthreads();
+    // E. C (symmetrised) into LDS over L
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        if (r < n && cin) S[r + c * ld] = x[q];
+    }
+    __syncthreads();
+    for (int el = t; el < n * n; el += SE_THREADS) {
+        const int i = el % n, j = el / n;
+        if (i > j) {
+            const double v = 0.5 * (S[i + j * ld] + S[j + i * ld]);
+            S[i + j * ld] = v;
+            S[j + i * ld] = v;
+        }
+    }
+    __syncthreads();
+    // F. tridiagonal T = Q^T C Q, eigenvalues by multisection
+    tridiag_lds(S, ld, n, dd, ee, beta, pv, red2);
+    for (int i = t; i < n; i += SE_THREADS) e2[i] = ee[i] * ee[i];
+    __syncthreads();
+    bisect_ptr(n, dd, ee, e2, lam);
+    // G. eigenvectors of T
+    double tn = 0.0;
+    for (int i = t; i < n; i += SE_THREADS) tn = fmax(tn, fmax(fabs(lam[i]), fabs(dd[i]) + fabs(ee[i])));
+    for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
+    if ((t & 63) == 0) red2[t >> 6] = tn;
+    __syncthreads();
+    tn = 0.0;
+    for (int i = 0; i < 16; ++i) tn = fmax(tn, red2[i]);
+    const double ortol = 1e-7 * tn;
+    const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
+    for (int i = t; i < n; i += SE_THREADS)
+        fw.cstart[i] = (i == 0 || lam[i] - lam[i - 1] > ortol) ? 1 : 0;
+    __syncthreads();
+    if (t < n) {
+        const int i = t;
+        if (fw.cstart[i]) {
+            int i1 = i + 1;
+            while (i1 < n && !fw.cstart[i1]) ++i1;
+            if (i1 == i + 1)
+                twisted_vector(dd, ee, n, lam[i], tiny, fw.dpm + i, fw.dpm + (int64_t)n * n + i, n,
+                               fw.Zt + (int64_t)i * n);
+            else
+                cluster_vectors(dd, ee, n, lam, i, i1, tiny, fw.scr + (int64_t)i * 6 * n, fw.Zt);
+        }
+    }
+    __syncthreads();
+    // H. back-transform Z = Q Z_T with Z in registers
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        x[q] = (r < n && cin) ? fw.Zt[r + c * n] : 0.0;
+    }
+    int pb = 0;  // partial-sum buffer, alternating between executed steps
+    for (int j = n - 3; j >= 0; --j) {
+        const double bt = beta[j];
+        if (bt == 0.0) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = g + 8 * q;
+            if (r > j && r < n) s += S[r + j * ld] * x[q];
+        }
+        double *pp = part + pb * 1024;
+        pb ^= 1;
+        pp[g * 128 + c] = s;
+        __syncthreads();
+        double tot = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) tot += pp[gg * 128 + c];
+        tot *= bt;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = g + 8 * q;
+            if (r > j && r < n) x[q] -= tot * S[r + j * ld];
+        }
+    }
+    __syncthreads();
+    // I. Y = L^{-T} Z with L back in LDS
+    for (int el = t; el < n * n; el += SE_THREADS) {
+        const int i = el % n, j = el / n;
+        S[i + j * ld] = fw.Lg[el];
+    }
+    __syncthreads();
+    bwd_solve_reg(S, ld, n, x, rowbuf);
+    // J. order: lam is ascending
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int r = g + 8 * q;
+        if (r < n && cin) {
+            const int pos = which_smallest ? c : n - 1 - c;
+            Y[r + (int64_t)pos * n] = x[q];
+        }
+    }
+    for (int i = t; i < n; i += SE_THREADS) theta[which_smallest ? i : n - 1 - i] = lam[i];
+    if (t == 0) {
+        status[0] = 0;
+        status[1] = n;
+    }
+}
+
+constexpr size_t fast_lds_bytes(int n) {
+    return ((size_t)n * (n + 1) + 256 + 2048 + 6 * 128) * sizeof(double);
+}
+
 PencilWork make_work(Context *ctx, int n) {
     PencilWork w;
     const size_t nn = (size_t)n * n;
@@ -669,8 +1094,34 @@ PencilWork make_work(Context *ctx, int n) {
 int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
                    double *theta, double *Y, bool want_rank) {
     OFRR_CHECK_ARG(b >= 1 && b <= 1024, "pencil: 1 <= b <= 1024");
-    PencilWork w = make_work(ctx, b + 1);
     int *status = ctx->buf<int>("pencil_status", 4);
+    if (b <= FP_NMAX) {
+        // fast path; falls through to the general kernel when G is not
+        // positive definite
+        const size_t nn = (size_t)b * b;
+        double *base = ctx->buf<double>("pencil_fast", 11 * nn + 8);
+        FastWork fw;
+        fw.Lg = base;
+        fw.Tg = base + nn;
+        fw.Zt = base + 2 * nn;
+        fw.dpm = base + 3 * nn;
+        fw.scr = base + 5 * nn;
+        fw.cstart = ctx->buf<int>("pencil_fast_i", (size_t)b + 8);
+        const size_t shmem = fast_lds_bytes(b);
+        OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_fast,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        {
+            KTimer tm(ctx, "small_eig");
+            hipLaunchKernelGGL(k_pencil_fast, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b,
+                               which == OFRR_SMALLEST ? 1 : 0, theta, Y, fw, status);
+            OFRR_HIP(hipGetLastError());
+        }
+        int host[2] = {1, 0};
+        OFRR_HIP(hipMemcpyAsync(host, status, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        if (host[0] == 0) return host[1];
+    }
+    PencilWork w = make_work(ctx, b + 1);
     zero_bytes(ctx, status, 16);
     const int use_lds = b <= SE_LDS_MAX_N ? 1 : 0;
     const size_t shmem = use_lds ? (size_t)b * b * sizeof(double) : 0;
