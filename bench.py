@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--refine", type=int, default=2,
                     help="1: BF16 then FP64 tail; 2: BF16, split-BF16, FP64 tail")
     ap.add_argument("--stall-iters", type=int, default=3)
+    ap.add_argument("--tail", choices=["f64", "i8"], default="i8",
+                    help="products of the final FP64 phase: FP64 arithmetic or exact INT8 digit planes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times; "
                          "used to scale rocprofv3 FETCH_SIZE/WRITE_SIZE readings")
@@ -147,8 +149,7 @@ def main():
     common = dict(filter="chebyshev", degree=DEGREE, lo=lo, hi=hi, tol=TOL * 0.5, anorm=anorm,
                   max_iters=400)
     mixed = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
-                           b_split=args.b_split,
-                           **common)
+                           b_split=args.b_split, tail=args.tail, **common)
     f64 = ofrr.make_plan(basis_dtype="f64", **common)
 
     res, ms_step, wall = run_steps(ctx, A, X0, mixed, args.steps, args.warmup, "mixed")
@@ -169,44 +170,56 @@ def main():
 
     # dominant kernel: the BF16 block product, timed per launch with HIP events
     prof = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
-                          b_split=args.b_split,
-                          profile=True, **common)
+                          b_split=args.b_split, tail=args.tail, profile=True, **common)
     ctx.kernel_stats_reset()
     ctx.eig_partial(A, K_WANT, BASIS, plan=prof, X0=X0)
     torch.cuda.synchronize()
-    fams = ["product_bf16", "product_bf16x2", "product_reduce", "product_f64", "hessenberg",
+    fams = ["product_bf16", "product_bf16x2", "product_i8x", "product_reduce", "product_f64", "hessenberg",
             "small_eig", "gram", "lift", "scale",
             "quantize", "residual"]
     stats = {f: ctx.kernel_stats(f) for f in fams}
     # dominant kernel: the block-product family with the largest total time
-    # in one call; algorithmic bytes per launch = A read once in its stored
-    # format + the basis block read once + the FP32/FP64 product written once
+    # in one call.  Per launch: algorithmic bytes = A read once in its stored
+    # format + the basis block read once + the product written once;
+    # algorithmic operations = 2 n^2 b per MFMA product (15 digit-pair
+    # products for the INT8 planes).  The bound is whichever of bytes / HBM
+    # peak and operations / MFMA peak of the kernel's type takes longer.
     vb = 2 if args.b_split >= 2 else 1
+    gemm = 2.0 * N * N * BASIS
     alg = {
-        "product_bf16": (N * N * 2 + vb * N * BASIS * 2 + N * BASIS * 4,
+        "product_bf16": (N * N * 2 + vb * N * BASIS * 2 + N * BASIS * 4, gemm * vb, 2500.0,
                          "k_gemm_lp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)"),
-        "product_bf16x2": (N * N * 4 + N * BASIS * 4 + N * BASIS * 4,
+        "product_bf16x2": (N * N * 4 + N * BASIS * 4 + N * BASIS * 4, 3 * gemm, 2500.0,
                            "k_gemm_lp<bf16, split A and V> (3 BF16 MFMAs per tile step)"),
-        "product_f64": (N * N * 4 + N * BASIS * 8 + N * BASIS * 8,
+        "product_f64": (N * N * 4 + N * BASIS * 8 + N * BASIS * 8, gemm, 78.6,
                         "k_gemm_f64 (A FP32 promoted, FP64 MFMA 16x16x4)"),
+        "product_i8x": (5 * N * N + 5 * N * BASIS + 8 * N * BASIS, 15 * gemm, 5000.0,
+                        "k_gemm_i8s (5 x 5 INT8 digit planes, 15 MFMA 32x32x32 pairs, exact int32)"),
     }
-    dom = max(alg, key=lambda f: stats[f][1])
-    launches, tot = stats[dom]
-    avg_ms = tot / max(launches, 1)
-    alg_bytes, kname = alg[dom]
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kname, "family": dom,
-                "avg_launch_ms": avg_ms, "launches": launches,
-                "algorithmic_bytes_per_launch": alg_bytes}
-    others = {}
-    for f, (ab, _) in alg.items():
+
+    def roof(f):
+        nb, ops, peak_t, kname = alg[f]
         n_l, t_l = stats[f]
-        if n_l:
-            others[f] = {"avg_launch_ms": t_l / n_l,
-                         "achieved_GBps": round(ab / (t_l / n_l * 1e-3) / 1e9, 1)}
-    roofline["per_family"] = others
+        avg = t_l / max(n_l, 1)
+        hbm_t = nb / (HBM_PEAK_GBS * 1e9)
+        mfma_t = ops / (peak_t * 1e12)
+        if hbm_t >= mfma_t:
+            ach = nb / (avg * 1e-3) / 1e9
+            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(ach / HBM_PEAK_GBS, 4)}
+        else:
+            ach = ops / (avg * 1e-3) / 1e12
+            r = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_t,
+                 "unit": "TOP/s" if f == "product_i8x" else "TFLOP/s", "frac": round(ach / peak_t, 4)}
+        r.update({"traffic": None, "kernel": kname, "family": f, "avg_launch_ms": avg, "launches": n_l,
+                  "algorithmic_bytes_per_launch": nb, "algorithmic_ops_per_launch": ops})
+        return r
+
+    dom = max(alg, key=lambda f: stats[f][1])
+    roofline = roof(dom)
+    roofline["per_family"] = {f: {k: v for k, v in roof(f).items() if k in ("bound", "achieved", "unit", "frac",
+                                                                           "avg_launch_ms")}
+                              for f in alg if stats[f][0]}
     kernel_ms = {f: {"launches": n, "total_ms": round(t, 3)} for f, (n, t) in stats.items()}
 
     cpu = None
@@ -222,7 +235,9 @@ def main():
         "config": {"workload": "dense symmetric n=16384, lambda_i=i^-1.5 + 1e-3 N(0,1) symmetric "
                                "noise, FP32 storage; top k=64, basis 128, degree-4 Chebyshev",
                    "n": N, "k": K_WANT, "basis": BASIS, "degree": DEGREE, "filter_interval": [lo, hi],
-                   "plan": "bf16 basis + FP32 accumulate, FP64 G/H and pencil, FP64 tail",
+                   "plan": (f"bf16 basis + FP32 accumulate{', split-BF16 middle phase' if args.refine >= 2 else ''}, "
+                            f"FP64 G/H and pencil, FP64 tail with "
+                            f"{'INT8 digit-plane' if args.tail == 'i8' else 'FP64'} products"),
                    "parallelism": "single GPU"},
         "n_converged": nconv, "iters": res[-1].info["iters"], "iters_low": res[-1].info["iters_low"],
         "fp64_form": f64_out,

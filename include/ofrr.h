@@ -60,6 +60,14 @@ typedef enum {
 
 typedef enum { OFRR_LARGEST = 0, OFRR_SMALLEST = 1 } ofrr_which;
 typedef enum { OFRR_POWER = 0, OFRR_CHEBYSHEV = 1 } ofrr_filter;
+/* Products of the FP64 phase that ends a refined plan (dense A). */
+typedef enum {
+    OFRR_TAIL_F64 = 0,       /* FP64 arithmetic */
+    OFRR_TAIL_I8_SLICED = 1  /* exact INT8 products of 7-bit digit planes: 5 of each row of
+                                A (FP32 or FP64 stored) and 5 of each basis column, the 15
+                                digit pairs of weight >= 2^-42 summed in int32; the result is
+                                within about 2^-33 of |A||V| per entry (FP64 gives 2^-53 K) */
+} ofrr_tail;
 
 /* Accumulation of the projections G = V^T V, H = V^T W (Sec. 4, mixed-
  * precision plan: reduced-precision inputs, higher-precision products). */
@@ -117,6 +125,9 @@ typedef struct {
     int32_t b_split;         /* BF16/F16 products: 2 carries the basis block as a two-
                                 term split (hi + lo) through the MFMA, 1 rounds it once */
     int32_t profile;         /* nonzero: time every kernel launch with HIP events */
+    int32_t tail_product;    /* ofrr_tail: products of the FP64 phase after reduced-precision
+                                phases (refine >= 1, dense A); the FP64 form (basis_dtype F64)
+                                always runs FP64 arithmetic */
 } ofrr_plan;
 
 typedef struct {
@@ -234,10 +245,20 @@ ofrr_status ofrr_quantize_fp8_blocks(ofrr_ctx ctx, int64_t rows, int64_t cols, c
  *             FP64 per v_dtype).
  *   trans     0: W = A V; 1: W = A^T V (dense only).
  *   v_dtype   element type of V and W as described above.
- *   V         (op(A) cols) x b, column-major ld = op cols; W (op rows) x b,
- *             ld = op rows. */
+ *   V         (op(A) cols) x b, row-major (ld = b); W (op rows) x b, row-major
+ *             (ld = b). */
 ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
                                ofrr_dtype v_dtype, const void *V, void *W);
+
+/* FP64-class block product W = op(A) V from exact INT8 digit-plane products
+ * (the OFRR_TAIL_I8_SLICED products of the final phase; Sec. 2 products).
+ * A: dense F32/F64 descriptor; V: FP64 row-major (op(A) cols) x b (ld b);
+ * W: FP64 row-major (op(A) rows) x b (ld b).  Per entry the error is below
+ * 2^-35 (2^e_i sum_k |V_kj| + 2^f_j sum_k |op(A)_ik| + 4.2 K 2^(e_i+f_j))
+ * plus FP64 rounding of the final sums, with 2^e_i the smallest power of two
+ * above max_k |op(A)_ik| and 2^f_j that above max_k |V_kj|. */
+ofrr_status ofrr_block_product_sliced(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
+                                      const double *V, double *W);
 
 /* FP8 block product W = op(A) V (trans 0: A V; 1: A^T V) for A given as
  * e4m3fn codes (rows x cols, column-major, ld = rows) with 32 x 32 block

@@ -18,7 +18,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                              double *V, double *resid, ofrr_info *info);
 
 static const char *kFamilies[] = {"quantize", "product_bf16", "product_bf16x2", "product_f16", "product_f8",
-                                  "product_f64", "product_f32", "product_reduce", "spmm", "scale",
+                                  "product_f64", "product_f32", "product_i8x", "product_reduce", "spmm", "scale",
                                   "hessenberg", "gram", "small_eig", "lift", "residual"};
 
 void *Workspace::get(const std::string &name, size_t bytes) {
@@ -156,6 +156,8 @@ static void validate_plan(const ofrr_plan *p) {
     OFRR_CHECK_ARG(p->max_iters >= 1, "max_iters must be >= 1");
     OFRR_CHECK_ARG(p->stall_iters >= 1, "stall_iters must be >= 1");
     OFRR_CHECK_ARG(p->b_split == 1 || p->b_split == 2, "b_split must be 1 or 2");
+    OFRR_CHECK_ARG(p->tail_product == OFRR_TAIL_F64 || p->tail_product == OFRR_TAIL_I8_SLICED,
+                   "tail_product must be OFRR_TAIL_F64 or OFRR_TAIL_I8_SLICED");
 }
 
 extern "C" {
@@ -178,6 +180,7 @@ void ofrr_plan_default(ofrr_plan *p) {
     p->switch_resid = 0.0;
     p->b_split = 1;
     p->profile = 0;
+    p->tail_product = OFRR_TAIL_F64;
 }
 
 ofrr_status ofrr_create(ofrr_ctx *out, int device, void *hip_stream) {
@@ -378,6 +381,22 @@ ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans
             OFRR_CHECK_ARG(v_dtype == OFRR_F64, "block_product: FP64 V for an F64/F32 dense A");
             product_f64(c, A, trans, b, (const double *)V, b, (double *)W, b);
         }
+        c->sync();
+        return OFRR_OK;
+    });
+}
+
+ofrr_status ofrr_block_product_sliced(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
+                                      const double *V, double *W) {
+    return guarded(ctx, [&](Context *c) {
+        OFRR_CHECK_ARG(A && V && W && b >= 1 && b <= 4096, "block_product_sliced: bad arguments");
+        OFRR_CHECK_ARG(trans == 0 || trans == 1, "trans must be 0 or 1");
+        validate_matrix(A, false);
+        OFRR_CHECK_ARG(A->format == OFRR_DENSE_COLMAJOR && (A->dtype == OFRR_F32 || A->dtype == OFRR_F64),
+                       "block_product_sliced: dense F32/F64 A");
+        OFRR_HIP(hipSetDevice(c->device));
+        const SlicedA sa = slice_matrix_i8(c, A, trans);
+        product_i8s(c, sa, b, V, b, W, b);
         c->sync();
         return OFRR_OK;
     });

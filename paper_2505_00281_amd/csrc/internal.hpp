@@ -191,6 +191,16 @@ void check_csr(Context *ctx, const ofrr_matrix *A);
 void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,
                  int64_t ldv, void *W, int64_t ldw);
 
+// k_gemm_i8.hip: FP64-class product from exact INT8 digit-plane products
+struct SlicedA {
+    int8_t *planes = nullptr;  // 5 planes of mpad x kpad digits (K-contiguous rows of op(A))
+    int32_t *ex = nullptr;     // per-row exponent bounds (mpad)
+    int64_t m = 0, kdim = 0, mpad = 0, kpad = 0, plane_stride = 0;
+};
+SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans);
+void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
+                 int64_t ldw);
+
 // k_hessenberg.hip
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                    double tol, int32_t *piv, int32_t *keep, bool want_count);

@@ -1,0 +1,359 @@
+// k_gemm_i8.hip -- FP64-class block product W = op(A) V for the final,
+// full-accuracy phase, on INT8 MFMA with exact integer accumulation.
+//
+// The final phase needs products accurate to far below the 1e-8 residual
+// target, which FP32 accumulation cannot give (its rounding is about
+// 2^-24 |A||V|).  MI355X runs FP64 at 78.6 TFLOP/s but INT8 MFMA at
+// 5 POP/s, so the product is rebuilt from exact integer pieces:
+//   op(A)[i][k] = 2^{e_i} sum_{s=1..5} a_s[i][k] 2^{-7s}   (+ |rest| < 2^{e_i-35})
+//   V[k][j]     = 2^{f_j} sum_{t=1..5} v_t[k][j] 2^{-7t}   (+ |rest| < 2^{f_j-35})
+// with signed 7-bit digits |a_s|, |v_t| <= 127 (truncation of the scaled
+// value, exact in floating point), e_i the exponent bound of row i of
+// op(A) and f_j that of column j of V.  Then
+//   W[i][j] = 2^{e_i + f_j} sum_{p=2..6} 2^{-7p} sum_{s+t=p} (a_s v_t)[i][j]
+// keeping the 15 digit pairs with s + t <= 6.  Every (a_s v_t) is an exact
+// int8 x int8 -> int32 dot product; pairs with equal s + t share one int32
+// accumulator (at most 5 pairs x 127^2 x 16384 < 2^31 per K range, so the
+// K range of one accumulation is capped at 16384).  The dropped pairs and
+// the digit remainders are below 2^-35 of the row/column scales, i.e.
+// about 1e-10 of |A||V| where FP32 accumulation gives 6e-8.
+//
+// MFMA v_mfma_i32_32x32x32_i8: lane l holds A[l%32][16(l/32)..+16] and
+// B[16(l/32)..+16][l%32] (any consistent K order is exact for integers);
+// accumulator register r is D[(r/4)*8 + 4(l/32) + r%4][l%32].
+#include "internal.hpp"
+#include "device_util.hpp"
+
+namespace ofrr {
+
+namespace {
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+constexpr int I8_S = 5;     // digit planes of A and of V
+constexpr int I8_BM = 64;   // rows per workgroup tile
+constexpr int I8_BK = 64;   // K bytes per LDS stage
+constexpr int I8_LD = 80;   // LDS row stride in bytes (64 + 16: conflict-free 16-byte reads)
+constexpr int I8_KMAX = 16384;  // K per int32 accumulation
+
+// exponent e with |x| < 2^e for the largest |x| (0 for an all-zero set)
+__device__ __forceinline__ int exp_bound(double amax) {
+    if (!(amax > 0.0)) return 0;
+    int e;
+    (void)frexp(amax, &e);  // amax = m 2^e, m in [0.5, 1)
+    return e;
+}
+
+// five signed 7-bit digits of x 2^-e, |x 2^-e| < 1, by truncation (exact)
+__device__ __forceinline__ void digits5(double x, int e, int8_t (&d)[I8_S]) {
+    double r = ldexp(x, -e);
+#pragma unroll
+    for (int s = 0; s < I8_S; ++s) {
+        r *= 128.0;
+        const double q = trunc(r);
+        d[s] = (int8_t)(int)q;
+        r -= q;
+    }
+}
+
+// Row slicing of op(A) (one workgroup per output row, rows past m zero).
+// ATRANS: op(A)[i][k] = A[k + i*lda] (K-contiguous), else A[i + k*lda].
+template <class TA, bool ATRANS>
+__global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, int64_t lda, int64_t m,
+                                                    int64_t kdim, int64_t kpad,
+                                                    int8_t *__restrict__ planes, int64_t plane_stride,
+                                                    int32_t *__restrict__ ex) {
+    __shared__ double red[4];
+    const int64_t i = blockIdx.x;
+    const int t = threadIdx.x;
+    auto at = [&](int64_t k) -> double {
+        return (double)(ATRANS ? A[k + i * lda] : A[i + k * lda]);
+    };
+    double amax = 0.0;
+    if (i < m)
+        for (int64_t k = t; k < kdim; k += 256) amax = fmax(amax, fabs(at(k)));
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+    if ((t & 63) == 0) red[t >> 6] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const int e = exp_bound(amax);
+    if (t == 0) ex[i] = e;
+    for (int64_t k0 = (int64_t)t * 16; k0 < kpad; k0 += 256 * 16) {
+        int8_t d[I8_S][16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            int8_t dq[I8_S];
+            const int64_t k = k0 + q;
+            digits5((i < m && k < kdim) ? at(k) : 0.0, e, dq);
+#pragma unroll
+            for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
+        }
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+            *(v4i_t *)(planes + s * plane_stride + i * kpad + k0) = __builtin_bit_cast(v4i_t, d[s]);
+    }
+}
+
+// Column-maximum partials of an FP64 row-major block (rows x b, ld):
+// block g covers rows [256 g, 256 g + 256); part[g * bpad + j].
+__global__ __launch_bounds__(256) void k_vmax_partial(const double *__restrict__ V, int64_t rows, int b,
+                                                      int64_t ld, int bpad, double *__restrict__ part) {
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    for (int j = threadIdx.x; j < bpad; j += 256) {
+        double m = 0.0;
+        if (j < b)
+            for (int64_t r = r0; r < r0 + 256 && r < rows; ++r) m = fmax(m, fabs(V[r * ld + j]));
+        part[(int64_t)blockIdx.x * bpad + j] = m;
+    }
+}
+
+__global__ void k_vexp(const double *__restrict__ part, int nblk, int bpad, int32_t *__restrict__ fx) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= bpad) return;
+    double m = 0.0;
+    for (int g = 0; g < nblk; ++g) m = fmax(m, part[(int64_t)g * bpad + j]);
+    fx[j] = exp_bound(m);
+}
+
+// Digit planes of V, K-contiguous per column: planes[s][j][k], 16 rows of
+// one column per thread (columns past b and rows past `rows` are zero).
+__global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, int64_t rows, int b,
+                                                int64_t ld, int bpad, int64_t kpad,
+                                                const int32_t *__restrict__ fx,
+                                                int8_t *__restrict__ planes, int64_t plane_stride) {
+    const int64_t total = (int64_t)bpad * (kpad / 16);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e % bpad);
+        const int64_t k0 = (e / bpad) * 16;
+        const int f = fx[j];
+        int8_t d[I8_S][16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t k = k0 + q;
+            int8_t dq[I8_S];
+            digits5((j < b && k < rows) ? V[k * ld + j] : 0.0, f, dq);
+#pragma unroll
+            for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
+        }
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+            *(v4i_t *)(planes + s * plane_stride + (int64_t)j * kpad + k0) = __builtin_bit_cast(v4i_t, d[s]);
+    }
+}
+
+// W slab z (rows x b FP64, ld) = the K range z of op(A) V from the digit
+// planes.  Workgroup tile 64 rows x (64 NCT) columns, 2 x 2 waves of
+// 32 rows x (32 NCT) columns; 64-byte K stages through LDS, the next stage
+// prefetched into registers.
+template <int NCT>
+__global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap, int64_t a_stride,
+                                                  const int32_t *__restrict__ ex,
+                                                  const int8_t *__restrict__ Vp, int64_t v_stride,
+                                                  const int32_t *__restrict__ fx, int64_t kpad,
+                                                  int64_t m, int b, double *__restrict__ W,
+                                                  int64_t ldw, int64_t k_per_split, int ntiles,
+                                                  int nsplit, int xcd_map) {
+    constexpr int BN = 64 * NCT;
+    __shared__ __attribute__((aligned(16))) int8_t As[I8_S][I8_BM][I8_LD];
+    __shared__ __attribute__((aligned(16))) int8_t Vs[I8_S][BN][I8_LD];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    int tile, z;
+    const int L = blockIdx.x;
+    if (xcd_map) {
+        const int xcd = L & 7, slot = L >> 3, per = 8 / nsplit;
+        z = xcd % nsplit;
+        tile = slot * per + xcd / nsplit;
+    } else {
+        tile = L % ntiles;
+        z = L / ntiles;
+    }
+    if (tile >= ntiles) return;
+    const int gy = (b + BN - 1) / BN;
+    const int64_t i0 = (int64_t)(tile / gy) * I8_BM;
+    const int j0 = (tile % gy) * BN;
+    const int64_t kbeg = (int64_t)z * k_per_split;
+    const int64_t kend = kbeg + k_per_split < kpad ? kbeg + k_per_split : kpad;
+
+    v16i_t acc[NCT][5];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int p = 0; p < 5; ++p) acc[ct][p] = v16i_t{};
+
+    // register staging: A 5 chunks (one per plane), V 5 x NCT chunks
+    v4i_t ra[I8_S], rv[I8_S][NCT];
+    const int arow = t >> 2, achk = (t & 3) * 16;
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+            ra[s] = *(const v4i_t *)(Ap + s * a_stride + (i0 + arow) * kpad + k0 + achk);
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+#pragma unroll
+            for (int h = 0; h < NCT; ++h)
+                rv[s][h] = *(const v4i_t *)(Vp + s * v_stride + (int64_t)(j0 + arow + 64 * h) * kpad + k0 + achk);
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s) *(v4i_t *)&As[s][arow][achk] = ra[s];
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+#pragma unroll
+            for (int h = 0; h < NCT; ++h) *(v4i_t *)&Vs[s][arow + 64 * h][achk] = rv[s][h];
+    };
+
+    fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += I8_BK) {
+        stash();
+        __syncthreads();
+        if (k0 + I8_BK < kend) fetch(k0 + I8_BK);
+#pragma unroll
+        for (int ks = 0; ks < I8_BK; ks += 32) {
+            const int kq = ks + 16 * (lane >> 5);
+            v4i_t a[I8_S];
+#pragma unroll
+            for (int s = 0; s < I8_S; ++s) a[s] = *(const v4i_t *)&As[s][32 * wr + (lane & 31)][kq];
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                const int col = 32 * NCT * wc + 32 * ct + (lane & 31);
+                v4i_t v[I8_S];
+#pragma unroll
+                for (int s = 0; s < I8_S; ++s) v[s] = *(const v4i_t *)&Vs[s][col][kq];
+#pragma unroll
+                for (int s = 0; s < I8_S; ++s)
+#pragma unroll
+                    for (int u = 0; u < I8_S; ++u)
+                        if (s + u <= 4)
+                            acc[ct][s + u] =
+                                __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[ct][s + u], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double *Wz = W + (int64_t)z * m * ldw;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+        const int gj = j0 + 32 * NCT * wc + 32 * ct + (lane & 31);
+        const int fj = gj < b ? fx[gj] : 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t gi = i0 + 32 * wr + (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
+            if (gi >= m || gj >= b) continue;
+            double v = (double)acc[ct][4][r];
+            v = (double)acc[ct][3][r] + v * 0.0078125;
+            v = (double)acc[ct][2][r] + v * 0.0078125;
+            v = (double)acc[ct][1][r] + v * 0.0078125;
+            v = (double)acc[ct][0][r] + v * 0.0078125;
+            Wz[gi * ldw + gj] = ldexp(v, ex[gi] + fj - 14);
+        }
+    }
+}
+
+__global__ void k_sum_slabs_f64(const double *__restrict__ P, int nsplit, int64_t m, int b, int64_t ld,
+                                double *__restrict__ W) {
+    const int64_t total = m * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        double s = 0.0;
+        for (int zz = 0; zz < nsplit; ++zz) s += P[(int64_t)zz * m * ld + i * ld + j];
+        W[i * ld + j] = s;
+    }
+}
+
+inline int grid1(int64_t total) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+}
+
+}  // namespace
+
+SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
+    OFRR_CHECK_ARG(A->format == OFRR_DENSE_COLMAJOR, "sliced product: dense A");
+    OFRR_CHECK_ARG(A->dtype == OFRR_F32 || A->dtype == OFRR_F64, "sliced product: A is F32 or F64");
+    SlicedA s;
+    s.m = trans ? A->cols : A->rows;
+    s.kdim = trans ? A->rows : A->cols;
+    s.mpad = (s.m + I8_BM - 1) / I8_BM * I8_BM;
+    s.kpad = (s.kdim + I8_BK - 1) / I8_BK * I8_BK;
+    s.plane_stride = s.mpad * s.kpad;
+    s.planes = ctx->buf<int8_t>("i8_a_planes", (size_t)I8_S * s.plane_stride);
+    s.ex = ctx->buf<int32_t>("i8_a_exp", (size_t)s.mpad);
+    KTimer tm(ctx, "quantize");
+    auto go = [&](auto kern, auto p) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)s.mpad), dim3(256), 0, ctx->stream, p, A->ld, s.m, s.kdim,
+                           s.kpad, s.planes, s.plane_stride, s.ex);
+    };
+    const float *af = (const float *)A->values;
+    const double *ad = (const double *)A->values;
+    if (A->dtype == OFRR_F32) {
+        if (trans) go(k_slice_rows<float, true>, af); else go(k_slice_rows<float, false>, af);
+    } else {
+        if (trans) go(k_slice_rows<double, true>, ad); else go(k_slice_rows<double, false>, ad);
+    }
+    OFRR_HIP(hipGetLastError());
+    return s;
+}
+
+void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
+                 int64_t ldw) {
+    OFRR_CHECK_ARG(b >= 1 && b <= 4096, "sliced product: 1 <= b <= 4096");
+    const int NCT = b > 64 ? 2 : 1;
+    const int BN = 64 * NCT;
+    const int bpad = (b + BN - 1) / BN * BN;
+    const int64_t kpad = sa.kpad;
+    // digit planes of V
+    const int64_t v_stride = (int64_t)bpad * kpad;
+    int8_t *vp = ctx->buf<int8_t>("i8_v_planes", (size_t)I8_S * v_stride);
+    int32_t *fx = ctx->buf<int32_t>("i8_v_exp", (size_t)bpad);
+    const int nblk = (int)((sa.kdim + 255) / 256);
+    double *part = ctx->buf<double>("i8_v_part", (size_t)nblk * bpad);
+    {
+        KTimer tm(ctx, "quantize");
+        hipLaunchKernelGGL(k_vmax_partial, dim3(nblk), dim3(256), 0, ctx->stream, V, sa.kdim, b, ldv, bpad,
+                           part);
+        hipLaunchKernelGGL(k_vexp, dim3((bpad + 255) / 256), dim3(256), 0, ctx->stream, part, nblk, bpad, fx);
+        hipLaunchKernelGGL(k_vslice, dim3(grid1((int64_t)bpad * (kpad / 16))), dim3(256), 0, ctx->stream, V,
+                           sa.kdim, b, ldv, bpad, kpad, fx, vp, v_stride);
+        OFRR_HIP(hipGetLastError());
+    }
+    // launch shape: enough workgroups for two per CU, K ranges <= I8_KMAX
+    const int gx = (int)(sa.mpad / I8_BM), gy = bpad / BN;
+    const int ntiles = gx * gy;
+    int nsplit = 1;
+    const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
+    while (((int64_t)ntiles * nsplit < want && kpad / (nsplit * 2) >= 2048 && nsplit < 8) ||
+           (kpad + nsplit - 1) / nsplit > I8_KMAX)
+        nsplit *= 2;
+    int64_t kps = (kpad + nsplit - 1) / nsplit;
+    kps = (kps + I8_BK - 1) / I8_BK * I8_BK;
+    nsplit = (int)((kpad + kps - 1) / kps);
+    const int xcd_map = (nsplit >= 2 && 8 % nsplit == 0) ? 1 : 0;
+    int64_t nwg = (int64_t)ntiles * nsplit;
+    if (xcd_map) nwg = (int64_t)((ntiles + 8 / nsplit - 1) / (8 / nsplit)) * 8;
+    double *dst = W;
+    if (nsplit > 1) dst = ctx->buf<double>("i8_slabs", (size_t)nsplit * sa.m * ldw);
+    {
+        KTimer tm(ctx, "product_i8x");
+        if (NCT == 2)
+            hipLaunchKernelGGL(k_gemm_i8s<2>, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, sa.planes,
+                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.m, b, dst, ldw, kps, ntiles,
+                               nsplit, xcd_map);
+        else
+            hipLaunchKernelGGL(k_gemm_i8s<1>, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, sa.planes,
+                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.m, b, dst, ldw, kps, ntiles,
+                               nsplit, xcd_map);
+        OFRR_HIP(hipGetLastError());
+    }
+    if (nsplit > 1) {
+        KTimer tm(ctx, "product_reduce");
+        hipLaunchKernelGGL(k_sum_slabs_f64, dim3(grid1(sa.m * b)), dim3(256), 0, ctx->stream, dst, nsplit, sa.m,
+                           b, ldw, W);
+        OFRR_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace ofrr

@@ -10,18 +10,24 @@
 // in place in HBM/L2).  Per column there is exactly one grid-wide exchange:
 //   1. every workgroup publishes its local pivot candidate (value, row) and
 //      a copy of that candidate row's trailing entries into a double-
-//      buffered slot, then raises the slot's sequence flag to j+1;
-//   2. every workgroup waits for all G flags (one thread per flag, polled in
-//      parallel: the barrier and the candidate exchange are one round trip,
-//      with no contended atomic counter);
-//   3. every workgroup picks the global winner (largest magnitude, smallest
-//      row on ties -- the same rule in every workgroup, so no broadcast is
-//      needed), reads the winner's published row as the multipliers, and
-//      runs the elimination over its rows.  That pass also produces the
-//      local candidate of column j+1, so the pivot search never needs a
-//      pass of its own.
-// The slot copy is what makes one barrier enough: the pivot row's owner may
-// already be overwriting that row while others still need its old values.
+//      buffered slot;
+//   2. every workgroup reads all G candidates (one thread per workgroup,
+//      in parallel), picks the global winner (largest magnitude, smallest
+//      row on ties -- the same rule everywhere, so no broadcast is needed),
+//      reads the winner's published row as the multipliers, and runs the
+//      elimination over its rows.  That pass also produces the local
+//      candidate of column j+1, so the pivot search never needs a pass of
+//      its own.
+// The exchange uses no fences and no flags: every published 32-bit word is
+// stored together with the column's sequence number as one 64-bit relaxed
+// device-scope atomic, and a reader polls each word it needs until the tag
+// matches.  A 64-bit atomic is single-copy atomic, so a matching tag proves
+// the payload beside it is the current one; cache write-backs and
+// invalidations (what release/acquire ordering costs across the XCDs) are
+// never needed.  The slot copy is what makes one exchange per column
+// enough: the pivot row's owner may already be overwriting that row while
+// others still read its old values.  The slots are cleared (tag 0) before
+// the sweep; column j uses tag j + 1.
 // Each update is one fused multiply-add, as in the reference process.
 #include <cstdlib>
 
@@ -72,21 +78,66 @@ __device__ __forceinline__ void wave_argmax(M &m, int &i) {
     }
 }
 
+// Tagged words: payload in the high 32 bits, sequence tag in the low 32.
+__device__ __forceinline__ void put_word(uint64_t *dst, uint32_t w, uint32_t tag) {
+    __hip_atomic_store(dst, ((uint64_t)w << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Polls *src until its tag is `tag`; false after the spin budget or once
+// another workgroup has raised the error flag.
+__device__ __forceinline__ bool get_word(const uint64_t *src, uint32_t tag, uint32_t &w, int *err) {
+    unsigned long long spins = 0;
+    for (;;) {
+        const uint64_t v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)v == tag) {
+            w = (uint32_t)(v >> 32);
+            return true;
+        }
+        if (++spins > (1ull << 22) ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// 32-bit words of a value
+template <class V>
+struct NWords {
+    static constexpr int value = sizeof(V) / 4;
+};
+template <class V>
+__device__ __forceinline__ void put_value(uint64_t *dst, V v, uint32_t tag) {
+    uint32_t w[NWords<V>::value];
+    __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+    for (int q = 0; q < NWords<V>::value; ++q) put_word(dst + q, w[q], tag);
+}
+template <class V>
+__device__ __forceinline__ bool get_value(const uint64_t *src, uint32_t tag, V &v, int *err) {
+    uint32_t w[NWords<V>::value];
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < NWords<V>::value; ++q) ok = ok && get_word(src + q, tag, w[q], err);
+    __builtin_memcpy(&v, w, sizeof(V));
+    return ok;
+}
+
 template <class T, bool RESIDENT>
 __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t ldy, int64_t n,
                                                     int b, double tol, int32_t *__restrict__ piv,
                                                     int32_t *__restrict__ keep, int64_t rows_per,
-                                                    T *__restrict__ slot_rows,
-                                                    typename MagT<T>::type *__restrict__ slot_mag,
-                                                    int32_t *__restrict__ slot_idx,
-                                                    int32_t *__restrict__ slot_seq,
+                                                    uint64_t *__restrict__ slot_rows,
+                                                    uint64_t *__restrict__ slot_cand,
                                                     int *__restrict__ err,
                                                     int32_t *__restrict__ kept_out) {
     using M = typename MagT<T>::type;
+    constexpr int TW = NWords<T>::value;      // words per row entry
+    constexpr int CW = NWords<M>::value + 1;  // words per candidate (magnitude, row)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ T w_sh[512];  // multipliers of the current column (b <= 512)
     __shared__ M red_m[4];
-    __shared__ int red_i[4];
+    __shared__ int red_i[4], red_g[4];
     __shared__ int s_win_idx, s_win_g;
     __shared__ M s_win_mag;
 
@@ -107,7 +158,6 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         __syncthreads();
     }
 
-    // local candidate of column 0
     auto local_argmax = [&](int col, M &bm, int &bi) {
         bm = (M)-1;
         bi = 0x7fffffff;
@@ -144,48 +194,32 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     int kept = 0;
     for (int j = 0; j < b; ++j) {
         const int buf = j & 1;
-        // 1. publish the local candidate and a copy of its row (columns j..b-1)
-        T *my_slot = slot_rows + ((int64_t)buf * G + g) * b;
+        const uint32_t tag = (uint32_t)j + 1u;
+        // 1. publish the candidate row (columns j..b-1), then the candidate
+        uint64_t *my_row = slot_rows + ((int64_t)buf * G + g) * b * TW;
         if (ci != 0x7fffffff) {
             const int64_t rr = ci - r0;
-            for (int c = j + t; c < b; c += 256)
-                __hip_atomic_store(my_slot + c, rows[rr * ldr + c], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int c = j + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, rows[rr * ldr + c], tag);
         }
         if (t == 0) {
-            __hip_atomic_store(slot_mag + buf * G + g, cm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(slot_idx + buf * G + g, ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t *my_cand = slot_cand + ((int64_t)buf * G + g) * CW;
+            put_value<M>(my_cand, cm, tag);
+            put_word(my_cand + CW - 1, (uint32_t)ci, tag);
         }
-        __threadfence();
-        __syncthreads();
-        // 2. the slot's sequence flag (column j+1) is the only grid-wide signal:
-        // readers poll every workgroup's flag in parallel (one thread each), so
-        // the barrier and the candidate exchange are one round trip and there
-        // is no contended counter
-        if (t == 0)
-            __hip_atomic_store(slot_seq + buf * G + g, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        // 3. global winner, same rule everywhere
+        // 2. every candidate, one thread per workgroup
         {
             M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
             int ok = 1;
             for (int h = t; h < G; h += 256) {
-                unsigned long long spins = 0;
-                while (__hip_atomic_load(slot_seq + buf * G + h, __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT) < j + 1) {
-                    if (++spins > (1ull << 24) ||
-                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+                const uint64_t *cand = slot_cand + ((int64_t)buf * G + h) * CW;
+                M m2;
+                uint32_t i2u = 0;
+                if (!get_value<M>(cand, tag, m2, err) || !get_word(cand + CW - 1, tag, i2u, err)) {
+                    ok = 0;
+                    break;
                 }
-                if (!ok) break;
-                const M m2 = __hip_atomic_load(slot_mag + buf * G + h, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                const int i2 = __hip_atomic_load(slot_idx + buf * G + h, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+                const int i2 = (int)i2u;
                 if (m2 > bm || (m2 == bm && i2 < bi)) {
                     bm = m2;
                     bi = i2;
@@ -193,7 +227,6 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
                 }
             }
             if (!__syncthreads_and(ok)) break;
-            // reduce (bm, bi) and carry the owning workgroup along with the row
             for (int o = 32; o > 0; o >>= 1) {
                 M m2 = __shfl_xor(bm, o, 64);
                 int i2 = __shfl_xor(bi, o, 64);
@@ -204,7 +237,6 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
                     bg = g2;
                 }
             }
-            __shared__ int red_g[4];
             if (lane == 0) {
                 red_m[wave] = bm;
                 red_i[wave] = bi;
@@ -242,14 +274,23 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             continue;
         }
         ++kept;
-        // multipliers: the winner's published row (columns j..b-1)
-        const T *win_slot = slot_rows + ((int64_t)buf * G + wg) * b;
-        for (int c = j + t; c < b; c += 256)
-            w_sh[c] = __hip_atomic_load(win_slot + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
+        // 3. multipliers: the winner's published row (columns j..b-1)
+        {
+            const uint64_t *win_row = slot_rows + ((int64_t)buf * G + wg) * b * TW;
+            int ok = 1;
+            for (int c = j + t; c < b; c += 256) {
+                T v;
+                if (!get_value<T>(win_row + (int64_t)c * TW, tag, v, err)) {
+                    ok = 0;
+                    break;
+                }
+                w_sh[c] = v;
+            }
+            if (!__syncthreads_and(ok)) break;
+        }
         const T pivot = w_sh[j];
         // elimination over own rows, one wavefront per row, lanes over columns;
-        // lane 0..63 also track the next column's candidate
+        // lane 0 of each wave also tracks the next column's candidate
         M nm = (M)-1;
         int ni = 0x7fffffff;
         for (int64_t rr = wave; rr < nrows; rr += 4) {
@@ -268,8 +309,6 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             }
             if (lane == 0) row[j] = q;
         }
-        // the candidate sits in lane 0 of each wave (column j+1 is handled by
-        // lane 0 since c = j+1 is the first column of the lane loop)
         if (j + 1 < b) {
             cm = nm;
             ci = ni;
@@ -293,10 +332,12 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     if (g == 0 && t == 0 && kept_out) *kept_out = kept;
 }
 
-// clears the error flag, the kept count and the 2*G sequence flags (a
-// kernel, not a memset, so the sweep can be captured in a graph)
-__global__ void k_hess_reset(int *flags, int nflags) {
-    for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
+// Clears the error flag, the kept count and every tagged slot word (a
+// kernel, not a memset, so the sweep can be captured in a graph).
+__global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x)
+        words[i] = 0;
 }
 
 template <class T>
@@ -306,11 +347,11 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     OFRR_CHECK_ARG(n >= 1 && n < (int64_t)0x7fffffff, "hessenberg: 1 <= n < 2^31");
     OFRR_CHECK_ARG(ldy >= b, "hessenberg: ld >= b");
     using M = typename MagT<T>::type;
-    // rows per workgroup: LDS-resident when the slice fits in 64 KiB
     // LDS per workgroup for its row slice (OFRR_HESS_LDS_KB overrides, for
-    // tuning sweeps): a bigger slice means fewer workgroups meeting at each
-    // per-column grid barrier
-    size_t lds_budget = 64 * 1024;
+    // tuning sweeps): the rows stay resident when the slices of all
+    // workgroups fit one per CU; fewer, larger slices mean fewer candidates
+    // to read per column
+    size_t lds_budget = 128 * 1024;
     if (const char *s = std::getenv("OFRR_HESS_LDS_KB")) {
         const long kb = std::strtol(s, nullptr, 10);
         if (kb >= 8 && kb <= 150) lds_budget = (size_t)kb * 1024;
@@ -322,8 +363,6 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     int G;
     if (rows_res >= 16 && (n + rows_res - 1) / rows_res <= cus) {
         resident = true;
-        // as many rows per workgroup as fit: the sweep is barrier-bound, and
-        // fewer participants make each grid barrier cheaper
         rows_per = std::min<int64_t>(rows_res, n);
         G = (int)((n + rows_per - 1) / rows_per);
     } else {
@@ -334,15 +373,19 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     }
     const size_t shmem = resident ? (size_t)rows_per * b * sizeof(T) : 0;
 
-    T *slot_rows = ctx->buf<T>("hess_slot_rows", (size_t)2 * G * b);
-    M *slot_mag = ctx->buf<M>("hess_slot_mag", (size_t)2 * G);
-    int32_t *slot_idx = ctx->buf<int32_t>("hess_slot_idx", (size_t)2 * G);
-    // flags: [0] error, [1] kept count, [2..2+2G) per-slot sequence numbers
-    int *flags = ctx->buf<int>("hess_flags", 2 + (size_t)2 * G);
-    int *err = flags;
-    int32_t *kept_d = flags + 1;
-    int32_t *slot_seq = flags + 2;
-    hipLaunchKernelGGL(k_hess_reset, dim3(1), dim3(256), 0, ctx->stream, flags, 2 + 2 * G);
+    // one word buffer: [0] error flag and kept count (two ints), then the
+    // candidate slots (2 x G x CW words), then the row slots (2 x G x b x TW)
+    constexpr int TW = (int)(sizeof(T) / 4);
+    constexpr int CW = (int)(sizeof(M) / 4) + 1;
+    const int64_t ncand = (int64_t)2 * G * CW, nrow = (int64_t)2 * G * b * TW;
+    const int64_t nwords = 1 + ncand + nrow;
+    uint64_t *words = ctx->buf<uint64_t>("hess_words", (size_t)nwords);
+    int *err = reinterpret_cast<int *>(words);
+    int32_t *kept_d = err + 1;
+    uint64_t *slot_cand = words + 1;
+    uint64_t *slot_rows = words + 1 + ncand;
+    hipLaunchKernelGGL(k_hess_reset, dim3((unsigned)std::min<int64_t>(256, (nwords + 255) / 256)), dim3(256), 0,
+                       ctx->stream, words, nwords);
     OFRR_HIP(hipGetLastError());
 
     auto kern = resident ? (void *)k_hessenberg<T, true> : (void *)k_hessenberg<T, false>;
@@ -351,8 +394,8 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, shmem));
     if ((int64_t)per_cu * cus < G)
         fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
-    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &rows_per, &slot_rows, &slot_mag,
-                    &slot_idx, &slot_seq, &err, &kept_d};
+    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &rows_per, &slot_rows, &slot_cand, &err,
+                    &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
         OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, (unsigned)shmem, ctx->stream));

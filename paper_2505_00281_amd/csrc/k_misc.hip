@@ -104,27 +104,37 @@ template <class T>
 __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
                                                         int64_t n, int b, int64_t rows_per_block,
                                                         float *__restrict__ part, int nblk) {
-    __shared__ unsigned cm[512];
-    for (int j = threadIdx.x; j < b; j += blockDim.x) cm[j] = 0u;
-    __syncthreads();
+    // no atomics: for b <= 256 the block is split into 256 / b row groups,
+    // thread t takes column t % b of group t / b (consecutive threads read
+    // consecutive columns); wider blocks loop over columns.  Magnitudes are
+    // compared as FP32 bit patterns (monotone for non-negative floats); a
+    // NaN or infinity anywhere marks the column with all ones.
+    __shared__ unsigned cm[256];
+    const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
-    const int64_t total = (r1 - r0) * b;
-    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-        const int64_t r = r0 + e / b;
-        const int j = (int)(e % b);
-        const double v = load_as_f64(Y + r * ldy + j);
-        unsigned bits;
-        if (!(v == v) || isinf(v))
-            bits = 0xFFFFFFFFu;
-        else
-            bits = __float_as_uint((float)fabs(v));
-        atomicMax(&cm[j], bits);
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < b; j += blockDim.x) {
-        const unsigned bits = cm[j];
-        part[(int64_t)j * nblk + blockIdx.x] = bits == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(bits);
+    auto mag_bits = [](double v) -> unsigned {
+        return (!(v == v) || isinf(v)) ? 0xFFFFFFFFu : __float_as_uint((float)fabs(v));
+    };
+    if (b <= 256) {
+        const int groups = 256 / b;
+        const int j = t % b, g = t / b;
+        unsigned m = 0u;
+        if (g < groups)
+            for (int64_t r = r0 + g; r < r1; r += groups) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
+        cm[t] = m;
+        __syncthreads();
+        if (t < b) {
+            unsigned mm = 0u;
+            for (int q = 0; q < groups; ++q) mm = max(mm, cm[q * b + t]);
+            part[(int64_t)t * nblk + blockIdx.x] = mm == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(mm);
+        }
+    } else {
+        for (int j = t; j < b; j += 256) {
+            unsigned m = 0u;
+            for (int64_t r = r0; r < r1; ++r) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
+            part[(int64_t)j * nblk + blockIdx.x] = m == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(m);
+        }
     }
 }
 
@@ -156,15 +166,17 @@ __global__ void k_colscale(const float *__restrict__ part, int nblk, int b, floa
 template <class T>
 __global__ void k_apply_scale(T *__restrict__ Y, int64_t ldy, int64_t n, int b,
                               const float *__restrict__ scale) {
-    int64_t total = n * b;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < total; i += stride) {
-        const int64_t r = i / b;
-        const int c = (int)(i - r * b);
-        T *p = Y + r * ldy + c;
-        store_as<T>(p, load_as_f64(p) * (double)scale[c]);
-    }
+    // grid.x over row blocks of 256 / min(b, 256) rows, threads over columns
+    const int t = threadIdx.x;
+    const int cols = b < 256 ? b : 256;
+    const int groups = 256 / cols;
+    const int j0 = t % cols, g = t / cols;
+    if (g >= groups) return;
+    for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)gridDim.x * groups)
+        for (int j = j0; j < b; j += cols) {
+            T *p = Y + r * ldy + j;
+            store_as<T>(p, load_as_f64(p) * (double)scale[j]);
+        }
 }
 
 // row-major compaction: d[i, dest[j]] = s[i, j] for kept j
@@ -319,7 +331,8 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
                            (const T *)Y, ldy, n, b, rpb, part, nblk);
     });
     hipLaunchKernelGGL(k_colscale, dim3((b + 63) / 64), dim3(64), 0, ctx->stream, part, nblk, b, scale);
-    int g = grid_for(n * b);
+    const int rows_per_wg = 256 / (b < 256 ? b : 256);
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 4096));
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
         hipLaunchKernelGGL((k_apply_scale<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, n,

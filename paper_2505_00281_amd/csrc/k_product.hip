@@ -18,91 +18,131 @@ namespace {
 // ------------------------------------------------------------------ FP64 --
 // W (m x b) = op(A) (m x kdim) * V (kdim x b) on FP64 MFMA
 // (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16];
-// accumulator register r of lane l is D[4r + l/16][l%16]).  64 x 64
-// output tile per 256-thread workgroup (2 x 2 waves, each 2 x 2 MFMA
-// blocks), 16-deep K slices staged in LDS; the next slice is loaded into
-// registers while the current one is multiplied.
+// accumulator register r of lane l is D[4r + l/16][l%16]).
+// Workgroup tile 64 rows x (64 NCT) columns (the whole basis for b <= 128,
+// so A is streamed once), 2 x 2 waves of 32 x (32 NCT); 32-deep K stages in
+// LDS, the next stage loaded into registers while the MFMAs run; split-K
+// with the XCD-aware workgroup map when the tiles alone cannot fill the chip.
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4_t;
 
-template <class TA>
-__device__ __forceinline__ void f64_tile_load(const TA *__restrict__ A, int64_t lda, int trans,
-                                              int64_t m, int64_t kdim, int b,
-                                              const double *__restrict__ V, int64_t ldv,
-                                              int64_t i0, int j0, int64_t k0, int t, double (&ra)[4],
-                                              double (&rv)[4]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        int ii, kk;
-        if (trans) {  // contiguous in k: 4 consecutive k per thread
-            ii = t >> 2;
-            kk = (t & 3) * 4 + s;
-        } else {  // contiguous in i: 4 consecutive i per thread
-            kk = t >> 4;
-            ii = (t & 15) * 4 + s;
-        }
-        const int64_t gi = i0 + ii, gk = k0 + kk;
-        ra[s] = (gi < m && gk < kdim) ? (double)(trans ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
-        const int vk = t >> 4, vj = (t & 15) * 4 + s;
-        const int64_t gvk = k0 + vk;
-        rv[s] = (gvk < kdim && j0 + vj < b) ? V[gvk * ldv + j0 + vj] : 0.0;
-    }
-}
+constexpr int F64_BM = 64;
+constexpr int F64_BK = 32;
 
-template <class TA>
-__global__ __launch_bounds__(256) void k_gemm_f64(const TA *__restrict__ A, int64_t lda, int trans,
-                                                  int64_t m, int64_t kdim, int b,
-                                                  const double *__restrict__ V, int64_t ldv,
-                                                  double *__restrict__ W, int64_t ldw) {
-    __shared__ double As[16][64 + 2];
-    __shared__ double Vs[16][64 + 2];
+template <class TA, bool ATRANS, int NCT>
+__global__ __launch_bounds__(256) void k_gemm_f64(const TA *__restrict__ A, int64_t lda, int64_t m,
+                                                  int64_t kdim, int b, const double *__restrict__ V,
+                                                  int64_t ldv, double *__restrict__ W, int64_t ldw,
+                                                  int64_t k_per_split, int ntiles, int nsplit,
+                                                  int xcd_map) {
+    constexpr int BN = 64 * NCT;
+    constexpr int VPT = BN / 8;  // V values per thread per stage
+    __shared__ double As[F64_BK][F64_BM + 4];
+    __shared__ double Vs[F64_BK][BN + 4];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int j0 = blockIdx.y * 64;
-    f64x4_t acc[2][2];
+    int tile, z;
+    const int L = blockIdx.x;
+    if (xcd_map) {
+        const int xcd = L & 7, slot = L >> 3, per = 8 / nsplit;
+        z = xcd % nsplit;
+        tile = slot * per + xcd / nsplit;
+    } else {
+        tile = L % ntiles;
+        z = L / ntiles;
+    }
+    if (tile >= ntiles) return;
+    const int gy = (b + BN - 1) / BN;
+    const int64_t i0 = (int64_t)(tile / gy) * F64_BM;
+    const int j0 = (tile % gy) * BN;
+    const int64_t kbeg = (int64_t)z * k_per_split;
+    const int64_t kend = kbeg + k_per_split < kdim ? kbeg + k_per_split : kdim;
+
+    f64x4_t acc[2][2 * NCT];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[p][q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-    double ra[4], rv[4];
-    f64_tile_load(A, lda, trans, m, kdim, b, V, ldv, i0, j0, 0, t, ra, rv);
-    for (int64_t k0 = 0; k0 < kdim; k0 += 16) {
+        for (int q = 0; q < 2 * NCT; ++q) acc[p][q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+
+    double ra[8], rv[VPT];
+    // A: ATRANS -> thread owns row t/4 and 8 consecutive k; else k t/8 and
+    // 8 consecutive rows.  V: k t/8 and VPT consecutive columns.
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (trans)
-                As[(t & 3) * 4 + s][t >> 2] = ra[s];
-            else
-                As[t >> 4][(t & 15) * 4 + s] = ra[s];
-            Vs[t >> 4][(t & 15) * 4 + s] = rv[s];
+        for (int q = 0; q < 8; ++q) {
+            int64_t gi, gk;
+            if (ATRANS) {
+                gi = i0 + (t >> 2);
+                gk = k0 + (t & 3) * 8 + q;
+            } else {
+                gk = k0 + (t >> 3);
+                gi = i0 + (t & 7) * 8 + q;
+            }
+            ra[q] = (gi < m && gk < kend) ? (double)(ATRANS ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
         }
-        __syncthreads();
-        if (k0 + 16 < kdim) f64_tile_load(A, lda, trans, m, kdim, b, V, ldv, i0, j0, k0 + 16, t, ra, rv);
+        const int64_t vk = k0 + (t >> 3);
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
+        for (int q = 0; q < VPT; ++q) {
+            const int jj = j0 + (t & 7) * VPT + q;
+            rv[q] = (vk < kend && jj < b) ? V[vk * ldv + jj] : 0.0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (ATRANS)
+                As[(t & 3) * 8 + q][t >> 2] = ra[q];
+            else
+                As[t >> 3][(t & 7) * 8 + q] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) Vs[t >> 3][(t & 7) * VPT + q] = rv[q];
+    };
+
+    fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += F64_BK) {
+        stash();
+        __syncthreads();
+        if (k0 + F64_BK < kend) fetch(k0 + F64_BK);
+#pragma unroll
+        for (int kk = 0; kk < F64_BK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            double a[2], bb[2];
+            double a[2], bv[2 * NCT];
 #pragma unroll
             for (int p = 0; p < 2; ++p) a[p] = As[kr][32 * wr + 16 * p + (lane & 15)];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) bb[q] = Vs[kr][32 * wc + 16 * q + (lane & 15)];
+            for (int q = 0; q < 2 * NCT; ++q) bv[q] = Vs[kr][32 * NCT * wc + 16 * q + (lane & 15)];
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], bb[q], acc[p][q], 0, 0, 0);
+                for (int q = 0; q < 2 * NCT; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], bv[q], acc[p][q], 0, 0, 0);
         }
         __syncthreads();
     }
+    double *Wz = W + (int64_t)z * m * ldw;
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2 * NCT; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = i0 + 32 * wr + 16 * p + 4 * r + (lane >> 4);
-                const int gj = j0 + 32 * wc + 16 * q + (lane & 15);
-                if (gi < m && gj < b) W[gi * ldw + gj] = acc[p][q][r];
+                const int gj = j0 + 32 * NCT * wc + 16 * q + (lane & 15);
+                if (gi < m && gj < b) Wz[gi * ldw + gj] = acc[p][q][r];
             }
+}
+
+__global__ void k_sum_slabs_d(const double *__restrict__ P, int nsplit, int64_t m, int b, int64_t ld,
+                              double *__restrict__ W) {
+    const int64_t total = m * b;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / b;
+        const int j = (int)(e - i * b);
+        double s = 0.0;
+        for (int zz = 0; zz < nsplit; ++zz) s += P[(int64_t)zz * m * ld + i * ld + j];
+        W[i * ld + j] = s;
+    }
 }
 
 // -------------------------------------------------------------- CSR SpMM --
@@ -152,19 +192,54 @@ __global__ void k_csr_check(const int32_t *__restrict__ rp, const int32_t *__res
 
 void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const double *V,
                  int64_t ldv, double *W, int64_t ldw) {
-    KTimer t(ctx, "product_f64");
+    OFRR_CHECK_ARG(A->dtype == OFRR_F64 || A->dtype == OFRR_F32, "product_f64: A must be F64 or F32");
     const int64_t m = trans ? A->cols : A->rows;
     const int64_t kdim = trans ? A->rows : A->cols;
-    dim3 grid((unsigned)((m + 63) / 64), (unsigned)((b + 63) / 64));
-    if (A->dtype == OFRR_F64)
-        hipLaunchKernelGGL((k_gemm_f64<double>), grid, dim3(256), 0, ctx->stream,
-                           (const double *)A->values, A->ld, trans, m, kdim, b, V, ldv, W, ldw);
-    else if (A->dtype == OFRR_F32)
-        hipLaunchKernelGGL((k_gemm_f64<float>), grid, dim3(256), 0, ctx->stream,
-                           (const float *)A->values, A->ld, trans, m, kdim, b, V, ldv, W, ldw);
-    else
-        fail(OFRR_ERR_UNSUPPORTED, "product_f64: A must be F64 or F32");
-    OFRR_HIP(hipGetLastError());
+    const int NCT = b > 64 ? 2 : 1;
+    const int BN = 64 * NCT;
+    const int gx = (int)((m + F64_BM - 1) / F64_BM), gy = (b + BN - 1) / BN;
+    const int ntiles = gx * gy;
+    int nsplit = 1;
+    const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
+    while ((int64_t)ntiles * nsplit < want && kdim / (nsplit * 2) >= 1024 && nsplit < 8) nsplit *= 2;
+    int64_t kps = (kdim + nsplit - 1) / nsplit;
+    kps = (kps + F64_BK - 1) / F64_BK * F64_BK;
+    nsplit = (int)((kdim + kps - 1) / kps);
+    const int xcd_map = (nsplit >= 2 && 8 % nsplit == 0) ? 1 : 0;
+    int64_t nwg = (int64_t)ntiles * nsplit;
+    if (xcd_map) nwg = (int64_t)((ntiles + 8 / nsplit - 1) / (8 / nsplit)) * 8;
+    double *dst = W;
+    if (nsplit > 1) dst = ctx->buf<double>("f64_slabs", (size_t)nsplit * m * ldw);
+    {
+        KTimer t(ctx, "product_f64");
+        auto go = [&](auto kern, auto ap) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, ap, A->ld, m, kdim, b, V,
+                               ldv, dst, ldw, kps, ntiles, nsplit, xcd_map);
+        };
+        const float *af = (const float *)A->values;
+        const double *ad = (const double *)A->values;
+        if (A->dtype == OFRR_F32) {
+            if (trans) {
+                if (NCT == 2) go(k_gemm_f64<float, true, 2>, af); else go(k_gemm_f64<float, true, 1>, af);
+            } else {
+                if (NCT == 2) go(k_gemm_f64<float, false, 2>, af); else go(k_gemm_f64<float, false, 1>, af);
+            }
+        } else {
+            if (trans) {
+                if (NCT == 2) go(k_gemm_f64<double, true, 2>, ad); else go(k_gemm_f64<double, true, 1>, ad);
+            } else {
+                if (NCT == 2) go(k_gemm_f64<double, false, 2>, ad); else go(k_gemm_f64<double, false, 1>, ad);
+            }
+        }
+        OFRR_HIP(hipGetLastError());
+    }
+    if (nsplit > 1) {
+        KTimer t(ctx, "product_reduce");
+        const int64_t total = m * b;
+        const int g = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+        hipLaunchKernelGGL(k_sum_slabs_d, dim3(g), dim3(256), 0, ctx->stream, dst, nsplit, m, b, ldw, W);
+        OFRR_HIP(hipGetLastError());
+    }
 }
 
 void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,

@@ -14,56 +14,65 @@ namespace ofrr {
 namespace {
 
 constexpr int PJ_T = 64;      // output tile (PJ_T x PJ_T) per workgroup
-constexpr int PJ_R = 16;      // rows staged per step
 
-// grid (nchunks, ntiles_i, ntiles_j).  Computes the partial sums over rows
-// [c*rows_per, (c+1)*rows_per) of X^T Y for one tile, written to
-// part[c][tile] (PJ_T x PJ_T, row-major within the tile).
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double pj_f64x4_t;
+
+// grid (nchunks, ntiles_i, ntiles_j).  Partial sums over rows
+// [c*rows_per, (c+1)*rows_per) of X^T Y for one 64 x 64 tile, written to
+// part[c][tile] (row-major within the tile).  FP64 MFMA 16x16x4 with both
+// operands read straight from the row-major blocks: for a 4-row step, lane
+// l needs X[r + l/16][i + l%16] and Y[r + l/16][j + l%16], 16 consecutive
+// values of a row per lane group, so no LDS staging is needed; the next
+// step's operands are loaded while the current MFMAs run.  Each wave owns a
+// 32 x 32 quarter of the tile (2 x 2 MFMA blocks).
 template <class TX, class TY>
 __global__ __launch_bounds__(256) void k_gram_partial(const TX *__restrict__ X, int64_t ldx,
                                                       const TY *__restrict__ Yb, int64_t ldy,
                                                       int64_t n, int b1, int b2, int64_t rows_per,
                                                       double *__restrict__ part) {
-    __shared__ double Xs[PJ_R][PJ_T + 1];
-    __shared__ double Ys[PJ_R][PJ_T + 1];
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    const int i0 = blockIdx.y * PJ_T, j0 = blockIdx.z * PJ_T;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int i0 = blockIdx.y * PJ_T + 32 * (wave >> 1), j0 = blockIdx.z * PJ_T + 32 * (wave & 1);
     const int64_t rbeg = (int64_t)blockIdx.x * rows_per;
     int64_t rend = rbeg + rows_per;
     if (rend > n) rend = n;
-    double acc[4][4] = {};
-    for (int64_t r0 = rbeg; r0 < rend; r0 += PJ_R) {
+    const int kr = lane >> 4, cc = lane & 15;
+    pj_f64x4_t acc[2][2];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int e = t + 256 * s;
-            const int rr = e >> 6, cc = e & 63;
-            const int64_t gr = r0 + rr;
-            const bool okr = gr < rend;
-            Xs[rr][cc] = (okr && i0 + cc < b1) ? load_as_f64(X + gr * ldx + i0 + cc) : 0.0;
-            Ys[rr][cc] = (okr && j0 + cc < b2) ? load_as_f64(Yb + gr * ldy + j0 + cc) : 0.0;
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = pj_f64x4_t{0.0, 0.0, 0.0, 0.0};
+    double xa[2], yb[2];
+    auto fetch = [&](int64_t r0) {
+        const int64_t r = r0 + kr;
+        const bool okr = r < rend;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int ci = i0 + 16 * p + cc, cj = j0 + 16 * p + cc;
+            xa[p] = (okr && ci < b1) ? load_as_f64(X + r * ldx + ci) : 0.0;
+            yb[p] = (okr && cj < b2) ? load_as_f64(Yb + r * ldy + cj) : 0.0;
         }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < PJ_R; ++rr) {
-            double a[4], v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = Xs[rr][ty + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = Ys[rr][tx + 16 * q];
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], v[q], acc[p][q]);
-        }
-        __syncthreads();
+    };
+    fetch(rbeg);
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 4) {
+        const double a0 = xa[0], a1 = xa[1], b0 = yb[0], b1v = yb[1];
+        if (r0 + 4 < rend) fetch(r0 + 4);
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[1][1], 0, 0, 0);
     }
+    // accumulator register r of lane l is D[4r + l/16][l%16]
     const int ntile = gridDim.y * gridDim.z;
     const int tile = blockIdx.y * gridDim.z + blockIdx.z;
     double *dst = part + ((int64_t)blockIdx.x * ntile + tile) * PJ_T * PJ_T;
+    const int ti = 32 * (wave >> 1), tj = 32 * (wave & 1);
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[(ty + 16 * p) * PJ_T + tx + 16 * q] = acc[p][q];
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                dst[(ti + 16 * p + 4 * r + kr) * PJ_T + tj + 16 * q + cc] = acc[p][q][r];
 }
 
 // Sum the chunk partials in chunk order and write C (b1 x b2, column-major,
@@ -104,7 +113,7 @@ void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, c
     // enough chunks to fill the chip, each at least 256 rows
     int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (2 * cus + nti * ntj - 1) / (nti * ntj)));
     int64_t rows_per = (n + nchunks - 1) / nchunks;
-    rows_per = (rows_per + PJ_R - 1) / PJ_R * PJ_R;
+    rows_per = (rows_per + 3) / 4 * 4;
     nchunks = (n + rows_per - 1) / rows_per;
     double *part = ctx->buf<double>("gram_part", (size_t)nchunks * nti * ntj * PJ_T * PJ_T);
     dim3 grid((unsigned)nchunks, nti, ntj);

@@ -52,6 +52,7 @@ double unit_roundoff(ofrr_dtype t) {
 struct Phase {
     ofrr_dtype basis;    // F64: everything FP64; BF16/F16: reduced products, FP32 master blocks
     bool split = false;  // BF16 with A and the basis as two-term (hi + lo) splits
+    bool sliced = false; // FP64 phase with products from exact INT8 digit planes
     bool f64() const { return basis == OFRR_F64; }
     ofrr_dtype master() const { return f64() ? OFRR_F64 : OFRR_F32; }
 };
@@ -69,6 +70,7 @@ struct EigRun {
     uint16_t *A_lo = nullptr;
     uint16_t *A_lo2 = nullptr;
     ofrr_dtype A_lo_t = OFRR_F64;
+    SlicedA A_sl;  // digit planes of A for a sliced FP64 phase
 
     // product of the current phase: W (master type) = A * Vblk (master type)
     void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc) {
@@ -89,7 +91,10 @@ struct EigRun {
             return;
         }
         if (ph.f64()) {
-            product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
+            if (ph.sliced)
+                product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld);
+            else
+                product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
             return;
         }
         // dense reduced precision: split the FP32 block into hi (+ lo), written
@@ -136,9 +141,18 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         mid.split = true;
         phases.push_back(mid);
     }
-    if (plan->refine && plan->basis_dtype != OFRR_F64) phases.push_back(Phase{OFRR_F64});
-    bool any_split = false;
-    for (auto &p : phases) any_split = any_split || p.split;
+    if (plan->refine && plan->basis_dtype != OFRR_F64) {
+        Phase tail{OFRR_F64};
+        tail.sliced = dense && plan->tail_product == OFRR_TAIL_I8_SLICED;
+        phases.push_back(tail);
+    }
+    bool any_split = false, any_sliced = false;
+    for (auto &p : phases) {
+        any_split = any_split || p.split;
+        any_sliced = any_sliced || p.sliced;
+    }
+    // digit planes of A (rows of A^T, K-contiguous) for a sliced FP64 phase
+    if (any_sliced) run.A_sl = slice_matrix_i8(ctx, A, 1);
 
     // quantise dense A once for the reduced-precision phases (Sec. 4: A
     // stored in reduced precision; a split phase also keeps A - bf16(A))

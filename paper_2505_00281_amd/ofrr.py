@@ -32,12 +32,13 @@ _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16, "f8e4m3": F8E4M3}
 _ACCUM = {"f32": ACC_F32, "f32c": ACC_F32_COMPENSATED, "f64": ACC_F64}
 _WHICH = {"largest": LARGEST, "smallest": SMALLEST}
 _FILTER = {"power": POWER, "chebyshev": CHEBYSHEV}
+_TAIL = {"f64": 0, "i8": 1}
 
 EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error",
             "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_eig_partial",
             "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_quantize",
-            "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_fp8",
-            "ofrr_hessenberg",
+            "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_sliced",
+            "ofrr_block_product_fp8", "ofrr_hessenberg",
             "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
 
 
@@ -61,7 +62,7 @@ class Plan(ctypes.Structure):
                 ("tol", ctypes.c_double), ("anorm", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("stall_iters", ctypes.c_int32),
                 ("switch_resid", ctypes.c_double), ("b_split", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("tail_product", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -104,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_quantize.argtypes = [vp, ctypes.c_int, i64, vp, vp]
     lib.ofrr_quantize_fp8_blocks.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     lib.ofrr_block_product.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, vp, vp]
+    lib.ofrr_block_product_sliced.argtypes = [vp, P(Matrix), i32, i32, vp, vp]
     lib.ofrr_block_product_fp8.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, vp]
     lib.ofrr_hessenberg.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
     lib.ofrr_project.argtypes = [vp, i64, i32, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
@@ -119,7 +121,7 @@ def load_library(path: str = LIB_PATH):
 
 def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power", degree=1,
               lo=0.0, hi=0.0, drop_tol=0.0, tol=0.0, anorm=0.0, max_iters=20, stall_iters=3,
-              switch_resid=0.0, b_split=1, profile=False) -> Plan:
+              switch_resid=0.0, b_split=1, profile=False, tail="f64") -> Plan:
     p = Plan()
     load_library().ofrr_plan_default(ctypes.byref(p))
     p.basis_dtype = _DTYPES[basis_dtype] if isinstance(basis_dtype, str) else basis_dtype
@@ -133,6 +135,7 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
     p.switch_resid = float(switch_resid)
     p.b_split = b_split
     p.profile = int(bool(profile))
+    p.tail_product = _TAIL[tail] if isinstance(tail, str) else int(tail)
     return p
 
 
@@ -339,6 +342,18 @@ class Context:
         W = torch.empty((rows, b), dtype=wdt, device=self.device)
         self._check(self.lib.ofrr_block_product(self.h, ctypes.byref(mat), int(trans), b,
                                                 _DTYPES[v_dtype], _ptr(V), _ptr(W)))
+        return W
+
+    def block_product_sliced(self, A, V: torch.Tensor, trans: bool = False):
+        """W = op(A) V (FP64, row-major) from exact INT8 digit-plane products;
+        A dense F32/F64."""
+        mat = A if isinstance(A, Matrix) else dense_matrix(A)
+        V = V.to(torch.float64).contiguous()
+        b = V.shape[1]
+        rows = mat.cols if trans else mat.rows
+        W = torch.empty((rows, b), dtype=torch.float64, device=self.device)
+        self._check(self.lib.ofrr_block_product_sliced(self.h, ctypes.byref(mat), int(trans), b,
+                                                       _ptr(V), _ptr(W)))
         return W
 
     def block_product_fp8(self, codes: torch.Tensor, scales: torch.Tensor, V: torch.Tensor,

@@ -40,8 +40,8 @@ def test_struct_layout_matches_header(tmp_path):
 #include "ofrr.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(ofrr_matrix), sizeof(ofrr_plan), sizeof(ofrr_info));
-  printf("%zu %zu %zu %zu\\n", offsetof(ofrr_plan, lo), offsetof(ofrr_plan, max_iters),
-         offsetof(ofrr_plan, b_split), offsetof(ofrr_plan, profile));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(ofrr_plan, lo), offsetof(ofrr_plan, max_iters),
+         offsetof(ofrr_plan, b_split), offsetof(ofrr_plan, profile), offsetof(ofrr_plan, tail_product));
   printf("%zu %zu\\n", offsetof(ofrr_matrix, values), offsetof(ofrr_matrix, nnz));
   printf("%zu\\n", offsetof(ofrr_info, max_resid));
   return 0;
@@ -53,10 +53,10 @@ int main(void) {
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     assert vals[0:3] == [ctypes.sizeof(ofrr.Matrix), ctypes.sizeof(ofrr.Plan), ctypes.sizeof(ofrr.Info)]
-    assert vals[3:7] == [ofrr.Plan.lo.offset, ofrr.Plan.max_iters.offset, ofrr.Plan.b_split.offset,
-                         ofrr.Plan.profile.offset]
-    assert vals[7:9] == [ofrr.Matrix.values.offset, ofrr.Matrix.nnz.offset]
-    assert vals[9] == ofrr.Info.max_resid.offset
+    assert vals[3:8] == [ofrr.Plan.lo.offset, ofrr.Plan.max_iters.offset, ofrr.Plan.b_split.offset,
+                         ofrr.Plan.profile.offset, ofrr.Plan.tail_product.offset]
+    assert vals[8:10] == [ofrr.Matrix.values.offset, ofrr.Matrix.nnz.offset]
+    assert vals[10] == ofrr.Info.max_resid.offset
 
 
 def test_plan_defaults():
@@ -64,7 +64,7 @@ def test_plan_defaults():
     ofrr.load_library().ofrr_plan_default(ctypes.byref(p))
     assert (p.basis_dtype, p.gram_accum, p.refine, p.filter, p.degree) == (ofrr.F64, ofrr.ACC_F64, 0,
                                                                           ofrr.POWER, 1)
-    assert (p.max_iters, p.stall_iters, p.b_split, p.profile) == (20, 3, 1, 0)
+    assert (p.max_iters, p.stall_iters, p.b_split, p.profile, p.tail_product) == (20, 3, 1, 0, 0)
 
 
 def test_descriptors_keep_their_tensors_alive():

@@ -126,11 +126,13 @@ def test_eig_converged_to_tolerance_fp64(ctx):
     assert r.resid.cpu().numpy().max() <= 1e-12
 
 
-@pytest.mark.parametrize("lowp,refine", [("bf16", 1), ("f16", 1), ("bf16", 2)])
-def test_eig_mixed_refined_converged(ctx, lowp, refine):
+@pytest.mark.parametrize("lowp,refine,tail", [("bf16", 1, "f64"), ("f16", 1, "f64"), ("bf16", 2, "f64"),
+                                               ("bf16", 2, "i8")])
+def test_eig_mixed_refined_converged(ctx, lowp, refine, tail):
     """Mixed form with the FP64 tail (refine=2: with the split-BF16 middle
-    phase) reaches residual <= 1e-8 and relative eigenvalue error <= 1e-10
-    against the oracle's converged pairs."""
+    phase; tail i8: FP64-phase products from exact INT8 digit planes)
+    reaches residual <= 1e-8 and relative eigenvalue error <= 1e-10 against
+    the oracle's converged pairs."""
     n, b, k = 2048, 32, 12
     lam = np.arange(1, n + 1) ** -1.5
     A = W.dense_symmetric_prescribed(lam, 1002, noise_scale=1e-4, noise_seed=2002, dtype=torch.float32)
@@ -141,7 +143,7 @@ def test_eig_mixed_refined_converged(ctx, lowp, refine):
     lo, hi = float(w[-1]), float(w[b])
     print("eig mixed refined", lowp, flush=True)
     plan = _plan(basis_dtype=lowp, refine=refine, filter="chebyshev", degree=4, lo=lo, hi=hi,
-                 tol=1e-9, anorm=float(w[0]), max_iters=400)
+                 tol=1e-9, anorm=float(w[0]), max_iters=400, tail=tail)
     r = ctx.eig_partial(A.cuda(), k, b, plan=plan, X0=torch.from_numpy(X0))
     print("info", r.info, flush=True)
     ref = O.subspace_eig(Ad, X0, k, filt="chebyshev", degree=4, lo=lo, hi=hi, tol=1e-12,

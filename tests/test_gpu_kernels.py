@@ -73,6 +73,43 @@ def test_product_f64(ctx, dtype, trans):
     assert np.all(np.abs(Wg - ref) <= bound + 1e-300)
 
 
+def _pow2_above(x):
+    """Smallest power of two strictly above each |x| (1 for zeros)."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    _, e = np.frexp(x)
+    return np.where(x > 0, np.ldexp(1.0, e), 1.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("trans", [0, 1])
+@pytest.mark.parametrize("shape", [(300, 257, 13), (130, 20000, 70), (1000, 1000, 128)])
+def test_product_sliced(ctx, dtype, trans, shape):
+    """INT8 digit-plane product against the FP64 product: within the
+    truncation bound 2^-35 (2^e_i sum|V_:j| + 2^f_j sum|A_i:| + 4.2 K 2^(e_i+f_j))
+    of the five-digit planes and the dropped digit pairs, plus FP64 rounding
+    of both sides.  The (130, 20000) case needs two K ranges (int32 cap)."""
+    rng = np.random.default_rng(21)
+    m, kd, b = shape
+    A = rng.standard_normal((m, kd) if not trans else (kd, m)) * np.exp(rng.uniform(-3, 0, (1, 1)))
+    A = A.astype(np.float32).astype(np.float64) if dtype == torch.float32 else A
+    V = rng.standard_normal((kd, b)) * np.exp(rng.uniform(-4, 1, (1, b)))
+    print("product_sliced", dtype, trans, shape, flush=True)
+    At = torch.from_numpy(np.asfortranarray(A)).to(dtype)
+    At = At.t().contiguous().t().cuda()
+    Wg = ctx.block_product_sliced(At, _cuda(V), trans=bool(trans)).cpu().numpy()
+    opA = A.T if trans else A
+    ref = opA @ V
+    ea = _pow2_above(np.max(np.abs(opA), axis=1))[:, None]
+    fv = _pow2_above(np.max(np.abs(V), axis=0))[None, :]
+    bound = 2.0 ** -35 * (ea * np.sum(np.abs(V), axis=0)[None, :] +
+                          fv * np.sum(np.abs(opA), axis=1)[:, None] + 4.2 * kd * ea * fv)
+    bound += 4 * kd * 2.0 ** -53 * (np.abs(opA) @ np.abs(V))
+    err = np.abs(Wg - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+    # and far tighter than an FP32 product could be
+    assert np.max(err / (np.abs(opA) @ np.abs(V))) < 1e-8
+
+
 @pytest.mark.parametrize("lowp", ["bf16", "f16"])
 @pytest.mark.parametrize("trans", [0, 1])
 @pytest.mark.parametrize("shape", [(300, 1000, 70), (128, 64, 64), (4100, 4096, 128)])
