@@ -121,6 +121,10 @@ def main():
     ap.add_argument("--stall-iters", type=int, default=3)
     ap.add_argument("--tail", choices=["f64", "i8"], default="i8",
                     help="products of the final FP64 phase: FP64 arithmetic or exact INT8 digit planes")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the three product kernels of the path (BF16 MFMA, INT8 digit planes, "
+                         "FP64 MFMA) three times each on a random n=16384 FP32 matrix and a 128-column "
+                         "block, for hardware-counter passes (no solver library calls)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times; "
                          "used to scale rocprofv3 FETCH_SIZE/WRITE_SIZE readings")
@@ -143,6 +147,21 @@ def main():
         return
     from paper_2505_00281_amd import ofrr
     device = torch.device("cuda", 0)
+    if args.traffic_probe:
+        ctx = ofrr.Context(0)
+        g = torch.Generator(device=device).manual_seed(7)
+        A = torch.randn((N, N), generator=g, device=device, dtype=torch.float32)
+        V = torch.randn((N, BASIS), generator=g, device=device, dtype=torch.float64)
+        Ab = A.to(torch.bfloat16)
+        Vb = V.to(torch.bfloat16)
+        for _ in range(3):
+            # column-major views (the values are random; only the traffic counts)
+            ctx.block_product(Ab.t(), Vb, trans=True)
+            ctx.block_product_sliced(A.t(), V, trans=True)
+            ctx.block_product(A.t(), V, trans=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe": {"n": N, "b": BASIS, "launches_per_kernel": 3}}))
+        return
     A, X0, lo, hi, anorm = make_problem(device)
     ctx = ofrr.Context(0)
 
@@ -181,7 +200,7 @@ def main():
     # dominant kernel: the block-product family with the largest total time
     # in one call.  Per launch: algorithmic bytes = A read once in its stored
     # format + the basis block read once + the product written once;
-    # algorithmic operations = 2 n^2 b per MFMA product (15 digit-pair
+    # algorithmic operations = 2 n^2 b per MFMA product (21 digit-pair
     # products for the INT8 planes).  The bound is whichever of bytes / HBM
     # peak and operations / MFMA peak of the kernel's type takes longer.
     vb = 2 if args.b_split >= 2 else 1
@@ -193,8 +212,8 @@ def main():
                            "k_gemm_lp<bf16, split A and V> (3 BF16 MFMAs per tile step)"),
         "product_f64": (N * N * 4 + N * BASIS * 8 + N * BASIS * 8, gemm, 78.6,
                         "k_gemm_f64 (A FP32 promoted, FP64 MFMA 16x16x4)"),
-        "product_i8x": (5 * N * N + 5 * N * BASIS + 8 * N * BASIS, 15 * gemm, 5000.0,
-                        "k_gemm_i8s (5 x 5 INT8 digit planes, 15 MFMA 32x32x32 pairs, exact int32)"),
+        "product_i8x": (6 * N * N + 6 * N * BASIS + 8 * N * BASIS, 21 * gemm, 5000.0,
+                        "k_gemm_i8s (6 x 6 INT8 digit planes, 21 MFMA 32x32x32 pairs, exact int32)"),
     }
 
     def roof(f):

@@ -63,10 +63,10 @@ typedef enum { OFRR_POWER = 0, OFRR_CHEBYSHEV = 1 } ofrr_filter;
 /* Products of the FP64 phase that ends a refined plan (dense A). */
 typedef enum {
     OFRR_TAIL_F64 = 0,       /* FP64 arithmetic */
-    OFRR_TAIL_I8_SLICED = 1  /* exact INT8 products of 7-bit digit planes: 5 of each row of
-                                A (FP32 or FP64 stored) and 5 of each basis column, the 15
-                                digit pairs of weight >= 2^-42 summed in int32; the result is
-                                within about 2^-33 of |A||V| per entry (FP64 gives 2^-53 K) */
+    OFRR_TAIL_I8_SLICED = 1  /* exact INT8 products of 7-bit digit planes: 6 of each row of
+                                A (FP32 or FP64 stored) and 6 of each basis column, the 21
+                                digit pairs with s + t <= 7 summed in int32; the result is
+                                within about 2^-40 of |A||V| per entry (FP64 gives 2^-53 K) */
 } ofrr_tail;
 
 /* Accumulation of the projections G = V^T V, H = V^T W (Sec. 4, mixed-
@@ -254,7 +254,7 @@ ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans
  * (the OFRR_TAIL_I8_SLICED products of the final phase; Sec. 2 products).
  * A: dense F32/F64 descriptor; V: FP64 row-major (op(A) cols) x b (ld b);
  * W: FP64 row-major (op(A) rows) x b (ld b).  Per entry the error is below
- * 2^-35 (2^e_i sum_k |V_kj| + 2^f_j sum_k |op(A)_ik| + 4.2 K 2^(e_i+f_j))
+ * 2^-42 (2^e_i sum_k |V_kj| + 2^f_j sum_k |op(A)_ik| + 5.1 K 2^(e_i+f_j))
  * plus FP64 rounding of the final sums, with 2^e_i the smallest power of two
  * above max_k |op(A)_ik| and 2^f_j that above max_k |V_kj|. */
 ofrr_status ofrr_block_product_sliced(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,

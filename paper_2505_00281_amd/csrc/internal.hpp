@@ -13,7 +13,7 @@
 #include <cmath>
 #include <vector>
 
-#include "../../include/ofrr.h"
+#include "ofrr.h"
 
 namespace ofrr {
 

@@ -5,18 +5,21 @@
 // target, which FP32 accumulation cannot give (its rounding is about
 // 2^-24 |A||V|).  MI355X runs FP64 at 78.6 TFLOP/s but INT8 MFMA at
 // 5 POP/s, so the product is rebuilt from exact integer pieces:
-//   op(A)[i][k] = 2^{e_i} sum_{s=1..5} a_s[i][k] 2^{-7s}   (+ |rest| < 2^{e_i-35})
-//   V[k][j]     = 2^{f_j} sum_{t=1..5} v_t[k][j] 2^{-7t}   (+ |rest| < 2^{f_j-35})
+//   op(A)[i][k] = 2^{e_i} sum_{s=1..6} a_s[i][k] 2^{-7s}   (+ |rest| < 2^{e_i-42})
+//   V[k][j]     = 2^{f_j} sum_{t=1..6} v_t[k][j] 2^{-7t}   (+ |rest| < 2^{f_j-42})
 // with signed 7-bit digits |a_s|, |v_t| <= 127 (truncation of the scaled
 // value, exact in floating point), e_i the exponent bound of row i of
 // op(A) and f_j that of column j of V.  Then
-//   W[i][j] = 2^{e_i + f_j} sum_{p=2..6} 2^{-7p} sum_{s+t=p} (a_s v_t)[i][j]
-// keeping the 15 digit pairs with s + t <= 6.  Every (a_s v_t) is an exact
+//   W[i][j] = 2^{e_i + f_j} sum_{p=2..7} 2^{-7p} sum_{s+t=p} (a_s v_t)[i][j]
+// keeping the 21 digit pairs with s + t <= 7.  Every (a_s v_t) is an exact
 // int8 x int8 -> int32 dot product; pairs with equal s + t share one int32
-// accumulator (at most 5 pairs x 127^2 x 16384 < 2^31 per K range, so the
+// accumulator (at most 6 pairs x 127^2 x 16384 < 2^31 per K range, so the
 // K range of one accumulation is capped at 16384).  The dropped pairs and
-// the digit remainders are below 2^-35 of the row/column scales, i.e.
-// about 1e-10 of |A||V| where FP32 accumulation gives 6e-8.
+// the digit remainders are below 2^-42 of the row/column scales, about
+// 2e-13 of |A||V| where FP32 accumulation gives 6e-8.  That margin matters:
+// the basis of a converging subspace is ill-conditioned, and the Ritz
+// values amplify per-column product errors by the cancellation in V z;
+// five digits per side (2^-35) left Ritz values 1e-9 off.
 //
 // MFMA v_mfma_i32_32x32x32_i8: lane l holds A[l%32][16(l/32)..+16] and
 // B[16(l/32)..+16][l%32] (any consistent K order is exact for integers);
@@ -31,7 +34,8 @@ namespace {
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef int v16i_t __attribute__((ext_vector_type(16)));
 
-constexpr int I8_S = 5;     // digit planes of A and of V
+constexpr int I8_S = 6;     // digit planes of A and of V
+constexpr int I8_NG = 6;    // digit-pair groups p = s + t (0-based 0..5)
 constexpr int I8_BM = 64;   // rows per workgroup tile
 constexpr int I8_BK = 64;   // K bytes per LDS stage
 constexpr int I8_LD = 80;   // LDS row stride in bytes (64 + 16: conflict-free 16-byte reads)
@@ -45,8 +49,8 @@ __device__ __forceinline__ int exp_bound(double amax) {
     return e;
 }
 
-// five signed 7-bit digits of x 2^-e, |x 2^-e| < 1, by truncation (exact)
-__device__ __forceinline__ void digits5(double x, int e, int8_t (&d)[I8_S]) {
+// I8_S signed 7-bit digits of x 2^-e, |x 2^-e| < 1, by truncation (exact)
+__device__ __forceinline__ void digits_of(double x, int e, int8_t (&d)[I8_S]) {
     double r = ldexp(x, -e);
 #pragma unroll
     for (int s = 0; s < I8_S; ++s) {
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
         for (int q = 0; q < 16; ++q) {
             int8_t dq[I8_S];
             const int64_t k = k0 + q;
-            digits5((i < m && k < kdim) ? at(k) : 0.0, e, dq);
+            digits_of((i < m && k < kdim) ? at(k) : 0.0, e, dq);
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
         }
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
         for (int q = 0; q < 16; ++q) {
             const int64_t k = k0 + q;
             int8_t dq[I8_S];
-            digits5((j < b && k < rows) ? V[k * ld + j] : 0.0, f, dq);
+            digits_of((j < b && k < rows) ? V[k * ld + j] : 0.0, f, dq);
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
         }
@@ -177,13 +181,13 @@ __global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap,
     const int64_t kbeg = (int64_t)z * k_per_split;
     const int64_t kend = kbeg + k_per_split < kpad ? kbeg + k_per_split : kpad;
 
-    v16i_t acc[NCT][5];
+    v16i_t acc[NCT][I8_NG];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int p = 0; p < 5; ++p) acc[ct][p] = v16i_t{};
+        for (int p = 0; p < I8_NG; ++p) acc[ct][p] = v16i_t{};
 
-    // register staging: A 5 chunks (one per plane), V 5 x NCT chunks
+    // register staging: A I8_S chunks (one per plane), V I8_S x NCT chunks
     v4i_t ra[I8_S], rv[I8_S][NCT];
     const int arow = t >> 2, achk = (t & 3) * 16;
     auto fetch = [&](int64_t k0) {
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap,
                 for (int s = 0; s < I8_S; ++s)
 #pragma unroll
                     for (int u = 0; u < I8_S; ++u)
-                        if (s + u <= 4)
+                        if (s + u < I8_NG)
                             acc[ct][s + u] =
                                 __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[ct][s + u], 0, 0, 0);
             }
@@ -242,11 +246,9 @@ __global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap,
         for (int r = 0; r < 16; ++r) {
             const int64_t gi = i0 + 32 * wr + (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
             if (gi >= m || gj >= b) continue;
-            double v = (double)acc[ct][4][r];
-            v = (double)acc[ct][3][r] + v * 0.0078125;
-            v = (double)acc[ct][2][r] + v * 0.0078125;
-            v = (double)acc[ct][1][r] + v * 0.0078125;
-            v = (double)acc[ct][0][r] + v * 0.0078125;
+            double v = (double)acc[ct][I8_NG - 1][r];
+#pragma unroll
+            for (int p = I8_NG - 2; p >= 0; --p) v = (double)acc[ct][p][r] + v * 0.0078125;
             Wz[gi * ldw + gj] = ldexp(v, ex[gi] + fj - 14);
         }
     }

@@ -82,14 +82,22 @@ __device__ __forceinline__ void wave_argmax(M &m, int &i) {
 __device__ __forceinline__ void put_word(uint64_t *dst, uint32_t w, uint32_t tag) {
     __hip_atomic_store(dst, ((uint64_t)w << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Polls *src until its tag is `tag`; false after the spin budget or once
-// another workgroup has raised the error flag.
-__device__ __forceinline__ bool get_word(const uint64_t *src, uint32_t tag, uint32_t &w, int *err) {
+// Loads N consecutive tagged words, all in flight at once, until every tag
+// is `tag`; false after the spin budget or once another workgroup has
+// raised the error flag.
+template <int N>
+__device__ __forceinline__ bool get_words(const uint64_t *src, uint32_t tag, uint32_t (&w)[N], int *err) {
     unsigned long long spins = 0;
     for (;;) {
-        const uint64_t v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)v == tag) {
-            w = (uint32_t)(v >> 32);
+        uint64_t v[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < N; ++q) ok = ok && ((uint32_t)v[q] == tag);
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) w[q] = (uint32_t)(v[q] >> 32);
             return true;
         }
         if (++spins > (1ull << 22) ||
@@ -116,9 +124,7 @@ __device__ __forceinline__ void put_value(uint64_t *dst, V v, uint32_t tag) {
 template <class V>
 __device__ __forceinline__ bool get_value(const uint64_t *src, uint32_t tag, V &v, int *err) {
     uint32_t w[NWords<V>::value];
-    bool ok = true;
-#pragma unroll
-    for (int q = 0; q < NWords<V>::value; ++q) ok = ok && get_word(src + q, tag, w[q], err);
+    const bool ok = get_words<NWords<V>::value>(src, tag, w, err);
     __builtin_memcpy(&v, w, sizeof(V));
     return ok;
 }
@@ -146,23 +152,33 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     const int64_t r0 = (int64_t)g * rows_per;
     const int64_t r1 = (r0 + rows_per < n) ? r0 + rows_per : n;
     const int64_t nrows = r1 > r0 ? r1 - r0 : 0;
-    const int ldl = b;  // leading dimension of the LDS copy
+    // element (rr, c) of the slice: column-major in LDS (consecutive rows
+    // of one column are consecutive words, so a thread-per-row pass is free
+    // of bank conflicts), row-major in place otherwise
     T *rows = RESIDENT ? reinterpret_cast<T *>(smem_raw) : Y + r0 * ldy;
-    const int64_t ldr = RESIDENT ? ldl : ldy;
+    auto at = [&](int64_t rr, int c) -> T & {
+        return RESIDENT ? rows[(int64_t)c * rows_per + rr] : rows[rr * ldy + c];
+    };
 
     if (RESIDENT) {
         for (int64_t e = t; e < nrows * b; e += 256) {
             const int64_t rr = e / b, c = e - rr * b;
-            rows[rr * ldl + c] = Y[(r0 + rr) * ldy + c];
+            rows[(int64_t)c * rows_per + rr] = Y[(r0 + rr) * ldy + c];
         }
         __syncthreads();
     }
+    // elimination mapping: tpr threads per row (so that all 256 threads work
+    // when the slice has fewer than 256 rows), each taking every tpr-th
+    // trailing column
+    int tpr = 1;
+    while (tpr < 16 && nrows * tpr * 2 <= 256) tpr *= 2;
+    const int sub = t % tpr, rstep = 256 / tpr;
 
     auto local_argmax = [&](int col, M &bm, int &bi) {
         bm = (M)-1;
         bi = 0x7fffffff;
         for (int64_t rr = t; rr < nrows; rr += 256) {
-            const M v = (M)fabs((double)rows[rr * ldr + col]);
+            const M v = (M)fabs((double)at(rr, col));
             if (v > bm) {  // rows visited in increasing order per thread
                 bm = v;
                 bi = (int)(r0 + rr);
@@ -199,7 +215,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         uint64_t *my_row = slot_rows + ((int64_t)buf * G + g) * b * TW;
         if (ci != 0x7fffffff) {
             const int64_t rr = ci - r0;
-            for (int c = j + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, rows[rr * ldr + c], tag);
+            for (int c = j + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, at(rr, c), tag);
         }
         if (t == 0) {
             uint64_t *my_cand = slot_cand + ((int64_t)buf * G + g) * CW;
@@ -213,13 +229,14 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             int ok = 1;
             for (int h = t; h < G; h += 256) {
                 const uint64_t *cand = slot_cand + ((int64_t)buf * G + h) * CW;
-                M m2;
-                uint32_t i2u = 0;
-                if (!get_value<M>(cand, tag, m2, err) || !get_word(cand + CW - 1, tag, i2u, err)) {
+                uint32_t cw[CW];
+                if (!get_words<CW>(cand, tag, cw, err)) {
                     ok = 0;
                     break;
                 }
-                const int i2 = (int)i2u;
+                M m2;
+                __builtin_memcpy(&m2, cw, sizeof(M));
+                const int i2 = (int)cw[CW - 1];
                 if (m2 > bm || (m2 == bm && i2 < bi)) {
                     bm = m2;
                     bi = i2;
@@ -289,33 +306,29 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             if (!__syncthreads_and(ok)) break;
         }
         const T pivot = w_sh[j];
-        // elimination over own rows, one wavefront per row, lanes over columns;
-        // lane 0 of each wave also tracks the next column's candidate
+        // elimination over own rows: thread-per-row (tpr threads per row when
+        // the slice is short), each row scaled by its own multiplier; the
+        // thread holding column j+1 also tracks the next column's candidate
         M nm = (M)-1;
         int ni = 0x7fffffff;
-        for (int64_t rr = wave; rr < nrows; rr += 4) {
-            T *row = rows + rr * ldr;
-            const T q = row[j] / pivot;
-            for (int c = j + 1 + lane; c < b; c += 64) {
-                const T y = fma(-w_sh[c], q, row[c]);
-                row[c] = y;
+        for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
+            const T q = at(rr, j) / pivot;
+            for (int c = j + 1 + sub; c < b; c += tpr) {
+                const T y = fma(-w_sh[c], q, at(rr, c));
+                at(rr, c) = y;
                 if (c == j + 1) {
                     const M v = (M)fabs((double)y);
-                    if (v > nm) {
+                    if (v > nm) {  // rows visited in increasing order per thread
                         nm = v;
                         ni = (int)(r0 + rr);
                     }
                 }
             }
-            if (lane == 0) row[j] = q;
+            if (sub == 0) at(rr, j) = q;
         }
         if (j + 1 < b) {
             cm = nm;
             ci = ni;
-            if (lane != 0) {
-                cm = (M)-1;
-                ci = 0x7fffffff;
-            }
             __syncthreads();
             block_argmax(cm, ci);
         }
@@ -326,7 +339,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         __syncthreads();
         for (int64_t e = t; e < nrows * b; e += 256) {
             const int64_t rr = e / b, c = e - rr * b;
-            Y[(r0 + rr) * ldy + c] = rows[rr * ldl + c];
+            Y[(r0 + rr) * ldy + c] = rows[(int64_t)c * rows_per + rr];
         }
     }
     if (g == 0 && t == 0 && kept_out) *kept_out = kept;

@@ -124,33 +124,33 @@ __global__ void k_res_reduce(const double *__restrict__ res2, const double *__re
     out[c] = (x > 0.0) ? sqrt(a) / sqrt(x) / anorm : 0.0;
 }
 
+// Elementwise kernels over row-major n x b blocks: 256 / min(b, 256) rows per
+// workgroup pass, threads over columns (no per-element integer division).
+#define OFRR_ROWS_COLS_LOOP(BODY)                                                        \
+    const int cols_ = b < 256 ? b : 256;                                                 \
+    const int groups_ = 256 / cols_;                                                     \
+    const int j0_ = threadIdx.x % cols_, g_ = threadIdx.x / cols_;                       \
+    if (g_ < groups_)                                                                    \
+        for (int64_t i = (int64_t)blockIdx.x * groups_ + g_; i < n; i += (int64_t)gridDim.x * groups_) \
+            for (int j = j0_; j < b; j += cols_) { BODY }
+
 template <class TI, class TO>
 __global__ void k_axpby(const TI *__restrict__ AX, const TI *__restrict__ X, int64_t ld, int64_t n,
                         int b, double alpha, double beta, TO *__restrict__ Y, int64_t ldy) {
-    const int64_t total = n * b;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / b;
-        const int j = (int)(e - i * b);
+    OFRR_ROWS_COLS_LOOP(
         const double v = alpha * load_as_f64(AX + i * ld + j) + (beta != 0.0 ? beta * load_as_f64(X + i * ld + j) : 0.0);
-        store_as<TO>(Y + i * ldy + j, v);
-    }
+        store_as<TO>(Y + i * ldy + j, v);)
 }
 
 template <class TP, class TS, class TN>
 __global__ void k_cheb(const TP *__restrict__ P, const TS *__restrict__ Yc, const TS *__restrict__ Yp,
                        int64_t ld, int64_t n, int b, double alpha, double c, double beta,
                        TN *__restrict__ Yn) {
-    const int64_t total = n * b;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / b;
-        const int j = (int)(e - i * b);
+    OFRR_ROWS_COLS_LOOP(
         const int64_t o = i * ld + j;
         double v = alpha * (load_as_f64(P + o) - c * load_as_f64(Yc + o));
         if (beta != 0.0) v -= beta * load_as_f64(Yp + o);
-        store_as<TN>(Yn + o, v);
-    }
+        store_as<TN>(Yn + o, v);)
 }
 
 // Final step: per column norms of X and of R = AX - theta X, sign of the

@@ -19,7 +19,8 @@
 //      symmetric rank-2 update C22 -= v w^T + w v^T with
 //      w = p - (beta/2)(v^T p) v, p = beta C22 v.
 //   2. Eigenvalues of T by Sturm-count multisection: 8 lanes per eigenvalue
-//      probe 7 interior points of its bracket per step (3 bits per step).
+//      probe 7 interior points of its bracket per step (3 bits per step,
+//      19 steps: the bracket shrinks below 2^-55 of the Gershgorin width).
 //   3. Eigenvectors of T by inverse iteration (row-pivoted tridiagonal LU,
 //      three solves), with modified Gram-Schmidt inside clusters of nearly
 //      equal eigenvalues so degenerate pairs stay independent.
@@ -192,7 +193,7 @@ __device__ void bisect_ptr(int n, const double *dg, const double *eo, const doub
         const int idx = base + (t >> 6) * 8 + grp;  // eigenvalue handled by this lane group
         const bool active = idx < n;
         double a = lo, b = hi;
-        for (int it = 0; it < 26; ++it) {
+        for (int it = 0; it < 19; ++it) {  // 3 bits each: 57 bits of the Gershgorin interval
             const double x = a + (b - a) * (double)(sub + 1) * 0.125;
             int c = 0;
             if (active && sub < 7) c = sturm_count(dg, eo2, n, x, pivmin);
@@ -372,11 +373,18 @@ __device__ void sym_eig(double *C, int n, double *w, double *Z, EigWork &wk, dou
 
 // In-place lower Cholesky (right-looking) of the n x n matrix A (ld n);
 // returns false if a pivot is not positive.
-__device__ bool cholesky(double *A, int n) {
+__device__ double chol_floor(const double *A, int ld, int n);
+
+// rel_floor: 1 applies the 1e-12 pivot floor (pencil), 0 only requires
+// positive pivots (the SVD pencil, whose caller reports failure instead of
+// falling back).
+__device__ bool cholesky(double *A, int n, int rel_floor) {
     const int t = threadIdx.x, T = blockDim.x;
+    const double floor_ = rel_floor ? chol_floor(A, n, n) : 0.0;
+    __syncthreads();
     for (int j = 0; j < n; ++j) {
         const double d = A[j + j * n];
-        if (!(d > 0.0)) {
+        if (!(d > floor_)) {
             __syncthreads();
             return false;
         }
@@ -483,7 +491,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
     }
     __syncthreads();
     int rank = n;
-    const bool pd = cholesky(w.L, n);
+    const bool pd = cholesky(w.L, n, 1);
     if (pd) {
         // C <- L^{-1} C L^{-T}
         trsm_lower(w.L, n, C, n);
@@ -595,11 +603,11 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
         LV[e] = 0.5 * (MV[i + j * k2] + MV[j + i * k2]);
     }
     __syncthreads();
-    if (!cholesky(LU, k1)) {
+    if (!cholesky(LU, k1, 0)) {
         if (t == 0) *status = 3;
         return;
     }
-    if (!cholesky(LV, k2)) {
+    if (!cholesky(LV, k2, 0)) {
         if (t == 0) *status = 4;
         return;
     }
@@ -683,19 +691,32 @@ __device__ __forceinline__ double bsum1(double v, double *red) {
     return r;
 }
 
+// Both Cholesky factorisations give up (and the caller falls back to the
+// G-eigen truncation) when a pivot is not above 1e-12 of the largest
+// diagonal entry: such a pivot bounds 1/kappa(G) from above, so G has a
+// condition number beyond 1e12 and its factor would not be trustworthy.
+__device__ double chol_floor(const double *A, int ld, int n) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fmax(m, A[i + i * ld]);
+    return 1e-12 * m;
+}
+
 __device__ bool chol_lds(double *S, int ld, int n) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+    const double floor_ = chol_floor(S, ld, n);
+    __syncthreads();
     for (int j = 0; j < n; ++j) {
         const double dj = S[j + j * ld];
-        if (!(dj > 0.0)) return false;  // every thread read the same value
+        if (!(dj > floor_)) return false;  // every thread read the same value
         const double l = sqrt(dj), il = 1.0 / l;
         __syncthreads();
         for (int i = j + t; i < n; i += SE_THREADS) S[i + j * ld] = (i == j) ? l : S[i + j * ld] * il;
         __syncthreads();
-        const int rem = n - j - 1;
-        for (int e = t; e < rem * rem; e += SE_THREADS) {
-            const int ii = j + 1 + e % rem, kk = j + 1 + e / rem;
-            if (kk <= ii) S[ii + kk * ld] -= S[ii + j * ld] * S[kk + j * ld];
+        // lower triangle of the trailing block: column kk (per ty), rows
+        // ii >= kk (per tx)
+        for (int kk = j + 1 + ty; kk < n; kk += 32) {
+            const double lk = S[kk + j * ld];
+            for (int ii = kk + tx; ii < n; ii += 32) S[ii + kk * ld] -= S[ii + j * ld] * lk;
         }
         __syncthreads();
     }
@@ -718,10 +739,14 @@ __device__ void fwd_solve_reg(const double *S, int ld, int n, double (&x)[16], d
             }
         __syncthreads();
         const double xi = rb[c];
+        // all 16 loads first (rows clamped into the matrix), then the updates
+        double l[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) l[q] = S[min(g + 8 * q, n - 1) + i * ld];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = g + 8 * q;
-            if (r > i && r < n) x[q] -= S[r + i * ld] * xi;
+            x[q] = (r > i && r < n) ? fma(-l[q], xi, x[q]) : x[q];
         }
     }
 }
@@ -740,10 +765,13 @@ __device__ void bwd_solve_reg(const double *S, int ld, int n, double (&x)[16], d
             }
         __syncthreads();
         const double xi = rb[c];
+        double l[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) l[q] = S[i + min(g + 8 * q, n - 1) * ld];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = g + 8 * q;
-            if (r < i) x[q] -= S[i + r * ld] * xi;
+            x[q] = (r < i) ? fma(-l[q], xi, x[q]) : x[q];
         }
     }
 }
@@ -787,16 +815,21 @@ __device__ void tridiag_lds(double *S, int ld, int n, double *d, double *e, doub
         vp = bsum1(vp, red2 + 16 * rb);  // also publishes pv
         rb ^= 1;
         const double K = 0.5 * bt * vp;
-        // C22 -= v w^T + w v^T, w = p - K v (lower triangle, mirrored)
-        for (int el = t; el < m * m; el += SE_THREADS) {
-            const int r = j + 1 + el % m, cc = j + 1 + el / m;
-            if (r >= cc) {
-                const double vr = (r == j + 1) ? vj1 : S[r + j * ld];
+        // C22 -= v w^T + w v^T, w = p - K v, over the whole trailing block on
+        // a 32 x 32 thread grid; each entry's update is v_r w_c + w_r v_c
+        // with both products rounded separately, so entries (r, c) and (c, r)
+        // receive bit-identical updates and C22 stays exactly symmetric
+        {
+            const int tx = t & 31, ty = t >> 5;
+            for (int cc = j + 1 + ty; cc < n; cc += 32) {
                 const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
-                const double wr = pv[r] - K * vr, wc = pv[cc] - K * vc;
-                const double val = S[r + cc * ld] - (vr * wc + wr * vc);
-                S[r + cc * ld] = val;
-                S[cc + r * ld] = val;
+                const double wc = pv[cc] - K * vc;
+                for (int r = j + 1 + tx; r < n; r += 32) {
+                    const double vr = (r == j + 1) ? vj1 : S[r + j * ld];
+                    const double wr = pv[r] - K * vr;
+                    const double upd = __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vc));
+                    S[r + cc * ld] -= upd;
+                }
             }
         }
         if (t == 0) S[(j + 1) + j * ld] = vj1;
@@ -1015,12 +1048,15 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
     for (int j = n - 3; j >= 0; --j) {
         const double bt = beta[j];
         if (bt == 0.0) continue;
-        double s = 0.0;
+        double vq[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = g + 8 * q;
-            if (r > j && r < n) s += S[r + j * ld] * x[q];
+            vq[q] = (r > j && r < n) ? S[min(r, n - 1) + j * ld] : 0.0;
         }
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s = fma(vq[q], x[q], s);
         double *pp = part + pb * 1024;
         pb ^= 1;
         pp[g * 128 + c] = s;
@@ -1030,10 +1066,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         for (int gg = 0; gg < 8; ++gg) tot += pp[gg * 128 + c];
         tot *= bt;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = g + 8 * q;
-            if (r > j && r < n) x[q] -= tot * S[r + j * ld];
-        }
+        for (int q = 0; q < 16; ++q) x[q] = fma(-tot, vq[q], x[q]);
     }
     __syncthreads();
     // I. Y = L^{-T} Z with L back in LDS
