@@ -41,6 +41,15 @@ constexpr int I8_BK = 64;   // K bytes per LDS stage
 constexpr int I8_LD = 80;   // LDS row stride in bytes (64 + 16: conflict-free 16-byte reads)
 constexpr int I8_KMAX = 16384;  // K per int32 accumulation
 
+// Digit planes are stored K-blocked: 64-deep K blocks, each holding all
+// (padded) rows of the plane with their 64 digits contiguous.  A workgroup's
+// 64-deep stage of 64 rows is then one contiguous 4 KiB span, so every
+// 128-byte line it fetches is used whole (a row-major plane read 64 bytes at
+// a time fetched each line twice).
+__device__ __forceinline__ int64_t plane_off(int64_t row, int64_t k, int64_t rows_pad) {
+    return ((k >> 6) * rows_pad + row) * 64 + (k & 63);
+}
+
 // exponent e with |x| < 2^e for the largest |x| (0 for an all-zero set)
 __device__ __forceinline__ int exp_bound(double amax) {
     if (!(amax > 0.0)) return 0;
@@ -65,7 +74,7 @@ __device__ __forceinline__ void digits_of(double x, int e, int8_t (&d)[I8_S]) {
 // ATRANS: op(A)[i][k] = A[k + i*lda] (K-contiguous), else A[i + k*lda].
 template <class TA, bool ATRANS>
 __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, int64_t lda, int64_t m,
-                                                    int64_t kdim, int64_t kpad,
+                                                    int64_t mpad, int64_t kdim, int64_t kpad,
                                                     int8_t *__restrict__ planes, int64_t plane_stride,
                                                     int32_t *__restrict__ ex) {
     __shared__ double red[4];
@@ -95,29 +104,58 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
         }
 #pragma unroll
         for (int s = 0; s < I8_S; ++s)
-            *(v4i_t *)(planes + s * plane_stride + i * kpad + k0) = __builtin_bit_cast(v4i_t, d[s]);
+            *(v4i_t *)(planes + s * plane_stride + plane_off(i, k0, mpad)) = __builtin_bit_cast(v4i_t, d[s]);
     }
 }
 
-// Column-maximum partials of an FP64 row-major block (rows x b, ld):
-// block g covers rows [256 g, 256 g + 256); part[g * bpad + j].
+// Column-maximum partials of an FP64 row-major block (rows x b, ld) over
+// 64-row blocks: part[j * nblk + g].  For b <= 256 the 256 threads split
+// into 256 / b row groups over the block's rows (consecutive threads read
+// consecutive columns), loads unrolled by 8.
 __global__ __launch_bounds__(256) void k_vmax_partial(const double *__restrict__ V, int64_t rows, int b,
-                                                      int64_t ld, int bpad, double *__restrict__ part) {
-    const int64_t r0 = (int64_t)blockIdx.x * 256;
-    for (int j = threadIdx.x; j < bpad; j += 256) {
+                                                      int64_t ld, int nblk, double *__restrict__ part) {
+    __shared__ double cm[256];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int64_t r1 = r0 + 64 < rows ? r0 + 64 : rows;
+    for (int jb = 0; jb < b; jb += 256) {
+        const int cols = (b - jb) < 256 ? (b - jb) : 256;
+        const int groups = 256 / cols;
+        const int j = jb + t % cols, g = t / cols;
         double m = 0.0;
-        if (j < b)
-            for (int64_t r = r0; r < r0 + 256 && r < rows; ++r) m = fmax(m, fabs(V[r * ld + j]));
-        part[(int64_t)blockIdx.x * bpad + j] = m;
+        if (g < groups) {
+            int64_t r = r0 + g;
+            for (; r + 7 * groups < r1; r += 8 * groups) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = V[(r + u * groups) * ld + j];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m = fmax(m, fabs(v[u]));
+            }
+            for (; r < r1; r += groups) m = fmax(m, fabs(V[r * ld + j]));
+        }
+        cm[t] = m;
+        __syncthreads();
+        if (t < cols) {
+            double mm = 0.0;
+            for (int q = 0; q < groups; ++q) mm = fmax(mm, cm[q * cols + t]);
+            part[(int64_t)(jb + t) * nblk + blockIdx.x] = mm;
+        }
+        __syncthreads();
     }
 }
 
-__global__ void k_vexp(const double *__restrict__ part, int nblk, int bpad, int32_t *__restrict__ fx) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// exponent bound of each column from its partials, one wavefront per
+// column (columns b..bpad-1 get 0)
+__global__ __launch_bounds__(256) void k_vexp(const double *__restrict__ part, int nblk, int b, int bpad,
+                                              int32_t *__restrict__ fx) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (j >= bpad) return;
     double m = 0.0;
-    for (int g = 0; g < nblk; ++g) m = fmax(m, part[(int64_t)g * bpad + j]);
-    fx[j] = exp_bound(m);
+    if (j < b)
+        for (int g = lane; g < nblk; g += 64) m = fmax(m, part[(int64_t)j * nblk + g]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) fx[j] = exp_bound(m);
 }
 
 // Digit planes of V, K-contiguous per column: planes[s][j][k], 16 rows of
@@ -143,27 +181,32 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
         }
 #pragma unroll
         for (int s = 0; s < I8_S; ++s)
-            *(v4i_t *)(planes + s * plane_stride + (int64_t)j * kpad + k0) = __builtin_bit_cast(v4i_t, d[s]);
+            *(v4i_t *)(planes + s * plane_stride + plane_off(j, k0, bpad)) = __builtin_bit_cast(v4i_t, d[s]);
     }
 }
 
 // W slab z (rows x b FP64, ld) = the K range z of op(A) V from the digit
-// planes.  Workgroup tile 64 rows x (64 NCT) columns, 2 x 2 waves of
-// 32 rows x (32 NCT) columns; 64-byte K stages through LDS, the next stage
-// prefetched into registers.
+// planes.  Workgroup tile 64 rows x (64 NCT) columns with 4 NCT waves, one
+// 32 x 32 output block each (six int32 accumulators = 96 registers), so two
+// waves share each SIMD and hide each other's LDS and global latency;
+// 64-byte K stages through LDS, the next stage prefetched into registers.
 template <int NCT>
-__global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap, int64_t a_stride,
-                                                  const int32_t *__restrict__ ex,
-                                                  const int8_t *__restrict__ Vp, int64_t v_stride,
-                                                  const int32_t *__restrict__ fx, int64_t kpad,
-                                                  int64_t m, int b, double *__restrict__ W,
-                                                  int64_t ldw, int64_t k_per_split, int ntiles,
-                                                  int nsplit, int xcd_map) {
+__global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict__ Ap, int64_t a_stride,
+                                                        const int32_t *__restrict__ ex,
+                                                        const int8_t *__restrict__ Vp, int64_t v_stride,
+                                                        const int32_t *__restrict__ fx, int64_t kpad,
+                                                        int64_t mpad, int bpad, int64_t m, int b,
+                                                        double *__restrict__ W, int64_t ldw,
+                                                        int64_t k_per_split, int ntiles, int nsplit,
+                                                        int xcd_map) {
     constexpr int BN = 64 * NCT;
+    constexpr int NT = 256 * NCT;                  // threads
+    constexpr int ACH = I8_S * I8_BM * 4 / NT;     // A 16-byte chunks per thread per stage
+    constexpr int VCH = I8_S * BN * 4 / NT;        // V chunks per thread per stage
     __shared__ __attribute__((aligned(16))) int8_t As[I8_S][I8_BM][I8_LD];
     __shared__ __attribute__((aligned(16))) int8_t Vs[I8_S][BN][I8_LD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / (2 * NCT), wc = wave % (2 * NCT);
     int tile, z;
     const int L = blockIdx.x;
     if (xcd_map) {
@@ -181,32 +224,35 @@ __global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap,
     const int64_t kbeg = (int64_t)z * k_per_split;
     const int64_t kend = kbeg + k_per_split < kpad ? kbeg + k_per_split : kpad;
 
-    v16i_t acc[NCT][I8_NG];
+    v16i_t acc[I8_NG];
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-        for (int p = 0; p < I8_NG; ++p) acc[ct][p] = v16i_t{};
+    for (int p = 0; p < I8_NG; ++p) acc[p] = v16i_t{};
 
-    // register staging: A I8_S chunks (one per plane), V I8_S x NCT chunks
-    v4i_t ra[I8_S], rv[I8_S][NCT];
-    const int arow = t >> 2, achk = (t & 3) * 16;
+    // chunk c of a stage: plane c / (rows * 4), row (c / 4) % rows, 16 bytes at 16 (c % 4)
+    v4i_t ra[ACH], rv[VCH];
     auto fetch = [&](int64_t k0) {
 #pragma unroll
-        for (int s = 0; s < I8_S; ++s)
-            ra[s] = *(const v4i_t *)(Ap + s * a_stride + (i0 + arow) * kpad + k0 + achk);
+        for (int u = 0; u < ACH; ++u) {
+            const int c = t + NT * u, pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
+            ra[u] = *(const v4i_t *)(Ap + pl * a_stride + plane_off(i0 + (rem >> 2), k0 + (rem & 3) * 16, mpad));
+        }
 #pragma unroll
-        for (int s = 0; s < I8_S; ++s)
-#pragma unroll
-            for (int h = 0; h < NCT; ++h)
-                rv[s][h] = *(const v4i_t *)(Vp + s * v_stride + (int64_t)(j0 + arow + 64 * h) * kpad + k0 + achk);
+        for (int u = 0; u < VCH; ++u) {
+            const int c = t + NT * u, pl = c / (BN * 4), rem = c % (BN * 4);
+            rv[u] = *(const v4i_t *)(Vp + pl * v_stride + plane_off(j0 + (rem >> 2), k0 + (rem & 3) * 16, bpad));
+        }
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int s = 0; s < I8_S; ++s) *(v4i_t *)&As[s][arow][achk] = ra[s];
+        for (int u = 0; u < ACH; ++u) {
+            const int c = t + NT * u, pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
+            *(v4i_t *)&As[pl][rem >> 2][(rem & 3) * 16] = ra[u];
+        }
 #pragma unroll
-        for (int s = 0; s < I8_S; ++s)
-#pragma unroll
-            for (int h = 0; h < NCT; ++h) *(v4i_t *)&Vs[s][arow + 64 * h][achk] = rv[s][h];
+        for (int u = 0; u < VCH; ++u) {
+            const int c = t + NT * u, pl = c / (BN * 4), rem = c % (BN * 4);
+            *(v4i_t *)&Vs[pl][rem >> 2][(rem & 3) * 16] = rv[u];
+        }
     };
 
     fetch(kbeg);
@@ -217,40 +263,31 @@ __global__ __launch_bounds__(256) void k_gemm_i8s(const int8_t *__restrict__ Ap,
 #pragma unroll
         for (int ks = 0; ks < I8_BK; ks += 32) {
             const int kq = ks + 16 * (lane >> 5);
-            v4i_t a[I8_S];
+            v4i_t a[I8_S], v[I8_S];
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) a[s] = *(const v4i_t *)&As[s][32 * wr + (lane & 31)][kq];
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                const int col = 32 * NCT * wc + 32 * ct + (lane & 31);
-                v4i_t v[I8_S];
+            for (int s = 0; s < I8_S; ++s) v[s] = *(const v4i_t *)&Vs[s][32 * wc + (lane & 31)][kq];
 #pragma unroll
-                for (int s = 0; s < I8_S; ++s) v[s] = *(const v4i_t *)&Vs[s][col][kq];
+            for (int s = 0; s < I8_S; ++s)
 #pragma unroll
-                for (int s = 0; s < I8_S; ++s)
-#pragma unroll
-                    for (int u = 0; u < I8_S; ++u)
-                        if (s + u < I8_NG)
-                            acc[ct][s + u] =
-                                __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[ct][s + u], 0, 0, 0);
-            }
+                for (int u = 0; u < I8_S; ++u)
+                    if (s + u < I8_NG)
+                        acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[s + u], 0, 0, 0);
         }
         __syncthreads();
     }
     double *Wz = W + (int64_t)z * m * ldw;
+    const int gj = j0 + 32 * wc + (lane & 31);
+    const int fj = gj < b ? fx[gj] : 0;
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) {
-        const int gj = j0 + 32 * NCT * wc + 32 * ct + (lane & 31);
-        const int fj = gj < b ? fx[gj] : 0;
+    for (int r = 0; r < 16; ++r) {
+        const int64_t gi = i0 + 32 * wr + (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
+        if (gi >= m || gj >= b) continue;
+        double v = (double)acc[I8_NG - 1][r];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t gi = i0 + 32 * wr + (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
-            if (gi >= m || gj >= b) continue;
-            double v = (double)acc[ct][I8_NG - 1][r];
-#pragma unroll
-            for (int p = I8_NG - 2; p >= 0; --p) v = (double)acc[ct][p][r] + v * 0.0078125;
-            Wz[gi * ldw + gj] = ldexp(v, ex[gi] + fj - 14);
-        }
+        for (int p = I8_NG - 2; p >= 0; --p) v = (double)acc[p][r] + v * 0.0078125;
+        Wz[gi * ldw + gj] = ldexp(v, ex[gi] + fj - 14);
     }
 }
 
@@ -286,8 +323,8 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
     s.ex = ctx->buf<int32_t>("i8_a_exp", (size_t)s.mpad);
     KTimer tm(ctx, "quantize");
     auto go = [&](auto kern, auto p) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)s.mpad), dim3(256), 0, ctx->stream, p, A->ld, s.m, s.kdim,
-                           s.kpad, s.planes, s.plane_stride, s.ex);
+        hipLaunchKernelGGL(kern, dim3((unsigned)s.mpad), dim3(256), 0, ctx->stream, p, A->ld, s.m, s.mpad,
+                           s.kdim, s.kpad, s.planes, s.plane_stride, s.ex);
     };
     const float *af = (const float *)A->values;
     const double *ad = (const double *)A->values;
@@ -311,23 +348,28 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
     const int64_t v_stride = (int64_t)bpad * kpad;
     int8_t *vp = ctx->buf<int8_t>("i8_v_planes", (size_t)I8_S * v_stride);
     int32_t *fx = ctx->buf<int32_t>("i8_v_exp", (size_t)bpad);
-    const int nblk = (int)((sa.kdim + 255) / 256);
-    double *part = ctx->buf<double>("i8_v_part", (size_t)nblk * bpad);
+    const int nblk = (int)((sa.kdim + 63) / 64);
+    double *part = ctx->buf<double>("i8_v_part", (size_t)nblk * b);
     {
         KTimer tm(ctx, "quantize");
-        hipLaunchKernelGGL(k_vmax_partial, dim3(nblk), dim3(256), 0, ctx->stream, V, sa.kdim, b, ldv, bpad,
+        hipLaunchKernelGGL(k_vmax_partial, dim3(nblk), dim3(256), 0, ctx->stream, V, sa.kdim, b, ldv, nblk,
                            part);
-        hipLaunchKernelGGL(k_vexp, dim3((bpad + 255) / 256), dim3(256), 0, ctx->stream, part, nblk, bpad, fx);
+        hipLaunchKernelGGL(k_vexp, dim3((bpad + 3) / 4), dim3(256), 0, ctx->stream, part, nblk, b, bpad, fx);
         hipLaunchKernelGGL(k_vslice, dim3(grid1((int64_t)bpad * (kpad / 16))), dim3(256), 0, ctx->stream, V,
                            sa.kdim, b, ldv, bpad, kpad, fx, vp, v_stride);
         OFRR_HIP(hipGetLastError());
     }
-    // launch shape: enough workgroups for two per CU, K ranges <= I8_KMAX
+    // launch shape: enough workgroups for two per CU; K ranges <= I8_KMAX;
+    // and K ranges short enough that one range of the basis planes
+    // (I8_S x bpad x range bytes, re-read by every row tile) stays within
+    // 2 MiB, so it is served from the XCD's L2 rather than refetched
     const int gx = (int)(sa.mpad / I8_BM), gy = bpad / BN;
     const int ntiles = gx * gy;
     int nsplit = 1;
     const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
-    while (((int64_t)ntiles * nsplit < want && kpad / (nsplit * 2) >= 2048 && nsplit < 8) ||
+    auto vslab = [&](int ns) { return (int64_t)I8_S * bpad * ((kpad + ns - 1) / ns); };
+    while ((((int64_t)ntiles * nsplit < want || vslab(nsplit) > (2LL << 20)) && kpad / (nsplit * 2) >= 1024 &&
+            nsplit < 8) ||
            (kpad + nsplit - 1) / nsplit > I8_KMAX)
         nsplit *= 2;
     int64_t kps = (kpad + nsplit - 1) / nsplit;
@@ -341,13 +383,13 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
     {
         KTimer tm(ctx, "product_i8x");
         if (NCT == 2)
-            hipLaunchKernelGGL(k_gemm_i8s<2>, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, sa.planes,
-                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.m, b, dst, ldw, kps, ntiles,
-                               nsplit, xcd_map);
+            hipLaunchKernelGGL(k_gemm_i8s<2>, dim3((unsigned)nwg), dim3(512), 0, ctx->stream, sa.planes,
+                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw,
+                               kps, ntiles, nsplit, xcd_map);
         else
             hipLaunchKernelGGL(k_gemm_i8s<1>, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, sa.planes,
-                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.m, b, dst, ldw, kps, ntiles,
-                               nsplit, xcd_map);
+                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw,
+                               kps, ntiles, nsplit, xcd_map);
         OFRR_HIP(hipGetLastError());
     }
     if (nsplit > 1) {

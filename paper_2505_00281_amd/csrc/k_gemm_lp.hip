@@ -218,21 +218,49 @@ __global__ void k_transpose_u16(const uint16_t *__restrict__ s, int64_t rows, in
     }
 }
 
+// FP32 row-major block (rows x b, ld) -> 16-bit hi (+ lo) K-contiguous per
+// column (b x ldt), through a 64 x 64 LDS tile: rows are read coalesced, and
+// each thread writes 8 consecutive rows of one column as one 16-byte store.
 template <bool BF16>
-__global__ void k_split_t(const float *__restrict__ s, int64_t rows, int b, int64_t ld,
-                          uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldt) {
-    const int64_t total = rows * b;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / b;
-        const int j = (int)(e - i * b);
-        const float x = s[i * ld + j];
-        const uint16_t h = BF16 ? f32_to_bf16_bits(x) : f32_to_f16_bits(x);
-        hi[(int64_t)j * ldt + i] = h;
-        if (lo) {
-            const float hv = BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
-            const float r = x - hv;  // exact: x and hv share their leading bits
-            lo[(int64_t)j * ldt + i] = BF16 ? f32_to_bf16_bits(r) : f32_to_f16_bits(r);
+__global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ s, int64_t rows, int b, int64_t ld,
+                                                 uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                 int64_t ldt) {
+    __shared__ float tile[64][65];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rr = (t >> 6) + 4 * q, cc = t & 63;
+        const int64_t gi = i0 + rr;
+        const int gj = j0 + cc;
+        tile[rr][cc] = (gi < rows && gj < b) ? s[gi * ld + gj] : 0.f;
+    }
+    __syncthreads();
+    // thread -> column j0 + (t >> 3), rows i0 + 8 (t & 7) .. + 8
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int cc = (t >> 3) + 32 * half, r8 = (t & 7) * 8;
+        const int gj = j0 + cc;
+        const int64_t gi = i0 + r8;
+        if (gj >= b || gi >= ldt) continue;
+        uint16_t h[8], l[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float x = (gi + u < rows) ? tile[r8 + u][cc] : 0.f;
+            h[u] = BF16 ? f32_to_bf16_bits(x) : f32_to_f16_bits(x);
+            const float hv = BF16 ? bf16_bits_to_f32(h[u]) : f16_bits_to_f32(h[u]);
+            l[u] = BF16 ? f32_to_bf16_bits(x - hv) : f32_to_f16_bits(x - hv);  // x - hv is exact
+        }
+        uint16_t *ph = hi + (int64_t)gj * ldt + gi;
+        if (gi + 8 <= ldt) {
+            *(u32x4_t *)ph = __builtin_bit_cast(u32x4_t, h);
+            if (lo) *(u32x4_t *)(lo + (int64_t)gj * ldt + gi) = __builtin_bit_cast(u32x4_t, l);
+        } else {
+            for (int u = 0; gi + u < ldt; ++u) {
+                ph[u] = h[u];
+                if (lo) lo[(int64_t)gj * ldt + gi + u] = l[u];
+            }
         }
     }
 }
@@ -247,12 +275,12 @@ int64_t lowp_ldt(int64_t rows) { return (rows + 7) / 8 * 8; }
 
 void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const float *src,
                    int64_t ld, uint16_t *hi, uint16_t *lo, int64_t ldt) {
+    // the tiles cover the padded length ldt, so its tail is written as zeros
+    const dim3 grid((unsigned)((ldt + 63) / 64), (unsigned)((b + 63) / 64));
     if (t == OFRR_BF16)
-        hipLaunchKernelGGL((k_split_t<true>), dim3(grid1(rows * b)), dim3(256), 0, ctx->stream, src,
-                           rows, b, ld, hi, lo, ldt);
+        hipLaunchKernelGGL((k_split_t<true>), grid, dim3(256), 0, ctx->stream, src, rows, b, ld, hi, lo, ldt);
     else if (t == OFRR_F16)
-        hipLaunchKernelGGL((k_split_t<false>), dim3(grid1(rows * b)), dim3(256), 0, ctx->stream, src,
-                           rows, b, ld, hi, lo, ldt);
+        hipLaunchKernelGGL((k_split_t<false>), grid, dim3(256), 0, ctx->stream, src, rows, b, ld, hi, lo, ldt);
     else
         fail(OFRR_ERR_UNSUPPORTED, "split_block_t: BF16 or F16");
     OFRR_HIP(hipGetLastError());

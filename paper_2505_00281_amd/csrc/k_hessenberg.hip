@@ -313,17 +313,32 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         int ni = 0x7fffffff;
         for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
             const T q = at(rr, j) / pivot;
-            for (int c = j + 1 + sub; c < b; c += tpr) {
+            int c = j + 1 + sub;
+            if (c == j + 1 && c < b) {  // column j+1 first: it feeds the next candidate
                 const T y = fma(-w_sh[c], q, at(rr, c));
                 at(rr, c) = y;
-                if (c == j + 1) {
-                    const M v = (M)fabs((double)y);
-                    if (v > nm) {  // rows visited in increasing order per thread
-                        nm = v;
-                        ni = (int)(r0 + rr);
-                    }
+                const M v = (M)fabs((double)y);
+                if (v > nm) {  // rows visited in increasing order per thread
+                    nm = v;
+                    ni = (int)(r0 + rr);
                 }
+                c += tpr;
             }
+            // the rest in groups of 8: all loads, then the updates, then the
+            // stores (a thread's row is its own, so nothing aliases)
+            for (; c + 7 * tpr < b; c += 8 * tpr) {
+                T y[8], w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    y[u] = at(rr, c + u * tpr);
+                    w[u] = w_sh[c + u * tpr];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) y[u] = fma(-w[u], q, y[u]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) at(rr, c + u * tpr) = y[u];
+            }
+            for (; c < b; c += tpr) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
             if (sub == 0) at(rr, j) = q;
         }
         if (j + 1 < b) {

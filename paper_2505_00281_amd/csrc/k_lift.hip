@@ -112,16 +112,21 @@ __global__ __launch_bounds__(256) void k_tall_small(const TI1 *__restrict__ In1,
 }
 
 // out[c] = sqrt(sum_blk res2[blk][c]) / sqrt(sum_blk xn2[blk][c]) / anorm
-__global__ void k_res_reduce(const double *__restrict__ res2, const double *__restrict__ xn2,
-                             int nblk, int nc, int count, double anorm, double *__restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_res_reduce(const double *__restrict__ res2,
+                                                    const double *__restrict__ xn2, int nblk, int nc,
+                                                    int count, double anorm, double *__restrict__ out) {
+    // one wavefront per column: lanes take every 64th partial, then a fixed
+    // butterfly sum (deterministic)
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (c >= count) return;
     double a = 0.0, x = 0.0;
-    for (int i = 0; i < nblk; ++i) {
+    for (int i = lane; i < nblk; i += 64) {
         a += res2[(int64_t)i * nc + c];
         x += xn2[(int64_t)i * nc + c];
     }
-    out[c] = (x > 0.0) ? sqrt(a) / sqrt(x) / anorm : 0.0;
+    a = wave_sum_f64(a);
+    x = wave_sum_f64(x);
+    if (lane == 0) out[c] = (x > 0.0) ? sqrt(a) / sqrt(x) / anorm : 0.0;
 }
 
 // Elementwise kernels over row-major n x b blocks: 256 / min(b, 256) rows per
@@ -369,7 +374,7 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
 
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
                      int count, double anorm, double *out) {
-    hipLaunchKernelGGL(k_res_reduce, dim3((count + 63) / 64), dim3(64), 0, ctx->stream, res2, xn2,
+    hipLaunchKernelGGL(k_res_reduce, dim3((count + 3) / 4), dim3(256), 0, ctx->stream, res2, xn2,
                        nblk, stride, count, anorm, out);
     OFRR_HIP(hipGetLastError());
 }

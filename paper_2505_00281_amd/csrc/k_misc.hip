@@ -120,8 +120,17 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
         const int groups = 256 / b;
         const int j = t % b, g = t / b;
         unsigned m = 0u;
-        if (g < groups)
-            for (int64_t r = r0 + g; r < r1; r += groups) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
+        if (g < groups) {
+            int64_t r = r0 + g;
+            for (; r + 7 * groups < r1; r += 8 * groups) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = load_as_f64(Y + (r + u * groups) * ldy + j);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m = max(m, mag_bits(v[u]));
+            }
+            for (; r < r1; r += groups) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
+        }
         cm[t] = m;
         __syncthreads();
         if (t < b) {
@@ -141,23 +150,27 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
 // Reduce partials of each column and turn them into power-of-two scales
 // 2^-ceil(log2(max)) (so the scaled column has infinity-norm in (1/2, 1]);
 // a zero column keeps scale 1.  NaN/Inf poison the scale (NaN).
-__global__ void k_colscale(const float *__restrict__ part, int nblk, int b, float *__restrict__ scale) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_colscale(const float *__restrict__ part, int nblk, int b,
+                                                  float *__restrict__ scale) {
+    // one wavefront per column
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (j >= b) return;
     float m = 0.f;
     bool bad = false;
-    for (int i = 0; i < nblk; ++i) {
-        float v = part[(int64_t)j * nblk + i];
+    for (int i = lane; i < nblk; i += 64) {
+        const float v = part[(int64_t)j * nblk + i];
         if (v != v) bad = true;
         m = fmaxf(m, v);
     }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    bad = __any(bad);
+    if (lane != 0) return;
     float s = 1.f;
     if (bad) {
         s = __builtin_nanf("");
     } else if (m > 0.f) {
         int e;
-        float mm = frexpf(m, &e);  // m = mm 2^e, mm in [0.5,1): 2^-e m in [0.5, 1)
-        (void)mm;
+        (void)frexpf(m, &e);  // m = mm 2^e, mm in [0.5,1): 2^-e m in [0.5, 1)
         s = ldexpf(1.f, -e);
     }
     scale[j] = s;
@@ -321,7 +334,7 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
     KTimer tm(ctx, "scale");
     (void)work;
     OFRR_CHECK_ARG(b <= 512, "scale_columns_pow2: b <= 512");
-    const int64_t rpb = 256;
+    const int64_t rpb = 64;
     const int nblk = (int)((n + rpb - 1) / rpb);
     float *part = ctx->buf<float>("colscale_work", (size_t)nblk * b + b + 64);
     float *scale = part + (size_t)nblk * b + 32;
@@ -330,7 +343,7 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
         hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream,
                            (const T *)Y, ldy, n, b, rpb, part, nblk);
     });
-    hipLaunchKernelGGL(k_colscale, dim3((b + 63) / 64), dim3(64), 0, ctx->stream, part, nblk, b, scale);
+    hipLaunchKernelGGL(k_colscale, dim3((b + 3) / 4), dim3(256), 0, ctx->stream, part, nblk, b, scale);
     const int rows_per_wg = 256 / (b < 256 ? b : 256);
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 4096));
     dispatch_type(t, [&](auto *p) {

@@ -86,8 +86,19 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int nchunks, int 
         const int ti = i / PJ_T, tj = j / PJ_T, ii = i % PJ_T, jj = j % PJ_T;
         const int ntile = ((b1 + PJ_T - 1) / PJ_T) * ntj;
         const int tile = ti * ntj + tj;
+        // chunk order fixed (deterministic); loads issued 8 at a time
+        const double *pp = part + (int64_t)tile * PJ_T * PJ_T + ii * PJ_T + jj;
+        const int64_t cstride = (int64_t)ntile * PJ_T * PJ_T;
         double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += part[((int64_t)c * ntile + tile) * PJ_T * PJ_T + ii * PJ_T + jj];
+        int c = 0;
+        for (; c + 8 <= nchunks; c += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)(c + u) * cstride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; c < nchunks; ++c) s += pp[(int64_t)c * cstride];
         C[e] = s;
     }
 }

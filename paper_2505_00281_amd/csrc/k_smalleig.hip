@@ -138,15 +138,34 @@ __device__ void tridiagonalize(double *C, int n, EigWork &wk, double *red) {
 }
 
 // ---------------------------------------------------------------- step 2
+// Number of eigenvalues of the tridiagonal (d, e) below x.  It equals the
+// number of sign changes in the leading principal minors p_k of T - x I,
+// p_k = (d_k - x) p_{k-1} - e_{k-1}^2 p_{k-2}, i.e. the number of negative
+// pivots p_k / p_{k-1} of its LDL^T factorisation.  The minors are carried
+// as (p_{k-1}, p_k) 2^-E, renormalised every step by the exponent of p_k
+// (exact, signs kept), so each step costs one fused multiply-add on the
+// dependency chain instead of a division.  A minor below 2^-901 of its
+// predecessor is replaced by that size with the opposite sign (a tiny
+// negative pivot, as the pivot floor of the ratio form).
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x,
                                            double pivmin) {
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int c = q < 0.0 ? 1 : 0;
+    (void)pivmin;
+    double pm = 1.0;
+    double p = d[0] - x;
+    if (fabs(p) < 0x1p-901) p = -0x1p-901;
+    int c = p < 0.0 ? 1 : 0;
+    {
+        const int ex = __builtin_amdgcn_frexp_exp(p);
+        p = __builtin_amdgcn_frexp_mant(p);
+        pm = __builtin_ldexp(pm, -ex);
+    }
     for (int k = 1; k < n; ++k) {
-        q = (d[k] - x) - e2[k - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        c += q < 0.0 ? 1 : 0;
+        double pn = fma(d[k] - x, p, -(e2[k - 1] * pm));
+        if (fabs(pn) < 0x1p-901) pn = p < 0.0 ? 0x1p-901 : -0x1p-901;
+        c += ((pn < 0.0) != (p < 0.0)) ? 1 : 0;
+        const int ex = __builtin_amdgcn_frexp_exp(pn);
+        pm = __builtin_ldexp(p, -ex);
+        p = __builtin_amdgcn_frexp_mant(pn);
     }
     return c;
 }
@@ -655,8 +674,11 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
 // ------------------------------------------------------------ fast path --
 // n <= 128.  One 1024-thread workgroup keeps the active n x n matrix in LDS
 // (leading dimension n + 1, so row and column walks are both free of bank
-// conflicts) and a second n x n matrix in registers: thread t holds column
-// c = t % 128, rows r = t / 128 + 8 q, q = 0..15.  Every phase then works
+// conflicts) and a second n x n matrix in registers: lane l of wave w holds
+// column c = 8 w + l % 8, rows r = l / 8 + 8 q, q = 0..15.  The eight lanes
+// of one column sit in one wavefront, so the triangular solves and the
+// back-transform exchange values with cross-lane shuffles and need no
+// workgroup barrier at all.  Every phase then works
 // out of LDS and registers; global memory only carries the Cholesky factor
 // while LDS holds the tridiagonal reduction, one transpose, and the
 // eigenvectors of T between their computation and the back-transform.
@@ -685,10 +707,13 @@ __device__ __forceinline__ double bsum1(double v, double *red) {
     v = wave_sum_f64(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    double r = 0.0;
+    // pairwise tree (fixed order, 4 dependent adds instead of 16)
+    double r[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) r += red[i];
-    return r;
+    for (int i = 0; i < 8; ++i) r[i] = red[2 * i] + red[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = r[2 * i] + r[2 * i + 1];
+    return (r[0] + r[1]) + (r[2] + r[3]);
 }
 
 // Both Cholesky factorisations give up (and the caller falls back to the
@@ -716,62 +741,71 @@ __device__ bool chol_lds(double *S, int ld, int n) {
         // ii >= kk (per tx)
         for (int kk = j + 1 + ty; kk < n; kk += 32) {
             const double lk = S[kk + j * ld];
-            for (int ii = kk + tx; ii < n; ii += 32) S[ii + kk * ld] -= S[ii + j * ld] * lk;
+            // rows ii = kk + tx + 32 u (u < 4 covers n <= 128 in one pass):
+            // loads first, then the stores
+            for (int i0 = kk + tx; i0 < n; i0 += 128) {
+                double a[4], l[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ii = min(i0 + 32 * u, n - 1);
+                    a[u] = S[ii + kk * ld];
+                    l[u] = S[ii + j * ld];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + 32 * u < n) S[i0 + 32 * u + kk * ld] = a[u] - l[u] * lk;
+            }
         }
         __syncthreads();
     }
     return true;
 }
 
-// X <- L^{-1} X, L lower triangular in LDS (S, ld), X in registers.  The
-// register holding row i is selected by predication over the unrolled q
-// loop, so x[] is never indexed dynamically.
-__device__ void fwd_solve_reg(const double *S, int ld, int n, double (&x)[16], double *rowbuf) {
-    const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
-    for (int i = 0; i < n; ++i) {
-        double *rb = rowbuf + (i & 1) * 128;
-        const double lii = S[i + i * ld];
+// X <- L^{-1} X, L lower triangular in LDS (S, ld), X in registers (wave-
+// local column layout), invd[i] = 1 / L_ii.  Fully unrolled so every
+// register index is static; row i's owner scales it and a shuffle hands
+// it to the other seven lanes of its column.
+__device__ __forceinline__ void fwd_solve_reg(const double *S, int ld, int n, double (&x)[16], const double *invd) {
+    const int l = threadIdx.x & 63, g = l >> 3, cl = l & 7;
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (g + 8 * q == i) {
-                x[q] /= lii;
-                rb[c] = x[q];
+    for (int q = 0; q < 16; ++q) {
+#pragma unroll 1
+        for (int sidx = 0; sidx < 8; ++sidx) {
+            const int i = 8 * q + sidx;
+            if (i < n) {
+                const double own = x[q] * invd[i];
+                if (g == sidx) x[q] = own;
+                const double xi = __shfl(own, cl + 8 * sidx, 64);
+#pragma unroll
+                for (int q2 = q; q2 < 16; ++q2) {
+                    const int r = g + 8 * q2;
+                    const double lv = S[min(r, n - 1) + i * ld];
+                    x[q2] = (r > i && r < n) ? fma(-lv, xi, x[q2]) : x[q2];
+                }
             }
-        __syncthreads();
-        const double xi = rb[c];
-        // all 16 loads first (rows clamped into the matrix), then the updates
-        double l[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) l[q] = S[min(g + 8 * q, n - 1) + i * ld];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = g + 8 * q;
-            x[q] = (r > i && r < n) ? fma(-l[q], xi, x[q]) : x[q];
         }
     }
 }
 
-// X <- L^{-T} X, L lower triangular in LDS (S, ld), X in registers.
-__device__ void bwd_solve_reg(const double *S, int ld, int n, double (&x)[16], double *rowbuf) {
-    const int c = threadIdx.x & 127, g = threadIdx.x >> 7;
-    for (int i = n - 1; i >= 0; --i) {
-        double *rb = rowbuf + (i & 1) * 128;
-        const double lii = S[i + i * ld];
+// X <- L^{-T} X, same layout.
+__device__ __forceinline__ void bwd_solve_reg(const double *S, int ld, int n, double (&x)[16], const double *invd) {
+    const int l = threadIdx.x & 63, g = l >> 3, cl = l & 7;
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (g + 8 * q == i) {
-                x[q] /= lii;
-                rb[c] = x[q];
+    for (int q = 15; q >= 0; --q) {
+#pragma unroll 1
+        for (int sidx = 7; sidx >= 0; --sidx) {
+            const int i = 8 * q + sidx;
+            if (i < n) {
+                const double own = x[q] * invd[i];
+                if (g == sidx) x[q] = own;
+                const double xi = __shfl(own, cl + 8 * sidx, 64);
+#pragma unroll
+                for (int q2 = 0; q2 <= q; ++q2) {
+                    const int r = g + 8 * q2;
+                    const double lv = S[i + min(r, n - 1) * ld];
+                    x[q2] = (r < i) ? fma(-lv, xi, x[q2]) : x[q2];
+                }
             }
-        __syncthreads();
-        const double xi = rb[c];
-        double l[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) l[q] = S[i + min(g + 8 * q, n - 1) * ld];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = g + 8 * q;
-            x[q] = (r < i) ? fma(-l[q], xi, x[q]) : x[q];
         }
     }
 }
@@ -798,18 +832,33 @@ __device__ void tridiag_lds(double *S, int ld, int n, double *d, double *e, doub
             beta[j] = bt;
         }
         if (bt == 0.0) continue;  // column already reduced; S untouched
-        // p = beta C22 v, one wavefront per row (column r of the symmetric C22)
+        // p = beta C22 v: eight lanes per row (column r of the symmetric C22),
+        // each over every eighth entry, then a 3-step shuffle sum; a wave
+        // covers 8 rows at once
         double vp = 0.0;
-        for (int r = j + 1 + wave; r < n; r += 16) {
-            double acc = 0.0;
-            for (int cc = j + 1 + lane; cc < n; cc += 64) {
-                const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
-                acc += S[cc + r * ld] * vc;
-            }
-            acc = wave_sum_f64(acc) * bt;
-            if (lane == 0) {
-                pv[r] = acc;
-                vp += ((r == j + 1) ? vj1 : S[r + j * ld]) * acc;
+        {
+            const int rl = lane & 7, sub = lane >> 3;
+            for (int r = j + 1 + 8 * wave + rl; r - rl < n; r += 128) {
+                double a0 = 0.0, a1 = 0.0;
+                if (r < n) {
+                    int cc = j + 1 + sub;
+                    for (; cc + 8 < n; cc += 16) {
+                        const double v0 = (cc == j + 1) ? vj1 : S[cc + j * ld];
+                        const double v1 = S[cc + 8 + j * ld];
+                        a0 = fma(S[cc + r * ld], v0, a0);
+                        a1 = fma(S[cc + 8 + r * ld], v1, a1);
+                    }
+                    if (cc < n) a0 = fma(S[cc + r * ld], (cc == j + 1) ? vj1 : S[cc + j * ld], a0);
+                }
+                double acc = a0 + a1;
+                acc += __shfl_xor(acc, 8, 64);
+                acc += __shfl_xor(acc, 16, 64);
+                acc += __shfl_xor(acc, 32, 64);
+                acc *= bt;
+                if (sub == 0 && r < n) {
+                    pv[r] = acc;
+                    vp += ((r == j + 1) ? vj1 : S[r + j * ld]) * acc;
+                }
             }
         }
         vp = bsum1(vp, red2 + 16 * rb);  // also publishes pv
@@ -823,12 +872,26 @@ __device__ void tridiag_lds(double *S, int ld, int n, double *d, double *e, doub
             const int tx = t & 31, ty = t >> 5;
             for (int cc = j + 1 + ty; cc < n; cc += 32) {
                 const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
-                const double wc = pv[cc] - K * vc;
-                for (int r = j + 1 + tx; r < n; r += 32) {
-                    const double vr = (r == j + 1) ? vj1 : S[r + j * ld];
-                    const double wr = pv[r] - K * vr;
-                    const double upd = __dadd_rn(__dmul_rn(vr, wc), __dmul_rn(wr, vc));
-                    S[r + cc * ld] -= upd;
+                // w_x = p_x - K v_x with explicit roundings, so a value is the
+                // same whether x indexes a row or a column
+                const double wc = __dsub_rn(pv[cc], __dmul_rn(K, vc));
+                // rows r = j + 1 + tx + 32 u, u < 4 (n <= 128: one pass):
+                // every load before any store
+                for (int r0 = j + 1 + tx; r0 < n; r0 += 128) {
+                    double vr[4], pr[4], a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int r = min(r0 + 32 * u, n - 1);
+                        vr[u] = (r == j + 1) ? vj1 : S[r + j * ld];
+                        pr[u] = pv[r];
+                        a[u] = S[r + cc * ld];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double wr = __dsub_rn(pr[u], __dmul_rn(K, vr[u]));
+                        const double upd = __dadd_rn(__dmul_rn(vr[u], wc), __dmul_rn(wr, vc));
+                        if (r0 + 32 * u < n) S[r0 + 32 * u + cc * ld] = a[u] - upd;
+                    }
                 }
             }
         }
@@ -943,12 +1006,12 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
     __shared__ double red2[32];
     const int ld = n + 1;
     double *S = smem;
-    double *rowbuf = S + (size_t)n * ld;  // 2 x 128
-    double *part = rowbuf + 256;          // 2 x 8 x 128
+    double *invd = S + (size_t)n * ld;    // 1 / L_ii (128)
+    double *part = invd + 256;            // spare (2 x 8 x 128)
     double *dd = part + 2048;             // d, e, e2, lam, beta, p: 128 each
     double *ee = dd + 128, *e2 = ee + 128, *lam = e2 + 128, *beta = lam + 128, *pv = beta + 128;
     const int t = threadIdx.x;
-    const int c = t & 127, g = t >> 7;
+    const int c = 8 * (t >> 6) + (t & 7), g = (t & 63) >> 3;  // wave-local column layout
     const bool cin = c < n;
 
     // A. Cholesky of sym(G) in LDS
@@ -964,11 +1027,13 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         }
         return;
     }
-    // B. keep L in global memory
+    // B. keep L in global memory; reciprocal pivots for the solves
     for (int el = t; el < n * n; el += SE_THREADS) {
         const int i = el % n, j = el / n;
         fw.Lg[el] = (i >= j) ? S[i + j * ld] : 0.0;
     }
+    for (int i = t; i < n; i += SE_THREADS) invd[i] = 1.0 / S[i + i * ld];
+    __syncthreads();
     // C. X = sym(H) in registers; X <- L^{-1} X
     double x[16];
 #pragma unroll
@@ -976,7 +1041,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         const int r = g + 8 * q;
         x[q] = (r < n && cin) ? 0.5 * (H[r + c * n] + H[c + r * n]) : 0.0;
     }
-    fwd_solve_reg(S, ld, n, x, rowbuf);
+    fwd_solve_reg(S, ld, n, x, invd);
     // D. transpose through global memory, X <- L^{-1} X^T = L^{-1} H L^{-T}
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -989,7 +1054,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         const int r = g + 8 * q;
         x[q] = (r < n && cin) ? fw.Tg[r + c * n] : 0.0;
     }
-    fwd_solve_reg(S, ld, n, x, rowbuf);
+    fwd_solve_reg(S, ld, n, x, invd);
     __syncthreads();
     // E. C (symmetrised) into LDS over L
 #pragma unroll
@@ -1044,7 +1109,6 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         const int r = g + 8 * q;
         x[q] = (r < n && cin) ? fw.Zt[r + c * n] : 0.0;
     }
-    int pb = 0;  // partial-sum buffer, alternating between executed steps
     for (int j = n - 3; j >= 0; --j) {
         const double bt = beta[j];
         if (bt == 0.0) continue;
@@ -1054,16 +1118,17 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
             const int r = g + 8 * q;
             vq[q] = (r > j && r < n) ? S[min(r, n - 1) + j * ld] : 0.0;
         }
-        double s = 0.0;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) s = fma(vq[q], x[q], s);
-        double *pp = part + pb * 1024;
-        pb ^= 1;
-        pp[g * 128 + c] = s;
-        __syncthreads();
-        double tot = 0.0;
-#pragma unroll
-        for (int gg = 0; gg < 8; ++gg) tot += pp[gg * 128 + c];
+        for (int q = 0; q < 16; q += 2) {
+            s0 = fma(vq[q], x[q], s0);
+            s1 = fma(vq[q + 1], x[q + 1], s1);
+        }
+        // sum over the eight lanes of the column (lane bits 3..5), fixed order
+        double tot = s0 + s1;
+        tot += __shfl_xor(tot, 8, 64);
+        tot += __shfl_xor(tot, 16, 64);
+        tot += __shfl_xor(tot, 32, 64);
         tot *= bt;
 #pragma unroll
         for (int q = 0; q < 16; ++q) x[q] = fma(-tot, vq[q], x[q]);
@@ -1075,7 +1140,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__rest
         S[i + j * ld] = fw.Lg[el];
     }
     __syncthreads();
-    bwd_solve_reg(S, ld, n, x, rowbuf);
+    bwd_solve_reg(S, ld, n, x, invd);
     // J. order: lam is ascending
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
