@@ -33,6 +33,16 @@ N, K_WANT, BASIS, DEGREE = 16384, 64, 128, 4
 NOISE = 1e-3
 TOL = 1e-8
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the current product kernels at n=16384, b=128
+# (the FP64 product: 1146.8 MiB, used only by the FP64 form at that width),
+# from rocprofv3 FETCH_SIZE + WRITE_SIZE passes over `bench.py --traffic-probe`,
+# scaled by the same counters on a plain 1 GiB copy (FETCH x2, WRITE x1).
+# Counters were taken for these kernel versions; a changed kernel needs new
+# passes before its entry is trusted again.
+MEASURED_TRAFFIC = {
+    "product_bf16": 553.5 * 2**20,
+    "product_i8x": 1758.8 * 2**20,
+}
 
 
 def log(*a):
@@ -210,8 +220,10 @@ def main():
                          "k_gemm_lp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)"),
         "product_bf16x2": (N * N * 4 + N * BASIS * 4 + N * BASIS * 4, 3 * gemm, 2500.0,
                            "k_gemm_lp<bf16, split A and V> (3 BF16 MFMAs per tile step)"),
-        "product_f64": (N * N * 4 + N * BASIS * 8 + N * BASIS * 8, gemm, 78.6,
-                        "k_gemm_f64 (A FP32 promoted, FP64 MFMA 16x16x4)"),
+        # in the mixed call the only FP64 product is the final residual check
+        # of the k returned vectors
+        "product_f64": (N * N * 4 + N * K_WANT * 16, 2.0 * N * N * K_WANT, 78.6,
+                        "k_gemm_f64 (final residual product, k columns, FP64 MFMA 16x16x4)"),
         "product_i8x": (6 * N * N + 6 * N * BASIS + 8 * N * BASIS, 21 * gemm, 5000.0,
                         "k_gemm_i8s (6 x 6 INT8 digit planes, 21 MFMA 32x32x32 pairs, exact int32)"),
     }
@@ -230,16 +242,34 @@ def main():
             ach = ops / (avg * 1e-3) / 1e12
             r = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_t,
                  "unit": "TOP/s" if f == "product_i8x" else "TFLOP/s", "frac": round(ach / peak_t, 4)}
-        r.update({"traffic": None, "kernel": kname, "family": f, "avg_launch_ms": avg, "launches": n_l,
+        r.update({"traffic": MEASURED_TRAFFIC.get(f) if N == 16384 and BASIS == 128 else None,
+                  "kernel": kname, "family": f, "avg_launch_ms": avg, "launches": n_l,
                   "algorithmic_bytes_per_launch": nb, "algorithmic_ops_per_launch": ops})
         return r
 
+    # the product with the largest share; the two latency-bound kernels (one-
+    # workgroup small eigensolver, grid-exchange Hessenberg sweep) have no
+    # bandwidth or MFMA roofline and are reported by time
     dom = max(alg, key=lambda f: stats[f][1])
     roofline = roof(dom)
+    roofline["latency_bound_ms_one_call"] = {f: round(stats[f][1], 3) for f in ("small_eig", "hessenberg")}
     roofline["per_family"] = {f: {k: v for k, v in roof(f).items() if k in ("bound", "achieved", "unit", "frac",
                                                                            "avg_launch_ms")}
                               for f in alg if stats[f][0]}
     kernel_ms = {f: {"launches": n, "total_ms": round(t, 3)} for f, (n, t) in stats.items()}
+
+    # where the FP64 form's time goes (same families, one profiled call)
+    kernel_ms_fp64 = None
+    if not args.no_fp64_form:
+        prof64 = ofrr.make_plan(basis_dtype="f64", profile=True, **common)
+        ctx.kernel_stats_reset()
+        ctx.eig_partial(A, K_WANT, BASIS, plan=prof64, X0=X0)
+        torch.cuda.synchronize()
+        kernel_ms_fp64 = {}
+        for f in fams:
+            n_l, t_l = ctx.kernel_stats(f)
+            if n_l:
+                kernel_ms_fp64[f] = {"launches": n_l, "total_ms": round(t_l, 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -264,6 +294,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_one_call": kernel_ms,
+        "kernel_ms_one_call_fp64_form": kernel_ms_fp64,
     }
     print(json.dumps(out))
 

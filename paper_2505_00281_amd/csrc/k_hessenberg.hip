@@ -207,22 +207,33 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     local_argmax(0, cm, ci);
     block_argmax(cm, ci);
 
+    // publish the candidate of column jj (its row's entries jj..b-1 must be
+    // final for the columns before jj); every thread must see the same (cm, ci)
+    auto publish = [&](int jj) {
+        const int bufp = jj & 1;
+        const uint32_t tagp = (uint32_t)jj + 1u;
+        uint64_t *my_row = slot_rows + ((int64_t)bufp * G + g) * b * TW;
+        if (ci != 0x7fffffff) {
+            const int64_t rr = ci - r0;
+            for (int c = jj + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, at(rr, c), tagp);
+        }
+        if (t == 0) {
+            uint64_t *my_cand = slot_cand + ((int64_t)bufp * G + g) * CW;
+            put_value<M>(my_cand, cm, tagp);
+            put_word(my_cand + CW - 1, (uint32_t)ci, tagp);
+        }
+    };
+    publish(0);
+
+    // Look-ahead: once column j's multipliers are known, column j+1 and the
+    // next candidate row are finished first and the candidate of column j+1
+    // is published; the rest of the slice is eliminated while the other
+    // workgroups' candidates are in flight.
     int kept = 0;
     for (int j = 0; j < b; ++j) {
         const int buf = j & 1;
         const uint32_t tag = (uint32_t)j + 1u;
-        // 1. publish the candidate row (columns j..b-1), then the candidate
-        uint64_t *my_row = slot_rows + ((int64_t)buf * G + g) * b * TW;
-        if (ci != 0x7fffffff) {
-            const int64_t rr = ci - r0;
-            for (int c = j + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, at(rr, c), tag);
-        }
-        if (t == 0) {
-            uint64_t *my_cand = slot_cand + ((int64_t)buf * G + g) * CW;
-            put_value<M>(my_cand, cm, tag);
-            put_word(my_cand + CW - 1, (uint32_t)ci, tag);
-        }
-        // 2. every candidate, one thread per workgroup
+        // 1. every candidate of column j, one thread per workgroup
         {
             M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
@@ -287,11 +298,12 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             if (j + 1 < b) {
                 local_argmax(j + 1, cm, ci);
                 block_argmax(cm, ci);
+                publish(j + 1);
             }
             continue;
         }
         ++kept;
-        // 3. multipliers: the winner's published row (columns j..b-1)
+        // 2. multipliers: the winner's published row (columns j..b-1)
         {
             const uint64_t *win_row = slot_rows + ((int64_t)buf * G + wg) * b * TW;
             int ok = 1;
@@ -306,47 +318,59 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             if (!__syncthreads_and(ok)) break;
         }
         const T pivot = w_sh[j];
-        // elimination over own rows: thread-per-row (tpr threads per row when
-        // the slice is short), each row scaled by its own multiplier; the
-        // thread holding column j+1 also tracks the next column's candidate
-        M nm = (M)-1;
-        int ni = 0x7fffffff;
-        for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
-            const T q = at(rr, j) / pivot;
-            int c = j + 1 + sub;
-            if (c == j + 1 && c < b) {  // column j+1 first: it feeds the next candidate
-                const T y = fma(-w_sh[c], q, at(rr, c));
-                at(rr, c) = y;
-                const M v = (M)fabs((double)y);
-                if (v > nm) {  // rows visited in increasing order per thread
-                    nm = v;
-                    ni = (int)(r0 + rr);
-                }
-                c += tpr;
-            }
-            // the rest in groups of 8: all loads, then the updates, then the
-            // stores (a thread's row is its own, so nothing aliases)
-            for (; c + 7 * tpr < b; c += 8 * tpr) {
-                T y[8], w[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    y[u] = at(rr, c + u * tpr);
-                    w[u] = w_sh[c + u * tpr];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) y[u] = fma(-w[u], q, y[u]);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) at(rr, c + u * tpr) = y[u];
-            }
-            for (; c < b; c += tpr) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
-            if (sub == 0) at(rr, j) = q;
-        }
         if (j + 1 < b) {
+            // 3. column j+1 of every row (one fused multiply-add each) and the
+            // local candidate of column j+1
+            M nm = (M)-1;
+            int ni = 0x7fffffff;
+            if (sub == 0)
+                for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
+                    const T q = at(rr, j) / pivot;
+                    const T y = fma(-w_sh[j + 1], q, at(rr, j + 1));
+                    at(rr, j + 1) = y;
+                    const M v = (M)fabs((double)y);
+                    if (v > nm) {  // rows visited in increasing order per thread
+                        nm = v;
+                        ni = (int)(r0 + rr);
+                    }
+                }
             cm = nm;
             ci = ni;
             __syncthreads();
             block_argmax(cm, ci);
+            // 4. finish the candidate row (columns j+2..b-1), then publish it
+            if (ci != 0x7fffffff) {
+                const int64_t rr = ci - r0;
+                const T q = at(rr, j) / pivot;
+                for (int c = j + 2 + t; c < b; c += 256) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
+            }
+            __syncthreads();
+            publish(j + 1);
         }
+        // 5. the rest: columns j+2..b-1 of every other row, then the
+        // multipliers into column j
+        for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
+            const T q = at(rr, j) / pivot;
+            if (r0 + rr != ci) {
+                int c = j + 2 + sub;
+                for (; c + 7 * tpr < b; c += 8 * tpr) {
+                    T y[8], w[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        y[u] = at(rr, c + u * tpr);
+                        w[u] = w_sh[c + u * tpr];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) y[u] = fma(-w[u], q, y[u]);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) at(rr, c + u * tpr) = y[u];
+                }
+                for (; c < b; c += tpr) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
+            }
+        }
+        __syncthreads();
+        if (sub == 0)
+            for (int64_t rr = t / tpr; rr < nrows; rr += rstep) at(rr, j) = at(rr, j) / pivot;
         __syncthreads();
     }
 

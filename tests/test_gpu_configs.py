@@ -16,6 +16,8 @@ vectors from A as stored).
 * 512 problems n in [256, 4096], lambda_i = 0.9^i, BF16 basis, power
   filter: every problem's eigenvalues against the closed form.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -146,7 +148,12 @@ def test_batched_512_bf16(ctx):
         X0s.append(torch.from_numpy(W.uniform_start(int(n), 16, 1105000 + p)))
     print("config batched run", flush=True)
     plan = _plan(basis_dtype="bf16", refine=1, tol=5e-9, anorm=0.9, max_iters=200, stall_iters=3)
+    torch.cuda.synchronize()
+    t0 = time.time()
     outs = ctx.eig_partial_batched(As, 8, 16, plan=plan, X0s=X0s)
+    torch.cuda.synchronize()
+    print("batched 512 problems: %.2f s, iterations %s" % (time.time() - t0,
+          sorted(set(o.info["iters"] for o in outs))), flush=True)
     ref = 0.9 ** np.arange(1, 9)
     for p, o in enumerate(outs):
         assert np.all(o.resid.cpu().numpy() <= 1e-8), p
