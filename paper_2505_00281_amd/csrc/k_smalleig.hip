@@ -672,48 +672,139 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
 }
 
 // ------------------------------------------------------------ fast path --
-// n <= 128.  One 1024-thread workgroup keeps the active n x n matrix in LDS
-// (leading dimension n + 1, so row and column walks are both free of bank
-// conflicts) and a second n x n matrix in registers: lane l of wave w holds
-// column c = 8 w + l % 8, rows r = l / 8 + 8 q, q = 0..15.  The eight lanes
-// of one column sit in one wavefront, so the triangular solves and the
-// back-transform exchange values with cross-lane shuffles and need no
-// workgroup barrier at all.  Every phase then works
-// out of LDS and registers; global memory only carries the Cholesky factor
-// while LDS holds the tridiagonal reduction, one transpose, and the
-// eigenvectors of T between their computation and the back-transform.
+// n <= 128, as a pipeline of seven launches on the stream, each shaped for
+// the parallelism its step has:
 //
-// Eigenvectors of T: for an eigenvalue separated from its neighbours by
-// more than 1e-7 |T| the twisted factorisation gives the vector in one pass
-// (forward pivots D+ of T - lam I = L+ D+ L+^T, backward pivots D- of the
-// U D- U^T factorisation, gamma_k = D+_k + D-_k - (a_k - lam), twist
-// r = argmin |gamma_k|, then z_r = 1 and the two one-term recurrences away
-// from r); clusters of closer eigenvalues go through inverse iteration with
-// Gram-Schmidt inside the cluster.
+//   k_fp_chol     one 1024-thread workgroup.  G = L L^T, right-looking, with
+//                 the n x n matrix in registers: thread t = 32 a + b holds
+//                 rows a + 32 u and columns b + 32 v (u, v < 4), so column j
+//                 reaches LDS from 32 threads and every rank-1 update is
+//                 register-local; one barrier per column.
+//   k_fp_solve    ceil(n / 16) workgroups of two waves: X = L^{-1} sym(H)
+//                 (stored transposed), then C = L^{-1} X^T = L^{-1} H L^{-T}.
+//                 A wave holds eight columns (lane l: column l % 8, rows
+//                 l / 8 + 8 q), so a row's value reaches its column's other
+//                 seven lanes by a shuffle and no barrier is needed.
+//   k_fp_tridiag  one 1024-thread workgroup, the same register layout as the
+//                 Cholesky: per column the reflector from a wave-redundant
+//                 norm, p = beta C v by 16 register products and a butterfly
+//                 sum over the 32 lanes sharing a row group, the rank-2
+//                 update in registers; two barriers per column.
+//   k_fp_bisect   one wave per eigenvalue: 63 Sturm counts per step split
+//                 the bracket into 64 (6 bits per step, 10 steps).
+//   k_fp_vectors  one wave per eigenvalue: an eigenvalue separated from its
+//                 neighbours by more than 1e-7 |T| gets its vector from the
+//                 twisted factorisation (forward pivots D+ of
+//                 T - lam I = L+ D+ L+^T and backward pivots D- of U D- U^T
+//                 on two lanes at once, gamma_k = D+_k + D-_k - (a_k - lam),
+//                 twist r = argmin |gamma_k|, then z_r = 1 and the two one-term
+//                 recurrences away from r); a cluster of closer eigenvalues
+//                 goes through inverse iteration with Gram-Schmidt inside the
+//                 cluster, on one lane of the cluster's first wave.
+//   k_fp_back     ceil(n / 16) workgroups: Z = Q Z_T (reflectors in LDS,
+//                 applied in reverse), Y = L^{-T} Z, output order.
+//
+// Every later launch reads the status word first and returns at once when
+// the Cholesky factorisation gave up, so the host decides about the general
+// kernel after one synchronisation.
 constexpr int FP_NMAX = 128;
+constexpr int FP_LD = 130;    // LDS leading dimension of the zero-padded 128 x 128 matrices
+constexpr int FP_COLS = 32;   // columns per solve / back-transform workgroup (two waves)
+constexpr int FP_WAVES = 4;   // waves (eigenvalues) per bisection / vector workgroup
 
-struct FastWork {
-    double *Lg;   // n x n, the Cholesky factor (column-major)
-    double *Tg;   // n x n, transpose scratch
-    double *Zt;   // n x n, eigenvectors of T (column-major)
-    double *dpm;  // 2 n x n, twisted-factorisation pivots, [k][i]
-    double *scr;  // 6 n per eigenvector (inverse iteration inside clusters)
-    int *cstart;  // n
+struct FPWork {
+    double *Lg;   // n x n  Cholesky factor, column-major, zero above the diagonal
+    double *Xg;   // n x n  (L^{-1} sym(H))^T
+    double *Cg;   // n x n  C = L^{-1} H L^{-T}
+    double *Vg;   // n x n  reflector j in column j, zero in rows <= j
+    double *Zt;   // n x n  eigenvectors of T
+    double *tri;  // 4 n    d, e, beta, lam
+    double *scr;  // 6 n per eigenvalue (inverse iteration inside clusters)
 };
 
-// one-sync block sum over 1024 threads (red: 16 doubles, alternate buffers
-// between consecutive calls)
-__device__ __forceinline__ double bsum1(double v, double *red) {
-    v = wave_sum_f64(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    // pairwise tree (fixed order, 4 dependent adds instead of 16)
-    double r[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = red[2 * i] + red[2 * i + 1];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r[i] = r[2 * i] + r[2 * i + 1];
-    return (r[0] + r[1]) + (r[2] + r[3]);
+// r[i] for a register array, from the values through a tree of selects
+// on the bits of i, so the array never needs an addressable (scratch) copy
+__device__ __forceinline__ double pick8v(double r0, double r1, double r2, double r3, double r4, double r5,
+                                         double r6, double r7, int i) {
+    const bool b0 = (i & 1) != 0, b1 = (i & 2) != 0, b2 = (i & 4) != 0;
+    const double a0 = b0 ? r1 : r0, a1 = b0 ? r3 : r2;
+    const double a2 = b0 ? r5 : r4, a3 = b0 ? r7 : r6;
+    const double c0 = b1 ? a1 : a0, c1 = b1 ? a3 : a2;
+    return b2 ? c1 : c0;
+}
+#define pick8(r, i) pick8v((r)[0], (r)[1], (r)[2], (r)[3], (r)[4], (r)[5], (r)[6], (r)[7], (i))
+
+// Cross-lane moves of an FP64 value through the DPP lane patterns (both
+// 32-bit halves), and a uniform read of one lane.  Callers keep every lane
+// of the wave active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- 7 - i within each 8
+constexpr int DPP_MIRROR = 0x140;      // lane i <- 15 - i within each 16
+
+// value of lane 4 (l / 4) + s of each quad, s a compile-time constant after unrolling
+__device__ __forceinline__ double quad_bcast(double v, int s) {
+    switch (s) {
+        case 0: return dpp_f64<0x00>(v);
+        case 1: return dpp_f64<0x55>(v);
+        case 2: return dpp_f64<0xAA>(v);
+        default: return dpp_f64<0xFF>(v);
+    }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+// Sum over the 64 lanes with a fixed pattern (rows of 16 lanes, then the
+// four row sums in a fixed order): every lane, and every wave summing the
+// same data, gets the same bits.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+    v += dpp_f64<DPP_XOR1>(v);
+    v += dpp_f64<DPP_XOR2>(v);
+    v += dpp_f64<DPP_HALF_MIRROR>(v);
+    v += dpp_f64<DPP_MIRROR>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// Orders this wave's LDS accesses before and after the call (lanes of one
+// wave exchanging values through LDS).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// 1 / sqrt(a) and 1 / a for positive normal a: the hardware estimates
+// refined by two Newton steps each (a few ulps; the IEEE-exact sequences
+// cost several times the latency on these serial chains)
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double r = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    r = fma(r, fma(-h * r, r, 0.5), r);
+    r = fma(r, fma(-h * r, r, 0.5), r);
+    return r;
+}
+__device__ __forceinline__ double rcp_nr(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = fma(r, fma(-a, r, 1.0), r);
+    r = fma(r, fma(-a, r, 1.0), r);
+    return r;
 }
 
 // Both Cholesky factorisations give up (and the caller falls back to the
@@ -726,235 +817,390 @@ __device__ double chol_floor(const double *A, int ld, int n) {
     return 1e-12 * m;
 }
 
-__device__ bool chol_lds(double *S, int ld, int n) {
-    const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
-    const double floor_ = chol_floor(S, ld, n);
+constexpr size_t fp_lds_bytes() { return ((size_t)FP_NMAX * FP_LD + 2 * FP_NMAX) * sizeof(double); }
+
+// M (n x n, column-major in global memory) into LDS as a 128 x 128 matrix,
+// zero outside n x n, leading dimension FP_LD; 16 pairs of loads in flight
+// per thread (blockDim.x must divide 512).
+__device__ void fp_load_padded(const double *M, int n, double *S) {
+    const int per = 64 * FP_NMAX / blockDim.x;
+    for (int k0 = 0; k0 < per; k0 += 16) {
+        double va[16], vb[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int el = threadIdx.x + (k0 + k) * blockDim.x;
+            const int r = 2 * (el & 63), c = min(el >> 6, n - 1);
+            va[k] = M[min(r, n - 1) + (size_t)c * n];
+            vb[k] = M[min(r + 1, n - 1) + (size_t)c * n];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int el = threadIdx.x + (k0 + k) * blockDim.x;
+            const int r = 2 * (el & 63), c = el >> 6;
+            double2 v;
+            v.x = (r < n && c < n) ? va[k] : 0.0;
+            v.y = (r + 1 < n && c < n) ? vb[k] : 0.0;
+            *reinterpret_cast<double2 *>(S + r + c * FP_LD) = v;
+        }
+    }
+}
+
+// X <- L^{-1} X and X <- L^{-T} X for the sixteen columns of a wave, L in
+// LDS (zero-padded, FP_LD), invd[i] = 1 / L_ii.  Lane l holds rows
+// (l & 3) + 4 q, q < 32, of column l / 4, so row i's value reaches the other
+// three lanes of its column by one DPP move.  The updates run over whole
+// register blocks: entries of L outside its triangle are zero, and the
+// owner's own row is overwritten with the solved value afterwards.
+__device__ __forceinline__ void fwd_solve_q4(const double *S, int n, double (&x)[32], const double *invd) {
+    const int sl = threadIdx.x & 3;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i = 4 * q + s;
+            if (i < n) {
+                const double xi = quad_bcast(x[q] * invd[i], s);
+#pragma unroll
+                for (int q2 = q; q2 < 32; ++q2) x[q2] = fma(-S[sl + 4 * q2 + i * FP_LD], xi, x[q2]);
+                if (sl == s) x[q] = xi;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void bwd_solve_q4(const double *S, int n, double (&x)[32], const double *invd) {
+    const int sl = threadIdx.x & 3;
+#pragma unroll
+    for (int q = 31; q >= 0; --q) {
+#pragma unroll
+        for (int s = 3; s >= 0; --s) {
+            const int i = 4 * q + s;
+            if (i < n) {
+                const double xi = quad_bcast(x[q] * invd[i], s);
+#pragma unroll
+                for (int q2 = 0; q2 <= q; ++q2) x[q2] = fma(-S[i + (sl + 4 * q2) * FP_LD], xi, x[q2]);
+                if (sl == s) x[q] = xi;
+            }
+        }
+    }
+}
+
+// second = 0: X = L^{-1} sym(H), written as X^T; second = 1: C = L^{-1} X^T.
+__global__ __launch_bounds__(4 * FP_COLS) void k_fp_solve(const double *__restrict__ H, int n, int second,
+                                                          FPWork w, const int *status) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    if (status[0] != 0) return;
+    double *S = smem, *invd = S + FP_NMAX * FP_LD;
+    fp_load_padded(w.Lg, n, S);
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double dj = S[j + j * ld];
-        if (!(dj > floor_)) return false;  // every thread read the same value
-        const double l = sqrt(dj), il = 1.0 / l;
-        __syncthreads();
-        for (int i = j + t; i < n; i += SE_THREADS) S[i + j * ld] = (i == j) ? l : S[i + j * ld] * il;
-        __syncthreads();
-        // lower triangle of the trailing block: column kk (per ty), rows
-        // ii >= kk (per tx)
-        for (int kk = j + 1 + ty; kk < n; kk += 32) {
-            const double lk = S[kk + j * ld];
-            // rows ii = kk + tx + 32 u (u < 4 covers n <= 128 in one pass):
-            // loads first, then the stores
-            for (int i0 = kk + tx; i0 < n; i0 += 128) {
-                double a[4], l[4];
+    for (int i = threadIdx.x; i < FP_NMAX; i += blockDim.x) invd[i] = (i < n) ? 1.0 / S[i + i * FP_LD] : 0.0;
+    __syncthreads();
+    const int l = threadIdx.x & 63, sl = l & 3;
+    const int c = blockIdx.x * FP_COLS + 16 * (threadIdx.x >> 6) + (l >> 2);
+    const bool cin = c < n;
+    double x[32];
+    {
+        const int cc = min(c, n - 1);
+        double a[32], b[32];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int ii = min(i0 + 32 * u, n - 1);
-                    a[u] = S[ii + kk * ld];
-                    l[u] = S[ii + j * ld];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (i0 + 32 * u < n) S[i0 + 32 * u + kk * ld] = a[u] - l[u] * lk;
-            }
+        for (int q = 0; q < 32; ++q) {
+            const int r = min(sl + 4 * q, n - 1);
+            a[q] = second ? w.Xg[r + cc * n] : H[r + cc * n];
+            b[q] = second ? 0.0 : H[cc + r * n];
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const bool in = (sl + 4 * q < n) && cin;
+            x[q] = in ? (second ? a[q] : 0.5 * (a[q] + b[q])) : 0.0;
+        }
     }
-    return true;
-}
-
-// X <- L^{-1} X, L lower triangular in LDS (S, ld), X in registers (wave-
-// local column layout), invd[i] = 1 / L_ii.  Fully unrolled so every
-// register index is static; row i's owner scales it and a shuffle hands
-// it to the other seven lanes of its column.
-__device__ __forceinline__ void fwd_solve_reg(const double *S, int ld, int n, double (&x)[16], const double *invd) {
-    const int l = threadIdx.x & 63, g = l >> 3, cl = l & 7;
+    fwd_solve_q4(S, n, x, invd);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-#pragma unroll 1
-        for (int sidx = 0; sidx < 8; ++sidx) {
-            const int i = 8 * q + sidx;
-            if (i < n) {
-                const double own = x[q] * invd[i];
-                if (g == sidx) x[q] = own;
-                const double xi = __shfl(own, cl + 8 * sidx, 64);
-#pragma unroll
-                for (int q2 = q; q2 < 16; ++q2) {
-                    const int r = g + 8 * q2;
-                    const double lv = S[min(r, n - 1) + i * ld];
-                    x[q2] = (r > i && r < n) ? fma(-lv, xi, x[q2]) : x[q2];
-                }
-            }
+    for (int q = 0; q < 32; ++q) {
+        const int r = sl + 4 * q;
+        if (r < n && cin) {
+            if (second)
+                w.Cg[r + c * n] = x[q];
+            else
+                w.Xg[c + r * n] = x[q];
         }
     }
 }
 
-// X <- L^{-T} X, same layout.
-__device__ __forceinline__ void bwd_solve_reg(const double *S, int ld, int n, double (&x)[16], const double *invd) {
-    const int l = threadIdx.x & 63, g = l >> 3, cl = l & 7;
+// The 128 x 128 register layout of the one-workgroup factorisations: 256
+// threads (one wave per SIMD), thread t = 16 A + B holds rows A + 16 u and
+// columns B + 16 v, u, v < 8 (block (u, v) of 16 x 16, element (A, B)).
+// Column loops run as eight unrolled sweeps of sixteen columns, so the
+// blocks left of the current sweep are pruned at compile time and the
+// block of column j + 1 is a static register index.
+constexpr int RL_THREADS = 256;
+
+__device__ __forceinline__ void rl_load_sym(const double *M, int n, int A, int B, double (&m)[8][8]) {
 #pragma unroll
-    for (int q = 15; q >= 0; --q) {
-#pragma unroll 1
-        for (int sidx = 7; sidx >= 0; --sidx) {
-            const int i = 8 * q + sidx;
-            if (i < n) {
-                const double own = x[q] * invd[i];
-                if (g == sidx) x[q] = own;
-                const double xi = __shfl(own, cl + 8 * sidx, 64);
+    for (int u = 0; u < 8; ++u) {
+        double a[8], b[8];
 #pragma unroll
-                for (int q2 = 0; q2 <= q; ++q2) {
-                    const int r = g + 8 * q2;
-                    const double lv = S[i + min(r, n - 1) * ld];
-                    x[q2] = (r < i) ? fma(-lv, xi, x[q2]) : x[q2];
-                }
-            }
+        for (int v = 0; v < 8; ++v) {
+            const int r = min(A + 16 * u, n - 1), c = min(B + 16 * v, n - 1);
+            a[v] = M[r + (size_t)c * n];
+            b[v] = M[c + (size_t)r * n];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const bool in = (A + 16 * u < n) && (B + 16 * v < n);
+            m[u][v] = in ? 0.5 * (a[v] + b[v]) : 0.0;
         }
     }
 }
 
-// Householder reduction of the symmetric matrix in S (LDS, ld) to
-// tridiagonal form; reflector j is left in S rows j+1..n-1 of column j.
-__device__ void tridiag_lds(double *S, int ld, int n, double *d, double *e, double *beta,
-                            double *pv, double *red2) {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    int rb = 0;
-    for (int j = 0; j + 2 < n; ++j) {
-        const int m = n - j - 1;
-        double s = 0.0;
-        for (int i = j + 1 + t; i < n; i += SE_THREADS) s += S[i + j * ld] * S[i + j * ld];
-        s = bsum1(s, red2 + 16 * rb);
-        rb ^= 1;
-        const double x0 = S[(j + 1) + j * ld];
-        const double alpha = (s > 0.0) ? -copysign(sqrt(s), x0) : 0.0;
-        const double bt = (s > 0.0) ? 1.0 / (alpha * (alpha - x0)) : 0.0;
-        const double vj1 = x0 - alpha;
-        if (t == 0) {
-            d[j] = S[j + j * ld];
-            e[j] = (s > 0.0) ? alpha : x0;
-            beta[j] = bt;
-        }
-        if (bt == 0.0) continue;  // column already reduced; S untouched
-        // p = beta C22 v: eight lanes per row (column r of the symmetric C22),
-        // each over every eighth entry, then a 3-step shuffle sum; a wave
-        // covers 8 rows at once
-        double vp = 0.0;
-        {
-            const int rl = lane & 7, sub = lane >> 3;
-            for (int r = j + 1 + 8 * wave + rl; r - rl < n; r += 128) {
-                double a0 = 0.0, a1 = 0.0;
-                if (r < n) {
-                    int cc = j + 1 + sub;
-                    for (; cc + 8 < n; cc += 16) {
-                        const double v0 = (cc == j + 1) ? vj1 : S[cc + j * ld];
-                        const double v1 = S[cc + 8 + j * ld];
-                        a0 = fma(S[cc + r * ld], v0, a0);
-                        a1 = fma(S[cc + 8 + r * ld], v1, a1);
-                    }
-                    if (cc < n) a0 = fma(S[cc + r * ld], (cc == j + 1) ? vj1 : S[cc + j * ld], a0);
-                }
-                double acc = a0 + a1;
-                acc += __shfl_xor(acc, 8, 64);
-                acc += __shfl_xor(acc, 16, 64);
-                acc += __shfl_xor(acc, 32, 64);
-                acc *= bt;
-                if (sub == 0 && r < n) {
-                    pv[r] = acc;
-                    vp += ((r == j + 1) ? vj1 : S[r + j * ld]) * acc;
-                }
-            }
-        }
-        vp = bsum1(vp, red2 + 16 * rb);  // also publishes pv
-        rb ^= 1;
-        const double K = 0.5 * bt * vp;
-        // C22 -= v w^T + w v^T, w = p - K v, over the whole trailing block on
-        // a 32 x 32 thread grid; each entry's update is v_r w_c + w_r v_c
-        // with both products rounded separately, so entries (r, c) and (c, r)
-        // receive bit-identical updates and C22 stays exactly symmetric
-        {
-            const int tx = t & 31, ty = t >> 5;
-            for (int cc = j + 1 + ty; cc < n; cc += 32) {
-                const double vc = (cc == j + 1) ? vj1 : S[cc + j * ld];
-                // w_x = p_x - K v_x with explicit roundings, so a value is the
-                // same whether x indexes a row or a column
-                const double wc = __dsub_rn(pv[cc], __dmul_rn(K, vc));
-                // rows r = j + 1 + tx + 32 u, u < 4 (n <= 128: one pass):
-                // every load before any store
-                for (int r0 = j + 1 + tx; r0 < n; r0 += 128) {
-                    double vr[4], pr[4], a[4];
+// status[0]: 0 factorised, 1 G not positive definite (nothing else runs);
+// status[1]: rank (= n when factorised).
+__global__ __launch_bounds__(RL_THREADS) void k_fp_chol(const double *__restrict__ G, int n, FPWork w,
+                                                        int *status) {
+    __shared__ double col[2][FP_NMAX];
+    const int t = threadIdx.x, A = t >> 4, B = t & 15, lane = t & 63;
+    double m[8][8];
+    rl_load_sym(G, n, A, B, m);
+    const double dg0 = G[(size_t)min(lane, n - 1) * (n + 1)], dg1 = G[(size_t)min(lane + 64, n - 1) * (n + 1)];
+    const double floor_ = 1e-12 * wave_max_f64(fmax(lane < n ? dg0 : 0.0, lane + 64 < n ? dg1 : 0.0));
+    if (B == 0) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int r = min(r0 + 32 * u, n - 1);
-                        vr[u] = (r == j + 1) ? vj1 : S[r + j * ld];
-                        pr[u] = pv[r];
-                        a[u] = S[r + cc * ld];
-                    }
+        for (int u = 0; u < 8; ++u)
+            if (A + 16 * u < n) col[0][A + 16 * u] = m[u][0];
+    }
+    __syncthreads();
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const double wr = __dsub_rn(pr[u], __dmul_rn(K, vr[u]));
-                        const double upd = __dadd_rn(__dmul_rn(vr[u], wc), __dmul_rn(wr, vc));
-                        if (r0 + 32 * u < n) S[r0 + 32 * u + cc * ld] = a[u] - upd;
-                    }
+    for (int jv = 0; jv < 8; ++jv) {
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * jv + jj;
+            if (j >= n) break;
+            const double *cj = col[j & 1];
+            const double piv = cj[j];
+            double cr[8], cc[8];
+#pragma unroll
+            for (int u = jv; u < 8; ++u) cr[u] = cj[A + 16 * u];
+#pragma unroll
+            for (int v = jv; v < 8; ++v) cc[v] = cj[B + 16 * v];
+            if (!(piv > floor_)) {  // the same value in every thread
+                if (t == 0) {
+                    status[0] = 1;
+                    status[1] = 0;
                 }
+                return;
             }
+            const double il = rsqrt_nr(piv), lj = piv * il;
+            double lr[8], lc[8];
+#pragma unroll
+            for (int u = jv; u < 8; ++u) {
+                const int r = A + 16 * u;
+                lr[u] = (r > j && r < n) ? cr[u] * il : 0.0;
+            }
+#pragma unroll
+            for (int v = jv; v < 8; ++v) {
+                const int c = B + 16 * v;
+                lc[v] = (c > j && c < n) ? cc[v] * il : 0.0;
+            }
+#pragma unroll
+            for (int u = jv; u < 8; ++u)
+#pragma unroll
+                for (int v = jv; v < 8; ++v) m[u][v] = fma(-lr[u], lc[v], m[u][v]);
+            if (t < FP_NMAX && t < n) {
+                const double lv = cj[t];
+                w.Lg[t + j * n] = (t == j) ? lj : (t > j ? lv * il : 0.0);
+            }
+            if (j + 1 < n && B == ((j + 1) & 15)) {
+                // column j + 1 lies in block jv, or jv + 1 after the sweep's last column
+                const int vn = (jv < 7) ? jv + 1 : 7;
+#pragma unroll
+                for (int u = jv; u < 8; ++u)
+                    if (A + 16 * u < n) col[(j + 1) & 1][A + 16 * u] = (jj == 15) ? m[u][vn] : m[u][jv];
+            }
+            __syncthreads();
         }
-        if (t == 0) S[(j + 1) + j * ld] = vj1;
-        __syncthreads();
     }
     if (t == 0) {
-        if (n >= 2) {
-            d[n - 2] = S[(n - 2) + (n - 2) * ld];
-            e[n - 2] = S[(n - 1) + (n - 2) * ld];
-            beta[n - 2] = 0.0;
-        }
-        d[n - 1] = S[(n - 1) + (n - 1) * ld];
-        beta[n - 1] = 0.0;
-        e[n - 1] = 0.0;
+        status[0] = 0;
+        status[1] = n;
     }
-    __syncthreads();
 }
 
-// Eigenvector of the symmetric tridiagonal (d, e) for the isolated
-// eigenvalue lam by the twisted factorisation; pivots go to dp/dm (stride
-// `st` between consecutive k).  Writes the unit vector to z (stride 1).
-__device__ void twisted_vector(const double *d, const double *e, int n, double lam, double tiny,
-                               double *dp, double *dm, int64_t st, double *z) {
-    double q = d[0] - lam;
-    if (q == 0.0) q = tiny;
-    dp[0] = q;
-    for (int k = 1; k < n; ++k) {
-        q = (d[k] - lam) - e[k - 1] * e[k - 1] / q;
-        if (q == 0.0) q = tiny;
-        dp[(int64_t)k * st] = q;
-    }
-    q = d[n - 1] - lam;
-    if (q == 0.0) q = tiny;
-    dm[(int64_t)(n - 1) * st] = q;
-    double gbest = fabs(dp[(int64_t)(n - 1) * st]);  // gamma_{n-1} = D+_{n-1}
-    int r = n - 1;
-    for (int k = n - 2; k >= 0; --k) {
-        q = (d[k] - lam) - e[k] * e[k] / q;
-        if (q == 0.0) q = tiny;
-        dm[(int64_t)k * st] = q;
-        const double gk = fabs(dp[(int64_t)k * st] + q - (d[k] - lam));
-        if (gk < gbest) {  // first minimum from the top; ties keep the larger k
-            gbest = gk;
-            r = k;
+// Householder reduction of sym(C) to tridiagonal form with C in registers.
+// Reflector j, H = I - beta v v^T with v = x - alpha e_{j+1} (x: column j
+// below the diagonal, alpha = -sign(x_{j+1}) |x|), goes to column j of Vg;
+// the trailing block takes C22 -= v w^T + w v^T with p = beta C22 v and
+// w = p - (beta/2)(v^T p) v.  Since C22 v = C22 x - alpha C22 e_{j+1}, the
+// product y = C22 x starts right after the previous column's barrier,
+// before |x| is known, and v^T C22 v = x^T y - 2 alpha y_{j+1}
+// + alpha^2 C_{j+1,j+1}.  Per column: 64 register products and a 16-lane
+// DPP sum for y, one barrier to publish it, two wave-redundant sums
+// (|x|^2, x^T y), v and w for all rows by the first 128 threads, one
+// barrier to publish them, the register update, one barrier to publish the
+// next two columns.  Each update entry is v_r w_c + w_r v_c with both
+// products and the sum rounded separately, so entries (r, c) and (c, r)
+// stay bit-identical and C stays exactly symmetric.
+// One sweep of sixteen columns j = 16 JV .. 16 JV + 15 of the reduction
+// below (JV a template parameter, so the register blocks left of the sweep
+// are pruned and every register index is static).
+template <int JV>
+__device__ __forceinline__ void tri_sweep(double (&m)[8][8], int n, int &cur, double (*col)[FP_NMAX],
+                                          double (*col1)[FP_NMAX], double *yb, double2 *vw, double *dg,
+                                          double *eo, double *bo, double *Vg) {
+    const int t = threadIdx.x, A = t >> 4, B = t & 15, lane = t & 63;
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * JV + jj;
+        if (j + 2 >= n) return;
+        const double *cj = col[cur], *c1 = col1[cur];
+        // y = C22 x over the active blocks (x zero at rows <= j, >= n)
+        {
+            double xc[8];
+#pragma unroll
+            for (int v = JV; v < 8; ++v) {
+                const int c = B + 16 * v;
+                const double cv = cj[c];
+                xc[v] = (c > j && c < n) ? cv : 0.0;
+            }
+            double y[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) y[u] = 0.0;
+#pragma unroll
+            for (int u = JV; u < 8; ++u) {
+                double ya = m[u][JV] * xc[JV], yc = 0.0;
+#pragma unroll
+                for (int v = JV + 1; v < 8; ++v) {
+                    if ((v - JV) & 1)
+                        yc = fma(m[u][v], xc[v], yc);
+                    else
+                        ya = fma(m[u][v], xc[v], ya);
+                }
+                y[u] = ya + yc;
+            }
+            // sum over the 16 lanes B of row group A: each stage pairs
+            // lanes holding the same rows and halves what a lane carries
+            const bool h8 = (B & 8) != 0, h4 = (B & 4) != 0, h2 = (B & 2) != 0;
+            double k4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) k4[i] = (h8 ? y[4 + i] : y[i]) + dpp_f64<DPP_MIRROR>(h8 ? y[i] : y[4 + i]);
+            double k2[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                k2[i] = (h4 ? k4[2 + i] : k4[i]) + dpp_f64<DPP_HALF_MIRROR>(h4 ? k4[i] : k4[2 + i]);
+            double k1 = (h2 ? k2[1] : k2[0]) + dpp_f64<DPP_XOR2>(h2 ? k2[0] : k2[1]);
+            k1 += dpp_f64<DPP_XOR1>(k1);
+            const int prow = A + 16 * (B >> 1);  // lanes 2u, 2u + 1 hold row A + 16 u
+            if ((B & 1) == 0 && prow < n) yb[prow] = k1;
         }
+        __syncthreads();
+        // |x|^2 and x^T y, the same bits in every wave
+        const double xw0 = cj[lane], xw1 = cj[lane + 64], yw0 = yb[lane], yw1 = yb[lane + 64];
+        const bool in0 = lane > j && lane < n, in1 = lane + 64 > j && lane + 64 < n;
+        const double x0 = cj[j + 1], djj = cj[j], y1v = yb[j + 1], c11 = c1[j + 1];
+        double s = (in0 ? xw0 * xw0 : 0.0) + (in1 ? xw1 * xw1 : 0.0);
+        double q1 = (in0 ? xw0 * yw0 : 0.0) + (in1 ? xw1 * yw1 : 0.0);
+        s = wave_sum_fixed(s);
+        q1 = wave_sum_fixed(q1);
+        const bool refl = s > 0.0;
+        const double alpha = refl ? -copysign(s * rsqrt_nr(s), x0) : 0.0;
+        const double bt = refl ? rcp_nr(alpha * (alpha - x0)) : 0.0;
+        const double vj1 = x0 - alpha;
+        if (t == 0) {
+            dg[j] = djj;
+            eo[j] = refl ? alpha : x0;
+            bo[j] = bt;
+        }
+        // v_r (vj1 at row j+1, x_r below, zero elsewhere) to Vg; and
+        // p_r = beta (y_r - alpha C_{r, j+1}), w_r = p_r - K v_r to LDS
+        if (t < FP_NMAX) {
+            const double xv = cj[t], yv = yb[t], cv = c1[t];
+            const bool in = t > j && t < n;
+            const double vr = in ? ((t == j + 1) ? vj1 : xv) : 0.0;
+            if (t < n) Vg[t + j * n] = vr;
+            const double vcv = (q1 - 2.0 * alpha * y1v) + alpha * alpha * c11;
+            const double K = 0.5 * bt * (bt * vcv);
+            const double pv = in ? bt * (yv - alpha * cv) : 0.0;
+            vw[t] = make_double2(vr, pv - K * vr);
+        }
+        __syncthreads();
+        if (refl) {  // the same value in every thread
+            double vr[8], wr[8], vc[8], wc[8];
+#pragma unroll
+            for (int u = JV; u < 8; ++u) {
+                const double2 q = vw[A + 16 * u];
+                vr[u] = q.x;
+                wr[u] = q.y;
+            }
+#pragma unroll
+            for (int v = JV; v < 8; ++v) {
+                const double2 q = vw[B + 16 * v];
+                vc[v] = q.x;
+                wc[v] = q.y;
+            }
+#pragma unroll
+            for (int u = JV; u < 8; ++u)
+#pragma unroll
+                for (int v = JV; v < 8; ++v)
+                    m[u][v] = __dsub_rn(m[u][v], __dadd_rn(__dmul_rn(vr[u], wc[v]), __dmul_rn(wr[u], vc[v])));
+        }
+        // the next two columns: j + 1 in block JV (JV + 1 after the
+        // sweep's last column), j + 2 in block JV (JV + 1 from jj = 14)
+        const int nx = cur ^ 1;
+        const int vn = (JV < 7) ? JV + 1 : 7;
+        if (B == ((j + 1) & 15)) {
+#pragma unroll
+            for (int u = JV; u < 8; ++u)
+                if (A + 16 * u < n) col[nx][A + 16 * u] = (jj == 15) ? m[u][vn] : m[u][JV];
+        }
+        if (B == ((j + 2) & 15)) {
+#pragma unroll
+            for (int u = JV; u < 8; ++u)
+                if (A + 16 * u < n) col1[nx][A + 16 * u] = (jj >= 14) ? m[u][vn] : m[u][JV];
+        }
+        __syncthreads();
+        cur = nx;
     }
-    z[r] = 1.0;
-    double nn = 1.0;
-    double zk = 1.0;
-    for (int k = r - 1; k >= 0; --k) {
-        zk = -(e[k] / dp[(int64_t)k * st]) * zk;
-        z[k] = zk;
-        nn += zk * zk;
+}
+
+__global__ __launch_bounds__(RL_THREADS) void k_fp_tridiag(int n, FPWork w, const int *status) {
+    __shared__ double col[2][FP_NMAX], col1[2][FP_NMAX], yb[FP_NMAX];
+    __shared__ double2 vw[FP_NMAX];
+    if (status[0] != 0) return;
+    const int t = threadIdx.x, A = t >> 4, B = t & 15, lane = t & 63;
+    double *dg = w.tri, *eo = w.tri + n, *bo = w.tri + 2 * n;
+    double m[8][8];
+    rl_load_sym(w.Cg, n, A, B, m);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (A + 16 * u < n) {
+            if (B == 0) col[0][A + 16 * u] = m[u][0];
+            if (B == 1) col1[0][A + 16 * u] = m[u][0];
+        }
+    if (t < FP_NMAX) {
+        yb[t] = 0.0;  // rows >= n stay zero
+        vw[t] = make_double2(0.0, 0.0);
     }
-    zk = 1.0;
-    for (int k = r + 1; k < n; ++k) {
-        zk = -(e[k - 1] / dm[(int64_t)k * st]) * zk;
-        z[k] = zk;
-        nn += zk * zk;
+    __syncthreads();
+    int cur = 0;
+    tri_sweep<0>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<1>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<2>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<3>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<4>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<5>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<6>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    tri_sweep<7>(m, n, cur, col, col1, yb, vw, dg, eo, bo, w.Vg);
+    // the trailing 2 x 2 (or 1 x 1) block: col[cur] holds column
+    // max(n - 2, 0), col1[cur] the column after it
+    if (t == 0) {
+        if (n >= 2) {
+            dg[n - 2] = col[cur][n - 2];
+            eo[n - 2] = col[cur][n - 1];
+            bo[n - 2] = 0.0;
+            dg[n - 1] = col1[cur][n - 1];
+        } else {
+            dg[0] = col[cur][0];
+        }
+        eo[n - 1] = 0.0;
+        bo[n - 1] = 0.0;
     }
-    const double inv = 1.0 / sqrt(nn);
-    for (int k = 0; k < n; ++k) z[k] *= inv;
 }
 
 // Inverse iteration for the eigenvalues lam[i0..i1) of one cluster, with
@@ -994,171 +1240,200 @@ __device__ void cluster_vectors(const double *d, const double *e, int n, const d
     }
 }
 
-// status[0]: 0 solved, 1 G not positive definite (nothing written);
-// status[1]: rank (= n when solved).
-__global__ __launch_bounds__(SE_THREADS) void k_pencil_fast(const double *__restrict__ H,
-                                                            const double *__restrict__ G, int n,
-                                                            int which_smallest,
-                                                            double *__restrict__ theta,
-                                                            double *__restrict__ Y, FastWork fw,
-                                                            int *status) {
-    extern __shared__ __attribute__((aligned(16))) double smem[];
-    __shared__ double red2[32];
-    const int ld = n + 1;
-    double *S = smem;
-    double *invd = S + (size_t)n * ld;    // 1 / L_ii (128)
-    double *part = invd + 256;            // spare (2 x 8 x 128)
-    double *dd = part + 2048;             // d, e, e2, lam, beta, p: 128 each
-    double *ee = dd + 128, *e2 = ee + 128, *lam = e2 + 128, *beta = lam + 128, *pv = beta + 128;
-    const int t = threadIdx.x;
-    const int c = 8 * (t >> 6) + (t & 7), g = (t & 63) >> 3;  // wave-local column layout
-    const bool cin = c < n;
-
-    // A. Cholesky of sym(G) in LDS
-    for (int el = t; el < n * n; el += SE_THREADS) {
-        const int i = el % n, j = el / n;
-        S[i + j * ld] = 0.5 * (G[i + j * n] + G[j + i * n]);
+// Gershgorin interval of T widened by a few ulps, and the pivot floor;
+// the same values in every lane of every wave.
+__device__ void fp_gershgorin(const double *sd, const double *se, int n, double &lo, double &hi,
+                              double &pivmin) {
+    const int lane = threadIdx.x & 63;
+    double l = INFINITY, h = -INFINITY, emax = 0.0;
+    for (int k = lane; k < n; k += 64) {
+        const double off = (k > 0 ? fabs(se[k - 1]) : 0.0) + (k + 1 < n ? fabs(se[k]) : 0.0);
+        l = fmin(l, sd[k] - off);
+        h = fmax(h, sd[k] + off);
+        if (k + 1 < n) emax = fmax(emax, se[k] * se[k]);
     }
-    __syncthreads();
-    if (!chol_lds(S, ld, n)) {
-        if (t == 0) {
-            status[0] = 1;
-            status[1] = 0;
-        }
-        return;
+    for (int o = 32; o > 0; o >>= 1) {
+        l = fmin(l, __shfl_xor(l, o, 64));
+        h = fmax(h, __shfl_xor(h, o, 64));
+        emax = fmax(emax, __shfl_xor(emax, o, 64));
     }
-    // B. keep L in global memory; reciprocal pivots for the solves
-    for (int el = t; el < n * n; el += SE_THREADS) {
-        const int i = el % n, j = el / n;
-        fw.Lg[el] = (i >= j) ? S[i + j * ld] : 0.0;
-    }
-    for (int i = t; i < n; i += SE_THREADS) invd[i] = 1.0 / S[i + i * ld];
-    __syncthreads();
-    // C. X = sym(H) in registers; X <- L^{-1} X
-    double x[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        x[q] = (r < n && cin) ? 0.5 * (H[r + c * n] + H[c + r * n]) : 0.0;
-    }
-    fwd_solve_reg(S, ld, n, x, invd);
-    // D. transpose through global memory, X <- L^{-1} X^T = L^{-1} H L^{-T}
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        if (r < n && cin) fw.Tg[c + r * n] = x[q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        x[q] = (r < n && cin) ? fw.Tg[r + c * n] : 0.0;
-    }
-    fwd_solve_reg(S, ld, n, x, invd);
-    __syncthreads();
-    // E. C (symmetrised) into LDS over L
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        if (r < n && cin) S[r + c * ld] = x[q];
-    }
-    __syncthreads();
-    for (int el = t; el < n * n; el += SE_THREADS) {
-        const int i = el % n, j = el / n;
-        if (i > j) {
-            const double v = 0.5 * (S[i + j * ld] + S[j + i * ld]);
-            S[i + j * ld] = v;
-            S[j + i * ld] = v;
-        }
-    }
-    __syncthreads();
-    // F. tridiagonal T = Q^T C Q, eigenvalues by multisection
-    tridiag_lds(S, ld, n, dd, ee, beta, pv, red2);
-    for (int i = t; i < n; i += SE_THREADS) e2[i] = ee[i] * ee[i];
-    __syncthreads();
-    bisect_ptr(n, dd, ee, e2, lam);
-    // G. eigenvectors of T
-    double tn = 0.0;
-    for (int i = t; i < n; i += SE_THREADS) tn = fmax(tn, fmax(fabs(lam[i]), fabs(dd[i]) + fabs(ee[i])));
-    for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
-    if ((t & 63) == 0) red2[t >> 6] = tn;
-    __syncthreads();
-    tn = 0.0;
-    for (int i = 0; i < 16; ++i) tn = fmax(tn, red2[i]);
-    const double ortol = 1e-7 * tn;
-    const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
-    for (int i = t; i < n; i += SE_THREADS)
-        fw.cstart[i] = (i == 0 || lam[i] - lam[i - 1] > ortol) ? 1 : 0;
-    __syncthreads();
-    if (t < n) {
-        const int i = t;
-        if (fw.cstart[i]) {
-            int i1 = i + 1;
-            while (i1 < n && !fw.cstart[i1]) ++i1;
-            if (i1 == i + 1)
-                twisted_vector(dd, ee, n, lam[i], tiny, fw.dpm + i, fw.dpm + (int64_t)n * n + i, n,
-                               fw.Zt + (int64_t)i * n);
-            else
-                cluster_vectors(dd, ee, n, lam, i, i1, tiny, fw.scr + (int64_t)i * 6 * n, fw.Zt);
-        }
-    }
-    __syncthreads();
-    // H. back-transform Z = Q Z_T with Z in registers
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        x[q] = (r < n && cin) ? fw.Zt[r + c * n] : 0.0;
-    }
-    for (int j = n - 3; j >= 0; --j) {
-        const double bt = beta[j];
-        if (bt == 0.0) continue;
-        double vq[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = g + 8 * q;
-            vq[q] = (r > j && r < n) ? S[min(r, n - 1) + j * ld] : 0.0;
-        }
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q += 2) {
-            s0 = fma(vq[q], x[q], s0);
-            s1 = fma(vq[q + 1], x[q + 1], s1);
-        }
-        // sum over the eight lanes of the column (lane bits 3..5), fixed order
-        double tot = s0 + s1;
-        tot += __shfl_xor(tot, 8, 64);
-        tot += __shfl_xor(tot, 16, 64);
-        tot += __shfl_xor(tot, 32, 64);
-        tot *= bt;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) x[q] = fma(-tot, vq[q], x[q]);
-    }
-    __syncthreads();
-    // I. Y = L^{-T} Z with L back in LDS
-    for (int el = t; el < n * n; el += SE_THREADS) {
-        const int i = el % n, j = el / n;
-        S[i + j * ld] = fw.Lg[el];
-    }
-    __syncthreads();
-    bwd_solve_reg(S, ld, n, x, invd);
-    // J. order: lam is ascending
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int r = g + 8 * q;
-        if (r < n && cin) {
-            const int pos = which_smallest ? c : n - 1 - c;
-            Y[r + (int64_t)pos * n] = x[q];
-        }
-    }
-    for (int i = t; i < n; i += SE_THREADS) theta[which_smallest ? i : n - 1 - i] = lam[i];
-    if (t == 0) {
-        status[0] = 0;
-        status[1] = n;
-    }
+    const double tnorm = fmax(fabs(l), fabs(h));
+    pivmin = 0x1.0p-1000 * fmax(1.0, emax);
+    lo = l - (4.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin);
+    hi = h + (4.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin);
 }
 
-constexpr size_t fast_lds_bytes(int n) {
-    return ((size_t)n * (n + 1) + 256 + 2048 + 6 * 128) * sizeof(double);
+__global__ __launch_bounds__(64 * FP_WAVES) void k_fp_bisect(int n, FPWork w, const int *status) {
+    __shared__ double sd[FP_NMAX], se[FP_NMAX], se2[FP_NMAX];
+    if (status[0] != 0) return;
+    const int t = threadIdx.x, lane = t & 63;
+    for (int k = t; k < n; k += blockDim.x) {
+        sd[k] = w.tri[k];
+        se[k] = w.tri[n + k];
+        se2[k] = w.tri[n + k] * w.tri[n + k];
+    }
+    __syncthreads();
+    double lo, hi, pivmin;
+    fp_gershgorin(sd, se, n, lo, hi, pivmin);
+    const int idx = blockIdx.x * FP_WAVES + (t >> 6);  // eigenvalue of this wave (ascending)
+    if (idx >= n) return;
+    double lo_ = lo, hi_ = hi;
+    for (int it = 0; it < 10; ++it) {  // 6 bits each: 60 bits of the Gershgorin interval
+        const double x = lo_ + (hi_ - lo_) * (double)(lane + 1) * 0.015625;
+        const int c = (lane < 63) ? sturm_count(sd, se2, n, x, pivmin) : 0;
+        const unsigned long long bal = __ballot(lane < 63 && c > idx);
+        // first probe with more than idx eigenvalues below it
+        const int s = bal ? __builtin_ctzll(bal) : 63;
+        const double na = (s == 0) ? lo_ : lo_ + (hi_ - lo_) * (double)s * 0.015625;
+        const double nb = (s == 63) ? hi_ : lo_ + (hi_ - lo_) * (double)(s + 1) * 0.015625;
+        lo_ = na;
+        hi_ = nb;
+    }
+    if (lane == 0) w.tri[3 * n + idx] = 0.5 * (lo_ + hi_);
+}
+
+__global__ __launch_bounds__(64 * FP_WAVES) void k_fp_vectors(int n, FPWork w, const int *status) {
+    __shared__ double sd[FP_NMAX], se[FP_NMAX], sl[FP_NMAX];
+    __shared__ double dpm[FP_WAVES][2][FP_NMAX], zz[FP_WAVES][FP_NMAX];
+    if (status[0] != 0) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int k = t; k < n; k += blockDim.x) {
+        sd[k] = w.tri[k];
+        se[k] = w.tri[n + k];
+        sl[k] = w.tri[3 * n + k];
+    }
+    __syncthreads();
+    double tn = 0.0;
+    for (int k = lane; k < n; k += 64) tn = fmax(tn, fmax(fabs(sl[k]), fabs(sd[k]) + fabs(se[k])));
+    tn = wave_max_f64(tn);
+    const double ortol = 1e-7 * tn;
+    const double tiny = 2.220446049250313e-16 * fmax(tn, 1e-300);
+    const int i = blockIdx.x * FP_WAVES + wv;
+    if (i >= n) return;
+    if (i > 0 && !(sl[i] - sl[i - 1] > ortol)) return;  // inside a cluster: its first wave
+    int i1 = i + 1;
+    while (i1 < n && !(sl[i1] - sl[i1 - 1] > ortol)) ++i1;
+    if (i1 > i + 1) {
+        if (lane == 0) cluster_vectors(sd, se, n, sl, i, i1, tiny, w.scr + (size_t)i * 6 * n, w.Zt);
+        return;
+    }
+    const double lm = sl[i];
+    double *Dp = dpm[wv][0], *Dm = dpm[wv][1], *z = zz[wv];
+    // lane 0: forward pivots D+, lane 1: backward pivots D-, the same
+    // instruction stream with mirrored indices
+    if (lane < 2) {
+        const bool fw = lane == 0;
+        double *dst = fw ? Dp : Dm;
+        int k = fw ? 0 : n - 1;
+        double q = sd[k] - lm;
+        if (q == 0.0) q = tiny;
+        dst[k] = q;
+        for (int s = 1; s < n; ++s) {
+            k = fw ? s : n - 1 - s;
+            const double ec = fw ? se[k - 1] : se[k];
+            q = (sd[k] - lm) - ec * ec / q;
+            if (q == 0.0) q = tiny;
+            dst[k] = q;
+        }
+    }
+    wave_lds_sync();
+    // twist r = argmin gamma_k (ties: the larger k), gamma_{n-1} = D+_{n-1}
+    double gb = INFINITY;
+    int rb = -1;
+    for (int k = lane; k < n; k += 64) {
+        double gk = (k == n - 1) ? fabs(Dp[k]) : fabs(Dp[k] + Dm[k] - (sd[k] - lm));
+        if (!(gk == gk)) gk = INFINITY;
+        if (gk < gb || (gk == gb && k > rb)) {
+            gb = gk;
+            rb = k;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double og = __shfl_xor(gb, o, 64);
+        const int orr = __shfl_xor(rb, o, 64);
+        if (og < gb || (og == gb && orr > rb)) {
+            gb = og;
+            rb = orr;
+        }
+    }
+    const int r = rb < 0 ? n - 1 : rb;
+    // one-term recurrences away from r: factors first (independent), then
+    // the two products on lanes 0 (downwards) and 1 (upwards)
+    for (int k = lane; k < n; k += 64) z[k] = (k < r) ? -(se[k] / Dp[k]) : ((k > r) ? -(se[k - 1] / Dm[k]) : 1.0);
+    wave_lds_sync();
+    if (lane < 2) {
+        const bool dn = lane == 0;
+        const int cnt = dn ? r : n - 1 - r;
+        int k = dn ? r - 1 : r + 1;
+        double zk = 1.0;
+        for (int s = 0; s < cnt; ++s) {
+            zk = z[k] * zk;
+            z[k] = zk;
+            k += dn ? -1 : 1;
+        }
+    }
+    wave_lds_sync();
+    double nn = 0.0;
+    for (int k = lane; k < n; k += 64) nn += z[k] * z[k];
+    nn = wave_sum_f64(nn);
+    const double inv = 1.0 / sqrt(nn);
+    for (int k = lane; k < n; k += 64) w.Zt[k + (size_t)i * n] = z[k] * inv;
+}
+
+__global__ __launch_bounds__(4 * FP_COLS) void k_fp_back(int n, int which_smallest, FPWork w,
+                                                         double *__restrict__ theta, double *__restrict__ Y,
+                                                         const int *status) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    if (status[0] != 0) return;
+    double *S = smem, *aux = S + FP_NMAX * FP_LD;
+    fp_load_padded(w.Vg, n, S);
+    for (int k = threadIdx.x; k < FP_NMAX; k += blockDim.x) aux[k] = (k < n) ? w.tri[2 * n + k] : 0.0;
+    __syncthreads();
+    const int l = threadIdx.x & 63, sl = l & 3;
+    const int c = blockIdx.x * FP_COLS + 16 * (threadIdx.x >> 6) + (l >> 2);
+    const bool cin = c < n;
+    double x[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) x[q] = w.Zt[min(sl + 4 * q, n - 1) + (size_t)min(c, n - 1) * n];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) x[q] = (sl + 4 * q < n && cin) ? x[q] : 0.0;
+    // Z = H_0 H_1 ... H_{n-3} Z_T, the last reflector first; reflector
+    // entries above row j + 1 and beyond n are stored zeros
+    for (int j = n - 3; j >= 0; --j) {
+        const double bt = aux[j];
+        if (bt == 0.0) continue;
+        double vq[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) vq[q] = S[sl + 4 * q + j * FP_LD];
+        double sa[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sa[k] = vq[k] * x[k];
+#pragma unroll
+        for (int q = 8; q < 32; ++q) sa[q & 7] = fma(vq[q], x[q], sa[q & 7]);
+        // over the four lanes of the column, the same bits in all four
+        double tot = ((sa[0] + sa[1]) + (sa[2] + sa[3])) + ((sa[4] + sa[5]) + (sa[6] + sa[7]));
+        tot += dpp_f64<DPP_XOR1>(tot);
+        tot += dpp_f64<DPP_XOR2>(tot);
+        tot *= bt;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) x[q] = fma(-tot, vq[q], x[q]);
+    }
+    __syncthreads();
+    fp_load_padded(w.Lg, n, S);
+    __syncthreads();
+    for (int i = threadIdx.x; i < FP_NMAX; i += blockDim.x) aux[i] = (i < n) ? 1.0 / S[i + i * FP_LD] : 0.0;
+    __syncthreads();
+    bwd_solve_q4(S, n, x, aux);
+    // eigenvalues ascending: column c of the result goes to position c
+    // (smallest first) or n - 1 - c (largest first)
+    const int pos = which_smallest ? c : n - 1 - c;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int r = sl + 4 * q;
+        if (r < n && cin) Y[r + (size_t)pos * n] = x[q];
+    }
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < n; k += blockDim.x) theta[which_smallest ? k : n - 1 - k] = w.tri[3 * n + k];
 }
 
 PencilWork make_work(Context *ctx, int n) {
@@ -1197,21 +1472,33 @@ int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, of
         // fast path; falls through to the general kernel when G is not
         // positive definite
         const size_t nn = (size_t)b * b;
-        double *base = ctx->buf<double>("pencil_fast", 11 * nn + 8);
-        FastWork fw;
+        double *base = ctx->buf<double>("pencil_fast", 5 * nn + 4 * (size_t)b + 6 * nn + 8);
+        FPWork fw;
         fw.Lg = base;
-        fw.Tg = base + nn;
-        fw.Zt = base + 2 * nn;
-        fw.dpm = base + 3 * nn;
-        fw.scr = base + 5 * nn;
-        fw.cstart = ctx->buf<int>("pencil_fast_i", (size_t)b + 8);
-        const size_t shmem = fast_lds_bytes(b);
-        OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_fast,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        fw.Xg = base + nn;
+        fw.Cg = base + 2 * nn;
+        fw.Vg = base + 3 * nn;
+        fw.Zt = base + 4 * nn;
+        fw.tri = base + 5 * nn;
+        fw.scr = fw.tri + 4 * b;
+        const size_t shmem = fp_lds_bytes();
+        OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shmem));
+        OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_back, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shmem));
+        const int ncb = (b + FP_COLS - 1) / FP_COLS, nwb = (b + FP_WAVES - 1) / FP_WAVES;
         {
             KTimer tm(ctx, "small_eig");
-            hipLaunchKernelGGL(k_pencil_fast, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b,
-                               which == OFRR_SMALLEST ? 1 : 0, theta, Y, fw, status);
+            hipLaunchKernelGGL(k_fp_chol, dim3(1), dim3(RL_THREADS), 0, ctx->stream, G, b, fw, status);
+            hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 0, fw,
+                               status);
+            hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 1, fw,
+                               status);
+            hipLaunchKernelGGL(k_fp_tridiag, dim3(1), dim3(RL_THREADS), 0, ctx->stream, b, fw, status);
+            hipLaunchKernelGGL(k_fp_bisect, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
+            hipLaunchKernelGGL(k_fp_vectors, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
+            hipLaunchKernelGGL(k_fp_back, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, b,
+                               which == OFRR_SMALLEST ? 1 : 0, fw, theta, Y, status);
             OFRR_HIP(hipGetLastError());
         }
         int host[2] = {1, 0};

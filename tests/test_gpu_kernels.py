@@ -279,6 +279,27 @@ def test_pencil_eig(ctx, b):
     np.testing.assert_allclose(H @ Y, G @ Y * theta, atol=1e-9 * scale * np.abs(Y).max())
 
 
+@pytest.mark.parametrize("b,which", [(33, "smallest"), (100, "largest"), (128, "smallest")])
+def test_pencil_eig_repeated_eigenvalues(ctx, b, which):
+    """H = M^T D M, G = M^T M: the pencil's eigenvalues are D's, here with
+    multiplicities up to four, so the cluster branch of the eigenvector step
+    runs; Y must still be G-orthonormal with a small residual."""
+    rng = np.random.default_rng(11 + b)
+    M = rng.standard_normal((b, b)) + 4.0 * np.eye(b)
+    lam = np.repeat(np.linspace(-1.0, 2.0, (b + 3) // 4), 4)[:b]
+    H, G = M.T @ (lam[:, None] * M), M.T @ M
+    print("pencil repeated", b, which, flush=True)
+    theta, Y, rank = ctx.pencil_eig(_cuda(H), _cuda(G), which)
+    theta, Y = theta.cpu().numpy(), Y.cpu().numpy()
+    t_ref, _ = O.sym_pencil_eig(H, G)
+    t_ref = t_ref if which == "smallest" else t_ref[::-1]
+    assert rank == b
+    np.testing.assert_allclose(np.sort(lam)[:: 1 if which == "smallest" else -1], t_ref, atol=1e-9)
+    np.testing.assert_allclose(theta, t_ref, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(Y.T @ G @ Y, np.eye(b), atol=1e-9)
+    np.testing.assert_allclose(H @ Y, G @ Y * theta, atol=1e-8 * np.abs(G @ Y).max())
+
+
 def test_pencil_eig_indefinite_mass_falls_back(ctx):
     rng = np.random.default_rng(10)
     A = rng.standard_normal((200, 200))
