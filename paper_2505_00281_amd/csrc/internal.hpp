@@ -215,6 +215,11 @@ void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, c
 // Pencil H y = theta G y; returns rank of G used.
 int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
                    double *theta, double *Y, bool want_rank);
+// The same solve with no host synchronisation: returns a device pointer
+// that holds the rank once the stream reaches it.  theta and the columns of
+// Y beyond the rank come out zero.
+const int32_t *pencil_eig_async(Context *ctx, int32_t b, const double *H, const double *G,
+                                ofrr_which which, double *theta, double *Y);
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,
                 const double *MV, double *sigma, double *Y, double *Z);
 

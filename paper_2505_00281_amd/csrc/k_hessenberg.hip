@@ -30,6 +30,9 @@
 // the sweep; column j uses tag j + 1.
 // Each update is one fused multiply-add, as in the reference process.
 #include <cstdlib>
+#include <map>
+#include <tuple>
+#include <utility>
 
 #include "internal.hpp"
 #include "device_util.hpp"
@@ -129,8 +132,8 @@ __device__ __forceinline__ bool get_value(const uint64_t *src, uint32_t tag, V &
     return ok;
 }
 
-template <class T, bool RESIDENT>
-__global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t ldy, int64_t n,
+template <class T, bool RESIDENT, int NT>
+__global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ldy, int64_t n,
                                                     int b, double tol, int32_t *__restrict__ piv,
                                                     int32_t *__restrict__ keep, int64_t rows_per,
                                                     uint64_t *__restrict__ slot_rows,
@@ -142,8 +145,9 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     constexpr int CW = NWords<M>::value + 1;  // words per candidate (magnitude, row)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ T w_sh[512];  // multipliers of the current column (b <= 512)
-    __shared__ M red_m[4];
-    __shared__ int red_i[4], red_g[4];
+    constexpr int NW = NT / 64;
+    __shared__ M red_m[NW];
+    __shared__ int red_i[NW], red_g[NW];
     __shared__ int s_win_idx, s_win_g;
     __shared__ M s_win_mag;
 
@@ -161,23 +165,23 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
     };
 
     if (RESIDENT) {
-        for (int64_t e = t; e < nrows * b; e += 256) {
+        for (int64_t e = t; e < nrows * b; e += NT) {
             const int64_t rr = e / b, c = e - rr * b;
             rows[(int64_t)c * rows_per + rr] = Y[(r0 + rr) * ldy + c];
         }
         __syncthreads();
     }
-    // elimination mapping: tpr threads per row (so that all 256 threads work
-    // when the slice has fewer than 256 rows), each taking every tpr-th
+    // elimination mapping: tpr threads per row (so that all NT threads work
+    // when the slice has fewer than NT rows), each taking every tpr-th
     // trailing column
     int tpr = 1;
-    while (tpr < 16 && nrows * tpr * 2 <= 256) tpr *= 2;
-    const int sub = t % tpr, rstep = 256 / tpr;
+    while (tpr < 16 && nrows * tpr * 2 <= NT) tpr *= 2;
+    const int sub = t % tpr, rstep = NT / tpr;
 
     auto local_argmax = [&](int col, M &bm, int &bi) {
         bm = (M)-1;
         bi = 0x7fffffff;
-        for (int64_t rr = t; rr < nrows; rr += 256) {
+        for (int64_t rr = t; rr < nrows; rr += NT) {
             const M v = (M)fabs((double)at(rr, col));
             if (v > bm) {  // rows visited in increasing order per thread
                 bm = v;
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         __syncthreads();
         bm = red_m[0];
         bi = red_i[0];
-        for (int w = 1; w < 4; ++w)
+        for (int w = 1; w < NW; ++w)
             if (red_m[w] > bm || (red_m[w] == bm && red_i[w] < bi)) {
                 bm = red_m[w];
                 bi = red_i[w];
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         uint64_t *my_row = slot_rows + ((int64_t)bufp * G + g) * b * TW;
         if (ci != 0x7fffffff) {
             const int64_t rr = ci - r0;
-            for (int c = jj + t; c < b; c += 256) put_value<T>(my_row + (int64_t)c * TW, at(rr, c), tagp);
+            for (int c = jj + t; c < b; c += NT) put_value<T>(my_row + (int64_t)c * TW, at(rr, c), tagp);
         }
         if (t == 0) {
             uint64_t *my_cand = slot_cand + ((int64_t)bufp * G + g) * CW;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
             int ok = 1;
-            for (int h = t; h < G; h += 256) {
+            for (int h = t; h < G; h += NT) {
                 const uint64_t *cand = slot_cand + ((int64_t)buf * G + h) * CW;
                 uint32_t cw[CW];
                 if (!get_words<CW>(cand, tag, cw, err)) {
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             if (t == 0) {
                 M m = red_m[0];
                 int i = red_i[0], gg = red_g[0];
-                for (int w = 1; w < 4; ++w)
+                for (int w = 1; w < NW; ++w)
                     if (red_m[w] > m || (red_m[w] == m && red_i[w] < i)) {
                         m = red_m[w];
                         i = red_i[w];
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
         {
             const uint64_t *win_row = slot_rows + ((int64_t)buf * G + wg) * b * TW;
             int ok = 1;
-            for (int c = j + t; c < b; c += 256) {
+            for (int c = j + t; c < b; c += NT) {
                 T v;
                 if (!get_value<T>(win_row + (int64_t)c * TW, tag, v, err)) {
                     ok = 0;
@@ -342,7 +346,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
             if (ci != 0x7fffffff) {
                 const int64_t rr = ci - r0;
                 const T q = at(rr, j) / pivot;
-                for (int c = j + 2 + t; c < b; c += 256) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
+                for (int c = j + 2 + t; c < b; c += NT) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
             }
             __syncthreads();
             publish(j + 1);
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(256) void k_hessenberg(T *__restrict__ Y, int64_t l
 
     if (RESIDENT) {
         __syncthreads();
-        for (int64_t e = t; e < nrows * b; e += 256) {
+        for (int64_t e = t; e < nrows * b; e += NT) {
             const int64_t rr = e / b, c = e - rr * b;
             Y[(r0 + rr) * ldy + c] = rows[(int64_t)c * rows_per + rr];
         }
@@ -440,17 +444,41 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
                        ctx->stream, words, nwords);
     OFRR_HIP(hipGetLastError());
 
-    auto kern = resident ? (void *)k_hessenberg<T, true> : (void *)k_hessenberg<T, false>;
-    if (shmem > 0) OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-    int per_cu = 0;
-    OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, shmem));
+    // workgroup size (OFRR_HESS_THREADS overrides, for tuning sweeps)
+    int nt = 256;
+    if (const char *s = std::getenv("OFRR_HESS_THREADS")) {
+        const long v = std::strtol(s, nullptr, 10);
+        if (v == 256 || v == 512 || v == 1024) nt = (int)v;
+    }
+    void *kern = nullptr;
+    if (nt == 256) kern = resident ? (void *)k_hessenberg<T, true, 256> : (void *)k_hessenberg<T, false, 256>;
+    else if (nt == 512) kern = resident ? (void *)k_hessenberg<T, true, 512> : (void *)k_hessenberg<T, false, 512>;
+    else kern = resident ? (void *)k_hessenberg<T, true, 1024> : (void *)k_hessenberg<T, false, 1024>;
+    // the dynamic-LDS limit and the occupancy answer depend only on the
+    // kernel variant, its LDS size and the device: asked once, then reused
+    // (the sweep runs every iteration)
+    static std::map<std::tuple<int, const void *, size_t>, int> occ;
+    static std::map<std::pair<int, const void *>, size_t> lds_set;
+    const auto key = std::make_tuple(ctx->device, (const void *)kern, shmem);
+    auto it = occ.find(key);
+    if (it == occ.end()) {
+        size_t &cur = lds_set[std::make_pair(ctx->device, (const void *)kern)];
+        if (shmem > cur) {  // the limit only ever grows
+            OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+            cur = shmem;
+        }
+        int pc = 0;
+        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, nt, shmem));
+        it = occ.emplace(key, pc).first;
+    }
+    const int per_cu = it->second;
     if ((int64_t)per_cu * cus < G)
         fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &rows_per, &slot_rows, &slot_cand, &err,
                     &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
-        OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(256), args, (unsigned)shmem, ctx->stream));
+        OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(nt), args, (unsigned)shmem, ctx->stream));
     }
     int32_t host[2] = {0, 0};
     OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));

@@ -25,6 +25,8 @@
 //      three solves), with modified Gram-Schmidt inside clusters of nearly
 //      equal eigenvalues so degenerate pairs stay independent.
 //   4. Z = Q Z_T by applying the reflectors in reverse order.
+#include <set>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -498,10 +500,13 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
                                                        const double *__restrict__ G, int n,
                                                        int which_smallest, double *__restrict__ theta,
                                                        double *__restrict__ Y, PencilWork w,
-                                                       int *status, int use_lds) {
+                                                       int *status, int use_lds, int skip_if_done) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     __shared__ double red[16];
     const int t = threadIdx.x, T = blockDim.x;
+    // after the fast path: nothing to do when it factorised G
+    if (skip_if_done && status[0] == 0) return;
+    __syncthreads();
     double *C = use_lds ? smem : w.C;
     for (int e = t; e < n * n; e += T) {
         const int i = e % n, j = e / n;
@@ -600,7 +605,10 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
         const int row = e % n, c = e / n;
         Y[e] = (c < rank) ? w.Z[row + w.ord[c] * n] : 0.0;
     }
-    if (t == 0) w.flag[1] = rank;
+    if (t == 0) {
+        w.flag[1] = rank;
+        status[1] = rank;
+    }
 }
 
 __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restrict__ B, int k1,
@@ -1462,15 +1470,36 @@ PencilWork make_work(Context *ctx, int n) {
     return w;
 }
 
+// Dynamic-LDS limits are per kernel and device; raising them once per
+// device to the largest size the launches below ask for keeps the attribute
+// calls off the per-iteration path.
+void pencil_attributes(Context *ctx) {
+    static std::set<int> done;
+    if (done.count(ctx->device)) return;
+    OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)fp_lds_bytes()));
+    OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_back, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)fp_lds_bytes()));
+    OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
+    done.insert(ctx->device);
+}
+
 }  // namespace
 
-int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
-                   double *theta, double *Y, bool want_rank) {
+const int32_t *pencil_eig_async(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
+                                double *theta, double *Y) {
     OFRR_CHECK_ARG(b >= 1 && b <= 1024, "pencil: 1 <= b <= 1024");
+    pencil_attributes(ctx);
     int *status = ctx->buf<int>("pencil_status", 4);
+    const int ws = which == OFRR_SMALLEST ? 1 : 0;
+    PencilWork w = make_work(ctx, b + 1);
+    const int use_lds = b <= SE_LDS_MAX_N ? 1 : 0;
+    const size_t gshmem = use_lds ? (size_t)b * b * sizeof(double) : 0;
+    KTimer tm(ctx, "small_eig");
     if (b <= FP_NMAX) {
-        // fast path; falls through to the general kernel when G is not
-        // positive definite
+        // fast path; the general kernel behind it returns at once unless G
+        // was not positive definite
         const size_t nn = (size_t)b * b;
         double *base = ctx->buf<double>("pencil_fast", 5 * nn + 4 * (size_t)b + 6 * nn + 8);
         FPWork fw;
@@ -1482,49 +1511,34 @@ int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, of
         fw.tri = base + 5 * nn;
         fw.scr = fw.tri + 4 * b;
         const size_t shmem = fp_lds_bytes();
-        OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)shmem));
-        OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_back, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)shmem));
         const int ncb = (b + FP_COLS - 1) / FP_COLS, nwb = (b + FP_WAVES - 1) / FP_WAVES;
-        {
-            KTimer tm(ctx, "small_eig");
-            hipLaunchKernelGGL(k_fp_chol, dim3(1), dim3(RL_THREADS), 0, ctx->stream, G, b, fw, status);
-            hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 0, fw,
-                               status);
-            hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 1, fw,
-                               status);
-            hipLaunchKernelGGL(k_fp_tridiag, dim3(1), dim3(RL_THREADS), 0, ctx->stream, b, fw, status);
-            hipLaunchKernelGGL(k_fp_bisect, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
-            hipLaunchKernelGGL(k_fp_vectors, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
-            hipLaunchKernelGGL(k_fp_back, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, b,
-                               which == OFRR_SMALLEST ? 1 : 0, fw, theta, Y, status);
-            OFRR_HIP(hipGetLastError());
-        }
-        int host[2] = {1, 0};
-        OFRR_HIP(hipMemcpyAsync(host, status, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        ctx->sync();
-        if (host[0] == 0) return host[1];
+        hipLaunchKernelGGL(k_fp_chol, dim3(1), dim3(RL_THREADS), 0, ctx->stream, G, b, fw, status);
+        hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 0, fw, status);
+        hipLaunchKernelGGL(k_fp_solve, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, H, b, 1, fw, status);
+        hipLaunchKernelGGL(k_fp_tridiag, dim3(1), dim3(RL_THREADS), 0, ctx->stream, b, fw, status);
+        hipLaunchKernelGGL(k_fp_bisect, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
+        hipLaunchKernelGGL(k_fp_vectors, dim3(nwb), dim3(64 * FP_WAVES), 0, ctx->stream, b, fw, status);
+        hipLaunchKernelGGL(k_fp_back, dim3(ncb), dim3(4 * FP_COLS), shmem, ctx->stream, b, ws, fw, theta, Y,
+                           status);
+        hipLaunchKernelGGL(k_pencil, dim3(1), dim3(SE_THREADS), gshmem, ctx->stream, H, G, b, ws, theta, Y, w,
+                           status, use_lds, 1);
+    } else {
+        zero_bytes(ctx, status, 16);
+        hipLaunchKernelGGL(k_pencil, dim3(1), dim3(SE_THREADS), gshmem, ctx->stream, H, G, b, ws, theta, Y, w,
+                           status, use_lds, 0);
     }
-    PencilWork w = make_work(ctx, b + 1);
-    zero_bytes(ctx, status, 16);
-    const int use_lds = b <= SE_LDS_MAX_N ? 1 : 0;
-    const size_t shmem = use_lds ? (size_t)b * b * sizeof(double) : 0;
-    if (shmem > 0)
-        OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)shmem));
-    {
-        KTimer tm(ctx, "small_eig");
-        hipLaunchKernelGGL(k_pencil, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b,
-                           which == OFRR_SMALLEST ? 1 : 0, theta, Y, w, status, use_lds);
-        OFRR_HIP(hipGetLastError());
-    }
-    int host[2] = {0, 0};
-    OFRR_HIP(hipMemcpyAsync(&host[0], status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    OFRR_HIP(hipMemcpyAsync(&host[1], w.flag + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
+    OFRR_HIP(hipGetLastError());
+    return status + 1;
+}
+
+int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, ofrr_which which,
+                   double *theta, double *Y, bool want_rank) {
     (void)want_rank;
-    return host[1];
+    const int32_t *rank = pencil_eig_async(ctx, b, H, G, which, theta, Y);
+    int32_t host = 0;
+    OFRR_HIP(hipMemcpyAsync(&host, rank, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    return host;
 }
 
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,

@@ -276,27 +276,31 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // ---- project
         run.product(ph, V, W, bc);
         project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
-        // ---- solve
-        const int32_t rank = pencil_eig(ctx, bc, H, G, which, theta, Yr, true);
-        if (rank < k) fail(OFRR_ERR_NUMERIC, "projected mass matrix lost rank below k");
+        // ---- solve; the rank comes back with the residual estimates (one
+        // host synchronisation per iteration): every column is lifted, those
+        // beyond the rank are zero and the next sweep drops them
+        const int32_t *rank_dev = pencil_eig_async(ctx, bc, H, G, which, theta, Yr);
         // ---- lift (X = V Y, AX = W Y) with residual estimates
-        lift(ctx, n, bc, rank, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
+        lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
         ++iters;
         if (!ph.f64()) ++iters_low;
         have_ax = true;
-        bc = rank;
         // residual estimates of the k wanted pairs
         if (plan->anorm <= 0) {
-            std::vector<double> th((size_t)rank);
-            OFRR_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * rank, hipMemcpyDeviceToHost, ctx->stream));
+            std::vector<double> th((size_t)bc);
+            OFRR_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * bc, hipMemcpyDeviceToHost, ctx->stream));
             ctx->sync();
             double m = 0.0;
             for (double v : th) m = std::max(m, std::fabs(v));
             anorm_used = m > 0 ? m : 1.0;
         }
-        residual_reduce(ctx, res2, xn2, (int)nblk, rank, k, anorm_used, rest);
+        residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest);
+        int32_t rank = 0;
         OFRR_HIP(hipMemcpyAsync(est.data(), rest, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+        OFRR_HIP(hipMemcpyAsync(&rank, rank_dev, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
         ctx->sync();
+        if (rank < k) fail(OFRR_ERR_NUMERIC, "projected mass matrix lost rank below k");
+        bc = rank;
         double emax = 0.0;
         for (double v : est) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
         if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "non-finite residual estimate");
