@@ -144,7 +144,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
     constexpr int TW = NWords<T>::value;      // words per row entry
     constexpr int CW = NWords<M>::value + 1;  // words per candidate (magnitude, row)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    __shared__ T w_sh[512];  // multipliers of the current column (b <= 512)
+    __shared__ __attribute__((aligned(16))) T w_sh[512];  // multipliers of the current column (b <= 512)
     constexpr int NW = NT / 64;
     __shared__ M red_m[NW];
     __shared__ int red_i[NW], red_g[NW];
@@ -156,21 +156,25 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
     const int64_t r0 = (int64_t)g * rows_per;
     const int64_t r1 = (r0 + rows_per < n) ? r0 + rows_per : n;
     const int64_t nrows = r1 > r0 ? r1 - r0 : 0;
-    // element (rr, c) of the slice: column-major in LDS (consecutive rows
-    // of one column are consecutive words, so a thread-per-row pass is free
-    // of bank conflicts), row-major in place otherwise
+    // element (rr, c) of the slice: row-major in both cases; in LDS each row
+    // is padded to a whole number of 16-byte chunks plus one more, so that a
+    // thread-per-row pass reading 16 bytes per lane touches every bank once
+    // per eight lanes (row stride = 4 banks modulo 32)
+    constexpr int VEC = 16 / (int)sizeof(T);
+    const int ldr = RESIDENT ? ((b + VEC - 1) / VEC + 1) * VEC : 0;
     T *rows = RESIDENT ? reinterpret_cast<T *>(smem_raw) : Y + r0 * ldy;
-    auto at = [&](int64_t rr, int c) -> T & {
-        return RESIDENT ? rows[(int64_t)c * rows_per + rr] : rows[rr * ldy + c];
-    };
+    auto at = [&](int64_t rr, int c) -> T & { return RESIDENT ? rows[rr * ldr + c] : rows[rr * ldy + c]; };
 
     if (RESIDENT) {
         for (int64_t e = t; e < nrows * b; e += NT) {
             const int64_t rr = e / b, c = e - rr * b;
-            rows[(int64_t)c * rows_per + rr] = Y[(r0 + rr) * ldy + c];
+            rows[rr * ldr + c] = Y[(r0 + rr) * ldy + c];
         }
-        __syncthreads();
     }
+    // multipliers beyond column b stay zero (the vector pass below runs over
+    // whole chunks)
+    for (int c = b + t; c < 512; c += NT) w_sh[c] = (T)0;
+    __syncthreads();
     // elimination mapping: tpr threads per row (so that all NT threads work
     // when the slice has fewer than NT rows), each taking every tpr-th
     // trailing column
@@ -355,7 +359,37 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
         // multipliers into column j
         for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
             const T q = at(rr, j) / pivot;
-            if (r0 + rr != ci) {
+            if (RESIDENT && r0 + rr != ci) {
+                // scalar head up to a chunk boundary, then 16-byte chunks
+                // (chunk u of the row to sub-thread u % tpr)
+                const int ca = (j + 2 + VEC - 1) / VEC * VEC;
+                if (sub == 0)
+                    for (int c = j + 2; c < ca && c < b; ++c) at(rr, c) = fma(-w_sh[c], q, at(rr, c));
+                typedef T vec_t __attribute__((ext_vector_type(VEC)));
+                T *row = &at(rr, 0);
+                int c = ca + sub * VEC;
+                for (; c + 3 * tpr * VEC < b; c += 4 * tpr * VEC) {
+                    vec_t y[4], w[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        y[u] = *reinterpret_cast<const vec_t *>(row + c + u * tpr * VEC);
+                        w[u] = *reinterpret_cast<const vec_t *>(w_sh + c + u * tpr * VEC);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) y[u][e] = fma(-w[u][e], q, y[u][e]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) *reinterpret_cast<vec_t *>(row + c + u * tpr * VEC) = y[u];
+                }
+                for (; c < b; c += tpr * VEC) {
+                    vec_t y = *reinterpret_cast<const vec_t *>(row + c);
+                    const vec_t w = *reinterpret_cast<const vec_t *>(w_sh + c);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) y[e] = fma(-w[e], q, y[e]);
+                    *reinterpret_cast<vec_t *>(row + c) = y;
+                }
+            } else if (r0 + rr != ci) {
                 int c = j + 2 + sub;
                 for (; c + 7 * tpr < b; c += 8 * tpr) {
                     T y[8], w[8];
@@ -382,7 +416,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
         __syncthreads();
         for (int64_t e = t; e < nrows * b; e += NT) {
             const int64_t rr = e / b, c = e - rr * b;
-            Y[(r0 + rr) * ldy + c] = rows[(int64_t)c * rows_per + rr];
+            Y[(r0 + rr) * ldy + c] = rows[rr * ldr + c];
         }
     }
     if (g == 0 && t == 0 && kept_out) *kept_out = kept;
@@ -413,7 +447,9 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         if (kb >= 8 && kb <= 150) lds_budget = (size_t)kb * 1024;
     }
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    int64_t rows_res = (int64_t)(lds_budget / ((size_t)b * sizeof(T)));
+    const int vec = 16 / (int)sizeof(T);
+    const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS
+    int64_t rows_res = (int64_t)(lds_budget / ((size_t)ldr * sizeof(T)));
     bool resident = false;
     int64_t rows_per;
     int G;
@@ -427,7 +463,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         rows_per = (n + want_g - 1) / want_g;
         G = (int)((n + rows_per - 1) / rows_per);
     }
-    const size_t shmem = resident ? (size_t)rows_per * b * sizeof(T) : 0;
+    const size_t shmem = resident ? (size_t)rows_per * ldr * sizeof(T) : 0;
 
     // one word buffer: [0] error flag and kept count (two ints), then the
     // candidate slots (2 x G x CW words), then the row slots (2 x G x b x TW)
