@@ -69,16 +69,68 @@ struct MagT<double> {
     using type = double;
 };
 
+// Cross-lane moves through the DPP lane patterns (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_val(float v) {
+    return __builtin_bit_cast(float, dpp_i32<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_val(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)u), hi = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_val(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One exchange step of the (magnitude, row, tag) maximum: larger magnitude,
+// then smaller row.  The lane patterns pair lanes symmetrically, so both
+// lanes of a pair keep the same winner.
+template <int CTRL, class M>
+__device__ __forceinline__ void argmax_step(M &m, int &i, int &g) {
+    const M m2 = dpp_val<CTRL>(m);
+    const int i2 = dpp_i32<CTRL>(i), g2 = dpp_i32<CTRL>(g);
+    if (m2 > m || (m2 == m && i2 < i)) {
+        m = m2;
+        i = i2;
+        g = g2;
+    }
+}
+// Wave maximum: within each row of 16 lanes (swap neighbours, swap pairs,
+// mirror each 8, mirror the 16), then the four row winners in a fixed order.
+// Magnitudes are never NaN here (the local searches skip NaN).
 template <class M>
-__device__ __forceinline__ void wave_argmax(M &m, int &i) {
-    for (int o = 32; o > 0; o >>= 1) {
-        M m2 = __shfl_xor(m, o, 64);
-        int i2 = __shfl_xor(i, o, 64);
-        if (m2 > m || (m2 == m && i2 < i)) {
-            m = m2;
-            i = i2;
+__device__ __forceinline__ void wave_argmax(M &m, int &i, int &g) {
+    argmax_step<0xB1>(m, i, g);
+    argmax_step<0x4E>(m, i, g);
+    argmax_step<0x141>(m, i, g);
+    argmax_step<0x140>(m, i, g);
+    M bm = lane_val(m, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0), bg = __builtin_amdgcn_readlane(g, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) {
+        const M m2 = lane_val(m, r);
+        const int i2 = __builtin_amdgcn_readlane(i, r), g2 = __builtin_amdgcn_readlane(g, r);
+        if (m2 > bm || (m2 == bm && i2 < bi)) {
+            bm = m2;
+            bi = i2;
+            bg = g2;
         }
     }
+    m = bm;
+    i = bi;
+    g = bg;
 }
 
 // Tagged words: payload in the high 32 bits, sequence tag in the low 32.
@@ -181,6 +233,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
     int tpr = 1;
     while (tpr < 16 && nrows * tpr * 2 <= NT) tpr *= 2;
     const int sub = t % tpr, rstep = NT / tpr;
+    const bool one_row = nrows <= rstep;
 
     auto local_argmax = [&](int col, M &bm, int &bi) {
         bm = (M)-1;
@@ -194,7 +247,8 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
         }
     };
     auto block_argmax = [&](M &bm, int &bi) {
-        wave_argmax(bm, bi);
+        int unused = 0;
+        wave_argmax(bm, bi, unused);
         if (lane == 0) {
             red_m[wave] = bm;
             red_i[wave] = bi;
@@ -263,16 +317,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
                 }
             }
             if (!__syncthreads_and(ok)) break;
-            for (int o = 32; o > 0; o >>= 1) {
-                M m2 = __shfl_xor(bm, o, 64);
-                int i2 = __shfl_xor(bi, o, 64);
-                int g2 = __shfl_xor(bg, o, 64);
-                if (m2 > bm || (m2 == bm && i2 < bi)) {
-                    bm = m2;
-                    bi = i2;
-                    bg = g2;
-                }
-            }
+            wave_argmax(bm, bi, bg);
             if (lane == 0) {
                 red_m[wave] = bm;
                 red_i[wave] = bi;
@@ -326,6 +371,9 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
             if (!__syncthreads_and(ok)) break;
         }
         const T pivot = w_sh[j];
+        // with at most one row per thread, that row's multiplier once per
+        // column (the same IEEE quotient everywhere it is used)
+        const T qm = (one_row && t / tpr < nrows) ? at(t / tpr, j) / pivot : (T)0;
         if (j + 1 < b) {
             // 3. column j+1 of every row (one fused multiply-add each) and the
             // local candidate of column j+1
@@ -333,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
             int ni = 0x7fffffff;
             if (sub == 0)
                 for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
-                    const T q = at(rr, j) / pivot;
+                    const T q = one_row ? qm : at(rr, j) / pivot;
                     const T y = fma(-w_sh[j + 1], q, at(rr, j + 1));
                     at(rr, j + 1) = y;
                     const M v = (M)fabs((double)y);
@@ -358,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
         // 5. the rest: columns j+2..b-1 of every other row, then the
         // multipliers into column j
         for (int64_t rr = t / tpr; rr < nrows; rr += rstep) {
-            const T q = at(rr, j) / pivot;
+            const T q = one_row ? qm : at(rr, j) / pivot;
             if (RESIDENT && r0 + rr != ci) {
                 // scalar head up to a chunk boundary, then 16-byte chunks
                 // (chunk u of the row to sub-thread u % tpr)
@@ -408,7 +456,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
         }
         __syncthreads();
         if (sub == 0)
-            for (int64_t rr = t / tpr; rr < nrows; rr += rstep) at(rr, j) = at(rr, j) / pivot;
+            for (int64_t rr = t / tpr; rr < nrows; rr += rstep) at(rr, j) = one_row ? qm : at(rr, j) / pivot;
         __syncthreads();
     }
 
