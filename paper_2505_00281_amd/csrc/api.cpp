@@ -224,6 +224,7 @@ ofrr_status ofrr_destroy(ofrr_ctx ctx) {
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
     ctx->c.ws.release_all();
+    if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
     for (auto e : ctx->c.timer.pool) (void)hipEventDestroy(e);
     for (auto &p : ctx->c.timer.pending) {
         (void)hipEventDestroy(p.a);

@@ -113,6 +113,21 @@ struct Context {
         return static_cast<T *>(ws.get(name, count * sizeof(T) + 256));
     }
     void sync() { OFRR_HIP(hipStreamSynchronize(stream)); }
+    // pinned host staging for small per-iteration readbacks (grows on demand,
+    // freed with the context)
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    template <class T>
+    T *host_stage(size_t count) {
+        const size_t need = count * sizeof(T);
+        if (need > pinned_bytes) {
+            if (pinned) OFRR_HIP(hipHostFree(pinned));
+            pinned = nullptr;
+            OFRR_HIP(hipHostMalloc(&pinned, need < 4096 ? 4096 : need, hipHostMallocDefault));
+            pinned_bytes = need < 4096 ? 4096 : need;
+        }
+        return static_cast<T *>(pinned);
+    }
     void resolve_timers();
 };
 
@@ -252,7 +267,7 @@ void finalize_eig(Context *ctx, int64_t n, int32_t k, const double *X, int64_t l
 // out[c] = sqrt(sum res2[blk][c]) / sqrt(sum xn2[blk][c]) / anorm for
 // c < count; partial arrays have row stride `stride`.
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
-                     int count, double anorm, double *out);
+                     int count, double anorm, double *out, const int32_t *extra = nullptr);
 // SVD final step: resid[c] = sqrt(|A v - s u|^2 + |A^T u - s v|^2)/anorm,
 // normalisation and sign rule (sign fixed on v, u follows); outputs
 // column-major FP64.

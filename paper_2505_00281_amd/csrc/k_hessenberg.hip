@@ -564,7 +564,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         KTimer tm(ctx, "hessenberg");
         OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(nt), args, (unsigned)shmem, ctx->stream));
     }
-    int32_t host[2] = {0, 0};
+    int32_t *host = ctx->host_stage<int32_t>(2);
     OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
     if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");

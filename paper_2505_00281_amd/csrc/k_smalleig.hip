@@ -1535,10 +1535,10 @@ int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, of
                    double *theta, double *Y, bool want_rank) {
     (void)want_rank;
     const int32_t *rank = pencil_eig_async(ctx, b, H, G, which, theta, Y);
-    int32_t host = 0;
-    OFRR_HIP(hipMemcpyAsync(&host, rank, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    int32_t *host = ctx->host_stage<int32_t>(1);
+    OFRR_HIP(hipMemcpyAsync(host, rank, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
-    return host;
+    return host[0];
 }
 
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,

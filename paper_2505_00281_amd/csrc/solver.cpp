@@ -294,11 +294,12 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             for (double v : th) m = std::max(m, std::fabs(v));
             anorm_used = m > 0 ? m : 1.0;
         }
-        residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest);
-        int32_t rank = 0;
-        OFRR_HIP(hipMemcpyAsync(est.data(), rest, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
-        OFRR_HIP(hipMemcpyAsync(&rank, rank_dev, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, rank_dev);
+        double *stage = ctx->host_stage<double>((size_t)k + 1);
+        OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, ctx->stream));
         ctx->sync();
+        std::copy(stage, stage + k, est.begin());
+        const int32_t rank = (int32_t)stage[k];
         if (rank < k) fail(OFRR_ERR_NUMERIC, "projected mass matrix lost rank below k");
         bc = rank;
         double emax = 0.0;
