@@ -190,6 +190,11 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
 // 32 x 32 output block each (six int32 accumulators = 96 registers), so two
 // waves share each SIMD and hide each other's LDS and global latency;
 // 64-byte K stages through LDS, the next stage prefetched into registers.
+// (s, u) digit pairs with s + u < 6 (0-based), ordered so that equal
+// s + u are at least three apart cyclically
+constexpr int kPairS[21] = {0, 5, 3, 2, 3, 0, 1, 1, 4, 0, 0, 2, 0, 2, 0, 1, 2, 1, 3, 1, 4};
+constexpr int kPairU[21] = {0, 0, 1, 1, 2, 1, 2, 3, 1, 2, 3, 2, 5, 0, 4, 0, 3, 1, 0, 4, 0};
+
 template <int NCT>
 __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict__ Ap, int64_t a_stride,
                                                         const int32_t *__restrict__ ex,
@@ -268,12 +273,13 @@ __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict
             for (int s = 0; s < I8_S; ++s) a[s] = *(const v4i_t *)&As[s][32 * wr + (lane & 31)][kq];
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) v[s] = *(const v4i_t *)&Vs[s][32 * wc + (lane & 31)][kq];
+            // the 21 digit pairs in an order that keeps two MFMAs on the
+            // same accumulator at least three apart, also across steps
 #pragma unroll
-            for (int s = 0; s < I8_S; ++s)
-#pragma unroll
-                for (int u = 0; u < I8_S; ++u)
-                    if (s + u < I8_NG)
-                        acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[s + u], 0, 0, 0);
+            for (int q = 0; q < 21; ++q) {
+                const int s = kPairS[q], u = kPairU[q];
+                acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[s + u], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
