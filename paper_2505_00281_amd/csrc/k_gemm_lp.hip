@@ -18,6 +18,8 @@
 // MFMA v_mfma_f32_32x32x16: lane l holds A[l%32][8(l/32)..+8] and
 // B[8(l/32)..+8][l%32]; accumulator register r of lane l is
 // D[(r/4)*8 + 4(l/32) + r%4][l%32].
+#include <cstdlib>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -41,8 +43,6 @@ __device__ __forceinline__ f32x16_t mfma_32x32x16(u32x4_t a, u32x4_t b, f32x16_t
 }
 
 constexpr int GL_BM = 128;  // rows per workgroup tile
-constexpr int GL_BK = 64;   // K depth per slice
-constexpr int GL_LD = 72;   // LDS row stride in halves (144 B, 16-byte aligned)
 
 // 8 halves starting at p, zero beyond `valid` (and for misaligned p).
 __device__ __forceinline__ u32x4_t load8(const uint16_t *p, int64_t valid) {
@@ -57,7 +57,10 @@ __device__ __forceinline__ u32x4_t load8(const uint16_t *p, int64_t valid) {
 // SPLITV: the basis is a two-term split Vhi + Vlo (two MFMAs per fragment).
 // SPLITA: A is also a two-term split Ahi + Alo (same layout); the product is
 // Ahi Vhi + Ahi Vlo + Alo Vhi, i.e. about 16 significant bits on each side.
-template <bool IS_BF16, int NB, bool ATRANS, bool SPLITV, bool SPLITA>
+// BK: K depth per slice (64 or 128); the LDS row stride is BK + 8 halves
+// (16-byte aligned, and 16-byte reads of eight consecutive rows hit
+// distinct banks).
+template <bool IS_BF16, int NB, bool ATRANS, bool SPLITV, bool SPLITA, int BK>
 __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
                                                  const uint16_t *__restrict__ Alo, int64_t lda,
                                                  int64_t m, int64_t kdim, int b,
@@ -67,6 +70,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
                                                  int64_t k_per_split, int ntiles, int nsplit,
                                                  int xcd_map) {
     constexpr int BN = 32 * NB;
+    constexpr int GL_BK = BK, GL_LD = BK + 8;
+    constexpr int CPR = BK / 8;                // 16-byte chunks per tile row
+    constexpr int ACH = GL_BM * CPR / 256;     // A chunks per thread per slice
+    constexpr int BCH = BN * CPR / 256;        // basis chunks per thread per slice
     __shared__ __attribute__((aligned(16))) uint16_t As[GL_BM][GL_LD];
     __shared__ __attribute__((aligned(16))) uint16_t Als[SPLITA ? GL_BM : 1][GL_LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][GL_LD];
@@ -95,14 +102,14 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16_t{};
 
-    // register staging of one K slice: A 4 chunks, B NB chunks (+NB lo)
-    u32x4_t ra[4], ral[SPLITA ? 4 : 1], rb[NB], rl[SPLITV ? NB : 1];
+    // register staging of one K slice: A ACH chunks, B BCH chunks (+ lo)
+    u32x4_t ra[ACH], ral[SPLITA ? ACH : 1], rb[BCH], rl[SPLITV ? BCH : 1];
     auto fetch = [&](int64_t k0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < ACH; ++s) {
             const int c = t + 256 * s;
             if (ATRANS) {
-                const int row = c >> 3, kc = (c & 7) * 8;
+                const int row = c / CPR, kc = (c % CPR) * 8;
                 const int64_t gi = i0 + row, gk = k0 + kc;
                 ra[s] = (gi < m) ? load8(A + gk + gi * lda, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
                 if constexpr (SPLITA)
@@ -116,9 +123,9 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
             }
         }
 #pragma unroll
-        for (int s = 0; s < NB; ++s) {
+        for (int s = 0; s < BCH; ++s) {
             const int c = t + 256 * s;
-            const int col = c >> 3, kc = (c & 7) * 8;
+            const int col = c / CPR, kc = (c % CPR) * 8;
             const int64_t gk = k0 + kc;
             const bool ok = j0 + col < b;
             rb[s] = ok ? load8(Vt + (int64_t)(j0 + col) * ldvt + gk, kend - gk) : u32x4_t{0u, 0u, 0u, 0u};
@@ -128,11 +135,11 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
     };
     auto stash = [&]() {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < ACH; ++s) {
             const int c = t + 256 * s;
             if (ATRANS) {
-                *(u32x4_t *)&As[c >> 3][(c & 7) * 8] = ra[s];
-                if constexpr (SPLITA) *(u32x4_t *)&Als[c >> 3][(c & 7) * 8] = ral[s];
+                *(u32x4_t *)&As[c / CPR][(c % CPR) * 8] = ra[s];
+                if constexpr (SPLITA) *(u32x4_t *)&Als[c / CPR][(c % CPR) * 8] = ral[s];
             } else {
                 const int kk = c >> 4, rc = (c & 15) * 8;
                 uint16_t tmp[8];
@@ -147,10 +154,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(const uint16_t *__restrict__ A,
             }
         }
 #pragma unroll
-        for (int s = 0; s < NB; ++s) {
+        for (int s = 0; s < BCH; ++s) {
             const int c = t + 256 * s;
-            *(u32x4_t *)&Bs[c >> 3][(c & 7) * 8] = rb[s];
-            if constexpr (SPLITV) *(u32x4_t *)&Bls[c >> 3][(c & 7) * 8] = rl[s];
+            *(u32x4_t *)&Bs[c / CPR][(c % CPR) * 8] = rb[s];
+            if constexpr (SPLITV) *(u32x4_t *)&Bls[c / CPR][(c % CPR) * 8] = rl[s];
         }
     };
 
@@ -301,7 +308,7 @@ void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const u
     const int64_t want = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
     while ((int64_t)ntiles * nsplit < want && kdim / (nsplit * 2) >= 2048 && nsplit < 8) nsplit *= 2;
     int64_t kps = (kdim + nsplit - 1) / nsplit;
-    kps = (kps + GL_BK - 1) / GL_BK * GL_BK;
+    kps = (kps + 127) / 128 * 128;  // a whole number of slices for every depth
     nsplit = (int)((kdim + kps - 1) / kps);
     // XCD-aware map when the splits divide the 8 XCDs evenly
     const int xcd_map = (nsplit >= 2 && 8 % nsplit == 0) ? 1 : 0;
@@ -315,18 +322,31 @@ void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const u
     const bool splitv = Vtlo != nullptr;
     {
         KTimer tm(ctx, Alo ? "product_bf16x2" : (t == OFRR_BF16 ? "product_bf16" : "product_f16"));
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, A, Alo, lda, m, kdim,
-                               b, Vt, Vtlo, ldvt, dst, ldw, kps, ntiles, nsplit, xcd_map);
+        // K slice depth: 128 (256 contiguous bytes per row and slice) for
+        // the unsplit products, 64 when A or the basis is split (the larger
+        // LDS stage would drop to one workgroup per CU); measured on the
+        // n = 16384 product.  OFRR_LP_BK=64|128 overrides, for tuning sweeps.
+        int bk = (Alo || splitv) ? 64 : 128;
+        if (const char *e = std::getenv("OFRR_LP_BK")) {
+            const int v = std::atoi(e);
+            if (v == 64 || v == 128) bk = v;
+        }
+        auto go2 = [&](auto k64, auto k128) {
+            auto launch = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, A, Alo, lda, m, kdim,
+                                   b, Vt, Vtlo, ldvt, dst, ldw, kps, ntiles, nsplit, xcd_map);
+            };
+            if (bk == 128) launch(k128); else launch(k64);
         };
-#define OFRR_GO(BFV, NBV, TR, SP) go(k_gemm_lp<BFV, NBV, TR, SP, false>)
+#define OFRR_GO(BFV, NBV, TR, SP) go2(k_gemm_lp<BFV, NBV, TR, SP, false, 64>, k_gemm_lp<BFV, NBV, TR, SP, false, 128>)
+#define OFRR_GO2(NBV, TR) go2(k_gemm_lp<true, NBV, TR, true, true, 64>, k_gemm_lp<true, NBV, TR, true, true, 128>)
         const bool bf = t == OFRR_BF16;
         const bool tr = trans != 0;
         if (Alo) {
             if (NB == 4) {
-                if (tr) go(k_gemm_lp<true, 4, true, true, true>); else go(k_gemm_lp<true, 4, false, true, true>);
+                if (tr) OFRR_GO2(4, true); else OFRR_GO2(4, false);
             } else {
-                if (tr) go(k_gemm_lp<true, 2, true, true, true>); else go(k_gemm_lp<true, 2, false, true, true>);
+                if (tr) OFRR_GO2(2, true); else OFRR_GO2(2, false);
             }
         } else if (bf) {
             if (NB == 4) {
@@ -346,6 +366,7 @@ void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const u
             }
         }
 #undef OFRR_GO
+#undef OFRR_GO2
         OFRR_HIP(hipGetLastError());
     }
     if (nsplit > 1) {
