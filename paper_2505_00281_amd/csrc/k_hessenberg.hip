@@ -33,6 +33,7 @@
 #include <map>
 #include <tuple>
 #include <utility>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "device_util.hpp"
@@ -470,12 +471,342 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
     if (g == 0 && t == 0 && kept_out) *kept_out = kept;
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident sweep for FP32 blocks of at most 128 columns: each of
+// the 256 threads holds one whole row of its workgroup's slice in
+// registers, so the eliminations are register fused multiply-adds on
+// multipliers read from LDS, and only the pivot-candidate row passes through
+// LDS (to be published).  The column loop runs as eight sweeps of sixteen
+// columns with the sweep index a template parameter: the registers of the
+// finished columns are left alone and every register index is static (a
+// column picked by the loop index is read through a select tree).  The
+// exchange between workgroups and every arithmetic operation are those of
+// k_hessenberg, so the result is bit-identical.
+constexpr int HR_B = 128;   // columns held per thread
+constexpr int HR_NT = 256;  // threads = rows per workgroup
+
+// r[base + i] for i in [0, 16): the sixteen values are passed as values and
+// picked by a select tree on the bits of i, so the register array is never
+// indexed (which would send it to scratch memory)
+__device__ __forceinline__ float hr_sel16(float x0, float x1, float x2, float x3, float x4, float x5, float x6,
+                                          float x7, float x8, float x9, float x10, float x11, float x12,
+                                          float x13, float x14, float x15, int i) {
+    const bool b0 = (i & 1) != 0, b1 = (i & 2) != 0, b2 = (i & 4) != 0, b3 = (i & 8) != 0;
+    const float a0 = b0 ? x1 : x0, a1 = b0 ? x3 : x2, a2 = b0 ? x5 : x4, a3 = b0 ? x7 : x6;
+    const float a4 = b0 ? x9 : x8, a5 = b0 ? x11 : x10, a6 = b0 ? x13 : x12, a7 = b0 ? x15 : x14;
+    const float c0 = b1 ? a1 : a0, c1 = b1 ? a3 : a2, c2 = b1 ? a5 : a4, c3 = b1 ? a7 : a6;
+    const float d0 = b2 ? c1 : c0, d1 = b2 ? c3 : c2;
+    return b3 ? d1 : d0;
+}
+#define hr_pick16(r, base, i)                                                                               \
+    hr_sel16((r)[(base) + 0], (r)[(base) + 1], (r)[(base) + 2], (r)[(base) + 3], (r)[(base) + 4],             \
+             (r)[(base) + 5], (r)[(base) + 6], (r)[(base) + 7], (r)[(base) + 8], (r)[(base) + 9],             \
+             (r)[(base) + 10], (r)[(base) + 11], (r)[(base) + 12], (r)[(base) + 13], (r)[(base) + 14],        \
+             (r)[(base) + 15], (i))
+
+struct HRShared {
+    float *w_sh;    // multipliers of the current column (HR_B + 16, zero beyond b)
+    float *cand;    // the candidate row being published (HR_B)
+    float *red_m;   // 4 per-wave partials
+    int *red_i, *red_g;
+    int *s_win;     // [0] row, [1] workgroup
+    float *s_wmag;
+};
+
+struct HRArgs {
+    int b, G, g, t, lane, wave;
+    int64_t r0, nrows;
+    double tol;
+    int32_t *piv, *keep;
+    uint64_t *slot_rows, *slot_cand;
+    int *err;
+};
+
+// block-wide (magnitude, row) maximum; the same winner in every thread
+__device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared &sh, float &bm, int &bi) {
+    int unused = 0;
+    wave_argmax(bm, bi, unused);
+    if (a.lane == 0) {
+        sh.red_m[a.wave] = bm;
+        sh.red_i[a.wave] = bi;
+    }
+    __syncthreads();
+    bm = sh.red_m[0];
+    bi = sh.red_i[0];
+    for (int w = 1; w < HR_NT / 64; ++w)
+        if (sh.red_m[w] > bm || (sh.red_m[w] == bm && sh.red_i[w] < bi)) {
+            bm = sh.red_m[w];
+            bi = sh.red_i[w];
+        }
+    __syncthreads();
+}
+
+// publish the candidate (cm, ci) of column jj and its row's entries jj..b-1
+// (in sh.cand); all threads
+__device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared &sh, int jj, float cm, int ci) {
+    const int bufp = jj & 1;
+    const uint32_t tagp = (uint32_t)jj + 1u;
+    uint64_t *my_row = a.slot_rows + ((int64_t)bufp * a.G + a.g) * a.b;
+    if (ci != 0x7fffffff)
+        for (int c = jj + a.t; c < a.b; c += HR_NT) put_value<float>(my_row + c, sh.cand[c], tagp);
+    if (a.t == 0) {
+        uint64_t *my_cand = a.slot_cand + ((int64_t)bufp * a.G + a.g) * 2;
+        put_value<float>(my_cand, cm, tagp);
+        put_word(my_cand + 1, (uint32_t)ci, tagp);
+    }
+}
+
+// local candidate of column c0 + i (my row's value x): magnitude -1 and
+// row 0x7fffffff when there is no (finite, non-NaN-compared) candidate
+__device__ __forceinline__ void hr_local_cand(const HRArgs &a, float x, float &cm, int &ci) {
+    const float v = fabsf(x);
+    const bool ok = a.t < a.nrows && v > -1.0f;
+    cm = ok ? v : -1.0f;
+    ci = ok ? (int)(a.r0 + a.t) : 0x7fffffff;
+}
+
+template <int JV>
+__device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, const HRShared &sh, float &cm,
+                                         int &ci, int &kept) {
+    const bool valid = a.t < a.nrows;
+    const int myrow = (int)(a.r0 + a.t);
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * JV + jj;
+        if (j >= a.b) return true;
+        const int buf = j & 1;
+        const uint32_t tag = (uint32_t)j + 1u;
+        // 1. every candidate of column j, one thread per workgroup
+        {
+            float bm = -1.0f;
+            int bi = 0x7fffffff, bg = -1;
+            int ok = 1;
+            for (int h = a.t; h < a.G; h += HR_NT) {
+                const uint64_t *c = a.slot_cand + ((int64_t)buf * a.G + h) * 2;
+                uint32_t cw[2];
+                if (!get_words<2>(c, tag, cw, a.err)) {
+                    ok = 0;
+                    break;
+                }
+                float m2;
+                __builtin_memcpy(&m2, cw, sizeof(float));
+                const int i2 = (int)cw[1];
+                if (m2 > bm || (m2 == bm && i2 < bi)) {
+                    bm = m2;
+                    bi = i2;
+                    bg = h;
+                }
+            }
+            if (!__syncthreads_and(ok)) return false;
+            wave_argmax(bm, bi, bg);
+            if (a.lane == 0) {
+                sh.red_m[a.wave] = bm;
+                sh.red_i[a.wave] = bi;
+                sh.red_g[a.wave] = bg;
+            }
+            __syncthreads();
+            if (a.t == 0) {
+                float m = sh.red_m[0];
+                int i = sh.red_i[0], gg = sh.red_g[0];
+                for (int w = 1; w < HR_NT / 64; ++w)
+                    if (sh.red_m[w] > m || (sh.red_m[w] == m && sh.red_i[w] < i)) {
+                        m = sh.red_m[w];
+                        i = sh.red_i[w];
+                        gg = sh.red_g[w];
+                    }
+                *sh.s_wmag = m;
+                sh.s_win[0] = i;
+                sh.s_win[1] = gg;
+            }
+            __syncthreads();
+        }
+        const float wmag = *sh.s_wmag;
+        const int wrow = sh.s_win[0], wg = sh.s_win[1];
+        const bool take = (wmag >= (float)a.tol) && (wmag > 0.0f) && wg >= 0;
+        if (a.g == 0 && a.t == 0) {
+            a.piv[j] = take ? wrow : -1;
+            a.keep[j] = take ? 1 : 0;
+        }
+        // column j + 1 of my row (static index through the select tree)
+        auto col_next = [&]() -> float {
+            if constexpr (JV < 7) return (jj == 15) ? row[16 * JV + 16] : hr_pick16(row, 16 * JV, (jj + 1) & 15);
+            else return hr_pick16(row, 16 * JV, (jj + 1) & 15);
+        };
+        if (!take) {
+            // dropped: nothing changes; the next candidate is a plain search
+            if (j + 1 < a.b) {
+                hr_local_cand(a, col_next(), cm, ci);
+                hr_block_argmax(a, sh, cm, ci);
+                if (valid && myrow == ci) {
+#pragma unroll
+                    for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
+                }
+                __syncthreads();
+                hr_publish(a, sh, j + 1, cm, ci);
+            }
+            continue;
+        }
+        ++kept;
+        // 2. multipliers: the winner's published row (columns j..b-1)
+        {
+            const uint64_t *win_row = a.slot_rows + ((int64_t)buf * a.G + wg) * a.b;
+            int ok = 1;
+            for (int c = j + a.t; c < a.b; c += HR_NT) {
+                float v;
+                if (!get_value<float>(win_row + c, tag, v, a.err)) {
+                    ok = 0;
+                    break;
+                }
+                sh.w_sh[c] = v;
+            }
+            if (!__syncthreads_and(ok)) return false;
+        }
+        const float pivot = sh.w_sh[j];
+        const float q = valid ? hr_pick16(row, 16 * JV, jj) / pivot : 0.0f;
+        // every column of this sweep and beyond, branch-free: the multiplier
+        // of a column at or left of j + 1 is taken as zero, and fma(-0, q, x)
+        // returns x unchanged (bit for bit)
+        auto eliminate = [&]() {
+#pragma unroll
+            for (int c = 16 * JV; c < HR_B; ++c) {
+                const float wv = sh.w_sh[c];
+                row[c] = fma(-((c > j + 1) ? wv : 0.0f), q, row[c]);
+            }
+        };
+        bool owner = false;
+        if (j + 1 < a.b) {
+            // 3. column j+1 of every row and the local candidate of column j+1
+            const float y = fma(-sh.w_sh[j + 1], q, col_next());
+#pragma unroll
+            for (int c = 16 * JV; c < HR_B && c < 16 * JV + 17; ++c) row[c] = (c == j + 1) ? y : row[c];
+            hr_local_cand(a, y, cm, ci);
+            hr_block_argmax(a, sh, cm, ci);
+            // 4. the candidate row is finished first and published
+            owner = valid && myrow == ci;
+            if (owner) {
+                eliminate();
+#pragma unroll
+                for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
+            }
+            __syncthreads();
+            hr_publish(a, sh, j + 1, cm, ci);
+        }
+        // 5. the rest of the slice, then the multiplier into column j
+        if (valid && !owner) eliminate();
+#pragma unroll
+        for (int c = 16 * JV; c < 16 * JV + 16; ++c) row[c] = (valid && c == j) ? q : row[c];
+        __syncthreads();
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(HR_NT) void k_hessenberg_reg(float *__restrict__ Y, int64_t ldy, int64_t n, int b,
+                                                          double tol, int32_t *__restrict__ piv,
+                                                          int32_t *__restrict__ keep,
+                                                          uint64_t *__restrict__ slot_rows,
+                                                          uint64_t *__restrict__ slot_cand, int *__restrict__ err,
+                                                          int32_t *__restrict__ kept_out) {
+    __shared__ __attribute__((aligned(16))) float w_sh[HR_B + 16];
+    __shared__ float cand[HR_B];
+    __shared__ float red_m[HR_NT / 64];
+    __shared__ int red_i[HR_NT / 64], red_g[HR_NT / 64];
+    __shared__ int s_win[2];
+    __shared__ float s_wmag;
+    HRArgs a;
+    a.b = b;
+    a.G = gridDim.x;
+    a.g = blockIdx.x;
+    a.t = threadIdx.x;
+    a.lane = a.t & 63;
+    a.wave = a.t >> 6;
+    a.r0 = (int64_t)a.g * HR_NT;
+    const int64_t r1 = (a.r0 + HR_NT < n) ? a.r0 + HR_NT : n;
+    a.nrows = r1 > a.r0 ? r1 - a.r0 : 0;
+    a.tol = tol;
+    a.piv = piv;
+    a.keep = keep;
+    a.slot_rows = slot_rows;
+    a.slot_cand = slot_cand;
+    a.err = err;
+    HRShared sh{w_sh, cand, red_m, red_i, red_g, s_win, &s_wmag};
+
+    const bool valid = a.t < a.nrows;
+    float row[HR_B];
+    {
+        const float *src = Y + (a.r0 + (valid ? a.t : 0)) * ldy;
+#pragma unroll
+        for (int c = 0; c < HR_B; ++c) row[c] = (valid && c < b) ? src[c < b ? c : 0] : 0.0f;
+    }
+    for (int c = b + a.t; c < HR_B + 16; c += HR_NT) w_sh[c] = 0.0f;
+    float cm;
+    int ci;
+    hr_local_cand(a, row[0], cm, ci);
+    hr_block_argmax(a, sh, cm, ci);
+    if (valid && (int)(a.r0 + a.t) == ci) {
+#pragma unroll
+        for (int c = 0; c < HR_B; ++c) cand[c] = row[c];
+    }
+    __syncthreads();
+    hr_publish(a, sh, 0, cm, ci);
+
+    int kept = 0;
+    const bool ok = hr_sweep<0>(row, a, sh, cm, ci, kept) && hr_sweep<1>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<2>(row, a, sh, cm, ci, kept) && hr_sweep<3>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<4>(row, a, sh, cm, ci, kept) && hr_sweep<5>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<6>(row, a, sh, cm, ci, kept) && hr_sweep<7>(row, a, sh, cm, ci, kept);
+    (void)ok;
+    if (valid) {
+        float *dst = Y + (a.r0 + a.t) * ldy;
+#pragma unroll
+        for (int c = 0; c < HR_B; ++c)
+            if (c < b) dst[c] = row[c];
+    }
+    if (a.g == 0 && a.t == 0 && kept_out) *kept_out = kept;
+}
+
 // Clears the error flag, the kept count and every tagged slot word (a
 // kernel, not a memset, so the sweep can be captured in a graph).
 __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
          i += (int64_t)gridDim.x * blockDim.x)
         words[i] = 0;
+}
+
+int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, double tol, int32_t *piv,
+                int32_t *keep) {
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    const int64_t G64 = (n + HR_NT - 1) / HR_NT;
+    // same word buffer layout as the LDS kernel: [0] error flag and kept
+    // count, candidate slots (2 x G x 2 words), row slots (2 x G x b words)
+    const int G = (int)G64;
+    const int64_t ncand = (int64_t)2 * G * 2, nrow = (int64_t)2 * G * b;
+    const int64_t nwords = 1 + ncand + nrow;
+    uint64_t *words = ctx->buf<uint64_t>("hess_words", (size_t)nwords);
+    int *err = reinterpret_cast<int *>(words);
+    int32_t *kept_d = err + 1;
+    uint64_t *slot_cand = words + 1;
+    uint64_t *slot_rows = words + 1 + ncand;
+    static std::map<int, int> occ;
+    auto it = occ.find(ctx->device);
+    if (it == occ.end()) {
+        int pc = 0;
+        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg, HR_NT, 0));
+        it = occ.emplace(ctx->device, pc).first;
+    }
+    if (G64 > (int64_t)it->second * cus) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
+    hipLaunchKernelGGL(k_hess_reset, dim3((unsigned)std::min<int64_t>(256, (nwords + 255) / 256)), dim3(256), 0,
+                       ctx->stream, words, nwords);
+    OFRR_HIP(hipGetLastError());
+    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &slot_rows, &slot_cand, &err, &kept_d};
+    {
+        KTimer tm(ctx, "hessenberg");
+        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg, dim3(G), dim3(HR_NT), args, 0,
+                                            ctx->stream));
+    }
+    int32_t *host = ctx->host_stage<int32_t>(2);
+    OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
+    return host[1];
 }
 
 template <class T>
@@ -495,6 +826,11 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         if (kb >= 8 && kb <= 150) lds_budget = (size_t)kb * 1024;
     }
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    // FP32 blocks of at most 128 columns: one row per thread in registers
+    // (OFRR_HESS_REG=0 selects the LDS kernel, for comparisons)
+    bool use_reg = std::is_same<T, float>::value && b <= HR_B && (n + HR_NT - 1) / HR_NT <= HR_NT;
+    if (const char *s = std::getenv("OFRR_HESS_REG")) use_reg = use_reg && std::atoi(s) != 0;
+    if (use_reg) return run_reg(ctx, n, b, reinterpret_cast<float *>(Y), ldy, tol, piv, keep);
     const int vec = 16 / (int)sizeof(T);
     const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS
     int64_t rows_res = (int64_t)(lds_budget / ((size_t)ldr * sizeof(T)));

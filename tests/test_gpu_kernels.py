@@ -211,18 +211,21 @@ def test_hessenberg_matches_oracle_bitwise(ctx, prec, shape):
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 
-def test_hessenberg_drops_like_oracle(ctx):
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_hessenberg_drops_like_oracle(ctx, prec):
     rng = np.random.default_rng(7)
     n, b = 3000, 12
     Y = rng.standard_normal((n, b))
     Y[:, 5] = Y[:, 1] - 0.5 * Y[:, 3]
     Y[:, 9] = 0.0
     Y /= np.maximum(np.abs(Y).max(axis=0), 1e-300)
-    tol = 2.0 ** -52 * 64
-    print("hessenberg drops", flush=True)
+    dt = np.float64 if prec == "f64" else np.float32
+    Y = Y.astype(dt)
+    tol = (2.0 ** -52 if prec == "f64" else 2.0 ** -23) * 64
+    print("hessenberg drops", prec, flush=True)
     Yg = torch.from_numpy(Y.copy()).cuda()
     piv, keep, kept = ctx.hessenberg(Yg, tol)
-    Q, p_ref, k_ref = O.hessenberg(Y, tol, "f64")
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
     np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
     assert k_ref[5] == 0 and k_ref[9] == 0
     np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
