@@ -161,6 +161,8 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
         p = __builtin_amdgcn_frexp_mant(p);
         pm = __builtin_ldexp(pm, -ex);
     }
+    // unrolled so that the loads of d and e2 run ahead of the dependency chain
+#pragma unroll 8
     for (int k = 1; k < n; ++k) {
         double pn = fma(d[k] - x, p, -(e2[k - 1] * pm));
         if (fabs(pn) < 0x1p-901) pn = p < 0.0 ? 0x1p-901 : -0x1p-901;
