@@ -14,6 +14,7 @@ namespace ofrr {
 namespace {
 
 constexpr int PJ_T = 64;      // output tile (PJ_T x PJ_T) per workgroup
+constexpr int PJ_D = 8;       // row steps (of four) in flight per wave
 
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double pj_f64x4_t;
 
@@ -41,25 +42,31 @@ __global__ __launch_bounds__(256) void k_gram_partial(const TX *__restrict__ X, 
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[p][q] = pj_f64x4_t{0.0, 0.0, 0.0, 0.0};
-    double xa[2], yb[2];
-    auto fetch = [&](int64_t r0) {
+    // PJ_D steps of four rows in flight: the loads of step s + PJ_D are
+    // issued when step s is consumed
+    double xa[PJ_D][2], yb[PJ_D][2];
+    auto fetch = [&](int64_t r0, double (&xs)[2], double (&ys)[2]) {
         const int64_t r = r0 + kr;
         const bool okr = r < rend;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const int ci = i0 + 16 * p + cc, cj = j0 + 16 * p + cc;
-            xa[p] = (okr && ci < b1) ? load_as_f64(X + r * ldx + ci) : 0.0;
-            yb[p] = (okr && cj < b2) ? load_as_f64(Yb + r * ldy + cj) : 0.0;
+            xs[p] = (okr && ci < b1) ? load_as_f64(X + r * ldx + ci) : 0.0;
+            ys[p] = (okr && cj < b2) ? load_as_f64(Yb + r * ldy + cj) : 0.0;
         }
     };
-    fetch(rbeg);
-    for (int64_t r0 = rbeg; r0 < rend; r0 += 4) {
-        const double a0 = xa[0], a1 = xa[1], b0 = yb[0], b1v = yb[1];
-        if (r0 + 4 < rend) fetch(r0 + 4);
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[1][1], 0, 0, 0);
+#pragma unroll
+    for (int st = 0; st < PJ_D; ++st) fetch(rbeg + 4 * st, xa[st], yb[st]);
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 4 * PJ_D) {
+#pragma unroll
+        for (int st = 0; st < PJ_D; ++st) {
+            const double a0 = xa[st][0], a1 = xa[st][1], b0 = yb[st][0], b1v = yb[st][1];
+            fetch(r0 + 4 * (st + PJ_D), xa[st], yb[st]);  // rows past rend load as zero
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[1][1], 0, 0, 0);
+        }
     }
     // accumulator register r of lane l is D[4r + l/16][l%16]
     const int ntile = gridDim.y * gridDim.z;
@@ -76,30 +83,30 @@ __global__ __launch_bounds__(256) void k_gram_partial(const TX *__restrict__ X, 
 }
 
 // Sum the chunk partials in chunk order and write C (b1 x b2, column-major,
-// ld = b1).
+// ld = b1).  Threads walk the partials in their memory order (tile, row,
+// column), so a wave reads 64 consecutive doubles of every chunk; the
+// scattered writes of C are 8 bytes each.
 __global__ void k_gram_reduce(const double *__restrict__ part, int nchunks, int ntj, int b1,
                               int b2, double *__restrict__ C) {
-    const int64_t total = (int64_t)b1 * b2;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+    const int nti = (b1 + PJ_T - 1) / PJ_T;
+    const int64_t cstride = (int64_t)nti * ntj * PJ_T * PJ_T;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cstride;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(e / b1), i = (int)(e - (int64_t)j * b1);
-        const int ti = i / PJ_T, tj = j / PJ_T, ii = i % PJ_T, jj = j % PJ_T;
-        const int ntile = ((b1 + PJ_T - 1) / PJ_T) * ntj;
-        const int tile = ti * ntj + tj;
-        // chunk order fixed (deterministic); loads issued 8 at a time
-        const double *pp = part + (int64_t)tile * PJ_T * PJ_T + ii * PJ_T + jj;
-        const int64_t cstride = (int64_t)ntile * PJ_T * PJ_T;
+        const int tile = (int)(e / (PJ_T * PJ_T)), rem = (int)(e % (PJ_T * PJ_T));
+        const int i = (tile / ntj) * PJ_T + rem / PJ_T, j = (tile % ntj) * PJ_T + rem % PJ_T;
+        // chunk order fixed (deterministic); 16 loads in flight
+        const double *pp = part + e;
         double s = 0.0;
         int c = 0;
-        for (; c + 8 <= nchunks; c += 8) {
-            double v[8];
+        for (; c + 16 <= nchunks; c += 16) {
+            double v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)(c + u) * cstride];
+            for (int u = 0; u < 16; ++u) v[u] = pp[(int64_t)(c + u) * cstride];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += v[u];
+            for (int u = 0; u < 16; ++u) s += v[u];
         }
         for (; c < nchunks; ++c) s += pp[(int64_t)c * cstride];
-        C[e] = s;
+        if (i < b1 && j < b2) C[(int64_t)j * b1 + i] = s;
     }
 }
 
@@ -137,7 +144,7 @@ void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, c
         });
     });
     OFRR_HIP(hipGetLastError());
-    const int64_t total = (int64_t)b1 * b2;
+    const int64_t total = (int64_t)nti * ntj * PJ_T * PJ_T;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 4096)),
                        dim3(256), 0, ctx->stream, part, (int)nchunks, ntj, b1, b2, C);
     OFRR_HIP(hipGetLastError());
