@@ -7,6 +7,10 @@
 // same identity makes the first filter step of the next outer iteration
 // free.  Blocks are row-major (i*ld + j); the small coefficient matrix Y is
 // column-major FP64.
+#include <set>
+#include <type_traits>
+#include <utility>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -129,6 +133,130 @@ __global__ __launch_bounds__(256) void k_res_reduce(const double *__restrict__ r
     a = wave_sum_f64(a);
     x = wave_sum_f64(x);
     if (lane == 0) out[c] = (x > 0.0) ? sqrt(a) / sqrt(x) / anorm : 0.0;
+}
+
+// The same lift on FP64 MFMA (v_mfma_f64_16x16x4) for b, nc <= 128 and one
+// input type: a workgroup takes 64 rows (16 per wave) and every column; Y is
+// staged in LDS once (b x nc FP64).  Within each 16-deep K block, lane l
+// holds row l % 16 of its wave's rows and the four consecutive K entries
+// 4 (l / 16) .. +3 (one vector load), and MFMA step s uses K = 4 (l / 16) + s
+// on both operands (any consistent K order gives the same sum up to
+// rounding).  Accumulator register r of lane l is D[4 r + l / 16][l % 16].
+typedef double lf_f64x4_t __attribute__((ext_vector_type(4)));
+template <class TI>
+struct LiftVec;
+template <>
+struct LiftVec<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+};
+template <>
+struct LiftVec<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+};
+
+template <class TI, class TO>
+__global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, int64_t ld1,
+                                                   const TI *__restrict__ In2, int64_t ld2, int64_t n, int b,
+                                                   int nc, const double *__restrict__ S, int lds,
+                                                   const double *__restrict__ theta, TO *__restrict__ Out1,
+                                                   TO *__restrict__ Out2, int64_t ldo, double *__restrict__ res2,
+                                                   double *__restrict__ xn2) {
+    extern __shared__ __attribute__((aligned(16))) double Ys[];  // [k][c], b x nc
+    __shared__ double red[2][4][128];
+    typedef typename LiftVec<TI>::v4 v4;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, cl = lane & 15;
+    const bool two = In2 != nullptr;
+    for (int e = t; e < b * nc; e += 256) {
+        const int k = e / nc, c = e - k * nc;
+        Ys[e] = S[k + (int64_t)c * lds];
+    }
+    __syncthreads();
+    const int64_t rowA = (int64_t)blockIdx.x * 64 + 16 * wave + cl;  // this lane's operand row
+    const bool rok = rowA < n;
+    const int ntile = (nc + 15) / 16;
+    lf_f64x4_t acc1[8], acc2[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc1[q] = acc2[q] = lf_f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < b; k0 += 16) {
+        const int kb = k0 + 4 * g;  // this lane's four K entries
+        double a1[4], a2[4];
+        if (rok && kb + 3 < b && (((uintptr_t)(In1 + rowA * ld1 + kb)) & (sizeof(v4) - 1)) == 0 &&
+            (!two || (((uintptr_t)(In2 + rowA * ld2 + kb)) & (sizeof(v4) - 1)) == 0)) {
+            const v4 x = *reinterpret_cast<const v4 *>(In1 + rowA * ld1 + kb);
+            const v4 y = two ? *reinterpret_cast<const v4 *>(In2 + rowA * ld2 + kb) : v4{};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                a1[s] = (double)x[s];
+                a2[s] = (double)y[s];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bool ok = rok && kb + s < b;
+                a1[s] = ok ? load_as_f64(In1 + rowA * ld1 + kb + s) : 0.0;
+                a2[s] = (ok && two) ? load_as_f64(In2 + rowA * ld2 + kb + s) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kb + s;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q < ntile) {
+                    const int c = 16 * q + cl;
+                    const double yv = (k < b && c < nc) ? Ys[k * nc + (c < nc ? c : 0)] : 0.0;
+                    acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yv, acc1[q], 0, 0, 0);
+                    if (two) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yv, acc2[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // outputs, and the residual partials of this 64-row block
+    const int64_t rbase = (int64_t)blockIdx.x * 64 + 16 * wave + g;  // + 4 r
+    double r2[8], x2[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r2[q] = x2[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = 16 * q + cl;
+        if (q >= ntile || c >= nc) continue;
+        const double th = res2 ? theta[c] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = rbase + 4 * r;
+            if (gi >= n) continue;
+            const double x = acc1[q][r];
+            store_as<TO>(Out1 + gi * ldo + c, x);
+            if (two) store_as<TO>(Out2 + gi * ldo + c, acc2[q][r]);
+            const double rr = acc2[q][r] - th * x;
+            r2[q] += rr * rr;
+            x2[q] += x * x;
+        }
+    }
+    if (res2) {
+        // over the four lane groups (fixed butterfly), then the four waves
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            r2[q] += __shfl_xor(r2[q], 16, 64);
+            r2[q] += __shfl_xor(r2[q], 32, 64);
+            x2[q] += __shfl_xor(x2[q], 16, 64);
+            x2[q] += __shfl_xor(x2[q], 32, 64);
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                red[0][wave][16 * q + cl] = r2[q];
+                red[1][wave][16 * q + cl] = x2[q];
+            }
+        }
+        __syncthreads();
+        if (t < nc) {
+            const double a = (red[0][0][t] + red[0][1][t]) + (red[0][2][t] + red[0][3][t]);
+            const double c = (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
+            res2[(int64_t)blockIdx.x * nc + t] = a;
+            xn2[(int64_t)blockIdx.x * nc + t] = c;
+        }
+    }
 }
 
 // Elementwise kernels over row-major n x b blocks: 256 / min(b, 256) rows per
@@ -362,15 +490,40 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
         OFRR_CHECK_ARG(res2 == nullptr, "lift: residual partials need one input type");
         return;
     }
-    dispatch_t(vt, [&](auto *ip) {
-        using TI = std::remove_pointer_t<decltype(ip)>;
-        dispatch_t(xt, [&](auto *op) {
-            using TO = std::remove_pointer_t<decltype(op)>;
-            hipLaunchKernelGGL((k_tall_small<TI, TI, TO>), grid, dim3(256), 0, ctx->stream,
-                               (const TI *)V, ldv, (const TI *)W, ldw, n, b, nc, Y, ldy, theta,
-                               (TO *)X, (TO *)AX, ldx, res2, xn2);
+    // FP64 MFMA path when the coefficients fit one LDS stage and the input is
+    // FP32 or FP64 (whose residual partials use the same 64-row blocks)
+    const bool mfma = b <= 128 && nc <= 128 && (vt == OFRR_F32 || vt == OFRR_F64);
+    if (mfma) {
+        static std::set<std::pair<int, const void *>> lds_set;
+        dispatch_t(vt, [&](auto *ip) {
+            using TI = std::remove_pointer_t<decltype(ip)>;
+            if constexpr (std::is_same<TI, float>::value || std::is_same<TI, double>::value) {
+                dispatch_t(xt, [&](auto *op) {
+                    using TO = std::remove_pointer_t<decltype(op)>;
+                    const void *kern = (const void *)k_lift_mfma<TI, TO>;
+                    if (!lds_set.count({ctx->device, kern})) {
+                        OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     128 * 128 * (int)sizeof(double)));
+                        lds_set.insert({ctx->device, kern});
+                    }
+                    hipLaunchKernelGGL((k_lift_mfma<TI, TO>), dim3((unsigned)((n + 63) / 64)), dim3(256),
+                                       (size_t)b * nc * sizeof(double), ctx->stream, (const TI *)V, ldv,
+                                       (const TI *)W, ldw, n, b, nc, Y, ldy, theta, (TO *)X, (TO *)AX, ldx, res2,
+                                       xn2);
+                });
+            }
         });
-    });
+    } else {
+        dispatch_t(vt, [&](auto *ip) {
+            using TI = std::remove_pointer_t<decltype(ip)>;
+            dispatch_t(xt, [&](auto *op) {
+                using TO = std::remove_pointer_t<decltype(op)>;
+                hipLaunchKernelGGL((k_tall_small<TI, TI, TO>), grid, dim3(256), 0, ctx->stream,
+                                   (const TI *)V, ldv, (const TI *)W, ldw, n, b, nc, Y, ldy, theta,
+                                   (TO *)X, (TO *)AX, ldx, res2, xn2);
+            });
+        });
+    }
     OFRR_HIP(hipGetLastError());
 }
 
