@@ -176,11 +176,21 @@ void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const
 void product_lowp(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                   int64_t lda, int trans, int32_t b, const uint16_t *V, const uint16_t *Vlo,
                   int64_t ldv, float *W, int64_t ldw);
+// Split-K partial slabs of a product left unreduced for a consumer that sums
+// them itself (in slab order, in the slab type: the same result as the
+// reduction kernel).  nsplit = 1: the single slab is W.
+struct SlabOut {
+    const void *p = nullptr;
+    ofrr_dtype t = OFRR_F32;
+    int nsplit = 0;      // 0: not deferred (W written)
+    int64_t stride = 0;  // elements between slabs
+};
 // Alo (may be null): low halves of a two-term BF16 split of A (then Vtlo is
-// required): W = Ahi Vhi + Ahi Vlo + Alo Vhi.
+// required): W = Ahi Vhi + Ahi Vlo + Alo Vhi.  With defer, the split-K
+// partials are left in the workspace and described there instead.
 void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                     int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
-                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo);
+                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo, SlabOut *defer = nullptr);
 // k_gemm_f8.hip.  FP8 e4m3fn product with 32 x 32 block scales on A and
 // per-(column, 32 rows) E8M0 scales on the basis.
 int64_t f8_ldt(int64_t rows);
@@ -214,7 +224,7 @@ struct SlicedA {
 };
 SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans);
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
-                 int64_t ldw);
+                 int64_t ldw, SlabOut *defer = nullptr);
 
 // k_hessenberg.hip
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
@@ -255,6 +265,10 @@ void axpby_block(Context *ctx, int64_t n, int32_t b, ofrr_dtype it, const void *
 void cheb_combine(Context *ctx, int64_t n, int32_t b, ofrr_dtype pt, const void *P,
                   ofrr_dtype st, const void *Ycur, const void *Yprev, int64_t ld, double alpha,
                   double c, double beta, ofrr_dtype nt, void *Ynext);
+// The same with P the sum of deferred split-K slabs.
+void cheb_combine_slabs(Context *ctx, int64_t n, int32_t b, const SlabOut &P, ofrr_dtype st,
+                        const void *Ycur, const void *Yprev, int64_t ld, double alpha, double c,
+                        double beta, ofrr_dtype nt, void *Ynext);
 void scale_array(Context *ctx, int64_t count, double *x, double f);
 // out[c] = ||X1_c - s_c X2_c|| / ||X2_c|| / anorm for row-major blocks
 void col_resid(Context *ctx, ofrr_dtype t, int64_t n, int32_t count, const void *X1, const void *X2,

@@ -344,7 +344,7 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
 }
 
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
-                 int64_t ldw) {
+                 int64_t ldw, SlabOut *defer) {
     OFRR_CHECK_ARG(b >= 1 && b <= 4096, "sliced product: 1 <= b <= 4096");
     const int NCT = b > 64 ? 2 : 1;
     const int BN = 64 * NCT;
@@ -397,6 +397,13 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
                                sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw,
                                kps, ntiles, nsplit, xcd_map);
         OFRR_HIP(hipGetLastError());
+    }
+    if (defer) {
+        defer->p = dst;
+        defer->t = OFRR_F64;
+        defer->nsplit = nsplit;
+        defer->stride = sa.m * ldw;
+        return;
     }
     if (nsplit > 1) {
         KTimer tm(ctx, "product_reduce");

@@ -295,7 +295,7 @@ void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const fl
 
 void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const uint16_t *A,
                     int64_t lda, int trans, int32_t b, const uint16_t *Vt, const uint16_t *Vtlo,
-                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo) {
+                    int64_t ldvt, float *W, int64_t ldw, const uint16_t *Alo, SlabOut *defer) {
     OFRR_CHECK_ARG(b >= 1 && b <= 4096, "product: 1 <= b <= 4096");
     OFRR_CHECK_ARG(Alo == nullptr || (Vtlo != nullptr && t == OFRR_BF16),
                    "product: a split A needs a split BF16 basis");
@@ -368,6 +368,13 @@ void product_lowp_t(Context *ctx, ofrr_dtype t, int64_t m, int64_t kdim, const u
 #undef OFRR_GO
 #undef OFRR_GO2
         OFRR_HIP(hipGetLastError());
+    }
+    if (defer) {
+        defer->p = dst;
+        defer->t = OFRR_F32;
+        defer->nsplit = nsplit;
+        defer->stride = m * ldw;
+        return;
     }
     if (nsplit > 1) {
         KTimer tm(ctx, "product_reduce");

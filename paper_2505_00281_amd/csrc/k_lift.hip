@@ -288,6 +288,21 @@ __global__ void k_cheb(const TP *__restrict__ P, const TS *__restrict__ Yc, cons
         store_as<TN>(Yn + o, v);)
 }
 
+// The recurrence with P = sum of nsplit split-K slabs, summed in slab order in
+// the slab type (the reduction kernel's arithmetic, so the same P).
+template <class TSL, class TS, class TN>
+__global__ void k_cheb_slabs(const TSL *__restrict__ P, int nsplit, int64_t sstride, const TS *__restrict__ Yc,
+                             const TS *__restrict__ Yp, int64_t ld, int64_t n, int b, double alpha, double c,
+                             double beta, TN *__restrict__ Yn) {
+    OFRR_ROWS_COLS_LOOP(
+        const int64_t o = i * ld + j;
+        TSL s = (TSL)0;
+        for (int z = 0; z < nsplit; ++z) s += P[(int64_t)z * sstride + o];
+        double v = alpha * ((double)s - c * load_as_f64(Yc + o));
+        if (beta != 0.0) v -= beta * load_as_f64(Yp + o);
+        store_as<TN>(Yn + o, v);)
+}
+
 // Final step: per column norms of X and of R = AX - theta X, sign of the
 // entry of largest magnitude (first on ties).  One workgroup per column.
 __global__ __launch_bounds__(256) void k_final_cols(const double *__restrict__ X, int64_t ldx,
@@ -562,6 +577,29 @@ void cheb_combine(Context *ctx, int64_t n, int32_t b, ofrr_dtype pt, const void 
             });
         });
     });
+    OFRR_HIP(hipGetLastError());
+}
+
+void cheb_combine_slabs(Context *ctx, int64_t n, int32_t b, const SlabOut &P, ofrr_dtype st, const void *Ycur,
+                        const void *Yprev, int64_t ld, double alpha, double c, double beta, ofrr_dtype nt,
+                        void *Ynext) {
+    OFRR_CHECK_ARG(P.t == OFRR_F32 || P.t == OFRR_F64, "slab type");
+    auto go = [&](auto *slp) {
+        using TSL = std::remove_pointer_t<decltype(slp)>;
+        dispatch_t(st, [&](auto *sp) {
+            using TS = std::remove_pointer_t<decltype(sp)>;
+            dispatch_t(nt, [&](auto *np) {
+                using TN = std::remove_pointer_t<decltype(np)>;
+                hipLaunchKernelGGL((k_cheb_slabs<TSL, TS, TN>), dim3(grid1(n * b)), dim3(256), 0, ctx->stream,
+                                   (const TSL *)P.p, P.nsplit, P.stride, (const TS *)Ycur, (const TS *)Yprev, ld, n,
+                                   b, alpha, c, beta, (TN *)Ynext);
+            });
+        });
+    };
+    if (P.t == OFRR_F32)
+        go((float *)nullptr);
+    else
+        go((double *)nullptr);
     OFRR_HIP(hipGetLastError());
 }
 

@@ -73,8 +73,12 @@ struct EigRun {
     SlicedA A_sl;  // digit planes of A for a sliced FP64 phase
 
     // product of the current phase: W (master type) = A * Vblk (master type)
-    void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc) {
+    // W = A V in the phase's arithmetic.  With defer (dense products only),
+    // split-K partials may be left unreduced and described in *defer for a
+    // consumer that sums them itself; defer->nsplit stays 0 when W is written.
+    void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc, SlabOut *defer = nullptr) {
         ++products;
+        if (defer) defer->nsplit = 0;
         const int64_t ld = b0;
         if (A->format == OFRR_CSR) {
             if (ph.f64()) {
@@ -92,7 +96,7 @@ struct EigRun {
         }
         if (ph.f64()) {
             if (ph.sliced)
-                product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld);
+                product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld, defer);
             else
                 product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
             return;
@@ -105,7 +109,7 @@ struct EigRun {
         if (plan->b_split >= 2 || ph.split) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
         split_block_t(ctx, ph.basis, n, bc, (const float *)Vm, ld, vhi, vlo, ldt);
         product_lowp_t(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ldt, (float *)Wm, ld,
-                       ph.split ? A_lo2 : nullptr);
+                       ph.split ? A_lo2 : nullptr, defer);
     }
 
     int64_t b0 = 0;  // leading dimension of every block (the initial basis size)
@@ -242,21 +246,32 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                 axpby_block(ctx, n, bc, mt, AX, X, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
             else
                 OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        } else if (cheb) {
+            // the combine sums the product's split-K partials itself
+            SlabOut so;
+            run.product(ph, Y0, W, bc, &so);
+            if (so.nsplit > 0)
+                cheb_combine_slabs(ctx, n, bc, so, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+            else
+                cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
         } else {
             run.product(ph, Y0, W, bc);
-            if (cheb)
-                cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
-            else
-                OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+            OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
         }
         for (int d = 2; d <= plan->degree; ++d) {
             scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
             if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
-            run.product(ph, Y1, W, bc);
-            if (cheb)
-                cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
-            else
+            if (cheb) {
+                SlabOut so;
+                run.product(ph, Y1, W, bc, &so);
+                if (so.nsplit > 0)
+                    cheb_combine_slabs(ctx, n, bc, so, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                else
+                    cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+            } else {
+                run.product(ph, Y1, W, bc);
                 OFRR_HIP(hipMemcpyAsync(Y2, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+            }
             std::swap(Y0, Y1);
             std::swap(Y1, Y2);
         }
