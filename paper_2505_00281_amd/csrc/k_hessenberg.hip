@@ -165,6 +165,34 @@ __device__ __forceinline__ bool get_words(const uint64_t *src, uint32_t tag, uin
     }
 }
 
+// Polls N tagged words at independent addresses, all loads in flight at
+// once, until every word with use[q] set carries `tag`; false after the
+// spin budget or once another workgroup has raised the error flag.
+template <int N>
+__device__ __forceinline__ bool get_words_at(const uint64_t *const (&src)[N], const bool (&use)[N], uint32_t tag,
+                                             uint32_t (&w)[N], int *err) {
+    unsigned long long spins = 0;
+    for (;;) {
+        uint64_t v[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] = __hip_atomic_load(src[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < N; ++q) ok = ok && (!use[q] || (uint32_t)v[q] == tag);
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) w[q] = (uint32_t)(v[q] >> 32);
+            return true;
+        }
+        if (++spins > (1ull << 22) ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // 32-bit words of a value
 template <class V>
 struct NWords {
@@ -473,8 +501,8 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
 
 // ---------------------------------------------------------------------------
 // Register-resident sweep for FP32 blocks of at most 128 columns: each of
-// the 256 threads holds one whole row of its workgroup's slice in
-// registers, so the eliminations are register fused multiply-adds on
+// the NT threads (64, 128 or 256) holds one whole row of its workgroup's
+// slice in registers, so the eliminations are register fused multiply-adds on
 // multipliers read from LDS, and only the pivot-candidate row passes through
 // LDS (to be published).  The column loop runs as eight sweeps of sixteen
 // columns with the sweep index a template parameter: the registers of the
@@ -482,8 +510,8 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
 // column picked by the loop index is read through a select tree).  The
 // exchange between workgroups and every arithmetic operation are those of
 // k_hessenberg, so the result is bit-identical.
-constexpr int HR_B = 128;   // columns held per thread
-constexpr int HR_NT = 256;  // threads = rows per workgroup
+constexpr int HR_B = 128;     // columns held per thread
+constexpr int HR_GMAX = 256;  // workgroups (one candidate each per column) at most
 
 // r[base + i] for i in [0, 16): the sixteen values are passed as values and
 // picked by a select tree on the bits of i, so the register array is never
@@ -522,10 +550,23 @@ struct HRArgs {
     int *err;
 };
 
+// every thread's `ok`, at a barrier (one wave: a ballot after the barrier)
+template <int NT>
+__device__ __forceinline__ bool hr_block_all(bool ok) {
+    if constexpr (NT == 64) {
+        __syncthreads();
+        return __builtin_amdgcn_ballot_w64(!ok) == 0;
+    } else {
+        return __syncthreads_and(ok) != 0;
+    }
+}
+
 // block-wide (magnitude, row) maximum; the same winner in every thread
+template <int NT>
 __device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared &sh, float &bm, int &bi) {
     int unused = 0;
     wave_argmax(bm, bi, unused);
+    if constexpr (NT == 64) return;
     if (a.lane == 0) {
         sh.red_m[a.wave] = bm;
         sh.red_i[a.wave] = bi;
@@ -533,7 +574,7 @@ __device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared 
     __syncthreads();
     bm = sh.red_m[0];
     bi = sh.red_i[0];
-    for (int w = 1; w < HR_NT / 64; ++w)
+    for (int w = 1; w < NT / 64; ++w)
         if (sh.red_m[w] > bm || (sh.red_m[w] == bm && sh.red_i[w] < bi)) {
             bm = sh.red_m[w];
             bi = sh.red_i[w];
@@ -543,12 +584,13 @@ __device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared 
 
 // publish the candidate (cm, ci) of column jj and its row's entries jj..b-1
 // (in sh.cand); all threads
+template <int NT>
 __device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared &sh, int jj, float cm, int ci) {
     const int bufp = jj & 1;
     const uint32_t tagp = (uint32_t)jj + 1u;
     uint64_t *my_row = a.slot_rows + ((int64_t)bufp * a.G + a.g) * a.b;
     if (ci != 0x7fffffff)
-        for (int c = jj + a.t; c < a.b; c += HR_NT) put_value<float>(my_row + c, sh.cand[c], tagp);
+        for (int c = jj + a.t; c < a.b; c += NT) put_value<float>(my_row + c, sh.cand[c], tagp);
     if (a.t == 0) {
         uint64_t *my_cand = a.slot_cand + ((int64_t)bufp * a.G + a.g) * 2;
         put_value<float>(my_cand, cm, tagp);
@@ -565,7 +607,7 @@ __device__ __forceinline__ void hr_local_cand(const HRArgs &a, float x, float &c
     ci = ok ? (int)(a.r0 + a.t) : 0x7fffffff;
 }
 
-template <int JV>
+template <int NT, int JV>
 __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, const HRShared &sh, float &cm,
                                          int &ci, int &kept) {
     const bool valid = a.t < a.nrows;
@@ -575,52 +617,68 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
         if (j >= a.b) return true;
         const int buf = j & 1;
         const uint32_t tag = (uint32_t)j + 1u;
-        // 1. every candidate of column j, one thread per workgroup
+        // 1. every candidate of column j (CPL per thread, all polled at once)
+        float wmag;
+        int wrow, wg;
         {
+            constexpr int CPL = (HR_GMAX + NT - 1) / NT;
+            const uint64_t *src[2 * CPL];
+            bool use[2 * CPL];
+            uint32_t cw[2 * CPL];
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const int h = a.t + q * NT;
+                const bool u = h < a.G;
+                src[2 * q] = a.slot_cand + ((int64_t)buf * a.G + (u ? h : 0)) * 2;
+                src[2 * q + 1] = src[2 * q] + 1;
+                use[2 * q] = use[2 * q + 1] = u;
+            }
+            const bool ok = get_words_at<2 * CPL>(src, use, tag, cw, a.err);
+            if (!hr_block_all<NT>(ok)) return false;
             float bm = -1.0f;
             int bi = 0x7fffffff, bg = -1;
-            int ok = 1;
-            for (int h = a.t; h < a.G; h += HR_NT) {
-                const uint64_t *c = a.slot_cand + ((int64_t)buf * a.G + h) * 2;
-                uint32_t cw[2];
-                if (!get_words<2>(c, tag, cw, a.err)) {
-                    ok = 0;
-                    break;
-                }
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
                 float m2;
-                __builtin_memcpy(&m2, cw, sizeof(float));
-                const int i2 = (int)cw[1];
-                if (m2 > bm || (m2 == bm && i2 < bi)) {
+                __builtin_memcpy(&m2, &cw[2 * q], sizeof(float));
+                const int i2 = (int)cw[2 * q + 1];
+                if (use[2 * q] && (m2 > bm || (m2 == bm && i2 < bi))) {
                     bm = m2;
                     bi = i2;
-                    bg = h;
+                    bg = a.t + q * NT;
                 }
             }
-            if (!__syncthreads_and(ok)) return false;
             wave_argmax(bm, bi, bg);
-            if (a.lane == 0) {
-                sh.red_m[a.wave] = bm;
-                sh.red_i[a.wave] = bi;
-                sh.red_g[a.wave] = bg;
+            if constexpr (NT == 64) {
+                wmag = bm;
+                wrow = bi;
+                wg = bg;
+            } else {
+                if (a.lane == 0) {
+                    sh.red_m[a.wave] = bm;
+                    sh.red_i[a.wave] = bi;
+                    sh.red_g[a.wave] = bg;
+                }
+                __syncthreads();
+                if (a.t == 0) {
+                    float m = sh.red_m[0];
+                    int i = sh.red_i[0], gg = sh.red_g[0];
+                    for (int w = 1; w < NT / 64; ++w)
+                        if (sh.red_m[w] > m || (sh.red_m[w] == m && sh.red_i[w] < i)) {
+                            m = sh.red_m[w];
+                            i = sh.red_i[w];
+                            gg = sh.red_g[w];
+                        }
+                    *sh.s_wmag = m;
+                    sh.s_win[0] = i;
+                    sh.s_win[1] = gg;
+                }
+                __syncthreads();
+                wmag = *sh.s_wmag;
+                wrow = sh.s_win[0];
+                wg = sh.s_win[1];
             }
-            __syncthreads();
-            if (a.t == 0) {
-                float m = sh.red_m[0];
-                int i = sh.red_i[0], gg = sh.red_g[0];
-                for (int w = 1; w < HR_NT / 64; ++w)
-                    if (sh.red_m[w] > m || (sh.red_m[w] == m && sh.red_i[w] < i)) {
-                        m = sh.red_m[w];
-                        i = sh.red_i[w];
-                        gg = sh.red_g[w];
-                    }
-                *sh.s_wmag = m;
-                sh.s_win[0] = i;
-                sh.s_win[1] = gg;
-            }
-            __syncthreads();
         }
-        const float wmag = *sh.s_wmag;
-        const int wrow = sh.s_win[0], wg = sh.s_win[1];
         const bool take = (wmag >= (float)a.tol) && (wmag > 0.0f) && wg >= 0;
         if (a.g == 0 && a.t == 0) {
             a.piv[j] = take ? wrow : -1;
@@ -635,30 +693,36 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
             // dropped: nothing changes; the next candidate is a plain search
             if (j + 1 < a.b) {
                 hr_local_cand(a, col_next(), cm, ci);
-                hr_block_argmax(a, sh, cm, ci);
+                hr_block_argmax<NT>(a, sh, cm, ci);
                 if (valid && myrow == ci) {
 #pragma unroll
                     for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
                 }
                 __syncthreads();
-                hr_publish(a, sh, j + 1, cm, ci);
+                hr_publish<NT>(a, sh, j + 1, cm, ci);
             }
             continue;
         }
         ++kept;
-        // 2. multipliers: the winner's published row (columns j..b-1)
+        // 2. multipliers: the winner's published row (columns j..b-1, all
+        // of a thread's words polled at once)
         {
+            constexpr int CPR = (HR_B + NT - 1) / NT;
             const uint64_t *win_row = a.slot_rows + ((int64_t)buf * a.G + wg) * a.b;
-            int ok = 1;
-            for (int c = j + a.t; c < a.b; c += HR_NT) {
-                float v;
-                if (!get_value<float>(win_row + c, tag, v, a.err)) {
-                    ok = 0;
-                    break;
-                }
-                sh.w_sh[c] = v;
+            const uint64_t *src[CPR];
+            bool use[CPR];
+            uint32_t rw[CPR];
+#pragma unroll
+            for (int q = 0; q < CPR; ++q) {
+                const int c = j + a.t + q * NT;
+                use[q] = c < a.b;
+                src[q] = win_row + (use[q] ? c : j);
             }
-            if (!__syncthreads_and(ok)) return false;
+            const bool ok = get_words_at<CPR>(src, use, tag, rw, a.err);
+#pragma unroll
+            for (int q = 0; q < CPR; ++q)
+                if (use[q]) __builtin_memcpy(&sh.w_sh[j + a.t + q * NT], &rw[q], sizeof(float));
+            if (!hr_block_all<NT>(ok)) return false;
         }
         const float pivot = sh.w_sh[j];
         const float q = valid ? hr_pick16(row, 16 * JV, jj) / pivot : 0.0f;
@@ -679,7 +743,7 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
 #pragma unroll
             for (int c = 16 * JV; c < HR_B && c < 16 * JV + 17; ++c) row[c] = (c == j + 1) ? y : row[c];
             hr_local_cand(a, y, cm, ci);
-            hr_block_argmax(a, sh, cm, ci);
+            hr_block_argmax<NT>(a, sh, cm, ci);
             // 4. the candidate row is finished first and published
             owner = valid && myrow == ci;
             if (owner) {
@@ -688,7 +752,7 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
                 for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
             }
             __syncthreads();
-            hr_publish(a, sh, j + 1, cm, ci);
+            hr_publish<NT>(a, sh, j + 1, cm, ci);
         }
         // 5. the rest of the slice, then the multiplier into column j
         if (valid && !owner) eliminate();
@@ -699,7 +763,8 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
     return true;
 }
 
-__global__ __launch_bounds__(HR_NT) void k_hessenberg_reg(float *__restrict__ Y, int64_t ldy, int64_t n, int b,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, int64_t ldy, int64_t n, int b,
                                                           double tol, int32_t *__restrict__ piv,
                                                           int32_t *__restrict__ keep,
                                                           uint64_t *__restrict__ slot_rows,
@@ -707,8 +772,8 @@ __global__ __launch_bounds__(HR_NT) void k_hessenberg_reg(float *__restrict__ Y,
                                                           int32_t *__restrict__ kept_out) {
     __shared__ __attribute__((aligned(16))) float w_sh[HR_B + 16];
     __shared__ float cand[HR_B];
-    __shared__ float red_m[HR_NT / 64];
-    __shared__ int red_i[HR_NT / 64], red_g[HR_NT / 64];
+    __shared__ float red_m[NT / 64];
+    __shared__ int red_i[NT / 64], red_g[NT / 64];
     __shared__ int s_win[2];
     __shared__ float s_wmag;
     HRArgs a;
@@ -718,8 +783,8 @@ __global__ __launch_bounds__(HR_NT) void k_hessenberg_reg(float *__restrict__ Y,
     a.t = threadIdx.x;
     a.lane = a.t & 63;
     a.wave = a.t >> 6;
-    a.r0 = (int64_t)a.g * HR_NT;
-    const int64_t r1 = (a.r0 + HR_NT < n) ? a.r0 + HR_NT : n;
+    a.r0 = (int64_t)a.g * NT;
+    const int64_t r1 = (a.r0 + NT < n) ? a.r0 + NT : n;
     a.nrows = r1 > a.r0 ? r1 - a.r0 : 0;
     a.tol = tol;
     a.piv = piv;
@@ -736,23 +801,23 @@ __global__ __launch_bounds__(HR_NT) void k_hessenberg_reg(float *__restrict__ Y,
 #pragma unroll
         for (int c = 0; c < HR_B; ++c) row[c] = (valid && c < b) ? src[c < b ? c : 0] : 0.0f;
     }
-    for (int c = b + a.t; c < HR_B + 16; c += HR_NT) w_sh[c] = 0.0f;
+    for (int c = b + a.t; c < HR_B + 16; c += NT) w_sh[c] = 0.0f;
     float cm;
     int ci;
     hr_local_cand(a, row[0], cm, ci);
-    hr_block_argmax(a, sh, cm, ci);
+    hr_block_argmax<NT>(a, sh, cm, ci);
     if (valid && (int)(a.r0 + a.t) == ci) {
 #pragma unroll
         for (int c = 0; c < HR_B; ++c) cand[c] = row[c];
     }
     __syncthreads();
-    hr_publish(a, sh, 0, cm, ci);
+    hr_publish<NT>(a, sh, 0, cm, ci);
 
     int kept = 0;
-    const bool ok = hr_sweep<0>(row, a, sh, cm, ci, kept) && hr_sweep<1>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<2>(row, a, sh, cm, ci, kept) && hr_sweep<3>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<4>(row, a, sh, cm, ci, kept) && hr_sweep<5>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<6>(row, a, sh, cm, ci, kept) && hr_sweep<7>(row, a, sh, cm, ci, kept);
+    const bool ok = hr_sweep<NT, 0>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 1>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<NT, 2>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 3>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<NT, 4>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 5>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<NT, 6>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 7>(row, a, sh, cm, ci, kept);
     (void)ok;
     if (valid) {
         float *dst = Y + (a.r0 + a.t) * ldy;
@@ -771,10 +836,12 @@ __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
         words[i] = 0;
 }
 
+template <int NT>
 int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, double tol, int32_t *piv,
                 int32_t *keep) {
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    const int64_t G64 = (n + HR_NT - 1) / HR_NT;
+    const int64_t G64 = (n + NT - 1) / NT;
+    if (G64 > HR_GMAX) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: too many row slices for the register kernel");
     // same word buffer layout as the LDS kernel: [0] error flag and kept
     // count, candidate slots (2 x G x 2 words), row slots (2 x G x b words)
     const int G = (int)G64;
@@ -789,7 +856,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
     auto it = occ.find(ctx->device);
     if (it == occ.end()) {
         int pc = 0;
-        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg, HR_NT, 0));
+        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg<NT>, NT, 0));
         it = occ.emplace(ctx->device, pc).first;
     }
     if (G64 > (int64_t)it->second * cus) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
@@ -799,7 +866,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &slot_rows, &slot_cand, &err, &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
-        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg, dim3(G), dim3(HR_NT), args, 0,
+        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg<NT>, dim3(G), dim3(NT), args, 0,
                                             ctx->stream));
     }
     int32_t *host = ctx->host_stage<int32_t>(2);
@@ -828,9 +895,26 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     // FP32 blocks of at most 128 columns: one row per thread in registers
     // (OFRR_HESS_REG=0 selects the LDS kernel, for comparisons)
-    bool use_reg = std::is_same<T, float>::value && b <= HR_B && (n + HR_NT - 1) / HR_NT <= HR_NT;
+    // rows per workgroup: the smallest of 64, 128, 256 (at least
+    // OFRR_HESS_REG_NT, for comparisons) that keeps the slices within
+    // HR_GMAX.  One wave per workgroup is fastest (n = 16384, b = 128:
+    // 0.51 ms against 0.60 ms at 128 and 0.68 ms at 256 rows, measured): its
+    // argmax is a DPP reduction with no LDS round trip or barrier, and the
+    // 256 workgroups spread the row updates over every CU.
+    int rnt = 64;
+    if (const char *s = std::getenv("OFRR_HESS_REG_NT")) {
+        const int v = std::atoi(s);
+        if (v == 64 || v == 128 || v == 256) rnt = v;
+    }
+    while (rnt < 256 && (n + rnt - 1) / rnt > HR_GMAX) rnt *= 2;
+    bool use_reg = std::is_same<T, float>::value && b <= HR_B && (n + rnt - 1) / rnt <= HR_GMAX;
     if (const char *s = std::getenv("OFRR_HESS_REG")) use_reg = use_reg && std::atoi(s) != 0;
-    if (use_reg) return run_reg(ctx, n, b, reinterpret_cast<float *>(Y), ldy, tol, piv, keep);
+    if (use_reg) {
+        float *Yf = reinterpret_cast<float *>(Y);
+        if (rnt == 64) return run_reg<64>(ctx, n, b, Yf, ldy, tol, piv, keep);
+        if (rnt == 128) return run_reg<128>(ctx, n, b, Yf, ldy, tol, piv, keep);
+        return run_reg<256>(ctx, n, b, Yf, ldy, tol, piv, keep);
+    }
     const int vec = 16 / (int)sizeof(T);
     const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS
     int64_t rows_res = (int64_t)(lds_budget / ((size_t)ldr * sizeof(T)));

@@ -232,6 +232,25 @@ def test_hessenberg_drops_like_oracle(ctx, prec):
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 
+@pytest.mark.parametrize("nt", ["64", "128", "256"])
+@pytest.mark.parametrize("shape", [(16384, 128), (3000, 77), (130, 5)])
+def test_hessenberg_register_widths(ctx, monkeypatch, nt, shape):
+    # the FP32 register sweep at each workgroup width gives the oracle's
+    # pivots and factor bit for bit (ragged last slice included)
+    n, b = shape
+    monkeypatch.setenv("OFRR_HESS_REG_NT", nt)
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((n, b)).astype(np.float32)
+    tol = 2.0 ** -23
+    print("hessenberg register width", nt, shape, flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, "f32")
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
+
+
 # ------------------------------------------------------------- projection
 
 @pytest.mark.parametrize("vt", ["f64", "f32", "bf16"])
