@@ -539,6 +539,7 @@ struct HRShared {
     int *red_i, *red_g;
     int *s_win;     // [0] row, [1] workgroup
     float *s_wmag;
+    float *s_qown;  // the candidate row's multiplier of the current column
 };
 
 struct HRArgs {
@@ -583,14 +584,24 @@ __device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared 
 }
 
 // publish the candidate (cm, ci) of column jj and its row's entries jj..b-1
-// (in sh.cand); all threads
+// (in sh.cand); all threads.  With `pending` the row in sh.cand still lacks
+// the elimination of column jj - 1 in its entries past jj, which is applied
+// here (multipliers sh.w_sh, the row's multiplier *sh.s_qown), one fused
+// multiply-add per entry exactly as the row update itself does it.
 template <int NT>
-__device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared &sh, int jj, float cm, int ci) {
+__device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared &sh, int jj, float cm, int ci,
+                                           bool pending) {
     const int bufp = jj & 1;
     const uint32_t tagp = (uint32_t)jj + 1u;
     uint64_t *my_row = a.slot_rows + ((int64_t)bufp * a.G + a.g) * a.b;
-    if (ci != 0x7fffffff)
-        for (int c = jj + a.t; c < a.b; c += NT) put_value<float>(my_row + c, sh.cand[c], tagp);
+    if (ci != 0x7fffffff) {
+        const float qo = pending ? *sh.s_qown : 0.0f;
+        for (int c = jj + a.t; c < a.b; c += NT) {
+            float v = sh.cand[c];
+            if (pending && c > jj) v = fma(-sh.w_sh[c], qo, v);
+            put_value<float>(my_row + c, v, tagp);
+        }
+    }
     if (a.t == 0) {
         uint64_t *my_cand = a.slot_cand + ((int64_t)bufp * a.G + a.g) * 2;
         put_value<float>(my_cand, cm, tagp);
@@ -699,7 +710,7 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
                     for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
                 }
                 __syncthreads();
-                hr_publish<NT>(a, sh, j + 1, cm, ci);
+                hr_publish<NT>(a, sh, j + 1, cm, ci, false);
             }
             continue;
         }
@@ -726,17 +737,17 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
         }
         const float pivot = sh.w_sh[j];
         const float q = valid ? hr_pick16(row, 16 * JV, jj) / pivot : 0.0f;
-        // every column of this sweep and beyond, branch-free: the multiplier
-        // of a column at or left of j + 1 is taken as zero, and fma(-0, q, x)
-        // returns x unchanged (bit for bit)
+        // columns j + 2 .. b - 1 of a row (the finished columns of this
+        // sweep are kept by a select; from column 16 JV + 17 on every column
+        // is past j + 1)
         auto eliminate = [&]() {
 #pragma unroll
             for (int c = 16 * JV; c < HR_B; ++c) {
-                const float wv = sh.w_sh[c];
-                row[c] = fma(-((c > j + 1) ? wv : 0.0f), q, row[c]);
+                const float r = fma(-sh.w_sh[c], q, row[c]);
+                if (c < 16 * JV + 17) row[c] = (c > j + 1) ? r : row[c];
+                else row[c] = r;
             }
         };
-        bool owner = false;
         if (j + 1 < a.b) {
             // 3. column j+1 of every row and the local candidate of column j+1
             const float y = fma(-sh.w_sh[j + 1], q, col_next());
@@ -744,18 +755,19 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
             for (int c = 16 * JV; c < HR_B && c < 16 * JV + 17; ++c) row[c] = (c == j + 1) ? y : row[c];
             hr_local_cand(a, y, cm, ci);
             hr_block_argmax<NT>(a, sh, cm, ci);
-            // 4. the candidate row is finished first and published
-            owner = valid && myrow == ci;
-            if (owner) {
-                eliminate();
+            // 4. the candidate row goes out first: its owner stages the row
+            // (column j + 1 already updated) and its multiplier, and the
+            // publishing threads apply the elimination of column j on the fly
+            if (valid && myrow == ci) {
 #pragma unroll
                 for (int c = 16 * JV; c < HR_B; ++c) sh.cand[c] = row[c];
+                *sh.s_qown = q;
             }
             __syncthreads();
-            hr_publish<NT>(a, sh, j + 1, cm, ci);
+            hr_publish<NT>(a, sh, j + 1, cm, ci, true);
         }
-        // 5. the rest of the slice, then the multiplier into column j
-        if (valid && !owner) eliminate();
+        // 5. every row of the slice, then the multiplier into column j
+        if (valid) eliminate();
 #pragma unroll
         for (int c = 16 * JV; c < 16 * JV + 16; ++c) row[c] = (valid && c == j) ? q : row[c];
         __syncthreads();
@@ -792,7 +804,8 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, in
     a.slot_rows = slot_rows;
     a.slot_cand = slot_cand;
     a.err = err;
-    HRShared sh{w_sh, cand, red_m, red_i, red_g, s_win, &s_wmag};
+    __shared__ float s_qown;
+    HRShared sh{w_sh, cand, red_m, red_i, red_g, s_win, &s_wmag, &s_qown};
 
     const bool valid = a.t < a.nrows;
     float row[HR_B];
@@ -811,7 +824,7 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, in
         for (int c = 0; c < HR_B; ++c) cand[c] = row[c];
     }
     __syncthreads();
-    hr_publish<NT>(a, sh, 0, cm, ci);
+    hr_publish<NT>(a, sh, 0, cm, ci, false);
 
     int kept = 0;
     const bool ok = hr_sweep<NT, 0>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 1>(row, a, sh, cm, ci, kept) &&

@@ -251,6 +251,31 @@ def test_hessenberg_register_widths(ctx, monkeypatch, nt, shape):
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 
+@pytest.mark.parametrize("prec,nt", [("f32", "64"), ("f32", "256"), ("f64", None)])
+def test_hessenberg_signed_zeros_bitwise(ctx, monkeypatch, prec, nt):
+    # negative zeros in the input: finished columns keep their sign of zero
+    # and updated ones get the fused multiply-add's, as in the oracle
+    # (compared as bit patterns, where -0.0 == 0.0 would hide a difference)
+    if nt is not None:
+        monkeypatch.setenv("OFRR_HESS_REG_NT", nt)
+    rng = np.random.default_rng(12)
+    n, b = 3000, 40
+    Y = rng.standard_normal((n, b))
+    Y[rng.random((n, b)) < 0.15] = -0.0
+    Y[:, 7] = -0.0
+    dt = np.float64 if prec == "f64" else np.float32
+    Y = Y.astype(dt)
+    tol = 2.0 ** -52 if prec == "f64" else 2.0 ** -23
+    print("hessenberg signed zeros", prec, nt, flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    ui = np.uint64 if prec == "f64" else np.uint32
+    np.testing.assert_array_equal(Yg.cpu().numpy().view(ui), np.ascontiguousarray(Q).view(ui))
+
+
 # ------------------------------------------------------------- projection
 
 @pytest.mark.parametrize("vt", ["f64", "f32", "bf16"])
