@@ -430,7 +430,7 @@ ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b
                        "hessenberg: bad arguments");
         OFRR_CHECK_ARG(dtype == OFRR_F64 || dtype == OFRR_F32, "hessenberg: F64 or F32");
         OFRR_HIP(hipSetDevice(c->device));
-        const int32_t kk = hessenberg(c, dtype, n, b, Y, ldy, tol, piv, keep, true);
+        const int32_t kk = hessenberg(c, dtype, n, b, Y, ldy, tol, piv, keep);
         if (kept) *kept = kk;
         return OFRR_OK;
     });

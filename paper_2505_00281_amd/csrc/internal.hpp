@@ -227,8 +227,12 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
                  int64_t ldw, SlabOut *defer = nullptr);
 
 // k_hessenberg.hip
+// Returns the kept count (after waiting for the sweep; a timed-out wait
+// raises).  With `status` given it returns 0 at once instead and sets
+// *status to the device pair {error flag, kept count}, valid on the stream
+// until the next sweep on this context.
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
-                   double tol, int32_t *piv, int32_t *keep, bool want_count);
+                   double tol, int32_t *piv, int32_t *keep, const int32_t **status = nullptr);
 
 // k_project.hip
 void project(Context *ctx, int64_t n, int32_t b, ofrr_dtype vt, const void *V, int64_t ldv,
@@ -279,9 +283,12 @@ void finalize_eig(Context *ctx, int64_t n, int32_t k, const double *X, int64_t l
                   const double *AX, int64_t ldax, const double *theta, double anorm,
                   double *evals, double *evecs, double *resid);
 // out[c] = sqrt(sum res2[blk][c]) / sqrt(sum xn2[blk][c]) / anorm for
-// c < count; partial arrays have row stride `stride`.
+// c < count; partial arrays have row stride `stride`.  out[count] =
+// extra[0] and out[count + 1 + i] = extra2[i] (i < 2) when given, so one
+// copy brings back device-side counts with the estimates.
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
-                     int count, double anorm, double *out, const int32_t *extra = nullptr);
+                     int count, double anorm, double *out, const int32_t *extra = nullptr,
+                     const int32_t *extra2 = nullptr);
 // SVD final step: resid[c] = sqrt(|A v - s u|^2 + |A^T u - s v|^2)/anorm,
 // normalisation and sign rule (sign fixed on v, u follows); outputs
 // column-major FP64.

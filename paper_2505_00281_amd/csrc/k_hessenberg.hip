@@ -851,7 +851,7 @@ __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
 
 template <int NT>
 int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, double tol, int32_t *piv,
-                int32_t *keep) {
+                int32_t *keep, const int32_t **status) {
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     const int64_t G64 = (n + NT - 1) / NT;
     if (G64 > HR_GMAX) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: too many row slices for the register kernel");
@@ -882,6 +882,10 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
         OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg<NT>, dim3(G), dim3(NT), args, 0,
                                             ctx->stream));
     }
+    if (status) {
+        *status = err;
+        return 0;
+    }
     int32_t *host = ctx->host_stage<int32_t>(2);
     OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
@@ -891,7 +895,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
 
 template <class T>
 int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv,
-            int32_t *keep, bool want_count) {
+            int32_t *keep, const int32_t **status) {
     OFRR_CHECK_ARG(b >= 1 && b <= 512, "hessenberg: 1 <= b <= 512");
     OFRR_CHECK_ARG(n >= 1 && n < (int64_t)0x7fffffff, "hessenberg: 1 <= n < 2^31");
     OFRR_CHECK_ARG(ldy >= b, "hessenberg: ld >= b");
@@ -924,9 +928,9 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     if (const char *s = std::getenv("OFRR_HESS_REG")) use_reg = use_reg && std::atoi(s) != 0;
     if (use_reg) {
         float *Yf = reinterpret_cast<float *>(Y);
-        if (rnt == 64) return run_reg<64>(ctx, n, b, Yf, ldy, tol, piv, keep);
-        if (rnt == 128) return run_reg<128>(ctx, n, b, Yf, ldy, tol, piv, keep);
-        return run_reg<256>(ctx, n, b, Yf, ldy, tol, piv, keep);
+        if (rnt == 64) return run_reg<64>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
+        if (rnt == 128) return run_reg<128>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
+        return run_reg<256>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
     }
     const int vec = 16 / (int)sizeof(T);
     const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS
@@ -997,20 +1001,23 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         KTimer tm(ctx, "hessenberg");
         OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(nt), args, (unsigned)shmem, ctx->stream));
     }
+    if (status) {
+        *status = err;
+        return 0;
+    }
     int32_t *host = ctx->host_stage<int32_t>(2);
     OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
     if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
-    (void)want_count;
     return host[1];
 }
 
 }  // namespace
 
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
-                   double tol, int32_t *piv, int32_t *keep, bool want_count) {
-    if (t == OFRR_F64) return run<double>(ctx, n, b, (double *)Y, ldy, tol, piv, keep, want_count);
-    if (t == OFRR_F32) return run<float>(ctx, n, b, (float *)Y, ldy, tol, piv, keep, want_count);
+                   double tol, int32_t *piv, int32_t *keep, const int32_t **status) {
+    if (t == OFRR_F64) return run<double>(ctx, n, b, (double *)Y, ldy, tol, piv, keep, status);
+    if (t == OFRR_F32) return run<float>(ctx, n, b, (float *)Y, ldy, tol, piv, keep, status);
     fail(OFRR_ERR_UNSUPPORTED, "hessenberg: element type must be F64 or F32");
 }
 

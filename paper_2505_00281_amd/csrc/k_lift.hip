@@ -119,11 +119,13 @@ __global__ __launch_bounds__(256) void k_tall_small(const TI1 *__restrict__ In1,
 __global__ __launch_bounds__(256) void k_res_reduce(const double *__restrict__ res2,
                                                     const double *__restrict__ xn2, int nblk, int nc,
                                                     int count, double anorm, double *__restrict__ out,
-                                                    const int32_t *__restrict__ extra) {
+                                                    const int32_t *__restrict__ extra,
+                                                    const int32_t *__restrict__ extra2) {
     // one wavefront per column: lanes take every 64th partial, then a fixed
     // butterfly sum (deterministic)
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (extra && blockIdx.x == 0 && threadIdx.x == 0) out[count] = (double)extra[0];
+    if (extra2 && blockIdx.x == 0 && threadIdx.x < 2) out[count + 1 + threadIdx.x] = (double)extra2[threadIdx.x];
     if (c >= count) return;
     double a = 0.0, x = 0.0;
     for (int i = lane; i < nblk; i += 64) {
@@ -543,9 +545,9 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
 }
 
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
-                     int count, double anorm, double *out, const int32_t *extra) {
+                     int count, double anorm, double *out, const int32_t *extra, const int32_t *extra2) {
     hipLaunchKernelGGL(k_res_reduce, dim3((count + 3) / 4), dim3(256), 0, ctx->stream, res2, xn2,
-                       nblk, stride, count, anorm, out, extra);
+                       nblk, stride, count, anorm, out, extra, extra2);
     OFRR_HIP(hipGetLastError());
 }
 

@@ -239,11 +239,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // its storage type)
         const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(mt);
         // ---- filter
-        // Y0 = X
-        OFRR_HIP(hipMemcpyAsync(Y0, X, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        // Y0 = X: the blocks trade places (X is dead until the lift writes it)
+        std::swap(Y0, X);
         if (have_ax) {
             if (cheb)
-                axpby_block(ctx, n, bc, mt, AX, X, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
+                axpby_block(ctx, n, bc, mt, AX, Y0, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
             else
                 OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
         } else if (cheb) {
@@ -276,43 +276,57 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             std::swap(Y1, Y2);
         }
         scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
-        // ---- stabilise (Hessenberg process, FP64 or FP32 arithmetic)
-        const int32_t kept = hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, true);
-        if (kept <= 0) fail(OFRR_ERR_NUMERIC, "every basis column was dropped");
-        if (kept < bc) {
-            compact_columns_rm(ctx, mt, n, bc, Y1, ld, keep, V, ld);
-        } else {
-            std::swap(V, Y1);
-        }
-        bc = kept;
-        if (bc < k) fail(OFRR_ERR_NUMERIC, "basis lost rank below k");
+        // ---- stabilise (Hessenberg process, FP64 or FP32 arithmetic).  Its
+        // kept count comes back with the residual estimates (one host
+        // synchronisation per iteration): the rest of the iteration assumes
+        // every column was kept and is redone on the compacted basis when
+        // one was dropped.
+        const int32_t *hstat = nullptr;
+        hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, &hstat);
+        std::swap(V, Y1);
         // storage rounding of the basis for a reduced-precision phase
+        // (elementwise, so it commutes with the column compaction)
         if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
-        // ---- project
-        run.product(ph, V, W, bc);
-        project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
-        // ---- solve; the rank comes back with the residual estimates (one
-        // host synchronisation per iteration): every column is lifted, those
-        // beyond the rank are zero and the next sweep drops them
-        const int32_t *rank_dev = pencil_eig_async(ctx, bc, H, G, which, theta, Yr);
-        // ---- lift (X = V Y, AX = W Y) with residual estimates
-        lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
+        double *stage = nullptr;
+        for (bool first = true;; first = false) {
+            // ---- project
+            run.product(ph, V, W, bc);
+            project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
+            // ---- solve; the rank comes back with the residual estimates:
+            // every column is lifted, those beyond the rank are zero and the
+            // next sweep drops them
+            const int32_t *rank_dev = pencil_eig_async(ctx, bc, H, G, which, theta, Yr);
+            // ---- lift (X = V Y, AX = W Y) with residual estimates
+            lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
+            // residual estimates of the k wanted pairs
+            if (plan->anorm <= 0) {
+                std::vector<double> th((size_t)bc);
+                OFRR_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * bc, hipMemcpyDeviceToHost,
+                                        ctx->stream));
+                ctx->sync();
+                double m = 0.0;
+                for (double v : th) m = std::max(m, std::fabs(v));
+                anorm_used = m > 0 ? m : 1.0;
+            }
+            residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, rank_dev,
+                            first ? hstat : nullptr);
+            stage = ctx->host_stage<double>((size_t)k + 3);
+            OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * (k + (first ? 3 : 1)), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+            ctx->sync();
+            if (!first) break;
+            if (stage[k + 1] != 0.0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
+            const int32_t kept = (int32_t)stage[k + 2];
+            if (kept <= 0) fail(OFRR_ERR_NUMERIC, "every basis column was dropped");
+            if (kept == bc) break;
+            compact_columns_rm(ctx, mt, n, bc, V, ld, keep, Y1, ld);
+            std::swap(V, Y1);
+            bc = kept;
+            if (bc < k) fail(OFRR_ERR_NUMERIC, "basis lost rank below k");
+        }
         ++iters;
         if (!ph.f64()) ++iters_low;
         have_ax = true;
-        // residual estimates of the k wanted pairs
-        if (plan->anorm <= 0) {
-            std::vector<double> th((size_t)bc);
-            OFRR_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * bc, hipMemcpyDeviceToHost, ctx->stream));
-            ctx->sync();
-            double m = 0.0;
-            for (double v : th) m = std::max(m, std::fabs(v));
-            anorm_used = m > 0 ? m : 1.0;
-        }
-        residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, rank_dev);
-        double *stage = ctx->host_stage<double>((size_t)k + 1);
-        OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, ctx->stream));
-        ctx->sync();
         std::copy(stage, stage + k, est.begin());
         const int32_t rank = (int32_t)stage[k];
         if (rank < k) fail(OFRR_ERR_NUMERIC, "projected mass matrix lost rank below k");

@@ -137,7 +137,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // machine epsilon of the sweep's arithmetic (FP32 in reduced phases)
         const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff_svd(master());
         scale_columns_pow2(ctx, master(), rows, bc, Tin, ld, master(), nullptr, ld, swork);
-        const int32_t kept = hessenberg(ctx, master(), rows, bc, Tin, ld, tol, piv, keep, true);
+        const int32_t kept = hessenberg(ctx, master(), rows, bc, Tin, ld, tol, piv, keep);
         if (kept < k) fail(OFRR_ERR_NUMERIC, "svd: basis lost rank below k");
         if (kept < bc)
             compact_columns_rm(ctx, master(), rows, bc, Tin, ld, keep, dst, ld);

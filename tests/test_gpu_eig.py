@@ -155,6 +155,24 @@ def test_eig_mixed_refined_converged(ctx, lowp, refine, tail):
     np.testing.assert_allclose(th, w[:k], rtol=1e-10)
 
 
+def test_eig_dropped_column_same_step(ctx):
+    """A dependent start column is dropped by the first sweep (that
+    iteration's projection is redone on the compacted basis); the subspace
+    then equals the oracle's from the start block without that column (the
+    same span) after the same number of steps."""
+    n, b, k, outer = 300, 10, 4, 5
+    lam = 0.7 ** np.arange(n)
+    A = W.dense_symmetric_prescribed(lam, 15)
+    X0 = W.uniform_start(n, b, 16)
+    X0[:, 7] = X0[:, 1]
+    print("eig dropped column same-step", flush=True)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=_plan(max_iters=outer), X0=torch.from_numpy(X0))
+    ref = O.subspace_eig(A.numpy(), np.delete(X0, 7, axis=1), k, outer=outer)
+    assert r.info["iters"] == outer
+    assert r.info["basis_eff"] == b - 1
+    _check_same_step(r, ref, k)
+
+
 def test_eig_rank_deficient_start_block_still_correct(ctx):
     n, b, k = 300, 10, 4
     lam = 0.7 ** np.arange(n)
