@@ -324,25 +324,42 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
     for (int j = 0; j < b; ++j) {
         const int buf = j & 1;
         const uint32_t tag = (uint32_t)j + 1u;
-        // 1. every candidate of column j, one thread per workgroup
+        // 1. every candidate of column j (CPL per thread and round, all
+        // words of a round polled at once)
         {
+            constexpr int CPL = (256 + NT - 1) / NT;
             M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
-            int ok = 1;
-            for (int h = t; h < G; h += NT) {
-                const uint64_t *cand = slot_cand + ((int64_t)buf * G + h) * CW;
-                uint32_t cw[CW];
-                if (!get_words<CW>(cand, tag, cw, err)) {
-                    ok = 0;
+            bool ok = true;
+            for (int h0 = 0; h0 < G; h0 += CPL * NT) {
+                const uint64_t *src[CPL * CW];
+                bool use[CPL * CW];
+                uint32_t cw[CPL * CW];
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    const int h = h0 + t + q * NT;
+                    const bool u = h < G;
+                    const uint64_t *base = slot_cand + ((int64_t)buf * G + (u ? h : 0)) * CW;
+#pragma unroll
+                    for (int w = 0; w < CW; ++w) {
+                        src[q * CW + w] = base + w;
+                        use[q * CW + w] = u;
+                    }
+                }
+                if (!get_words_at<CPL * CW>(src, use, tag, cw, err)) {
+                    ok = false;
                     break;
                 }
-                M m2;
-                __builtin_memcpy(&m2, cw, sizeof(M));
-                const int i2 = (int)cw[CW - 1];
-                if (m2 > bm || (m2 == bm && i2 < bi)) {
-                    bm = m2;
-                    bi = i2;
-                    bg = h;
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    M m2;
+                    __builtin_memcpy(&m2, &cw[q * CW], sizeof(M));
+                    const int i2 = (int)cw[q * CW + CW - 1];
+                    if (use[q * CW] && (m2 > bm || (m2 == bm && i2 < bi))) {
+                        bm = m2;
+                        bi = i2;
+                        bg = h0 + t + q * NT;
+                    }
                 }
             }
             if (!__syncthreads_and(ok)) break;
@@ -385,18 +402,28 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
             continue;
         }
         ++kept;
-        // 2. multipliers: the winner's published row (columns j..b-1)
+        // 2. multipliers: the winner's published row (columns j..b-1, all of
+        // a thread's words polled at once; b <= 512)
         {
+            constexpr int CPR = (512 + NT - 1) / NT;
             const uint64_t *win_row = slot_rows + ((int64_t)buf * G + wg) * b * TW;
-            int ok = 1;
-            for (int c = j + t; c < b; c += NT) {
-                T v;
-                if (!get_value<T>(win_row + (int64_t)c * TW, tag, v, err)) {
-                    ok = 0;
-                    break;
+            const uint64_t *src[CPR * TW];
+            bool use[CPR * TW];
+            uint32_t rw[CPR * TW];
+#pragma unroll
+            for (int q = 0; q < CPR; ++q) {
+                const int c = j + t + q * NT;
+                const bool u = c < b;
+#pragma unroll
+                for (int w = 0; w < TW; ++w) {
+                    src[q * TW + w] = win_row + (int64_t)(u ? c : j) * TW + w;
+                    use[q * TW + w] = u;
                 }
-                w_sh[c] = v;
             }
+            const bool ok = get_words_at<CPR * TW>(src, use, tag, rw, err);
+#pragma unroll
+            for (int q = 0; q < CPR; ++q)
+                if (use[q * TW]) __builtin_memcpy(&w_sh[j + t + q * NT], &rw[q * TW], sizeof(T));
             if (!__syncthreads_and(ok)) break;
         }
         const T pivot = w_sh[j];
@@ -938,9 +965,19 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     bool resident = false;
     int64_t rows_per;
     int G;
+    // workgroup size (OFRR_HESS_THREADS overrides, for tuning sweeps): 256
+    // measured fastest for this kernel (FP64, n = 16384, b = 128: 0.72 ms
+    // against 0.74 ms at 128 and 0.76 ms at 64 threads with one row each)
+    int nt = 256;
+    if (const char *s = std::getenv("OFRR_HESS_THREADS")) {
+        const long v = std::strtol(s, nullptr, 10);
+        if (v == 64 || v == 128 || v == 256 || v == 512 || v == 1024) nt = (int)v;
+    }
     if (rows_res >= 16 && (n + rows_res - 1) / rows_res <= cus) {
         resident = true;
         rows_per = std::min<int64_t>(rows_res, n);
+        // narrow workgroups take one row per thread where the CUs allow it
+        if (nt <= 128) rows_per = std::min<int64_t>(rows_per, std::max<int64_t>(nt, (n + cus - 1) / cus));
         G = (int)((n + rows_per - 1) / rows_per);
     } else {
         int64_t want_g = std::min<int64_t>(cus, (n + 255) / 256);
@@ -965,14 +1002,10 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
                        ctx->stream, words, nwords);
     OFRR_HIP(hipGetLastError());
 
-    // workgroup size (OFRR_HESS_THREADS overrides, for tuning sweeps)
-    int nt = 256;
-    if (const char *s = std::getenv("OFRR_HESS_THREADS")) {
-        const long v = std::strtol(s, nullptr, 10);
-        if (v == 256 || v == 512 || v == 1024) nt = (int)v;
-    }
     void *kern = nullptr;
-    if (nt == 256) kern = resident ? (void *)k_hessenberg<T, true, 256> : (void *)k_hessenberg<T, false, 256>;
+    if (nt == 64) kern = resident ? (void *)k_hessenberg<T, true, 64> : (void *)k_hessenberg<T, false, 64>;
+    else if (nt == 128) kern = resident ? (void *)k_hessenberg<T, true, 128> : (void *)k_hessenberg<T, false, 128>;
+    else if (nt == 256) kern = resident ? (void *)k_hessenberg<T, true, 256> : (void *)k_hessenberg<T, false, 256>;
     else if (nt == 512) kern = resident ? (void *)k_hessenberg<T, true, 512> : (void *)k_hessenberg<T, false, 512>;
     else kern = resident ? (void *)k_hessenberg<T, true, 1024> : (void *)k_hessenberg<T, false, 1024>;
     // the dynamic-LDS limit and the occupancy answer depend only on the
