@@ -163,14 +163,36 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
                                                    const double *__restrict__ theta, TO *__restrict__ Out1,
                                                    TO *__restrict__ Out2, int64_t ldo, double *__restrict__ res2,
                                                    double *__restrict__ xn2) {
-    extern __shared__ __attribute__((aligned(16))) double Ys[];  // [k][c], b x nc
+    extern __shared__ __attribute__((aligned(16))) double Ys[];  // [k][c], b x nc, row stride nc + 1
     __shared__ double red[2][4][128];
     typedef typename LiftVec<TI>::v4 v4;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, cl = lane & 15;
     const bool two = In2 != nullptr;
-    for (int e = t; e < b * nc; e += 256) {
-        const int k = e / nc, c = e - k * nc;
-        Ys[e] = S[k + (int64_t)c * lds];
+    // Y (column-major, leading dimension lds) into LDS as [k][c]: consecutive
+    // threads read consecutive k of a column (coalesced), eight loads in
+    // flight per thread; the odd row stride nc + 1 spreads both the stores
+    // (consecutive k) and the MFMA operand reads (consecutive c) over the banks
+    const int ldk = nc + 1;
+    {
+        const int tot = b * nc;
+        for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + 256 * u + t;
+                const int ee = e < tot ? e : tot - 1;
+                const int c = ee / b, k = ee - c * b;
+                v[u] = S[k + (int64_t)c * lds];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + 256 * u + t;
+                if (e < tot) {
+                    const int c = e / b, k = e - c * b;
+                    Ys[k * ldk + c] = v[u];
+                }
+            }
+        }
     }
     __syncthreads();
     const int64_t rowA = (int64_t)blockIdx.x * 64 + 16 * wave + cl;  // this lane's operand row
@@ -179,38 +201,67 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
     lf_f64x4_t acc1[8], acc2[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc1[q] = acc2[q] = lf_f64x4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < b; k0 += 16) {
-        const int kb = k0 + 4 * g;  // this lane's four K entries
-        double a1[4], a2[4];
-        if (rok && kb + 3 < b && (((uintptr_t)(In1 + rowA * ld1 + kb)) & (sizeof(v4) - 1)) == 0 &&
-            (!two || (((uintptr_t)(In2 + rowA * ld2 + kb)) & (sizeof(v4) - 1)) == 0)) {
-            const v4 x = *reinterpret_cast<const v4 *>(In1 + rowA * ld1 + kb);
-            const v4 y = two ? *reinterpret_cast<const v4 *>(In2 + rowA * ld2 + kb) : v4{};
+    // K blocks of 16; lane group g takes the block's entries 4g .. 4g + 3
+    auto mfma_block = [&](int k0, const double (&a1)[4], const double (&a2)[4]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * g + s;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q < ntile) {
+                    const int c = 16 * q + cl;
+                    const double yv = (k < b && c < nc) ? Ys[k * ldk + (c < nc ? c : 0)] : 0.0;
+                    acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yv, acc1[q], 0, 0, 0);
+                    if (two) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yv, acc2[q], 0, 0, 0);
+                }
+            }
+        }
+    };
+    const auto vec_aligned = [](const TI *p, int64_t ld) {
+        return ((uintptr_t)p & (sizeof(v4) - 1)) == 0 && (ld & 3) == 0;
+    };
+    const bool fast = (b & 15) == 0 && vec_aligned(In1, ld1) && (!two || vec_aligned(In2, ld2));
+    if (fast) {
+        // every load of the lane's row (clamped to the block, unconditional)
+        // is issued D blocks ahead of its use; rows past n are zeroed where
+        // the values are used
+        constexpr int NKB = 8;  // b <= 128
+        constexpr int D = sizeof(TI) == 4 ? 8 : 4;
+        const int64_t rc = rok ? rowA : n - 1;
+        const TI *p1 = In1 + rc * ld1;
+        const TI *p2 = two ? In2 + rc * ld2 : p1;
+        v4 xr[D], yr[D];
+        auto fetch = [&](int kb8, v4 &x, v4 &y) {
+            const int col = (16 * kb8 + 4 * g < b) ? 16 * kb8 + 4 * g : b - 4;
+            x = *reinterpret_cast<const v4 *>(p1 + col);
+            y = *reinterpret_cast<const v4 *>(p2 + col);
+        };
+#pragma unroll
+        for (int q = 0; q < D; ++q) fetch(q, xr[q], yr[q]);
+#pragma unroll
+        for (int kb8 = 0; kb8 < NKB; ++kb8) {
+            if (16 * kb8 >= b) break;
+            const v4 x = xr[kb8 % D], y = yr[kb8 % D];
+            if (kb8 + D < NKB) fetch(kb8 + D, xr[kb8 % D], yr[kb8 % D]);
+            double a1[4], a2[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                a1[s] = (double)x[s];
-                a2[s] = (double)y[s];
+                a1[s] = rok ? (double)x[s] : 0.0;
+                a2[s] = rok ? (double)y[s] : 0.0;
             }
-        } else {
+            mfma_block(16 * kb8, a1, a2);
+        }
+    } else {
+        for (int k0 = 0; k0 < b; k0 += 16) {
+            const int kb = k0 + 4 * g;  // this lane's four K entries
+            double a1[4], a2[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const bool ok = rok && kb + s < b;
                 a1[s] = ok ? load_as_f64(In1 + rowA * ld1 + kb + s) : 0.0;
                 a2[s] = (ok && two) ? load_as_f64(In2 + rowA * ld2 + kb + s) : 0.0;
             }
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = kb + s;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (q < ntile) {
-                    const int c = 16 * q + cl;
-                    const double yv = (k < b && c < nc) ? Ys[k * nc + (c < nc ? c : 0)] : 0.0;
-                    acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yv, acc1[q], 0, 0, 0);
-                    if (two) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yv, acc2[q], 0, 0, 0);
-                }
-            }
+            mfma_block(k0, a1, a2);
         }
     }
     // outputs, and the residual partials of this 64-row block
@@ -520,11 +571,11 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
                     const void *kern = (const void *)k_lift_mfma<TI, TO>;
                     if (!lds_set.count({ctx->device, kern})) {
                         OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     128 * 128 * (int)sizeof(double)));
+                                                     128 * 129 * (int)sizeof(double)));
                         lds_set.insert({ctx->device, kern});
                     }
                     hipLaunchKernelGGL((k_lift_mfma<TI, TO>), dim3((unsigned)((n + 63) / 64)), dim3(256),
-                                       (size_t)b * nc * sizeof(double), ctx->stream, (const TI *)V, ldv,
+                                       (size_t)b * (nc + 1) * sizeof(double), ctx->stream, (const TI *)V, ldv,
                                        (const TI *)W, ldw, n, b, nc, Y, ldy, theta, (TO *)X, (TO *)AX, ldx, res2,
                                        xn2);
                 });

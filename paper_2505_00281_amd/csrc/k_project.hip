@@ -6,6 +6,8 @@
 // 16, 16 x 24 and 24 x 24 significand bits all fit in 53), so the only
 // rounding is the FP64 accumulation: row chunks are summed per workgroup,
 // then the chunk partials are added in a fixed order (deterministic).
+#include <cstdlib>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -43,25 +45,42 @@ __global__ __launch_bounds__(256) void k_gram_partial(const TX *__restrict__ X, 
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[p][q] = pj_f64x4_t{0.0, 0.0, 0.0, 0.0};
     // PJ_D steps of four rows in flight: the loads of step s + PJ_D are
-    // issued when step s is consumed
-    double xa[PJ_D][2], yb[PJ_D][2];
-    auto fetch = [&](int64_t r0, double (&xs)[2], double (&ys)[2]) {
+    // issued when step s is consumed.  Every load is unconditional (row and
+    // column clamped into the block) and holds the stored value; the range
+    // test and the conversion to FP64 happen where the value is used, so no
+    // load waits for its data before the next ones are issued.
+    bool oki[2], okj[2];
+    int64_t ci[2], cj[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int i = i0 + 16 * p + cc, j = j0 + 16 * p + cc;
+        oki[p] = i < b1;
+        okj[p] = j < b2;
+        ci[p] = oki[p] ? i : b1 - 1;
+        cj[p] = okj[p] ? j : b2 - 1;
+    }
+    TX xr[PJ_D][2];
+    TY yr[PJ_D][2];
+    auto fetch = [&](int64_t r0, TX (&xs)[2], TY (&ys)[2]) {
         const int64_t r = r0 + kr;
-        const bool okr = r < rend;
+        const int64_t rc = r < rend ? r : rend - 1;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const int ci = i0 + 16 * p + cc, cj = j0 + 16 * p + cc;
-            xs[p] = (okr && ci < b1) ? load_as_f64(X + r * ldx + ci) : 0.0;
-            ys[p] = (okr && cj < b2) ? load_as_f64(Yb + r * ldy + cj) : 0.0;
+            xs[p] = X[rc * ldx + ci[p]];
+            ys[p] = Yb[rc * ldy + cj[p]];
         }
     };
 #pragma unroll
-    for (int st = 0; st < PJ_D; ++st) fetch(rbeg + 4 * st, xa[st], yb[st]);
+    for (int st = 0; st < PJ_D; ++st) fetch(rbeg + 4 * st, xr[st], yr[st]);
     for (int64_t r0 = rbeg; r0 < rend; r0 += 4 * PJ_D) {
 #pragma unroll
         for (int st = 0; st < PJ_D; ++st) {
-            const double a0 = xa[st][0], a1 = xa[st][1], b0 = yb[st][0], b1v = yb[st][1];
-            fetch(r0 + 4 * (st + PJ_D), xa[st], yb[st]);  // rows past rend load as zero
+            const bool okr = r0 + 4 * st + kr < rend;
+            const double a0 = (okr && oki[0]) ? load_as_f64(&xr[st][0]) : 0.0;
+            const double a1 = (okr && oki[1]) ? load_as_f64(&xr[st][1]) : 0.0;
+            const double b0 = (okr && okj[0]) ? load_as_f64(&yr[st][0]) : 0.0;
+            const double b1v = (okr && okj[1]) ? load_as_f64(&yr[st][1]) : 0.0;
+            fetch(r0 + 4 * (st + PJ_D), xr[st], yr[st]);
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -128,8 +147,15 @@ void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, c
     KTimer tm(ctx, "gram");
     const int nti = (b1 + PJ_T - 1) / PJ_T, ntj = (b2 + PJ_T - 1) / PJ_T;
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    // enough chunks to fill the chip, each at least 256 rows
-    int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (2 * cus + nti * ntj - 1) / (nti * ntj)));
+    // enough chunks to fill the chip, each at least min_rows rows
+    // (OFRR_GRAM_ROWS overrides, for tuning sweeps)
+    int64_t min_rows = 256;
+    if (const char *e = std::getenv("OFRR_GRAM_ROWS")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 32 && v <= 4096) min_rows = v;
+    }
+    int64_t nchunks = std::max<int64_t>(
+        1, std::min<int64_t>((n + min_rows - 1) / min_rows, (8 * cus + nti * ntj - 1) / (nti * ntj)));
     int64_t rows_per = (n + nchunks - 1) / nchunks;
     rows_per = (rows_per + 3) / 4 * 4;
     nchunks = (n + rows_per - 1) / rows_per;

@@ -279,9 +279,10 @@ def test_hessenberg_signed_zeros_bitwise(ctx, monkeypatch, prec, nt):
 # ------------------------------------------------------------- projection
 
 @pytest.mark.parametrize("vt", ["f64", "f32", "bf16"])
-def test_project(ctx, vt):
+@pytest.mark.parametrize("shape", [(3001, 70), (16384, 128), (5, 3)])
+def test_project(ctx, vt, shape):
     rng = np.random.default_rng(8)
-    n, b = 3001, 70
+    n, b = shape
     V = rng.standard_normal((n, b))
     Wm = rng.standard_normal((n, b))
     if vt == "bf16":
@@ -296,7 +297,7 @@ def test_project(ctx, vt):
         Wg = _cuda(Wm.astype(np.float32))
     else:
         Vg, Wg = _cuda(V), _cuda(Wm)
-    print("project", vt, flush=True)
+    print("project", vt, shape, flush=True)
     G, H = ctx.project(Vg, Wg, v_dtype=vt)
     G, H = G.cpu().numpy(), H.cpu().numpy()
     bound = 2 * n * 2.0 ** -53
