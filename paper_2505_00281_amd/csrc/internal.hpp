@@ -107,6 +107,9 @@ struct Context {
     KernelTimer timer;
     int cu_count = 0;
     int max_lds = 0;
+    // which of the two column-maximum merge arrays the next column scaling
+    // uses (-1: not cleared yet)
+    int colmax_parity = -1;
 
     template <class T>
     T *buf(const std::string &name, size_t count) {
@@ -149,6 +152,9 @@ void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X)
 // colmax[j] = max_i |Y_ij| for the n x b block (element type t, ld), then
 // Y (and Z if not null, same layout and type tz) are multiplied per column
 // by 2^-ceil(log2(colmax)); returns nothing; scale factors stay on device.
+// Clears the column-maximum merge arrays (at the start of a solve, so a
+// failed call cannot leave stale maxima behind).
+void scale_columns_reset(Context *ctx);
 void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                         ofrr_dtype tz, void *Z, int64_t ldz, float *work);
 // Row-major block helpers (element (i, j) at i*ld + j).

@@ -100,10 +100,14 @@ __global__ void k_uniform(double *X, int64_t count, uint64_t seed) {
 // per-column maxima are combined in LDS with an integer max on the float
 // bits (valid for non-negative floats, and order independent).  A NaN/Inf
 // in a column marks it with an all-ones pattern.
+// With `cmax` given, the block maxima are merged into cmax[j] (FP32 bit
+// patterns, zero on entry) by atomic maximum instead of written to `part`
+// (the maximum of bit patterns does not depend on the merge order).
 template <class T>
 __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
                                                         int64_t n, int b, int64_t rows_per_block,
-                                                        float *__restrict__ part, int nblk) {
+                                                        float *__restrict__ part, int nblk,
+                                                        unsigned *__restrict__ cmax) {
     // no atomics: for b <= 256 the block is split into 256 / b row groups,
     // thread t takes column t % b of group t / b (consecutive threads read
     // consecutive columns); wider blocks loop over columns.  Magnitudes are
@@ -136,60 +140,72 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
         if (t < b) {
             unsigned mm = 0u;
             for (int q = 0; q < groups; ++q) mm = max(mm, cm[q * b + t]);
-            part[(int64_t)t * nblk + blockIdx.x] = mm == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(mm);
+            if (cmax)
+                atomicMax(cmax + t, mm);
+            else
+                part[(int64_t)t * nblk + blockIdx.x] = mm == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(mm);
         }
     } else {
         for (int j = t; j < b; j += 256) {
             unsigned m = 0u;
             for (int64_t r = r0; r < r1; ++r) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
-            part[(int64_t)j * nblk + blockIdx.x] = m == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(m);
+            if (cmax)
+                atomicMax(cmax + j, m);
+            else
+                part[(int64_t)j * nblk + blockIdx.x] = m == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(m);
         }
     }
 }
 
-// Reduce partials of each column and turn them into power-of-two scales
-// 2^-ceil(log2(max)) (so the scaled column has infinity-norm in (1/2, 1]);
-// a zero column keeps scale 1.  NaN/Inf poison the scale (NaN).
-__global__ __launch_bounds__(256) void k_colscale(const float *__restrict__ part, int nblk, int b,
-                                                  float *__restrict__ scale) {
-    // one wavefront per column
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (j >= b) return;
-    float m = 0.f;
-    bool bad = false;
-    for (int i = lane; i < nblk; i += 64) {
-        const float v = part[(int64_t)j * nblk + i];
-        if (v != v) bad = true;
-        m = fmaxf(m, v);
-    }
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    bad = __any(bad);
-    if (lane != 0) return;
-    float s = 1.f;
-    if (bad) {
-        s = __builtin_nanf("");
-    } else if (m > 0.f) {
-        int e;
-        (void)frexpf(m, &e);  // m = mm 2^e, mm in [0.5,1): 2^-e m in [0.5, 1)
-        s = ldexpf(1.f, -e);
-    }
-    scale[j] = s;
-}
-
+// Power-of-two column scales 2^-ceil(log2(max)) (the scaled column has
+// infinity-norm in (1/2, 1]; a zero column keeps scale 1, NaN/Inf poison the
+// scale) from merged maxima (cmax[j]: FP32 bits of the column's largest
+// magnitude, all ones for NaN/Inf), applied to Y and, when given, Z;
+// workgroup 0 also zeroes clear[0..b) for the next merge.
 template <class T>
-__global__ void k_apply_scale(T *__restrict__ Y, int64_t ldy, int64_t n, int b,
-                              const float *__restrict__ scale) {
-    // grid.x over row blocks of 256 / min(b, 256) rows, threads over columns
+__global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t ldy, T *__restrict__ Z,
+                                                      int64_t ldz, int64_t n, int b,
+                                                      const unsigned *__restrict__ cmax,
+                                                      unsigned *__restrict__ clear) {
+    __shared__ float sc[512];
     const int t = threadIdx.x;
+    for (int j = t; j < b; j += 256) {
+        const unsigned mb = cmax[j];
+        float s = 1.f;
+        if (mb == 0xFFFFFFFFu) {
+            s = __builtin_nanf("");
+        } else {
+            const float m = __uint_as_float(mb);
+            if (m > 0.f) {
+                int e;
+                (void)frexpf(m, &e);
+                s = ldexpf(1.f, -e);
+            }
+        }
+        sc[j] = s;
+        if (blockIdx.x == 0) clear[j] = 0u;
+    }
+    __syncthreads();
     const int cols = b < 256 ? b : 256;
     const int groups = 256 / cols;
     const int j0 = t % cols, g = t / cols;
     if (g >= groups) return;
     for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)gridDim.x * groups)
         for (int j = j0; j < b; j += cols) {
+            const double f = (double)sc[j];
             T *p = Y + r * ldy + j;
-            store_as<T>(p, load_as_f64(p) * (double)scale[j]);
+            const double yv = load_as_f64(p);
+            if (Z) {
+                T *q = Z + r * ldz + j;
+                const double zv = load_as_f64(q);
+                store_as<T>(q, zv * f);
+            }
+            store_as<T>(p, yv * f);
         }
+}
+
+__global__ void k_zero_u32(unsigned *__restrict__ p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // row-major compaction: d[i, dest[j]] = s[i, j] for kept j
@@ -329,36 +345,40 @@ void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X)
     OFRR_HIP(hipGetLastError());
 }
 
+void scale_columns_reset(Context *ctx) {
+    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 1024);
+    hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, ctx->stream, cm2, 1024);
+    OFRR_HIP(hipGetLastError());
+    ctx->colmax_parity = 0;
+}
+
 void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                         ofrr_dtype tz, void *Z, int64_t ldz, float *work) {
     KTimer tm(ctx, "scale");
     (void)work;
     OFRR_CHECK_ARG(b <= 512, "scale_columns_pow2: b <= 512");
+    OFRR_CHECK_ARG(Z == nullptr || tz == t, "scale_columns_pow2: both blocks of one type");
     const int64_t rpb = 64;
     const int nblk = (int)((n + rpb - 1) / rpb);
-    float *part = ctx->buf<float>("colscale_work", (size_t)nblk * b + b + 64);
-    float *scale = part + (size_t)nblk * b + 32;
+    // two maxima arrays used alternately: each call merges into one and its
+    // apply kernel clears the other, which the next call merges into
+    if (ctx->colmax_parity < 0) scale_columns_reset(ctx);
+    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 1024);
+    unsigned *cur = cm2 + 512 * ctx->colmax_parity, *nxt = cm2 + 512 * (1 - ctx->colmax_parity);
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
         hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const T *)Y, ldy, n, b, rpb, part, nblk);
+                           (const T *)Y, ldy, n, b, rpb, (float *)nullptr, nblk, cur);
     });
-    hipLaunchKernelGGL(k_colscale, dim3((b + 3) / 4), dim3(256), 0, ctx->stream, part, nblk, b, scale);
     const int rows_per_wg = 256 / (b < 256 ? b : 256);
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 4096));
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
-        hipLaunchKernelGGL((k_apply_scale<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, n,
-                           b, scale);
+        hipLaunchKernelGGL((k_scale_apply2<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, (T *)Z, ldz, n,
+                           b, (const unsigned *)cur, nxt);
     });
-    if (Z) {
-        dispatch_type(tz, [&](auto *p) {
-            using T = std::remove_pointer_t<decltype(p)>;
-            hipLaunchKernelGGL((k_apply_scale<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Z, ldz,
-                               n, b, scale);
-        });
-    }
     OFRR_HIP(hipGetLastError());
+    ctx->colmax_parity ^= 1;
 }
 
 void compact_columns_rm(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *src,

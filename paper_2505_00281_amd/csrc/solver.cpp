@@ -223,6 +223,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     const double ee = cheb ? 0.5 * (plan->hi - plan->lo) : 1.0;
 
     int32_t bc = basis;  // current basis size
+    scale_columns_reset(ctx);
     bool have_ax = false;
     int iters = 0, iters_low = 0;
     StallDetector stall_det{plan->stall_iters};

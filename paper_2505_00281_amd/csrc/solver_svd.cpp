@@ -149,6 +149,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     };
 
     int32_t bv = basis;
+    scale_columns_reset(ctx);
     int iters = 0, iters_low = 0;
     double anorm = plan->anorm;
     StallDetector stall_det{plan->stall_iters};
