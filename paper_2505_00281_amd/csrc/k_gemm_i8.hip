@@ -80,12 +80,24 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
     __shared__ double red[4];
     const int64_t i = blockIdx.x;
     const int t = threadIdx.x;
+    // row i clamped into A, so every load is unconditional; eight loads in
+    // flight per thread for the row maximum
+    const int64_t ic = i < m ? i : m - 1;
     auto at = [&](int64_t k) -> double {
-        return (double)(ATRANS ? A[k + i * lda] : A[i + k * lda]);
+        return (double)(ATRANS ? A[k + ic * lda] : A[ic + k * lda]);
     };
     double amax = 0.0;
-    if (i < m)
-        for (int64_t k = t; k < kdim; k += 256) amax = fmax(amax, fabs(at(k)));
+    if (i < m) {
+        int64_t k = t;
+        for (; k + 7 * 256 < kdim; k += 8 * 256) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = at(k + 256 * u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) amax = fmax(amax, fabs(v[u]));
+        }
+        for (; k < kdim; k += 256) amax = fmax(amax, fabs(at(k)));
+    }
     for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
     if ((t & 63) == 0) red[t >> 6] = amax;
     __syncthreads();
@@ -93,12 +105,14 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
     const int e = exp_bound(amax);
     if (t == 0) ex[i] = e;
     for (int64_t k0 = (int64_t)t * 16; k0 < kpad; k0 += 256 * 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = at(k0 + q < kdim ? k0 + q : kdim - 1);
         int8_t d[I8_S][16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             int8_t dq[I8_S];
-            const int64_t k = k0 + q;
-            digits_of((i < m && k < kdim) ? at(k) : 0.0, e, dq);
+            digits_of((i < m && k0 + q < kdim) ? v[q] : 0.0, e, dq);
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
         }
@@ -170,12 +184,20 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
         const int j = (int)(e % bpad);
         const int64_t k0 = (e / bpad) * 16;
         const int f = fx[j];
-        int8_t d[I8_S][16];
+        // the sixteen loads first (clamped into the block, unconditional),
+        // the range test where the values are used
+        const int jc = j < b ? j : b - 1;
+        double v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int64_t k = k0 + q;
+            v[q] = V[(k < rows ? k : rows - 1) * ld + jc];
+        }
+        int8_t d[I8_S][16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
             int8_t dq[I8_S];
-            digits_of((j < b && k < rows) ? V[k * ld + j] : 0.0, f, dq);
+            digits_of((j < b && k0 + q < rows) ? v[q] : 0.0, f, dq);
 #pragma unroll
             for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
         }

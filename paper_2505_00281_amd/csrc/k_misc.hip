@@ -100,9 +100,12 @@ __global__ void k_uniform(double *X, int64_t count, uint64_t seed) {
 // per-column maxima are combined in LDS with an integer max on the float
 // bits (valid for non-negative floats, and order independent).  A NaN/Inf
 // in a column marks it with an all-ones pattern.
-// With `cmax` given, the block maxima are merged into cmax[j] (FP32 bit
-// patterns, zero on entry) by atomic maximum instead of written to `part`
-// (the maximum of bit patterns does not depend on the merge order).
+// With `cmax` given, the block maxima are merged into cmax[c * 512 + j]
+// (c = block index mod CM_COPIES; FP32 bit patterns, zero on entry) by atomic
+// maximum instead of written to `part` (the maximum of bit patterns does not
+// depend on the merge order; the copies spread the atomics of many blocks).
+constexpr int CM_COPIES = 4;
+
 template <class T>
 __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
                                                         int64_t n, int b, int64_t rows_per_block,
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
             unsigned mm = 0u;
             for (int q = 0; q < groups; ++q) mm = max(mm, cm[q * b + t]);
             if (cmax)
-                atomicMax(cmax + t, mm);
+                atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + t, mm);
             else
                 part[(int64_t)t * nblk + blockIdx.x] = mm == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(mm);
         }
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
             unsigned m = 0u;
             for (int64_t r = r0; r < r1; ++r) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
             if (cmax)
-                atomicMax(cmax + j, m);
+                atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + j, m);
             else
                 part[(int64_t)j * nblk + blockIdx.x] = m == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(m);
         }
@@ -160,8 +163,9 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
 // Power-of-two column scales 2^-ceil(log2(max)) (the scaled column has
 // infinity-norm in (1/2, 1]; a zero column keeps scale 1, NaN/Inf poison the
 // scale) from merged maxima (cmax[j]: FP32 bits of the column's largest
-// magnitude, all ones for NaN/Inf), applied to Y and, when given, Z;
-// workgroup 0 also zeroes clear[0..b) for the next merge.
+// magnitude, all ones for NaN/Inf; the largest of CM_COPIES copies), applied
+// to Y and, when given, Z; workgroup 0 also zeroes the copies of `clear` for
+// the next merge.
 template <class T>
 __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t ldy, T *__restrict__ Z,
                                                       int64_t ldz, int64_t n, int b,
@@ -170,7 +174,9 @@ __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t
     __shared__ float sc[512];
     const int t = threadIdx.x;
     for (int j = t; j < b; j += 256) {
-        const unsigned mb = cmax[j];
+        unsigned mb = cmax[j];
+#pragma unroll
+        for (int c = 1; c < CM_COPIES; ++c) mb = max(mb, cmax[c * 512 + j]);
         float s = 1.f;
         if (mb == 0xFFFFFFFFu) {
             s = __builtin_nanf("");
@@ -183,7 +189,9 @@ __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t
             }
         }
         sc[j] = s;
-        if (blockIdx.x == 0) clear[j] = 0u;
+        if (blockIdx.x == 0)
+#pragma unroll
+            for (int c = 0; c < CM_COPIES; ++c) clear[c * 512 + j] = 0u;
     }
     __syncthreads();
     const int cols = b < 256 ? b : 256;
@@ -346,8 +354,8 @@ void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X)
 }
 
 void scale_columns_reset(Context *ctx) {
-    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 1024);
-    hipLaunchKernelGGL(k_zero_u32, dim3(4), dim3(256), 0, ctx->stream, cm2, 1024);
+    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 2 * CM_COPIES * 512);
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, ctx->stream, cm2, 2 * CM_COPIES * 512);
     OFRR_HIP(hipGetLastError());
     ctx->colmax_parity = 0;
 }
@@ -363,15 +371,17 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
     // two maxima arrays used alternately: each call merges into one and its
     // apply kernel clears the other, which the next call merges into
     if (ctx->colmax_parity < 0) scale_columns_reset(ctx);
-    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 1024);
-    unsigned *cur = cm2 + 512 * ctx->colmax_parity, *nxt = cm2 + 512 * (1 - ctx->colmax_parity);
+    unsigned *cm2 = ctx->buf<unsigned>("colmax_merge", 2 * CM_COPIES * 512);
+    unsigned *cur = cm2 + CM_COPIES * 512 * ctx->colmax_parity;
+    unsigned *nxt = cm2 + CM_COPIES * 512 * (1 - ctx->colmax_parity);
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
         hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream,
                            (const T *)Y, ldy, n, b, rpb, (float *)nullptr, nblk, cur);
     });
+    // at most 1024 workgroups (each reads the merged maxima once)
     const int rows_per_wg = 256 / (b < 256 ? b : 256);
-    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 4096));
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 1024));
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
         hipLaunchKernelGGL((k_scale_apply2<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, (T *)Z, ldz, n,
