@@ -63,39 +63,57 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const TA *__restrict__ A, int6
 #pragma unroll
         for (int q = 0; q < 2 * NCT; ++q) acc[p][q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 
-    double ra[8], rv[VPT];
     // A: ATRANS -> thread owns row t/4 and 8 consecutive k; else k t/8 and
-    // 8 consecutive rows.  V: k t/8 and VPT consecutive columns.
+    // 8 consecutive rows.  V: k t/8 and VPT consecutive columns.  The loads
+    // are unconditional (indices clamped into the operands) and keep the
+    // stored values; the range test and the promotion to FP64 happen when
+    // the stage is written to LDS, so no load waits before the next is issued.
+    TA ra[8];
+    double rv[VPT];
+    int64_t kf = kbeg;  // first k of the stage held in ra / rv
+    auto a_index = [&](int64_t k0, int q, int64_t &gi, int64_t &gk) {
+        if (ATRANS) {
+            gi = i0 + (t >> 2);
+            gk = k0 + (t & 3) * 8 + q;
+        } else {
+            gk = k0 + (t >> 3);
+            gi = i0 + (t & 7) * 8 + q;
+        }
+    };
     auto fetch = [&](int64_t k0) {
+        kf = k0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             int64_t gi, gk;
-            if (ATRANS) {
-                gi = i0 + (t >> 2);
-                gk = k0 + (t & 3) * 8 + q;
-            } else {
-                gk = k0 + (t >> 3);
-                gi = i0 + (t & 7) * 8 + q;
-            }
-            ra[q] = (gi < m && gk < kend) ? (double)(ATRANS ? A[gk + gi * lda] : A[gi + gk * lda]) : 0.0;
+            a_index(k0, q, gi, gk);
+            const int64_t ci = gi < m ? gi : m - 1, ck = gk < kend ? gk : kend - 1;
+            ra[q] = ATRANS ? A[ck + ci * lda] : A[ci + ck * lda];
         }
         const int64_t vk = k0 + (t >> 3);
+        const int64_t cvk = vk < kend ? vk : kend - 1;
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
             const int jj = j0 + (t & 7) * VPT + q;
-            rv[q] = (vk < kend && jj < b) ? V[vk * ldv + jj] : 0.0;
+            rv[q] = V[cvk * ldv + (jj < b ? jj : b - 1)];
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
+            int64_t gi, gk;
+            a_index(kf, q, gi, gk);
+            const double v = (gi < m && gk < kend) ? (double)ra[q] : 0.0;
             if (ATRANS)
-                As[(t & 3) * 8 + q][t >> 2] = ra[q];
+                As[(t & 3) * 8 + q][t >> 2] = v;
             else
-                As[t >> 3][(t & 7) * 8 + q] = ra[q];
+                As[t >> 3][(t & 7) * 8 + q] = v;
         }
+        const int64_t vk = kf + (t >> 3);
 #pragma unroll
-        for (int q = 0; q < VPT; ++q) Vs[t >> 3][(t & 7) * VPT + q] = rv[q];
+        for (int q = 0; q < VPT; ++q) {
+            const int jj = j0 + (t & 7) * VPT + q;
+            Vs[t >> 3][(t & 7) * VPT + q] = (vk < kend && jj < b) ? rv[q] : 0.0;
+        }
     };
 
     fetch(kbeg);
