@@ -527,9 +527,9 @@ __global__ __launch_bounds__(NT) void k_hessenberg(T *__restrict__ Y, int64_t ld
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident sweep for FP32 blocks of at most 128 columns: each of
-// the NT threads (64, 128 or 256) holds one whole row of its workgroup's
-// slice in registers, so the eliminations are register fused multiply-adds on
+// Register-resident sweep for blocks of at most 128 columns (FP32, and FP64
+// with one-wave workgroups): each of the NT threads (64, 128 or 256) holds
+// one whole row of its workgroup's slice in registers, so the eliminations are register fused multiply-adds on
 // multipliers read from LDS, and only the pivot-candidate row passes through
 // LDS (to be published).  The column loop runs as eight sweeps of sixteen
 // columns with the sweep index a template parameter: the registers of the
@@ -543,14 +543,14 @@ constexpr int HR_GMAX = 256;  // workgroups (one candidate each per column) at m
 // r[base + i] for i in [0, 16): the sixteen values are passed as values and
 // picked by a select tree on the bits of i, so the register array is never
 // indexed (which would send it to scratch memory)
-__device__ __forceinline__ float hr_sel16(float x0, float x1, float x2, float x3, float x4, float x5, float x6,
-                                          float x7, float x8, float x9, float x10, float x11, float x12,
-                                          float x13, float x14, float x15, int i) {
+template <class V>
+__device__ __forceinline__ V hr_sel16(V x0, V x1, V x2, V x3, V x4, V x5, V x6, V x7, V x8, V x9, V x10, V x11,
+                                      V x12, V x13, V x14, V x15, int i) {
     const bool b0 = (i & 1) != 0, b1 = (i & 2) != 0, b2 = (i & 4) != 0, b3 = (i & 8) != 0;
-    const float a0 = b0 ? x1 : x0, a1 = b0 ? x3 : x2, a2 = b0 ? x5 : x4, a3 = b0 ? x7 : x6;
-    const float a4 = b0 ? x9 : x8, a5 = b0 ? x11 : x10, a6 = b0 ? x13 : x12, a7 = b0 ? x15 : x14;
-    const float c0 = b1 ? a1 : a0, c1 = b1 ? a3 : a2, c2 = b1 ? a5 : a4, c3 = b1 ? a7 : a6;
-    const float d0 = b2 ? c1 : c0, d1 = b2 ? c3 : c2;
+    const V a0 = b0 ? x1 : x0, a1 = b0 ? x3 : x2, a2 = b0 ? x5 : x4, a3 = b0 ? x7 : x6;
+    const V a4 = b0 ? x9 : x8, a5 = b0 ? x11 : x10, a6 = b0 ? x13 : x12, a7 = b0 ? x15 : x14;
+    const V c0 = b1 ? a1 : a0, c1 = b1 ? a3 : a2, c2 = b1 ? a5 : a4, c3 = b1 ? a7 : a6;
+    const V d0 = b2 ? c1 : c0, d1 = b2 ? c3 : c2;
     return b3 ? d1 : d0;
 }
 #define hr_pick16(r, base, i)                                                                               \
@@ -559,14 +559,16 @@ __device__ __forceinline__ float hr_sel16(float x0, float x1, float x2, float x3
              (r)[(base) + 10], (r)[(base) + 11], (r)[(base) + 12], (r)[(base) + 13], (r)[(base) + 14],        \
              (r)[(base) + 15], (i))
 
+template <class T>
 struct HRShared {
-    float *w_sh;    // multipliers of the current column (HR_B + 16, zero beyond b)
-    float *cand;    // the candidate row being published (HR_B)
-    float *red_m;   // 4 per-wave partials
+    using M = typename MagT<T>::type;
+    T *w_sh;    // multipliers of the current column (HR_B + 16, zero beyond b)
+    T *cand;    // the candidate row being published (HR_B)
+    M *red_m;   // per-wave partials
     int *red_i, *red_g;
-    int *s_win;     // [0] row, [1] workgroup
-    float *s_wmag;
-    float *s_qown;  // the candidate row's multiplier of the current column
+    int *s_win;  // [0] row, [1] workgroup
+    M *s_wmag;
+    T *s_qown;  // the candidate row's multiplier of the current column
 };
 
 struct HRArgs {
@@ -590,8 +592,9 @@ __device__ __forceinline__ bool hr_block_all(bool ok) {
 }
 
 // block-wide (magnitude, row) maximum; the same winner in every thread
-template <int NT>
-__device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared &sh, float &bm, int &bi) {
+template <int NT, class T>
+__device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared<T> &sh,
+                                                typename MagT<T>::type &bm, int &bi) {
     int unused = 0;
     wave_argmax(bm, bi, unused);
     if constexpr (NT == 64) return;
@@ -615,39 +618,45 @@ __device__ __forceinline__ void hr_block_argmax(const HRArgs &a, const HRShared 
 // the elimination of column jj - 1 in its entries past jj, which is applied
 // here (multipliers sh.w_sh, the row's multiplier *sh.s_qown), one fused
 // multiply-add per entry exactly as the row update itself does it.
-template <int NT>
-__device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared &sh, int jj, float cm, int ci,
-                                           bool pending) {
+template <int NT, class T>
+__device__ __forceinline__ void hr_publish(const HRArgs &a, const HRShared<T> &sh, int jj,
+                                           typename MagT<T>::type cm, int ci, bool pending) {
+    using M = typename MagT<T>::type;
+    constexpr int TW = NWords<T>::value, CW = NWords<M>::value + 1;
     const int bufp = jj & 1;
     const uint32_t tagp = (uint32_t)jj + 1u;
-    uint64_t *my_row = a.slot_rows + ((int64_t)bufp * a.G + a.g) * a.b;
+    uint64_t *my_row = a.slot_rows + ((int64_t)bufp * a.G + a.g) * a.b * TW;
     if (ci != 0x7fffffff) {
-        const float qo = pending ? *sh.s_qown : 0.0f;
+        const T qo = pending ? *sh.s_qown : (T)0;
         for (int c = jj + a.t; c < a.b; c += NT) {
-            float v = sh.cand[c];
+            T v = sh.cand[c];
             if (pending && c > jj) v = fma(-sh.w_sh[c], qo, v);
-            put_value<float>(my_row + c, v, tagp);
+            put_value<T>(my_row + (int64_t)c * TW, v, tagp);
         }
     }
     if (a.t == 0) {
-        uint64_t *my_cand = a.slot_cand + ((int64_t)bufp * a.G + a.g) * 2;
-        put_value<float>(my_cand, cm, tagp);
-        put_word(my_cand + 1, (uint32_t)ci, tagp);
+        uint64_t *my_cand = a.slot_cand + ((int64_t)bufp * a.G + a.g) * CW;
+        put_value<M>(my_cand, cm, tagp);
+        put_word(my_cand + CW - 1, (uint32_t)ci, tagp);
     }
 }
 
 // local candidate of column c0 + i (my row's value x): magnitude -1 and
 // row 0x7fffffff when there is no (finite, non-NaN-compared) candidate
-__device__ __forceinline__ void hr_local_cand(const HRArgs &a, float x, float &cm, int &ci) {
-    const float v = fabsf(x);
-    const bool ok = a.t < a.nrows && v > -1.0f;
-    cm = ok ? v : -1.0f;
+template <class T>
+__device__ __forceinline__ void hr_local_cand(const HRArgs &a, T x, typename MagT<T>::type &cm, int &ci) {
+    using M = typename MagT<T>::type;
+    const M v = (M)fabs(x);
+    const bool ok = a.t < a.nrows && v > (M)-1;
+    cm = ok ? v : (M)-1;
     ci = ok ? (int)(a.r0 + a.t) : 0x7fffffff;
 }
 
-template <int NT, int JV>
-__device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, const HRShared &sh, float &cm,
-                                         int &ci, int &kept) {
+template <class T, int NT, int JV>
+__device__ __forceinline__ bool hr_sweep(T (&row)[HR_B], const HRArgs &a, const HRShared<T> &sh,
+                                         typename MagT<T>::type &cm, int &ci, int &kept) {
+    using M = typename MagT<T>::type;
+    constexpr int TW = NWords<T>::value, CW = NWords<M>::value + 1;
     const bool valid = a.t < a.nrows;
     const int myrow = (int)(a.r0 + a.t);
     for (int jj = 0; jj < 16; ++jj) {
@@ -656,31 +665,34 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
         const int buf = j & 1;
         const uint32_t tag = (uint32_t)j + 1u;
         // 1. every candidate of column j (CPL per thread, all polled at once)
-        float wmag;
+        M wmag;
         int wrow, wg;
         {
             constexpr int CPL = (HR_GMAX + NT - 1) / NT;
-            const uint64_t *src[2 * CPL];
-            bool use[2 * CPL];
-            uint32_t cw[2 * CPL];
+            const uint64_t *src[CW * CPL];
+            bool use[CW * CPL];
+            uint32_t cw[CW * CPL];
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
                 const int h = a.t + q * NT;
                 const bool u = h < a.G;
-                src[2 * q] = a.slot_cand + ((int64_t)buf * a.G + (u ? h : 0)) * 2;
-                src[2 * q + 1] = src[2 * q] + 1;
-                use[2 * q] = use[2 * q + 1] = u;
+                const uint64_t *base = a.slot_cand + ((int64_t)buf * a.G + (u ? h : 0)) * CW;
+#pragma unroll
+                for (int w = 0; w < CW; ++w) {
+                    src[CW * q + w] = base + w;
+                    use[CW * q + w] = u;
+                }
             }
-            const bool ok = get_words_at<2 * CPL>(src, use, tag, cw, a.err);
+            const bool ok = get_words_at<CW * CPL>(src, use, tag, cw, a.err);
             if (!hr_block_all<NT>(ok)) return false;
-            float bm = -1.0f;
+            M bm = (M)-1;
             int bi = 0x7fffffff, bg = -1;
 #pragma unroll
             for (int q = 0; q < CPL; ++q) {
-                float m2;
-                __builtin_memcpy(&m2, &cw[2 * q], sizeof(float));
-                const int i2 = (int)cw[2 * q + 1];
-                if (use[2 * q] && (m2 > bm || (m2 == bm && i2 < bi))) {
+                M m2;
+                __builtin_memcpy(&m2, &cw[CW * q], sizeof(M));
+                const int i2 = (int)cw[CW * q + CW - 1];
+                if (use[CW * q] && (m2 > bm || (m2 == bm && i2 < bi))) {
                     bm = m2;
                     bi = i2;
                     bg = a.t + q * NT;
@@ -699,7 +711,7 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
                 }
                 __syncthreads();
                 if (a.t == 0) {
-                    float m = sh.red_m[0];
+                    M m = sh.red_m[0];
                     int i = sh.red_i[0], gg = sh.red_g[0];
                     for (int w = 1; w < NT / 64; ++w)
                         if (sh.red_m[w] > m || (sh.red_m[w] == m && sh.red_i[w] < i)) {
@@ -717,13 +729,13 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
                 wg = sh.s_win[1];
             }
         }
-        const bool take = (wmag >= (float)a.tol) && (wmag > 0.0f) && wg >= 0;
+        const bool take = (wmag >= (M)a.tol) && (wmag > (M)0) && wg >= 0;
         if (a.g == 0 && a.t == 0) {
             a.piv[j] = take ? wrow : -1;
             a.keep[j] = take ? 1 : 0;
         }
         // column j + 1 of my row (static index through the select tree)
-        auto col_next = [&]() -> float {
+        auto col_next = [&]() -> T {
             if constexpr (JV < 7) return (jj == 15) ? row[16 * JV + 16] : hr_pick16(row, 16 * JV, (jj + 1) & 15);
             else return hr_pick16(row, 16 * JV, (jj + 1) & 15);
         };
@@ -746,38 +758,42 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
         // of a thread's words polled at once)
         {
             constexpr int CPR = (HR_B + NT - 1) / NT;
-            const uint64_t *win_row = a.slot_rows + ((int64_t)buf * a.G + wg) * a.b;
-            const uint64_t *src[CPR];
-            bool use[CPR];
-            uint32_t rw[CPR];
+            const uint64_t *win_row = a.slot_rows + ((int64_t)buf * a.G + wg) * a.b * TW;
+            const uint64_t *src[CPR * TW];
+            bool use[CPR * TW];
+            uint32_t rw[CPR * TW];
 #pragma unroll
             for (int q = 0; q < CPR; ++q) {
                 const int c = j + a.t + q * NT;
-                use[q] = c < a.b;
-                src[q] = win_row + (use[q] ? c : j);
+                const bool u = c < a.b;
+#pragma unroll
+                for (int w = 0; w < TW; ++w) {
+                    src[TW * q + w] = win_row + (int64_t)(u ? c : j) * TW + w;
+                    use[TW * q + w] = u;
+                }
             }
-            const bool ok = get_words_at<CPR>(src, use, tag, rw, a.err);
+            const bool ok = get_words_at<CPR * TW>(src, use, tag, rw, a.err);
 #pragma unroll
             for (int q = 0; q < CPR; ++q)
-                if (use[q]) __builtin_memcpy(&sh.w_sh[j + a.t + q * NT], &rw[q], sizeof(float));
+                if (use[TW * q]) __builtin_memcpy(&sh.w_sh[j + a.t + q * NT], &rw[TW * q], sizeof(T));
             if (!hr_block_all<NT>(ok)) return false;
         }
-        const float pivot = sh.w_sh[j];
-        const float q = valid ? hr_pick16(row, 16 * JV, jj) / pivot : 0.0f;
+        const T pivot = sh.w_sh[j];
+        const T q = valid ? hr_pick16(row, 16 * JV, jj) / pivot : (T)0;
         // columns j + 2 .. b - 1 of a row (the finished columns of this
         // sweep are kept by a select; from column 16 JV + 17 on every column
         // is past j + 1)
         auto eliminate = [&]() {
 #pragma unroll
             for (int c = 16 * JV; c < HR_B; ++c) {
-                const float r = fma(-sh.w_sh[c], q, row[c]);
+                const T r = fma(-sh.w_sh[c], q, row[c]);
                 if (c < 16 * JV + 17) row[c] = (c > j + 1) ? r : row[c];
                 else row[c] = r;
             }
         };
         if (j + 1 < a.b) {
             // 3. column j+1 of every row and the local candidate of column j+1
-            const float y = fma(-sh.w_sh[j + 1], q, col_next());
+            const T y = fma(-sh.w_sh[j + 1], q, col_next());
 #pragma unroll
             for (int c = 16 * JV; c < HR_B && c < 16 * JV + 17; ++c) row[c] = (c == j + 1) ? y : row[c];
             hr_local_cand(a, y, cm, ci);
@@ -802,19 +818,20 @@ __device__ __forceinline__ bool hr_sweep(float (&row)[HR_B], const HRArgs &a, co
     return true;
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, int64_t ldy, int64_t n, int b,
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_hessenberg_reg(T *__restrict__ Y, int64_t ldy, int64_t n, int b,
                                                           double tol, int32_t *__restrict__ piv,
                                                           int32_t *__restrict__ keep,
                                                           uint64_t *__restrict__ slot_rows,
                                                           uint64_t *__restrict__ slot_cand, int *__restrict__ err,
                                                           int32_t *__restrict__ kept_out) {
-    __shared__ __attribute__((aligned(16))) float w_sh[HR_B + 16];
-    __shared__ float cand[HR_B];
-    __shared__ float red_m[NT / 64];
+    using M = typename MagT<T>::type;
+    __shared__ __attribute__((aligned(16))) T w_sh[HR_B + 16];
+    __shared__ T cand[HR_B];
+    __shared__ M red_m[NT / 64];
     __shared__ int red_i[NT / 64], red_g[NT / 64];
     __shared__ int s_win[2];
-    __shared__ float s_wmag;
+    __shared__ M s_wmag;
     HRArgs a;
     a.b = b;
     a.G = gridDim.x;
@@ -831,18 +848,18 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, in
     a.slot_rows = slot_rows;
     a.slot_cand = slot_cand;
     a.err = err;
-    __shared__ float s_qown;
-    HRShared sh{w_sh, cand, red_m, red_i, red_g, s_win, &s_wmag, &s_qown};
+    __shared__ T s_qown;
+    HRShared<T> sh{w_sh, cand, red_m, red_i, red_g, s_win, &s_wmag, &s_qown};
 
     const bool valid = a.t < a.nrows;
-    float row[HR_B];
+    T row[HR_B];
     {
-        const float *src = Y + (a.r0 + (valid ? a.t : 0)) * ldy;
+        const T *src = Y + (a.r0 + (valid ? a.t : 0)) * ldy;
 #pragma unroll
-        for (int c = 0; c < HR_B; ++c) row[c] = (valid && c < b) ? src[c < b ? c : 0] : 0.0f;
+        for (int c = 0; c < HR_B; ++c) row[c] = (valid && c < b) ? src[c < b ? c : 0] : (T)0;
     }
-    for (int c = b + a.t; c < HR_B + 16; c += NT) w_sh[c] = 0.0f;
-    float cm;
+    for (int c = b + a.t; c < HR_B + 16; c += NT) w_sh[c] = (T)0;
+    M cm;
     int ci;
     hr_local_cand(a, row[0], cm, ci);
     hr_block_argmax<NT>(a, sh, cm, ci);
@@ -854,13 +871,13 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(float *__restrict__ Y, in
     hr_publish<NT>(a, sh, 0, cm, ci, false);
 
     int kept = 0;
-    const bool ok = hr_sweep<NT, 0>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 1>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<NT, 2>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 3>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<NT, 4>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 5>(row, a, sh, cm, ci, kept) &&
-                    hr_sweep<NT, 6>(row, a, sh, cm, ci, kept) && hr_sweep<NT, 7>(row, a, sh, cm, ci, kept);
+    const bool ok = hr_sweep<T, NT, 0>(row, a, sh, cm, ci, kept) && hr_sweep<T, NT, 1>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<T, NT, 2>(row, a, sh, cm, ci, kept) && hr_sweep<T, NT, 3>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<T, NT, 4>(row, a, sh, cm, ci, kept) && hr_sweep<T, NT, 5>(row, a, sh, cm, ci, kept) &&
+                    hr_sweep<T, NT, 6>(row, a, sh, cm, ci, kept) && hr_sweep<T, NT, 7>(row, a, sh, cm, ci, kept);
     (void)ok;
     if (valid) {
-        float *dst = Y + (a.r0 + a.t) * ldy;
+        T *dst = Y + (a.r0 + a.t) * ldy;
 #pragma unroll
         for (int c = 0; c < HR_B; ++c)
             if (c < b) dst[c] = row[c];
@@ -876,8 +893,8 @@ __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
         words[i] = 0;
 }
 
-template <int NT>
-int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, double tol, int32_t *piv,
+template <class T, int NT>
+int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv,
                 int32_t *keep, const int32_t **status) {
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     const int64_t G64 = (n + NT - 1) / NT;
@@ -885,7 +902,8 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
     // same word buffer layout as the LDS kernel: [0] error flag and kept
     // count, candidate slots (2 x G x 2 words), row slots (2 x G x b words)
     const int G = (int)G64;
-    const int64_t ncand = (int64_t)2 * G * 2, nrow = (int64_t)2 * G * b;
+    constexpr int TW = NWords<T>::value, CW = NWords<typename MagT<T>::type>::value + 1;
+    const int64_t ncand = (int64_t)2 * G * CW, nrow = (int64_t)2 * G * b * TW;
     const int64_t nwords = 1 + ncand + nrow;
     uint64_t *words = ctx->buf<uint64_t>("hess_words", (size_t)nwords);
     int *err = reinterpret_cast<int *>(words);
@@ -896,7 +914,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
     auto it = occ.find(ctx->device);
     if (it == occ.end()) {
         int pc = 0;
-        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg<NT>, NT, 0));
+        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg<T, NT>, NT, 0));
         it = occ.emplace(ctx->device, pc).first;
     }
     if (G64 > (int64_t)it->second * cus) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
@@ -906,7 +924,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, float *Y, int64_t ldy, doubl
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &slot_rows, &slot_cand, &err, &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
-        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg<NT>, dim3(G), dim3(NT), args, 0,
+        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg<T, NT>, dim3(G), dim3(NT), args, 0,
                                             ctx->stream));
     }
     if (status) {
@@ -937,7 +955,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         if (kb >= 8 && kb <= 150) lds_budget = (size_t)kb * 1024;
     }
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    // FP32 blocks of at most 128 columns: one row per thread in registers
+    // blocks of at most 128 columns: one row per thread in registers
     // (OFRR_HESS_REG=0 selects the LDS kernel, for comparisons)
     // rows per workgroup: the smallest of 64, 128, 256 (at least
     // OFRR_HESS_REG_NT, for comparisons) that keeps the slices within
@@ -951,13 +969,20 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         if (v == 64 || v == 128 || v == 256) rnt = v;
     }
     while (rnt < 256 && (n + rnt - 1) / rnt > HR_GMAX) rnt *= 2;
-    bool use_reg = std::is_same<T, float>::value && b <= HR_B && (n + rnt - 1) / rnt <= HR_GMAX;
+    // FP64 rows take 256 registers per thread (plus accumulation registers
+    // for the rest): faster than the LDS kernel only with one-wave
+    // workgroups (n = 16384, b = 128: 0.60 ms against 0.72 ms; 0.67 and
+    // 0.77 ms at 128 and 256 rows, measured).  OFRR_HESS_REG64=0|1 forces
+    // the choice, for comparisons.
+    bool reg_type = std::is_same<T, float>::value || rnt == 64;
+    if (const char *s = std::getenv("OFRR_HESS_REG64"))
+        reg_type = std::is_same<T, float>::value || std::atoi(s) != 0;
+    bool use_reg = reg_type && b <= HR_B && (n + rnt - 1) / rnt <= HR_GMAX;
     if (const char *s = std::getenv("OFRR_HESS_REG")) use_reg = use_reg && std::atoi(s) != 0;
     if (use_reg) {
-        float *Yf = reinterpret_cast<float *>(Y);
-        if (rnt == 64) return run_reg<64>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
-        if (rnt == 128) return run_reg<128>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
-        return run_reg<256>(ctx, n, b, Yf, ldy, tol, piv, keep, status);
+        if (rnt == 64) return run_reg<T, 64>(ctx, n, b, Y, ldy, tol, piv, keep, status);
+        if (rnt == 128) return run_reg<T, 128>(ctx, n, b, Y, ldy, tol, piv, keep, status);
+        return run_reg<T, 256>(ctx, n, b, Y, ldy, tol, piv, keep, status);
     }
     const int vec = 16 / (int)sizeof(T);
     const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS

@@ -212,6 +212,26 @@ def test_hessenberg_matches_oracle_bitwise(ctx, prec, shape):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16384, 128), (5000, 64)])
+def test_hessenberg_lds_kernel_matches_oracle(ctx, monkeypatch, prec, shape):
+    # the LDS-resident sweep (the one for blocks the register kernel does not
+    # take), forced on shapes the register kernel would otherwise run
+    monkeypatch.setenv("OFRR_HESS_REG", "0")
+    n, b = shape
+    rng = np.random.default_rng(13)
+    dt = np.float64 if prec == "f64" else np.float32
+    Y = rng.random((n, b)).astype(dt)
+    tol = 2.0 ** -52 if prec == "f64" else 2.0 ** -23
+    print("hessenberg lds kernel", prec, shape, flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_hessenberg_drops_like_oracle(ctx, prec):
     rng = np.random.default_rng(7)
     n, b = 3000, 12
@@ -232,31 +252,37 @@ def test_hessenberg_drops_like_oracle(ctx, prec):
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("nt", ["64", "128", "256"])
 @pytest.mark.parametrize("shape", [(16384, 128), (3000, 77), (130, 5)])
-def test_hessenberg_register_widths(ctx, monkeypatch, nt, shape):
-    # the FP32 register sweep at each workgroup width gives the oracle's
-    # pivots and factor bit for bit (ragged last slice included)
+def test_hessenberg_register_widths(ctx, monkeypatch, prec, nt, shape):
+    # the register sweep (FP32 and FP64 rows) at each workgroup width gives
+    # the oracle's pivots and factor bit for bit (ragged last slice included)
     n, b = shape
     monkeypatch.setenv("OFRR_HESS_REG_NT", nt)
+    monkeypatch.setenv("OFRR_HESS_REG64", "1")
     rng = np.random.default_rng(11)
-    Y = rng.standard_normal((n, b)).astype(np.float32)
-    tol = 2.0 ** -23
-    print("hessenberg register width", nt, shape, flush=True)
+    dt = np.float32 if prec == "f32" else np.float64
+    Y = rng.standard_normal((n, b)).astype(dt)
+    tol = 2.0 ** -23 if prec == "f32" else 2.0 ** -52
+    print("hessenberg register width", prec, nt, shape, flush=True)
     Yg = torch.from_numpy(Y.copy()).cuda()
     piv, keep, kept = ctx.hessenberg(Yg, tol)
-    Q, p_ref, k_ref = O.hessenberg(Y, tol, "f32")
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
     np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
     np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 
-@pytest.mark.parametrize("prec,nt", [("f32", "64"), ("f32", "256"), ("f64", None)])
+@pytest.mark.parametrize("prec,nt", [("f32", "64"), ("f32", "256"), ("f64", "64"), ("f64", "lds"),
+                                     ("f32", "lds")])
 def test_hessenberg_signed_zeros_bitwise(ctx, monkeypatch, prec, nt):
     # negative zeros in the input: finished columns keep their sign of zero
     # and updated ones get the fused multiply-add's, as in the oracle
     # (compared as bit patterns, where -0.0 == 0.0 would hide a difference)
-    if nt is not None:
+    if nt == "lds":
+        monkeypatch.setenv("OFRR_HESS_REG", "0")
+    else:
         monkeypatch.setenv("OFRR_HESS_REG_NT", nt)
     rng = np.random.default_rng(12)
     n, b = 3000, 40
