@@ -156,41 +156,41 @@ struct LiftVec<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
 };
 
-template <class TI, class TO>
+constexpr int LF_LDK = 129;  // LDS row stride of the coefficients (128 columns + 1)
+
+template <class TI, class TO, bool TWO>
 __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, int64_t ld1,
                                                    const TI *__restrict__ In2, int64_t ld2, int64_t n, int b,
                                                    int nc, const double *__restrict__ S, int lds,
                                                    const double *__restrict__ theta, TO *__restrict__ Out1,
                                                    TO *__restrict__ Out2, int64_t ldo, double *__restrict__ res2,
                                                    double *__restrict__ xn2) {
-    extern __shared__ __attribute__((aligned(16))) double Ys[];  // [k][c], b x nc, row stride nc + 1
+    extern __shared__ __attribute__((aligned(16))) double Ys[];  // [k][c], kpad x 128, row stride LF_LDK
     __shared__ double red[2][4][128];
     typedef typename LiftVec<TI>::v4 v4;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, cl = lane & 15;
-    const bool two = In2 != nullptr;
-    // Y (column-major, leading dimension lds) into LDS as [k][c]: consecutive
-    // threads read consecutive k of a column (coalesced), eight loads in
-    // flight per thread; the odd row stride nc + 1 spreads both the stores
-    // (consecutive k) and the MFMA operand reads (consecutive c) over the banks
-    const int ldk = nc + 1;
+    constexpr bool two = TWO;
+    // Y (column-major, leading dimension lds) into LDS as [k][c], zero-padded
+    // to kpad = 16 ceil(b / 16) rows and 128 columns, so every operand read
+    // below is unconditional: consecutive threads read consecutive k of a
+    // column (coalesced), eight loads in flight per thread; the odd row
+    // stride spreads both the stores and the MFMA operand reads over the banks
+    const int kpad = (b + 15) / 16 * 16;
     {
-        const int tot = b * nc;
+        const int tot = kpad * 128;
         for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
             double v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = e0 + 256 * u + t;
-                const int ee = e < tot ? e : tot - 1;
-                const int c = ee / b, k = ee - c * b;
-                v[u] = S[k + (int64_t)c * lds];
+                const int c = e / kpad, k = e - c * kpad;
+                v[u] = S[(k < b ? k : b - 1) + (int64_t)(c < nc ? c : nc - 1) * lds];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = e0 + 256 * u + t;
-                if (e < tot) {
-                    const int c = e / b, k = e - c * b;
-                    Ys[k * ldk + c] = v[u];
-                }
+                const int c = e / kpad, k = e - c * kpad;
+                if (e < tot) Ys[k * LF_LDK + c] = (k < b && c < nc) ? v[u] : 0.0;
             }
         }
     }
@@ -206,14 +206,15 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * g + s;
+            // all eight column tiles (the padding is zero): the operand reads
+            // are static and unconditional, so they are issued together
+            double yq[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) yq[q] = Ys[k * LF_LDK + 16 * q + cl];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                if (q < ntile) {
-                    const int c = 16 * q + cl;
-                    const double yv = (k < b && c < nc) ? Ys[k * ldk + (c < nc ? c : 0)] : 0.0;
-                    acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yv, acc1[q], 0, 0, 0);
-                    if (two) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yv, acc2[q], 0, 0, 0);
-                }
+                acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yq[q], acc1[q], 0, 0, 0);
+                if constexpr (TWO) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yq[q], acc2[q], 0, 0, 0);
             }
         }
     };
@@ -568,16 +569,22 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
             if constexpr (std::is_same<TI, float>::value || std::is_same<TI, double>::value) {
                 dispatch_t(xt, [&](auto *op) {
                     using TO = std::remove_pointer_t<decltype(op)>;
-                    const void *kern = (const void *)k_lift_mfma<TI, TO>;
-                    if (!lds_set.count({ctx->device, kern})) {
-                        OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     128 * 129 * (int)sizeof(double)));
-                        lds_set.insert({ctx->device, kern});
-                    }
-                    hipLaunchKernelGGL((k_lift_mfma<TI, TO>), dim3((unsigned)((n + 63) / 64)), dim3(256),
-                                       (size_t)b * (nc + 1) * sizeof(double), ctx->stream, (const TI *)V, ldv,
-                                       (const TI *)W, ldw, n, b, nc, Y, ldy, theta, (TO *)X, (TO *)AX, ldx, res2,
-                                       xn2);
+                    auto launch = [&](auto kernel) {
+                        const void *kern = (const void *)kernel;
+                        if (!lds_set.count({ctx->device, kern})) {
+                            OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                         128 * LF_LDK * (int)sizeof(double)));
+                            lds_set.insert({ctx->device, kern});
+                        }
+                        const size_t shmem = (size_t)((b + 15) / 16 * 16) * LF_LDK * sizeof(double);
+                        hipLaunchKernelGGL(kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), shmem, ctx->stream,
+                                           (const TI *)V, ldv, (const TI *)W, ldw, n, b, nc, Y, ldy, theta,
+                                           (TO *)X, (TO *)AX, ldx, res2, xn2);
+                    };
+                    if (W)
+                        launch(k_lift_mfma<TI, TO, true>);
+                    else
+                        launch(k_lift_mfma<TI, TO, false>);
                 });
             }
         });
