@@ -865,15 +865,17 @@ __device__ __forceinline__ void fwd_solve_q4(const double *S, int n, double (&x)
     const int sl = threadIdx.x & 3;
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
+        if (4 * q >= n) break;  // one uniform test per block of four rows
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int i = 4 * q + s;
-            if (i < n) {
-                const double xi = quad_bcast(x[q] * invd[i], s);
+            // rows past n in the last block: invd and the padded L are zero,
+            // so xi = 0 and every update adds a zero (values unchanged up to
+            // the sign of a zero); no branch inside the block
+            const double xi = quad_bcast(x[q] * invd[i], s);
 #pragma unroll
-                for (int q2 = q; q2 < 32; ++q2) x[q2] = fma(-S[sl + 4 * q2 + i * FP_LD], xi, x[q2]);
-                if (sl == s) x[q] = xi;
-            }
+            for (int q2 = q; q2 < 32; ++q2) x[q2] = fma(-S[sl + 4 * q2 + i * FP_LD], xi, x[q2]);
+            if (sl == s) x[q] = xi;
         }
     }
 }
@@ -885,12 +887,11 @@ __device__ __forceinline__ void bwd_solve_q4(const double *S, int n, double (&x)
 #pragma unroll
         for (int s = 3; s >= 0; --s) {
             const int i = 4 * q + s;
-            if (i < n) {
-                const double xi = quad_bcast(x[q] * invd[i], s);
+            // rows past n: as in the forward solve, no change and no branch
+            const double xi = quad_bcast(x[q] * invd[i], s);
 #pragma unroll
-                for (int q2 = 0; q2 <= q; ++q2) x[q2] = fma(-S[i + (sl + 4 * q2) * FP_LD], xi, x[q2]);
-                if (sl == s) x[q] = xi;
-            }
+            for (int q2 = 0; q2 <= q; ++q2) x[q2] = fma(-S[i + (sl + 4 * q2) * FP_LD], xi, x[q2]);
+            if (sl == s) x[q] = xi;
         }
     }
 }
