@@ -225,6 +225,7 @@ ofrr_status ofrr_destroy(ofrr_ctx ctx) {
     (void)hipStreamSynchronize(ctx->c.stream);
     ctx->c.ws.release_all();
     if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+    if (ctx->c.sync_ev) (void)hipEventDestroy(ctx->c.sync_ev);
     for (auto e : ctx->c.timer.pool) (void)hipEventDestroy(e);
     for (auto &p : ctx->c.timer.pending) {
         (void)hipEventDestroy(p.a);

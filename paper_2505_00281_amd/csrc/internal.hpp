@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <cstdlib>
 #include <string>
 #include <algorithm>
 #include <cmath>
@@ -115,7 +116,29 @@ struct Context {
     T *buf(const std::string &name, size_t count) {
         return static_cast<T *>(ws.get(name, count * sizeof(T) + 256));
     }
-    void sync() { OFRR_HIP(hipStreamSynchronize(stream)); }
+    // Waits for the stream by polling an event: a spinning host thread sees
+    // the completion sooner than a blocking wait, which matters for the one
+    // small readback per outer iteration (OFRR_SYNC_BLOCKING=1 restores
+    // hipStreamSynchronize, for comparisons).
+    hipEvent_t sync_ev = nullptr;
+    int sync_blocking = -1;
+    void sync() {
+        if (sync_blocking < 0) {
+            const char *e = std::getenv("OFRR_SYNC_BLOCKING");
+            sync_blocking = (e && std::atoi(e) != 0) ? 1 : 0;
+        }
+        if (sync_blocking) {
+            OFRR_HIP(hipStreamSynchronize(stream));
+            return;
+        }
+        if (!sync_ev) OFRR_HIP(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
+        OFRR_HIP(hipEventRecord(sync_ev, stream));
+        for (;;) {
+            const hipError_t e = hipEventQuery(sync_ev);
+            if (e == hipSuccess) return;
+            if (e != hipErrorNotReady) OFRR_HIP(e);
+        }
+    }
     // pinned host staging for small per-iteration readbacks (grows on demand,
     // freed with the context)
     void *pinned = nullptr;

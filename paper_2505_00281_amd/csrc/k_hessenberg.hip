@@ -885,6 +885,22 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(T *__restrict__ Y, int64_
     if (a.g == 0 && a.t == 0 && kept_out) *kept_out = kept;
 }
 
+// The sweeps exchange data between all workgroups of the grid, so every
+// workgroup must be resident: a cooperative launch guarantees it.
+// OFRR_HESS_COOP=0 launches plainly instead, for comparisons (the grid is
+// sized to the occupancy either way, and every wait is bounded and ends in
+// an error rather than a hang); measured, the plain launch saved nothing on
+// the whole call.
+inline hipError_t launch_resident(const void *kern, dim3 grid, dim3 block, void **args, size_t shmem,
+                                  hipStream_t stream) {
+    static const bool coop = [] {
+        const char *e = std::getenv("OFRR_HESS_COOP");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return coop ? hipLaunchCooperativeKernel(kern, grid, block, args, (unsigned)shmem, stream)
+                : hipLaunchKernel(kern, grid, block, args, shmem, stream);
+}
+
 // Clears the error flag, the kept count and every tagged slot word (a
 // kernel, not a memset, so the sweep can be captured in a graph).
 __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
@@ -924,8 +940,7 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double to
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &slot_rows, &slot_cand, &err, &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
-        OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_hessenberg_reg<T, NT>, dim3(G), dim3(NT), args, 0,
-                                            ctx->stream));
+        OFRR_HIP(launch_resident((const void *)k_hessenberg_reg<T, NT>, dim3(G), dim3(NT), args, 0, ctx->stream));
     }
     if (status) {
         *status = err;
@@ -1057,7 +1072,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
                     &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
-        OFRR_HIP(hipLaunchCooperativeKernel(kern, dim3(G), dim3(nt), args, (unsigned)shmem, ctx->stream));
+        OFRR_HIP(launch_resident(kern, dim3(G), dim3(nt), args, shmem, ctx->stream));
     }
     if (status) {
         *status = err;
