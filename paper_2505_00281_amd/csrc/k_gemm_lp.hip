@@ -236,12 +236,23 @@ __global__ __launch_bounds__(256) void k_split_t(const float *__restrict__ s, in
     const int t = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int rr = (t >> 6) + 4 * q, cc = t & 63;
-        const int64_t gi = i0 + rr;
+    // sixteen unconditional loads (indices clamped into the block) in flight,
+    // the range test when the tile is written
+    {
+        const int cc = t & 63;
         const int gj = j0 + cc;
-        tile[rr][cc] = (gi < rows && gj < b) ? s[gi * ld + gj] : 0.f;
+        const int gjc = gj < b ? gj : b - 1;
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t gi = i0 + (t >> 6) + 4 * q;
+            v[q] = s[(gi < rows ? gi : rows - 1) * ld + gjc];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int rr = (t >> 6) + 4 * q;
+            tile[rr][cc] = (i0 + rr < rows && gj < b) ? v[q] : 0.f;
+        }
     }
     __syncthreads();
     // thread -> column j0 + (t >> 3), rows i0 + 8 (t & 7) .. + 8
