@@ -111,6 +111,8 @@ struct Context {
     // which of the two column-maximum merge arrays the next column scaling
     // uses (-1: not cleared yet)
     int colmax_parity = -1;
+    // the same for the merged column maxima of the digit-plane slicing
+    int vmax_parity = -1;
 
     template <class T>
     T *buf(const std::string &name, size_t count) {

@@ -122,12 +122,21 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
     }
 }
 
-// Column-maximum partials of an FP64 row-major block (rows x b, ld) over
-// 64-row blocks: part[j * nblk + g].  For b <= 256 the 256 threads split
+constexpr int VM_COPIES = 4;    // copies of the merged column maxima
+constexpr int VM_STRIDE = 4096;  // entries per copy (b <= 4096)
+
+__global__ void k_zero_u64(unsigned long long *__restrict__ p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+// Column maxima of an FP64 row-major block (rows x b, ld) over 64-row
+// blocks, merged by atomic maximum of the (non-negative) FP64 bit patterns
+// into cmax[c * VM_STRIDE + j], c = block index mod VM_COPIES (zero on
+// entry; the maximum does not depend on the merge order).  For b <= 256 the 256 threads split
 // into 256 / b row groups over the block's rows (consecutive threads read
 // consecutive columns), loads unrolled by 8.
 __global__ __launch_bounds__(256) void k_vmax_partial(const double *__restrict__ V, int64_t rows, int b,
-                                                      int64_t ld, int nblk, double *__restrict__ part) {
+                                                      int64_t ld, unsigned long long *__restrict__ cmax) {
     __shared__ double cm[256];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * 64;
@@ -153,37 +162,35 @@ __global__ __launch_bounds__(256) void k_vmax_partial(const double *__restrict__
         if (t < cols) {
             double mm = 0.0;
             for (int q = 0; q < groups; ++q) mm = fmax(mm, cm[q * cols + t]);
-            part[(int64_t)(jb + t) * nblk + blockIdx.x] = mm;
+            atomicMax(cmax + (blockIdx.x % VM_COPIES) * VM_STRIDE + jb + t, (unsigned long long)__double_as_longlong(mm));
         }
         __syncthreads();
     }
-}
-
-// exponent bound of each column from its partials, one wavefront per
-// column (columns b..bpad-1 get 0)
-__global__ __launch_bounds__(256) void k_vexp(const double *__restrict__ part, int nblk, int b, int bpad,
-                                              int32_t *__restrict__ fx) {
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (j >= bpad) return;
-    double m = 0.0;
-    if (j < b)
-        for (int g = lane; g < nblk; g += 64) m = fmax(m, part[(int64_t)j * nblk + g]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (lane == 0) fx[j] = exp_bound(m);
 }
 
 // Digit planes of V, K-contiguous per column: planes[s][j][k], 16 rows of
 // one column per thread (columns past b and rows past `rows` are zero).
 __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, int64_t rows, int b,
                                                 int64_t ld, int bpad, int64_t kpad,
-                                                const int32_t *__restrict__ fx,
+                                                const unsigned long long *__restrict__ cmax,
+                                                unsigned long long *__restrict__ clear,
+                                                int32_t *__restrict__ fx,
                                                 int8_t *__restrict__ planes, int64_t plane_stride) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gstride = (int64_t)gridDim.x * blockDim.x;
+    // the other merge arrays, for the next call
+    for (int64_t e = gid; e < (int64_t)VM_COPIES * bpad; e += gstride)
+        clear[(e / bpad) * VM_STRIDE + e % bpad] = 0ull;
     const int64_t total = (int64_t)bpad * (kpad / 16);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = gid; e < total; e += gstride) {
         const int j = (int)(e % bpad);
         const int64_t k0 = (e / bpad) * 16;
-        const int f = fx[j];
+        // the column's exponent bound from its merged maximum (columns past
+        // b have none: 0); written out once for the product
+        unsigned long long mb = 0ull;
+#pragma unroll
+        for (int c = 0; c < VM_COPIES; ++c) mb = max(mb, cmax[c * VM_STRIDE + j]);
+        const int f = exp_bound(__longlong_as_double((long long)mb));
+        if (k0 == 0) fx[j] = f;
         // the sixteen loads first (clamped into the block, unconditional),
         // the range test where the values are used
         const int jc = j < b ? j : b - 1;
@@ -377,16 +384,23 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
     int8_t *vp = ctx->buf<int8_t>("i8_v_planes", (size_t)I8_S * v_stride);
     int32_t *fx = ctx->buf<int32_t>("i8_v_exp", (size_t)bpad);
     const int nblk = (int)((sa.kdim + 63) / 64);
-    double *part = ctx->buf<double>("i8_v_part", (size_t)nblk * b);
+    // column maxima merged into one of two alternating sets of arrays; the
+    // slicing kernel clears the other set, which the next call merges into
+    unsigned long long *vm = ctx->buf<unsigned long long>("i8_v_merge", (size_t)2 * VM_COPIES * VM_STRIDE);
+    if (ctx->vmax_parity < 0) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, ctx->stream, vm, 2 * VM_COPIES * VM_STRIDE);
+        ctx->vmax_parity = 0;
+    }
+    unsigned long long *cur = vm + (size_t)VM_COPIES * VM_STRIDE * ctx->vmax_parity;
+    unsigned long long *nxt = vm + (size_t)VM_COPIES * VM_STRIDE * (1 - ctx->vmax_parity);
     {
         KTimer tm(ctx, "quantize");
-        hipLaunchKernelGGL(k_vmax_partial, dim3(nblk), dim3(256), 0, ctx->stream, V, sa.kdim, b, ldv, nblk,
-                           part);
-        hipLaunchKernelGGL(k_vexp, dim3((bpad + 3) / 4), dim3(256), 0, ctx->stream, part, nblk, b, bpad, fx);
+        hipLaunchKernelGGL(k_vmax_partial, dim3(nblk), dim3(256), 0, ctx->stream, V, sa.kdim, b, ldv, cur);
         hipLaunchKernelGGL(k_vslice, dim3(grid1((int64_t)bpad * (kpad / 16))), dim3(256), 0, ctx->stream, V,
-                           sa.kdim, b, ldv, bpad, kpad, fx, vp, v_stride);
+                           sa.kdim, b, ldv, bpad, kpad, (const unsigned long long *)cur, nxt, fx, vp, v_stride);
         OFRR_HIP(hipGetLastError());
     }
+    ctx->vmax_parity ^= 1;
     // launch shape: enough workgroups for two per CU; K ranges <= I8_KMAX;
     // and K ranges short enough that one range of the basis planes
     // (I8_S x bpad x range bytes, re-read by every row tile) stays within

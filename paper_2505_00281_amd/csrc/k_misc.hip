@@ -358,6 +358,7 @@ void scale_columns_reset(Context *ctx) {
     hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, ctx->stream, cm2, 2 * CM_COPIES * 512);
     OFRR_HIP(hipGetLastError());
     ctx->colmax_parity = 0;
+    ctx->vmax_parity = -1;  // the digit-plane slicing clears its own on next use
 }
 
 void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
