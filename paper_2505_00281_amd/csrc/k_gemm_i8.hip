@@ -177,9 +177,8 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
                                                 int32_t *__restrict__ fx,
                                                 int8_t *__restrict__ planes, int64_t plane_stride) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gstride = (int64_t)gridDim.x * blockDim.x;
-    // the other merge arrays, for the next call
-    for (int64_t e = gid; e < (int64_t)VM_COPIES * bpad; e += gstride)
-        clear[(e / bpad) * VM_STRIDE + e % bpad] = 0ull;
+    // the other merge arrays, whole, for the next call (whatever its width)
+    for (int64_t e = gid; e < (int64_t)VM_COPIES * VM_STRIDE; e += gstride) clear[e] = 0ull;
     const int64_t total = (int64_t)bpad * (kpad / 16);
     for (int64_t e = gid; e < total; e += gstride) {
         const int j = (int)(e % bpad);

@@ -164,8 +164,8 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
 // infinity-norm in (1/2, 1]; a zero column keeps scale 1, NaN/Inf poison the
 // scale) from merged maxima (cmax[j]: FP32 bits of the column's largest
 // magnitude, all ones for NaN/Inf; the largest of CM_COPIES copies), applied
-// to Y and, when given, Z; workgroup 0 also zeroes the copies of `clear` for
-// the next merge.
+// to Y and, when given, Z; workgroup 0 also zeroes all copies of `clear`
+// for the next merge.
 template <class T>
 __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t ldy, T *__restrict__ Z,
                                                       int64_t ldz, int64_t n, int b,
@@ -189,10 +189,10 @@ __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t
             }
         }
         sc[j] = s;
-        if (blockIdx.x == 0)
-#pragma unroll
-            for (int c = 0; c < CM_COPIES; ++c) clear[c * 512 + j] = 0u;
     }
+    // the other merge arrays, whole, for the next call (whatever its width)
+    if (blockIdx.x == 0)
+        for (int e = t; e < CM_COPIES * 512; e += 256) clear[e] = 0u;
     __syncthreads();
     const int cols = b < 256 ? b : 256;
     const int groups = 256 / cols;

@@ -110,6 +110,33 @@ def test_product_sliced(ctx, dtype, trans, shape):
     assert np.max(err / (np.abs(opA) @ np.abs(V))) < 1e-10
 
 
+def test_product_sliced_width_sequence(ctx):
+    """Products of different widths in a row on one context (wide, narrow,
+    wide): the column maxima merged for one call never leak into a later
+    one, so the last product is bit-identical to the same product on a
+    fresh context (its trailing columns are smaller than the first call's,
+    so a leaked maximum would change their digit planes)."""
+    from paper_2505_00281_amd import ofrr
+    rng = np.random.default_rng(22)
+    n = 2000
+    A = rng.standard_normal((n, n))
+    At = torch.from_numpy(np.asfortranarray(A)).cuda()
+    V1 = rng.standard_normal((n, 128)) * 1e3
+    Vn = rng.standard_normal((n, 16)) * 1e6
+    V3 = rng.standard_normal((n, 128))
+    V3[:, 64:] *= 1e-3
+    print("product_sliced width sequence", flush=True)
+    fresh = ofrr.Context(0)
+    try:
+        Wref = fresh.block_product_sliced(At, _cuda(V3)).cpu().numpy()
+    finally:
+        fresh.close()
+    ctx.block_product_sliced(At, _cuda(V1))
+    ctx.block_product_sliced(At, _cuda(Vn))
+    W3 = ctx.block_product_sliced(At, _cuda(V3)).cpu().numpy()
+    np.testing.assert_array_equal(W3.view(np.uint64), Wref.view(np.uint64))
+
+
 @pytest.mark.parametrize("lowp", ["bf16", "f16"])
 @pytest.mark.parametrize("trans", [0, 1])
 @pytest.mark.parametrize("shape", [(300, 1000, 70), (128, 64, 64), (4100, 4096, 128)])
