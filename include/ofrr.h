@@ -69,12 +69,18 @@ typedef enum {
                                 within about 2^-40 of |A||V| per entry (FP64 gives 2^-53 K) */
 } ofrr_tail;
 
-/* Accumulation of the projections G = V^T V, H = V^T W (Sec. 4, mixed-
- * precision plan: reduced-precision inputs, higher-precision products). */
+/* Accumulation of the projections G = V^T V, H = V^T W (the mixed-
+ * precision plan at the end of Sec. 4 forms them in FP32 from reduced-
+ * precision data).  The FP32 modes take FP32, BF16 or F16 blocks (FP64
+ * blocks give OFRR_ERR_UNSUPPORTED) and use FP32 MFMA, whose products of
+ * such values are rounded to FP32. */
 typedef enum {
-    OFRR_ACC_F32 = 0,             /* FP32 sums */
-    OFRR_ACC_F32_COMPENSATED = 1, /* FP32 sums over row chunks, FP64 across chunks */
-    OFRR_ACC_F64 = 2              /* FP64 sums */
+    OFRR_ACC_F32 = 0,             /* FP32 sums over each workgroup's row chunk (at least
+                                     256 rows), chunk partials summed in FP32 */
+    OFRR_ACC_F32_COMPENSATED = 1, /* FP32 sums over runs of 32 rows, the runs and the
+                                     chunk partials summed in FP64: per entry the error
+                                     of a 32-term FP32 sum, independent of n */
+    OFRR_ACC_F64 = 2              /* FP64 sums (products of stored values are exact) */
 } ofrr_accum;
 
 /* Matrix descriptor.  Dense: values (rows x cols, column-major, ld).
@@ -96,7 +102,9 @@ typedef struct {
     ofrr_dtype basis_dtype;  /* storage/compute type of the products and the basis in
                                 the first phase: F64 gives the FP64 form of the method
                                 (all FP64); F32, BF16, F16, F8E4M3 the mixed forms */
-    ofrr_accum gram_accum;   /* accumulation of G and H in the first phase */
+    ofrr_accum gram_accum;   /* accumulation of G and H in the first phase (later
+                                phases and the FP64 form accumulate in FP64); see
+                                gram_switch_t */
     int32_t refine;          /* 0: one phase in basis_dtype; 1: first phase until its
                                 residual estimate stalls, then an FP64 tail; 2 (dense,
                                 BF16): BF16 phase, then a phase with A and the basis as
@@ -128,6 +136,14 @@ typedef struct {
     int32_t tail_product;    /* ofrr_tail: products of the FP64 phase after reduced-precision
                                 phases (refine >= 1, dense A); the FP64 form (basis_dtype F64)
                                 always runs FP64 arithmetic */
+    double gram_switch_t;    /* FP32 gram_accum: a projection is accumulated in FP64 instead
+                                when the conditioning statistic of the previous iteration's
+                                mass matrix, t(G) = sum_i G_ii (G^-1)_ii / b (t = 1 for a
+                                diagonal G; t <= kappa of G scaled to unit diagonal), is
+                                above this value, or when that G was not numerically
+                                positive definite; 0 -> 1000 (an FP32 perturbation of
+                                2^-24 per term of a 32-row run, scaled by t, stays below
+                                about 1e-3 of G's smallest eigenvalue) */
 } ofrr_plan;
 
 typedef struct {
@@ -138,6 +154,9 @@ typedef struct {
     int32_t products;        /* block products by A (or A^T) */
     double max_resid;        /* largest final residual among the k pairs */
     double seconds;          /* device time of the call (HIP events on the stream) */
+    double gram_t_max;       /* largest t(G) seen while the FP32 gram_accum was in force
+                                (0 if it never was) */
+    int32_t grams_f64;       /* first-phase projections that t(G) sent to FP64 */
 } ofrr_info;
 
 /* --------------------------------------------------------------------- */
@@ -146,7 +165,7 @@ typedef struct {
 
 /* Defaults: FP64 basis, FP64 accumulation, no refinement, power filter of
  * degree 1, drop_tol 0, tol 0, anorm 0, max_iters 20, stall_iters 3,
- * switch_resid 0, b_split 1, profile 0. */
+ * switch_resid 0, b_split 1, profile 0, tail_product F64, gram_switch_t 0. */
 void ofrr_plan_default(ofrr_plan *plan);
 
 /* Creates a context bound to `device` and to `hip_stream` (a hipStream_t,
@@ -203,7 +222,8 @@ ofrr_status ofrr_eig_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
  *   V0     n x basis FP64 start block or NULL.
  *   sigma  k FP64 descending; U m x k and V n x k FP64 column-major;
  *   resid  k FP64 sqrt(||A v - s u||^2 + ||A^T u - s v||^2) / anorm.
- * plan.filter must be OFRR_POWER with degree 1. */
+ * plan.filter must be OFRR_POWER with degree 1; plan.gram_accum must be
+ * OFRR_ACC_F64 (OFRR_ERR_UNSUPPORTED otherwise). */
 ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              const ofrr_plan *plan, const double *V0, double *sigma,
                              double *U, double *V, double *resid, ofrr_info *info);
@@ -285,9 +305,10 @@ ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b
                             int32_t *kept);
 
 /* Projections G = V^T V and H = V^T W (Alg. "Orthogonalization-Free
- * Rayleigh-Ritz Projection", lines computing B and M), b x b FP64 outputs.
- * V: n x b in v_dtype (F64, F32, BF16, F16); W: n x b in w_dtype (F64 or
- * F32); both column-major with ld = n; accumulation per `accum`. */
+ * Rayleigh-Ritz Projection", the products forming B and M), b x b FP64
+ * outputs, column-major.  V: n x b in v_dtype (F64, F32, BF16, F16); W:
+ * n x b in w_dtype (F64 or F32); both row-major with ld = b.  Accumulation
+ * per `accum` (FP32 modes: no FP64 block; else OFRR_ERR_UNSUPPORTED). */
 ofrr_status ofrr_project(ofrr_ctx ctx, int64_t n, int32_t b, ofrr_dtype v_dtype, const void *V,
                          ofrr_dtype w_dtype, const void *W, ofrr_accum accum, double *G,
                          double *H);

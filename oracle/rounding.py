@@ -74,10 +74,32 @@ def f32_to_e4m3_bits(x) -> np.ndarray:
     return code.astype(np.uint8)
 
 
+# Smallest and largest exponent of a block scale: 2^k with k in [-126, 127]
+# is a normal FP32 number, its reciprocal too, and it is an E8M0 scale
+# byte (OCP microscaling formats: bias 127, 0xFF reserved for NaN).
+SCALE_EXP_MIN, SCALE_EXP_MAX = -126, 127
+
+
+def e4m3_block_scale(amax: float) -> float:
+    """Power-of-two scale of one FP8 block: the smallest 2^k, k >= -126,
+    with amax / 2^k <= 448 (the largest finite e4m3fn value), so that every
+    scaled entry is in range and the division by the scale is exact; 1 for
+    an all-zero block.  Found by walking k from an exact starting point
+    (frexp gives amax = m 2^e with m in [0.5, 1), so amax <= 2^e)."""
+    amax = float(amax)
+    if not amax > 0.0:
+        return 1.0
+    _, e = np.frexp(amax)
+    k = max(int(e), SCALE_EXP_MIN)  # amax / 2^k <= amax / 2^e <= 1 <= 448
+    while k - 1 >= SCALE_EXP_MIN and amax / 2.0 ** (k - 1) <= E4M3_MAX:
+        k -= 1
+    assert k <= SCALE_EXP_MAX
+    return 2.0 ** k
+
+
 def fp8_block_quantize(A, block: int = 32):
     """Per-block e4m3fn quantisation of a 2-D FP32 array: each block x block
-    tile gets the scale 2^ceil(log2(amax / 448)) (1 for an all-zero tile), a
-    power of two so that dividing by it is exact, and the codes are
+    tile gets the scale e4m3_block_scale(amax of the tile) and the codes
     e4m3fn(A / scale).  Returns (codes uint8, scales float32 of shape
     (ceil(rows/block), ceil(cols/block)))."""
     A = np.asarray(A, dtype=np.float32)
@@ -88,41 +110,25 @@ def fp8_block_quantize(A, block: int = 32):
     for i in range(br):
         for j in range(bc):
             t = A[i * block:(i + 1) * block, j * block:(j + 1) * block]
-            amax = float(np.max(np.abs(t))) if t.size else 0.0
-            s = 1.0
-            if amax > 0:
-                s = 2.0 ** int(np.ceil(np.log2(amax / 448.0)))
-                # guard the log2 rounding at exact powers of two
-                while amax / s > 448.0:
-                    s *= 2.0
-                while s > 2.0 ** -149 and amax / (s / 2.0) <= 448.0:
-                    s /= 2.0
+            s = e4m3_block_scale(np.max(np.abs(t)) if t.size else 0.0)
             scales[i, j] = s
             codes[i * block:(i + 1) * block, j * block:(j + 1) * block] = \
-                f32_to_e4m3_bits((t / np.float32(s)).astype(np.float32))
+                f32_to_e4m3_bits(t.astype(np.float64) / s)
     return codes, scales
 
 
 def fp8_colblock_quantize(V, block: int = 32):
-    """e4m3fn quantisation of a 2-D FP32 array with one power-of-two scale per
-    `block` consecutive rows of each column (the smallest 2^k with
-    amax / 2^k <= 448; 1 for an all-zero segment).  Returns the dequantised
-    values (codes * scale) as float64."""
+    """e4m3fn quantisation of a 2-D FP32 array with one scale per `block`
+    consecutive rows of each column (e4m3_block_scale of the segment's
+    amax).  Returns the dequantised values (codes * scale) as float64."""
     V = np.asarray(V, dtype=np.float32)
     out = np.zeros(V.shape, dtype=np.float64)
     rows, cols = V.shape
     for j in range(cols):
         for r0 in range(0, rows, block):
             seg = V[r0:r0 + block, j]
-            amax = float(np.max(np.abs(seg))) if seg.size else 0.0
-            s = 1.0
-            if amax > 0:
-                s = 2.0 ** int(np.ceil(np.log2(amax / 448.0)))
-                while amax / s > 448.0:
-                    s *= 2.0
-                while amax / (s / 2.0) <= 448.0:
-                    s /= 2.0
-            codes = f32_to_e4m3_bits((seg / np.float32(s)).astype(np.float32))
+            s = e4m3_block_scale(np.max(np.abs(seg)) if seg.size else 0.0)
+            codes = f32_to_e4m3_bits(seg.astype(np.float64) / s)
             out[r0:r0 + block, j] = e4m3_bits_to_f32(codes).astype(np.float64) * s
     return out
 

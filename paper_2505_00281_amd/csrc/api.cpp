@@ -181,6 +181,7 @@ void ofrr_plan_default(ofrr_plan *p) {
     p->b_split = 1;
     p->profile = 0;
     p->tail_product = OFRR_TAIL_F64;
+    p->gram_switch_t = 0.0;
 }
 
 ofrr_status ofrr_create(ofrr_ctx *out, int device, void *hip_stream) {
@@ -295,6 +296,8 @@ ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
         OFRR_CHECK_ARG(k >= 1 && k <= basis && basis <= mn, "need 1 <= k <= basis <= min(m, n)");
         OFRR_CHECK_ARG(basis <= 256, "svd basis must be <= 256");
         OFRR_CHECK_ARG(sigma && U && V && resid, "output pointers must not be NULL");
+        if (plan->gram_accum != OFRR_ACC_F64)
+            fail(OFRR_ERR_UNSUPPORTED, "svd_partial: the projections are accumulated in FP64 (gram_accum F64)");
         OFRR_HIP(hipSetDevice(c->device));
         c->profile = plan->profile != 0;
         return svd_partial_impl(c, A, k, basis, plan, V0, sigma, U, V, resid, info);
@@ -444,10 +447,12 @@ ofrr_status ofrr_project(ofrr_ctx ctx, int64_t n, int32_t b, ofrr_dtype v_dtype,
         OFRR_CHECK_ARG(V && W && G && H && n >= 1 && b >= 1 && b <= 4096, "project: bad arguments");
         OFRR_CHECK_ARG(w_dtype == OFRR_F64 || w_dtype == OFRR_F32, "project: W is F64 or F32");
         OFRR_CHECK_ARG(v_dtype != OFRR_F8E4M3, "project: V type");
+        OFRR_CHECK_ARG(accum == OFRR_ACC_F32 || accum == OFRR_ACC_F32_COMPENSATED || accum == OFRR_ACC_F64,
+                       "project: accumulation mode");
+        if (accum != OFRR_ACC_F64 && (v_dtype == OFRR_F64 || w_dtype == OFRR_F64))
+            fail(OFRR_ERR_UNSUPPORTED, "project: FP32 accumulation takes FP32, BF16 or F16 blocks");
         OFRR_HIP(hipSetDevice(c->device));
-        gram_rect(c, n, b, b, v_dtype, V, b, v_dtype, V, b, G);
-        gram_rect(c, n, b, b, v_dtype, V, b, w_dtype, W, b, H);
-        (void)accum;
+        project(c, n, b, v_dtype, V, b, w_dtype, W, b, accum, G, H);
         c->sync();
         return OFRR_OK;
     });

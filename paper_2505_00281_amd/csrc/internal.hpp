@@ -266,10 +266,20 @@ int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, in
                    double tol, int32_t *piv, int32_t *keep, const int32_t **status = nullptr);
 
 // k_project.hip
+// G = V^T V, H = V^T W (b x b FP64, column-major) accumulated per `acc`
+// (FP32 modes take FP32, BF16 or F16 blocks only).
 void project(Context *ctx, int64_t n, int32_t b, ofrr_dtype vt, const void *V, int64_t ldv,
              ofrr_dtype wt, const void *W, int64_t ldw, ofrr_accum acc, double *G, double *H);
 void gram_rect(Context *ctx, int64_t n, int32_t b1, int32_t b2, ofrr_dtype xt, const void *X,
-               int64_t ldx, ofrr_dtype yt, const void *Y, int64_t ldy, double *C);
+               int64_t ldx, ofrr_dtype yt, const void *Y, int64_t ldy, double *C,
+               ofrr_accum acc = OFRR_ACC_F64);
+// Conditioning statistic of the projected mass matrix after a pencil solve
+// with Y^T G Y = I: t = sum_i G_ii (Y Y^T)_ii / b (Y Y^T = G^{-1} when G has
+// full rank; t = 1 for a diagonal G, t <= kappa(D^-1 G D^-1), D = diag(G)^(1/2)),
+// written to *out on the device; +inf when the pencil's rank (device
+// pointer) is below b.
+void gram_condition(Context *ctx, int32_t b, const double *G, const double *Y, const int32_t *rank,
+                    double *out);
 
 // k_smalleig.hip
 // Pencil H y = theta G y; returns rank of G used.

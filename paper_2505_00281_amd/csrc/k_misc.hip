@@ -66,13 +66,15 @@ __global__ void k_fp8_blocks(const float *__restrict__ A, int64_t lda, int64_t r
         __syncthreads();
     }
     amax = red[0];
-    // scale = smallest power of two s with amax / s <= 448 (448 = 0.875 * 2^9),
-    // decided exactly from amax = m 2^e, m in [0.5, 1); 1 for an all-zero block
+    // scale = smallest power of two 2^k, k >= -126, with amax / 2^k <= 448
+    // (448 = 0.875 * 2^9), decided exactly from amax = m 2^e, m in [0.5, 1);
+    // 1 for an all-zero block.  The floor keeps 2^k and 2^-k normal FP32
+    // numbers and 2^k an E8M0 scale byte.
     float scale = 1.f;
     if (amax > 0.f) {
         int e;
         const float m = frexpf(amax, &e);
-        scale = ldexpf(1.f, m <= 0.875f ? e - 9 : e - 8);
+        scale = ldexpf(1.f, max(m <= 0.875f ? e - 9 : e - 8, -126));
     }
     if (tid == 0) scales[bi + bj * brows] = scale;
     const float inv = 1.f / scale;  // exact: scale is a power of two
@@ -95,34 +97,52 @@ __global__ void k_uniform(double *X, int64_t count, uint64_t seed) {
     }
 }
 
-// Column abs-max partials of a row-major block: block x reduces rows
-// [x*rows_per_block, ...) over all b columns.  Rows are read contiguously;
-// per-column maxima are combined in LDS with an integer max on the float
-// bits (valid for non-negative floats, and order independent).  A NaN/Inf
-// in a column marks it with an all-ones pattern.
-// With `cmax` given, the block maxima are merged into cmax[c * 512 + j]
-// (c = block index mod CM_COPIES; FP32 bit patterns, zero on entry) by atomic
-// maximum instead of written to `part` (the maximum of bit patterns does not
-// depend on the merge order; the copies spread the atomics of many blocks).
+// Column maxima of a row-major block, as order-preserving 32-bit keys of
+// the magnitudes: the FP32 bits for FP32 and narrower element types, the
+// upper word of the FP64 bits for FP64 (sign cleared: exponent and leading
+// mantissa bits, so the largest key has the largest exponent over FP64's
+// whole range; a column whose entries are all FP64 subnormals below 2^-1022
+// keys as zero).  NaN or infinity gives all ones.
+template <class T>
+__device__ __forceinline__ unsigned mag_key(double v) {
+    if (!(v == v) || isinf(v)) return 0xFFFFFFFFu;
+    if constexpr (sizeof(T) == 8)
+        return (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
+    else
+        return __float_as_uint((float)fabs(v));
+}
+
+// 2^-e for the column maximum m = f 2^e, f in [1/2, 1) (the scaled column has
+// infinity-norm in (1/2, 1]); 1 for a zero column; NaN for a NaN/Inf key.
+template <class T>
+__device__ __forceinline__ double key_scale(unsigned key) {
+    if (key == 0xFFFFFFFFu) return __builtin_nan("");
+    if (key == 0u) return 1.0;
+    int e;
+    if constexpr (sizeof(T) == 8)
+        (void)frexp(__hiloint2double((int)key, 0), &e);
+    else
+        (void)frexpf(__uint_as_float(key), &e);
+    return ldexp(1.0, -e);
+}
+
+// Block x reduces rows [x*rows_per_block, ...) over all b columns and merges
+// its maxima into cmax[c * 512 + j] (c = block index mod CM_COPIES, zero on
+// entry) by atomic maximum: the maximum of keys does not depend on the
+// merge order, and the copies spread the atomics of many blocks.
 constexpr int CM_COPIES = 4;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
                                                         int64_t n, int b, int64_t rows_per_block,
-                                                        float *__restrict__ part, int nblk,
                                                         unsigned *__restrict__ cmax) {
-    // no atomics: for b <= 256 the block is split into 256 / b row groups,
-    // thread t takes column t % b of group t / b (consecutive threads read
-    // consecutive columns); wider blocks loop over columns.  Magnitudes are
-    // compared as FP32 bit patterns (monotone for non-negative floats); a
-    // NaN or infinity anywhere marks the column with all ones.
+    // for b <= 256 the block is split into 256 / b row groups, thread t takes
+    // column t % b of group t / b (consecutive threads read consecutive
+    // columns); wider blocks loop over columns
     __shared__ unsigned cm[256];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
-    auto mag_bits = [](double v) -> unsigned {
-        return (!(v == v) || isinf(v)) ? 0xFFFFFFFFu : __float_as_uint((float)fabs(v));
-    };
     if (b <= 256) {
         const int groups = 256 / b;
         const int j = t % b, g = t / b;
@@ -134,61 +154,41 @@ __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y,
 #pragma unroll
                 for (int u = 0; u < 8; ++u) v[u] = load_as_f64(Y + (r + u * groups) * ldy + j);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) m = max(m, mag_bits(v[u]));
+                for (int u = 0; u < 8; ++u) m = max(m, mag_key<T>(v[u]));
             }
-            for (; r < r1; r += groups) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
+            for (; r < r1; r += groups) m = max(m, mag_key<T>(load_as_f64(Y + r * ldy + j)));
         }
         cm[t] = m;
         __syncthreads();
         if (t < b) {
             unsigned mm = 0u;
             for (int q = 0; q < groups; ++q) mm = max(mm, cm[q * b + t]);
-            if (cmax)
-                atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + t, mm);
-            else
-                part[(int64_t)t * nblk + blockIdx.x] = mm == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(mm);
+            atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + t, mm);
         }
     } else {
         for (int j = t; j < b; j += 256) {
             unsigned m = 0u;
-            for (int64_t r = r0; r < r1; ++r) m = max(m, mag_bits(load_as_f64(Y + r * ldy + j)));
-            if (cmax)
-                atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + j, m);
-            else
-                part[(int64_t)j * nblk + blockIdx.x] = m == 0xFFFFFFFFu ? __builtin_nanf("") : __uint_as_float(m);
+            for (int64_t r = r0; r < r1; ++r) m = max(m, mag_key<T>(load_as_f64(Y + r * ldy + j)));
+            atomicMax(cmax + (blockIdx.x % CM_COPIES) * 512 + j, m);
         }
     }
 }
 
-// Power-of-two column scales 2^-ceil(log2(max)) (the scaled column has
-// infinity-norm in (1/2, 1]; a zero column keeps scale 1, NaN/Inf poison the
-// scale) from merged maxima (cmax[j]: FP32 bits of the column's largest
-// magnitude, all ones for NaN/Inf; the largest of CM_COPIES copies), applied
-// to Y and, when given, Z; workgroup 0 also zeroes all copies of `clear`
-// for the next merge.
+// Power-of-two column scales (key_scale of the merged maxima, the largest of
+// CM_COPIES copies) applied to Y and, when given, Z; workgroup 0 also zeroes
+// all copies of `clear` for the next merge.
 template <class T>
 __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t ldy, T *__restrict__ Z,
                                                       int64_t ldz, int64_t n, int b,
                                                       const unsigned *__restrict__ cmax,
                                                       unsigned *__restrict__ clear) {
-    __shared__ float sc[512];
+    __shared__ double sc[512];
     const int t = threadIdx.x;
     for (int j = t; j < b; j += 256) {
         unsigned mb = cmax[j];
 #pragma unroll
         for (int c = 1; c < CM_COPIES; ++c) mb = max(mb, cmax[c * 512 + j]);
-        float s = 1.f;
-        if (mb == 0xFFFFFFFFu) {
-            s = __builtin_nanf("");
-        } else {
-            const float m = __uint_as_float(mb);
-            if (m > 0.f) {
-                int e;
-                (void)frexpf(m, &e);
-                s = ldexpf(1.f, -e);
-            }
-        }
-        sc[j] = s;
+        sc[j] = key_scale<T>(mb);
     }
     // the other merge arrays, whole, for the next call (whatever its width)
     if (blockIdx.x == 0)
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_scale_apply2(T *__restrict__ Y, int64_t
     if (g >= groups) return;
     for (int64_t r = (int64_t)blockIdx.x * groups + g; r < n; r += (int64_t)gridDim.x * groups)
         for (int j = j0; j < b; j += cols) {
-            const double f = (double)sc[j];
+            const double f = sc[j];
             T *p = Y + r * ldy + j;
             const double yv = load_as_f64(p);
             if (Z) {
@@ -378,7 +378,7 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
     dispatch_type(t, [&](auto *p) {
         using T = std::remove_pointer_t<decltype(p)>;
         hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream,
-                           (const T *)Y, ldy, n, b, rpb, (float *)nullptr, nblk, cur);
+                           (const T *)Y, ldy, n, b, rpb, cur);
     });
     // at most 1024 workgroups (each reads the merged maxima once)
     const int rows_per_wg = 256 / (b < 256 ? b : 256);

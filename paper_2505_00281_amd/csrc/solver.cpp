@@ -230,6 +230,13 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     size_t pi = 0;
     std::vector<double> est((size_t)k);
     double anorm_used = plan->anorm;
+    // FP32 accumulation of G and H in the first (reduced-precision) phase,
+    // switched to FP64 for an iteration when the previous mass matrix was
+    // poorly conditioned: t(G) above the plan's bound, or not numerically
+    // positive definite (t = inf)
+    const double t_switch = plan->gram_switch_t > 0 ? plan->gram_switch_t : 1000.0;
+    double gram_t = 1.0, gram_t_max = 0.0;
+    int grams_f64 = 0;
 
     while (iters < plan->max_iters) {
         const Phase &ph = phases[pi];
@@ -289,14 +296,23 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // (elementwise, so it commutes with the column compaction)
         if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
         double *stage = nullptr;
+        const bool f32_gram = pi == 0 && !ph.f64() && plan->gram_accum != OFRR_ACC_F64;
+        ofrr_accum acc = OFRR_ACC_F64;
+        if (f32_gram) {
+            if (gram_t <= t_switch)
+                acc = plan->gram_accum;
+            else
+                ++grams_f64;
+        }
         for (bool first = true;; first = false) {
             // ---- project
             run.product(ph, V, W, bc);
-            project(ctx, n, bc, mt, V, ld, mt, W, ld, plan->gram_accum, G, H);
+            project(ctx, n, bc, mt, V, ld, mt, W, ld, acc, G, H);
             // ---- solve; the rank comes back with the residual estimates:
             // every column is lifted, those beyond the rank are zero and the
             // next sweep drops them
             const int32_t *rank_dev = pencil_eig_async(ctx, bc, H, G, which, theta, Yr);
+            if (f32_gram) gram_condition(ctx, bc, G, Yr, rank_dev, rest + k + 3);
             // ---- lift (X = V Y, AX = W Y) with residual estimates
             lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
             // residual estimates of the k wanted pairs
@@ -311,9 +327,9 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             }
             residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, rank_dev,
                             first ? hstat : nullptr);
-            stage = ctx->host_stage<double>((size_t)k + 3);
-            OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * (k + (first ? 3 : 1)), hipMemcpyDeviceToHost,
-                                    ctx->stream));
+            stage = ctx->host_stage<double>((size_t)k + 4);
+            const int nread = f32_gram ? k + 4 : k + (first ? 3 : 1);
+            OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * nread, hipMemcpyDeviceToHost, ctx->stream));
             ctx->sync();
             if (!first) break;
             if (stage[k + 1] != 0.0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
@@ -327,6 +343,10 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         }
         ++iters;
         if (!ph.f64()) ++iters_low;
+        if (f32_gram) {
+            gram_t = stage[k + 3];
+            gram_t_max = std::max(gram_t_max, gram_t);
+        }
         have_ax = true;
         std::copy(stage, stage + k, est.begin());
         const int32_t rank = (int32_t)stage[k];
@@ -387,6 +407,8 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         info->products = run.products;
         info->max_resid = rmax;
         info->seconds = ms * 1e-3;
+        info->gram_t_max = gram_t_max;
+        info->grams_f64 = grams_f64;
     }
     return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
 }

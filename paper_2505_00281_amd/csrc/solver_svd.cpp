@@ -177,8 +177,12 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             if (!last) {
                 const bool stalled = stall_det.push(emax);
                 if (stalled || (plan->switch_resid > 0 && emax <= plan->switch_resid)) {
-                    // FP64 tail: promote the right block, redo its product in FP64
+                    // FP64 tail: promote the right block and redo its product in
+                    // FP64; the left Ritz block is promoted too, since the final
+                    // residual reads it in the new phase's type when the
+                    // iteration cap ends the loop right after the switch
                     promote_block(ctx, n * ld, Vb);
+                    promote_block(ctx, m * ld, Ut);
                     ++pi;
                     stall_det.reset();
                     mt = master();
@@ -264,6 +268,8 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         info->products = products;
         info->max_resid = rmax;
         info->seconds = ms * 1e-3;
+        info->gram_t_max = 0.0;
+        info->grams_f64 = 0;
     }
     return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
 }

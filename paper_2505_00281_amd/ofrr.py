@@ -62,14 +62,16 @@ class Plan(ctypes.Structure):
                 ("tol", ctypes.c_double), ("anorm", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("stall_iters", ctypes.c_int32),
                 ("switch_resid", ctypes.c_double), ("b_split", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("tail_product", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("tail_product", ctypes.c_int32),
+                ("gram_switch_t", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("iters_low", ctypes.c_int32),
                 ("n_converged", ctypes.c_int32), ("basis_eff", ctypes.c_int32),
                 ("products", ctypes.c_int32), ("max_resid", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("gram_t_max", ctypes.c_double),
+                ("grams_f64", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -121,7 +123,7 @@ def load_library(path: str = LIB_PATH):
 
 def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power", degree=1,
               lo=0.0, hi=0.0, drop_tol=0.0, tol=0.0, anorm=0.0, max_iters=20, stall_iters=3,
-              switch_resid=0.0, b_split=1, profile=False, tail="f64") -> Plan:
+              switch_resid=0.0, b_split=1, profile=False, tail="f64", gram_switch_t=0.0) -> Plan:
     p = Plan()
     load_library().ofrr_plan_default(ctypes.byref(p))
     p.basis_dtype = _DTYPES[basis_dtype] if isinstance(basis_dtype, str) else basis_dtype
@@ -136,6 +138,7 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
     p.b_split = b_split
     p.profile = int(bool(profile))
     p.tail_product = _TAIL[tail] if isinstance(tail, str) else int(tail)
+    p.gram_switch_t = float(gram_switch_t)
     return p
 
 
@@ -244,6 +247,34 @@ class Context:
         except Exception:
             pass
 
+    # ------------------------------------------------------- validation
+    # Every pointer handed to the library must be device memory of this
+    # context's device, and every block must have the rows the operation
+    # reads: a host pointer or a short block would otherwise reach a kernel.
+    def _on_device(self, *tensors):
+        for t in tensors:
+            if t is None:
+                continue
+            if not (t.is_cuda and t.device == self.device):
+                raise OfrrError(ERR_INVALID_ARG,
+                                f"tensor on {t.device}; this context needs {self.device}")
+
+    def _mat(self, A, symmetric=False) -> Matrix:
+        mat = A if isinstance(A, Matrix) else dense_matrix(A, symmetric=symmetric)
+        self._on_device(*getattr(mat, "_keep", ()))
+        return mat
+
+    @staticmethod
+    def _rows(t, rows, what):
+        if t.dim() != 2 or t.shape[0] != rows:
+            raise OfrrError(ERR_INVALID_ARG, f"{what} must have {rows} rows, got shape {tuple(t.shape)}")
+
+    @staticmethod
+    def _dtype(t, allowed, what):
+        if t.dtype not in allowed:
+            raise OfrrError(ERR_INVALID_ARG, f"{what} has dtype {t.dtype}; expected one of "
+                                             f"{[str(d) for d in allowed]}")
+
     def _check(self, st, allow_warning=False):
         if st < 0 or (st > 0 and not allow_warning):
             raise OfrrError(st, self.lib.ofrr_last_error(self.h).decode())
@@ -252,7 +283,7 @@ class Context:
     # ---------------------------------------------------------- whole method
     def eig_partial(self, A, k: int, basis: int, which: str = "largest", plan: Plan | None = None,
                     X0=None) -> EigResult:
-        mat = A if isinstance(A, Matrix) else dense_matrix(A, symmetric=True)
+        mat = self._mat(A, symmetric=True)
         n = mat.rows
         plan = plan or make_plan()
         X0c = _colmajor_f64(X0, n, basis, self.device)
@@ -267,7 +298,7 @@ class Context:
         return EigResult(evals, evecs, resid, info.as_dict(), st)
 
     def svd_partial(self, A, k: int, basis: int, plan: Plan | None = None, V0=None) -> SvdResult:
-        mat = A if isinstance(A, Matrix) else dense_matrix(A)
+        mat = self._mat(A)
         m, n = mat.rows, mat.cols
         plan = plan or make_plan()
         V0c = _colmajor_f64(V0, n, basis, self.device)
@@ -286,7 +317,7 @@ class Context:
                             plan: Plan | None = None, X0s=None):
         nprob = len(As)
         # the descriptors (and the tensors they keep alive) live until the call returns
-        descs = [a if isinstance(a, Matrix) else dense_matrix(a, symmetric=True) for a in As]
+        descs = [self._mat(a, symmetric=True) for a in As]
         mats = (Matrix * nprob)(*descs)
         plan = plan or make_plan()
         X0c = [(_colmajor_f64(X0s[p], mats[p].rows, basis, self.device) if X0s else None)
@@ -308,14 +339,17 @@ class Context:
 
     # ----------------------------------------------------------------- steps
     def quantize(self, src: torch.Tensor, dtype: str = "bf16") -> torch.Tensor:
+        self._on_device(src)
+        self._dtype(src, (torch.float32,), "src")
         src = src.contiguous()
-        assert src.dtype == torch.float32
         out = torch.empty(src.shape, dtype=torch.int16, device=self.device)
         self._check(self.lib.ofrr_quantize(self.h, _DTYPES[dtype], src.numel(), _ptr(src), _ptr(out)))
         return out
 
     def quantize_fp8_blocks(self, A: torch.Tensor):
-        mat = dense_matrix(A)
+        mat = self._mat(A)
+        if mat.dtype != F32:
+            raise OfrrError(ERR_INVALID_ARG, "quantize_fp8_blocks: A must be float32")
         rows, cols = mat.rows, mat.cols
         codes = torch.empty((cols, rows), dtype=torch.uint8, device=self.device).t()
         br, bc = (rows + 31) // 32, (cols + 31) // 32
@@ -327,12 +361,25 @@ class Context:
     def block_product(self, A, V: torch.Tensor, trans: bool = False, v_dtype: str | None = None):
         """W = op(A) V with V a row-major (rows x b) device block."""
         mat = A if isinstance(A, Matrix) else dense_matrix(A)
-        V = V.contiguous()
+        self._rows(V, mat.rows if trans else mat.cols, "V")
         b = V.shape[1]
         rows = mat.cols if trans else mat.rows
         if v_dtype is None:
             v_dtype = {torch.float64: "f64", torch.float32: "f32", torch.float16: "f16",
-                       torch.bfloat16: "bf16"}[V.dtype]
+                       torch.bfloat16: "bf16"}.get(V.dtype)
+            if v_dtype is None:
+                raise OfrrError(ERR_INVALID_ARG, f"V has dtype {V.dtype}")
+        if V.element_size() != {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}.get(v_dtype, 0):
+            raise OfrrError(ERR_INVALID_ARG, f"V dtype {V.dtype} does not hold {v_dtype} elements")
+        if mat.format == DENSE:
+            want = {F64: ("f64",), F32: ("f64",), BF16: ("bf16",), F16: ("f16",)}[mat.dtype]
+            if v_dtype not in want:
+                raise OfrrError(ERR_INVALID_ARG, f"dense A of this dtype takes V as {want[0]}")
+        elif trans:
+            raise OfrrError(ERR_INVALID_ARG, "CSR products take trans = 0")
+        self._mat(mat)
+        self._on_device(V)
+        V = V.contiguous()
         if mat.format == DENSE and mat.dtype in (BF16, F16):
             wdt = torch.float32
         elif mat.format == CSR and v_dtype != "f64":
@@ -348,6 +395,9 @@ class Context:
         """W = op(A) V (FP64, row-major) from exact INT8 digit-plane products;
         A dense F32/F64."""
         mat = A if isinstance(A, Matrix) else dense_matrix(A)
+        self._rows(V, mat.rows if trans else mat.cols, "V")
+        self._mat(mat)
+        self._on_device(V)
         V = V.to(torch.float64).contiguous()
         b = V.shape[1]
         rows = mat.cols if trans else mat.rows
@@ -360,8 +410,16 @@ class Context:
                           trans: bool = False):
         """W = op(A) V for FP8 block-quantised A (codes, scales from
         quantize_fp8_blocks, column-major) and an FP32 row-major V."""
+        self._on_device(codes, scales, V)
+        self._dtype(codes, (torch.uint8,), "codes")
+        self._dtype(scales, (torch.float32,), "scales")
         rows, cols = codes.shape
-        assert codes.stride(0) == 1 and scales.stride(0) == 1
+        if not (codes.stride(0) == 1 and codes.stride(1) == rows and scales.stride(0) == 1
+                and tuple(scales.shape) == ((rows + 31) // 32, (cols + 31) // 32)
+                and scales.stride(1) == scales.shape[0]):
+            raise OfrrError(ERR_INVALID_ARG, "codes and scales must be the column-major arrays of "
+                                             "quantize_fp8_blocks")
+        self._rows(V, rows if trans else cols, "V")
         V = V.to(torch.float32).contiguous()
         b = V.shape[1]
         W = torch.empty((cols if trans else rows, b), dtype=torch.float32, device=self.device)
@@ -372,7 +430,10 @@ class Context:
     def hessenberg(self, Y: torch.Tensor, tol: float):
         """In-place Hessenberg process on a row-major (n x b) FP64/FP32 block.
         Returns (piv, keep, kept)."""
-        assert Y.is_contiguous() and Y.dtype in (torch.float64, torch.float32)
+        self._on_device(Y)
+        self._dtype(Y, (torch.float64, torch.float32), "Y")
+        if Y.dim() != 2 or not Y.is_contiguous():
+            raise OfrrError(ERR_INVALID_ARG, "Y must be a contiguous (row-major) n x b block")
         n, b = Y.shape
         piv = torch.empty(b, dtype=torch.int32, device=self.device)
         keep = torch.empty(b, dtype=torch.int32, device=self.device)
@@ -385,11 +446,17 @@ class Context:
     def project(self, V: torch.Tensor, W: torch.Tensor, accum: str = "f64", v_dtype: str | None = None):
         """G = V^T V, H = V^T W for row-major (n x b) blocks; FP64 b x b
         outputs (column-major; symmetric G)."""
+        self._on_device(V, W)
+        self._dtype(W, (torch.float64, torch.float32), "W")
+        if V.dim() != 2 or tuple(W.shape) != tuple(V.shape):
+            raise OfrrError(ERR_INVALID_ARG, f"V {tuple(V.shape)} and W {tuple(W.shape)} must both be n x b")
         V = V.contiguous()
         W = W.contiguous()
         n, b = V.shape
         vdt = v_dtype or {torch.float64: "f64", torch.float32: "f32", torch.float16: "f16",
-                          torch.bfloat16: "bf16", torch.int16: "bf16"}[V.dtype]
+                          torch.bfloat16: "bf16", torch.int16: "bf16"}.get(V.dtype)
+        if vdt is None or V.element_size() != {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[vdt]:
+            raise OfrrError(ERR_INVALID_ARG, f"V dtype {V.dtype} does not hold {vdt} elements")
         wdt = {torch.float64: "f64", torch.float32: "f32"}[W.dtype]
         G = _empty_colmajor(b, b, self.device)
         H = _empty_colmajor(b, b, self.device)
@@ -398,7 +465,10 @@ class Context:
         return G, H
 
     def pencil_eig(self, H: torch.Tensor, G: torch.Tensor, which: str = "largest"):
+        self._on_device(H, G)
         b = H.shape[0]
+        if tuple(H.shape) != (b, b) or tuple(G.shape) != (b, b):
+            raise OfrrError(ERR_INVALID_ARG, "H and G must be square and of the same size")
         Hc = H.to(torch.float64).t().contiguous().t()
         Gc = G.to(torch.float64).t().contiguous().t()
         theta = torch.empty(b, dtype=torch.float64, device=self.device)
@@ -409,7 +479,10 @@ class Context:
         return theta, Y, rank.value
 
     def svd_pencil(self, B: torch.Tensor, MU: torch.Tensor, MV: torch.Tensor):
+        self._on_device(B, MU, MV)
         k1, k2 = B.shape
+        if tuple(MU.shape) != (k1, k1) or tuple(MV.shape) != (k2, k2):
+            raise OfrrError(ERR_INVALID_ARG, "MU must be k1 x k1 and MV k2 x k2 for a k1 x k2 B")
         r = min(k1, k2)
         cm = lambda t: t.to(torch.float64).t().contiguous().t()
         Bc, MUc, MVc = cm(B), cm(MU), cm(MV)

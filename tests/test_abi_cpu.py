@@ -43,7 +43,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(ofrr_plan, lo), offsetof(ofrr_plan, max_iters),
          offsetof(ofrr_plan, b_split), offsetof(ofrr_plan, profile), offsetof(ofrr_plan, tail_product));
   printf("%zu %zu\\n", offsetof(ofrr_matrix, values), offsetof(ofrr_matrix, nnz));
-  printf("%zu\\n", offsetof(ofrr_info, max_resid));
+  printf("%zu %zu %zu %zu\\n", offsetof(ofrr_info, max_resid), offsetof(ofrr_plan, gram_switch_t),
+         offsetof(ofrr_info, gram_t_max), offsetof(ofrr_info, grams_f64));
   return 0;
 }
 """)
@@ -56,7 +57,8 @@ int main(void) {
     assert vals[3:8] == [ofrr.Plan.lo.offset, ofrr.Plan.max_iters.offset, ofrr.Plan.b_split.offset,
                          ofrr.Plan.profile.offset, ofrr.Plan.tail_product.offset]
     assert vals[8:10] == [ofrr.Matrix.values.offset, ofrr.Matrix.nnz.offset]
-    assert vals[10] == ofrr.Info.max_resid.offset
+    assert vals[10:14] == [ofrr.Info.max_resid.offset, ofrr.Plan.gram_switch_t.offset,
+                           ofrr.Info.gram_t_max.offset, ofrr.Info.grams_f64.offset]
 
 
 def test_plan_defaults():
@@ -65,6 +67,7 @@ def test_plan_defaults():
     assert (p.basis_dtype, p.gram_accum, p.refine, p.filter, p.degree) == (ofrr.F64, ofrr.ACC_F64, 0,
                                                                           ofrr.POWER, 1)
     assert (p.max_iters, p.stall_iters, p.b_split, p.profile, p.tail_product) == (20, 3, 1, 0, 0)
+    assert p.gram_switch_t == 0.0
 
 
 def test_descriptors_keep_their_tensors_alive():
@@ -108,3 +111,54 @@ def test_null_context_and_no_device_status():
     assert b"device" in lib.ofrr_last_error(None)
     with pytest.raises(ofrr.OfrrError):
         ofrr.Context(0)
+
+
+def _unbound_context():
+    """A Context object that never reached the library (no GPU here): the
+    binding's argument checks run before any library call, so they can be
+    exercised on the CPU."""
+    import torch
+    c = ofrr.Context.__new__(ofrr.Context)
+    c.lib, c.h, c.device = None, None, torch.device("cuda", 0)
+    return c
+
+
+def test_binding_rejects_host_tensors_and_short_blocks():
+    import torch
+    c = _unbound_context()
+    A = torch.eye(8, dtype=torch.float64).t()  # column-major view
+    with pytest.raises(ofrr.OfrrError) as e:   # V has 7 rows, A has 8 columns
+        c.block_product(A, torch.zeros(7, 4, dtype=torch.float64))
+    assert e.value.status == ofrr.ERR_INVALID_ARG and "rows" in str(e.value)
+    with pytest.raises(ofrr.OfrrError) as e:   # trans: A^T V needs rows(A) = 8 rows
+        c.block_product_sliced(torch.zeros(8, 5, dtype=torch.float64).t().contiguous().t(),
+                               torch.zeros(5, 4, dtype=torch.float64), trans=True)
+    assert "rows" in str(e.value)
+    with pytest.raises(ofrr.OfrrError) as e:   # right shape, but host memory
+        c.block_product(A, torch.zeros(8, 4, dtype=torch.float64))
+    assert e.value.status == ofrr.ERR_INVALID_ARG and "cuda" in str(e.value)
+    with pytest.raises(ofrr.OfrrError):
+        c.eig_partial(A, 2, 4)
+    with pytest.raises(ofrr.OfrrError):
+        c.svd_partial(A, 2, 4)
+    with pytest.raises(ofrr.OfrrError):
+        c.hessenberg(torch.zeros(8, 4), 0.0)
+    with pytest.raises(ofrr.OfrrError):
+        c.project(torch.zeros(8, 4), torch.zeros(8, 4))
+    with pytest.raises(ofrr.OfrrError):
+        c.quantize(torch.zeros(16))
+    with pytest.raises(ofrr.OfrrError):
+        c.pencil_eig(torch.eye(4, dtype=torch.float64), torch.eye(4, dtype=torch.float64))
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32)
+    csr = ofrr.csr_matrix(rp, torch.tensor([0, 1], dtype=torch.int32), torch.tensor([1.0, 2.0]))
+    with pytest.raises(ofrr.OfrrError):        # host CSR arrays
+        c.block_product(csr, torch.zeros(2, 4, dtype=torch.float32), v_dtype="f32")
+
+
+def test_binding_rejects_mismatched_element_types():
+    import torch
+    c = _unbound_context()
+    A = torch.eye(8, dtype=torch.float32).t()
+    with pytest.raises(ofrr.OfrrError) as e:   # 4-byte V declared as FP64
+        c.block_product(A, torch.zeros(8, 4, dtype=torch.float32), v_dtype="f64")
+    assert "elements" in str(e.value)

@@ -49,18 +49,28 @@ def _sampled_checks(A_host64, evals, evecs, idx, anorm):
     return rq, res
 
 
+@pytest.mark.timeout(1200)
 def test_dense_n16384_refined_bf16(ctx):
+    """The benchmarked call (refined BF16 plan with the split middle phase,
+    FP32-compensated first-phase projections and the INT8 digit-plane tail)
+    against the oracle run to convergence on the same stored A and start
+    block: all 64 returned eigenvalues within 1e-10 (relative) of the
+    oracle's, which are the top 64 of A (checked against a full FP32
+    eigendecomposition), final residuals <= 1e-8, and sampled vectors'
+    Rayleigh quotients and residuals recomputed on the host."""
+    from oracle import ofrr_oracle as O
     n, k, b = 16384, 64, 128
     lam = np.arange(1, n + 1, dtype=np.float64) ** -1.5
     print("config dense n=16384 generate", flush=True)
     A = W.dense_symmetric_prescribed(lam, 1002, noise_scale=1e-3, noise_seed=2002,
                                      dtype=torch.float32, device="cuda")
-    X0 = torch.from_numpy(W.uniform_start(n, b, 1102))
+    X0h = W.uniform_start(n, b, 1102)
+    X0 = torch.from_numpy(X0h)
     w = torch.linalg.eigvalsh(A).double().cpu().numpy()[::-1]
     lo, hi, anorm = float(w[-1]) * 1.001, float(w[b]), float(max(abs(w[0]), abs(w[-1])))
     print("config dense n=16384 run", flush=True)
     plan = _plan(basis_dtype="bf16", refine=2, filter="chebyshev", degree=4, lo=lo, hi=hi,
-                 tol=5e-9, anorm=anorm, max_iters=400, stall_iters=3)
+                 tol=5e-9, anorm=anorm, max_iters=400, stall_iters=3, tail="i8", gram_accum="f32c")
     r = ctx.eig_partial(A, k, b, plan=plan, X0=X0)
     print("info", r.info, flush=True)
     ev, X, res = r.evals.cpu().numpy(), r.evecs.cpu().numpy(), r.resid.cpu().numpy()
@@ -71,6 +81,18 @@ def test_dense_n16384_refined_bf16(ctx):
     np.testing.assert_allclose(ev[idx], rq, rtol=1e-10)
     assert np.all(rr <= 1e-8)
     np.testing.assert_allclose(rr, res[idx], rtol=1e-3, atol=1e-12)
+    print("config dense n=16384 oracle (converged)", flush=True)
+    t = time.time()
+    ref = O.subspace_eig(A64, X0h, k, filt="chebyshev", degree=4, lo=lo, hi=hi, tol=1e-12,
+                         anorm=anorm, max_outer=400)
+    print(f"oracle: {ref.iters} outer iterations, {time.time() - t:.1f}s, "
+          f"max resid {ref.resid.max():.2e}", flush=True)
+    assert np.all(ref.resid <= 1e-12)
+    # the oracle's pairs are the top 64 of A (FP32 eigvalsh is good to ~1e-6 here)
+    np.testing.assert_allclose(ref.theta, w[:k], rtol=0, atol=1e-5)
+    relerr = np.abs(ev - ref.theta) / np.abs(ref.theta)
+    print(f"max relative eigenvalue error vs oracle {relerr.max():.3e}", flush=True)
+    assert np.all(relerr <= 1e-10), relerr.max()
 
 
 def test_dense_svd_65536x8192_fp8(ctx):

@@ -55,6 +55,26 @@ def test_eig_dense_n512_power_fp64_same_step(ctx):
     _check_same_step(r, ref, k)
 
 
+@pytest.mark.parametrize("scale", [1e295, 1e-300])
+def test_eig_fp64_extreme_magnitudes_same_step(ctx, scale):
+    """FP64 form on c * A with c far outside FP32's range: the column scaling
+    must bring every product column to infinity-norm (1/2, 1] (an FP32 view
+    of the magnitudes saturates at 1e295 and flushes 1e-300 to zero, which
+    leaves the columns unscaled and the Hessenberg sweep drops them all).
+    Ritz values scale with c, vectors and relative residuals do not."""
+    n, b, k, outer = 200, 12, 5, 6
+    lam = 0.9 ** np.arange(1, n + 1)
+    A0 = W.dense_symmetric_prescribed(lam, 1201)
+    X0 = W.uniform_start(n, b, 1202)
+    ref = O.subspace_eig(A0.numpy(), X0, k, outer=outer)
+    print("eig fp64 extreme magnitude", scale, flush=True)
+    r = ctx.eig_partial((A0 * scale).cuda(), k, b, plan=_plan(max_iters=outer), X0=torch.from_numpy(X0))
+    assert r.info["basis_eff"] == b
+    np.testing.assert_allclose(r.evals.cpu().numpy() / scale, ref.theta, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(r.evecs.cpu().numpy(), ref.X, atol=1e-8)
+    np.testing.assert_allclose(r.resid.cpu().numpy(), ref.resid, rtol=1e-6, atol=1e-12)
+
+
 @pytest.mark.parametrize("n,b,k,deg", [(300, 10, 4, 3), (257, 9, 3, 5)])
 def test_eig_dense_chebyshev_fp64_same_step(ctx, n, b, k, deg):
     lam = np.linspace(1.0, -0.5, n) ** 3
@@ -155,6 +175,39 @@ def test_eig_mixed_refined_converged(ctx, lowp, refine, tail):
     np.testing.assert_allclose(th, w[:k], rtol=1e-10)
 
 
+@pytest.mark.parametrize("accum,switch_t", [("f32c", 0.0), ("f32", 0.0), ("f32c", 1.0)])
+def test_eig_mixed_fp32_projections_converged(ctx, accum, switch_t):
+    """Mixed form whose BF16 phase forms G and H with FP32 accumulation
+    (compensated or plain): the same converged pairs as the oracle's
+    (residual <= 1e-8, relative eigenvalue error <= 1e-10).  With the
+    conditioning bound at 1 (t(G) >= 1, equal only for a diagonal G) every
+    first-phase projection after the first is switched to FP64."""
+    n, b, k = 2048, 32, 12
+    lam = np.arange(1, n + 1) ** -1.5
+    A = W.dense_symmetric_prescribed(lam, 1002, noise_scale=1e-4, noise_seed=2002, dtype=torch.float32)
+    Ad = A.double().numpy()
+    w = np.linalg.eigvalsh(Ad)[::-1]
+    X0 = W.uniform_start(n, b, 1102)
+    lo, hi = float(w[-1]), float(w[b])
+    print("eig mixed fp32 projections", accum, switch_t, flush=True)
+    plan = _plan(basis_dtype="bf16", refine=2, filter="chebyshev", degree=4, lo=lo, hi=hi,
+                 tol=1e-9, anorm=float(w[0]), max_iters=400, tail="i8", gram_accum=accum,
+                 gram_switch_t=switch_t)
+    r = ctx.eig_partial(A.cuda(), k, b, plan=plan, X0=torch.from_numpy(X0))
+    print("info", r.info, flush=True)
+    assert r.info["iters_low"] >= 2
+    assert r.info["gram_t_max"] >= 1.0
+    # the first phase ends when it stalls; iters_low also counts the split phase
+    if switch_t == 1.0:
+        assert r.info["grams_f64"] >= 1
+    else:
+        assert r.info["grams_f64"] == 0 or r.info["gram_t_max"] > 1000.0
+    ref = O.subspace_eig(Ad, X0, k, filt="chebyshev", degree=4, lo=lo, hi=hi, tol=1e-12,
+                         anorm=float(w[0]), max_outer=2000)
+    assert r.resid.cpu().numpy().max() <= 1e-8
+    np.testing.assert_allclose(r.evals.cpu().numpy(), ref.theta, rtol=1e-10)
+
+
 def test_eig_dropped_column_same_step(ctx):
     """A dependent start column is dropped by the first sweep (that
     iteration's projection is redone on the compacted basis); the subspace
@@ -250,6 +303,28 @@ def test_svd_mixed_refined_converged(ctx, lowp):
     assert r.info["iters_low"] >= 1
     assert r.resid.cpu().numpy().max() <= 1e-8
     np.testing.assert_allclose(r.sigma.cpu().numpy(), s_ref[:k], rtol=1e-10)
+
+
+@pytest.mark.parametrize("lowp", ["bf16", "f8e4m3"])
+def test_svd_phase_switch_at_iteration_cap(ctx, lowp):
+    """The iteration cap lands on the switch to the FP64 tail: the left and
+    right Ritz blocks are promoted exactly, so U, V, sigma and the final
+    residuals equal those of the same run that does not switch, bit for
+    bit (a left block left in FP32 and read as FP64 would not)."""
+    m, n, b, k = 900, 300, 16, 6
+    sig = np.exp(-np.arange(1, n + 1) / 30.0)
+    A = W.svd_prescribed(m, n, sig, 44, dtype=torch.float32).cuda()
+    V0 = torch.from_numpy(W.uniform_start(n, b, 45))
+    print("svd switch at cap", lowp, flush=True)
+    common = dict(basis_dtype=lowp, refine=True, tol=1e-15, max_iters=1)
+    sw = ctx.svd_partial(A, k, b, plan=_plan(stall_iters=1, switch_resid=1e3, **common), V0=V0)
+    ns = ctx.svd_partial(A, k, b, plan=_plan(stall_iters=50, switch_resid=0.0, **common), V0=V0)
+    assert sw.info["iters"] == ns.info["iters"] == 1
+    assert sw.info["products"] == ns.info["products"] + 1  # the redone FP64 product
+    for a, c in ((sw.sigma, ns.sigma), (sw.U, ns.U), (sw.V, ns.V), (sw.resid, ns.resid)):
+        np.testing.assert_array_equal(a.cpu().numpy(), c.cpu().numpy())
+    U = sw.U.cpu().numpy()
+    np.testing.assert_allclose(np.linalg.norm(U, axis=0), 1.0, atol=1e-3)
 
 
 def test_batched_matches_single(ctx):

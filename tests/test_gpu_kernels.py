@@ -53,6 +53,25 @@ def test_fp8_block_quantize_bit_exact(ctx):
     np.testing.assert_array_equal(codes.cpu().numpy(), c_ref)
 
 
+def test_fp8_block_quantize_hand_worked(ctx):
+    """The kernel on the hand-worked 40 x 33 case of the oracle pins (scale 8,
+    16, 1 and the 2^-126 floor; subnormal and tie codes), compared with the
+    hand-derived values rather than with the oracle."""
+    A = np.zeros((40, 33), dtype=np.float32)
+    A[3, 5], A[7, 9], A[0, 0] = 3584.0, 8.0, -1.0
+    A[10, 32], A[11, 32] = 3585.0, 0.5
+    A[33, 32], A[34, 32] = 2.0 ** -130, -(2.0 ** -133)
+    want = np.zeros((40, 33), dtype=np.uint8)
+    want[3, 5], want[7, 9], want[0, 0] = 0x7E, 0x38, 0xA0
+    want[10, 32], want[11, 32] = 0x76, 0x10
+    want[33, 32], want[34, 32] = 0x18, 0x84
+    print("fp8 blocks hand-worked 40x33", flush=True)
+    codes, scales = ctx.quantize_fp8_blocks(torch.from_numpy(A.T.copy()).cuda().t())
+    np.testing.assert_array_equal(scales.cpu().numpy(),
+                                  np.array([[8.0, 16.0], [1.0, 2.0 ** -126]], np.float32))
+    np.testing.assert_array_equal(codes.cpu().numpy(), want)
+
+
 # ---------------------------------------------------------------- products
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -331,9 +350,18 @@ def test_hessenberg_signed_zeros_bitwise(ctx, monkeypatch, prec, nt):
 
 # ------------------------------------------------------------- projection
 
-@pytest.mark.parametrize("vt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("vt", ["f64", "bf16", "f32"])
 @pytest.mark.parametrize("shape", [(3001, 70), (16384, 128), (5, 3)])
-def test_project(ctx, vt, shape):
+@pytest.mark.parametrize("accum", ["f64", "f32c", "f32"])
+def test_project(ctx, vt, shape, accum):
+    """G = V^T V and H = V^T W against the FP64 products of the same stored
+    values, within the bound of each accumulation: FP64 sums of exact
+    products (2n u64); compensated: FP32 runs of 32 rows of FP32-rounded
+    products, the runs summed in FP64 ((32+2) u32 + 2n u64); FP32: a sum of
+    n rounded products in FP32 ((n+2) u32).  Bounds are elementwise,
+    relative to |V|^T |W|; u32 is taken as 2^-23 (one unit in the last
+    place per FP32 operation, whatever rounding the MFMA applies inside)."""
+    from paper_2505_00281_amd import ofrr
     rng = np.random.default_rng(8)
     n, b = shape
     V = rng.standard_normal((n, b))
@@ -350,13 +378,25 @@ def test_project(ctx, vt, shape):
         Wg = _cuda(Wm.astype(np.float32))
     else:
         Vg, Wg = _cuda(V), _cuda(Wm)
-    print("project", vt, shape, flush=True)
-    G, H = ctx.project(Vg, Wg, v_dtype=vt)
+    print("project", vt, shape, accum, flush=True)
+    if vt == "f64" and accum != "f64":
+        with pytest.raises(ofrr.OfrrError) as e:
+            ctx.project(Vg, Wg, accum=accum, v_dtype=vt)
+        assert e.value.status == ofrr.ERR_UNSUPPORTED
+        return
+    G, H = ctx.project(Vg, Wg, accum=accum, v_dtype=vt)
     G, H = G.cpu().numpy(), H.cpu().numpy()
-    bound = 2 * n * 2.0 ** -53
-    np.testing.assert_allclose(G, V.T @ V, rtol=0, atol=bound * (np.abs(V).T @ np.abs(V)).max())
-    np.testing.assert_allclose(H, V.T @ Wm, rtol=0, atol=bound * (np.abs(V).T @ np.abs(Wm)).max())
-    assert np.array_equal(G, G.T)
+    u32, u64 = 2.0 ** -23, 2.0 ** -53
+    rel = {"f64": 2 * n * u64, "f32c": 34 * u32 + 2 * n * u64, "f32": (n + 2) * u32}[accum]
+    aVV, aVW = np.abs(V).T @ np.abs(V), np.abs(V).T @ np.abs(Wm)
+    eG, eH = np.abs(G - V.T @ V), np.abs(H - V.T @ Wm)
+    assert np.all(eG <= rel * aVV), float(np.max(eG / (rel * aVV)))
+    assert np.all(eH <= rel * aVW), float(np.max(eH / (rel * aVW)))
+    if accum == "f64":
+        assert np.array_equal(G, G.T)
+    else:
+        # FP32 rounding shows: the result is not the FP64 one
+        assert n < 32 or not np.array_equal(H, V.T @ Wm)
 
 
 # ---------------------------------------------------------- small problems

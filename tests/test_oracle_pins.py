@@ -344,3 +344,118 @@ def test_rounding_roundtrip_exhaustive_e4m3():
     x = np.random.default_rng(0).standard_normal(10000).astype(np.float32) * 10
     bf = R.round_bf16(x)
     assert np.all(np.abs(bf - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def _golden_fp8():
+    scales, codes = [], []
+    for line in open(os.path.join(GOLDEN, "fp8_block_scale.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        kind, a, b = line.split()
+        if kind == "scale":
+            scales.append((float.fromhex(a), float.fromhex(b)))
+        else:
+            codes.append((float.fromhex(a), int(b, 16)))
+    return scales, codes
+
+
+def test_fp8_scale_rule_and_codes_hand_worked():
+    from oracle import rounding as R
+    scales, codes = _golden_fp8()
+    for amax, want in scales:
+        assert R.e4m3_block_scale(amax) == want, (amax.hex(), want)
+    for v, want in codes:
+        got = int(R.f32_to_e4m3_bits(np.float32(v)).ravel()[0])
+        assert got == want, (v.hex(), hex(got), hex(want))
+
+
+def test_fp8_block_quantize_hand_worked():
+    """40 x 33 matrix = 2 x 2 blocks (one full, three ragged); expected scales
+    and codes worked by hand from the format and the scale rule."""
+    from oracle import rounding as R
+    A = np.zeros((40, 33), dtype=np.float32)
+    A[3, 5], A[7, 9], A[0, 0] = 3584.0, 8.0, -1.0     # block (0,0): amax 448*8 -> scale 8
+    A[10, 32], A[11, 32] = 3585.0, 0.5                # block (0,1): 3585 > 3584 -> scale 16
+    A[33, 32], A[34, 32] = 2.0 ** -130, -(2.0 ** -133)  # block (1,1): scale clamped at 2^-126
+    codes, scales = R.fp8_block_quantize(A)           # block (1,0): all zero -> scale 1
+    np.testing.assert_array_equal(scales, np.array([[8.0, 16.0], [1.0, 2.0 ** -126]], np.float32))
+    want = np.zeros((40, 33), dtype=np.uint8)
+    want[3, 5] = 0x7E    # 3584/8 = 448
+    want[7, 9] = 0x38    # 8/8 = 1
+    want[0, 0] = 0xA0    # -1/8 = -2^-3: exponent field 4, mantissa 0, sign
+    want[10, 32] = 0x76  # 3585/16 = 224.0625 -> 224 = 1.75 * 2^7
+    want[11, 32] = 0x10  # 0.5/16 = 2^-5: exponent field 2
+    want[33, 32] = 0x18  # 2^-130 / 2^-126 = 2^-4: exponent field 3
+    want[34, 32] = 0x84  # -2^-7 = -4 * 2^-9 (subnormal)
+    np.testing.assert_array_equal(codes, want)
+
+
+def test_fp8_colblock_quantize_hand_worked():
+    """One scale per 32 rows of a column; dequantised values worked by hand."""
+    from oracle import rounding as R
+    V = np.zeros((70, 2), dtype=np.float32)
+    V[40, 0], V[41, 0], V[42, 0], V[43, 0] = 3584.0, 8.0, 3.0, 100.0  # rows 32..63: scale 8
+    V[64, 0], V[65, 0] = 1.0, 0.1                                      # rows 64..69: scale 2^-8
+    V[0, 1], V[1, 1], V[2, 1], V[3, 1] = 449.0, 2.0 ** -8, 3 * 2.0 ** -10, 2.0 ** -11  # scale 2
+    V[69, 1] = -7.0                                                    # 7 * 2^6 = 448: scale 2^-6
+    got = R.fp8_colblock_quantize(V)
+    want = np.zeros((70, 2))
+    want[40, 0], want[41, 0], want[42, 0] = 3584.0, 8.0, 3.0
+    want[43, 0] = 96.0          # 100/8 = 12.5: tie between 12 and 13 -> even mantissa -> 12
+    want[64, 0] = 1.0
+    want[65, 0] = 26.0 / 256.0  # 0.1 * 256 = 25.6 -> 26 (1.625 * 2^4)
+    want[0, 1] = 448.0          # 449/2 = 224.5 -> 224
+    want[1, 1] = 2.0 ** -8      # 2^-9 exactly (smallest subnormal)
+    want[2, 1] = 2.0 ** -8      # 0.75 * 2^-9 -> 2^-9
+    want[3, 1] = 0.0            # 0.125 * 2^-9 -> 0
+    want[69, 1] = -7.0
+    np.testing.assert_array_equal(got, want)
+
+
+def test_normalize_signs_hand_worked(oracle):
+    """Unit 2-norm, largest-magnitude entry positive, first index on ties;
+    the partner block (U of an SVD pair) flips with its column."""
+    X = np.array([[0.0, 1.0, 0.0, 0.1],
+                  [-3.0, 2.0, 0.0, -0.9],
+                  [3.0, -2.0, 0.0, 0.0],
+                  [0.0, 0.0, 0.0, 0.0]])
+    P = np.array([[2.0, 0.0, 0.0, 0.0],
+                  [0.0, 0.0, 3.0, 1.0],
+                  [0.0, 5.0, 4.0, 0.0]])
+    Xn, Pn = oracle.normalize_signs(X, P)
+    r2 = 1.0 / math.sqrt(2.0)
+    n4 = math.sqrt(0.82)
+    np.testing.assert_allclose(Xn, [[0.0, 1 / 3, 0.0, -0.1 / n4],
+                                    [r2, 2 / 3, 0.0, 0.9 / n4],
+                                    [-r2, -2 / 3, 0.0, 0.0],
+                                    [0.0, 0.0, 0.0, 0.0]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Pn, [[-1.0, 0.0, 0.0, 0.0],
+                                    [0.0, 0.0, 0.6, -1.0],
+                                    [0.0, 1.0, 0.8, 0.0]], rtol=0, atol=1e-15)
+
+
+def test_eig_residual_normalisation_hand_worked(oracle):
+    """||A x - theta x|| / ||x|| / anorm on a 3 x 3 matrix (||A||_2 = 5) for
+    non-eigenvectors, a non-unit vector and an exact eigenvector."""
+    A = np.array([[2.0, 1.0, 0.0], [1.0, 2.0, 0.0], [0.0, 0.0, 5.0]])
+    X = np.array([[1.0, 2.0, 1.0, 1.0],
+                  [0.0, 0.0, 2.0, 1.0],
+                  [0.0, 0.0, 2.0, 0.0]])
+    theta = np.array([2.0, 2.0, 1.0, 3.0])
+    # r = (0,1,0) ; (0,2,0)/2 ; (3,3,8)/3 ; 0
+    want = np.array([0.2, 0.2, math.sqrt(82.0) / 15.0, 0.0])
+    np.testing.assert_allclose(oracle.eig_residuals(A @ X, X, theta, 5.0), want, rtol=1e-15, atol=1e-16)
+    np.testing.assert_allclose(oracle.true_residuals(A, theta, X, 5.0), want, rtol=1e-15, atol=1e-16)
+
+
+def test_svd_residual_normalisation_hand_worked(oracle):
+    """sqrt(||A v - s u||^2 + ||A^T u - s v||^2) / anorm on a 3 x 2 matrix
+    with ||A||_2 = 2, for an exact triplet and two inexact ones."""
+    A = np.array([[1.0, 0.0], [0.0, 2.0], [0.0, 0.0]])
+    U = np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    V = np.array([[0.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    s = np.array([2.0, 1.0, 0.5])
+    # (1): exact.  (2): A v - u = (-1,2,0), A^T u - v = (1,-1).
+    # (3): A v - u/2 = (1,0,-1/2), A^T u - v/2 = (-1/2,0).
+    want = np.array([0.0, math.sqrt(7.0) / 2.0, math.sqrt(1.5) / 2.0])
+    np.testing.assert_allclose(oracle.svd_residuals(A, s, U, V, 2.0), want, rtol=1e-15, atol=1e-16)
