@@ -5,13 +5,19 @@ Workload (the dense eigenvalue configuration of the method's headline
 metric): symmetric A = Q diag(i^-1.5) Q^T + 1e-3 * (G + G^T)/sqrt(2),
 n = 16384, stored FP32; k = 64 wanted pairs, basis 128, Chebyshev filter of
 degree 4 per outer iteration.  Mixed form: BF16 basis and products (FP32
-accumulation), FP64 projections and pencil, FP64 tail after the BF16 phase
-stalls.  FP64 form: the same method with every step in FP64.
+accumulation) with FP32-compensated projections, then a split-BF16 phase
+(FP64 projections), then an FP64-accurate tail, each entered when the
+previous one stalls; FP64 pencil throughout.  FP64 form: the same method
+with every step in FP64.
 
 One step = one complete eig_partial call (quantisation of A, every outer
 iteration, the final FP64 residual check) with A and the start block
-resident in HBM.  value = converged pairs (final FP64 residual
-||Ax - lambda x|| / ||A|| <= 1e-8) / step time.
+resident in HBM.  value = converged pairs / step time, where a returned pair
+counts when its final FP64 residual ||Ax - lambda x|| / ||A|| is <= 1e-8 AND
+its eigenvalue is within 1e-10 (relative) of the CPU oracle's, run to
+convergence (residuals <= 1e-12) on the same stored A and start block after
+the timed region.  The same oracle run, timed on the host cores, is the CPU
+baseline (the whole run, until its 64 pairs met the same two criteria).
 
 Prints ONE JSON line.
 """
@@ -100,30 +106,58 @@ def call_ms_summary(results):
     return {"median": statistics.median(ms), "mean": statistics.fmean(ms), "per_call": ms}
 
 
-def cpu_baseline(A, X0, lo, hi, anorm, iters_needed):
-    """The oracle as it stands (FP64, orthonormal basis + classical RR) timed
-    on the host for ONE outer iteration of the same workload; scaled to
-    Ritz pairs/s with the outer-iteration count the FP64 form needed."""
+EVAL_RTOL = 1e-10   # relative eigenvalue error against the converged oracle
+ORACLE_TOL = 1e-12  # the oracle's own stopping residual
+
+
+def oracle_converged(A, X0, lo, hi, anorm):
+    """The oracle as it stands (FP64, MGS2 after every product, classical
+    Rayleigh-Ritz, cyclic Jacobi) run to convergence on the host copy of the
+    same stored A and start block, with the same filter.  Returns the
+    reference pairs and the CPU baseline: the time at which all 64 of the
+    oracle's own pairs met the metric's two criteria (residual <= 1e-8 and
+    eigenvalue within 1e-10 of the converged value)."""
     from oracle import ofrr_oracle as O
     Ah = A.double().cpu().numpy()
     X0h = X0.cpu().numpy()
     t = time.time()
-    r = O.subspace_eig(Ah, X0h, K_WANT, filt="chebyshev", degree=DEGREE, lo=lo, hi=hi, outer=1,
-                       anorm=anorm)
-    dt = time.time() - t
+    ref = O.subspace_eig(Ah, X0h, K_WANT, filt="chebyshev", degree=DEGREE, lo=lo, hi=hi,
+                         tol=ORACLE_TOL, anorm=anorm, max_outer=400, history=True)
+    total = time.time() - t
+    t_conv, it_conv = None, None
+    for it, th, r, ts in ref.history:
+        ok = (r <= TOL) & (np.abs(th - ref.theta) <= EVAL_RTOL * np.abs(ref.theta))
+        if ok.all():
+            t_conv, it_conv = ts, it
+            break
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    projected = dt * iters_needed
-    return {"value": K_WANT / projected, "unit": "Ritz pairs/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": (f"one outer iteration (degree-{DEGREE} Chebyshev filter, MGS2 after each "
-                       f"product, classical Rayleigh-Ritz) of the same n={N} workload took "
-                       f"{dt:.2f}s on the host; projected over the {iters_needed} outer iterations "
-                       f"the FP64 form needed to reach the tolerance"),
-            "seconds_per_outer_iter": dt}
+    log(f"[bench] oracle: {ref.iters} outer iterations in {total:.1f}s, "
+        f"64 pairs met the criteria at iteration {it_conv} ({t_conv}s), {cores} threads")
+    cpu = None
+    if t_conv:
+        cpu = {"value": K_WANT / t_conv, "unit": "Ritz pairs/s", "cores": int(cores), "kind": "oracle",
+               "sample": (f"the whole workload (n={N}, k={K_WANT}, basis {BASIS}, degree-{DEGREE} "
+                          f"Chebyshev) run by the oracle on the host, not projected: its {K_WANT} pairs "
+                          f"met residual <= {TOL:g} and eigenvalue within {EVAL_RTOL:g} of its converged "
+                          f"values after {it_conv} outer iterations, {t_conv:.1f}s; it stopped at "
+                          f"residual <= {ORACLE_TOL:g} after {ref.iters} iterations, {total:.1f}s"),
+               "oracle_iters_to_criteria": it_conv, "oracle_seconds_total": total}
+    return ref, cpu
+
+
+def accuracy(r, ref):
+    """Per-result errors against the converged oracle and the number of
+    pairs meeting both criteria."""
+    ev = r.evals.cpu().numpy()
+    res = r.resid.cpu().numpy()
+    rel = np.abs(ev - ref.theta) / np.abs(ref.theta)
+    nconv = int(((res <= TOL) & (rel <= EVAL_RTOL)).sum())
+    return nconv, {"max_rel_eval_err_vs_oracle": float(rel.max()), "max_resid": float(res.max()),
+                   "n_converged_both_criteria": nconv}
 
 
 def main():
@@ -131,7 +165,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", "--no-cpu-baseline", dest="no_oracle", action="store_true",
+                    help="skip the converged oracle run (the accuracy reference and the CPU baseline)")
+    ap.add_argument("--gram-accum", choices=["f32c", "f32", "f64"], default="f32c",
+                    help="accumulation of G and H in the BF16 phase")
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--b-split", type=int, default=1)
     ap.add_argument("--refine", type=int, default=2,
@@ -178,6 +215,7 @@ def main():
             ctx.block_product_sliced(A.t(), V, trans=True)
             ctx.block_product(A.t(), V, trans=True)
         torch.cuda.synchronize()
+        ctx.close()
         print(json.dumps({"traffic_probe": {"n": N, "b": BASIS, "launches_per_kernel": 3}}))
         return
     A, X0, lo, hi, anorm = make_problem(device)
@@ -185,94 +223,30 @@ def main():
 
     common = dict(filter="chebyshev", degree=DEGREE, lo=lo, hi=hi, tol=TOL * 0.5, anorm=anorm,
                   max_iters=400)
-    mixed = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
-                           b_split=args.b_split, tail=args.tail, **common)
+    mixed_kw = dict(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
+                    b_split=args.b_split, tail=args.tail, gram_accum=args.gram_accum, **common)
+    mixed = ofrr.make_plan(**mixed_kw)
     f64 = ofrr.make_plan(basis_dtype="f64", **common)
 
     res, ms_step, wall = run_steps(ctx, A, X0, mixed, args.steps, args.warmup, "mixed")
-    nconv = [int((r.resid <= TOL).sum().item()) for r in res]
-    value = sum(nconv) / (ms_step * 1e-3 * len(res))
 
     # FP64 form of the same method on the same GPU
-    f64_out = None
-    iters_f64 = None
+    fres, fms = None, None
     if not args.no_fp64_form:
         fres, fms, _ = run_steps(ctx, A, X0, f64, 3, 1, "fp64")
-        fr = fres[-1]
-        iters_f64 = fr.info["iters"]
-        fconv = int((fr.resid <= TOL).sum().item())
-        ev_diff = float(torch.max(torch.abs(fr.evals - res[-1].evals) / torch.abs(fr.evals)).item())
-        f64_out = {"value": fconv / (fms * 1e-3), "ms_per_step": fms, "steps": len(fres),
-                   "call_ms": call_ms_summary(fres), "iters": iters_f64,
-                   "n_converged": fconv, "max_rel_eval_diff_mixed_vs_fp64": ev_diff}
 
-    # dominant kernel: the BF16 block product, timed per launch with HIP events
-    prof = ofrr.make_plan(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters,
-                          b_split=args.b_split, tail=args.tail, profile=True, **common)
-    ctx.kernel_stats_reset()
-    ctx.eig_partial(A, K_WANT, BASIS, plan=prof, X0=X0)
-    torch.cuda.synchronize()
+    # where the time goes: every kernel family timed with HIP events on the
+    # library's stream over one more (profiled) call of each form
     fams = ["product_bf16", "product_bf16x2", "product_i8x", "product_reduce", "product_f64", "hessenberg",
-            "small_eig", "gram", "lift", "scale",
-            "quantize", "residual"]
+            "small_eig", "gram", "lift", "scale", "quantize", "residual"]
+    ctx.kernel_stats_reset()
+    ctx.eig_partial(A, K_WANT, BASIS, plan=ofrr.make_plan(profile=True, **mixed_kw), X0=X0)
+    torch.cuda.synchronize()
     stats = {f: ctx.kernel_stats(f) for f in fams}
-    # dominant kernel: the block-product family with the largest total time
-    # in one call.  Per launch: algorithmic bytes = A read once in its stored
-    # format + the basis block read once + the product written once;
-    # algorithmic operations = 2 n^2 b per MFMA product (21 digit-pair
-    # products for the INT8 planes).  The bound is whichever of bytes / HBM
-    # peak and operations / MFMA peak of the kernel's type takes longer.
-    vb = 2 if args.b_split >= 2 else 1
-    gemm = 2.0 * N * N * BASIS
-    alg = {
-        "product_bf16": (N * N * 2 + vb * N * BASIS * 2 + N * BASIS * 4, gemm * vb, 2500.0,
-                         "k_gemm_lp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)"),
-        "product_bf16x2": (N * N * 4 + N * BASIS * 4 + N * BASIS * 4, 3 * gemm, 2500.0,
-                           "k_gemm_lp<bf16, split A and V> (3 BF16 MFMAs per tile step)"),
-        # in the mixed call the only FP64 product is the final residual check
-        # of the k returned vectors
-        "product_f64": (N * N * 4 + N * K_WANT * 16, 2.0 * N * N * K_WANT, 78.6,
-                        "k_gemm_f64 (final residual product, k columns, FP64 MFMA 16x16x4)"),
-        "product_i8x": (6 * N * N + 6 * N * BASIS + 8 * N * BASIS, 21 * gemm, 5000.0,
-                        "k_gemm_i8s (6 x 6 INT8 digit planes, 21 MFMA 32x32x32 pairs, exact int32)"),
-    }
-
-    def roof(f):
-        nb, ops, peak_t, kname = alg[f]
-        n_l, t_l = stats[f]
-        avg = t_l / max(n_l, 1)
-        hbm_t = nb / (HBM_PEAK_GBS * 1e9)
-        mfma_t = ops / (peak_t * 1e12)
-        if hbm_t >= mfma_t:
-            ach = nb / (avg * 1e-3) / 1e9
-            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(ach / HBM_PEAK_GBS, 4)}
-        else:
-            ach = ops / (avg * 1e-3) / 1e12
-            r = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_t,
-                 "unit": "TOP/s" if f == "product_i8x" else "TFLOP/s", "frac": round(ach / peak_t, 4)}
-        r.update({"traffic": MEASURED_TRAFFIC.get(f) if N == 16384 and BASIS == 128 else None,
-                  "kernel": kname, "family": f, "avg_launch_ms": avg, "launches": n_l,
-                  "algorithmic_bytes_per_launch": nb, "algorithmic_ops_per_launch": ops})
-        return r
-
-    # the product with the largest share; the two latency-bound kernels (one-
-    # workgroup small eigensolver, grid-exchange Hessenberg sweep) have no
-    # bandwidth or MFMA roofline and are reported by time
-    dom = max(alg, key=lambda f: stats[f][1])
-    roofline = roof(dom)
-    roofline["latency_bound_ms_one_call"] = {f: round(stats[f][1], 3) for f in ("small_eig", "hessenberg")}
-    roofline["per_family"] = {f: {k: v for k, v in roof(f).items() if k in ("bound", "achieved", "unit", "frac",
-                                                                           "avg_launch_ms")}
-                              for f in alg if stats[f][0]}
-    kernel_ms = {f: {"launches": n, "total_ms": round(t, 3)} for f, (n, t) in stats.items()}
-
-    # where the FP64 form's time goes (same families, one profiled call)
     kernel_ms_fp64 = None
     if not args.no_fp64_form:
-        prof64 = ofrr.make_plan(basis_dtype="f64", profile=True, **common)
         ctx.kernel_stats_reset()
-        ctx.eig_partial(A, K_WANT, BASIS, plan=prof64, X0=X0)
+        ctx.eig_partial(A, K_WANT, BASIS, plan=ofrr.make_plan(basis_dtype="f64", profile=True, **common), X0=X0)
         torch.cuda.synchronize()
         kernel_ms_fp64 = {}
         for f in fams:
@@ -280,9 +254,95 @@ def main():
             if n_l:
                 kernel_ms_fp64[f] = {"launches": n_l, "total_ms": round(t_l, 3)}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, X0, lo, hi, anorm, iters_f64 or res[-1].info["iters"])
+    # Roofline of the product families on the METHOD's work per launch:
+    # bytes = A read once in the basis build's storage type (BF16, the
+    # method's reduced copy) + the basis block + the product; flops = 2 n^2 b.
+    # The split-BF16 and INT8 digit-plane kernels do more than that (they are
+    # how this build gets FP32- and FP64-class accuracy out of 16-bit and
+    # 8-bit units): their own bytes and operations are reported beside it as
+    # kernel_rate, not as the roofline.  Peaks are MI355X's data-sheet ones.
+    gemm = 2.0 * N * N * BASIS
+    bf16_bytes = N * N * 2 + N * BASIS * 2 + N * BASIS * 4
+    alg = {
+        "product_bf16": dict(bytes=bf16_bytes, ops=gemm, peak_mfma=2500.0, dtype="bf16",
+                             kernel="k_gemm_lp<bf16> (A*V, BF16 MFMA 32x32x16, FP32 accumulate)",
+                             kernel_bytes=bf16_bytes, kernel_ops=gemm),
+        "product_bf16x2": dict(bytes=bf16_bytes, ops=gemm, peak_mfma=2500.0, dtype="bf16",
+                               kernel="k_gemm_lp<bf16, split A and V> (hi+lo BF16 operands, 3 MFMAs per step)",
+                               kernel_bytes=N * N * 4 + N * BASIS * 4 + N * BASIS * 4, kernel_ops=3 * gemm),
+        # FP64-class product: the method's flops on the kernel's own unit (INT8)
+        "product_i8x": dict(bytes=N * N * 4 + N * BASIS * 8 + N * BASIS * 8, ops=gemm, peak_mfma=5000.0,
+                            dtype="int8",
+                            kernel="k_gemm_i8s (6 x 6 INT8 digit planes, 21 MFMA 32x32x32 pairs, exact int32)",
+                            kernel_bytes=6 * N * N + 6 * N * BASIS + 8 * N * BASIS, kernel_ops=21 * gemm),
+        # in the mixed call the only FP64 product is the final residual check
+        "product_f64": dict(bytes=N * N * 4 + N * K_WANT * 16, ops=2.0 * N * N * K_WANT, peak_mfma=78.6,
+                            dtype="f64", kernel="k_gemm_f64 (final residual product, k columns, FP64 MFMA)",
+                            kernel_bytes=N * N * 4 + N * K_WANT * 16, kernel_ops=2.0 * N * N * K_WANT),
+    }
+
+    def roof(f):
+        a = alg[f]
+        n_l, t_l = stats[f]
+        avg = t_l / max(n_l, 1)
+        sec = avg * 1e-3
+        hbm_t = a["bytes"] / (HBM_PEAK_GBS * 1e9)
+        mfma_t = a["ops"] / (a["peak_mfma"] * 1e12)
+        if hbm_t >= mfma_t:
+            ach = a["bytes"] / sec / 1e9
+            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(ach / HBM_PEAK_GBS, 4)}
+        else:
+            ach = a["ops"] / sec / 1e12
+            r = {"bound": "mfma", "achieved": round(ach, 2), "peak": a["peak_mfma"],
+                 "unit": "TOP/s" if a["dtype"] == "int8" else "TFLOP/s", "frac": round(ach / a["peak_mfma"], 4)}
+        r.update({"traffic": MEASURED_TRAFFIC.get(f) if N == 16384 and BASIS == 128 else None,
+                  "kernel": a["kernel"], "family": f, "avg_launch_ms": avg, "launches": n_l,
+                  "algorithmic_bytes_per_launch": a["bytes"], "algorithmic_flops_per_launch": a["ops"],
+                  "kernel_rate": {"bytes_per_launch": a["kernel_bytes"], "ops_per_launch": a["kernel_ops"],
+                                  "GB_s": round(a["kernel_bytes"] / sec / 1e9, 1),
+                                  "TOP_s": round(a["kernel_ops"] / sec / 1e12, 2)}})
+        if f == "product_i8x":
+            # the same product at FP64 accuracy on the FP64 MFMA roof
+            r["fp64_equivalent"] = {"achieved_TFLOP_s": round(gemm / sec / 1e12, 2), "peak": 78.6,
+                                    "frac": round(gemm / sec / 1e12 / 78.6, 3)}
+        return r
+
+    # the product family with the largest share of the call; the two
+    # latency-bound kernels (one-workgroup small eigensolver, grid-exchange
+    # Hessenberg sweep) have no bandwidth or MFMA roofline and are reported by time
+    dom = max(alg, key=lambda f: stats[f][1])
+    roofline = roof(dom)
+    roofline["latency_bound_ms_one_call"] = {f: round(stats[f][1], 3) for f in ("small_eig", "hessenberg")}
+    roofline["per_family"] = {f: {k: v for k, v in roof(f).items()
+                                  if k in ("bound", "achieved", "unit", "frac", "avg_launch_ms", "fp64_equivalent")}
+                              for f in alg if stats[f][0]}
+    kernel_ms = {f: {"launches": n, "total_ms": round(t, 3)} for f, (n, t) in stats.items()}
+
+    # accuracy against the converged oracle (after the timed region), which
+    # is also the CPU baseline
+    ref, cpu = None, None
+    if not args.no_oracle:
+        ref, cpu = oracle_converged(A, X0, lo, hi, anorm)
+        acc = [accuracy(r, ref) for r in res]
+        nconv = [a[0] for a in acc]
+        acc_mixed = acc[-1][1]
+    else:
+        nconv = [int((r.resid <= TOL).sum().item()) for r in res]
+        acc_mixed = None
+    value = sum(nconv) / (ms_step * 1e-3 * len(res))
+
+    f64_out = None
+    if fres:
+        fr = fres[-1]
+        if ref is not None:
+            fconv, facc = accuracy(fr, ref)
+        else:
+            fconv, facc = int((fr.resid <= TOL).sum().item()), None
+        ev_diff = float(torch.max(torch.abs(fr.evals - res[-1].evals) / torch.abs(fr.evals)).item())
+        f64_out = {"value": fconv / (fms * 1e-3), "ms_per_step": fms, "steps": len(fres),
+                   "call_ms": call_ms_summary(fres), "iters": fr.info["iters"], "n_converged": fconv,
+                   "accuracy_vs_oracle": facc, "max_rel_eval_diff_mixed_vs_fp64": ev_diff}
 
     out = {
         "metric": "Ritz pairs/sec at residual <=1e-8, mixed vs FP64 form, 1 MI355X; % roofline",
@@ -293,11 +353,16 @@ def main():
         "config": {"workload": "dense symmetric n=16384, lambda_i=i^-1.5 + 1e-3 N(0,1) symmetric "
                                "noise, FP32 storage; top k=64, basis 128, degree-4 Chebyshev",
                    "n": N, "k": K_WANT, "basis": BASIS, "degree": DEGREE, "filter_interval": [lo, hi],
+                   "filter_interval_source": "exact spectrum of the stored A (FP32 eigendecomposition "
+                                             "on the GPU, outside the timed region)",
                    "plan": (f"bf16 basis + FP32 accumulate{', split-BF16 middle phase' if args.refine >= 2 else ''}, "
-                            f"FP64 G/H and pencil, FP64 tail with "
+                            f"{ {'f32c': 'FP32-compensated', 'f32': 'FP32', 'f64': 'FP64'}[args.gram_accum]} "
+                            f"first-phase G/H (FP64 when t(G) > 1000), FP64 pencil, FP64 tail with "
                             f"{'INT8 digit-plane' if args.tail == 'i8' else 'FP64'} products"),
                    "parallelism": "single GPU"},
         "n_converged": nconv, "iters": res[-1].info["iters"], "iters_low": res[-1].info["iters_low"],
+        "accuracy_vs_oracle": acc_mixed,
+        "gram": {"t_max": res[-1].info["gram_t_max"], "projections_switched_to_f64": res[-1].info["grams_f64"]},
         "call_ms": call_ms_summary(res),
         "fp64_form": f64_out,
         "speedup_vs_fp64_form": (value / f64_out["value"]) if f64_out and f64_out["value"] else None,
@@ -306,6 +371,7 @@ def main():
         "kernel_ms_one_call": kernel_ms,
         "kernel_ms_one_call_fp64_form": kernel_ms_fp64,
     }
+    ctx.close()
     print(json.dumps(out))
 
 

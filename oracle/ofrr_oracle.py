@@ -50,6 +50,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -381,6 +382,7 @@ def subspace_eig(A, X0, k: int, which: str = "largest", filt: str = "power",
     outer iterations.  Converged mode: `tol` given, iterate (up to
     max_outer) until the k wanted residuals are <= tol.  anorm (None ->
     max |Ritz value| of the last projection) normalises the residuals."""
+    t_start = time.perf_counter()
     op = as_op(A)
     X = np.array(X0, dtype=np.float64, order="F", copy=True)
     hist = []
@@ -397,7 +399,9 @@ def subspace_eig(A, X0, k: int, which: str = "largest", filt: str = "power",
         an = anorm if anorm else float(np.max(np.abs(theta)))
         r = eig_residuals(AX[:, :k], Xr[:, :k], theta[:k], an)
         if history:
-            hist.append((it, theta[:k].copy(), r.copy()))
+            # (outer iteration, wanted Ritz values, their residuals, seconds
+            # since the call started): bookkeeping only
+            hist.append((it, theta[:k].copy(), r.copy(), time.perf_counter() - t_start))
         if tol is not None and np.all(r <= tol):
             break
     an = anorm if anorm else float(np.max(np.abs(theta)))
