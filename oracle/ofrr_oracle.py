@@ -97,6 +97,13 @@ def _load():
     lib.orc_hessenberg_f32.restype = _i64
     lib.orc_hessenberg_f32.argtypes = [_i64, _i64, _f32p, _i64, ctypes.c_float,
                                        _i32p, _i32p, _f32p, _i64]
+    lib.orc_hessenberg_f16s.restype = _i64
+    lib.orc_hessenberg_f16s.argtypes = [_i64, _i64, _f32p, _i64, ctypes.c_float,
+                                        _i32p, _i32p, _f32p, _i64]
+    lib.orc_round_binary16.restype = ctypes.c_float
+    lib.orc_round_binary16.argtypes = [ctypes.c_float]
+    lib.orc_round_binary16_array.restype = None
+    lib.orc_round_binary16_array.argtypes = [_i64, _f32p]
     lib.orc_csr_mm.restype = None
     lib.orc_csr_mm.argtypes = [_i64, _i32p, _i32p, _f64p, _i64, _f64p, _i64, _f64p, _i64]
     _lib = lib
@@ -159,7 +166,8 @@ def mgs2(X):
 
 
 def hessenberg(Y, tol: float, precision: str = "f64", want_u: bool = False):
-    """Right-looking Hessenberg process (Sec. 4.2).  Returns
+    """Right-looking Hessenberg process (Sec. 4.2) in FP64, FP32 or with
+    binary16 storage and FP32 arithmetic ("f16s").  Returns
     (Q, piv, keep[, U]) where Q holds every column after processing (use
     Q[:, keep == 1] for the basis), piv[j] the pivot row of column j (-1 if
     dropped) and U the multipliers (input = Q[:, keep] U[keep, :])."""
@@ -172,17 +180,29 @@ def hessenberg(Y, tol: float, precision: str = "f64", want_u: bool = False):
         U = np.zeros((k, k), order="F") if want_u else None
         lib.orc_hessenberg_f64(n, k, _p64(Q), n, float(tol), _pi32(piv), _pi32(keep),
                                _p64(U) if want_u else None, k)
-    elif precision == "f32":
+    elif precision in ("f32", "f16s"):
+        # f16s: binary16 storage (the input is rounded to binary16 first),
+        # FP32 arithmetic
         Q = np.array(Y, dtype=np.float32, order="F", copy=True)
         n, k = Q.shape
+        if precision == "f16s":
+            Q = np.asfortranarray(round_binary16(Q))
         piv = np.empty(k, np.int32)
         keep = np.empty(k, np.int32)
         U = np.zeros((k, k), dtype=np.float32, order="F") if want_u else None
-        lib.orc_hessenberg_f32(n, k, _p32(Q), n, float(tol), _pi32(piv), _pi32(keep),
-                               _p32(U) if want_u else None, k)
+        fn = lib.orc_hessenberg_f32 if precision == "f32" else lib.orc_hessenberg_f16s
+        fn(n, k, _p32(Q), n, float(tol), _pi32(piv), _pi32(keep), _p32(U) if want_u else None, k)
     else:
         raise ValueError(precision)
     return (Q, piv, keep, U) if want_u else (Q, piv, keep)
+
+
+def round_binary16(x):
+    """FP32 values rounded to the nearest IEEE binary16 value (ties to
+    even), as FP32 (the C oracle's rounding, applied elementwise)."""
+    a = np.array(x, dtype=np.float32, copy=True, order="C")
+    _load().orc_round_binary16_array(a.size, _p32(a))
+    return a
 
 
 def csr_matmul(row_ptr, col_idx, values, X):

@@ -26,7 +26,9 @@
  *                      (Sec. 5.1, implementation details).
  *   orc_hessenberg_f64 the right-looking Hessenberg process for a block
  *   orc_hessenberg_f32 (Sec. 4.2, Algorithm "Computing non-orthogonal bases
- *                      from the Hessenberg Process"), in FP64 and in FP32.
+ *                      from the Hessenberg Process"), in FP64 and in FP32;
+ *   orc_hessenberg_f16s the same with binary16 storage and FP32 arithmetic
+ *                      (orc_round_binary16: round to nearest binary16).
  *   orc_csr_mm         Y = A X for A in CSR (Sec. 5.1 uses CSR for sparse A).
  */
 #include <math.h>
@@ -276,6 +278,77 @@ int64_t orc_hessenberg_f32(int64_t n, int64_t k, float *Q, int64_t ldq,
                 const float wgt = qi[r];
                 if (U) U[IDX(j, i, ldu)] = wgt;
                 for (int64_t t = 0; t < n; ++t) qi[t] = fmaf(-wgt, q[t], qi[t]);
+            }
+        } else {
+            keep[j] = 0;
+            piv[j] = -1;
+        }
+    }
+    return kept;
+}
+
+/* ------------------------------------------------------------------------
+ * x rounded to the nearest IEEE binary16 value, ties to even, returned as
+ * FP32 (every binary16 value is an FP32 value).  binary16 has 11 significant
+ * bits, normal numbers down to 2^-14 and subnormal multiples of 2^-24 below;
+ * the largest finite value is 65504 = (2 - 2^-10) 2^15, and anything from
+ * 65520 (the midpoint to 2^16, which ties to the even 2^16) up overflows to
+ * infinity.  With |x| = f 2^e, f in [1/2, 1), a value in that binade is a
+ * multiple of 2^(e-11) (of 2^-24 below the normal range); x / 2^q is exact
+ * and is rounded to an integer by nearbyint in the default (nearest-even)
+ * rounding mode.
+ * ---------------------------------------------------------------------- */
+float orc_round_binary16(float x)
+{
+    if (isnan(x) || isinf(x)) return x;
+    const double a = fabs((double)x);
+    if (a >= 65520.0) return copysignf(INFINITY, x);
+    if (a == 0.0) return x;
+    int e;
+    (void)frexp(a, &e);
+    int q = e - 11;
+    if (q < -24) q = -24;
+    const double r = nearbyint(ldexp(a, -q));
+    return (float)copysign(ldexp(r, q), (double)x);
+}
+
+/* orc_round_binary16 applied to x[0..count-1] in place. */
+void orc_round_binary16_array(int64_t count, float *x)
+{
+    for (int64_t i = 0; i < count; ++i) x[i] = orc_round_binary16(x[i]);
+}
+
+/* The Hessenberg process with binary16 storage and FP32 arithmetic (the
+ * paper's FP16 runs compute in FP32 on FP16 data): as orc_hessenberg_f32,
+ * but every value written back to Q (the divided column and each updated
+ * entry) is rounded to binary16 first.  Q holds binary16 values on entry.
+ * U (may be NULL) receives the multipliers as read from Q. */
+int64_t orc_hessenberg_f16s(int64_t n, int64_t k, float *Q, int64_t ldq,
+                            float tol, int32_t *piv, int32_t *keep,
+                            float *U, int64_t ldu)
+{
+    int64_t kept = 0;
+    if (U)
+        for (int64_t j = 0; j < k; ++j)
+            for (int64_t i = 0; i < k; ++i) U[IDX(i, j, ldu)] = 0.0f;
+    for (int64_t j = 0; j < k; ++j) {
+        float *q = Q + IDX(0, j, ldq);
+        int64_t r = 0;
+        float best = fabsf(q[0]);
+        for (int64_t t = 1; t < n; ++t)
+            if (fabsf(q[t]) > best) { best = fabsf(q[t]); r = t; }
+        if (best >= tol && best > 0.0f) {
+            const float pivot = q[r];
+            for (int64_t t = 0; t < n; ++t) q[t] = orc_round_binary16(q[t] / pivot);
+            piv[j] = (int32_t)r;
+            keep[j] = 1;
+            ++kept;
+            if (U) U[IDX(j, j, ldu)] = pivot;
+            for (int64_t i = j + 1; i < k; ++i) {
+                float *qi = Q + IDX(0, i, ldq);
+                const float wgt = qi[r];
+                if (U) U[IDX(j, i, ldu)] = wgt;
+                for (int64_t t = 0; t < n; ++t) qi[t] = orc_round_binary16(fmaf(-wgt, q[t], qi[t]));
             }
         } else {
             keep[j] = 0;

@@ -459,3 +459,55 @@ def test_svd_residual_normalisation_hand_worked(oracle):
     # (3): A v - u/2 = (1,0,-1/2), A^T u - v/2 = (-1/2,0).
     want = np.array([0.0, math.sqrt(7.0) / 2.0, math.sqrt(1.5) / 2.0])
     np.testing.assert_allclose(oracle.svd_residuals(A, s, U, V, 2.0), want, rtol=1e-15, atol=1e-16)
+
+
+# ------------------------------------------------- binary16 storage ----
+
+def test_round_binary16_matches_numpy_float16(oracle):
+    """The oracle's binary16 rounding against numpy's float16 conversion
+    (IEEE round to nearest even): normals, subnormals, ties, overflow."""
+    rng = np.random.default_rng(3)
+    x = np.concatenate([
+        (rng.standard_normal(200000) * np.exp(rng.uniform(-20, 12, 200000))).astype(np.float32),
+        np.array([65504.0, 65519.0, 65520.0, 70000.0, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -25,
+                  2.0 ** -14, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, -0.0, 0.0], dtype=np.float32)])
+    got = oracle.round_binary16(x)
+    want = x.astype(np.float16).astype(np.float32)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_hessenberg_f16s_exact_inputs_equal_f64(oracle):
+    """Y = L U with dyadic L (|entries| <= 1/2 below the unit diagonal) and
+    power-of-two pivots U_jj: every intermediate value is a short dyadic
+    number, exact in binary16, so the FP16-storage process rounds nothing,
+    recovers L (rows already in pivot order) and equals the FP64 one."""
+    L = np.array([[1.0, 0.0, 0.0],
+                  [0.5, 1.0, 0.0],
+                  [0.25, -0.5, 1.0],
+                  [-0.5, 0.25, 0.5]])
+    U = np.array([[4.0, 2.0, 1.0],
+                  [0.0, 2.0, -1.0],
+                  [0.0, 0.0, 8.0]])
+    Y = L @ U
+    Q64, p64, k64 = oracle.hessenberg(Y, 1e-12, "f64")
+    Q16, p16, k16 = oracle.hessenberg(Y, 1e-12, "f16s")
+    np.testing.assert_array_equal(p64, [0, 1, 2])
+    np.testing.assert_array_equal(Q64, L)
+    np.testing.assert_array_equal(p16, p64)
+    np.testing.assert_array_equal(k16, k64)
+    np.testing.assert_array_equal(Q16.astype(np.float64), L)
+
+
+def test_hessenberg_f16s_is_rounded_f32_process(oracle):
+    """Every stored value of the FP16-storage process is a binary16 value,
+    the pivots are the row-pivoted LU pivots of the rounded input, and the
+    result stays within binary16 rounding of the FP64 process."""
+    rng = np.random.default_rng(5)
+    Y = rng.uniform(0.0, 1.0, (300, 12))
+    Q16, p16, k16 = oracle.hessenberg(Y, 2.0 ** -10, "f16s")
+    assert k16.all()
+    np.testing.assert_array_equal(Q16, Q16.astype(np.float16).astype(np.float32))
+    Yr = Y.astype(np.float16).astype(np.float64)
+    Q64, p64, _ = oracle.hessenberg(Yr, 1e-12, "f64")
+    np.testing.assert_array_equal(p16[:4], p64[:4])  # early pivots agree (later ones may swap on ties)
+    assert np.max(np.abs(Q16[:, :4] - Q64[:, :4])) < 2e-2
