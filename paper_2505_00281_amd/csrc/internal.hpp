@@ -169,8 +169,12 @@ void zero_bytes(Context *ctx, void *p, size_t bytes);
 void cast_f32_to_bf16(Context *ctx, int64_t count, const float *src, uint16_t *dst);
 void cast_f32_to_f16(Context *ctx, int64_t count, const float *src, uint16_t *dst);
 void cast_f64_to_f32(Context *ctx, int64_t count, const double *src, float *dst);
+// dst = scale * src elementwise (column-major, any element types)
 void cast_matrix(Context *ctx, ofrr_dtype src_t, ofrr_dtype dst_t, int64_t rows, int64_t cols,
-                 const void *src, int64_t lds, void *dst, int64_t ldd);
+                 const void *src, int64_t lds, void *dst, int64_t ldd, double scale = 1.0);
+// max |a| over the FP64 values of a dense or CSR descriptor (one readback;
+// +inf when a value is NaN or infinite)
+double absmax_values(Context *ctx, const ofrr_matrix *A);
 void quantize_fp8_blocks(Context *ctx, int64_t rows, int64_t cols, const float *A, int64_t lda,
                          uint8_t *codes, float *scales);
 void uniform_start(Context *ctx, int64_t n, int32_t b, uint64_t seed, double *X);

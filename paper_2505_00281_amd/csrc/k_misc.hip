@@ -36,14 +36,37 @@ __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d
 
 template <class S, class D>
 __global__ void k_cast_matrix(const S *__restrict__ s, int64_t lds, D *__restrict__ d,
-                              int64_t ldd, int64_t rows, int64_t cols) {
+                              int64_t ldd, int64_t rows, int64_t cols, double scale) {
     int64_t total = rows * cols;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < total; i += stride) {
         int64_t c = i / rows, r = i - c * rows;
-        store_as<D>(d + r + c * ldd, load_as_f64(s + r + c * lds));
+        store_as<D>(d + r + c * ldd, load_as_f64(s + r + c * lds) * scale);
     }
+}
+
+// Largest magnitude of an FP64 array (dense column-major rows x cols with
+// leading dimension ld, or a flat array: rows = count, cols = 1), merged as
+// the FP64 bit pattern by atomic maximum (non-negative doubles order as
+// their bits); NaN or infinity merges all ones.
+__global__ __launch_bounds__(256) void k_absmax_f64(const double *__restrict__ a, int64_t ld, int64_t rows,
+                                                    int64_t cols, unsigned long long *__restrict__ out) {
+    const int64_t total = rows * cols;
+    unsigned long long m = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / rows, r = i - c * rows;
+        const double v = a[r + c * ld];
+        const unsigned long long key =
+            (v == v && !isinf(v)) ? (unsigned long long)__double_as_longlong(fabs(v)) : ~0ull;
+        m = key > m ? key : m;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long q = __shfl_xor(m, o);
+        m = q > m ? q : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
 // One 32 x 32 block per 256-thread workgroup: amax, power-of-two scale,
@@ -323,7 +346,7 @@ void cast_f64_to_f32(Context *ctx, int64_t count, const double *src, float *dst)
 }
 
 void cast_matrix(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64_t cols,
-                 const void *src, int64_t lds, void *dst, int64_t ldd) {
+                 const void *src, int64_t lds, void *dst, int64_t ldd, double scale) {
     if (rows <= 0 || cols <= 0) return;
     int g = grid_for(rows * cols);
     dispatch_type(st, [&](auto *sp) {
@@ -331,10 +354,34 @@ void cast_matrix(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64
         dispatch_type(dt, [&](auto *dp) {
             using D = std::remove_pointer_t<decltype(dp)>;
             hipLaunchKernelGGL((k_cast_matrix<S, D>), dim3(g), dim3(256), 0, ctx->stream,
-                               (const S *)src, lds, (D *)dst, ldd, rows, cols);
+                               (const S *)src, lds, (D *)dst, ldd, rows, cols, scale);
         });
     });
     OFRR_HIP(hipGetLastError());
+}
+
+double absmax_values(Context *ctx, const ofrr_matrix *A) {
+    OFRR_CHECK_ARG(A->dtype == OFRR_F64, "absmax_values: FP64 values");
+    int64_t rows = A->rows, cols = A->cols, ld = A->ld;
+    if (A->format == OFRR_CSR) {
+        rows = A->nnz;
+        cols = 1;
+        ld = rows;
+    }
+    if (rows <= 0 || cols <= 0) return 0.0;
+    unsigned long long *d = ctx->buf<unsigned long long>("absmax", 1);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, ctx->stream, (uint32_t *)d, (int64_t)2);
+    const int g = (int)std::min<int64_t>(2048, (rows * cols + 255) / 256);
+    hipLaunchKernelGGL(k_absmax_f64, dim3(g), dim3(256), 0, ctx->stream, (const double *)A->values, ld, rows,
+                       cols, d);
+    OFRR_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    OFRR_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    OFRR_HIP(hipStreamSynchronize(ctx->stream));
+    if (h == ~0ull) return INFINITY;
+    double v;
+    std::memcpy(&v, &h, sizeof(v));
+    return v;
 }
 
 void quantize_fp8_blocks(Context *ctx, int64_t rows, int64_t cols, const float *A, int64_t lda,

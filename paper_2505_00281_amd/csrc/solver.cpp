@@ -71,12 +71,23 @@ struct EigRun {
     uint16_t *A_lo2 = nullptr;
     ofrr_dtype A_lo_t = OFRR_F64;
     SlicedA A_sl;  // digit planes of A for a sliced FP64 phase
+    // power of two the method scales A by (A' = sigma A) when A's FP64
+    // entries lie far outside the range in which sums of squares of the
+    // products stay finite and normal; 1 otherwise (no extra work)
+    double sigma = 1.0;
 
     // product of the current phase: W (master type) = A * Vblk (master type)
     // W = A V in the phase's arithmetic.  With defer (dense products only),
     // split-K partials may be left unreduced and described in *defer for a
     // consumer that sums them itself; defer->nsplit stays 0 when W is written.
     void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc, SlabOut *defer = nullptr) {
+        product_raw(ph, Vm, Wm, bc, sigma == 1.0 ? defer : nullptr);
+        if (defer && sigma != 1.0) defer->nsplit = 0;
+        // FP64 phases read A as stored: scale their products (exact: a power
+        // of two on normal numbers); the reduced phases' copy of A is scaled
+        if (sigma != 1.0 && ph.f64()) scale_array(ctx, n * b0, (double *)Wm, sigma);
+    }
+    void product_raw(const Phase &ph, const void *Vm, void *Wm, int32_t bc, SlabOut *defer) {
         ++products;
         if (defer) defer->nsplit = 0;
         const int64_t ld = b0;
@@ -91,6 +102,8 @@ struct EigRun {
                 else
                     cast_f32_to_bf16(ctx, n * ld, (const float *)Vm, vlo);
                 product_csr(ctx, A, bc, ph.basis, vlo, ld, Wm, ld);
+                if (sigma != 1.0) fail(OFRR_ERR_UNSUPPORTED, "CSR A with entries outside [2^-300, 2^300] "
+                                                             "needs the FP64 form");
             }
             return;
         }
@@ -155,6 +168,19 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         any_split = any_split || p.split;
         any_sliced = any_sliced || p.sliced;
     }
+    // magnitude guard for FP64 entries: sums of squares of products (the
+    // small pencil's reductions, residual norms) stay finite and normal for
+    // |a| in [2^-300, 2^300]; outside it the method runs on sigma A with
+    // sigma a power of two, and eigenvalues are scaled back at the end
+    if (A->dtype == OFRR_F64) {
+        const double amax = absmax_values(ctx, A);
+        if (!std::isfinite(amax)) fail(OFRR_ERR_NUMERIC, "A holds NaN or infinity");
+        if (amax > 0) {
+            int e = 0;
+            (void)std::frexp(amax, &e);
+            if (e > 300 || e < -300) run.sigma = std::ldexp(1.0, -e);
+        }
+    }
     // digit planes of A (rows of A^T, K-contiguous) for a sliced FP64 phase
     if (any_sliced) run.A_sl = slice_matrix_i8(ctx, A, 1);
 
@@ -169,7 +195,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             Af = (const float *)A->values;
         } else {
             float *tmp = ctx->buf<float>("A_f32", (size_t)n * n);
-            cast_matrix(ctx, OFRR_F64, OFRR_F32, n, n, A->values, A->ld, tmp, n);
+            cast_matrix(ctx, OFRR_F64, OFRR_F32, n, n, A->values, A->ld, tmp, n, run.sigma);
             Af = tmp;
             lda = n;
         }
@@ -219,8 +245,9 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     }
 
     const bool cheb = plan->filter == OFRR_CHEBYSHEV;
-    const double cc = cheb ? 0.5 * (plan->hi + plan->lo) : 0.0;
-    const double ee = cheb ? 0.5 * (plan->hi - plan->lo) : 1.0;
+    // the damping interval of sigma A
+    const double cc = cheb ? 0.5 * (plan->hi + plan->lo) * run.sigma : 0.0;
+    const double ee = cheb ? 0.5 * (plan->hi - plan->lo) * run.sigma : 1.0;
 
     int32_t bc = basis;  // current basis size
     scale_columns_reset(ctx);
@@ -229,7 +256,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     StallDetector stall_det{plan->stall_iters};
     size_t pi = 0;
     std::vector<double> est((size_t)k);
-    double anorm_used = plan->anorm;
+    double anorm_used = plan->anorm * run.sigma;
     // FP32 accumulation of G and H in the first (reduced-precision) phase,
     // switched to FP64 for an iteration when the previous mass matrix was
     // poorly conditioned: t(G) above the plan's bound, or not numerically
@@ -383,8 +410,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             product_csr(ctx, A, k, OFRR_F64, Xf, k, AXf, k);
         else
             product_f64(ctx, A, 1, k, Xf, k, AXf, k);
+        if (run.sigma != 1.0) scale_array(ctx, n * k, AXf, run.sigma);
     }
     finalize_eig(ctx, n, k, Xf, k, AXf, k, theta, anorm_used, evals, evecs, resid);
+    // eigenvalues of A = those of sigma A over sigma (residuals are relative)
+    if (run.sigma != 1.0) scale_array(ctx, k, evals, 1.0 / run.sigma);
     OFRR_HIP(hipEventRecord(ev1, ctx->stream));
     std::vector<double> r((size_t)k);
     OFRR_HIP(hipMemcpyAsync(r.data(), resid, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
