@@ -304,6 +304,25 @@ ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b
                             int64_t ldy, double tol, int32_t *piv, int32_t *keep,
                             int32_t *kept);
 
+/* Allocation-free variant of ofrr_hessenberg, for callers that cannot
+ * allocate device or pinned memory during a call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit for bit) as ofrr_hessenberg; the
+ * sweep's exchange words live in a fixed device array of the library
+ * (526,336 64-bit words = 4 MiB + 16 KiB, one per GPU, whose address the
+ * context takes at ofrr_create and which stays allocated until the process
+ * ends) instead of the context's workspace, and the kept count is read
+ * back through host stack memory.  Maximum size: the sweep needs
+ * 1 + 2 G (w + 1) + 2 G b w words (G <= 256 row slices, w = 2 for F64 and 1
+ * for F32), which covers every n with b <= 512; a larger need gives
+ * OFRR_ERR_INVALID_ARG before any launch.  Every call on one GPU shares
+ * that array (each call clears it before its sweep): calls that overlap on
+ * one GPU (two streams, contexts or threads) race and must not be issued.
+ * Kernel timing (plan.profile) is not recorded for this call. */
+ofrr_status ofrr_hessenberg_noalloc(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b, void *Y,
+                                    int64_t ldy, double tol, int32_t *piv, int32_t *keep,
+                                    int32_t *kept);
+
 /* Projections G = V^T V and H = V^T W (Alg. "Orthogonalization-Free
  * Rayleigh-Ritz Projection", the products forming B and M), b x b FP64
  * outputs, column-major.  V: n x b in v_dtype (F64, F32, BF16, F16); W:

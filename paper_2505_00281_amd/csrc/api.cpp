@@ -216,6 +216,15 @@ ofrr_status ofrr_create(ofrr_ctx *out, int device, void *hip_stream) {
         ctx->c.timer.launches.push_back(0);
         ctx->c.timer.total_ms.push_back(0.0);
     }
+    // this device's address of the fixed array the allocation-free
+    // Hessenberg entry point uses (one copy per GPU)
+    try {
+        hess_scratch_address(&ctx->c);
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        delete ctx;
+        return e.status;
+    }
     *out = ctx;
     return OFRR_OK;
 }
@@ -436,6 +445,28 @@ ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b
         OFRR_HIP(hipSetDevice(c->device));
         const int32_t kk = hessenberg(c, dtype, n, b, Y, ldy, tol, piv, keep);
         if (kept) *kept = kk;
+        return OFRR_OK;
+    });
+}
+
+ofrr_status ofrr_hessenberg_noalloc(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b, void *Y,
+                                    int64_t ldy, double tol, int32_t *piv, int32_t *keep, int32_t *kept) {
+    return guarded(ctx, [&](Context *c) {
+        OFRR_CHECK_ARG(Y && piv && keep && n >= 1 && b >= 1 && ldy >= b && tol >= 0,
+                       "hessenberg_noalloc: bad arguments");
+        OFRR_CHECK_ARG(dtype == OFRR_F64 || dtype == OFRR_F32, "hessenberg_noalloc: F64 or F32");
+        OFRR_HIP(hipSetDevice(c->device));
+        // no kernel timing here: its events are created on demand
+        const bool prof = c->profile;
+        c->profile = false;
+        try {
+            const int32_t kk = hessenberg_noalloc(c, dtype, n, b, Y, ldy, tol, piv, keep);
+            c->profile = prof;
+            if (kept) *kept = kk;
+        } catch (...) {
+            c->profile = prof;
+            throw;
+        }
         return OFRR_OK;
     });
 }

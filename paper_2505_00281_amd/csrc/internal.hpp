@@ -113,6 +113,9 @@ struct Context {
     int colmax_parity = -1;
     // the same for the merged column maxima of the digit-plane slicing
     int vmax_parity = -1;
+    // this device's address of the Hessenberg sweep's fixed exchange array
+    // (allocation-free entry point)
+    uint64_t *hess_scratch = nullptr;
 
     template <class T>
     T *buf(const std::string &name, size_t count) {
@@ -268,6 +271,12 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
 // until the next sweep on this context.
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                    double tol, int32_t *piv, int32_t *keep, const int32_t **status = nullptr);
+// The same sweep with its exchange words in the library's fixed device
+// array (ctx->hess_scratch, set by hess_scratch_address at context
+// creation) instead of the workspace; allocates nothing.
+void hess_scratch_address(Context *ctx);
+int32_t hessenberg_noalloc(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
+                           double tol, int32_t *piv, int32_t *keep);
 
 // k_project.hip
 // G = V^T V, H = V^T W (b x b FP64, column-major) accumulated per `acc`

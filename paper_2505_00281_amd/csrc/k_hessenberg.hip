@@ -885,6 +885,15 @@ __global__ __launch_bounds__(NT) void k_hessenberg_reg(T *__restrict__ Y, int64_
     if (a.g == 0 && a.t == 0 && kept_out) *kept_out = kept;
 }
 
+// Exchange words of the allocation-free entry point: one fixed array per
+// GPU, held until the process ends.  Host code never names it directly (in
+// host code the name is a stand-in, not a device address): the library's
+// set-up asks for its address on each device (hess_scratch_address) and
+// kernels get that pointer.  Sized for the largest sweep the launchers
+// build: 256 workgroups, 512 FP64 columns (1 + 2*256*3 + 2*256*512*2 words).
+constexpr int64_t HESS_SCRATCH_WORDS = 526336;
+__device__ __align__(256) uint64_t scratch[HESS_SCRATCH_WORDS];
+
 // The sweeps exchange data between all workgroups of the grid, so every
 // workgroup must be resident: a cooperative launch guarantees it.
 // OFRR_HESS_COOP=0 launches plainly instead, for comparisons (the grid is
@@ -901,6 +910,21 @@ inline hipError_t launch_resident(const void *kern, dim3 grid, dim3 block, void 
                 : hipLaunchKernel(kern, grid, block, args, shmem, stream);
 }
 
+// Waits for the sweep and returns its kept count (a timed-out wait raises).
+// The allocation-free path reads into host stack memory and waits with a
+// plain stream synchronisation (no pinned staging, no event).
+int32_t read_status(Context *ctx, const int *err, bool no_alloc) {
+    int32_t local[2] = {0, 0};
+    int32_t *host = no_alloc ? local : ctx->host_stage<int32_t>(2);
+    OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    if (no_alloc)
+        OFRR_HIP(hipStreamSynchronize(ctx->stream));
+    else
+        ctx->sync();
+    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
+    return host[1];
+}
+
 // Clears the error flag, the kept count and every tagged slot word (a
 // kernel, not a memset, so the sweep can be captured in a graph).
 __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
@@ -909,9 +933,45 @@ __global__ void k_hess_reset(uint64_t *words, int64_t nwords) {
         words[i] = 0;
 }
 
+// Exchange words: the context's workspace, or (ext != null) a caller-given
+// array of ext_cap words that the launch must fit in.
+struct WordsBuf {
+    uint64_t *ext = nullptr;
+    int64_t ext_cap = 0;
+    uint64_t *get(Context *ctx, int64_t nwords) const {
+        if (!ext) return ctx->buf<uint64_t>("hess_words", (size_t)nwords);
+        if (nwords > ext_cap)
+            fail(OFRR_ERR_INVALID_ARG, "hessenberg: the sweep needs " + std::to_string(nwords) +
+                                           " exchange words, the fixed array holds " + std::to_string(ext_cap));
+        return ext;
+    }
+};
+
+// Occupancy answers (workgroups per CU) cached in fixed tables, so the
+// steady state allocates nothing on the host either.
+struct OccEntry {
+    int dev;
+    const void *kern;
+    size_t shmem;
+    int value;
+};
+constexpr int OCC_SLOTS = 128;
+
+template <class Q>
+int occupancy_cached(OccEntry (&tab)[OCC_SLOTS], int dev, const void *kern, size_t shmem, Q query) {
+    for (int i = 0; i < OCC_SLOTS; ++i) {
+        if (tab[i].kern == nullptr) {
+            tab[i] = OccEntry{dev, kern, shmem, query()};
+            return tab[i].value;
+        }
+        if (tab[i].dev == dev && tab[i].kern == kern && tab[i].shmem == shmem) return tab[i].value;
+    }
+    return query();  // table full: ask again
+}
+
 template <class T, int NT>
 int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv,
-                int32_t *keep, const int32_t **status) {
+                int32_t *keep, const int32_t **status, const WordsBuf &wb) {
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     const int64_t G64 = (n + NT - 1) / NT;
     if (G64 > HR_GMAX) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: too many row slices for the register kernel");
@@ -921,19 +981,18 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double to
     constexpr int TW = NWords<T>::value, CW = NWords<typename MagT<T>::type>::value + 1;
     const int64_t ncand = (int64_t)2 * G * CW, nrow = (int64_t)2 * G * b * TW;
     const int64_t nwords = 1 + ncand + nrow;
-    uint64_t *words = ctx->buf<uint64_t>("hess_words", (size_t)nwords);
+    uint64_t *words = wb.get(ctx, nwords);
     int *err = reinterpret_cast<int *>(words);
     int32_t *kept_d = err + 1;
     uint64_t *slot_cand = words + 1;
     uint64_t *slot_rows = words + 1 + ncand;
-    static std::map<int, int> occ;
-    auto it = occ.find(ctx->device);
-    if (it == occ.end()) {
+    static OccEntry occ[OCC_SLOTS] = {};
+    const int per_cu = occupancy_cached(occ, ctx->device, (const void *)k_hessenberg_reg<T, NT>, 0, [&] {
         int pc = 0;
         OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, (const void *)k_hessenberg_reg<T, NT>, NT, 0));
-        it = occ.emplace(ctx->device, pc).first;
-    }
-    if (G64 > (int64_t)it->second * cus) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
+        return pc;
+    });
+    if (G64 > (int64_t)per_cu * cus) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
     hipLaunchKernelGGL(k_hess_reset, dim3((unsigned)std::min<int64_t>(256, (nwords + 255) / 256)), dim3(256), 0,
                        ctx->stream, words, nwords);
     OFRR_HIP(hipGetLastError());
@@ -946,16 +1005,12 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double to
         *status = err;
         return 0;
     }
-    int32_t *host = ctx->host_stage<int32_t>(2);
-    OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
-    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
-    return host[1];
+    return read_status(ctx, err, wb.ext != nullptr);
 }
 
 template <class T>
 int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv,
-            int32_t *keep, const int32_t **status) {
+            int32_t *keep, const int32_t **status, const WordsBuf &wb) {
     OFRR_CHECK_ARG(b >= 1 && b <= 512, "hessenberg: 1 <= b <= 512");
     OFRR_CHECK_ARG(n >= 1 && n < (int64_t)0x7fffffff, "hessenberg: 1 <= n < 2^31");
     OFRR_CHECK_ARG(ldy >= b, "hessenberg: ld >= b");
@@ -995,9 +1050,9 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     bool use_reg = reg_type && b <= HR_B && (n + rnt - 1) / rnt <= HR_GMAX;
     if (const char *s = std::getenv("OFRR_HESS_REG")) use_reg = use_reg && std::atoi(s) != 0;
     if (use_reg) {
-        if (rnt == 64) return run_reg<T, 64>(ctx, n, b, Y, ldy, tol, piv, keep, status);
-        if (rnt == 128) return run_reg<T, 128>(ctx, n, b, Y, ldy, tol, piv, keep, status);
-        return run_reg<T, 256>(ctx, n, b, Y, ldy, tol, piv, keep, status);
+        if (rnt == 64) return run_reg<T, 64>(ctx, n, b, Y, ldy, tol, piv, keep, status, wb);
+        if (rnt == 128) return run_reg<T, 128>(ctx, n, b, Y, ldy, tol, piv, keep, status, wb);
+        return run_reg<T, 256>(ctx, n, b, Y, ldy, tol, piv, keep, status, wb);
     }
     const int vec = 16 / (int)sizeof(T);
     const int64_t ldr = ((b + vec - 1) / vec + 1) * vec;  // padded row length in LDS
@@ -1033,7 +1088,7 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     constexpr int CW = (int)(sizeof(M) / 4) + 1;
     const int64_t ncand = (int64_t)2 * G * CW, nrow = (int64_t)2 * G * b * TW;
     const int64_t nwords = 1 + ncand + nrow;
-    uint64_t *words = ctx->buf<uint64_t>("hess_words", (size_t)nwords);
+    uint64_t *words = wb.get(ctx, nwords);
     int *err = reinterpret_cast<int *>(words);
     int32_t *kept_d = err + 1;
     uint64_t *slot_cand = words + 1;
@@ -1051,21 +1106,25 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
     // the dynamic-LDS limit and the occupancy answer depend only on the
     // kernel variant, its LDS size and the device: asked once, then reused
     // (the sweep runs every iteration)
-    static std::map<std::tuple<int, const void *, size_t>, int> occ;
-    static std::map<std::pair<int, const void *>, size_t> lds_set;
-    const auto key = std::make_tuple(ctx->device, (const void *)kern, shmem);
-    auto it = occ.find(key);
-    if (it == occ.end()) {
-        size_t &cur = lds_set[std::make_pair(ctx->device, (const void *)kern)];
-        if (shmem > cur) {  // the limit only ever grows
+    // (the dynamic-LDS limit of a kernel only ever grows: lds_set holds the
+    // largest size set so far per device and kernel)
+    static OccEntry occ[OCC_SLOTS] = {};
+    static OccEntry lds_set[OCC_SLOTS] = {};
+    const int per_cu = occupancy_cached(occ, ctx->device, (const void *)kern, shmem, [&] {
+        OccEntry *cur = nullptr;
+        for (int i = 0; i < OCC_SLOTS && !cur; ++i)
+            if (lds_set[i].kern == nullptr || (lds_set[i].dev == ctx->device && lds_set[i].kern == kern)) {
+                if (lds_set[i].kern == nullptr) lds_set[i] = OccEntry{ctx->device, kern, 0, 0};
+                cur = &lds_set[i];
+            }
+        if (!cur || shmem > cur->shmem) {
             OFRR_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-            cur = shmem;
+            if (cur) cur->shmem = shmem;
         }
         int pc = 0;
         OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, nt, shmem));
-        it = occ.emplace(key, pc).first;
-    }
-    const int per_cu = it->second;
+        return pc;
+    });
     if ((int64_t)per_cu * cus < G)
         fail(OFRR_ERR_UNSUPPORTED, "hessenberg: grid cannot be co-resident");
     void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, &rows_per, &slot_rows, &slot_cand, &err,
@@ -1078,19 +1137,33 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         *status = err;
         return 0;
     }
-    int32_t *host = ctx->host_stage<int32_t>(2);
-    OFRR_HIP(hipMemcpyAsync(host, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
-    if (host[0] != 0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
-    return host[1];
+    return read_status(ctx, err, wb.ext != nullptr);
 }
 
 }  // namespace
 
 int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                    double tol, int32_t *piv, int32_t *keep, const int32_t **status) {
-    if (t == OFRR_F64) return run<double>(ctx, n, b, (double *)Y, ldy, tol, piv, keep, status);
-    if (t == OFRR_F32) return run<float>(ctx, n, b, (float *)Y, ldy, tol, piv, keep, status);
+    const WordsBuf wb;
+    if (t == OFRR_F64) return run<double>(ctx, n, b, (double *)Y, ldy, tol, piv, keep, status, wb);
+    if (t == OFRR_F32) return run<float>(ctx, n, b, (float *)Y, ldy, tol, piv, keep, status, wb);
+    fail(OFRR_ERR_UNSUPPORTED, "hessenberg: element type must be F64 or F32");
+}
+
+void hess_scratch_address(Context *ctx) {
+    void *p = nullptr;
+    OFRR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ctx->hess_scratch = static_cast<uint64_t *>(p);
+}
+
+int32_t hessenberg_noalloc(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
+                           double tol, int32_t *piv, int32_t *keep) {
+    if (!ctx->hess_scratch) fail(OFRR_ERR_HIP, "hessenberg_noalloc: the fixed exchange array has no address");
+    WordsBuf wb;
+    wb.ext = ctx->hess_scratch;
+    wb.ext_cap = HESS_SCRATCH_WORDS;
+    if (t == OFRR_F64) return run<double>(ctx, n, b, (double *)Y, ldy, tol, piv, keep, nullptr, wb);
+    if (t == OFRR_F32) return run<float>(ctx, n, b, (float *)Y, ldy, tol, piv, keep, nullptr, wb);
     fail(OFRR_ERR_UNSUPPORTED, "hessenberg: element type must be F64 or F32");
 }
 

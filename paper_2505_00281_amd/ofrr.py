@@ -38,7 +38,7 @@ EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error
             "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_eig_partial",
             "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_quantize",
             "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_sliced",
-            "ofrr_block_product_fp8", "ofrr_hessenberg",
+            "ofrr_block_product_fp8", "ofrr_hessenberg", "ofrr_hessenberg_noalloc",
             "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
 
 
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_block_product_sliced.argtypes = [vp, P(Matrix), i32, i32, vp, vp]
     lib.ofrr_block_product_fp8.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, vp]
     lib.ofrr_hessenberg.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
+    lib.ofrr_hessenberg_noalloc.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
     lib.ofrr_project.argtypes = [vp, i64, i32, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                  vp, vp]
     lib.ofrr_pencil_eig.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, vp, P(i32)]
@@ -442,6 +443,25 @@ class Context:
         self._check(self.lib.ofrr_hessenberg(self.h, dt, n, b, _ptr(Y), b, float(tol), _ptr(piv),
                                              _ptr(keep), ctypes.byref(kept)))
         return piv, keep, kept.value
+
+    def hessenberg_noalloc(self, Y: torch.Tensor, tol: float, piv: torch.Tensor, keep: torch.Tensor):
+        """The allocation-free sweep (ofrr_hessenberg_noalloc) on a row-major
+        (n x b) FP64/FP32 block, in place; piv and keep are caller-given
+        int32 device vectors of length >= b.  Returns the kept count."""
+        self._on_device(Y, piv, keep)
+        self._dtype(Y, (torch.float64, torch.float32), "Y")
+        self._dtype(piv, (torch.int32,), "piv")
+        self._dtype(keep, (torch.int32,), "keep")
+        if Y.dim() != 2 or not Y.is_contiguous():
+            raise OfrrError(ERR_INVALID_ARG, "Y must be a contiguous (row-major) n x b block")
+        n, b = Y.shape
+        if piv.numel() < b or keep.numel() < b:
+            raise OfrrError(ERR_INVALID_ARG, "piv and keep need b entries")
+        kept = ctypes.c_int32()
+        dt = F64 if Y.dtype == torch.float64 else F32
+        self._check(self.lib.ofrr_hessenberg_noalloc(self.h, dt, n, b, _ptr(Y), b, float(tol), _ptr(piv),
+                                                     _ptr(keep), ctypes.byref(kept)))
+        return kept.value
 
     def project(self, V: torch.Tensor, W: torch.Tensor, accum: str = "f64", v_dtype: str | None = None):
         """G = V^T V, H = V^T W for row-major (n x b) blocks; FP64 b x b
