@@ -239,6 +239,19 @@ ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_mat
                                      double *const *evals, double *const *evecs,
                                      double *const *resid, ofrr_info *infos);
 
+/* What the last ofrr_eig_partial_batched call on this context ran (host
+ * outputs, any may be NULL): *grouped = 1 if it took the grouped path (one
+ * launch per step over all unconverged problems, iterations replayed from a
+ * HIP graph: plans with degree 1, basis <= 32, refine <= 1, BF16/F16 or F64
+ * basis, FP64 projections, dense A), else 0 (problems one after another);
+ * *rows_red and *rows_f64 the row-tile heights of its reduced and FP64
+ * grouped products, picked by timing each candidate (64, 128, 256 rows) on
+ * the first call for a given problem set and cached in the context;
+ * *replays the graph replays (outer iterations of the slowest problem,
+ * rounded up to the readback interval). */
+ofrr_status ofrr_batched_last_config(ofrr_ctx ctx, int32_t *grouped, int32_t *rows_red, int32_t *rows_f64,
+                                     int32_t *replays);
+
 /* --------------------------------------------------------------------- */
 /* Step entry points: one step of the method on caller buffers.  They run  */
 /* the same kernels the whole-method calls use.                           */

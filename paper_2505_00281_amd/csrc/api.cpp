@@ -236,6 +236,7 @@ ofrr_status ofrr_destroy(ofrr_ctx ctx) {
     ctx->c.ws.release_all();
     if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
     if (ctx->c.sync_ev) (void)hipEventDestroy(ctx->c.sync_ev);
+    if (ctx->c.graph_stream) (void)hipStreamDestroy(ctx->c.graph_stream);
     for (auto e : ctx->c.timer.pool) (void)hipEventDestroy(e);
     for (auto &p : ctx->c.timer.pending) {
         (void)hipEventDestroy(p.a);
@@ -331,6 +332,12 @@ ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_mat
             fail(OFRR_ERR_UNSUPPORTED, "batched: basis_dtype F8E4M3/F32 not supported");
         OFRR_HIP(hipSetDevice(c->device));
         c->profile = plan->profile != 0;
+        c->batched_last_grouped = 0;
+        if (batched_grouped_supported(plan, nprob, As, k, basis)) {
+            c->batched_last_grouped = 1;
+            return batched_grouped_impl(c, nprob, As, k, basis, which, plan, X0s, evals, evecs, resid, infos);
+        }
+        // other plans: one problem after another
         ofrr_status worst = OFRR_OK;
         for (int32_t p = 0; p < nprob; ++p) {
             ofrr_status st = eig_partial_impl(c, &As[p], k, basis, which, plan,
@@ -339,6 +346,17 @@ ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_mat
             if (st != OFRR_OK) worst = st;
         }
         return worst;
+    });
+}
+
+ofrr_status ofrr_batched_last_config(ofrr_ctx ctx, int32_t *grouped, int32_t *rows_red, int32_t *rows_f64,
+                                     int32_t *replays) {
+    return guarded(ctx, [&](Context *c) {
+        if (grouped) *grouped = c->batched_last_grouped;
+        if (rows_red) *rows_red = 32 * c->batched_last_waves[0];
+        if (rows_f64) *rows_f64 = 32 * c->batched_last_waves[1];
+        if (replays) *replays = c->batched_last_replays;
+        return OFRR_OK;
     });
 }
 

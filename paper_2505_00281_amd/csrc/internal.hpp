@@ -116,6 +116,15 @@ struct Context {
     // this device's address of the Hessenberg sweep's fixed exchange array
     // (allocation-free entry point)
     uint64_t *hess_scratch = nullptr;
+    // batched solver: tile heights picked by its autotuner (waves per
+    // workgroup of the reduced and the FP64 grouped product) per problem-set
+    // key, the stream its iteration graph is captured on, and what the last
+    // call used
+    std::map<std::string, std::pair<int, int>> batched_tune;
+    hipStream_t graph_stream = nullptr;
+    int batched_last_grouped = 0;
+    int batched_last_replays = 0;
+    int batched_last_waves[2] = {0, 0};
 
     template <class T>
     T *buf(const std::string &name, size_t count) {
@@ -277,6 +286,16 @@ int32_t hessenberg(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, in
 void hess_scratch_address(Context *ctx);
 int32_t hessenberg_noalloc(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy,
                            double tol, int32_t *piv, int32_t *keep);
+
+// k_batched.hip: many problems per grouped launch, iterations replayed from
+// a HIP graph (plans with one product per iteration, basis <= 32, BF16/F16
+// or FP64 first phase, FP64 projections)
+bool batched_grouped_supported(const ofrr_plan *plan, int32_t nprob, const ofrr_matrix *As, int32_t k,
+                               int32_t basis);
+ofrr_status batched_grouped_impl(Context *ctx, int32_t nprob, const ofrr_matrix *As, int32_t k, int32_t basis,
+                                 ofrr_which which, const ofrr_plan *plan, const double *const *X0s,
+                                 double *const *evals, double *const *evecs, double *const *resid,
+                                 ofrr_info *infos);
 
 // k_project.hip
 // G = V^T V, H = V^T W (b x b FP64, column-major) accumulated per `acc`

@@ -36,7 +36,7 @@ _TAIL = {"f64": 0, "i8": 1}
 
 EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error",
             "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_eig_partial",
-            "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_quantize",
+            "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_batched_last_config", "ofrr_quantize",
             "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_sliced",
             "ofrr_block_product_fp8", "ofrr_hessenberg", "ofrr_hessenberg_noalloc",
             "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_svd_partial.argtypes = [vp, P(Matrix), i32, i32, P(Plan), vp, vp, vp, vp, vp, P(Info)]
     lib.ofrr_eig_partial_batched.argtypes = [vp, i32, P(Matrix), i32, i32, ctypes.c_int, P(Plan),
                                              P(vp), P(vp), P(vp), P(vp), P(Info)]
+    lib.ofrr_batched_last_config.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     lib.ofrr_quantize.argtypes = [vp, ctypes.c_int, i64, vp, vp]
     lib.ofrr_quantize_fp8_blocks.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     lib.ofrr_block_product.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, vp, vp]
@@ -337,6 +338,15 @@ class Context:
             arr([o[2] for o in outs]), infos)
         self._check(st, allow_warning=True)
         return [EigResult(o[0], o[1], o[2], infos[p].as_dict(), st) for p, o in enumerate(outs)]
+
+    def batched_last_config(self) -> dict:
+        """What the last eig_partial_batched call ran: grouped path or not,
+        the autotuned row-tile heights of its grouped products, and the
+        number of iteration-graph replays."""
+        g, rr, rf, rp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.ofrr_batched_last_config(self.h, ctypes.byref(g), ctypes.byref(rr), ctypes.byref(rf),
+                                                      ctypes.byref(rp)))
+        return {"grouped": bool(g.value), "rows_red": rr.value, "rows_f64": rf.value, "replays": rp.value}
 
     # ----------------------------------------------------------------- steps
     def quantize(self, src: torch.Tensor, dtype: str = "bf16") -> torch.Tensor:
