@@ -197,6 +197,76 @@ def hessenberg(Y, tol: float, precision: str = "f64", want_u: bool = False):
     return (Q, piv, keep, U) if want_u else (Q, piv, keep)
 
 
+# ---------------------------------------------------------------------------
+# Basis-generation comparators (Sec. 4.2 comparison table; Sec. 5.3,
+# Table 3): Gram-Schmidt without re-orthogonalisation in its left- and
+# right-looking forms, classical Gram-Schmidt and CGS with one re-
+# orthogonalisation.  Plain FP64 definitions, column by column; every
+# inner product is the same library dot product, so the two MGS forms do
+# identical arithmetic on every column (they differ only in when a
+# column's projections are applied).  Each returns (Q, R) with A = Q R.
+# ---------------------------------------------------------------------------
+
+def _dot(x, y):
+    return float(np.dot(x, y))
+
+
+def gs_mgs_left(A):
+    """Left-looking MGS: column j is projected against q_0 .. q_{j-1} one at
+    a time, each coefficient taken from the partly projected column."""
+    A = np.array(A, dtype=np.float64, order="F", copy=True)
+    m, n = A.shape
+    Q = np.zeros_like(A)
+    R = np.zeros((n, n))
+    for j in range(n):
+        v = A[:, j].copy()
+        for i in range(j):
+            R[i, j] = _dot(Q[:, i], v)
+            v = v - R[i, j] * Q[:, i]
+        R[j, j] = np.sqrt(_dot(v, v))
+        Q[:, j] = v / R[j, j]
+    return Q, R
+
+
+def gs_mgs_right(A):
+    """Right-looking MGS: once q_i is final, its projection is removed from
+    every later column at once."""
+    W = np.array(A, dtype=np.float64, order="F", copy=True)
+    m, n = W.shape
+    Q = np.zeros_like(W)
+    R = np.zeros((n, n))
+    for i in range(n):
+        R[i, i] = np.sqrt(_dot(W[:, i], W[:, i]))
+        Q[:, i] = W[:, i] / R[i, i]
+        for j in range(i + 1, n):
+            R[i, j] = _dot(Q[:, i], W[:, j])
+            W[:, j] = W[:, j] - R[i, j] * Q[:, i]
+    return Q, R
+
+
+def gs_cgs(A, reorth: bool = False):
+    """Classical Gram-Schmidt: all coefficients of column j from the
+    original column (r = Q^T a_j, v = a_j - Q r); with `reorth` the
+    projection is repeated once on v and the coefficients are added."""
+    A = np.array(A, dtype=np.float64, order="F", copy=True)
+    m, n = A.shape
+    Q = np.zeros_like(A)
+    R = np.zeros((n, n))
+    for j in range(n):
+        a = A[:, j]
+        Qj = Q[:, :j]
+        r = Qj.T @ a
+        v = a - Qj @ r
+        if reorth:
+            r2 = Qj.T @ v
+            v = v - Qj @ r2
+            r = r + r2
+        R[:j, j] = r
+        R[j, j] = np.sqrt(_dot(v, v))
+        Q[:, j] = v / R[j, j]
+    return Q, R
+
+
 def round_binary16(x):
     """FP32 values rounded to the nearest IEEE binary16 value (ties to
     even), as FP32 (the C oracle's rounding, applied elementwise)."""

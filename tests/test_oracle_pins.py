@@ -11,6 +11,7 @@ import pytest
 import scipy.linalg as sla
 
 import workloads as W
+from oracle import ofrr_oracle as O
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -511,3 +512,64 @@ def test_hessenberg_f16s_is_rounded_f32_process(oracle):
     Q64, p64, _ = oracle.hessenberg(Yr, 1e-12, "f64")
     np.testing.assert_array_equal(p16[:4], p64[:4])  # early pivots agree (later ones may swap on ties)
     assert np.max(np.abs(Q16[:, :4] - Q64[:, :4])) < 2e-2
+
+
+# ---------------------------------------------------------------------------
+# Gram-Schmidt comparators (Sec. 4.2 comparison table; Sec. 5.3, Table 3)
+# ---------------------------------------------------------------------------
+
+_GS = {
+    "mgs_left": lambda A: O.gs_mgs_left(A),
+    "mgs_right": lambda A: O.gs_mgs_right(A),
+    "cgs": lambda A: O.gs_cgs(A),
+    "cgs2": lambda A: O.gs_cgs(A, reorth=True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(_GS))
+def test_gs_hand_worked_3x2(name):
+    # a1 = (3, 4, 0): r11 = 5, q1 = (0.6, 0.8, 0); a2 = (1, 2, 2):
+    # r12 = q1.a2 = 2.2, v = a2 - 2.2 q1 = (-0.32, 0.24, 2), r22 = sqrt(4.16)
+    A = np.array([[3.0, 1.0], [4.0, 2.0], [0.0, 2.0]])
+    Q, R = _GS[name](A)
+    r22 = np.sqrt(4.16)
+    np.testing.assert_allclose(R, [[5.0, 2.2], [0.0, r22]], rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(Q[:, 0], [0.6, 0.8, 0.0], atol=1e-16)
+    np.testing.assert_allclose(Q[:, 1], np.array([-0.32, 0.24, 2.0]) / r22, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", sorted(_GS))
+def test_gs_matches_householder_qr(name):
+    A = np.random.default_rng(11).random((300, 40))
+    Qh, Rh = np.linalg.qr(A)
+    s = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * s, Rh * s[:, None]
+    Q, R = _GS[name](A)
+    np.testing.assert_allclose(Q, Qh, atol=1e-12)
+    np.testing.assert_allclose(R, Rh, atol=1e-11)
+
+
+def test_gs_loss_of_orthogonality_ordering():
+    # kappa = 1e6: CGS loses orthogonality like kappa^2 u, MGS like kappa u,
+    # CGS with one re-orthogonalisation stays at u; every variant is
+    # backward stable (A = Q R to working precision)
+    rng = np.random.default_rng(12)
+    U, _ = np.linalg.qr(rng.standard_normal((100, 20)))
+    V, _ = np.linalg.qr(rng.standard_normal((20, 20)))
+    A = (U * np.logspace(0, -6, 20)) @ V.T
+    loss = {}
+    for name, f in _GS.items():
+        Q, R = f(A)
+        loss[name] = np.linalg.norm(Q.T @ Q - np.eye(20), 2)
+        assert np.linalg.norm(A - Q @ R) <= 1e-14 * np.linalg.norm(A)
+    assert loss["cgs2"] <= 1e-13
+    assert 1e-14 <= loss["mgs_left"] <= 1e-8 and loss["mgs_right"] <= 1e-8
+    assert loss["cgs"] >= 1e-6
+
+
+def test_mgs_left_and_right_are_bitwise_equal():
+    A = np.random.default_rng(13).random((500, 30))
+    Ql, Rl = O.gs_mgs_left(A)
+    Qr, Rr = O.gs_mgs_right(A)
+    np.testing.assert_array_equal(Ql, Qr)
+    np.testing.assert_array_equal(Rl, Rr)
