@@ -573,3 +573,63 @@ def test_mgs_left_and_right_are_bitwise_equal():
     Qr, Rr = O.gs_mgs_right(A)
     np.testing.assert_array_equal(Ql, Qr)
     np.testing.assert_array_equal(Rl, Rr)
+
+
+# ---------------------------------------------------------------------------
+# Krylov-Hessenberg process and the restarted Krylov reference (Sec. 4.1,
+# Alg. "Computing non-orthogonal bases from the Krylov-Hessenberg Process";
+# Sec. 5.2 sparse experiments)
+# ---------------------------------------------------------------------------
+
+def test_krylov_hessenberg_hand_worked_3x3():
+    # v = e1: v1 = e1 (pivot 0); A e1 = (2, 1, 0) loses 2 e1 -> e2 (pivot 1,
+    # scale 1); A e2 = (1, 3, 1) loses 1 e1 and 3 e2 -> e3 (pivot 2)
+    A = np.array([[2.0, 1.0, 0.0], [1.0, 3.0, 1.0], [0.0, 1.0, 4.0]])
+    V, piv, H = O.krylov_hessenberg(A, np.array([1.0, 0.0, 0.0]), 3)
+    np.testing.assert_array_equal(V, np.eye(3))
+    np.testing.assert_array_equal(piv, [0, 1, 2])
+    np.testing.assert_array_equal(H, [[2.0, 1.0], [1.0, 3.0], [0.0, 1.0]])
+
+
+def test_krylov_hessenberg_relation_and_structure():
+    rng = np.random.default_rng(21)
+    A = _rand_sym(60, 22)
+    v = rng.random(60)
+    k = 15
+    V, piv, H = O.krylov_hessenberg(A, v, k)
+    assert V.shape == (60, k) and len(set(piv.tolist())) == k
+    # A V_{k-1} = V H (the Krylov relation of the process), H upper Hessenberg
+    np.testing.assert_allclose(A @ V[:, :k - 1], V @ H, atol=1e-12 * np.abs(A).max() * 60)
+    assert np.all(np.tril(H, -2) == 0.0)
+    # unit pivots, exact zeros at earlier pivot rows, |entries| <= 1
+    for i in range(k):
+        assert V[piv[i], i] == 1.0
+        for l in range(i):
+            assert V[piv[l], i] == 0.0
+    assert np.abs(V).max() <= 1.0
+    # the same subspace as the orthonormal Krylov basis
+    Q = np.linalg.qr(np.column_stack([np.linalg.matrix_power(A, p) @ v for p in range(6)]))[0]
+    Vq = np.linalg.qr(V[:, :6])[0]
+    assert O.subspace_sin(Q, Vq) <= 1e-8
+
+
+def test_krylov_eig_full_space_is_exact():
+    # k = n: the Krylov space of a generic start vector is the whole space,
+    # so the Ritz values are the eigenvalues (brute force)
+    A = _rand_sym(12, 23)
+    v = np.random.default_rng(24).random(12)
+    r = O.krylov_eig(A, v, 12, 5)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    np.testing.assert_allclose(r.theta, lam[:5], rtol=1e-12, atol=1e-12)
+    assert np.all(r.resid <= 1e-12)
+
+
+def test_krylov_eig_restarts_converge_on_prescribed_spectrum():
+    lam = np.concatenate([[10.0, 9.0, 8.0], np.linspace(1.0, 0.0, 397)])
+    A = _prescribed(lam, 25)
+    v = np.random.default_rng(26).random(400)
+    r0 = O.krylov_eig(A, v, 20, 3, restarts=0)
+    r4 = O.krylov_eig(A, v, 20, 3, restarts=4)
+    assert r4.resid[0] < r0.resid[0]
+    np.testing.assert_allclose(r4.theta[0], 10.0, rtol=1e-12)
+    assert r4.resid[0] <= 1e-10
