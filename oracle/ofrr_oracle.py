@@ -273,7 +273,7 @@ def gs_cgs(A, reorth: bool = False):
 # of the largest Ritz value, Sec. 5.2 sparse-matrix experiments)
 # ---------------------------------------------------------------------------
 
-def krylov_hessenberg(A, v, k: int):
+def krylov_hessenberg(A, v, k: int, brk: float = 64 * 2.0 ** -52):
     """The Krylov-Hessenberg process in FP64, step by step as the algorithm
     states it: v is scaled by its entry of largest magnitude (first index
     on ties), then for j = 1..k-1 the product w = A v_j loses, for
@@ -281,8 +281,11 @@ def krylov_hessenberg(A, v, k: int):
     by its new largest entry.  Returns (V (n x k_eff), pi, H) with
     A V[:, :k_eff-1] = V H (H (k_eff x k_eff-1) upper Hessenberg: H[i, j]
     the weight w(pi_i) removed at step j, H[j+1, j] the scaling pivot); the
-    process stops early (k_eff < k) when w vanishes (an invariant
-    subspace was reached)."""
+    process stops early (k_eff < k) when what is left of A v_j after the
+    removals is at the rounding level of the quantities it came from
+    (max |w| <= brk (max |A v_j| + sum_i |H[i, j]|): an invariant subspace
+    was reached; the algorithm as printed has no such test, w being exactly
+    zero there in exact arithmetic)."""
     op = as_op(A)
     v = np.array(v, dtype=np.float64).ravel()
     n = v.size
@@ -294,11 +297,12 @@ def krylov_hessenberg(A, v, k: int):
     piv.append(r)
     for j in range(k - 1):
         w = op.apply(V[:, j:j + 1])[:, 0]
+        scale = float(np.abs(w).max())
         for i in range(j + 1):
             H[i, j] = w[piv[i]]
             w = w - H[i, j] * V[:, i]
         r = int(np.argmax(np.abs(w)))
-        if w[r] == 0.0:
+        if not abs(w[r]) > brk * (scale + float(np.abs(H[:j + 1, j]).sum())):
             return V[:, :j + 1], np.array(piv, np.int32), H[:j + 1, :j]
         H[j + 1, j] = w[r]
         V[:, j + 1] = w / w[r]
@@ -334,11 +338,12 @@ def krylov_eig(A, v0, k: int, nev: int, restarts: int = 0):
         kk = k
         for j in range(1, k):
             w = op.apply(Q[:, j - 1:j])[:, 0]
+            scale = np.linalg.norm(w)
             for _ in range(2):
                 for i in range(j):
                     w = w - _dot(Q[:, i], w) * Q[:, i]
             nw = np.linalg.norm(w)
-            if nw == 0.0:
+            if not nw > 64 * 2.0 ** -52 * scale:  # an invariant subspace: stop there
                 kk = j
                 break
             Q[:, j] = w / nw

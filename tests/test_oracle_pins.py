@@ -633,3 +633,14 @@ def test_krylov_eig_restarts_converge_on_prescribed_spectrum():
     assert r4.resid[0] < r0.resid[0]
     np.testing.assert_allclose(r4.theta[0], 10.0, rtol=1e-12)
     assert r4.resid[0] <= 1e-10
+
+
+def test_krylov_stops_at_an_invariant_subspace():
+    # five distinct eigenvalues: K(A, v) has dimension 5 for a generic v
+    lam = np.repeat([5.0, 4.0, 3.0, 2.0, 1.0], 10)
+    A = _prescribed(lam, 27)
+    v = np.random.default_rng(28).random(50)
+    V, piv, H = O.krylov_hessenberg(A, v, 12)
+    assert V.shape[1] == 5
+    r = O.krylov_eig(A, v, 12, 5)
+    np.testing.assert_allclose(r.theta, [5.0, 4.0, 3.0, 2.0, 1.0], rtol=1e-13)
