@@ -467,8 +467,20 @@ class CsrOp:
         return csr_matmul(self.row_ptr, self.col_idx, self.values, X)
 
 
+class NormalOp:
+    """op(X) = A^T (A X) for a dense m x n A held in FP64: the operator of the
+    normal-equations (A^T A) form of the SVD."""
+
+    def __init__(self, A):
+        self.A = np.asarray(A, dtype=np.float64)
+        self.n = self.A.shape[1]
+
+    def apply(self, X):
+        return self.A.T @ (self.A @ X)
+
+
 def as_op(A):
-    if isinstance(A, (DenseOp, CsrOp)):
+    if isinstance(A, (DenseOp, CsrOp, NormalOp)):
         return A
     if isinstance(A, tuple) and len(A) == 3:
         return CsrOp(*A)
@@ -667,6 +679,26 @@ def subspace_svd(A, V0, k: int, outer: int = 10, tol: float | None = None,
     r = svd_residuals(A, s[:k], Ur[:, :k], Vr[:, :k], an)
     Vk, Uk = normalize_signs(Vr[:, :k], Ur[:, :k])
     return SvdResult(s[:k].copy(), Uk, Vk, r, s.copy(), Vr, it)
+
+
+def subspace_svd_normal(A, V0, k: int, outer: int = 10, tol: float | None = None,
+                        anorm: float | None = None, max_outer: int = 100000):
+    """The normal-equations form of the SVD: subspace iteration with
+    Rayleigh-Ritz on A^T A (power filter, restart from all Ritz vectors),
+    singular values s = sqrt(theta), right vectors the Ritz vectors, left
+    vectors u = A v / s; residuals as for the SVD.  Same-step mode when tol
+    is None; converged mode iterates the eigenproblem to tol * (anorm^2)."""
+    A = np.asarray(A, dtype=np.float64)
+    op = NormalOp(A)
+    an2 = anorm * anorm if anorm else None
+    r = subspace_eig(op, V0, k, outer=outer, tol=tol, anorm=an2, max_outer=max_outer)
+    s = np.sqrt(np.maximum(r.theta, 0.0))
+    V = r.X
+    U = (A @ V) / s
+    an = anorm if anorm else float(s[0])
+    res = svd_residuals(A, s, U, V, an)
+    Vn, Un = normalize_signs(V, U)
+    return SvdResult(s.copy(), Un, Vn, res, s.copy(), Vn, r.iters)
 
 
 # ---------------------------------------------------------------------------

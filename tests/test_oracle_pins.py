@@ -644,3 +644,20 @@ def test_krylov_stops_at_an_invariant_subspace():
     assert V.shape[1] == 5
     r = O.krylov_eig(A, v, 12, 5)
     np.testing.assert_allclose(r.theta, [5.0, 4.0, 3.0, 2.0, 1.0], rtol=1e-13)
+
+
+def test_svd_normal_equations_matches_lapack():
+    # the A^T A form: s = sqrt(theta) of the Ritz values of A^T A, u = A v / s
+    rng = np.random.default_rng(29)
+    m, n, k = 120, 40, 5
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sig = 2.0 ** (-np.arange(n) / 3.0)
+    A = (U * sig) @ V.T
+    V0 = rng.random((n, 10))
+    r = O.subspace_svd_normal(A, V0, k, tol=1e-14, max_outer=500)
+    s_ref = np.linalg.svd(A, compute_uv=False)[:k]
+    np.testing.assert_allclose(r.sigma, s_ref, rtol=1e-11)
+    assert np.all(r.resid <= 1e-10)
+    # u_i = A v_i / s_i are unit and orthogonal
+    np.testing.assert_allclose(r.U.T @ r.U, np.eye(k), atol=1e-10)
