@@ -144,6 +144,31 @@ typedef struct {
                                 positive definite; 0 -> 1000 (an FP32 perturbation of
                                 2^-24 per term of a 32-row run, scaled by t, stays below
                                 about 1e-3 of G's smallest eigenvalue) */
+    int32_t svd_form;        /* ofrr_svd_partial: 0 the augmented pencil [0 B; B^T 0] of
+                                Sec. 3.2 (the paper's form); 1 the normal equations: the
+                                eigen solver on the operator A^T A (each product A V then
+                                A^T (A V)), s = sqrt(theta), u = A v / s.  The second
+                                squares the condition of the singular values: s is found
+                                to about u (s_1 / s)^2 relative (dense A, BF16/F16/F64
+                                basis) */
+    int32_t stab;            /* basis stabilisation: 0 the Hessenberg process (Sec. 4.2);
+                                1 QR by MGS with re-orthogonalisation (the comparison of
+                                Sec. 5.2) */
+    int32_t projection;      /* 0 the orthogonalization-free pencil H y = theta G y
+                                (Sec. 3.1); 1 the classical Rayleigh-Ritz projection,
+                                which takes the basis as orthonormal (G = I) */
+    int32_t qr_dtype;        /* stab 1: arithmetic of the QR (an ofrr_dtype: F64, F32, or F16
+                                storage with FP32 arithmetic); -1 -> the phase's storage type.  A QR wider
+                                than a reduced-precision phase's storage leaves its basis at
+                                the phase's FP32 master precision (the products still read it
+                                rounded to the storage type): the [MatVec]-[QR] precision
+                                pairs of the Sec. 2 experiment */
+    int32_t tail_digits;     /* OFRR_TAIL_I8_SLICED: signed 7-bit digits per side of the
+                                digit-plane products.  0: chosen per iteration from the
+                                previous largest residual estimate r (4 while r > 1600
+                                2^-28, 5 while r > 1600 2^-35, else 6); 4, 5 or 6: fixed.
+                                S digits are exact to about 2^-7S of the row and column
+                                scales of A and V */
 } ofrr_plan;
 
 typedef struct {
@@ -165,7 +190,8 @@ typedef struct {
 
 /* Defaults: FP64 basis, FP64 accumulation, no refinement, power filter of
  * degree 1, drop_tol 0, tol 0, anorm 0, max_iters 20, stall_iters 3,
- * switch_resid 0, b_split 1, profile 0, tail_product F64, gram_switch_t 0. */
+ * switch_resid 0, b_split 1, profile 0, tail_product F64, gram_switch_t 0,
+ * svd_form 0, stab 0, projection 0, qr_dtype -1, tail_digits 0. */
 void ofrr_plan_default(ofrr_plan *plan);
 
 /* Creates a context bound to `device` and to `hip_stream` (a hipStream_t,
@@ -189,6 +215,10 @@ const char *ofrr_last_error(ofrr_ctx ctx);
 ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches /*host*/,
                               double *total_ms /*host*/);
 ofrr_status ofrr_kernel_stats_reset(ofrr_ctx ctx);
+/* Kernel timing for the step entry points (on != 0: every launch of a step
+ * call is timed into the families above); the whole-method calls set it
+ * from plan.profile. */
+ofrr_status ofrr_set_profile(ofrr_ctx ctx, int32_t on);
 
 /* --------------------------------------------------------------------- */
 /* Whole-method entry points (Sec. 2-4)                                   */
@@ -248,9 +278,38 @@ ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_mat
  * grouped products, picked by timing each candidate (64, 128, 256 rows) on
  * the first call for a given problem set and cached in the context;
  * *replays the graph replays (outer iterations of the slowest problem,
- * rounded up to the readback interval). */
+ * rounded up to the readback interval); *first_product_ms the device time
+ * (HIP events on the context's stream) of the call's first grouped product
+ * A X0, which covers every problem in the first phase. */
 ofrr_status ofrr_batched_last_config(ofrr_ctx ctx, int32_t *grouped, int32_t *rows_red, int32_t *rows_f64,
-                                     int32_t *replays);
+                                     int32_t *replays, double *first_product_ms);
+
+/* The paper's Krylov method for sparse (or dense) symmetric A (Sec. 4.1,
+ * Alg. "Computing non-orthogonal bases from the Krylov-Hessenberg
+ * Process", with the orthogonalization-free projection of Sec. 3.1 and the
+ * restart of the sparse experiments in Sec. 5.2): each cycle builds the
+ * Krylov-Hessenberg basis of K_k(A, v) (v scaled by its largest entry,
+ * then per step w = A v_j loses its entry at each earlier pivot row times
+ * that basis vector, and is scaled by its new largest entry: no inner
+ * products), projects G = V^T V and H = V^T A V in FP64, solves the pencil
+ * in FP64, and restarts from the Ritz vector of the largest Ritz value;
+ * `restarts` cycles follow the first.
+ *   k          Krylov dimension, 2 <= k <= 512, k <= n.
+ *   nev        wanted pairs (largest algebraic), 1 <= nev <= k.
+ *   basis_dtype storage and arithmetic of the process: OFRR_F64, OFRR_F32,
+ *              or OFRR_F16 (binary16 storage, FP32 arithmetic).
+ *   v0         n FP64 start vector (device) or NULL for U(0,1).
+ *   tol        > 0: info.n_converged counts resid <= tol (and the status is
+ *              OFRR_NOT_CONVERGED if fewer than nev meet it); 0: no test.
+ *   evals      nev FP64, descending; evecs n x nev FP64 column-major, unit
+ *              2-norm, sign rule as ofrr_eig_partial.
+ *   resid      nev FP64: ||A x - lambda x||_2 / |lambda|, from A as stored
+ *              in FP64 (the paper's Krylov metric).
+ * If the process meets an invariant subspace (w = 0) the basis stops there
+ * (info.basis_eff < k) and the projection drops the missing directions. */
+ofrr_status ofrr_krylov_eig(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t nev, int32_t restarts,
+                            ofrr_dtype basis_dtype, const double *v0, double tol, double *evals,
+                            double *evecs, double *resid, ofrr_info *info);
 
 /* --------------------------------------------------------------------- */
 /* Step entry points: one step of the method on caller buffers.  They run  */
@@ -335,6 +394,53 @@ ofrr_status ofrr_hessenberg(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b
 ofrr_status ofrr_hessenberg_noalloc(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, int32_t b, void *Y,
                                     int64_t ldy, double tol, int32_t *piv, int32_t *keep,
                                     int32_t *kept);
+
+/* The basis-generation processes compared with the Hessenberg process
+ * (Sec. 4.2, the comparison table of MGS, CGS and Hessenberg; timed in
+ * Sec. 5.3, Table 3). */
+typedef enum {
+    OFRR_BASIS_MGS_L = 0,  /* left-looking MGS, no re-orthogonalisation: column j is
+                              projected against q_0..q_{j-1} one at a time */
+    OFRR_BASIS_MGS_R = 1,  /* right-looking MGS: q_i removed from all later columns */
+    OFRR_BASIS_CGS = 2,    /* classical GS: r = Q^T a_j, v = a_j - Q r */
+    OFRR_BASIS_CGS2 = 3,   /* CGS with one re-orthogonalisation */
+    OFRR_BASIS_HESS_L = 4, /* Hessenberg process, left-looking (column j receives the
+                              eliminations of the kept columns before it, in order) */
+    OFRR_BASIS_HESS_R = 5, /* Hessenberg process, right-looking (Alg. "Computing
+                              non-orthogonal bases from the Hessenberg Process") */
+    OFRR_BASIS_MGS2 = 6    /* left-looking MGS with a second projection pass when the
+                              first reduced the norm below sqrt(2)/2 of its value
+                              (Sec. 5.1); the QR of the classical comparisons */
+} ofrr_basis_method;
+
+/* One basis-generation process on a column-major m x n block A (lda >= m,
+ * n <= m, n <= 512, m < 2^31), in place, as one cooperative launch on the
+ * context's stream:
+ *   storage  OFRR_F64 (double), OFRR_F32 (float) or OFRR_F16 (binary16 bits,
+ *            uint16 per entry, every result rounded to binary16, FP32
+ *            arithmetic and FP32 inner products: the paper's FP16 runs).
+ *   Gram-Schmidt methods: A becomes Q (orthonormal columns up to rounding);
+ *            R (n x n FP64, column-major, upper triangle; NULL to skip) gets
+ *            the coefficients, A_in = Q R.  No column is dropped, except by
+ *            MGS2 with tol > 0: a column whose norm after its projections is
+ *            at most tol times its norm before them is excluded (keep = 0,
+ *            piv = -1, left unnormalised and not projected out of later
+ *            columns; piv = j for a kept column); piv and keep may then be
+ *            NULL (not returned).
+ *   Hessenberg methods: the pivot of column j is its first row of largest
+ *            magnitude, the column is divided by it and its multiple removed
+ *            from later columns (one fused multiply-add per entry); columns
+ *            whose pivot magnitude is below tol are dropped (keep = 0,
+ *            piv = -1) and eliminate nothing.  The kept columns of A are
+ *            then P^T L of the row-pivoted LU factorisation.  piv, keep:
+ *            int32[n] device; R ignored.  The two forms give the same bits.
+ *   kept     host, may be NULL: kept columns (n for Gram-Schmidt without
+ *            exclusion).
+ *   kernel_ms host, may be NULL: device time of the launch (HIP events).
+ * A grid-barrier wait that times out gives OFRR_ERR_HIP. */
+ofrr_status ofrr_basis_generate(ofrr_ctx ctx, ofrr_basis_method method, ofrr_dtype storage, int64_t m,
+                                int32_t n, void *A, int64_t lda, double tol, double *R, int32_t *piv,
+                                int32_t *keep, int32_t *kept, double *kernel_ms);
 
 /* Projections G = V^T V and H = V^T W (Alg. "Orthogonalization-Free
  * Rayleigh-Ritz Projection", the products forming B and M), b x b FP64

@@ -12,7 +12,11 @@ namespace ofrr {
 
 ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              ofrr_which which, const ofrr_plan *plan, const double *X0,
-                             double *evals, double *evecs, double *resid, ofrr_info *info);
+                             double *evals, double *evecs, double *resid, ofrr_info *info,
+                             bool normal = false);
+ofrr_status svd_normal_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                            const ofrr_plan *plan, const double *V0, double *sigma, double *U,
+                            double *V, double *resid, ofrr_info *info);
 ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              const ofrr_plan *plan, const double *V0, double *sigma, double *U,
                              double *V, double *resid, ofrr_info *info);
@@ -142,6 +146,12 @@ static void validate_matrix(const ofrr_matrix *A, bool square) {
 
 static void validate_plan(const ofrr_plan *p) {
     OFRR_CHECK_ARG(p != nullptr, "plan is NULL");
+    OFRR_CHECK_ARG(p->stab == 0 || p->stab == 1, "plan.stab must be 0 or 1");
+    OFRR_CHECK_ARG(p->projection == 0 || p->projection == 1, "plan.projection must be 0 or 1");
+    OFRR_CHECK_ARG(p->qr_dtype == -1 || p->qr_dtype == OFRR_F64 || p->qr_dtype == OFRR_F32 || p->qr_dtype == OFRR_F16,
+                   "plan.qr_dtype must be -1, F64, F32 or F16");
+    OFRR_CHECK_ARG(p->tail_digits == 0 || (p->tail_digits >= 4 && p->tail_digits <= 6),
+                   "plan.tail_digits must be 0, 4, 5 or 6");
     OFRR_CHECK_ARG(p->basis_dtype == OFRR_F64 || p->basis_dtype == OFRR_BF16 ||
                        p->basis_dtype == OFRR_F16 || p->basis_dtype == OFRR_F32 ||
                        p->basis_dtype == OFRR_F8E4M3,
@@ -182,6 +192,11 @@ void ofrr_plan_default(ofrr_plan *p) {
     p->profile = 0;
     p->tail_product = OFRR_TAIL_F64;
     p->gram_switch_t = 0.0;
+    p->svd_form = 0;
+    p->stab = 0;
+    p->projection = 0;
+    p->qr_dtype = -1;
+    p->tail_digits = 0;
 }
 
 ofrr_status ofrr_create(ofrr_ctx *out, int device, void *hip_stream) {
@@ -282,8 +297,11 @@ ofrr_status ofrr_eig_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
         OFRR_CHECK_ARG(k >= 1 && k <= basis && basis <= A->rows, "need 1 <= k <= basis <= n");
         OFRR_CHECK_ARG(basis <= 512, "basis must be <= 512");
         OFRR_CHECK_ARG(evals && evecs && resid, "output pointers must not be NULL");
-        if (plan->basis_dtype == OFRR_F8E4M3 || plan->basis_dtype == OFRR_F32)
-            fail(OFRR_ERR_UNSUPPORTED, "eig_partial: basis_dtype F8E4M3/F32 not supported");
+        if (plan->basis_dtype == OFRR_F8E4M3)
+            fail(OFRR_ERR_UNSUPPORTED, "eig_partial: basis_dtype F8E4M3 (the SVD path) not supported");
+        if (plan->basis_dtype == OFRR_F32 && plan->refine >= 2)
+            fail(OFRR_ERR_UNSUPPORTED, "eig_partial: the split middle phase needs a BF16 basis");
+        if (plan->stab == 1) OFRR_CHECK_ARG(basis <= 512, "QR stabilisation: basis <= 512");
         if (A->format == OFRR_DENSE_COLMAJOR && plan->basis_dtype != OFRR_F64)
             OFRR_CHECK_ARG(A->rows < (int64_t)1 << 31, "dense reduced-precision path needs n < 2^31");
         OFRR_HIP(hipSetDevice(c->device));
@@ -300,6 +318,20 @@ ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
         validate_matrix(A, false);
         validate_plan(plan);
         OFRR_CHECK_ARG(A->format == OFRR_DENSE_COLMAJOR, "svd_partial: dense A only");
+        OFRR_CHECK_ARG(plan->svd_form == 0 || plan->svd_form == 1, "svd_partial: svd_form 0 or 1");
+        if (plan->svd_form == 1) {
+            const int64_t mn = A->rows < A->cols ? A->rows : A->cols;
+            OFRR_CHECK_ARG(k >= 1 && k <= basis && basis <= mn, "need 1 <= k <= basis <= min(m, n)");
+            OFRR_CHECK_ARG(sigma && U && V && resid, "output pointers must not be NULL");
+            OFRR_CHECK_ARG(plan->basis_dtype == OFRR_F64 || plan->basis_dtype == OFRR_BF16 ||
+                               plan->basis_dtype == OFRR_F16,
+                           "svd_partial (normal equations): basis F64, BF16 or F16");
+            OFRR_HIP(hipSetDevice(c->device));
+            c->profile = plan->profile != 0;
+            return svd_normal_impl(c, A, k, basis, plan, V0, sigma, U, V, resid, info);
+        }
+        if (plan->stab != 0 || plan->projection != 0)
+            fail(OFRR_ERR_UNSUPPORTED, "svd_partial: Hessenberg stabilisation and the OFRR projection only");
         OFRR_CHECK_ARG(plan->filter == OFRR_POWER && plan->degree == 1,
                        "svd_partial: power filter of degree 1");
         const int64_t mn = A->rows < A->cols ? A->rows : A->cols;
@@ -349,9 +381,35 @@ ofrr_status ofrr_eig_partial_batched(ofrr_ctx ctx, int32_t nprob, const ofrr_mat
     });
 }
 
-ofrr_status ofrr_batched_last_config(ofrr_ctx ctx, int32_t *grouped, int32_t *rows_red, int32_t *rows_f64,
-                                     int32_t *replays) {
+ofrr_status ofrr_krylov_eig(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t nev, int32_t restarts,
+                            ofrr_dtype basis_dtype, const double *v0, double tol, double *evals,
+                            double *evecs, double *resid, ofrr_info *info) {
     return guarded(ctx, [&](Context *c) {
+        validate_matrix(A, true);
+        OFRR_CHECK_ARG(k >= 2 && k <= 512 && k <= A->rows, "krylov: 2 <= k <= min(512, n)");
+        OFRR_CHECK_ARG(nev >= 1 && nev <= k, "krylov: 1 <= nev <= k");
+        OFRR_CHECK_ARG(restarts >= 0, "krylov: restarts >= 0");
+        OFRR_CHECK_ARG(tol >= 0, "krylov: tol >= 0");
+        OFRR_CHECK_ARG(evals && evecs && resid, "krylov: NULL output");
+        OFRR_CHECK_ARG(basis_dtype == OFRR_F64 || basis_dtype == OFRR_F32 || basis_dtype == OFRR_F16,
+                       "krylov: basis F64, F32 or F16");
+        OFRR_HIP(hipSetDevice(c->device));
+        if (A->format == OFRR_CSR) check_csr(c, A);
+        return krylov_eig_impl(c, A, k, nev, restarts, basis_dtype, v0, tol, evals, evecs, resid, info);
+    });
+}
+
+ofrr_status ofrr_set_profile(ofrr_ctx ctx, int32_t on) {
+    return guarded(ctx, [&](Context *c) {
+        c->profile = on != 0;
+        return OFRR_OK;
+    });
+}
+
+ofrr_status ofrr_batched_last_config(ofrr_ctx ctx, int32_t *grouped, int32_t *rows_red, int32_t *rows_f64,
+                                     int32_t *replays, double *first_product_ms) {
+    return guarded(ctx, [&](Context *c) {
+        if (first_product_ms) *first_product_ms = c->batched_last_first_ms;
         if (grouped) *grouped = c->batched_last_grouped;
         if (rows_red) *rows_red = 32 * c->batched_last_waves[0];
         if (rows_f64) *rows_f64 = 32 * c->batched_last_waves[1];
@@ -485,6 +543,18 @@ ofrr_status ofrr_hessenberg_noalloc(ofrr_ctx ctx, ofrr_dtype dtype, int64_t n, i
             c->profile = prof;
             throw;
         }
+        return OFRR_OK;
+    });
+}
+
+ofrr_status ofrr_basis_generate(ofrr_ctx ctx, ofrr_basis_method method, ofrr_dtype storage, int64_t m,
+                                int32_t n, void *A, int64_t lda, double tol, double *R, int32_t *piv,
+                                int32_t *keep, int32_t *kept, double *kernel_ms) {
+    return guarded(ctx, [&](Context *c) {
+        OFRR_CHECK_ARG(A && m >= 1 && n >= 1 && tol >= 0, "basis_generate: bad arguments");
+        OFRR_CHECK_ARG((int)method >= 0 && (int)method <= 6, "basis_generate: unknown method");
+        OFRR_HIP(hipSetDevice(c->device));
+        basis_generate(c, (int)method, storage, m, n, A, lda, tol, R, piv, keep, kept, kernel_ms);
         return OFRR_OK;
     });
 }

@@ -18,7 +18,14 @@ struct f16_t {
     uint16_t bits;
 };
 
+// The conversions below round an FP32 value that has already been rounded
+// to FP32.  The empty asm hides the value's origin from the compiler, which
+// would otherwise fuse an FP32 fma followed by the conversion into one
+// mixed-precision fma (v_fma_mixlo_f16) that rounds the exact result to
+// binary16 once; FP32 arithmetic on 16-bit data rounds twice (to FP32, then
+// to the storage type), and the tests compare against exactly that.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+    __asm__("" : "+v"(x));
     __bf16 h = (__bf16)x;  // round to nearest even (hardware conversion on gfx950)
     return __builtin_bit_cast(uint16_t, h);
 }
@@ -26,6 +33,7 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
     return __builtin_bit_cast(float, (uint32_t)b << 16);
 }
 __device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
+    __asm__("" : "+v"(x));
     _Float16 h = (_Float16)x;
     return __builtin_bit_cast(uint16_t, h);
 }
@@ -127,6 +135,9 @@ __device__ __forceinline__ double block_sum_f64(double v) {
 __device__ __forceinline__ bool grid_barrier(unsigned *counter, unsigned nblocks, unsigned &epoch,
                                              int *err) {
     __shared__ int s_ok;
+    // every thread's earlier global writes are released at device scope
+    // before the workgroup arrives; every thread acquires after it leaves
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         epoch += 1;
@@ -146,6 +157,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned *counter, unsigned nblocks
         s_ok = ok;
     }
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const bool ok = s_ok != 0;
     __syncthreads();
     return ok;

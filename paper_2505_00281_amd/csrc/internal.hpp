@@ -123,6 +123,7 @@ struct Context {
     std::map<std::string, std::pair<int, int>> batched_tune;
     hipStream_t graph_stream = nullptr;
     int batched_last_grouped = 0;
+    double batched_last_first_ms = 0.0;
     int batched_last_replays = 0;
     int batched_last_waves[2] = {0, 0};
 
@@ -184,6 +185,14 @@ void cast_f64_to_f32(Context *ctx, int64_t count, const double *src, float *dst)
 // dst = scale * src elementwise (column-major, any element types)
 void cast_matrix(Context *ctx, ofrr_dtype src_t, ofrr_dtype dst_t, int64_t rows, int64_t cols,
                  const void *src, int64_t lds, void *dst, int64_t ldd, double scale = 1.0);
+// a device pair {a, b} (written by a kernel on the stream; valid until the
+// next call)
+const int32_t *status_pair(Context *ctx, int32_t a, int32_t b);
+// G = I (b x b)
+void set_identity(Context *ctx, int32_t b, double *G);
+// dst[c + r * ldd] = (dt) src[r * lds + c] for r < rows, c < cols
+void transpose_cast(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64_t cols, const void *src,
+                    int64_t lds, void *dst, int64_t ldd);
 // max |a| over the FP64 values of a dense or CSR descriptor (one readback;
 // +inf when a value is NaN or infinite)
 double absmax_values(Context *ctx, const ofrr_matrix *A);
@@ -262,6 +271,12 @@ void split_block_t(Context *ctx, ofrr_dtype t, int64_t rows, int32_t b, const fl
 void check_csr(Context *ctx, const ofrr_matrix *A);
 void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,
                  int64_t ldv, void *W, int64_t ldw);
+// W = A V for CSR A read from a phase's master block (FP64, or FP32 holding
+// the FP32/binary16/bfloat16 basis, rounded to the phase's type on load);
+// with cheb, Out = alpha (A V - c Yc) - beta Yp (Yp may be null when beta = 0).
+// Returns false (nothing launched) when the blocks are not pair-aligned.
+bool product_csr_master(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype phase, const void *Vm, int64_t ld,
+                        void *Out, const void *Yc, const void *Yp, bool cheb, double alpha, double c, double beta);
 
 // k_gemm_i8.hip: FP64-class product from exact INT8 digit-plane products
 struct SlicedA {
@@ -270,8 +285,10 @@ struct SlicedA {
     int64_t m = 0, kdim = 0, mpad = 0, kpad = 0, plane_stride = 0;
 };
 SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans);
+// digits: signed 7-bit digits per side (6: 21 digit pairs, exact to about
+// 2^-42 of the row and column scales; 5: 15 pairs, 2^-35; 4: 10 pairs, 2^-28)
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
-                 int64_t ldw, SlabOut *defer = nullptr);
+                 int64_t ldw, SlabOut *defer = nullptr, int digits = 6);
 
 // k_hessenberg.hip
 // Returns the kept count (after waiting for the sweep; a timed-out wait
@@ -296,6 +313,19 @@ ofrr_status batched_grouped_impl(Context *ctx, int32_t nprob, const ofrr_matrix 
                                  ofrr_which which, const ofrr_plan *plan, const double *const *X0s,
                                  double *const *evals, double *const *evecs, double *const *resid,
                                  ofrr_info *infos);
+
+// k_basis.hip: the basis-generation processes of the comparison (method:
+// 0 MGS-L, 1 MGS-R, 2 CGS, 3 CGS-2, 4 Hess-L, 5 Hess-R) on a column-major
+// m x n block of storage type st (F64, F32, F16 = binary16 storage with
+// FP32 arithmetic), in place; one cooperative launch, timed with events.
+void basis_generate(Context *ctx, int method, ofrr_dtype st, int64_t m, int32_t n, void *A, int64_t lda,
+                    double tol, double *R, int32_t *piv, int32_t *keep, int32_t *kept_out, double *kernel_ms);
+
+// k_krylov.hip: restarted Krylov-Hessenberg + OFRR (arguments as
+// ofrr_krylov_eig, validated by the caller)
+ofrr_status krylov_eig_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t nev, int32_t restarts,
+                            ofrr_dtype bt, const double *v0, double tol, double *evals, double *evecs,
+                            double *resid, ofrr_info *info);
 
 // k_project.hip
 // G = V^T V, H = V^T W (b x b FP64, column-major) accumulated per `acc`

@@ -1248,6 +1248,7 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 bool batched_grouped_supported(const ofrr_plan *plan, int32_t nprob, const ofrr_matrix *As, int32_t k,
                                int32_t basis) {
     if (basis > KB_BMAX || k > basis) return false;
+    if (plan->stab != 0 || plan->projection != 0) return false;
     if (plan->degree != 1) return false;
     if (plan->refine > 1) return false;
     if (!(plan->basis_dtype == OFRR_BF16 || plan->basis_dtype == OFRR_F16 || plan->basis_dtype == OFRR_F64))
@@ -1445,13 +1446,20 @@ ofrr_status batched_grouped_impl(Context *ctx, int32_t nprob, const ofrr_matrix 
     }
     const int rows_red = 32 * tuned.waves_red, rows_f64 = 32 * tuned.waves_f64;
 
-    // ---- first product A X (the first filter step of iteration 1)
+    // ---- first product A X (the first filter step of iteration 1), timed
+    // with events on the stream (every problem in the first phase: the
+    // grouped product's rate over the whole set)
     lists(rows_red, rows_f64, st);
+    hipEvent_t pa, pb;
+    OFRR_HIP(hipEventCreate(&pa));
+    OFRR_HIP(hipEventCreate(&pb));
+    OFRR_HIP(hipEventRecord(pa, st));
     if (first_f64)
         launch_f64(tuned.waves_f64, st, grid_prod, d_probs, d_states, d_items_f64, d_counts, 2, BLK_X, BLK_AX, ld, ld,
                    0);
     else
         launch_lp(tuned.waves_red, bf16, st, grid_prod, d_probs, d_states, d_items_red, d_counts, 1, BLK_AX, ld);
+    OFRR_HIP(hipEventRecord(pb, st));
     hipLaunchKernelGGL(kb_set_xf64, dim3((nprob + 255) / 256), dim3(256), 0, st, d_states, nprob, first_f64 ? 1 : 0);
     OFRR_HIP(hipGetLastError());
 
@@ -1525,10 +1533,14 @@ ofrr_status batched_grouped_impl(Context *ctx, int32_t nprob, const ofrr_matrix 
     std::vector<BState> hs((size_t)nprob);
     OFRR_HIP(hipMemcpyAsync(hs.data(), d_states, sizeof(BState) * nprob, hipMemcpyDeviceToHost, st));
     OFRR_HIP(hipStreamSynchronize(st));
-    float ms = 0.f;
+    float ms = 0.f, pms = 0.f;
     OFRR_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    OFRR_HIP(hipEventElapsedTime(&pms, pa, pb));
     OFRR_HIP(hipEventDestroy(ev0));
     OFRR_HIP(hipEventDestroy(ev1));
+    OFRR_HIP(hipEventDestroy(pa));
+    OFRR_HIP(hipEventDestroy(pb));
+    ctx->batched_last_first_ms = pms;
     ctx->batched_last_replays = replays;
     ctx->batched_last_waves[0] = tuned.waves_red;
     ctx->batched_last_waves[1] = tuned.waves_f64;

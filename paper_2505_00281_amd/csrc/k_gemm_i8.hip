@@ -19,7 +19,9 @@
 // 2e-13 of |A||V| where FP32 accumulation gives 6e-8.  That margin matters:
 // the basis of a converging subspace is ill-conditioned, and the Ritz
 // values amplify per-column product errors by the cancellation in V z;
-// five digits per side (2^-35) left Ritz values 1e-9 off.
+// five digits per side (2^-35) left Ritz values 1e-9 off.  Iterations whose
+// residuals are still far above that level take fewer digits: five (15
+// pairs) or four (10 pairs), the leading digit planes of the same slicing.
 //
 // MFMA v_mfma_i32_32x32x32_i8: lane l holds A[l%32][16(l/32)..+16] and
 // B[16(l/32)..+16][l%32] (any consistent K order is exact for integers);
@@ -35,7 +37,6 @@ typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef int v16i_t __attribute__((ext_vector_type(16)));
 
 constexpr int I8_S = 6;     // digit planes of A and of V
-constexpr int I8_NG = 6;    // digit-pair groups p = s + t (0-based 0..5)
 constexpr int I8_BM = 64;   // rows per workgroup tile
 constexpr int I8_BK = 64;   // K bytes per LDS stage
 constexpr int I8_LD = 80;   // LDS row stride in bytes (64 + 16: conflict-free 16-byte reads)
@@ -218,12 +219,27 @@ __global__ __launch_bounds__(256) void k_vslice(const double *__restrict__ V, in
 // 32 x 32 output block each (six int32 accumulators = 96 registers), so two
 // waves share each SIMD and hide each other's LDS and global latency;
 // 64-byte K stages through LDS, the next stage prefetched into registers.
-// (s, u) digit pairs with s + u < 6 (0-based), ordered so that equal
-// s + u are at least three apart cyclically
-constexpr int kPairS[21] = {0, 5, 3, 2, 3, 0, 1, 1, 4, 0, 0, 2, 0, 2, 0, 1, 2, 1, 3, 1, 4};
-constexpr int kPairU[21] = {0, 0, 1, 1, 2, 1, 2, 3, 1, 2, 3, 2, 5, 0, 4, 0, 3, 1, 0, 4, 0};
+// (s, u) digit pairs with s + u < S (0-based) for S = 6, 5, 4 digits per
+// side, ordered so that two pairs of equal s + u (one accumulator) are at
+// least three apart, also cyclically across K steps (four digits: two, the
+// most an order of ten pairs with a group of four allows)
+constexpr int kPair6S[21] = {0, 5, 3, 2, 3, 0, 1, 1, 4, 0, 0, 2, 0, 2, 0, 1, 2, 1, 3, 1, 4};
+constexpr int kPair6U[21] = {0, 0, 1, 1, 2, 1, 2, 3, 1, 2, 3, 2, 5, 0, 4, 0, 3, 1, 0, 4, 0};
+constexpr int kPair5S[15] = {4, 1, 2, 1, 1, 2, 0, 0, 0, 2, 0, 1, 3, 3, 0};
+constexpr int kPair5U[15] = {0, 2, 0, 3, 0, 1, 4, 1, 3, 2, 0, 1, 1, 0, 2};
+constexpr int kPair4S[10] = {0, 1, 0, 2, 0, 1, 1, 0, 2, 3};
+constexpr int kPair4U[10] = {1, 2, 0, 1, 2, 0, 1, 3, 0, 0};
 
-template <int NCT>
+template <int S>
+__device__ __forceinline__ int pair_s(int q) {
+    return S == 6 ? kPair6S[q] : (S == 5 ? kPair5S[q] : kPair4S[q]);
+}
+template <int S>
+__device__ __forceinline__ int pair_u(int q) {
+    return S == 6 ? kPair6U[q] : (S == 5 ? kPair5U[q] : kPair4U[q]);
+}
+
+template <int NCT, int S>
 __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict__ Ap, int64_t a_stride,
                                                         const int32_t *__restrict__ ex,
                                                         const int8_t *__restrict__ Vp, int64_t v_stride,
@@ -234,10 +250,13 @@ __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict
                                                         int xcd_map) {
     constexpr int BN = 64 * NCT;
     constexpr int NT = 256 * NCT;                  // threads
-    constexpr int ACH = I8_S * I8_BM * 4 / NT;     // A 16-byte chunks per thread per stage
-    constexpr int VCH = I8_S * BN * 4 / NT;        // V chunks per thread per stage
-    __shared__ __attribute__((aligned(16))) int8_t As[I8_S][I8_BM][I8_LD];
-    __shared__ __attribute__((aligned(16))) int8_t Vs[I8_S][BN][I8_LD];
+    constexpr int NG = S;                          // digit-pair groups p = s + u
+    constexpr int NP = S * (S + 1) / 2;            // digit pairs
+    constexpr int ATOT = S * I8_BM * 4, VTOT = S * BN * 4;  // 16-byte chunks per stage
+    constexpr int ACH = (ATOT + NT - 1) / NT;      // A chunks per thread per stage
+    constexpr int VCH = (VTOT + NT - 1) / NT;      // V chunks per thread per stage
+    __shared__ __attribute__((aligned(16))) int8_t As[S][I8_BM][I8_LD];
+    __shared__ __attribute__((aligned(16))) int8_t Vs[S][BN][I8_LD];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wr = wave / (2 * NCT), wc = wave % (2 * NCT);
     int tile, z;
@@ -257,33 +276,44 @@ __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict
     const int64_t kbeg = (int64_t)z * k_per_split;
     const int64_t kend = kbeg + k_per_split < kpad ? kbeg + k_per_split : kpad;
 
-    v16i_t acc[I8_NG];
+    v16i_t acc[NG];
 #pragma unroll
-    for (int p = 0; p < I8_NG; ++p) acc[p] = v16i_t{};
+    for (int p = 0; p < NG; ++p) acc[p] = v16i_t{};
 
     // chunk c of a stage: plane c / (rows * 4), row (c / 4) % rows, 16 bytes at 16 (c % 4)
     v4i_t ra[ACH], rv[VCH];
     auto fetch = [&](int64_t k0) {
+    // (a chunk index past the stage, possible when the chunks do not divide
+    // evenly among the threads, is clamped to the last chunk for the load
+    // and skipped for the store)
 #pragma unroll
         for (int u = 0; u < ACH; ++u) {
-            const int c = t + NT * u, pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
+            int c = t + NT * u;
+            if (ATOT % NT != 0) c = c < ATOT ? c : ATOT - 1;
+            const int pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
             ra[u] = *(const v4i_t *)(Ap + pl * a_stride + plane_off(i0 + (rem >> 2), k0 + (rem & 3) * 16, mpad));
         }
 #pragma unroll
         for (int u = 0; u < VCH; ++u) {
-            const int c = t + NT * u, pl = c / (BN * 4), rem = c % (BN * 4);
+            int c = t + NT * u;
+            if (VTOT % NT != 0) c = c < VTOT ? c : VTOT - 1;
+            const int pl = c / (BN * 4), rem = c % (BN * 4);
             rv[u] = *(const v4i_t *)(Vp + pl * v_stride + plane_off(j0 + (rem >> 2), k0 + (rem & 3) * 16, bpad));
         }
     };
     auto stash = [&]() {
 #pragma unroll
         for (int u = 0; u < ACH; ++u) {
-            const int c = t + NT * u, pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
+            const int c = t + NT * u;
+            if (ATOT % NT != 0 && c >= ATOT) continue;
+            const int pl = c / (I8_BM * 4), rem = c % (I8_BM * 4);
             *(v4i_t *)&As[pl][rem >> 2][(rem & 3) * 16] = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < VCH; ++u) {
-            const int c = t + NT * u, pl = c / (BN * 4), rem = c % (BN * 4);
+            const int c = t + NT * u;
+            if (VTOT % NT != 0 && c >= VTOT) continue;
+            const int pl = c / (BN * 4), rem = c % (BN * 4);
             *(v4i_t *)&Vs[pl][rem >> 2][(rem & 3) * 16] = rv[u];
         }
     };
@@ -296,16 +326,16 @@ __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict
 #pragma unroll
         for (int ks = 0; ks < I8_BK; ks += 32) {
             const int kq = ks + 16 * (lane >> 5);
-            v4i_t a[I8_S], v[I8_S];
+            v4i_t a[S], v[S];
 #pragma unroll
-            for (int s = 0; s < I8_S; ++s) a[s] = *(const v4i_t *)&As[s][32 * wr + (lane & 31)][kq];
+            for (int s = 0; s < S; ++s) a[s] = *(const v4i_t *)&As[s][32 * wr + (lane & 31)][kq];
 #pragma unroll
-            for (int s = 0; s < I8_S; ++s) v[s] = *(const v4i_t *)&Vs[s][32 * wc + (lane & 31)][kq];
-            // the 21 digit pairs in an order that keeps two MFMAs on the
-            // same accumulator at least three apart, also across steps
+            for (int s = 0; s < S; ++s) v[s] = *(const v4i_t *)&Vs[s][32 * wc + (lane & 31)][kq];
+            // the digit pairs in an order that keeps two MFMAs on the same
+            // accumulator apart
 #pragma unroll
-            for (int q = 0; q < 21; ++q) {
-                const int s = kPairS[q], u = kPairU[q];
+            for (int q = 0; q < NP; ++q) {
+                const int s = pair_s<S>(q), u = pair_u<S>(q);
                 acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], v[u], acc[s + u], 0, 0, 0);
             }
         }
@@ -318,9 +348,9 @@ __global__ __launch_bounds__(256 * NCT) void k_gemm_i8s(const int8_t *__restrict
     for (int r = 0; r < 16; ++r) {
         const int64_t gi = i0 + 32 * wr + (r >> 2) * 8 + 4 * (lane >> 5) + (r & 3);
         if (gi >= m || gj >= b) continue;
-        double v = (double)acc[I8_NG - 1][r];
+        double v = (double)acc[NG - 1][r];
 #pragma unroll
-        for (int p = I8_NG - 2; p >= 0; --p) v = (double)acc[p][r] + v * 0.0078125;
+        for (int p = NG - 2; p >= 0; --p) v = (double)acc[p][r] + v * 0.0078125;
         Wz[gi * ldw + gj] = ldexp(v, ex[gi] + fj - 14);
     }
 }
@@ -372,8 +402,9 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
 }
 
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
-                 int64_t ldw, SlabOut *defer) {
+                 int64_t ldw, SlabOut *defer, int digits) {
     OFRR_CHECK_ARG(b >= 1 && b <= 4096, "sliced product: 1 <= b <= 4096");
+    OFRR_CHECK_ARG(digits >= 4 && digits <= I8_S, "sliced product: 4 to 6 digits per side");
     const int NCT = b > 64 ? 2 : 1;
     const int BN = 64 * NCT;
     const int bpad = (b + BN - 1) / BN * BN;
@@ -423,14 +454,20 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
     if (nsplit > 1) dst = ctx->buf<double>("i8_slabs", (size_t)nsplit * sa.m * ldw);
     {
         KTimer tm(ctx, "product_i8x");
-        if (NCT == 2)
-            hipLaunchKernelGGL(k_gemm_i8s<2>, dim3((unsigned)nwg), dim3(512), 0, ctx->stream, sa.planes,
-                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw,
-                               kps, ntiles, nsplit, xcd_map);
-        else
-            hipLaunchKernelGGL(k_gemm_i8s<1>, dim3((unsigned)nwg), dim3(256), 0, ctx->stream, sa.planes,
-                               sa.plane_stride, sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw,
-                               kps, ntiles, nsplit, xcd_map);
+        auto go = [&](auto kern, int nt) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(nt), 0, ctx->stream, sa.planes, sa.plane_stride,
+                               sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw, kps, ntiles, nsplit,
+                               xcd_map);
+        };
+        if (NCT == 2) {
+            if (digits == 6) go(k_gemm_i8s<2, 6>, 512);
+            else if (digits == 5) go(k_gemm_i8s<2, 5>, 512);
+            else go(k_gemm_i8s<2, 4>, 512);
+        } else {
+            if (digits == 6) go(k_gemm_i8s<1, 6>, 256);
+            else if (digits == 5) go(k_gemm_i8s<1, 5>, 256);
+            else go(k_gemm_i8s<1, 4>, 256);
+        }
         OFRR_HIP(hipGetLastError());
     }
     if (defer) {

@@ -1008,6 +1008,321 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double to
     return read_status(ctx, err, wb.ext != nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Panel form of the sweep for blocks too tall for the row slices to stay in
+// LDS or registers across all b columns (rows per CU x b x element size well
+// above the CU's storage).  The per-column form then streams every trailing
+// column of every row through HBM once per column (n b^2 element reads and
+// writes).  Here the columns are taken P at a time:
+//   1. the panel's P columns of the workgroup's rows are loaded into
+//      registers (R rows per thread) and swept column by column as above:
+//      one grid barrier per column, every workgroup publishing its candidate
+//      (magnitude, row, value) and that row's panel entries, every workgroup
+//      taking the same winner (largest magnitude, first row on ties);
+//   2. the multipliers of the trailing columns, U[l][i] = entry i of pivot
+//      row l at the time column l is processed, come from the pivot rows'
+//      trailing entries at the start of the panel by the small triangular
+//      chain over the panel's earlier pivots (each workgroup computes it);
+//   3. after one more grid barrier every row's trailing entries receive the
+//      panel's eliminations, in column order, one fused multiply-add each:
+//      Y[r][i] = fma(-U[l][i], Y[r][l], Y[r][i]).
+// Every entry therefore goes through the same operations in the same order
+// as in the per-column process (pivots, drops and bits unchanged), and the
+// trailing block is read and written once per panel instead of once per
+// column: about n b^2 / P element reads and writes.
+constexpr int HP_NT = 512;  // threads per workgroup of the panel sweep
+constexpr int HP_PMAX = 8;  // widest panel
+
+// one column of the panel sweep (JJ: the column within the panel, a
+// compile-time index so the panel stays in registers)
+template <class T, int R, int P, int JJ>
+__device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int64_t r0, int64_t r1, double tol,
+                                          int32_t *__restrict__ piv, int32_t *__restrict__ keep,
+                                          double *__restrict__ slots, unsigned *__restrict__ bar, int *__restrict__ err,
+                                          unsigned &epoch, int &step, int &kept, double *s_cm, double *s_cr,
+                                          double *s_cv, double *s_win, T *s_Lp, int *s_keep, int64_t *s_pr) {
+    constexpr int NT = HP_NT, SW = 3 + P, NW = NT / 64;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int G = gridDim.x, g = blockIdx.x;
+    // local candidate: largest magnitude, first row on ties
+    T bm = (T)-1;
+    int64_t br = INT64_MAX;
+    T bv = (T)0;
+    int bq = -1;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t row = r0 + t + (int64_t)NT * q;
+        const T m = v[q][JJ] < (T)0 ? -v[q][JJ] : v[q][JJ];
+        if (row < r1 && m > bm) {
+            bm = m;
+            br = row;
+            bv = v[q][JJ];
+            bq = q;
+        }
+    }
+    double cm = (double)bm, cr = br == INT64_MAX ? 9.0e18 : (double)br, cv = (double)bv;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double qm = __shfl_xor(cm, o, 64), qr = __shfl_xor(cr, o, 64), qv = __shfl_xor(cv, o, 64);
+        if (qm > cm || (qm == cm && qr < cr)) {
+            cm = qm;
+            cr = qr;
+            cv = qv;
+        }
+    }
+    if (lane == 0) {
+        s_cm[wave] = cm;
+        s_cr[wave] = cr;
+        s_cv[wave] = cv;
+    }
+    __syncthreads();
+    double wm = s_cm[0], wr = s_cr[0], wv = s_cv[0];
+    for (int w = 1; w < NW; ++w)
+        if (s_cm[w] > wm || (s_cm[w] == wm && s_cr[w] < wr)) {
+            wm = s_cm[w];
+            wr = s_cr[w];
+            wv = s_cv[w];
+        }
+    __syncthreads();
+    // publish the candidate and its row's panel entries
+    const int buf = step & 1;
+    double *my = slots + ((int64_t)buf * G + g) * SW;
+    if (t == 0) {
+        my[0] = wm;
+        my[1] = wr;
+        my[2] = wv;
+    }
+    if (bq >= 0 && (double)br == wr) {
+        // the row by a select over the compile-time indices (an indexed
+        // read would move the panel to scratch memory)
+        T e[P];
+#pragma unroll
+        for (int ii = 0; ii < P; ++ii) e[ii] = v[0][ii];
+#pragma unroll
+        for (int q = 1; q < R; ++q)
+#pragma unroll
+            for (int ii = 0; ii < P; ++ii) e[ii] = q == bq ? v[q][ii] : e[ii];
+#pragma unroll
+        for (int ii = 0; ii < P; ++ii) my[3 + ii] = (double)e[ii];
+    }
+    if (!grid_barrier(bar, (unsigned)G, epoch, err)) return false;
+    ++step;
+    // the winner over all workgroups (thread h reads workgroup h's slot)
+    double hm = -2.0, hr = 9.1e18;
+    int hg = 0;
+    for (int h = t; h < G; h += NT) {
+        const double *ps = slots + ((int64_t)buf * G + h) * SW;
+        const double qm = ps[0], qr = ps[1];
+        if (qm > hm || (qm == hm && qr < hr)) {
+            hm = qm;
+            hr = qr;
+            hg = h;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double qm = __shfl_xor(hm, o, 64), qr = __shfl_xor(hr, o, 64);
+        const int qg = __shfl_xor(hg, o, 64);
+        if (qm > hm || (qm == hm && qr < hr)) {
+            hm = qm;
+            hr = qr;
+            hg = qg;
+        }
+    }
+    if (lane == 0) {
+        s_cm[wave] = hm;
+        s_cr[wave] = hr;
+        s_cv[wave] = (double)hg;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double xm = s_cm[0], xr = s_cr[0];
+        int xg = (int)s_cv[0];
+        for (int w = 1; w < NW; ++w)
+            if (s_cm[w] > xm || (s_cm[w] == xm && s_cr[w] < xr)) {
+                xm = s_cm[w];
+                xr = s_cr[w];
+                xg = (int)s_cv[w];
+            }
+        const double *ps = slots + ((int64_t)buf * G + xg) * SW;
+        for (int i = 0; i < SW; ++i) s_win[i] = ps[i];
+    }
+    __syncthreads();
+    const T wmag = (T)s_win[0];
+    const int64_t wrow = (int64_t)s_win[1];
+    const T pv = (T)s_win[2];
+    const bool take = (double)wmag >= tol && wmag > (T)0;
+    if (t == 0) {
+        s_keep[JJ] = take ? 1 : 0;
+        s_pr[JJ] = wrow;
+        for (int ii = 0; ii < P; ++ii) s_Lp[JJ * P + ii] = (T)s_win[3 + ii];
+        if (g == 0) {
+            piv[j0 + JJ] = take ? (int32_t)wrow : -1;
+            keep[j0 + JJ] = take ? 1 : 0;
+        }
+    }
+    if (take) {
+        ++kept;
+        T w[P];
+#pragma unroll
+        for (int ii = 0; ii < P; ++ii) w[ii] = (T)s_win[3 + ii];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T x = v[q][JJ] / pv;
+            v[q][JJ] = x;
+#pragma unroll
+            for (int ii = JJ + 1; ii < P; ++ii)
+                if (ii < pw) v[q][ii] = fma(-w[ii], x, v[q][ii]);
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+template <class T, int R, int P>
+__global__ __launch_bounds__(HP_NT) void k_hess_panel(T *__restrict__ Y, int64_t ldy, int64_t n, int b, double tol,
+                                                      int32_t *__restrict__ piv, int32_t *__restrict__ keep,
+                                                      int64_t per, double *__restrict__ slots,
+                                                      unsigned *__restrict__ bar, int *__restrict__ err,
+                                                      int32_t *__restrict__ kept_d) {
+    constexpr int NT = HP_NT, NW = NT / 64;
+    __shared__ T s_L[NT * P];   // a row chunk's panel entries (trailing update)
+    __shared__ T s_U[P * 512];  // multipliers of the trailing columns (b <= 512)
+    __shared__ T s_Lp[P * P];   // pivot rows' panel entries
+    __shared__ int s_keep[P];
+    __shared__ int64_t s_pr[P];
+    __shared__ double s_cm[NW], s_cr[NW], s_cv[NW];
+    __shared__ double s_win[3 + P];
+    const int t = threadIdx.x;
+    const int g = blockIdx.x;
+    const int64_t r0 = (int64_t)g * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    unsigned epoch = 0;
+    int step = 0, kept = 0;
+    T v[R][P];
+    for (int j0 = 0; j0 < b; j0 += P) {
+        const int pw = b - j0 < P ? b - j0 : P;
+        // 1. the panel, swept column by column
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t row = r0 + t + (int64_t)NT * q;
+#pragma unroll
+            for (int jj = 0; jj < P; ++jj) v[q][jj] = (row < r1 && jj < pw) ? Y[row * ldy + j0 + jj] : (T)0;
+        }
+#define OFRR_HP_COL(JJ)                                                                                         \
+        if constexpr (JJ < P) {                                                                                \
+            if (JJ < pw && !hp_column<T, R, P, JJ>(v, j0, pw, r0, r1, tol, piv, keep, slots, bar, err, epoch,  \
+                                                   step, kept, s_cm, s_cr, s_cv, s_win, s_Lp, s_keep, s_pr))   \
+                return;                                                                                        \
+        }
+        OFRR_HP_COL(0)
+        OFRR_HP_COL(1)
+        OFRR_HP_COL(2)
+        OFRR_HP_COL(3)
+        OFRR_HP_COL(4)
+        OFRR_HP_COL(5)
+        OFRR_HP_COL(6)
+        OFRR_HP_COL(7)
+#undef OFRR_HP_COL
+        const int c0 = j0 + pw;
+        const int nt_ = b - c0;  // trailing columns
+        if (nt_ > 0) {
+            // 2. multipliers: entry i of pivot row jj once the panel's earlier
+            // pivots have been eliminated from it
+            for (int i = t; i < nt_; i += NT)
+                for (int jj = 0; jj < pw; ++jj) {
+                    T x = (T)0;
+                    if (s_keep[jj]) {
+                        x = Y[s_pr[jj] * ldy + c0 + i];
+                        for (int l = 0; l < jj; ++l)
+                            if (s_keep[l]) x = fma(-s_U[l * 512 + i], s_Lp[jj * P + l], x);
+                    }
+                    s_U[jj * 512 + i] = x;
+                }
+            // every workgroup has read the pivot rows before any is updated
+            if (!grid_barrier(bar, (unsigned)gridDim.x, epoch, err)) return;
+            // 3. trailing update, one chunk of NT rows at a time (the chunk
+            // index is a loop variable: the panel rows are picked by a select
+            // over the compile-time indices, so they stay in registers)
+            for (int q = 0; q < R; ++q) {
+                T e[P];
+#pragma unroll
+                for (int jj = 0; jj < P; ++jj) e[jj] = v[0][jj];
+#pragma unroll
+                for (int qq = 1; qq < R; ++qq)
+#pragma unroll
+                    for (int jj = 0; jj < P; ++jj) e[jj] = qq == q ? v[qq][jj] : e[jj];
+#pragma unroll
+                for (int jj = 0; jj < P; ++jj) s_L[t * P + jj] = e[jj];
+                __syncthreads();
+                const int64_t rb = r0 + (int64_t)NT * q;
+                for (int item = t; item < NT * nt_; item += NT) {
+                    const int rr = item / nt_, i = item - rr * nt_;
+                    const int64_t row = rb + rr;
+                    if (row >= r1) continue;
+                    T x = Y[row * ldy + c0 + i];
+                    for (int l = 0; l < pw; ++l)
+                        if (s_keep[l]) x = fma(-s_U[l * 512 + i], s_L[rr * P + l], x);
+                    Y[row * ldy + c0 + i] = x;
+                }
+                __syncthreads();
+            }
+        }
+        // the panel's columns are final
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t row = r0 + t + (int64_t)NT * q;
+            if (row < r1)
+#pragma unroll
+                for (int jj = 0; jj < P; ++jj)
+                    if (jj < pw) Y[row * ldy + j0 + jj] = v[q][jj];
+        }
+        __syncthreads();
+    }
+    if (g == 0 && t == 0) *kept_d = kept;
+}
+
+template <class T>
+int32_t run_panel(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv, int32_t *keep,
+                  const int32_t **status, const WordsBuf &wb) {
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    const int G = (int)std::min<int64_t>(cus, (n + HP_NT - 1) / HP_NT);
+    const int64_t per = (n + G - 1) / G;
+    const int R = (int)((per + HP_NT - 1) / HP_NT);
+    // word buffer: [0] error flag and kept count, [1] barrier counter, then
+    // the candidate slots (2 x G x (3 + P) doubles)
+    const int64_t nwords = 2 + (int64_t)2 * G * (3 + HP_PMAX);
+    uint64_t *words = wb.get(ctx, nwords);
+    int *err = reinterpret_cast<int *>(words);
+    int32_t *kept_d = err + 1;
+    unsigned *bar = reinterpret_cast<unsigned *>(words + 1);
+    double *slots = reinterpret_cast<double *>(words + 2);
+    // panel width eight (eight FP64 rows per thread: the 8 x 8 panel takes
+    // the whole register budget of two waves per SIMD, with no spill)
+    const void *kern = R <= 1   ? (const void *)k_hess_panel<T, 1, 8>
+                       : R <= 2 ? (const void *)k_hess_panel<T, 2, 8>
+                       : R <= 4 ? (const void *)k_hess_panel<T, 4, 8>
+                                : (const void *)k_hess_panel<T, 8, 8>;
+    static OccEntry occ[OCC_SLOTS] = {};
+    const int per_cu = occupancy_cached(occ, ctx->device, kern, 0, [&] {
+        int pc = 0;
+        OFRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, HP_NT, 0));
+        return pc;
+    });
+    if ((int64_t)per_cu * cus < G) fail(OFRR_ERR_UNSUPPORTED, "hessenberg: panel grid cannot be co-resident");
+    hipLaunchKernelGGL(k_hess_reset, dim3((unsigned)std::min<int64_t>(256, (nwords + 255) / 256)), dim3(256), 0,
+                       ctx->stream, words, nwords);
+    OFRR_HIP(hipGetLastError());
+    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, (void *)&per, &slots, &bar, &err, &kept_d};
+    {
+        KTimer tm(ctx, "hessenberg");
+        OFRR_HIP(launch_resident(kern, dim3(G), dim3(HP_NT), args, 0, ctx->stream));
+    }
+    if (status) {
+        *status = err;
+        return 0;
+    }
+    return read_status(ctx, err, wb.ext != nullptr);
+}
+
 template <class T>
 int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv,
             int32_t *keep, const int32_t **status, const WordsBuf &wb) {
@@ -1080,6 +1395,13 @@ int32_t run(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, i
         rows_per = (n + want_g - 1) / want_g;
         G = (int)((n + rows_per - 1) / rows_per);
     }
+    // too tall for the slices to stay on chip: the panel form (trailing
+    // block streamed once per panel of columns instead of once per column),
+    // up to eight rows per thread (OFRR_HESS_PANEL=0 selects the in-place
+    // per-column kernel, for comparisons)
+    bool panel = !resident && n <= (int64_t)cus * HP_NT * 8;
+    if (const char *s = std::getenv("OFRR_HESS_PANEL")) panel = panel && std::atoi(s) != 0;
+    if (panel) return run_panel<T>(ctx, n, b, Y, ldy, tol, piv, keep, status, wb);
     const size_t shmem = resident ? (size_t)rows_per * ldr * sizeof(T) : 0;
 
     // one word buffer: [0] error flag and kept count (two ints), then the

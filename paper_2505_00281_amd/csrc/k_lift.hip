@@ -337,8 +337,8 @@ __global__ void k_cheb(const TP *__restrict__ P, const TS *__restrict__ Yc, cons
                        TN *__restrict__ Yn) {
     OFRR_ROWS_COLS_LOOP(
         const int64_t o = i * ld + j;
-        double v = alpha * (load_as_f64(P + o) - c * load_as_f64(Yc + o));
-        if (beta != 0.0) v -= beta * load_as_f64(Yp + o);
+        double v = alpha * fma(-c, load_as_f64(Yc + o), load_as_f64(P + o));
+        if (beta != 0.0) v = fma(-beta, load_as_f64(Yp + o), v);
         store_as<TN>(Yn + o, v);)
 }
 
@@ -352,8 +352,8 @@ __global__ void k_cheb_slabs(const TSL *__restrict__ P, int nsplit, int64_t sstr
         const int64_t o = i * ld + j;
         TSL s = (TSL)0;
         for (int z = 0; z < nsplit; ++z) s += P[(int64_t)z * sstride + o];
-        double v = alpha * ((double)s - c * load_as_f64(Yc + o));
-        if (beta != 0.0) v -= beta * load_as_f64(Yp + o);
+        double v = alpha * fma(-c, load_as_f64(Yc + o), (double)s);
+        if (beta != 0.0) v = fma(-beta, load_as_f64(Yp + o), v);
         store_as<TN>(Yn + o, v);)
 }
 

@@ -46,6 +46,18 @@ __global__ void k_cast_matrix(const S *__restrict__ s, int64_t lds, D *__restric
     }
 }
 
+// dst[c + r * ldd] = src[r * lds + c] (a row-major rows x cols block into a
+// column-major one, or back with the roles swapped), converting the type
+template <class S, class D>
+__global__ void k_transpose_cast(const S *__restrict__ s, int64_t lds, D *__restrict__ d, int64_t ldd,
+                                 int64_t rows, int64_t cols) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / cols, c = e - r * cols;
+        store_as<D>(d + c * ldd + r, load_as_f64(s + r * lds + c));
+    }
+}
+
 // Largest magnitude of an FP64 array (dense column-major rows x cols with
 // leading dimension ld, or a flat array: rows = count, cols = 1), merged as
 // the FP64 bit pattern by atomic maximum (non-negative doubles order as
@@ -360,6 +372,44 @@ void cast_matrix(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64
     OFRR_HIP(hipGetLastError());
 }
 
+__global__ void k_pair(int32_t *d, int32_t a, int32_t b) {
+    if (threadIdx.x == 0) {
+        d[0] = a;
+        d[1] = b;
+    }
+}
+
+__global__ void k_identity(double *G, int b) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < b * b; e += gridDim.x * blockDim.x)
+        G[e] = (e % b == e / b) ? 1.0 : 0.0;
+}
+
+const int32_t *status_pair(Context *ctx, int32_t a, int32_t b) {
+    int32_t *d = ctx->buf<int32_t>("status_pair", 2);
+    hipLaunchKernelGGL(k_pair, dim3(1), dim3(64), 0, ctx->stream, d, a, b);
+    OFRR_HIP(hipGetLastError());
+    return d;
+}
+
+void set_identity(Context *ctx, int32_t b, double *G) {
+    hipLaunchKernelGGL(k_identity, dim3((b * b + 255) / 256), dim3(256), 0, ctx->stream, G, b);
+    OFRR_HIP(hipGetLastError());
+}
+
+void transpose_cast(Context *ctx, ofrr_dtype st, ofrr_dtype dt, int64_t rows, int64_t cols, const void *src,
+                    int64_t lds, void *dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return;
+    dispatch_type(st, [&](auto *sp) {
+        using S = std::remove_pointer_t<decltype(sp)>;
+        dispatch_type(dt, [&](auto *dp) {
+            using D = std::remove_pointer_t<decltype(dp)>;
+            hipLaunchKernelGGL((k_transpose_cast<S, D>), dim3(grid_for(rows * cols)), dim3(256), 0, ctx->stream,
+                               (const S *)src, lds, (D *)dst, ldd, rows, cols);
+        });
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
 double absmax_values(Context *ctx, const ofrr_matrix *A) {
     OFRR_CHECK_ARG(A->dtype == OFRR_F64, "absmax_values: FP64 values");
     int64_t rows = A->rows, cols = A->cols, ld = A->ld;
@@ -476,6 +526,7 @@ void split_block(Context *ctx, ofrr_dtype t, int64_t count, const float *src, ui
 }
 
 void round_block(Context *ctx, ofrr_dtype t, int64_t count, float *x) {
+    if (t == OFRR_F32) return;  // already the storage type
     if (t == OFRR_BF16)
         hipLaunchKernelGGL((k_round<true>), dim3(grid_for(count)), dim3(256), 0, ctx->stream, x, count);
     else if (t == OFRR_F16)

@@ -191,6 +191,145 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t *__restrict__ rp,
     }
 }
 
+// CSR SpMM, vector form (rows of V stored with an even leading dimension).
+// A group of L lanes (a power of two, L <= 64) takes one row; every lane
+// holds two adjacent columns, so each gathered row of V is read by one
+// 4-, 8- or 16-byte load per lane and a 64-column FP64 row by 32 lanes.
+// The entries of a row are visited in storage order, four index/value loads
+// issued before their four gathers.  Accumulation: FP64 for FP64 vectors,
+// FP32 otherwise (the method's reduced-precision products compute in FP32).
+// RND rounds each gathered FP32 value to binary16 (1) or bfloat16 (2) on
+// load: the product of a reduced-precision phase read straight from its
+// FP32 master block, bit for bit the product of the rounded copy.
+// With CHEB the Chebyshev three-term step is applied to the product, as
+// rounded to its output type, before it is stored:
+//   Yn = alpha (P - c Yc) - beta Yp
+// with the same fused operations as the separate combine kernel.  Rows are
+// handed to the XCDs in contiguous ranges (blockIdx modulo 8 picks the
+// XCD), so the rows that share gathered neighbours share an L2.
+template <class TG>
+struct Pair;
+template <>
+struct Pair<double> {
+    using T = double2;
+    static __device__ __forceinline__ void get(const double *p, double &a, double &b) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        a = v.x;
+        b = v.y;
+    }
+};
+template <>
+struct Pair<float> {
+    static __device__ __forceinline__ void get(const float *p, float &a, float &b) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        a = v.x;
+        b = v.y;
+    }
+};
+template <>
+struct Pair<f16_t> {
+    static __device__ __forceinline__ void get(const f16_t *p, float &a, float &b) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+        a = f16_bits_to_f32((uint16_t)(v & 0xffffu));
+        b = f16_bits_to_f32((uint16_t)(v >> 16));
+    }
+};
+template <>
+struct Pair<bf16_t> {
+    static __device__ __forceinline__ void get(const bf16_t *p, float &a, float &b) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+        a = __builtin_bit_cast(float, v << 16);
+        b = __builtin_bit_cast(float, v & 0xffff0000u);
+    }
+};
+
+template <int RND>
+__device__ __forceinline__ float spmm_round(float x) {
+    if (RND == 1) return f16_bits_to_f32(f32_to_f16_bits(x));
+    if (RND == 2) return bf16_bits_to_f32(f32_to_bf16_bits(x));
+    return x;
+}
+template <int RND>
+__device__ __forceinline__ double spmm_round(double x) {
+    return x;
+}
+
+__device__ __forceinline__ int64_t xcd_row_block(int64_t bid, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = bid % 8, k = bid / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
+template <class TG, int RND, class TA, bool CHEB>
+__global__ __launch_bounds__(256) void k_spmm_v(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                const TA *__restrict__ val, int64_t n_rows, int64_t n_cols,
+                                                int64_t nnz, int b, int lanes_log2, const TG *__restrict__ V,
+                                                int64_t ld,
+                                                typename std::conditional<std::is_same<TG, double>::value, double,
+                                                                          float>::type *__restrict__ W,
+                                                const typename std::conditional<std::is_same<TG, double>::value,
+                                                                                double, float>::type *__restrict__ Yc,
+                                                const typename std::conditional<std::is_same<TG, double>::value,
+                                                                                double, float>::type *__restrict__ Yp,
+                                                double alpha, double c, double beta) {
+    using ACC = typename std::conditional<std::is_same<TG, double>::value, double, float>::type;
+    const int L = 1 << lanes_log2;
+    const int rows_per = 256 >> lanes_log2;
+    const int64_t blk = xcd_row_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * rows_per + (threadIdx.x >> lanes_log2);
+    const int li = threadIdx.x & (L - 1);
+    if (row >= n_rows) return;
+    int64_t e0 = rp[row], e1 = rp[row + 1];
+    if (e0 < 0) e0 = 0;
+    if (e1 > nnz) e1 = nnz;
+    const int64_t cmax = n_cols - 1;
+    for (int j = 2 * li; j < b; j += 2 * L) {
+        ACC acc0 = (ACC)0, acc1 = (ACC)0;
+        int64_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            int64_t cc[4];
+            ACC a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = ci[e + u];
+                cc[u] = q < 0 ? 0 : (q > cmax ? cmax : q);
+                a[u] = (ACC)val[e + u];
+            }
+            ACC x0[4], x1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Pair<TG>::get(V + cc[u] * ld + j, x0[u], x1[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc0 = fma(a[u], spmm_round<RND>(x0[u]), acc0);
+                acc1 = fma(a[u], spmm_round<RND>(x1[u]), acc1);
+            }
+        }
+        for (; e < e1; ++e) {
+            const int64_t q = ci[e];
+            const int64_t cc = q < 0 ? 0 : (q > cmax ? cmax : q);
+            const ACC a = (ACC)val[e];
+            ACC x0, x1;
+            Pair<TG>::get(V + cc * ld + j, x0, x1);
+            acc0 = fma(a, spmm_round<RND>(x0), acc0);
+            acc1 = fma(a, spmm_round<RND>(x1), acc1);
+        }
+        const int64_t o = row * ld + j;
+        const bool two = j + 1 < b;
+        if (CHEB) {
+            double v0 = alpha * fma(-c, (double)Yc[o], (double)acc0);
+            if (beta != 0.0) v0 = fma(-beta, (double)Yp[o], v0);
+            W[o] = (ACC)v0;
+            if (two) {
+                double v1 = alpha * fma(-c, (double)Yc[o + 1], (double)acc1);
+                if (beta != 0.0) v1 = fma(-beta, (double)Yp[o + 1], v1);
+                W[o + 1] = (ACC)v1;
+            }
+        } else {
+            W[o] = acc0;
+            if (two) W[o + 1] = acc1;
+        }
+    }
+}
+
 // CSR structure check: row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
 // every column index in [0, n_cols).  Sets *bad to a nonzero code.
 __global__ void k_csr_check(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -260,10 +399,66 @@ void product_f64(Context *ctx, const ofrr_matrix *A, int trans, int32_t b, const
     }
 }
 
+namespace {
+
+int spmm_lanes_log2(int b) {
+    const int need = (b + 1) / 2;
+    int lg = 0;
+    while ((1 << lg) < need && lg < 6) ++lg;
+    return lg;
+}
+
+template <class TG, int RND, bool CHEB, class TW>
+void launch_spmm_v(Context *ctx, const ofrr_matrix *A, int32_t b, const TG *V, int64_t ld, TW *W, const TW *Yc,
+                   const TW *Yp, double alpha, double c, double beta) {
+    const int lg = spmm_lanes_log2(b);
+    const int64_t rows_per = 256 >> lg;
+    const int64_t G = (A->rows + rows_per - 1) / rows_per;
+    OFRR_CHECK_ARG(G < ((int64_t)1 << 31), "spmm: too many rows");
+    if (A->dtype == OFRR_F32)
+        hipLaunchKernelGGL((k_spmm_v<TG, RND, float, CHEB>), dim3((unsigned)G), dim3(256), 0, ctx->stream,
+                           A->row_ptr, A->col_idx, (const float *)A->values, A->rows, A->cols, A->nnz, b, lg, V, ld,
+                           W, Yc, Yp, alpha, c, beta);
+    else
+        hipLaunchKernelGGL((k_spmm_v<TG, RND, double, CHEB>), dim3((unsigned)G), dim3(256), 0, ctx->stream,
+                           A->row_ptr, A->col_idx, (const double *)A->values, A->rows, A->cols, A->nnz, b, lg, V,
+                           ld, W, Yc, Yp, alpha, c, beta);
+    OFRR_HIP(hipGetLastError());
+}
+
+bool pair_aligned(const void *p, int64_t ld, size_t es) {
+    return ld % 2 == 0 && (reinterpret_cast<uintptr_t>(p) % (2 * es)) == 0;
+}
+
+}  // namespace
+
 void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, const void *V,
                  int64_t ldv, void *W, int64_t ldw) {
     KTimer tm(ctx, "spmm");
     const int64_t n = A->rows;
+    const size_t es = vt == OFRR_F64 ? 8 : (vt == OFRR_F32 ? 4 : 2);
+    const size_t ws = vt == OFRR_F64 ? 8 : 4;
+    if (ldv == ldw && pair_aligned(V, ldv, es) && pair_aligned(W, ldw, ws)) {
+        switch (vt) {
+            case OFRR_F64:
+                launch_spmm_v<double, 0, false>(ctx, A, b, (const double *)V, ldv, (double *)W, (const double *)nullptr,
+                                                (const double *)nullptr, 0.0, 0.0, 0.0);
+                return;
+            case OFRR_F32:
+                launch_spmm_v<float, 0, false>(ctx, A, b, (const float *)V, ldv, (float *)W, (const float *)nullptr,
+                                               (const float *)nullptr, 0.0, 0.0, 0.0);
+                return;
+            case OFRR_F16:
+                launch_spmm_v<f16_t, 0, false>(ctx, A, b, (const f16_t *)V, ldv, (float *)W, (const float *)nullptr,
+                                               (const float *)nullptr, 0.0, 0.0, 0.0);
+                return;
+            case OFRR_BF16:
+                launch_spmm_v<bf16_t, 0, false>(ctx, A, b, (const bf16_t *)V, ldv, (float *)W,
+                                                (const float *)nullptr, (const float *)nullptr, 0.0, 0.0, 0.0);
+                return;
+            default: fail(OFRR_ERR_UNSUPPORTED, "spmm: basis type");
+        }
+    }
     dim3 grid((unsigned)((n + 3) / 4));
     auto go = [&](auto *vtag, auto *wtag) {
         using TV = std::remove_pointer_t<decltype(vtag)>;
@@ -285,6 +480,34 @@ void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, c
         default: fail(OFRR_ERR_UNSUPPORTED, "spmm: basis type");
     }
     OFRR_HIP(hipGetLastError());
+}
+
+bool product_csr_master(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype phase, const void *Vm, int64_t ld,
+                        void *Out, const void *Yc, const void *Yp, bool cheb, double alpha, double c, double beta) {
+    const size_t es = phase == OFRR_F64 ? 8 : 4;
+    if (!pair_aligned(Vm, ld, es) || !pair_aligned(Out, ld, es)) return false;
+    if (cheb && (!pair_aligned(Yc, ld, es) || (Yp && !pair_aligned(Yp, ld, es)))) return false;
+    KTimer tm(ctx, "spmm");
+    auto go = [&](auto *tag, auto rnd) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        constexpr int R = decltype(rnd)::value;
+        const T *v = static_cast<const T *>(Vm);
+        T *o = static_cast<T *>(Out);
+        const T *yc = static_cast<const T *>(Yc);
+        const T *yp = static_cast<const T *>(Yp);
+        if (cheb)
+            launch_spmm_v<T, R, true>(ctx, A, b, v, ld, o, yc, yp, alpha, c, beta);
+        else
+            launch_spmm_v<T, R, false>(ctx, A, b, v, ld, o, yc, yp, 0.0, 0.0, 0.0);
+    };
+    switch (phase) {
+        case OFRR_F64: go((double *)nullptr, std::integral_constant<int, 0>{}); break;
+        case OFRR_F32: go((float *)nullptr, std::integral_constant<int, 0>{}); break;
+        case OFRR_F16: go((float *)nullptr, std::integral_constant<int, 1>{}); break;
+        case OFRR_BF16: go((float *)nullptr, std::integral_constant<int, 2>{}); break;
+        default: return false;
+    }
+    return true;
 }
 
 }  // namespace ofrr

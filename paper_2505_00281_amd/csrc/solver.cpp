@@ -75,6 +75,10 @@ struct EigRun {
     // entries lie far outside the range in which sums of squares of the
     // products stay finite and normal; 1 otherwise (no extra work)
     double sigma = 1.0;
+    // normal-equations operator (the A^T A form of the SVD): the products
+    // are A^T (A V) with A m x n, n the operator's dimension
+    bool normal = false;
+    int64_t m = 0;
 
     // product of the current phase: W (master type) = A * Vblk (master type)
     // W = A V in the phase's arithmetic.  With defer (dense products only),
@@ -92,8 +96,14 @@ struct EigRun {
         if (defer) defer->nsplit = 0;
         const int64_t ld = b0;
         if (A->format == OFRR_CSR) {
+            // the SpMM reads the phase's master block, rounding on load
+            if ((sigma == 1.0 || ph.f64()) &&
+                product_csr_master(ctx, A, bc, ph.basis, Vm, ld, Wm, nullptr, nullptr, false, 0.0, 0.0, 0.0))
+                return;
             if (ph.f64()) {
                 product_csr(ctx, A, bc, OFRR_F64, Vm, ld, Wm, ld);
+            } else if (ph.basis == OFRR_F32) {
+                product_csr(ctx, A, bc, OFRR_F32, Vm, ld, Wm, ld);
             } else {
                 // round the FP32 block to the storage type and run the SpMM on it
                 uint16_t *vlo = ctx->buf<uint16_t>("spmm_vlo", (size_t)n * ld);
@@ -107,11 +117,39 @@ struct EigRun {
             }
             return;
         }
+        if (normal) {
+            // T = A V (m x bc), then W = A^T T, each in the phase's arithmetic
+            void *T = ctx->buf<double>("normal_T", (size_t)m * ld);
+            if (ph.f64()) {
+                product_f64(ctx, A, 0, bc, (const double *)Vm, ld, (double *)T, ld);
+                product_f64(ctx, A, 1, bc, (const double *)T, ld, (double *)Wm, ld);
+                return;
+            }
+            const int64_t ldt = lowp_ldt(std::max(m, n));
+            uint16_t *vhi = ctx->buf<uint16_t>("prod_vhi", (size_t)ld * ldt);
+            uint16_t *vlo = nullptr;
+            if (plan->b_split >= 2) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
+            split_block_t(ctx, ph.basis, n, bc, (const float *)Vm, ld, vhi, vlo, ldt);
+            product_lowp_t(ctx, ph.basis, m, n, A_lo, m, 0, bc, vhi, vlo, ldt, (float *)T, ld, nullptr);
+            split_block_t(ctx, ph.basis, m, bc, (const float *)T, ld, vhi, vlo, ldt);
+            product_lowp_t(ctx, ph.basis, n, m, A_lo, m, 1, bc, vhi, vlo, ldt, (float *)Wm, ld, nullptr);
+            return;
+        }
         if (ph.f64()) {
             if (ph.sliced)
-                product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld, defer);
+                product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld, defer, i8_digits);
             else
                 product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
+            return;
+        }
+        if (ph.basis == OFRR_F32) {
+            // FP32 basis and product output; the sums are formed in FP64 from
+            // A as stored and the FP32 block, then rounded to FP32
+            double *v64 = ctx->buf<double>("f32_v64", (size_t)n * ld);
+            double *w64 = ctx->buf<double>("f32_w64", (size_t)n * ld);
+            cast_matrix(ctx, OFRR_F32, OFRR_F64, ld, n, Vm, ld, v64, ld);
+            product_f64(ctx, A, 1, bc, v64, ld, w64, ld);
+            cast_matrix(ctx, OFRR_F64, OFRR_F32, ld, n, w64, ld, Wm, ld);
             return;
         }
         // dense reduced precision: split the FP32 block into hi (+ lo), written
@@ -125,15 +163,46 @@ struct EigRun {
                        ph.split ? A_lo2 : nullptr, defer);
     }
 
+    // one Chebyshev step Ynext = alpha (A Ycur - c Ycur) - beta Yprev with the
+    // combine fused into a CSR product; false when this A or these blocks
+    // take the separate product and combine
+    bool cheb_fused(const Phase &ph, const void *Ycur, const void *Yprev, double alpha, double c, double beta,
+                    void *Ynext, int32_t bc) {
+        if (A->format != OFRR_CSR || sigma != 1.0 || normal) return false;
+        if (!product_csr_master(ctx, A, bc, ph.basis, Ycur, b0, Ynext, Ycur, Yprev, true, alpha, c, beta))
+            return false;
+        ++products;
+        return true;
+    }
+
     int64_t b0 = 0;  // leading dimension of every block (the initial basis size)
+    // digits per side of the INT8 digit-plane products (sliced FP64 phase)
+    int i8_digits = 6;
 };
+
+// Digits per side for a sliced FP64 iteration, from the largest wanted
+// residual estimate of the iteration before it.  A product with S digits
+// per side is exact up to about 2^-7S of the row and column scales (four:
+// 3.7e-9, five: 2.9e-11, six: 2.3e-13), which bounds the residual the
+// iteration can reach.  Fewer digits are taken only while the residual is
+// at least a hundred times above that level, with a factor 16 for |A||V|
+// over |A V|: the subspace is not perturbed beyond what the iteration still
+// has to shed, and the final iterations, which decide the returned pairs,
+// run six.
+int i8_digits_for(double emax) {
+    if (!(emax < INFINITY)) return 6;
+    if (emax > 1600.0 * std::ldexp(1.0, -28)) return 4;
+    if (emax > 1600.0 * std::ldexp(1.0, -35)) return 5;
+    return 6;
+}
 
 }  // namespace
 
 ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              ofrr_which which, const ofrr_plan *plan, const double *X0,
-                             double *evals, double *evecs, double *resid, ofrr_info *info) {
-    const int64_t n = A->rows;
+                             double *evals, double *evecs, double *resid, ofrr_info *info, bool normal) {
+    // the operator: A (symmetric, n x n), or A^T A for an m x n A (normal)
+    const int64_t n = normal ? A->cols : A->rows;
     const int64_t ld = basis;
     hipEvent_t ev0, ev1;
     OFRR_HIP(hipEventCreate(&ev0));
@@ -149,18 +218,20 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     run.k = k;
     run.which = which;
     run.b0 = ld;
+    run.normal = normal;
+    run.m = A->rows;
 
     std::vector<Phase> phases;
     phases.push_back(Phase{plan->basis_dtype});
     const bool dense = A->format == OFRR_DENSE_COLMAJOR;
-    if (plan->refine >= 2 && dense && plan->basis_dtype == OFRR_BF16) {
+    if (plan->refine >= 2 && dense && !normal && plan->basis_dtype == OFRR_BF16) {
         Phase mid{OFRR_BF16};
         mid.split = true;
         phases.push_back(mid);
     }
     if (plan->refine && plan->basis_dtype != OFRR_F64) {
         Phase tail{OFRR_F64};
-        tail.sliced = dense && plan->tail_product == OFRR_TAIL_I8_SLICED;
+        tail.sliced = dense && !normal && plan->tail_product == OFRR_TAIL_I8_SLICED;
         phases.push_back(tail);
     }
     bool any_split = false, any_sliced = false;
@@ -172,7 +243,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     // small pencil's reductions, residual norms) stay finite and normal for
     // |a| in [2^-300, 2^300]; outside it the method runs on sigma A with
     // sigma a power of two, and eigenvalues are scaled back at the end
-    if (A->dtype == OFRR_F64) {
+    if (A->dtype == OFRR_F64 && !normal) {
         const double amax = absmax_values(ctx, A);
         if (!std::isfinite(amax)) fail(OFRR_ERR_NUMERIC, "A holds NaN or infinity");
         if (amax > 0) {
@@ -186,7 +257,13 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
 
     // quantise dense A once for the reduced-precision phases (Sec. 4: A
     // stored in reduced precision; a split phase also keeps A - bf16(A))
-    if (dense && !phases[0].f64()) {
+    if (dense && normal && !phases[0].f64()) {
+        // the m x n reduced copy, column-major (ld m): both products read it
+        run.A_lo_t = phases[0].basis;
+        const int64_t m = A->rows;
+        run.A_lo = ctx->buf<uint16_t>("A_lo", (size_t)m * n);
+        cast_matrix(ctx, A->dtype, run.A_lo_t, m, n, A->values, A->ld, run.A_lo, m);
+    } else if (dense && !phases[0].f64() && phases[0].basis != OFRR_F32) {
         run.A_lo_t = phases[0].basis;
         run.A_lo = ctx->buf<uint16_t>("A_lo", (size_t)n * n);
         const float *Af = nullptr;
@@ -265,9 +342,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     double gram_t = 1.0, gram_t_max = 0.0;
     int grams_f64 = 0;
 
+    double emax_prev = INFINITY;
     while (iters < plan->max_iters) {
         const Phase &ph = phases[pi];
         const ofrr_dtype mt = ph.master();
+        run.i8_digits = !ph.sliced ? 6 : (plan->tail_digits == 0 ? i8_digits_for(emax_prev) : plan->tail_digits);
         // default drop tolerance: machine epsilon of the arithmetic the
         // Hessenberg sweep runs in (FP32 for reduced-precision phases: it
         // works on the FP32 product output before the basis is rounded to
@@ -282,13 +361,15 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             else
                 OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
         } else if (cheb) {
-            // the combine sums the product's split-K partials itself
-            SlabOut so;
-            run.product(ph, Y0, W, bc, &so);
-            if (so.nsplit > 0)
-                cheb_combine_slabs(ctx, n, bc, so, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
-            else
-                cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+            if (!run.cheb_fused(ph, Y0, nullptr, 1.0 / ee, cc, 0.0, Y1, bc)) {
+                // the combine sums the product's split-K partials itself
+                SlabOut so;
+                run.product(ph, Y0, W, bc, &so);
+                if (so.nsplit > 0)
+                    cheb_combine_slabs(ctx, n, bc, so, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+                else
+                    cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+            }
         } else {
             run.product(ph, Y0, W, bc);
             OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
@@ -297,12 +378,14 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
             if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
             if (cheb) {
-                SlabOut so;
-                run.product(ph, Y1, W, bc, &so);
-                if (so.nsplit > 0)
-                    cheb_combine_slabs(ctx, n, bc, so, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
-                else
-                    cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                if (!run.cheb_fused(ph, Y1, Y0, 2.0 / ee, cc, 1.0, Y2, bc)) {
+                    SlabOut so;
+                    run.product(ph, Y1, W, bc, &so);
+                    if (so.nsplit > 0)
+                        cheb_combine_slabs(ctx, n, bc, so, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                    else
+                        cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                }
             } else {
                 run.product(ph, Y1, W, bc);
                 OFRR_HIP(hipMemcpyAsync(Y2, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
@@ -317,11 +400,33 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // every column was kept and is redone on the compacted basis when
         // one was dropped.
         const int32_t *hstat = nullptr;
-        hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, &hstat);
+        // QR in a wider type than the phase stores: its basis is kept at the
+        // phase's master precision, not rounded to the storage type
+        const bool qr_wide = plan->stab == 1 && !ph.f64() && plan->qr_dtype >= 0 &&
+                             !(plan->qr_dtype == OFRR_F16 && ph.basis == OFRR_F16);
+        if (plan->stab == 1) {
+            // QR by MGS with re-orthogonalisation (the classical comparison of
+            // Sec. 5.2), by default in the phase's storage type: column-major
+            // copy, the basis-generation kernel, back
+            const ofrr_dtype qt = ph.f64() ? OFRR_F64
+                                  : plan->qr_dtype >= 0 ? (ofrr_dtype)plan->qr_dtype
+                                  : (ph.basis == OFRR_F16 ? OFRR_F16 : OFRR_F32);
+            // columns whose norm the projections reduce below the QR type's
+            // epsilon (relative) are excluded, as for the Hessenberg basis
+            const double qtol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(qt);
+            void *cm = ctx->buf<double>("qr_colmajor", (size_t)n * ld);
+            transpose_cast(ctx, mt, qt, n, bc, Y1, ld, cm, n);
+            int32_t kept_q = bc;
+            basis_generate(ctx, 6, qt, n, bc, cm, n, qtol, nullptr, piv, keep, &kept_q, nullptr);
+            transpose_cast(ctx, qt, mt, bc, n, cm, n, Y1, ld);
+            hstat = status_pair(ctx, 0, kept_q);
+        } else {
+            hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, &hstat);
+        }
         std::swap(V, Y1);
         // storage rounding of the basis for a reduced-precision phase
         // (elementwise, so it commutes with the column compaction)
-        if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
+        if (!ph.f64() && !ph.split && plan->b_split < 2 && !qr_wide) round_block(ctx, ph.basis, n * ld, (float *)V);
         double *stage = nullptr;
         const bool f32_gram = pi == 0 && !ph.f64() && plan->gram_accum != OFRR_ACC_F64;
         ofrr_accum acc = OFRR_ACC_F64;
@@ -335,6 +440,9 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             // ---- project
             run.product(ph, V, W, bc);
             project(ctx, n, bc, mt, V, ld, mt, W, ld, acc, G, H);
+            // the classical Rayleigh-Ritz projection takes the basis as
+            // orthonormal: H y = theta y
+            if (plan->projection == 1) set_identity(ctx, bc, G);
             // ---- solve; the rank comes back with the residual estimates:
             // every column is lifted, those beyond the rank are zero and the
             // next sweep drops them
@@ -382,6 +490,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         double emax = 0.0;
         for (double v : est) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
         if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "non-finite residual estimate");
+        emax_prev = emax;
         const bool last_phase = pi + 1 == phases.size();
         if (last_phase && plan->tol > 0 && emax <= plan->tol) break;
         if (!last_phase) {
@@ -406,7 +515,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     cast_matrix(ctx, ph.master(), OFRR_F64, k, n, X, ld, Xf, k);
     {
         ++run.products;
-        if (A->format == OFRR_CSR)
+        if (normal) {
+            double *Tf = ctx->buf<double>("normal_Tf", (size_t)A->rows * k + 8);
+            product_f64(ctx, A, 0, k, Xf, k, Tf, k);
+            product_f64(ctx, A, 1, k, Tf, k, AXf, k);
+        } else if (A->format == OFRR_CSR)
             product_csr(ctx, A, k, OFRR_F64, Xf, k, AXf, k);
         else
             product_f64(ctx, A, 1, k, Xf, k, AXf, k);

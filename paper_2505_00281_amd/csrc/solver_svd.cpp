@@ -274,4 +274,88 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
 }
 
+ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                             ofrr_which which, const ofrr_plan *plan, const double *X0,
+                             double *evals, double *evecs, double *resid, ofrr_info *info, bool normal);
+
+namespace {
+
+// sigma_i = sqrt(max(theta_i, 0)); U = (A V) / sigma column by column
+__global__ void k_sqrt_clamp(const double *theta, double *sigma, int k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) sigma[i] = sqrt(theta[i] > 0.0 ? theta[i] : 0.0);
+}
+__global__ void k_div_cols(const double *AV, const double *sigma, double *U, int64_t m, int k) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * k; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % k);
+        U[e] = sigma[c] > 0.0 ? AV[e] / sigma[c] : 0.0;
+    }
+}
+
+}  // namespace
+
+// The normal-equations form of the SVD (the A^T A variant): the eigen
+// solver runs on the operator A^T A (each product is A V then A^T (A V), in
+// the phase's arithmetic) and returns the largest eigenvalues theta = s^2
+// with right vectors V; then s = sqrt(theta), U = A V / s, and the same
+// FP64 finalisation as the augmented form (residual sqrt(||A v - s u||^2 +
+// ||A^T u - s v||^2) / anorm, unit columns, sign fixed on v).  The
+// eigenvalues carry the condition of A^T A: a singular value s is found to
+// about u (s_1 / s)^2 relative, against u s_1 / s for the augmented pencil.
+ofrr_status svd_normal_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
+                            const ofrr_plan *plan, const double *V0, double *sigma, double *U,
+                            double *V, double *resid, ofrr_info *info) {
+    const int64_t m = A->rows, n = A->cols;
+    ofrr_plan p = *plan;
+    // the operator's normaliser is ||A||^2; its residual target is tighter by
+    // the factor the left vector's division brings in (s_1 / s_k, unknown
+    // beforehand: a fixed quarter)
+    p.anorm = plan->anorm > 0 ? plan->anorm * plan->anorm : 0.0;
+    p.tol = plan->tol * 0.25;
+    double *th = ctx->buf<double>("svdn_theta", (size_t)k + 8);
+    double *Xv = ctx->buf<double>("svdn_evecs", (size_t)n * k + 8);
+    double *re = ctx->buf<double>("svdn_resid", (size_t)k + 8);
+    ofrr_info ei;
+    std::memset(&ei, 0, sizeof ei);
+    const ofrr_status st = eig_partial_impl(ctx, A, k, basis, OFRR_LARGEST, &p, V0, th, Xv, re, &ei, true);
+    if (st < 0) return st;
+    double *sg = ctx->buf<double>("svdn_sigma", (size_t)k + 8);
+    hipLaunchKernelGGL(k_sqrt_clamp, dim3(1), dim3(256), 0, ctx->stream, th, sg, k);
+    double *Vf = ctx->buf<double>("svdn_Vf", (size_t)n * k + 8);
+    double *AVf = ctx->buf<double>("svdn_AVf", (size_t)m * k + 8);
+    double *Uf = ctx->buf<double>("svdn_Uf", (size_t)m * k + 8);
+    double *ATUf = ctx->buf<double>("svdn_ATUf", (size_t)n * k + 8);
+    colmajor_to_rowmajor(ctx, n, k, Xv, n, OFRR_F64, Vf, k);
+    product_f64(ctx, A, 0, k, Vf, k, AVf, k);
+    hipLaunchKernelGGL(k_div_cols, dim3((unsigned)std::min<int64_t>(4096, (m * k + 255) / 256)), dim3(256), 0,
+                       ctx->stream, AVf, sg, Uf, m, k);
+    product_f64(ctx, A, 1, k, Uf, k, ATUf, k);
+    OFRR_HIP(hipGetLastError());
+    // anorm of the SVD residual: the caller's, else the largest singular value
+    double anorm = plan->anorm;
+    if (!(anorm > 0)) {
+        double s0 = 0.0;
+        OFRR_HIP(hipMemcpyAsync(&s0, sg, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        OFRR_HIP(hipStreamSynchronize(ctx->stream));
+        anorm = s0 > 0 ? s0 : 1.0;
+    }
+    finalize_svd(ctx, m, n, k, Uf, AVf, Vf, ATUf, k, sg, anorm, sigma, U, V, resid);
+    std::vector<double> rr((size_t)k);
+    OFRR_HIP(hipMemcpyAsync(rr.data(), resid, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    OFRR_HIP(hipStreamSynchronize(ctx->stream));
+    int nconv = 0;
+    double rmax = 0.0;
+    for (double v : rr) {
+        rmax = std::max(rmax, v);
+        if (plan->tol > 0 ? v <= plan->tol : true) ++nconv;
+    }
+    if (info) {
+        *info = ei;
+        info->n_converged = nconv;
+        info->max_resid = rmax;
+        info->products = ei.products * 2 + 2;  // every operator product is two products with A
+    }
+    return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
+}
+
 }  // namespace ofrr

@@ -35,10 +35,11 @@ _FILTER = {"power": POWER, "chebyshev": CHEBYSHEV}
 _TAIL = {"f64": 0, "i8": 1}
 
 EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error",
-            "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_eig_partial",
-            "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_batched_last_config", "ofrr_quantize",
+            "ofrr_kernel_stats", "ofrr_kernel_stats_reset", "ofrr_set_profile", "ofrr_eig_partial",
+            "ofrr_svd_partial", "ofrr_eig_partial_batched", "ofrr_batched_last_config", "ofrr_krylov_eig",
+            "ofrr_quantize",
             "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_sliced",
-            "ofrr_block_product_fp8", "ofrr_hessenberg", "ofrr_hessenberg_noalloc",
+            "ofrr_block_product_fp8", "ofrr_hessenberg", "ofrr_hessenberg_noalloc", "ofrr_basis_generate",
             "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
 
 
@@ -63,7 +64,9 @@ class Plan(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("stall_iters", ctypes.c_int32),
                 ("switch_resid", ctypes.c_double), ("b_split", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("tail_product", ctypes.c_int32),
-                ("gram_switch_t", ctypes.c_double)]
+                ("gram_switch_t", ctypes.c_double), ("svd_form", ctypes.c_int32),
+                ("stab", ctypes.c_int32), ("projection", ctypes.c_int32),
+                ("qr_dtype", ctypes.c_int32), ("tail_digits", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -99,12 +102,14 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_last_error.restype = ctypes.c_char_p
     lib.ofrr_kernel_stats.argtypes = [vp, ctypes.c_char_p, P(i64), P(dbl)]
     lib.ofrr_kernel_stats_reset.argtypes = [vp]
+    lib.ofrr_set_profile.argtypes = [vp, i32]
     lib.ofrr_eig_partial.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, P(Plan), vp, vp, vp,
                                      vp, P(Info)]
     lib.ofrr_svd_partial.argtypes = [vp, P(Matrix), i32, i32, P(Plan), vp, vp, vp, vp, vp, P(Info)]
     lib.ofrr_eig_partial_batched.argtypes = [vp, i32, P(Matrix), i32, i32, ctypes.c_int, P(Plan),
                                              P(vp), P(vp), P(vp), P(vp), P(Info)]
-    lib.ofrr_batched_last_config.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+    lib.ofrr_krylov_eig.argtypes = [vp, P(Matrix), i32, i32, i32, ctypes.c_int, vp, dbl, vp, vp, vp, P(Info)]
+    lib.ofrr_batched_last_config.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(dbl)]
     lib.ofrr_quantize.argtypes = [vp, ctypes.c_int, i64, vp, vp]
     lib.ofrr_quantize_fp8_blocks.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     lib.ofrr_block_product.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, vp, vp]
@@ -112,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_block_product_fp8.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, vp]
     lib.ofrr_hessenberg.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
     lib.ofrr_hessenberg_noalloc.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
+    lib.ofrr_basis_generate.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, vp,
+                                        P(i32), P(dbl)]
     lib.ofrr_project.argtypes = [vp, i64, i32, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                  vp, vp]
     lib.ofrr_pencil_eig.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, vp, P(i32)]
@@ -125,7 +132,9 @@ def load_library(path: str = LIB_PATH):
 
 def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power", degree=1,
               lo=0.0, hi=0.0, drop_tol=0.0, tol=0.0, anorm=0.0, max_iters=20, stall_iters=3,
-              switch_resid=0.0, b_split=1, profile=False, tail="f64", gram_switch_t=0.0) -> Plan:
+              switch_resid=0.0, b_split=1, profile=False, tail="f64", gram_switch_t=0.0,
+              svd_form="augmented", stab="hessenberg", projection="ofrr", qr_dtype=None,
+              tail_digits=0) -> Plan:
     p = Plan()
     load_library().ofrr_plan_default(ctypes.byref(p))
     p.basis_dtype = _DTYPES[basis_dtype] if isinstance(basis_dtype, str) else basis_dtype
@@ -141,6 +150,12 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
     p.profile = int(bool(profile))
     p.tail_product = _TAIL[tail] if isinstance(tail, str) else int(tail)
     p.gram_switch_t = float(gram_switch_t)
+    p.svd_form = {"augmented": 0, "normal": 1}[svd_form] if isinstance(svd_form, str) else int(svd_form)
+    p.stab = {"hessenberg": 0, "qr": 1}[stab] if isinstance(stab, str) else int(stab)
+    p.projection = {"ofrr": 0, "classical": 1}[projection] if isinstance(projection, str) else int(projection)
+    # QR arithmetic of stab="qr" (None: the phase's storage type)
+    p.qr_dtype = -1 if qr_dtype is None else (_DTYPES[qr_dtype] if isinstance(qr_dtype, str) else int(qr_dtype))
+    p.tail_digits = int(tail_digits)
     return p
 
 
@@ -315,6 +330,26 @@ class Context:
         self._check(st, allow_warning=True)
         return SvdResult(sigma, U, V, resid, info.as_dict(), st)
 
+    def krylov_eig(self, A, k: int, nev: int, restarts: int = 0, basis_dtype: str = "f64", v0=None,
+                   tol: float = 0.0) -> EigResult:
+        """Restarted Krylov-Hessenberg + OFRR (ofrr_krylov_eig); A dense or
+        a csr_matrix descriptor, symmetric."""
+        mat = self._mat(A, symmetric=True)
+        n = mat.rows
+        if v0 is not None:
+            v0 = torch.as_tensor(v0, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+            if v0.numel() != n:
+                raise OfrrError(ERR_INVALID_ARG, f"v0 has {v0.numel()} entries, A has {n} rows")
+        evals = torch.empty(nev, dtype=torch.float64, device=self.device)
+        evecs = _empty_colmajor(n, nev, self.device)
+        resid = torch.empty(nev, dtype=torch.float64, device=self.device)
+        info = Info()
+        st = self.lib.ofrr_krylov_eig(self.h, ctypes.byref(mat), k, nev, restarts, _DTYPES[basis_dtype],
+                                      _ptr(v0), float(tol), _ptr(evals), _ptr(evecs), _ptr(resid),
+                                      ctypes.byref(info))
+        self._check(st, allow_warning=True)
+        return EigResult(evals, evecs, resid, info.as_dict(), st)
+
     def eig_partial_batched(self, As, k: int, basis: int, which: str = "largest",
                             plan: Plan | None = None, X0s=None):
         nprob = len(As)
@@ -339,14 +374,20 @@ class Context:
         self._check(st, allow_warning=True)
         return [EigResult(o[0], o[1], o[2], infos[p].as_dict(), st) for p, o in enumerate(outs)]
 
+    def set_profile(self, on: bool):
+        """Kernel timing for the step calls (see kernel_stats)."""
+        self._check(self.lib.ofrr_set_profile(self.h, 1 if on else 0))
+
     def batched_last_config(self) -> dict:
         """What the last eig_partial_batched call ran: grouped path or not,
         the autotuned row-tile heights of its grouped products, and the
         number of iteration-graph replays."""
         g, rr, rf, rp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        fm = ctypes.c_double()
         self._check(self.lib.ofrr_batched_last_config(self.h, ctypes.byref(g), ctypes.byref(rr), ctypes.byref(rf),
-                                                      ctypes.byref(rp)))
-        return {"grouped": bool(g.value), "rows_red": rr.value, "rows_f64": rf.value, "replays": rp.value}
+                                                      ctypes.byref(rp), ctypes.byref(fm)))
+        return {"grouped": bool(g.value), "rows_red": rr.value, "rows_f64": rf.value, "replays": rp.value,
+                "first_product_ms": fm.value}
 
     # ----------------------------------------------------------------- steps
     def quantize(self, src: torch.Tensor, dtype: str = "bf16") -> torch.Tensor:
@@ -472,6 +513,31 @@ class Context:
         self._check(self.lib.ofrr_hessenberg_noalloc(self.h, dt, n, b, _ptr(Y), b, float(tol), _ptr(piv),
                                                      _ptr(keep), ctypes.byref(kept)))
         return kept.value
+
+    BASIS_METHODS = {"mgs_l": 0, "mgs_r": 1, "cgs": 2, "cgs2": 3, "hess_l": 4, "hess_r": 5, "mgs2": 6}
+
+    def basis_generate(self, A: torch.Tensor, method: str, tol: float = 0.0, want_r: bool = False):
+        """ofrr_basis_generate in place on a column-major m x n block (a
+        transposed view of a contiguous n x m tensor): float64, float32, or
+        float16 (binary16 storage, FP32 arithmetic).  Returns (R or None,
+        piv, keep, kept, kernel_ms)."""
+        self._on_device(A)
+        self._dtype(A, (torch.float64, torch.float32, torch.float16), "A")
+        if A.dim() != 2 or A.stride(0) != 1:
+            raise OfrrError(ERR_INVALID_ARG, "A must be column-major (a transposed contiguous tensor)")
+        m, n = A.shape
+        lda = A.stride(1)
+        st = {torch.float64: F64, torch.float32: F32, torch.float16: F16}[A.dtype]
+        R = torch.zeros((n, n), dtype=torch.float64, device=self.device) if want_r else None
+        piv = torch.empty(n, dtype=torch.int32, device=self.device)
+        keep = torch.empty(n, dtype=torch.int32, device=self.device)
+        kept = ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._check(self.lib.ofrr_basis_generate(self.h, self.BASIS_METHODS[method], st, m, n, _ptr(A), lda,
+                                                 float(tol), _ptr(R) if want_r else None, _ptr(piv), _ptr(keep),
+                                                 ctypes.byref(kept), ctypes.byref(ms)))
+        # R is column-major: the tensor holds R^T
+        return (R.t().contiguous() if want_r else None), piv, keep, kept.value, ms.value
 
     def project(self, V: torch.Tensor, W: torch.Tensor, accum: str = "f64", v_dtype: str | None = None):
         """G = V^T V, H = V^T W for row-major (n x b) blocks; FP64 b x b

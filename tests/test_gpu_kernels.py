@@ -210,13 +210,16 @@ def test_product_fp8_block_scaled(ctx, trans, shape):
     assert np.all(err <= bound + 1e-30), float(np.max(err / np.maximum(bound, 1e-300)))
 
 
+@pytest.mark.parametrize("b", [24, 23, 130])
 @pytest.mark.parametrize("vt", ["f64", "f16", "f32"])
-def test_spmm_laplacian(ctx, vt):
+def test_spmm_laplacian(ctx, vt, b):
+    # even widths take the paired-column kernel (130: more than 64 column
+    # pairs per row), odd widths the one-column kernel
     from paper_2505_00281_amd import ofrr
     N = 37
     rp, ci, v = W.laplacian_2d_csr(N)
     n = N * N
-    X = np.random.default_rng(5).standard_normal((n, 24))
+    X = np.random.default_rng(5).standard_normal((n, b))
     if vt == "f16":
         X = R.round_f16(X).astype(np.float64)
         Xg = torch.from_numpy(X.astype(np.float16)).cuda()
@@ -240,8 +243,6 @@ def test_spmm_laplacian(ctx, vt):
 @pytest.mark.parametrize("shape", [(1000, 24), (5000, 64), (70000, 128), (16384, 128), (7, 3)])
 def test_hessenberg_matches_oracle_bitwise(ctx, prec, shape):
     n, b = shape
-    if prec == "f32" and n == 70000:
-        pytest.skip("FP32 streaming case covered at FP64")
     rng = np.random.default_rng(6)
     Y = rng.random((n, b))
     dt = np.float64 if prec == "f64" else np.float32
@@ -274,6 +275,35 @@ def test_hessenberg_lds_kernel_matches_oracle(ctx, monkeypatch, prec, shape):
     Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
     np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
     np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1048576, 64), (300001, 37), (70000, 128)])
+def test_hessenberg_panel_kernel_matches_oracle(ctx, prec, shape):
+    # blocks too tall for the row slices to stay on chip take the panel
+    # form (eight columns per panel, trailing block updated once per panel):
+    # the same bits as the per-column process, pivots and drops included.
+    # Columns 5 and 20 (inside and across panels) depend on earlier ones and
+    # column 11 is zero, so drops occur at several positions in a panel
+    n, b = shape
+    rng = np.random.default_rng(17 + b)
+    Y = rng.standard_normal((n, b))
+    Y[:, 5] = Y[:, 1] - 0.5 * Y[:, 3]
+    Y[:, 11] = 0.0
+    Y[:, 20] = Y[:, 2] + Y[:, 13]
+    Y /= np.maximum(np.abs(Y).max(axis=0), 1e-300)
+    dt = np.float64 if prec == "f64" else np.float32
+    Y = Y.astype(dt)
+    tol = (2.0 ** -52 if prec == "f64" else 2.0 ** -23) * 64
+    print("hessenberg panel", prec, shape, flush=True)
+    Yg = torch.from_numpy(Y.copy()).cuda()
+    piv, keep, kept = ctx.hessenberg(Yg, tol)
+    Q, p_ref, k_ref = O.hessenberg(Y, tol, prec)
+    assert k_ref[5] == 0 and k_ref[11] == 0 and k_ref[20] == 0
+    np.testing.assert_array_equal(keep.cpu().numpy(), k_ref)
+    np.testing.assert_array_equal(piv.cpu().numpy(), p_ref)
+    assert kept == int(k_ref.sum())
     np.testing.assert_array_equal(Yg.cpu().numpy(), Q)
 
 

@@ -14,5 +14,8 @@ from .generators import (  # noqa: F401
     laplacian_2d_eigenvalues,
     uniform_start,
     batched_sizes,
+    kernel_points,
+    kernel_subset,
+    gaussian_kernel,
     WORKLOADS,
 )

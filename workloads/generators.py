@@ -114,6 +114,34 @@ def laplacian_2d_eigenvalues(N: int) -> np.ndarray:
     return np.sort((t[:, None] + t[None, :]).ravel())
 
 
+def kernel_points(n: int, seed: int, d: int = 2) -> np.ndarray:
+    """n points drawn uniformly from the square (cube) of side sqrt(n)."""
+    return rng(seed).random((n, d)) * np.sqrt(n)
+
+
+def kernel_subset(X: np.ndarray, m: int, seed: int):
+    """m of the points of X drawn without replacement: (the points, their
+    row indices in X)."""
+    idx = rng(seed).choice(X.shape[0], size=m, replace=False)
+    return X[idx], idx
+
+
+def gaussian_kernel(X: np.ndarray, Y: np.ndarray | None = None, f: float = 1.0, length: float = 10.0,
+                    s: float = 0.0, dtype=torch.float64, device: str | torch.device = "cpu") -> torch.Tensor:
+    """Gaussian kernel matrix A_ij = f (exp(-||x_i - y_j||^2 / (2 l^2)) + s [i == j])
+    (Y = X for the square case), assembled in FP64, column-major."""
+    x = torch.as_tensor(X, dtype=torch.float64, device=device)
+    y = x if Y is None else torch.as_tensor(Y, dtype=torch.float64, device=device)
+    d2 = torch.cdist(x, y, compute_mode="donot_use_mm_for_euclid_dist") ** 2
+    a = torch.exp(-d2 / (2.0 * length * length))
+    if Y is None and s:
+        a = a + s * torch.eye(x.shape[0], dtype=torch.float64, device=device)
+    a = f * a
+    if Y is None:
+        a = 0.5 * (a + a.T)
+    return a.to(dtype).T.contiguous().T
+
+
 def uniform_start(n: int, b: int, seed: int) -> np.ndarray:
     """U(0,1) start block in FP64, column-major (Fortran order)."""
     return np.asfortranarray(rng(seed).random(size=(n, b), dtype=np.float64))
