@@ -109,7 +109,9 @@ typedef struct {
                                 residual estimate stalls, then an FP64 tail; 2 (dense,
                                 BF16): BF16 phase, then a phase with A and the basis as
                                 two-term BF16 splits (about 16 significant bits each,
-                                three MFMAs per fragment), then the FP64 tail */
+                                three MFMAs per fragment), then the FP64 tail; 2 (CSR,
+                                F16 or BF16): the 16-bit phase, an FP32 phase, the FP64
+                                tail */
     ofrr_filter filter;
     int32_t degree;          /* products per outer iteration (power steps or
                                 Chebyshev degree), >= 1 */
@@ -163,6 +165,11 @@ typedef struct {
                                 the phase's FP32 master precision (the products still read it
                                 rounded to the storage type): the [MatVec]-[QR] precision
                                 pairs of the Sec. 2 experiment */
+    int32_t matvec_round;    /* reduced-precision phases: every product's result rounded to
+                                this type, F16 or BF16, before use, the product itself
+                                computed in the phase's arithmetic (an F32 phase: from A as
+                                stored); -1 -> not rounded.  With stab 1 and qr_dtype this
+                                gives the [MatVec]-[QR] pairs of the Sec. 2 experiment */
     int32_t tail_digits;     /* OFRR_TAIL_I8_SLICED: signed 7-bit digits per side of the
                                 digit-plane products.  0: chosen per iteration from the
                                 previous largest residual estimate r (4 while r > 1600
@@ -191,7 +198,7 @@ typedef struct {
 /* Defaults: FP64 basis, FP64 accumulation, no refinement, power filter of
  * degree 1, drop_tol 0, tol 0, anorm 0, max_iters 20, stall_iters 3,
  * switch_resid 0, b_split 1, profile 0, tail_product F64, gram_switch_t 0,
- * svd_form 0, stab 0, projection 0, qr_dtype -1, tail_digits 0. */
+ * svd_form 0, stab 0, projection 0, qr_dtype -1, matvec_round -1, tail_digits 0. */
 void ofrr_plan_default(ofrr_plan *plan);
 
 /* Creates a context bound to `device` and to `hip_stream` (a hipStream_t,
@@ -209,7 +216,9 @@ const char *ofrr_last_error(ofrr_ctx ctx);
  * milliseconds of the kernel family `name` since the last reset, measured
  * with HIP events on the context's stream.  Families: "quantize",
  * "product_bf16", "product_bf16x2", "product_f16", "product_f8", "product_f64", "product_f32",
- * "product_reduce" (the fixed-order sum of split-K partials), "spmm",
+ * "product_i8x", "product_reduce" (the fixed-order sum of split-K
+ * partials), "spmm" (every CSR product; the solver's phases also by block
+ * storage: "spmm_f16" for binary16/bfloat16, "spmm_f32", "spmm_f64"),
  * "scale", "hessenberg", "gram", "small_eig", "lift", "residual".
  * Returns OFRR_ERR_INVALID_ARG for an unknown name. */
 ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches /*host*/,

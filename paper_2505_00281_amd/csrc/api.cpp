@@ -23,7 +23,8 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
 
 static const char *kFamilies[] = {"quantize", "product_bf16", "product_bf16x2", "product_f16", "product_f8",
                                   "product_f64", "product_f32", "product_i8x", "product_reduce", "spmm", "scale",
-                                  "hessenberg", "gram", "small_eig", "lift", "residual"};
+                                  "hessenberg", "gram", "small_eig", "lift", "residual", "spmm_f16", "spmm_f32",
+                                  "spmm_f64"};
 
 void *Workspace::get(const std::string &name, size_t bytes) {
     Buf &b = bufs[name];
@@ -150,6 +151,8 @@ static void validate_plan(const ofrr_plan *p) {
     OFRR_CHECK_ARG(p->projection == 0 || p->projection == 1, "plan.projection must be 0 or 1");
     OFRR_CHECK_ARG(p->qr_dtype == -1 || p->qr_dtype == OFRR_F64 || p->qr_dtype == OFRR_F32 || p->qr_dtype == OFRR_F16,
                    "plan.qr_dtype must be -1, F64, F32 or F16");
+    OFRR_CHECK_ARG(p->matvec_round == -1 || p->matvec_round == OFRR_F16 || p->matvec_round == OFRR_BF16,
+                   "plan.matvec_round must be -1, F16 or BF16");
     OFRR_CHECK_ARG(p->tail_digits == 0 || (p->tail_digits >= 4 && p->tail_digits <= 6),
                    "plan.tail_digits must be 0, 4, 5 or 6");
     OFRR_CHECK_ARG(p->basis_dtype == OFRR_F64 || p->basis_dtype == OFRR_BF16 ||
@@ -196,6 +199,7 @@ void ofrr_plan_default(ofrr_plan *p) {
     p->stab = 0;
     p->projection = 0;
     p->qr_dtype = -1;
+    p->matvec_round = -1;
     p->tail_digits = 0;
 }
 
@@ -274,6 +278,13 @@ ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches,
         c->resolve_timers();
         *launches = c->timer.launches[f];
         *total_ms = c->timer.total_ms[f];
+        // "spmm" is every CSR product: also the per-storage families
+        if (std::string(name) == "spmm")
+            for (const char *sub : {"spmm_f16", "spmm_f32", "spmm_f64"}) {
+                const int g = c->timer.family(sub);
+                *launches += c->timer.launches[g];
+                *total_ms += c->timer.total_ms[g];
+            }
         return OFRR_OK;
     });
 }

@@ -86,6 +86,39 @@ __device__ __forceinline__ void store_as<bf16_t>(bf16_t *p, double v) { p->bits 
 template <>
 __device__ __forceinline__ void store_as<f16_t>(f16_t *p, double v) { p->bits = f32_to_f16_bits((float)v); }
 
+// Column maxima of a row-major block, as order-preserving 32-bit keys of
+// the magnitudes: the FP32 bits for FP32 and narrower element types, the
+// upper word of the FP64 bits for FP64 (sign cleared: exponent and leading
+// mantissa bits, so the largest key has the largest exponent over FP64's
+// whole range; a column whose entries are all FP64 subnormals below 2^-1022
+// keys as zero).  NaN or infinity gives all ones.
+template <class T>
+__device__ __forceinline__ unsigned mag_key(double v) {
+    if (!(v == v) || isinf(v)) return 0xFFFFFFFFu;
+    if constexpr (sizeof(T) == 8)
+        return (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
+    else
+        return __float_as_uint((float)fabs(v));
+}
+
+// 2^-e for the column maximum m = f 2^e, f in [1/2, 1) (the scaled column has
+// infinity-norm in (1/2, 1]); 1 for a zero column; NaN for a NaN/Inf key.
+template <class T>
+__device__ __forceinline__ double key_scale(unsigned key) {
+    if (key == 0xFFFFFFFFu) return __builtin_nan("");
+    if (key == 0u) return 1.0;
+    int e;
+    if constexpr (sizeof(T) == 8)
+        (void)frexp(__hiloint2double((int)key, 0), &e);
+    else
+        (void)frexpf(__uint_as_float(key), &e);
+    return ldexp(1.0, -e);
+}
+
+// column maxima are merged into CM_COPIES copies of a 512-entry key array
+// (block index mod CM_COPIES), which spreads the atomics of many blocks
+constexpr int CM_COPIES = 4;
+
 // ---------------------------------------------------------------- reductions
 
 __device__ __forceinline__ float wave_max_f32(float v) {

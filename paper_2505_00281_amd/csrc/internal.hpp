@@ -275,6 +275,20 @@ void product_csr(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype vt, c
 // the FP32/binary16/bfloat16 basis, rounded to the phase's type on load);
 // with cheb, Out = alpha (A V - c Yc) - beta Yp (Yp may be null when beta = 0).
 // Returns false (nothing launched) when the blocks are not pair-aligned.
+// Column magnitude keys of a row-major block merged into keys (CM_COPIES x
+// 512, zero on entry); the power-of-two column scaling from such keys
+// applied to Y (clear, CM_COPIES x 512, is zeroed); a key array cleared.
+void column_keys(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *Y, int64_t ldy, unsigned *keys);
+void scale_apply_keys(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy, const unsigned *keys,
+                      unsigned *clear);
+void zero_keys(Context *ctx, unsigned *keys, int count);
+constexpr int CM_KEYS = 4 * 512;  // one key array: CM_COPIES copies of 512 columns
+// One Chebyshev step on CSR A with the column scaling folded in (see the
+// kernel); false (nothing launched) when the blocks are not pair-aligned.
+bool spmm_cheb_scaled(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype phase, const void *Y1,
+                      const void *Y0, void *Y2, int64_t ld, double alpha, double c, double beta,
+                      const unsigned *cmax_in, const double *p0, bool round_prev, double *s_out, unsigned *cmax_out,
+                      unsigned *clear);
 bool product_csr_master(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype phase, const void *Vm, int64_t ld,
                         void *Out, const void *Yc, const void *Yp, bool cheb, double alpha, double c, double beta);
 

@@ -132,40 +132,10 @@ __global__ void k_uniform(double *X, int64_t count, uint64_t seed) {
     }
 }
 
-// Column maxima of a row-major block, as order-preserving 32-bit keys of
-// the magnitudes: the FP32 bits for FP32 and narrower element types, the
-// upper word of the FP64 bits for FP64 (sign cleared: exponent and leading
-// mantissa bits, so the largest key has the largest exponent over FP64's
-// whole range; a column whose entries are all FP64 subnormals below 2^-1022
-// keys as zero).  NaN or infinity gives all ones.
-template <class T>
-__device__ __forceinline__ unsigned mag_key(double v) {
-    if (!(v == v) || isinf(v)) return 0xFFFFFFFFu;
-    if constexpr (sizeof(T) == 8)
-        return (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
-    else
-        return __float_as_uint((float)fabs(v));
-}
-
-// 2^-e for the column maximum m = f 2^e, f in [1/2, 1) (the scaled column has
-// infinity-norm in (1/2, 1]); 1 for a zero column; NaN for a NaN/Inf key.
-template <class T>
-__device__ __forceinline__ double key_scale(unsigned key) {
-    if (key == 0xFFFFFFFFu) return __builtin_nan("");
-    if (key == 0u) return 1.0;
-    int e;
-    if constexpr (sizeof(T) == 8)
-        (void)frexp(__hiloint2double((int)key, 0), &e);
-    else
-        (void)frexpf(__uint_as_float(key), &e);
-    return ldexp(1.0, -e);
-}
-
 // Block x reduces rows [x*rows_per_block, ...) over all b columns and merges
 // its maxima into cmax[c * 512 + j] (c = block index mod CM_COPIES, zero on
 // entry) by atomic maximum: the maximum of keys does not depend on the
 // merge order, and the copies spread the atomics of many blocks.
-constexpr int CM_COPIES = 4;
 
 template <class T>
 __global__ __launch_bounds__(256) void k_colmax_partial(const T *__restrict__ Y, int64_t ldy,
@@ -487,6 +457,39 @@ void scale_columns_pow2(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *
     });
     OFRR_HIP(hipGetLastError());
     ctx->colmax_parity ^= 1;
+}
+
+void column_keys(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *Y, int64_t ldy, unsigned *keys) {
+    KTimer tm(ctx, "scale");
+    OFRR_CHECK_ARG(b <= 512, "column_keys: b <= 512");
+    const int64_t rpb = 64;
+    const int nblk = (int)((n + rpb - 1) / rpb);
+    dispatch_type(t, [&](auto *p) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_colmax_partial<T>), dim3(nblk), dim3(256), 0, ctx->stream, (const T *)Y, ldy, n, b,
+                           rpb, keys);
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
+void scale_apply_keys(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, void *Y, int64_t ldy, const unsigned *keys,
+                      unsigned *clear) {
+    KTimer tm(ctx, "scale");
+    OFRR_CHECK_ARG(b <= 512, "scale_apply_keys: b <= 512");
+    const int rows_per_wg = 256 / (b < 256 ? b : 256);
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + rows_per_wg - 1) / rows_per_wg, 1024));
+    dispatch_type(t, [&](auto *p) {
+        using T = std::remove_pointer_t<decltype(p)>;
+        hipLaunchKernelGGL((k_scale_apply2<T>), dim3(g), dim3(256), 0, ctx->stream, (T *)Y, ldy, (T *)nullptr, ldy,
+                           n, b, keys, clear);
+    });
+    OFRR_HIP(hipGetLastError());
+}
+
+void zero_keys(Context *ctx, unsigned *keys, int count) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::max(1, std::min(64, (count + 255) / 256))), dim3(256), 0,
+                       ctx->stream, keys, count);
+    OFRR_HIP(hipGetLastError());
 }
 
 void compact_columns_rm(Context *ctx, ofrr_dtype t, int64_t n, int32_t b, const void *src,

@@ -330,6 +330,124 @@ __global__ __launch_bounds__(256) void k_spmm_v(const int32_t *__restrict__ rp, 
     }
 }
 
+// One Chebyshev step on CSR A with the recurrence's column scaling folded
+// in.  The scaled iteration brings the newest block Y1 to infinity-norm
+// (1/2, 1] per column by a power of two s (from the merged magnitude keys
+// of its columns) and multiplies the older block Y0 by the same s before
+// the step; here neither block is rewritten: Y1 is read as s Y1 (rounded
+// to the phase's storage type for reduced phases, as the stored block
+// would be) and Y0 as s p0 Y0, p0 being the factor still pending on Y0 from
+// the step before (rounded when Y0 was that step's Y1).  Powers of two
+// scale exactly, so the values are those of the scaled iteration.  The
+// step's output Y2 = alpha (A Y1 - c Y1) - beta Y0 is written unscaled and
+// its column keys are merged into cmax_out for the next step; workgroup 0
+// records s for that step's p0 and clears the key array two steps ahead.
+template <class T, int RND, class TA>
+__global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const TA *__restrict__ val, int64_t n_rows,
+    int64_t n_cols, int64_t nnz, int b, int lanes_log2, const T *__restrict__ Y1, const T *__restrict__ Y0,
+    T *__restrict__ Y2, int64_t ld, double alpha, double c, double beta, const unsigned *__restrict__ cmax_in,
+    const double *__restrict__ p0, int round_prev, double *__restrict__ s_out, unsigned *__restrict__ cmax_out,
+    unsigned *__restrict__ clear) {
+    using ACC = T;
+    __shared__ ACC sc[512], pp[512];
+    __shared__ unsigned km[512];
+    const int t = threadIdx.x;
+    for (int j = t; j < b; j += 256) {
+        double f = 1.0;
+        if (cmax_in) {
+            unsigned mb = cmax_in[j];
+#pragma unroll
+            for (int q = 1; q < CM_COPIES; ++q) mb = max(mb, cmax_in[q * 512 + j]);
+            f = key_scale<T>(mb);
+        }
+        sc[j] = (ACC)f;
+        pp[j] = p0 ? (ACC)p0[j] : (ACC)1;
+        km[j] = 0u;
+        if (blockIdx.x == 0 && s_out) s_out[j] = f;
+    }
+    if (blockIdx.x == 0 && clear)
+        for (int e = t; e < CM_COPIES * 512; e += 256) clear[e] = 0u;
+    __syncthreads();
+    const int L = 1 << lanes_log2;
+    const int rows_per = 256 >> lanes_log2;
+    const int64_t blk = xcd_row_block(blockIdx.x, gridDim.x);
+    const int64_t row = blk * rows_per + (t >> lanes_log2);
+    const int li = t & (L - 1);
+    if (row < n_rows) {
+        int64_t e0 = rp[row], e1 = rp[row + 1];
+        if (e0 < 0) e0 = 0;
+        if (e1 > nnz) e1 = nnz;
+        const int64_t cmx = n_cols - 1;
+        for (int j = 2 * li; j < b; j += 2 * L) {
+            const ACC s0 = sc[j], s1 = sc[j + 1 < b ? j + 1 : j];
+            ACC acc0 = (ACC)0, acc1 = (ACC)0;
+            int64_t e = e0;
+            for (; e + 4 <= e1; e += 4) {
+                int64_t cc[4];
+                ACC a[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = ci[e + u];
+                    cc[u] = q < 0 ? 0 : (q > cmx ? cmx : q);
+                    a[u] = (ACC)val[e + u];
+                }
+                ACC x0[4], x1[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) Pair<T>::get(Y1 + cc[u] * ld + j, x0[u], x1[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc0 = fma(a[u], spmm_round<RND>(x0[u] * s0), acc0);
+                    acc1 = fma(a[u], spmm_round<RND>(x1[u] * s1), acc1);
+                }
+            }
+            for (; e < e1; ++e) {
+                const int64_t q = ci[e];
+                const int64_t cc = q < 0 ? 0 : (q > cmx ? cmx : q);
+                const ACC a = (ACC)val[e];
+                ACC x0, x1;
+                Pair<T>::get(Y1 + cc * ld + j, x0, x1);
+                acc0 = fma(a, spmm_round<RND>(x0 * s0), acc0);
+                acc1 = fma(a, spmm_round<RND>(x1 * s1), acc1);
+            }
+            const int64_t o = row * ld + j;
+            const bool two = j + 1 < b;
+            ACC yc0, yc1, yp0 = (ACC)0, yp1 = (ACC)0;
+            Pair<T>::get(Y1 + o, yc0, yc1);
+            // a scaled step's Y1 is the stored (rounded) block; the first
+            // step's combine reads its input as it is, only the product
+            // reading it rounded
+            if (cmax_in) {
+                yc0 = spmm_round<RND>(yc0 * s0);
+                yc1 = spmm_round<RND>(yc1 * s1);
+            }
+            if (beta != 0.0) {
+                Pair<T>::get(Y0 + o, yp0, yp1);
+                const ACC q0 = yp0 * pp[j], q1 = yp1 * pp[two ? j + 1 : j];
+                yp0 = (round_prev ? spmm_round<RND>(q0) : q0) * s0;
+                yp1 = (round_prev ? spmm_round<RND>(q1) : q1) * s1;
+            }
+            double v0 = alpha * fma(-c, (double)yc0, (double)acc0);
+            if (beta != 0.0) v0 = fma(-beta, (double)yp0, v0);
+            const T w0 = (T)v0;
+            Y2[o] = w0;
+            if (cmax_out) atomicMax(&km[j], mag_key<T>((double)w0));
+            if (two) {
+                double v1 = alpha * fma(-c, (double)yc1, (double)acc1);
+                if (beta != 0.0) v1 = fma(-beta, (double)yp1, v1);
+                const T w1 = (T)v1;
+                Y2[o + 1] = w1;
+                if (cmax_out) atomicMax(&km[j + 1], mag_key<T>((double)w1));
+            }
+        }
+    }
+    if (cmax_out) {
+        __syncthreads();
+        for (int j = t; j < b; j += 256)
+            if (km[j]) atomicMax(cmax_out + (blockIdx.x % CM_COPIES) * 512 + j, km[j]);
+    }
+}
+
 // CSR structure check: row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
 // every column index in [0, n_cols).  Sets *bad to a nonzero code.
 __global__ void k_csr_check(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -487,7 +605,7 @@ bool product_csr_master(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtyp
     const size_t es = phase == OFRR_F64 ? 8 : 4;
     if (!pair_aligned(Vm, ld, es) || !pair_aligned(Out, ld, es)) return false;
     if (cheb && (!pair_aligned(Yc, ld, es) || (Yp && !pair_aligned(Yp, ld, es)))) return false;
-    KTimer tm(ctx, "spmm");
+    KTimer tm(ctx, phase == OFRR_F64 ? "spmm_f64" : phase == OFRR_F32 ? "spmm_f32" : "spmm_f16");
     auto go = [&](auto *tag, auto rnd) {
         using T = std::remove_pointer_t<decltype(tag)>;
         constexpr int R = decltype(rnd)::value;
@@ -507,6 +625,42 @@ bool product_csr_master(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtyp
         case OFRR_BF16: go((float *)nullptr, std::integral_constant<int, 2>{}); break;
         default: return false;
     }
+    return true;
+}
+
+bool spmm_cheb_scaled(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype phase, const void *Y1,
+                      const void *Y0, void *Y2, int64_t ld, double alpha, double c, double beta,
+                      const unsigned *cmax_in, const double *p0, bool round_prev, double *s_out, unsigned *cmax_out,
+                      unsigned *clear) {
+    const size_t es = phase == OFRR_F64 ? 8 : 4;
+    if (!pair_aligned(Y1, ld, es) || !pair_aligned(Y2, ld, es) || (Y0 && !pair_aligned(Y0, ld, es))) return false;
+    if (b > 512) return false;
+    KTimer tm(ctx, phase == OFRR_F64 ? "spmm_f64" : phase == OFRR_F32 ? "spmm_f32" : "spmm_f16");
+    const int lg = spmm_lanes_log2(b);
+    const int64_t rows_per = 256 >> lg;
+    const int64_t G = (A->rows + rows_per - 1) / rows_per;
+    OFRR_CHECK_ARG(G < ((int64_t)1 << 31), "spmm: too many rows");
+    const int rp = round_prev ? 1 : 0;
+    auto go = [&](auto *tag, auto rnd, auto *atag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        using TA = std::remove_pointer_t<decltype(atag)>;
+        constexpr int R = decltype(rnd)::value;
+        hipLaunchKernelGGL((k_spmm_cheb_scaled<T, R, TA>), dim3((unsigned)G), dim3(256), 0, ctx->stream, A->row_ptr,
+                           A->col_idx, (const TA *)A->values, A->rows, A->cols, A->nnz, b, lg, (const T *)Y1,
+                           (const T *)Y0, (T *)Y2, ld, alpha, c, beta, cmax_in, p0, rp, s_out, cmax_out, clear);
+    };
+    auto by_a = [&](auto *tag, auto rnd) {
+        if (A->dtype == OFRR_F32) go(tag, rnd, (float *)nullptr);
+        else go(tag, rnd, (double *)nullptr);
+    };
+    switch (phase) {
+        case OFRR_F64: by_a((double *)nullptr, std::integral_constant<int, 0>{}); break;
+        case OFRR_F32: by_a((float *)nullptr, std::integral_constant<int, 0>{}); break;
+        case OFRR_F16: by_a((float *)nullptr, std::integral_constant<int, 1>{}); break;
+        case OFRR_BF16: by_a((float *)nullptr, std::integral_constant<int, 2>{}); break;
+        default: return false;
+    }
+    OFRR_HIP(hipGetLastError());
     return true;
 }
 

@@ -16,6 +16,7 @@
 //   lift       X = V Y, A X = W Y, residual estimates.
 // A refined plan runs this first in the reduced precision and switches to
 // an all-FP64 tail when the residual estimates stop improving.
+#include <cstdlib>
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -85,8 +86,13 @@ struct EigRun {
     // split-K partials may be left unreduced and described in *defer for a
     // consumer that sums them itself; defer->nsplit stays 0 when W is written.
     void product(const Phase &ph, const void *Vm, void *Wm, int32_t bc, SlabOut *defer = nullptr) {
-        product_raw(ph, Vm, Wm, bc, sigma == 1.0 ? defer : nullptr);
-        if (defer && sigma != 1.0) defer->nsplit = 0;
+        const bool rounded = plan->matvec_round >= 0 && !ph.f64();
+        product_raw(ph, Vm, Wm, bc, sigma == 1.0 && !rounded ? defer : nullptr);
+        if (defer && (sigma != 1.0 || rounded)) defer->nsplit = 0;
+        // product outputs rounded to a narrower type (the MatVec precision
+        // of the Sec. 2 experiment: computed accurately, the result stored
+        // in the narrower type)
+        if (rounded) round_block(ctx, (ofrr_dtype)plan->matvec_round, n * b0, (float *)Wm);
         // FP64 phases read A as stored: scale their products (exact: a power
         // of two on normal numbers); the reduced phases' copy of A is scaled
         if (sigma != 1.0 && ph.f64()) scale_array(ctx, n * b0, (double *)Wm, sigma);
@@ -229,6 +235,11 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         mid.split = true;
         phases.push_back(mid);
     }
+    // CSR A: an FP32 middle phase after a 16-bit one (the SpMM reads only the
+    // block and the sparse structure, so FP32 vectors cost about half the
+    // FP64 tail's traffic per iteration)
+    if (plan->refine >= 2 && !dense && (plan->basis_dtype == OFRR_F16 || plan->basis_dtype == OFRR_BF16))
+        phases.push_back(Phase{OFRR_F32});
     if (plan->refine && plan->basis_dtype != OFRR_F64) {
         Phase tail{OFRR_F64};
         tail.sliced = dense && !normal && plan->tail_product == OFRR_TAIL_I8_SLICED;
@@ -355,45 +366,83 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         // ---- filter
         // Y0 = X: the blocks trade places (X is dead until the lift writes it)
         std::swap(Y0, X);
-        if (have_ax) {
-            if (cheb)
+        // CSR A with a Chebyshev filter: the column scaling of the recurrence
+        // is folded into the fused steps (keys of each output merged in its
+        // epilogue, the scales applied as the next step reads its inputs),
+        // so no pass over the blocks is spent on it
+        // (OFRR_CHEB_FOLD=0 selects the separate scaling passes, for
+        // comparisons: both give the same values)
+        const char *fold_e = std::getenv("OFRR_CHEB_FOLD");
+        const bool fold_env = !(fold_e && std::atoi(fold_e) == 0);
+        const bool csr_scaled = fold_env && cheb && A->format == OFRR_CSR && run.sigma == 1.0 && !ph.split &&
+                                plan->b_split < 2 && ld % 2 == 0 && bc <= 512;
+        if (csr_scaled) {
+            unsigned *keys = ctx->buf<unsigned>("cheb_keys", (size_t)3 * CM_KEYS);
+            double *svec = ctx->buf<double>("cheb_s", 2 * 512);
+            zero_keys(ctx, keys, 3 * CM_KEYS);
+            auto K = [&](int i) { return keys + (size_t)(i % 3) * CM_KEYS; };
+            bool ok = true;
+            if (have_ax) {
                 axpby_block(ctx, n, bc, mt, AX, Y0, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
-            else
-                OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
-        } else if (cheb) {
-            if (!run.cheb_fused(ph, Y0, nullptr, 1.0 / ee, cc, 0.0, Y1, bc)) {
-                // the combine sums the product's split-K partials itself
-                SlabOut so;
-                run.product(ph, Y0, W, bc, &so);
-                if (so.nsplit > 0)
-                    cheb_combine_slabs(ctx, n, bc, so, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
-                else
-                    cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
+                column_keys(ctx, mt, n, bc, Y1, ld, K(0));
+            } else {
+                ok = spmm_cheb_scaled(ctx, A, bc, ph.basis, Y0, nullptr, Y1, ld, 1.0 / ee, cc, 0.0, nullptr, nullptr,
+                                      false, nullptr, K(0), nullptr);
+                ++run.products;
             }
+            int ki = 0;
+            for (int d = 2; ok && d <= plan->degree; ++d, ++ki) {
+                // p0: the scale step d - 1 applied, still pending on Y0
+                const double *p0 = d == 2 ? nullptr : svec + (size_t)((d - 1) & 1) * 512;
+                ok = spmm_cheb_scaled(ctx, A, bc, ph.basis, Y1, Y0, Y2, ld, 2.0 / ee, cc, 1.0, K(ki), p0, d > 2,
+                                      svec + (size_t)(d & 1) * 512, K(ki + 1), K(ki + 2));
+                ++run.products;
+                std::swap(Y0, Y1);
+                std::swap(Y1, Y2);
+            }
+            if (!ok) fail(OFRR_ERR_HIP, "scaled Chebyshev step: blocks not pair-aligned");
+            scale_apply_keys(ctx, mt, n, bc, Y1, ld, K(ki), K(ki + 1));
         } else {
-            run.product(ph, Y0, W, bc);
-            OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
-        }
-        for (int d = 2; d <= plan->degree; ++d) {
-            scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
-            if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
-            if (cheb) {
-                if (!run.cheb_fused(ph, Y1, Y0, 2.0 / ee, cc, 1.0, Y2, bc)) {
+            if (have_ax) {
+                if (cheb)
+                    axpby_block(ctx, n, bc, mt, AX, Y0, ld, 1.0 / ee, -cc / ee, mt, Y1, ld);
+                else
+                    OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+            } else if (cheb) {
+                if (!run.cheb_fused(ph, Y0, nullptr, 1.0 / ee, cc, 0.0, Y1, bc)) {
+                    // the combine sums the product's split-K partials itself
                     SlabOut so;
-                    run.product(ph, Y1, W, bc, &so);
+                    run.product(ph, Y0, W, bc, &so);
                     if (so.nsplit > 0)
-                        cheb_combine_slabs(ctx, n, bc, so, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                        cheb_combine_slabs(ctx, n, bc, so, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
                     else
-                        cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                        cheb_combine(ctx, n, bc, mt, W, mt, Y0, nullptr, ld, 1.0 / ee, cc, 0.0, mt, Y1);
                 }
             } else {
-                run.product(ph, Y1, W, bc);
-                OFRR_HIP(hipMemcpyAsync(Y2, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+                run.product(ph, Y0, W, bc);
+                OFRR_HIP(hipMemcpyAsync(Y1, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
             }
-            std::swap(Y0, Y1);
-            std::swap(Y1, Y2);
+            for (int d = 2; d <= plan->degree; ++d) {
+                scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, cheb ? Y0 : nullptr, ld, swork);
+                if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
+                if (cheb) {
+                    if (!run.cheb_fused(ph, Y1, Y0, 2.0 / ee, cc, 1.0, Y2, bc)) {
+                        SlabOut so;
+                        run.product(ph, Y1, W, bc, &so);
+                        if (so.nsplit > 0)
+                            cheb_combine_slabs(ctx, n, bc, so, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                        else
+                            cheb_combine(ctx, n, bc, mt, W, mt, Y1, Y0, ld, 2.0 / ee, cc, 1.0, mt, Y2);
+                    }
+                } else {
+                    run.product(ph, Y1, W, bc);
+                    OFRR_HIP(hipMemcpyAsync(Y2, W, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+                }
+                std::swap(Y0, Y1);
+                std::swap(Y1, Y2);
+            }
+            scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
         }
-        scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
         // ---- stabilise (Hessenberg process, FP64 or FP32 arithmetic).  Its
         // kept count comes back with the residual estimates (one host
         // synchronisation per iteration): the rest of the iteration assumes
@@ -411,9 +460,12 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             const ofrr_dtype qt = ph.f64() ? OFRR_F64
                                   : plan->qr_dtype >= 0 ? (ofrr_dtype)plan->qr_dtype
                                   : (ph.basis == OFRR_F16 ? OFRR_F16 : OFRR_F32);
-            // columns whose norm the projections reduce below the QR type's
-            // epsilon (relative) are excluded, as for the Hessenberg basis
-            const double qtol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(qt);
+            // with plan.drop_tol > 0, columns whose norm the projections
+            // reduce to at most drop_tol of their norm before them are
+            // excluded; by default none is (on the Gaussian-kernel studies
+            // the FP32 and binary16 QR bases otherwise fell below the wanted
+            // pair count in their first iteration)
+            const double qtol = plan->drop_tol > 0 ? plan->drop_tol : 0.0;
             void *cm = ctx->buf<double>("qr_colmajor", (size_t)n * ld);
             transpose_cast(ctx, mt, qt, n, bc, Y1, ld, cm, n);
             int32_t kept_q = bc;
@@ -492,7 +544,10 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "non-finite residual estimate");
         emax_prev = emax;
         const bool last_phase = pi + 1 == phases.size();
-        if (last_phase && plan->tol > 0 && emax <= plan->tol) break;
+        // (an iteration whose products took fewer than six digits is
+        // followed by one with six before the loop may stop: its Ritz
+        // values carry that product's error)
+        if (last_phase && plan->tol > 0 && emax <= plan->tol && run.i8_digits == 6) break;
         if (!last_phase) {
             const bool stalled = stall_det.push(emax);
             const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;

@@ -66,7 +66,8 @@ class Plan(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("tail_product", ctypes.c_int32),
                 ("gram_switch_t", ctypes.c_double), ("svd_form", ctypes.c_int32),
                 ("stab", ctypes.c_int32), ("projection", ctypes.c_int32),
-                ("qr_dtype", ctypes.c_int32), ("tail_digits", ctypes.c_int32)]
+                ("qr_dtype", ctypes.c_int32), ("matvec_round", ctypes.c_int32),
+                ("tail_digits", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -134,7 +135,7 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
               lo=0.0, hi=0.0, drop_tol=0.0, tol=0.0, anorm=0.0, max_iters=20, stall_iters=3,
               switch_resid=0.0, b_split=1, profile=False, tail="f64", gram_switch_t=0.0,
               svd_form="augmented", stab="hessenberg", projection="ofrr", qr_dtype=None,
-              tail_digits=0) -> Plan:
+              matvec_round=None, tail_digits=0) -> Plan:
     p = Plan()
     load_library().ofrr_plan_default(ctypes.byref(p))
     p.basis_dtype = _DTYPES[basis_dtype] if isinstance(basis_dtype, str) else basis_dtype
@@ -155,6 +156,9 @@ def make_plan(basis_dtype="f64", gram_accum="f64", refine=False, filter="power",
     p.projection = {"ofrr": 0, "classical": 1}[projection] if isinstance(projection, str) else int(projection)
     # QR arithmetic of stab="qr" (None: the phase's storage type)
     p.qr_dtype = -1 if qr_dtype is None else (_DTYPES[qr_dtype] if isinstance(qr_dtype, str) else int(qr_dtype))
+    # storage type every reduced-phase product is rounded to (None: none)
+    p.matvec_round = -1 if matvec_round is None else (
+        _DTYPES[matvec_round] if isinstance(matvec_round, str) else int(matvec_round))
     p.tail_digits = int(tail_digits)
     return p
 

@@ -118,3 +118,31 @@ def test_basis_rejects_bad_arguments(ctx):
     A = _colmajor(np.zeros((10, 20)), torch.float64)  # n > m
     with pytest.raises(ofrr.OfrrError):
         ctx.basis_generate(A, "cgs")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_mgs2_excludes_dependent_columns(ctx, prec):
+    # with tol > 0, MGS2 excludes a column whose norm its projections reduce
+    # to at most tol of its norm before them; the kept columns stay
+    # orthonormal to the storage rounding and span the input's columns
+    m, n = 5000, 24
+    A = np.random.default_rng(990).random((m, n))
+    A[:, 7] = A[:, 2] - 0.25 * A[:, 5]
+    A[:, 15] = 0.0
+    A[:, 20] = A[:, 1] + A[:, 3]
+    Ag = _colmajor(A, _TORCH[prec])
+    print("basis mgs2 exclusion", prec, flush=True)
+    # dependent columns keep a few units of the storage rounding; the others
+    # about half their norm (U(0,1) columns share their mean direction)
+    tol = {"f64": 2.0 ** -40, "f32": 2.0 ** -16, "f16": 2.0 ** -6}[prec]
+    _, piv, keep, kept, _ = ctx.basis_generate(Ag, "mgs2", tol=tol)
+    k = keep.cpu().numpy()
+    assert k[7] == 0 and k[15] == 0 and k[20] == 0 and kept == n - 3 and k.sum() == kept
+    np.testing.assert_array_equal(piv.cpu().numpy(), np.where(k == 1, np.arange(n), -1))
+    Q = Ag.double().cpu().numpy()[:, k == 1]
+    u = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11}[prec]
+    assert np.linalg.norm(Q.T @ Q - np.eye(kept), 2) <= 50 * u * np.sqrt(m)
+    # every input column lies in the span of the kept columns
+    Ain = torch.from_numpy(np.ascontiguousarray(A.T)).to(_TORCH[prec]).double().numpy().T
+    res = Ain - Q @ (Q.T @ Ain)
+    assert np.linalg.norm(res) <= 50 * u * np.sqrt(m) * np.linalg.norm(Ain)

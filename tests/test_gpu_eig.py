@@ -339,3 +339,25 @@ def test_batched_matches_single(ctx):
     for i, o in enumerate(outs):
         ref = O.subspace_eig(As[i].numpy(), X0s[i].numpy(), 8, outer=10)
         np.testing.assert_allclose(o.evals.cpu().numpy(), ref.theta, rtol=1e-12)
+
+
+@pytest.mark.parametrize("basis_dtype", ["f64", "f16"])
+def test_eig_csr_folded_scaling_equals_separate_passes(ctx, monkeypatch, basis_dtype):
+    """CSR + Chebyshev: the column scaling folded into the fused steps gives
+    the bits of the separate scaling passes (powers of two scale exactly;
+    the reduced phase reads its block rounded to binary16 either way)."""
+    from paper_2505_00281_amd import ofrr
+    N, b, k = 40, 16, 6
+    rp, ci, v = W.laplacian_2d_csr(N)
+    ev = W.laplacian_2d_eigenvalues(N)
+    X0 = torch.from_numpy(W.uniform_start(N * N, b, 19))
+    mat = ofrr.csr_matrix(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), torch.from_numpy(v).cuda())
+    plan = _plan(basis_dtype=basis_dtype, filter="chebyshev", degree=7, lo=float(ev[b]), hi=8.0, anorm=8.0,
+                 max_iters=6)
+    print("eig csr folded scaling", basis_dtype, flush=True)
+    r1 = ctx.eig_partial(mat, k, b, which="smallest", plan=plan, X0=X0)
+    monkeypatch.setenv("OFRR_CHEB_FOLD", "0")
+    r2 = ctx.eig_partial(mat, k, b, which="smallest", plan=plan, X0=X0)
+    np.testing.assert_array_equal(r1.evals.cpu().numpy(), r2.evals.cpu().numpy())
+    np.testing.assert_array_equal(r1.evecs.cpu().numpy(), r2.evecs.cpu().numpy())
+    assert r1.info["products"] == r2.info["products"]
