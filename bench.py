@@ -40,15 +40,16 @@ NOISE = 1e-3
 TOL = 1e-8
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the current product kernels at n=16384, b=128
-# (the FP64 product: 1146.8 MiB, used only by the FP64 form at that width),
+# (the FP64 product: 1123.4 MiB, used only by the FP64 form at that width),
 # from rocprofv3 FETCH_SIZE + WRITE_SIZE passes over `bench.py --traffic-probe`,
 # scaled by the same counters on a plain 1 GiB copy (FETCH x2, WRITE x1).
-# Counters were taken for these kernel versions; a changed kernel needs new
-# passes before its entry is trusted again.
+# The digit-plane product by digits per side; its family's entry is the
+# average over the call's launches.  Counters were taken for these kernel
+# versions; a changed kernel needs new passes before its entry is trusted.
 MEASURED_TRAFFIC = {
     "product_bf16": 553.0 * 2**20,
-    "product_i8x": 1758.7 * 2**20,
 }
+MEASURED_TRAFFIC_I8 = {4: 1214.0 * 2**20, 5: 1488.6 * 2**20, 6: 1760.6 * 2**20}
 
 
 def log(*a):
@@ -621,7 +622,8 @@ def main():
         for _ in range(3):
             # column-major views (the values are random; only the traffic counts)
             ctx.block_product(Ab.t(), Vb, trans=True)
-            ctx.block_product_sliced(A.t(), V, trans=True)
+            for d in (6, 5, 4):
+                ctx.block_product_sliced(A.t(), V, trans=True, digits=d)
             ctx.block_product(A.t(), V, trans=True)
         torch.cuda.synchronize()
         ctx.close()
@@ -652,6 +654,8 @@ def main():
     ctx.eig_partial(A, K_WANT, BASIS, plan=ofrr.make_plan(profile=True, **mixed_kw), X0=X0)
     torch.cuda.synchronize()
     stats = {f: ctx.kernel_stats(f) for f in fams}
+    # digit-plane launches by digits per side (4, 5, 6: 10, 15, 21 pairs)
+    i8_by_digits = {d: ctx.kernel_stats(f"product_i8x_d{d}") for d in (4, 5, 6)}
     kernel_ms_fp64 = None
     if not args.no_fp64_form:
         ctx.kernel_stats_reset()
@@ -679,11 +683,18 @@ def main():
         "product_bf16x2": dict(bytes=bf16_bytes, ops=gemm, peak_mfma=2500.0, dtype="bf16",
                                kernel="k_gemm_lp<bf16, split A and V> (hi+lo BF16 operands, 3 MFMAs per step)",
                                kernel_bytes=N * N * 4 + N * BASIS * 4 + N * BASIS * 4, kernel_ops=3 * gemm),
-        # FP64-class product: the method's flops on the kernel's own unit (INT8)
+        # FP64-class product: the method's flops on the kernel's own unit
+        # (INT8); the kernel's own bytes and operations averaged over its
+        # launches by digits per side (d planes of A and V, d(d+1)/2 pairs)
         "product_i8x": dict(bytes=N * N * 4 + N * BASIS * 8 + N * BASIS * 8, ops=gemm, peak_mfma=5000.0,
                             dtype="int8",
-                            kernel="k_gemm_i8s (6 x 6 INT8 digit planes, 21 MFMA 32x32x32 pairs, exact int32)",
-                            kernel_bytes=6 * N * N + 6 * N * BASIS + 8 * N * BASIS, kernel_ops=21 * gemm),
+                            kernel="k_gemm_i8s (4, 5 or 6 INT8 digit planes per side chosen per iteration; "
+                                   "10, 15 or 21 MFMA 32x32x32 pairs, exact int32)",
+                            kernel_bytes=sum(n_ * (d * N * N + d * N * BASIS + 8 * N * BASIS)
+                                             for d, (n_, _) in i8_by_digits.items())
+                            / max(1, sum(n_ for n_, _ in i8_by_digits.values())),
+                            kernel_ops=sum(n_ * d * (d + 1) // 2 * gemm for d, (n_, _) in i8_by_digits.items())
+                            / max(1, sum(n_ for n_, _ in i8_by_digits.values()))),
         # in the mixed call the only FP64 product is the final residual check
         "product_f64": dict(bytes=N * N * 4 + N * K_WANT * 16, ops=2.0 * N * N * K_WANT, peak_mfma=78.6,
                             dtype="f64", kernel="k_gemm_f64 (final residual product, k columns, FP64 MFMA)",
@@ -705,7 +716,12 @@ def main():
             ach = a["ops"] / sec / 1e12
             r = {"bound": "mfma", "achieved": round(ach, 2), "peak": a["peak_mfma"],
                  "unit": "TOP/s" if a["dtype"] == "int8" else "TFLOP/s", "frac": round(ach / a["peak_mfma"], 4)}
-        r.update({"traffic": MEASURED_TRAFFIC.get(f) if N == 16384 and BASIS == 128 else None,
+        traffic = MEASURED_TRAFFIC.get(f)
+        if f == "product_i8x":
+            n_i8 = sum(n_ for n_, _ in i8_by_digits.values())
+            traffic = (sum(n_ * MEASURED_TRAFFIC_I8[d] for d, (n_, _) in i8_by_digits.items()) / n_i8
+                       if n_i8 else None)
+        r.update({"traffic": traffic if N == 16384 and BASIS == 128 else None,
                   "kernel": a["kernel"], "family": f, "avg_launch_ms": avg, "launches": n_l,
                   "algorithmic_bytes_per_launch": a["bytes"], "algorithmic_flops_per_launch": a["ops"],
                   "kernel_rate": {"bytes_per_launch": a["kernel_bytes"], "ops_per_launch": a["kernel_ops"],
@@ -715,6 +731,8 @@ def main():
             # the same product at FP64 accuracy on the FP64 MFMA roof
             r["fp64_equivalent"] = {"achieved_TFLOP_s": round(gemm / sec / 1e12, 2), "peak": 78.6,
                                     "frac": round(gemm / sec / 1e12 / 78.6, 3)}
+            r["launches_by_digits"] = {str(d): {"launches": n_, "avg_launch_ms": round(t_ / n_, 4) if n_ else None}
+                                       for d, (n_, t_) in i8_by_digits.items()}
         return r
 
     # the product family with the largest share of the call; the two

@@ -216,7 +216,9 @@ const char *ofrr_last_error(ofrr_ctx ctx);
  * milliseconds of the kernel family `name` since the last reset, measured
  * with HIP events on the context's stream.  Families: "quantize",
  * "product_bf16", "product_bf16x2", "product_f16", "product_f8", "product_f64", "product_f32",
- * "product_i8x", "product_reduce" (the fixed-order sum of split-K
+ * "product_i8x" (the digit-plane products; also by digits per side:
+ * "product_i8x_d4", "product_i8x_d5", "product_i8x_d6"), "product_reduce"
+ * (the fixed-order sum of split-K
  * partials), "spmm" (every CSR product; the solver's phases also by block
  * storage: "spmm_f16" for binary16/bfloat16, "spmm_f32", "spmm_f64"),
  * "scale", "hessenberg", "gram", "small_eig", "lift", "residual".
@@ -354,12 +356,14 @@ ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans
 /* FP64-class block product W = op(A) V from exact INT8 digit-plane products
  * (the OFRR_TAIL_I8_SLICED products of the final phase; Sec. 2 products).
  * A: dense F32/F64 descriptor; V: FP64 row-major (op(A) cols) x b (ld b);
- * W: FP64 row-major (op(A) rows) x b (ld b).  Per entry the error is below
- * 2^-42 (2^e_i sum_k |V_kj| + 2^f_j sum_k |op(A)_ik| + 5.1 K 2^(e_i+f_j))
- * plus FP64 rounding of the final sums, with 2^e_i the smallest power of two
- * above max_k |op(A)_ik| and 2^f_j that above max_k |V_kj|. */
+ * W: FP64 row-major (op(A) rows) x b (ld b); digits: signed 7-bit digits per
+ * side, 4, 5 or 6 (0 -> 6).  Per entry the error is below
+ * 2^-7d (2^e_i sum_k |V_kj| + 2^f_j sum_k |op(A)_ik| + 1.02 (d - 1) K 2^(e_i+f_j))
+ * plus FP64 rounding of the final sums, with d the digits, 2^e_i the
+ * smallest power of two above max_k |op(A)_ik| and 2^f_j that above
+ * max_k |V_kj| (d = 6: 2^-42 and 5.1 K). */
 ofrr_status ofrr_block_product_sliced(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
-                                      const double *V, double *W);
+                                      int32_t digits, const double *V, double *W);
 
 /* FP8 block product W = op(A) V (trans 0: A V; 1: A^T V) for A given as
  * e4m3fn codes (rows x cols, column-major, ld = rows) with 32 x 32 block

@@ -1,6 +1,7 @@
 // api.cpp -- the extern "C" entry points of include/ofrr.h: context
 // lifetime, argument validation (before any device work), error capture (no
 // C++ exception crosses the boundary) and kernel timing.
+#include <initializer_list>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,7 +25,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
 static const char *kFamilies[] = {"quantize", "product_bf16", "product_bf16x2", "product_f16", "product_f8",
                                   "product_f64", "product_f32", "product_i8x", "product_reduce", "spmm", "scale",
                                   "hessenberg", "gram", "small_eig", "lift", "residual", "spmm_f16", "spmm_f32",
-                                  "spmm_f64"};
+                                  "spmm_f64", "product_i8x_d4", "product_i8x_d5", "product_i8x_d6"};
 
 void *Workspace::get(const std::string &name, size_t bytes) {
     Buf &b = bufs[name];
@@ -278,13 +279,17 @@ ofrr_status ofrr_kernel_stats(ofrr_ctx ctx, const char *name, int64_t *launches,
         c->resolve_timers();
         *launches = c->timer.launches[f];
         *total_ms = c->timer.total_ms[f];
-        // "spmm" is every CSR product: also the per-storage families
-        if (std::string(name) == "spmm")
-            for (const char *sub : {"spmm_f16", "spmm_f32", "spmm_f64"}) {
+        // "spmm" is every CSR product: also the per-storage families;
+        // "product_i8x" every digit-plane product: also the per-digit ones
+        auto add = [&](std::initializer_list<const char *> subs) {
+            for (const char *sub : subs) {
                 const int g = c->timer.family(sub);
                 *launches += c->timer.launches[g];
                 *total_ms += c->timer.total_ms[g];
             }
+        };
+        if (std::string(name) == "spmm") add({"spmm_f16", "spmm_f32", "spmm_f64"});
+        if (std::string(name) == "product_i8x") add({"product_i8x_d4", "product_i8x_d5", "product_i8x_d6"});
         return OFRR_OK;
     });
 }
@@ -488,16 +493,17 @@ ofrr_status ofrr_block_product(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans
 }
 
 ofrr_status ofrr_block_product_sliced(ofrr_ctx ctx, const ofrr_matrix *A, int32_t trans, int32_t b,
-                                      const double *V, double *W) {
+                                      int32_t digits, const double *V, double *W) {
     return guarded(ctx, [&](Context *c) {
         OFRR_CHECK_ARG(A && V && W && b >= 1 && b <= 4096, "block_product_sliced: bad arguments");
+        OFRR_CHECK_ARG(digits == 0 || (digits >= 4 && digits <= 6), "block_product_sliced: digits 0, 4, 5 or 6");
         OFRR_CHECK_ARG(trans == 0 || trans == 1, "trans must be 0 or 1");
         validate_matrix(A, false);
         OFRR_CHECK_ARG(A->format == OFRR_DENSE_COLMAJOR && (A->dtype == OFRR_F32 || A->dtype == OFRR_F64),
                        "block_product_sliced: dense F32/F64 A");
         OFRR_HIP(hipSetDevice(c->device));
         const SlicedA sa = slice_matrix_i8(c, A, trans);
-        product_i8s(c, sa, b, V, b, W, b);
+        product_i8s(c, sa, b, V, b, W, b, nullptr, digits == 0 ? 6 : digits);
         c->sync();
         return OFRR_OK;
     });

@@ -453,7 +453,7 @@ void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, in
     double *dst = W;
     if (nsplit > 1) dst = ctx->buf<double>("i8_slabs", (size_t)nsplit * sa.m * ldw);
     {
-        KTimer tm(ctx, "product_i8x");
+        KTimer tm(ctx, digits == 6 ? "product_i8x_d6" : digits == 5 ? "product_i8x_d5" : "product_i8x_d4");
         auto go = [&](auto kern, int nt) {
             hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(nt), 0, ctx->stream, sa.planes, sa.plane_stride,
                                sa.ex, vp, v_stride, fx, kpad, sa.mpad, bpad, sa.m, b, dst, ldw, kps, ntiles, nsplit,

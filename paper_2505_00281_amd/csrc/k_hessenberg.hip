@@ -1031,69 +1031,78 @@ int32_t run_reg(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double to
 // trailing block is read and written once per panel instead of once per
 // column: about n b^2 / P element reads and writes.
 constexpr int HP_NT = 512;  // threads per workgroup of the panel sweep
-constexpr int HP_PMAX = 8;  // widest panel
+
+// value of lane l of the wave, in every lane (l a compile-time lane)
+__device__ __forceinline__ double wave_bcast(double v, int l) {
+    return lane_val(v, l);
+}
+__device__ __forceinline__ float wave_bcast(float v, int l) {
+    return lane_val(v, l);
+}
 
 // one column of the panel sweep (JJ: the column within the panel, a
-// compile-time index so the panel stays in registers)
+// compile-time index so the panel stays in registers).  The exchange is the
+// per-column sweeps' tagged words: every workgroup publishes its candidate
+// (magnitude, row) and that row's entries (the panel's, then the trailing
+// ones as they stand at the start of the panel) beside the column's tag;
+// readers poll the words they need.  No fence and no grid barrier: a
+// reader waits only for the words of the current column, and the slot
+// copy of the pivot row is what the trailing multipliers are built from,
+// so its owner may overwrite the row itself later.
 template <class T, int R, int P, int JJ>
-__device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int64_t r0, int64_t r1, double tol,
-                                          int32_t *__restrict__ piv, int32_t *__restrict__ keep,
-                                          double *__restrict__ slots, unsigned *__restrict__ bar, int *__restrict__ err,
-                                          unsigned &epoch, int &step, int &kept, double *s_cm, double *s_cr,
-                                          double *s_cv, double *s_win, T *s_Lp, int *s_keep, int64_t *s_pr) {
-    constexpr int NT = HP_NT, SW = 3 + P, NW = NT / 64;
+__device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int b, int64_t r0, int64_t r1, double tol,
+                                          const T *__restrict__ Y, int64_t ldy, int32_t *__restrict__ piv,
+                                          int32_t *__restrict__ keep, uint64_t *__restrict__ slots, int64_t slot_w,
+                                          int *__restrict__ err, int &kept, double *s_cm, int *s_cr, T *s_pan,
+                                          T *s_Lp, T *s_Tr, int *s_keep, int *s_flag) {
+    using M = typename MagT<T>::type;
+    constexpr int NT = HP_NT, NW = NT / 64;
+    constexpr int TW = NWords<T>::value, MW = NWords<M>::value, CW = MW + 1;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int G = gridDim.x, g = blockIdx.x;
+    const int j = j0 + JJ;
+    const uint32_t tag = (uint32_t)j + 1u;
+    const int buf = j & 1;
+    const int c0 = j0 + pw, ntr = b - c0;
     // local candidate: largest magnitude, first row on ties
-    T bm = (T)-1;
-    int64_t br = INT64_MAX;
-    T bv = (T)0;
-    int bq = -1;
+    M bm = (M)-1;
+    int br = INT32_MAX, bq = -1;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int64_t row = r0 + t + (int64_t)NT * q;
-        const T m = v[q][JJ] < (T)0 ? -v[q][JJ] : v[q][JJ];
+        const M m = (M)(v[q][JJ] < (T)0 ? -v[q][JJ] : v[q][JJ]);
         if (row < r1 && m > bm) {
             bm = m;
-            br = row;
-            bv = v[q][JJ];
+            br = (int)row;
             bq = q;
         }
     }
-    double cm = (double)bm, cr = br == INT64_MAX ? 9.0e18 : (double)br, cv = (double)bv;
+    M cm = bm;
+    int cr = br;
     for (int o = 32; o > 0; o >>= 1) {
-        const double qm = __shfl_xor(cm, o, 64), qr = __shfl_xor(cr, o, 64), qv = __shfl_xor(cv, o, 64);
+        const M qm = __shfl_xor(cm, o, 64);
+        const int qr = __shfl_xor(cr, o, 64);
         if (qm > cm || (qm == cm && qr < cr)) {
             cm = qm;
             cr = qr;
-            cv = qv;
         }
     }
     if (lane == 0) {
-        s_cm[wave] = cm;
+        s_cm[wave] = (double)cm;
         s_cr[wave] = cr;
-        s_cv[wave] = cv;
     }
+    if (t == 0) *s_flag = 0;
     __syncthreads();
-    double wm = s_cm[0], wr = s_cr[0], wv = s_cv[0];
+    M wm = (M)s_cm[0];
+    int wr = s_cr[0];
     for (int w = 1; w < NW; ++w)
-        if (s_cm[w] > wm || (s_cm[w] == wm && s_cr[w] < wr)) {
-            wm = s_cm[w];
+        if ((M)s_cm[w] > wm || ((M)s_cm[w] == wm && s_cr[w] < wr)) {
+            wm = (M)s_cm[w];
             wr = s_cr[w];
-            wv = s_cv[w];
         }
-    __syncthreads();
-    // publish the candidate and its row's panel entries
-    const int buf = step & 1;
-    double *my = slots + ((int64_t)buf * G + g) * SW;
-    if (t == 0) {
-        my[0] = wm;
-        my[1] = wr;
-        my[2] = wv;
-    }
-    if (bq >= 0 && (double)br == wr) {
-        // the row by a select over the compile-time indices (an indexed
-        // read would move the panel to scratch memory)
+    // the candidate row's panel entries staged in LDS by its owner (a select
+    // over the compile-time indices keeps the panel in registers)
+    if (bq >= 0 && br == wr) {
         T e[P];
 #pragma unroll
         for (int ii = 0; ii < P; ++ii) e[ii] = v[0][ii];
@@ -1102,16 +1111,32 @@ __device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int64_t 
 #pragma unroll
             for (int ii = 0; ii < P; ++ii) e[ii] = q == bq ? v[q][ii] : e[ii];
 #pragma unroll
-        for (int ii = 0; ii < P; ++ii) my[3 + ii] = (double)e[ii];
+        for (int ii = 0; ii < P; ++ii) s_pan[ii] = e[ii];
     }
-    if (!grid_barrier(bar, (unsigned)G, epoch, err)) return false;
-    ++step;
-    // the winner over all workgroups (thread h reads workgroup h's slot)
-    double hm = -2.0, hr = 9.1e18;
-    int hg = 0;
+    __syncthreads();
+    // publish: candidate words, then the row (panel entries, trailing entries)
+    uint64_t *my = slots + ((int64_t)buf * G + g) * slot_w;
+    if (t == 0) {
+        put_value<M>(my, wm, tag);
+        put_word(my + MW, (uint32_t)wr, tag);
+    }
+    if (wm >= (M)0)
+        for (int i = t; i < pw + ntr; i += NT) {
+            const T x = i < pw ? s_pan[i] : Y[(int64_t)wr * ldy + c0 + (i - pw)];
+            put_value<T>(my + CW + (int64_t)i * TW, x, tag);
+        }
+    // the winner: thread h reads workgroup h's candidate
+    M hm = (M)-2;
+    int hr = INT32_MAX, hg = 0;
     for (int h = t; h < G; h += NT) {
-        const double *ps = slots + ((int64_t)buf * G + h) * SW;
-        const double qm = ps[0], qr = ps[1];
+        uint32_t w[CW];
+        if (!get_words<CW>(slots + ((int64_t)buf * G + h) * slot_w, tag, w, err)) {
+            *s_flag = 1;
+            break;
+        }
+        M qm;
+        __builtin_memcpy(&qm, w, sizeof(M));
+        const int qr = (int)w[MW];
         if (qm > hm || (qm == hm && qr < hr)) {
             hm = qm;
             hr = qr;
@@ -1119,51 +1144,61 @@ __device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int64_t 
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
-        const double qm = __shfl_xor(hm, o, 64), qr = __shfl_xor(hr, o, 64);
-        const int qg = __shfl_xor(hg, o, 64);
+        const M qm = __shfl_xor(hm, o, 64);
+        const int qr = __shfl_xor(hr, o, 64), qg = __shfl_xor(hg, o, 64);
         if (qm > hm || (qm == hm && qr < hr)) {
             hm = qm;
             hr = qr;
             hg = qg;
         }
     }
+    __syncthreads();
     if (lane == 0) {
-        s_cm[wave] = hm;
+        s_cm[wave] = (double)hm;
         s_cr[wave] = hr;
-        s_cv[wave] = (double)hg;
+        s_cr[NW + wave] = hg;
     }
     __syncthreads();
-    if (t == 0) {
-        double xm = s_cm[0], xr = s_cr[0];
-        int xg = (int)s_cv[0];
-        for (int w = 1; w < NW; ++w)
-            if (s_cm[w] > xm || (s_cm[w] == xm && s_cr[w] < xr)) {
-                xm = s_cm[w];
-                xr = s_cr[w];
-                xg = (int)s_cv[w];
+    if (*s_flag) return false;
+    M xm = (M)s_cm[0];
+    int xr = s_cr[0], xg = s_cr[NW];
+    for (int w = 1; w < NW; ++w)
+        if ((M)s_cm[w] > xm || ((M)s_cm[w] == xm && s_cr[w] < xr)) {
+            xm = (M)s_cm[w];
+            xr = s_cr[w];
+            xg = s_cr[NW + w];
+        }
+    const bool take = (double)xm >= tol && xm > (M)0;
+    // the pivot row: panel entries and trailing entries at the panel start
+    if (take) {
+        const uint64_t *wp = slots + ((int64_t)buf * G + xg) * slot_w + CW;
+        for (int i = t; i < pw + ntr; i += NT) {
+            T x;
+            if (!get_value<T>(wp + (int64_t)i * TW, tag, x, err)) {
+                *s_flag = 1;
+                break;
             }
-        const double *ps = slots + ((int64_t)buf * G + xg) * SW;
-        for (int i = 0; i < SW; ++i) s_win[i] = ps[i];
-    }
-    __syncthreads();
-    const T wmag = (T)s_win[0];
-    const int64_t wrow = (int64_t)s_win[1];
-    const T pv = (T)s_win[2];
-    const bool take = (double)wmag >= tol && wmag > (T)0;
-    if (t == 0) {
-        s_keep[JJ] = take ? 1 : 0;
-        s_pr[JJ] = wrow;
-        for (int ii = 0; ii < P; ++ii) s_Lp[JJ * P + ii] = (T)s_win[3 + ii];
-        if (g == 0) {
-            piv[j0 + JJ] = take ? (int32_t)wrow : -1;
-            keep[j0 + JJ] = take ? 1 : 0;
+            if (i < pw)
+                s_Lp[JJ * P + i] = x;
+            else
+                s_Tr[JJ * 512 + (i - pw)] = x;
         }
     }
+    if (t == 0) {
+        s_keep[JJ] = take ? 1 : 0;
+        if (g == 0) {
+            piv[j] = take ? xr : -1;
+            keep[j] = take ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (*s_flag) return false;
     if (take) {
         ++kept;
+        const T pv = s_Lp[JJ * P + JJ];
         T w[P];
 #pragma unroll
-        for (int ii = 0; ii < P; ++ii) w[ii] = (T)s_win[3 + ii];
+        for (int ii = 0; ii < P; ++ii) w[ii] = s_Lp[JJ * P + ii];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const T x = v[q][JJ] / pv;
@@ -1173,30 +1208,27 @@ __device__ __forceinline__ bool hp_column(T (&v)[R][P], int j0, int pw, int64_t 
                 if (ii < pw) v[q][ii] = fma(-w[ii], x, v[q][ii]);
         }
     }
-    __syncthreads();
     return true;
 }
 
 template <class T, int R, int P>
 __global__ __launch_bounds__(HP_NT) void k_hess_panel(T *__restrict__ Y, int64_t ldy, int64_t n, int b, double tol,
                                                       int32_t *__restrict__ piv, int32_t *__restrict__ keep,
-                                                      int64_t per, double *__restrict__ slots,
-                                                      unsigned *__restrict__ bar, int *__restrict__ err,
-                                                      int32_t *__restrict__ kept_d) {
+                                                      int64_t per, uint64_t *__restrict__ slots, int64_t slot_w,
+                                                      int *__restrict__ err, int32_t *__restrict__ kept_d) {
     constexpr int NT = HP_NT, NW = NT / 64;
-    __shared__ T s_L[NT * P];   // a row chunk's panel entries (trailing update)
-    __shared__ T s_U[P * 512];  // multipliers of the trailing columns (b <= 512)
+    __shared__ T s_Tr[P * 512]; // pivot rows' trailing entries, then the multipliers
     __shared__ T s_Lp[P * P];   // pivot rows' panel entries
+    __shared__ T s_pan[P];      // the local candidate row's panel entries
     __shared__ int s_keep[P];
-    __shared__ int64_t s_pr[P];
-    __shared__ double s_cm[NW], s_cr[NW], s_cv[NW];
-    __shared__ double s_win[3 + P];
+    __shared__ double s_cm[NW];
+    __shared__ int s_cr[2 * NW];
+    __shared__ int s_flag;
     const int t = threadIdx.x;
     const int g = blockIdx.x;
     const int64_t r0 = (int64_t)g * per;
     const int64_t r1 = r0 + per < n ? r0 + per : n;
-    unsigned epoch = 0;
-    int step = 0, kept = 0;
+    int kept = 0;
     T v[R][P];
     for (int j0 = 0; j0 < b; j0 += P) {
         const int pw = b - j0 < P ? b - j0 : P;
@@ -1207,11 +1239,11 @@ __global__ __launch_bounds__(HP_NT) void k_hess_panel(T *__restrict__ Y, int64_t
 #pragma unroll
             for (int jj = 0; jj < P; ++jj) v[q][jj] = (row < r1 && jj < pw) ? Y[row * ldy + j0 + jj] : (T)0;
         }
-#define OFRR_HP_COL(JJ)                                                                                         \
-        if constexpr (JJ < P) {                                                                                \
-            if (JJ < pw && !hp_column<T, R, P, JJ>(v, j0, pw, r0, r1, tol, piv, keep, slots, bar, err, epoch,  \
-                                                   step, kept, s_cm, s_cr, s_cv, s_win, s_Lp, s_keep, s_pr))   \
-                return;                                                                                        \
+#define OFRR_HP_COL(JJ)                                                                                          \
+        if constexpr (JJ < P) {                                                                                 \
+            if (JJ < pw && !hp_column<T, R, P, JJ>(v, j0, pw, b, r0, r1, tol, Y, ldy, piv, keep, slots, slot_w, \
+                                                   err, kept, s_cm, s_cr, s_pan, s_Lp, s_Tr, s_keep, &s_flag))  \
+                return;                                                                                         \
         }
         OFRR_HP_COL(0)
         OFRR_HP_COL(1)
@@ -1225,57 +1257,88 @@ __global__ __launch_bounds__(HP_NT) void k_hess_panel(T *__restrict__ Y, int64_t
         const int c0 = j0 + pw;
         const int nt_ = b - c0;  // trailing columns
         if (nt_ > 0) {
-            // 2. multipliers: entry i of pivot row jj once the panel's earlier
-            // pivots have been eliminated from it
+            // 2. multipliers, in place: entry i of pivot row jj once the
+            // panel's earlier pivots have been eliminated from it
             for (int i = t; i < nt_; i += NT)
                 for (int jj = 0; jj < pw; ++jj) {
-                    T x = (T)0;
-                    if (s_keep[jj]) {
-                        x = Y[s_pr[jj] * ldy + c0 + i];
-                        for (int l = 0; l < jj; ++l)
-                            if (s_keep[l]) x = fma(-s_U[l * 512 + i], s_Lp[jj * P + l], x);
-                    }
-                    s_U[jj * 512 + i] = x;
+                    if (!s_keep[jj]) continue;
+                    T x = s_Tr[jj * 512 + i];
+                    for (int l = 0; l < jj; ++l)
+                        if (s_keep[l]) x = fma(-s_Tr[l * 512 + i], s_Lp[jj * P + l], x);
+                    s_Tr[jj * 512 + i] = x;
                 }
-            // every workgroup has read the pivot rows before any is updated
-            if (!grid_barrier(bar, (unsigned)gridDim.x, epoch, err)) return;
-            // 3. trailing update, one chunk of NT rows at a time (the chunk
-            // index is a loop variable: the panel rows are picked by a select
-            // over the compile-time indices, so they stay in registers)
+            __syncthreads();
+            // 3. the panel's columns are final: stored first, so the trailing
+            // update reads each row's panel entries with the row and the
+            // panel registers are free for loads in flight.  A wave takes
+            // rows, its lanes 64 consecutive trailing columns (one coalesced
+            // access per row segment); a lane keeps its columns' multipliers
+            // in registers, and the row's panel entries are read by the
+            // first lanes and broadcast across the wave.
+#pragma unroll
             for (int q = 0; q < R; ++q) {
-                T e[P];
+                const int64_t row = r0 + t + (int64_t)NT * q;
+                if (row < r1)
 #pragma unroll
-                for (int jj = 0; jj < P; ++jj) e[jj] = v[0][jj];
-#pragma unroll
-                for (int qq = 1; qq < R; ++qq)
-#pragma unroll
-                    for (int jj = 0; jj < P; ++jj) e[jj] = qq == q ? v[qq][jj] : e[jj];
-#pragma unroll
-                for (int jj = 0; jj < P; ++jj) s_L[t * P + jj] = e[jj];
-                __syncthreads();
-                const int64_t rb = r0 + (int64_t)NT * q;
-                for (int item = t; item < NT * nt_; item += NT) {
-                    const int rr = item / nt_, i = item - rr * nt_;
-                    const int64_t row = rb + rr;
-                    if (row >= r1) continue;
-                    T x = Y[row * ldy + c0 + i];
-                    for (int l = 0; l < pw; ++l)
-                        if (s_keep[l]) x = fma(-s_U[l * 512 + i], s_L[rr * P + l], x);
-                    Y[row * ldy + c0 + i] = x;
-                }
-                __syncthreads();
+                    for (int jj = 0; jj < P; ++jj)
+                        if (jj < pw) Y[row * ldy + j0 + jj] = v[q][jj];
             }
-        }
-        // the panel's columns are final
+            __syncthreads();
+            int kk[P];
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int64_t row = r0 + t + (int64_t)NT * q;
-            if (row < r1)
+            for (int l = 0; l < P; ++l) kk[l] = l < pw ? s_keep[l] : 0;
+            const int lane = t & 63, wave = t >> 6;
+            const int nrows = (int)(r1 - r0 > 0 ? r1 - r0 : 0);
+            constexpr int UR = 4;  // rows in flight per lane
+            for (int cb = 0; cb < nt_; cb += 64) {
+                const int i = cb + lane;
+                const bool on = i < nt_;
+                T u[P];
 #pragma unroll
-                for (int jj = 0; jj < P; ++jj)
-                    if (jj < pw) Y[row * ldy + j0 + jj] = v[q][jj];
+                for (int l = 0; l < P; ++l) u[l] = on && kk[l] ? s_Tr[l * 512 + i] : (T)0;
+                T *col = Y + c0 + (on ? i : 0);
+                const T *pan = Y + j0 + (lane < pw ? lane : 0);
+                int rr = wave;
+                for (; rr + (UR - 1) * NW < nrows; rr += UR * NW) {
+                    T x[UR], lv[UR];
+#pragma unroll
+                    for (int z = 0; z < UR; ++z) {
+                        const int64_t row = r0 + rr + z * NW;
+                        x[z] = on ? col[row * ldy] : (T)0;
+                        lv[z] = pan[row * ldy];
+                    }
+#pragma unroll
+                    for (int z = 0; z < UR; ++z)
+#pragma unroll
+                        for (int l = 0; l < P; ++l)
+                            if (kk[l]) x[z] = fma(-u[l], wave_bcast(lv[z], l), x[z]);
+                    if (on)
+#pragma unroll
+                        for (int z = 0; z < UR; ++z) col[(r0 + rr + z * NW) * ldy] = x[z];
+                }
+                for (; rr < nrows; rr += NW) {
+                    const int64_t row = r0 + rr;
+                    T x = on ? col[row * ldy] : (T)0;
+                    const T lv = pan[row * ldy];
+#pragma unroll
+                    for (int l = 0; l < P; ++l)
+                        if (kk[l]) x = fma(-u[l], wave_bcast(lv, l), x);
+                    if (on) col[row * ldy] = x;
+                }
+            }
+            __syncthreads();
+        } else {
+            // the panel's columns are final
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int64_t row = r0 + t + (int64_t)NT * q;
+                if (row < r1)
+#pragma unroll
+                    for (int jj = 0; jj < P; ++jj)
+                        if (jj < pw) Y[row * ldy + j0 + jj] = v[q][jj];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (g == 0 && t == 0) *kept_d = kept;
 }
@@ -1287,14 +1350,16 @@ int32_t run_panel(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double 
     const int G = (int)std::min<int64_t>(cus, (n + HP_NT - 1) / HP_NT);
     const int64_t per = (n + G - 1) / G;
     const int R = (int)((per + HP_NT - 1) / HP_NT);
-    // word buffer: [0] error flag and kept count, [1] barrier counter, then
-    // the candidate slots (2 x G x (3 + P) doubles)
-    const int64_t nwords = 2 + (int64_t)2 * G * (3 + HP_PMAX);
+    // word buffer: [0] error flag and kept count, then per column parity and
+    // workgroup one slot: the candidate (magnitude words, row) and a row of
+    // up to b entries
+    constexpr int TW = NWords<T>::value, CW = NWords<typename MagT<T>::type>::value + 1;
+    const int64_t slot_w = CW + (int64_t)b * TW;
+    const int64_t nwords = 1 + (int64_t)2 * G * slot_w;
     uint64_t *words = wb.get(ctx, nwords);
     int *err = reinterpret_cast<int *>(words);
     int32_t *kept_d = err + 1;
-    unsigned *bar = reinterpret_cast<unsigned *>(words + 1);
-    double *slots = reinterpret_cast<double *>(words + 2);
+    uint64_t *slots = words + 1;
     // panel width eight (eight FP64 rows per thread: the 8 x 8 panel takes
     // the whole register budget of two waves per SIMD, with no spill)
     const void *kern = R <= 1   ? (const void *)k_hess_panel<T, 1, 8>
@@ -1311,7 +1376,7 @@ int32_t run_panel(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double 
     hipLaunchKernelGGL(k_hess_reset, dim3((unsigned)std::min<int64_t>(256, (nwords + 255) / 256)), dim3(256), 0,
                        ctx->stream, words, nwords);
     OFRR_HIP(hipGetLastError());
-    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, (void *)&per, &slots, &bar, &err, &kept_d};
+    void *args[] = {&Y, &ldy, &n, &b, &tol, &piv, &keep, (void *)&per, &slots, (void *)&slot_w, &err, &kept_d};
     {
         KTimer tm(ctx, "hessenberg");
         OFRR_HIP(launch_resident(kern, dim3(G), dim3(HP_NT), args, 0, ctx->stream));

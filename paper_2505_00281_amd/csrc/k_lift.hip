@@ -195,7 +195,11 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
         }
     }
     __syncthreads();
-    const int64_t rowA = (int64_t)blockIdx.x * 64 + 16 * wave + cl;  // this lane's operand row
+    // the workgroup lifts 64-row blocks blockIdx.x, + gridDim.x, ... with the
+    // coefficients staged once (a grid of at most a few workgroups per CU)
+    const int64_t nblk = (n + 63) / 64;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t rowA = blk * 64 + 16 * wave + cl;  // this lane's operand row
     const bool rok = rowA < n;
     const int ntile = (nc + 15) / 16;
     lf_f64x4_t acc1[8], acc2[8];
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
         }
     }
     // outputs, and the residual partials of this 64-row block
-    const int64_t rbase = (int64_t)blockIdx.x * 64 + 16 * wave + g;  // + 4 r
+    const int64_t rbase = blk * 64 + 16 * wave + g;  // + 4 r
     double r2[8], x2[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) r2[q] = x2[q] = 0.0;
@@ -307,9 +311,11 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
         if (t < nc) {
             const double a = (red[0][0][t] + red[0][1][t]) + (red[0][2][t] + red[0][3][t]);
             const double c = (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
-            res2[(int64_t)blockIdx.x * nc + t] = a;
-            xn2[(int64_t)blockIdx.x * nc + t] = c;
+            res2[blk * nc + t] = a;
+            xn2[blk * nc + t] = c;
         }
+        __syncthreads();  // red is rewritten by the next block
+    }
     }
 }
 
@@ -577,7 +583,12 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
                             lds_set.insert({ctx->device, kern});
                         }
                         const size_t shmem = (size_t)((b + 15) / 16 * 16) * LF_LDK * sizeof(double);
-                        hipLaunchKernelGGL(kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), shmem, ctx->stream,
+                        // at most two workgroups per CU (what its registers and
+                        // LDS hold at once), each over several 64-row blocks
+                        const int64_t nblk = (n + 63) / 64;
+                        const int64_t cap = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
+                        const unsigned gl = (unsigned)(nblk < cap ? nblk : cap);
+                        hipLaunchKernelGGL(kernel, dim3(gl), dim3(256), shmem, ctx->stream,
                                            (const TI *)V, ldv, (const TI *)W, ldw, n, b, nc, Y, ldy, theta,
                                            (TO *)X, (TO *)AX, ldx, res2, xn2);
                     };

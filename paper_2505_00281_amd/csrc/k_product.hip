@@ -254,6 +254,8 @@ __device__ __forceinline__ double spmm_round(double x) {
     return x;
 }
 
+constexpr int SPMM_PASSES = 8;  // row groups per workgroup of the scaled Chebyshev step
+
 __device__ __forceinline__ int64_t xcd_row_block(int64_t bid, int64_t G) {
     const int64_t q = G / 8, r = G % 8, x = bid % 8, k = bid / 8;
     return x * q + (x < r ? x : r) + k;
@@ -372,9 +374,12 @@ __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
     const int L = 1 << lanes_log2;
     const int rows_per = 256 >> lanes_log2;
     const int64_t blk = xcd_row_block(blockIdx.x, gridDim.x);
-    const int64_t row = blk * rows_per + (t >> lanes_log2);
     const int li = t & (L - 1);
-    if (row < n_rows) {
+    // SPMM_PASSES row groups per workgroup: the scale setup and the key
+    // merge (one global atomic per column) are shared by all of them
+    for (int pass = 0; pass < SPMM_PASSES; ++pass) {
+        const int64_t row = (blk * SPMM_PASSES + pass) * rows_per + (t >> lanes_log2);
+        if (row >= n_rows) break;
         int64_t e0 = rp[row], e1 = rp[row + 1];
         if (e0 < 0) e0 = 0;
         if (e1 > nnz) e1 = nnz;
@@ -447,6 +452,8 @@ __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
             if (km[j]) atomicMax(cmax_out + (blockIdx.x % CM_COPIES) * 512 + j, km[j]);
     }
 }
+
+
 
 // CSR structure check: row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
 // every column index in [0, n_cols).  Sets *bad to a nonzero code.
@@ -637,7 +644,7 @@ bool spmm_cheb_scaled(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype 
     if (b > 512) return false;
     KTimer tm(ctx, phase == OFRR_F64 ? "spmm_f64" : phase == OFRR_F32 ? "spmm_f32" : "spmm_f16");
     const int lg = spmm_lanes_log2(b);
-    const int64_t rows_per = 256 >> lg;
+    const int64_t rows_per = (int64_t)(256 >> lg) * SPMM_PASSES;
     const int64_t G = (A->rows + rows_per - 1) / rows_per;
     OFRR_CHECK_ARG(G < ((int64_t)1 << 31), "spmm: too many rows");
     const int rp = round_prev ? 1 : 0;

@@ -114,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.ofrr_quantize.argtypes = [vp, ctypes.c_int, i64, vp, vp]
     lib.ofrr_quantize_fp8_blocks.argtypes = [vp, i64, i64, vp, i64, vp, vp]
     lib.ofrr_block_product.argtypes = [vp, P(Matrix), i32, i32, ctypes.c_int, vp, vp]
-    lib.ofrr_block_product_sliced.argtypes = [vp, P(Matrix), i32, i32, vp, vp]
+    lib.ofrr_block_product_sliced.argtypes = [vp, P(Matrix), i32, i32, i32, vp, vp]
     lib.ofrr_block_product_fp8.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, vp]
     lib.ofrr_hessenberg.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
     lib.ofrr_hessenberg_noalloc.argtypes = [vp, ctypes.c_int, i64, i32, vp, i64, dbl, vp, vp, P(i32)]
@@ -447,9 +447,10 @@ class Context:
                                                 _DTYPES[v_dtype], _ptr(V), _ptr(W)))
         return W
 
-    def block_product_sliced(self, A, V: torch.Tensor, trans: bool = False):
-        """W = op(A) V (FP64, row-major) from exact INT8 digit-plane products;
-        A dense F32/F64."""
+    def block_product_sliced(self, A, V: torch.Tensor, trans: bool = False, digits: int = 6):
+        """W = op(A) V (FP64, row-major) from exact INT8 digit-plane products
+        with `digits` (4, 5 or 6) signed 7-bit digits per side; A dense
+        F32/F64."""
         mat = A if isinstance(A, Matrix) else dense_matrix(A)
         self._rows(V, mat.rows if trans else mat.cols, "V")
         self._mat(mat)
@@ -458,7 +459,7 @@ class Context:
         b = V.shape[1]
         rows = mat.cols if trans else mat.rows
         W = torch.empty((rows, b), dtype=torch.float64, device=self.device)
-        self._check(self.lib.ofrr_block_product_sliced(self.h, ctypes.byref(mat), int(trans), b,
+        self._check(self.lib.ofrr_block_product_sliced(self.h, ctypes.byref(mat), int(trans), b, int(digits),
                                                        _ptr(V), _ptr(W)))
         return W
 
