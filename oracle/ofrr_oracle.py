@@ -25,6 +25,11 @@ What the oracle computes
 * For the SVD: alternating subspaces U_s = span(A V_{s-1}),
   V_s = span(A^T U_s) and the classical two-sided projection (Alg.
   "Rayleigh-Ritz Projection for SVD"), `subspace_svd`.
+* For a real non-symmetric A the Ritz values are complex (Sec. 3.1):
+  `subspace_eig_general` runs the same iteration with the library's
+  non-symmetric eigensolver on Q^T A Q, or, on a Hessenberg basis, on the
+  Cholesky-reduced pencil (V^T A V, V^T V), restarting from a real basis
+  of all Ritz vectors.
 * The pieces the GPU path computes step by step also have their own
   reference here: the Hessenberg process (Sec. 4.2), the symmetric
   definite pencil (eq. (geig), Alg. "Orthogonalization-Free Rayleigh-Ritz
@@ -44,6 +49,11 @@ Readings of the paper taken here (each also listed in the design notes):
 * Sign of a returned vector: unit 2-norm and its entry of largest
   magnitude (first index on ties) positive; for the SVD the sign is fixed
   on v and u flips with it.
+* Non-symmetric A: wanted values are those of largest modulus, ties
+  broken by larger real part, then larger imaginary part; a complex Ritz
+  vector is scaled to unit 2-norm with its largest-modulus entry (first on
+  ties) real and positive; a conjugate pair restarts as its real and
+  imaginary parts.
 """
 from __future__ import annotations
 
@@ -699,6 +709,138 @@ def subspace_svd_normal(A, V0, k: int, outer: int = 10, tol: float | None = None
     res = svd_residuals(A, s, U, V, an)
     Vn, Un = normalize_signs(V, U)
     return SvdResult(s.copy(), Un, Vn, res, s.copy(), Vn, r.iters)
+
+
+# ---------------------------------------------------------------------------
+# General (non-symmetric) real A (Sec. 3.1: for A in R^{n x n} the Galerkin
+# condition admits complex Ritz values; with a basis U that need not be
+# orthonormal it becomes the pencil U^* A U y = lambda U^* U y, eq. (geig),
+# Alg. "Orthogonalization-Free Rayleigh-Ritz Projection"; for a real U the
+# conjugate transpose is the transpose).  The k values of largest modulus
+# are wanted.
+# ---------------------------------------------------------------------------
+
+def general_order(theta):
+    """Order of complex Ritz values: modulus descending, then real part
+    descending, then imaginary part descending (of a conjugate pair the
+    member with positive imaginary part comes first)."""
+    th = np.asarray(theta)
+    return np.lexsort((-th.imag, -th.real, -np.abs(th)))
+
+
+def phase_normalize(x):
+    """A complex vector scaled to unit 2-norm with its entry of largest
+    modulus (the first on ties) real and positive."""
+    x = np.asarray(x, dtype=np.complex128)
+    i = int(np.argmax(np.abs(x)))
+    nrm = np.linalg.norm(x)
+    y = x * (np.conj(x[i]) / (abs(x[i]) * nrm))
+    y[i] = abs(x[i]) / nrm  # exactly real
+    return y
+
+
+def general_real_basis(Z, theta):
+    """Real columns spanning the space of the complex columns of Z (ordered
+    as theta, the two members of a conjugate pair adjacent): a real value
+    contributes Re z, a pair contributes Re z and Im z of its first member
+    (the second member's column is the conjugate: it adds nothing)."""
+    cols = []
+    j = 0
+    b = Z.shape[1]
+    while j < b:
+        if theta[j].imag != 0.0 and j + 1 < b and theta[j + 1] == np.conj(theta[j]):
+            cols += [Z[:, j].real, Z[:, j].imag]
+            j += 2
+        else:
+            cols.append(Z[:, j].real)
+            j += 1
+    return np.stack(cols, axis=1)
+
+
+def general_pencil_eig(B, M):
+    """Eigenpairs of the pencil B y = theta M y with B = U^T A U real and
+    non-symmetric and M = U^T U symmetric positive definite (eq. (geig)).
+    Reduction with the Cholesky factor M = L L^T: C = L^{-1} B L^{-T} (a
+    real non-symmetric matrix with the pencil's eigenvalues), C z = theta z
+    by the library's non-symmetric eigensolver, y = L^{-T} z.  Returns
+    (theta ordered by general_order, Y) with y^H M y = 1, so that U y has
+    unit 2-norm."""
+    B = np.asarray(B, dtype=np.float64)
+    L = cholesky(0.5 * (np.asarray(M, dtype=np.float64) + np.asarray(M, dtype=np.float64).T))
+    T = sla.solve_triangular(L, B, lower=True)              # L^{-1} B
+    C = sla.solve_triangular(L, T.T, lower=True).T           # (L^{-1} (L^{-1} B)^T)^T = L^{-1} B L^{-T}
+    theta, Z = np.linalg.eig(C)
+    o = general_order(theta)
+    theta, Z = theta[o], Z[:, o]
+    Z = Z / np.linalg.norm(Z, axis=0)[None, :]
+    Y = sla.solve_triangular(L.T, Z, lower=False)
+    return theta, Y
+
+
+@dataclass
+class GeneralResult:
+    theta: np.ndarray      # complex, the k wanted Ritz values (general_order)
+    X: np.ndarray          # complex n x k Ritz vectors (phase_normalize)
+    resid: np.ndarray      # ||A x - theta x|| / (||x|| anorm)
+    theta_all: np.ndarray  # all b Ritz values of the last projection
+    iters: int
+
+
+def subspace_eig_general(A, X0, k: int, degree: int = 1, outer: int = 20, tol: float | None = None,
+                         anorm: float | None = None, basis: str = "mgs2", hess_tol: float = 1e-300,
+                         max_outer: int = 100000):
+    """Subspace iteration for a real non-symmetric A with restart from all
+    Ritz vectors (Sec. 2), `degree` products per outer iteration.
+
+    basis='mgs2': each product is followed by MGS2 and the projection is
+    the classical B = Q^T A Q with the library's eigensolver.
+    basis='hessenberg': each product is followed by the Hessenberg process
+    (Sec. 4.2, every column kept) and the projection is the pencil
+    (V^T A V, V^T V) of the orthogonalization-free form
+    (general_pencil_eig).  In exact arithmetic both give the same Ritz
+    pairs (Sec. 3.1: they depend on the subspace only).
+
+    The restart block is the real basis (general_real_basis) of all Ritz
+    vectors.  Same-step mode when tol is None; otherwise iterate until the
+    k wanted residuals are <= tol.  anorm (None -> largest Ritz modulus)
+    normalises the residuals."""
+    op = as_op(A)
+    X = np.array(X0, dtype=np.float64, order="F", copy=True)
+    if basis not in ("mgs2", "hessenberg"):
+        raise ValueError(basis)
+
+    def stab(Y):
+        if basis == "mgs2":
+            return mgs2(Y)[0]
+        Q, _, keep = hessenberg(Y, hess_tol, "f64")
+        if not (keep == 1).all():
+            raise np.linalg.LinAlgError("the Hessenberg process dropped a column")
+        return Q
+
+    it = 0
+    limit = outer if tol is None else max_outer
+    while it < limit:
+        Q = X
+        for _ in range(degree):
+            Q = stab(op.apply(Q))
+        AQ = op.apply(Q)
+        if basis == "mgs2":
+            theta, Z = np.linalg.eig(Q.T @ AQ)
+            o = general_order(theta)
+            theta, Z = theta[o], Z[:, o]
+        else:
+            theta, Z = general_pencil_eig(Q.T @ AQ, Q.T @ Q)
+        Xc = Q @ Z
+        AXc = AQ @ Z
+        it += 1
+        an = anorm if anorm else float(np.max(np.abs(theta)))
+        r = np.linalg.norm(AXc[:, :k] - Xc[:, :k] * theta[None, :k], axis=0) / \
+            np.linalg.norm(Xc[:, :k], axis=0) / an
+        X = np.asfortranarray(general_real_basis(Xc, theta))
+        if tol is not None and np.all(r <= tol):
+            break
+    Xk = np.stack([phase_normalize(Xc[:, j]) for j in range(k)], axis=1)
+    return GeneralResult(theta[:k].copy(), Xk, r, theta.copy(), it)
 
 
 # ---------------------------------------------------------------------------

@@ -14,6 +14,7 @@ from .generators import (  # noqa: F401
     laplacian_2d_eigenvalues,
     uniform_start,
     batched_sizes,
+    general_prescribed,
     kernel_points,
     kernel_subset,
     gaussian_kernel,

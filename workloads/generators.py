@@ -114,6 +114,32 @@ def laplacian_2d_eigenvalues(N: int) -> np.ndarray:
     return np.sort((t[:, None] + t[None, :]).ravel())
 
 
+def general_prescribed(real_eigs, complex_pairs, seed: int, nonnormal: float = 0.0,
+                       dtype=torch.float64, device: str | torch.device = "cpu") -> torch.Tensor:
+    """Real non-symmetric A = S D S^-1 with D block diagonal: the given real
+    eigenvalues, and for each (a, b) in complex_pairs a 2 x 2 block
+    [[a, b], [-b, a]] (eigenvalues a +- ib).  S = Q (I + nonnormal N) with Q
+    Haar orthogonal and N strictly upper triangular N(0,1) / sqrt(n) (S = Q:
+    a normal matrix).  Assembled in FP64, column-major."""
+    reals = np.asarray(real_eigs, dtype=np.float64)
+    pairs = np.asarray(complex_pairs, dtype=np.float64).reshape(-1, 2)
+    n = reals.size + 2 * pairs.shape[0]
+    D = np.zeros((n, n))
+    i = 0
+    for a, b in pairs:
+        D[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
+        i += 2
+    D[np.arange(i, n), np.arange(i, n)] = reals
+    q = haar_orthogonal(n, seed).numpy()
+    if nonnormal:
+        N = np.triu(_normal((n, n), seed + 1), 1) / np.sqrt(n)
+        S = q @ (np.eye(n) + nonnormal * N)
+    else:
+        S = q
+    A = torch.from_numpy(S @ D) @ torch.linalg.inv(torch.from_numpy(S))
+    return A.to(dtype).T.contiguous().T.to(device)
+
+
 def kernel_points(n: int, seed: int, d: int = 2) -> np.ndarray:
     """n points drawn uniformly from the square (cube) of side sqrt(n)."""
     return rng(seed).random((n, d)) * np.sqrt(n)
