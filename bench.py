@@ -310,9 +310,11 @@ def bench_laplacian(args):
     steps = max(1, min(args.steps, 2))
     res, ms = _timed_calls(lambda: ctx.eig_partial(mat, k, b, which="smallest", plan=ofrr.make_plan(**mixed_kw),
                                                    X0=X0), steps, max(0, min(args.warmup, 1)), "laplacian mixed")
-    fres, fms = _timed_calls(lambda: ctx.eig_partial(mat, k, b, which="smallest",
-                                                     plan=ofrr.make_plan(basis_dtype="f64", **common), X0=X0),
-                             1, 0, "laplacian fp64")
+    fres, fms = None, None
+    if not args.no_fp64_form:
+        fres, fms = _timed_calls(lambda: ctx.eig_partial(mat, k, b, which="smallest",
+                                                         plan=ofrr.make_plan(basis_dtype="f64", **common), X0=X0),
+                                 1, 0, "laplacian fp64")
 
     def count(r):
         th = r.evals.cpu().numpy()
@@ -321,9 +323,9 @@ def bench_laplacian(args):
         return int(((res_ <= TOL) & (rel <= 1e-10)).sum()), float(rel.max()), float(res_.max())
 
     acc = [count(r) for r in res]
-    facc = count(fres[-1])
     value = sum(a[0] for a in acc) / (ms * 1e-3 * len(res))
-    fvalue = facc[0] / (fms * 1e-3)
+    facc = count(fres[-1]) if fres else None
+    fvalue = facc[0] / (fms * 1e-3) if fres else None
     ctx.kernel_stats_reset()
     ctx.eig_partial(mat, k, b, which="smallest", plan=ofrr.make_plan(profile=True, **mixed_kw), X0=X0)
     torch.cuda.synchronize()
@@ -355,15 +357,18 @@ def bench_laplacian(args):
     # CPU baseline: a bounded sample, one outer iteration of the oracle with a
     # degree-10 filter (10 CSR products, MGS2 after each, Rayleigh-Ritz),
     # scaled per product to the products the FP64 form needs
-    t = time.time()
-    O.subspace_eig((rp, ci, v.astype(np.float64)), X0.numpy(), k, which="smallest", filt="chebyshev", degree=10,
-                   lo=float(ev[b]), hi=8.0, outer=1)
-    per_prod = (time.time() - t) / 10
-    prods_needed = fres[-1].info["products"]
-    cpu = {"value": k / (per_prod * prods_needed), "unit": "Ritz pairs/s", "cores": int(_cores()), "kind": "oracle",
-           "sample": (f"one outer iteration of the oracle with a degree-10 filter (10 CSR products with MGS2 after "
-                      f"each, Rayleigh-Ritz) on the same matrix, {per_prod:.2f}s per product, scaled to the "
-                      f"{prods_needed} products the FP64 form needs (projected)")}
+    cpu = None
+    if not args.no_oracle:
+        t = time.time()
+        O.subspace_eig((rp, ci, v.astype(np.float64)), X0.numpy(), k, which="smallest", filt="chebyshev",
+                       degree=10, lo=float(ev[b]), hi=8.0, outer=1)
+        per_prod = (time.time() - t) / 10
+        prods_needed = (fres or res)[-1].info["products"]
+        cpu = {"value": k / (per_prod * prods_needed), "unit": "Ritz pairs/s", "cores": int(_cores()),
+               "kind": "oracle",
+               "sample": (f"one outer iteration of the oracle with a degree-10 filter (10 CSR products with MGS2 "
+                          f"after each, Rayleigh-Ritz) on the same matrix, {per_prod:.2f}s per product, scaled to "
+                          f"the {prods_needed} products the FP64 form needs (projected)")}
     ctx.close()
     return {"metric": "Ritz pairs/sec at residual <=1e-8, mixed vs FP64 form, 1 MI355X; % roofline",
             "value": value, "unit": "Ritz pairs/s", "n_gpus": 1, "steps": len(res), "warmup": 1, "ms_per_step": ms,
@@ -377,8 +382,8 @@ def bench_laplacian(args):
                          "max_resid": max(a[2] for a in acc),
                          "criterion": "residual <= 1e-8 and eigenvalue within 1e-10 (relative) of the closed form "
                                       "4 - 2cos(p pi/1025) - 2cos(q pi/1025) (exact for the stored integer matrix)"},
-            "fp64_form": {"value": fvalue, "ms_per_step": fms, "iters": fres[-1].info["iters"],
-                          "n_converged": facc[0]},
+            "fp64_form": ({"value": fvalue, "ms_per_step": fms, "iters": fres[-1].info["iters"],
+                           "n_converged": facc[0]} if fres else None),
             "speedup_vs_fp64_form": value / fvalue if fvalue else None,
             "roofline": roofline, "cpu_baseline": cpu}
 
@@ -438,9 +443,9 @@ def bench_batched(args):
             nconv += int(ok.sum())
         return nconv, worst_rel, worst_res, worst_closed
     acc = [count(r) for r in res]
-    facc = count(fres[-1])
     value = sum(a[0] for a in acc) / (ms * 1e-3 * len(res))
-    fvalue = facc[0] / (fms * 1e-3)
+    facc = count(fres[-1]) if fres else None
+    fvalue = facc[0] / (fms * 1e-3) if fres else None
     # roofline of the grouped BF16 product over all 512 problems (its first
     # launch in the call, timed with HIP events on the library's stream)
     nn = sizes.astype(np.float64)
