@@ -269,6 +269,36 @@ ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
                              const ofrr_plan *plan, const double *V0, double *sigma,
                              double *U, double *V, double *resid, ofrr_info *info);
 
+/* k eigenpairs of largest modulus of a real non-symmetric A (rows == cols
+ * == n, dense or CSR) by the same subspace iteration: products A V, the
+ * power filter, the Hessenberg process, and the orthogonalization-free
+ * projection with complex Ritz values (Sec. 3.1: the Galerkin condition
+ * on a basis that is not orthonormal gives the pencil V^T A V y =
+ * lambda V^T V y, eq. (geig); Alg. "Orthogonalization-Free Rayleigh-Ritz
+ * Projection").  The pencil is solved in FP64 on the GPU by Cholesky
+ * reduction and a Francis double-shift QR iteration; the restart block is
+ * the real basis of all Ritz vectors (a conjugate pair contributes the real
+ * and imaginary parts of one member).
+ *   X0        n x basis FP64 start block (column-major) or NULL.
+ *   evals_re, evals_im  k FP64: modulus descending, then real part, then
+ *             imaginary part descending (of a conjugate pair the member
+ *             with positive imaginary part first).  A pair cut at k keeps
+ *             its first member only.
+ *   evecs_re, evecs_im  n x k FP64 column-major: the real and imaginary
+ *             parts of unit-2-norm vectors whose entry of largest modulus
+ *             (first on ties) is real and positive.
+ *   resid     k FP64: ||A x - lambda x||_2 / anorm, in FP64 from A as
+ *             stored (anorm = plan.anorm, or the largest Ritz modulus).
+ * plan: basis_dtype F64, BF16 or F16 (refine as for ofrr_eig_partial: a
+ * split-BF16 middle phase for refine 2 with dense A, an FP32 one for CSR,
+ * and the FP64 tail), filter OFRR_POWER, stab Hessenberg, projection OFRR,
+ * gram_accum F64, qr_dtype and matvec_round unset; OFRR_ERR_UNSUPPORTED
+ * otherwise.  OFRR_ERR_NUMERIC if the projected mass matrix is not positive
+ * definite or the small eigensolver does not converge. */
+ofrr_status ofrr_eig_general(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis, const ofrr_plan *plan,
+                             const double *X0, double *evals_re, double *evals_im, double *evecs_re,
+                             double *evecs_im, double *resid, ofrr_info *info);
+
 /* nprob independent symmetric eigenproblems (dense, each with its own n),
  * the same k, basis and plan.  As[p], X0s (may be NULL), evals[p],
  * evecs[p], resid[p] are per-problem pointers held in HOST arrays of length
@@ -473,6 +503,21 @@ ofrr_status ofrr_project(ofrr_ctx ctx, int64_t n, int32_t b, ofrr_dtype v_dtype,
  * the number of retained directions. */
 ofrr_status ofrr_pencil_eig(ofrr_ctx ctx, int32_t b, const double *H, const double *G,
                             ofrr_which which, double *theta, double *Y, int32_t *rank);
+
+/* Non-symmetric pencil H y = theta G y (eq. (geig) for a real
+ * non-symmetric A, Sec. 3.1), FP64 on the GPU: Cholesky G = L L^T,
+ * C = L^{-1} H L^{-T}, Householder reduction of C to Hessenberg form,
+ * Francis double-shift QR iteration to real Schur form, eigenvectors by
+ * back substitution, y = L^{-T} z with unit z.  H, G: b x b column-major
+ * (G symmetric positive definite; its symmetric part is used).
+ *   theta_re, theta_im  b: the order of ofrr_eig_general.
+ *   Y   b x b column-major, packed real: a real theta's column is y; a
+ *       conjugate pair (slots j, j+1, theta_im[j] > 0) holds Re y and Im y
+ *       of the member with positive imaginary part.  y^H G y = 1.
+ * OFRR_ERR_NUMERIC if G is not positive definite or the iteration does not
+ * converge (30 max(10, b) double-shift steps). */
+ofrr_status ofrr_pencil_eig_general(ofrr_ctx ctx, int32_t b, const double *H, const double *G, double *theta_re,
+                                    double *theta_im, double *Y);
 
 /* The SVD pencil of Sec. 3.2 for B (k1 x k2), MU (k1 x k1), MV (k2 x k2):
  * sigma (min(k1,k2), descending, the positive eigenvalues), Y (k1 x

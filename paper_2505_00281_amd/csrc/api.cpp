@@ -21,6 +21,9 @@ ofrr_status svd_normal_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32
 ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              const ofrr_plan *plan, const double *V0, double *sigma, double *U,
                              double *V, double *resid, ofrr_info *info);
+ofrr_status eig_general_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis, const ofrr_plan *plan,
+                             const double *X0, double *evals_re, double *evals_im, double *evecs_re,
+                             double *evecs_im, double *resid, ofrr_info *info);
 
 static const char *kFamilies[] = {"quantize", "product_bf16", "product_bf16x2", "product_f16", "product_f8",
                                   "product_f64", "product_f32", "product_i8x", "product_reduce", "spmm", "scale",
@@ -327,6 +330,34 @@ ofrr_status ofrr_eig_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int3
     });
 }
 
+ofrr_status ofrr_eig_general(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis, const ofrr_plan *plan,
+                             const double *X0, double *evals_re, double *evals_im, double *evecs_re,
+                             double *evecs_im, double *resid, ofrr_info *info) {
+    return guarded(ctx, [&](Context *c) {
+        validate_matrix(A, true);
+        validate_plan(plan);
+        OFRR_CHECK_ARG(k >= 1 && k <= basis && basis <= A->rows, "need 1 <= k <= basis <= n");
+        OFRR_CHECK_ARG(basis <= 512, "basis must be <= 512");
+        OFRR_CHECK_ARG(evals_re && evals_im && evecs_re && evecs_im && resid, "output pointers must not be NULL");
+        OFRR_CHECK_ARG(plan->basis_dtype == OFRR_F64 || plan->basis_dtype == OFRR_BF16 ||
+                           plan->basis_dtype == OFRR_F16,
+                       "eig_general: basis F64, BF16 or F16");
+        if (plan->filter != OFRR_POWER) fail(OFRR_ERR_UNSUPPORTED, "eig_general: power filter only");
+        if (plan->stab != 0 || plan->projection != 0)
+            fail(OFRR_ERR_UNSUPPORTED, "eig_general: Hessenberg stabilisation and the OFRR projection only");
+        if (plan->gram_accum != OFRR_ACC_F64)
+            fail(OFRR_ERR_UNSUPPORTED, "eig_general: the projections are accumulated in FP64 (gram_accum F64)");
+        if (plan->qr_dtype >= 0 || plan->matvec_round >= 0)
+            fail(OFRR_ERR_UNSUPPORTED, "eig_general: qr_dtype and matvec_round are not used");
+        if (A->format == OFRR_DENSE_COLMAJOR && plan->basis_dtype != OFRR_F64)
+            OFRR_CHECK_ARG(A->rows < (int64_t)1 << 31, "dense reduced-precision path needs n < 2^31");
+        OFRR_HIP(hipSetDevice(c->device));
+        c->profile = plan->profile != 0;
+        if (A->format == OFRR_CSR) check_csr(c, A);
+        return eig_general_impl(c, A, k, basis, plan, X0, evals_re, evals_im, evecs_re, evecs_im, resid, info);
+    });
+}
+
 ofrr_status ofrr_svd_partial(ofrr_ctx ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              const ofrr_plan *plan, const double *V0, double *sigma, double *U,
                              double *V, double *resid, ofrr_info *info) {
@@ -601,6 +632,17 @@ ofrr_status ofrr_pencil_eig(ofrr_ctx ctx, int32_t b, const double *H, const doub
         OFRR_HIP(hipSetDevice(c->device));
         const int32_t r = pencil_eig(c, b, H, G, which, theta, Y, true);
         if (rank) *rank = r;
+        return OFRR_OK;
+    });
+}
+
+ofrr_status ofrr_pencil_eig_general(ofrr_ctx ctx, int32_t b, const double *H, const double *G, double *theta_re,
+                                    double *theta_im, double *Y) {
+    return guarded(ctx, [&](Context *c) {
+        OFRR_CHECK_ARG(H && G && theta_re && theta_im && Y && b >= 1 && b <= 1024,
+                       "pencil_eig_general: bad arguments");
+        OFRR_HIP(hipSetDevice(c->device));
+        pencil_general(c, b, H, G, theta_re, theta_im, Y);
         return OFRR_OK;
     });
 }

@@ -368,6 +368,17 @@ const int32_t *pencil_eig_async(Context *ctx, int32_t b, const double *H, const 
                                 ofrr_which which, double *theta, double *Y);
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,
                 const double *MV, double *sigma, double *Y, double *Z);
+// Non-symmetric pencil H y = theta G y (G symmetric positive definite):
+// theta_re/theta_im (b) ordered by modulus, real part, imaginary part
+// (descending; a conjugate pair adjacent, + member first), Y (b x b) packed
+// real: a real value's column is y, a pair's two columns Re y and Im y of
+// the + member; y^H G y = 1.  The async form returns a device pointer to
+// {status (0 ok, 1 G not positive definite, 2 no convergence), QR
+// iterations}; pencil_general raises on a nonzero status.
+const int32_t *pencil_general_async(Context *ctx, int32_t b, const double *H, const double *G, double *theta_re,
+                                    double *theta_im, double *Y);
+void pencil_general(Context *ctx, int32_t b, const double *H, const double *G, double *theta_re, double *theta_im,
+                    double *Y);
 
 // k_lift.hip
 // X = V Y[:, :nc], AX = W Y[:, :nc] (n x nc outputs, element type per xt),
@@ -406,6 +417,18 @@ void finalize_eig(Context *ctx, int64_t n, int32_t k, const double *X, int64_t l
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,
                      int count, double anorm, double *out, const int32_t *extra = nullptr,
                      const int32_t *extra2 = nullptr);
+// k_general.hip: complex Ritz pairs held packed real (a pair = Re, Im of
+// its + member in adjacent columns; th_im > 0 first member, < 0 second).
+// Residual partials per 64-row block for slots c < nc (layout of lift's).
+void residual_partials_general(Context *ctx, ofrr_dtype t, int64_t n, int32_t nc, const void *X, const void *AX,
+                               int64_t ld, const double *th_re, const double *th_im, double *res2, double *xn2);
+// Final outputs of the k wanted slots from FP64 row-major X, AX (ld, the
+// columns of a pair cut at k included): evals, complex unit vectors with
+// the largest-modulus entry real positive (column-major n x k, re and im
+// parts), resid = ||A x - lambda x|| / (||x|| anorm).
+void finalize_general(Context *ctx, int64_t n, int32_t k, const double *X, const double *AX, int64_t ld,
+                      const double *th_re, const double *th_im, double anorm, double *evals_re,
+                      double *evals_im, double *evecs_re, double *evecs_im, double *resid);
 // SVD final step: resid[c] = sqrt(|A v - s u|^2 + |A^T u - s v|^2)/anorm,
 // normalisation and sign rule (sign fixed on v, u follows); outputs
 // column-major FP64.

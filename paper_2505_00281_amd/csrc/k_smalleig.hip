@@ -1473,6 +1473,521 @@ PencilWork make_work(Context *ctx, int n) {
     return w;
 }
 
+// ---------------------------------------------------------------------------
+// Non-symmetric pencil H y = theta G y with H = V^T A V real non-symmetric
+// and G = V^T V symmetric positive definite (Sec. 3.1: a real A has complex
+// Ritz values; eq. (geig) on a non-orthogonal basis).  One workgroup:
+//   1. G = L L^T; C = L^{-1} H L^{-T}, the standard problem with the same
+//      eigenvalues (y = L^{-T} z for C z = theta z).
+//   2. Householder reduction C = Q Hs Q^T to upper Hessenberg form, Q
+//      accumulated (all threads; per column one reflector applied from the
+//      left to the trailing columns and from the right to every row).
+//   3. Francis double-shift QR iteration on Hs to the real Schur form
+//      T = Z^T Hs Z (implicit double shift from the trailing 2 x 2 block,
+//      an exceptional shift after every ten iterations without a
+//      deflation, a 2 x 2 block with real eigenvalues rotated to triangular
+//      form).  One wavefront chases the bulge; the reflectors and rotations
+//      are logged and applied to Q afterwards by every thread, each taking
+//      rows of Q (the transforms act on the rows independently).
+//   4. Eigenvectors of the quasi-triangular T by back substitution, one
+//      thread per real eigenvalue or conjugate pair (complex arithmetic,
+//      2 x 2 diagonal blocks solved as 2 x 2 systems), then V = Q X_T, each
+//      complex vector scaled to unit 2-norm, Y = L^{-T} V (so y^H G y = 1).
+//   5. Output order: modulus descending, then real part, then imaginary
+//      part descending; a conjugate pair is placed as one unit, + member
+//      first.  Y is packed real: a real value's column is its vector; a
+//      pair occupies two columns, Re y and Im y of the + member.
+// status[0]: 0 ok, 1 G not positive definite, 2 the QR iteration did not
+// converge; status[1]: QR iterations.
+// ---------------------------------------------------------------------------
+
+constexpr int GN_LOGW = 4;  // doubles per logged transform
+
+struct GenWork {
+    double *L, *C, *Q, *X;  // n x n each (C may be replaced by an LDS copy)
+    double *wr, *wi;        // n
+    double *lg;             // GN_LOGW * cap: v0, v1, v2, beta (rotation: c, s)
+    int *lcode;             // cap: k | m << 16 (m = 2, 3: reflector; 0: rotation)
+    int cap;
+};
+
+// orders the wavefront's memory accesses (LDS or global) before and after
+__device__ __forceinline__ void gn_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// rows r = r0 + i * stride of Q (col-major, n) times the logged transforms
+// [0, count), in order
+__device__ void gn_apply_log(double *Q, int n, const double *lg, const int *lcode, int count, int r0,
+                             int stride) {
+    for (int r = r0; r < n; r += stride) {
+        for (int e = 0; e < count; ++e) {
+            const int code = lcode[e];
+            const int k = code & 0xffff, m = code >> 16;
+            const double v0 = lg[GN_LOGW * e], v1 = lg[GN_LOGW * e + 1];
+            double *q0 = Q + r + (int64_t)k * n;
+            double *q1 = q0 + n;
+            if (m == 0) {
+                const double u = *q0, w = *q1;
+                *q0 = v0 * u + v1 * w;
+                *q1 = v0 * w - v1 * u;
+            } else {
+                const double v2 = lg[GN_LOGW * e + 2], beta = lg[GN_LOGW * e + 3];
+                double *q2 = q1 + n;
+                const double a = *q0, b = *q1, c = m == 3 ? *q2 : 0.0;
+                const double t = beta * (v0 * a + v1 * b + v2 * c);
+                *q0 = a - t * v0;
+                *q1 = b - t * v1;
+                if (m == 3) *q2 = c - t * v2;
+            }
+        }
+    }
+}
+
+// step 3 for wavefront 0: C (n x n, upper Hessenberg) -> T in place;
+// eigenvalues in diagonal order to w.wr, w.wi
+__device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
+    const int lane = threadIdx.x & 63;
+    const double eps = 0x1p-52;
+    double hn = 0.0;
+    for (int e = lane; e < n * n; e += 64) {
+        const int i = e % n, j = e / n;
+        if (i <= j + 1) hn = fmax(hn, fabs(C[e]));
+    }
+    for (int o = 32; o > 0; o >>= 1) hn = fmax(hn, __shfl_xor(hn, o, 64));
+    int nn = n - 1, it = 0, total = 0, nlog = 0, fail = 0;
+    const int itmax = 30 * (n > 10 ? n : 10);
+    auto logt = [&](int k, int m, double a0, double a1, double a2, double a3) {
+        if (lane == 0) {
+            double *p = w.lg + (int64_t)GN_LOGW * nlog;
+            p[0] = a0;
+            p[1] = a1;
+            p[2] = a2;
+            p[3] = a3;
+            w.lcode[nlog] = k | (m << 16);
+        }
+        ++nlog;
+        if (nlog == w.cap) {
+            // log full: this wavefront applies it to Q now
+            gn_wave_sync();
+            gn_apply_log(w.Q, n, w.lg, w.lcode, nlog, lane, 64);
+            gn_wave_sync();
+            nlog = 0;
+        }
+    };
+    while (nn >= 0) {
+        // the largest l <= nn whose subdiagonal entry is negligible against
+        // its two diagonal neighbours (l = 0: none)
+        int l = 0;
+        for (int base = nn; base >= 1; base -= 64) {
+            const int c = base - lane;
+            bool ok = false;
+            if (c >= 1) {
+                double s = fabs(C[(c - 1) + (int64_t)(c - 1) * n]) + fabs(C[c + (int64_t)c * n]);
+                if (s == 0.0) s = hn;
+                ok = fabs(C[c + (int64_t)(c - 1) * n]) <= eps * s;
+            }
+            const unsigned long long m = __ballot(ok);
+            if (m) {
+                l = base - (int)__builtin_ctzll(m);
+                break;
+            }
+        }
+        if (l > 0 && lane == 0) C[l + (int64_t)(l - 1) * n] = 0.0;
+        gn_wave_sync();
+        if (l == nn) {
+            if (lane == 0) {
+                w.wr[nn] = C[nn + (int64_t)nn * n];
+                w.wi[nn] = 0.0;
+            }
+            --nn;
+            it = 0;
+            continue;
+        }
+        if (l == nn - 1) {
+            const int a = nn - 1, b = nn;
+            const double t11 = C[a + (int64_t)a * n], t12 = C[a + (int64_t)b * n];
+            const double t21 = C[b + (int64_t)a * n], t22 = C[b + (int64_t)b * n];
+            const double p = 0.5 * (t11 - t22);
+            const double q = p * p + t12 * t21;
+            if (q >= 0.0) {
+                // real pair: rotate with the eigenvector (z, t21) of
+                // t22 + z so the block becomes upper triangular
+                const double z = p + copysign(sqrt(q), p);
+                const double r = hypot(z, t21);
+                const double cs = r > 0.0 ? z / r : 1.0, sn = r > 0.0 ? t21 / r : 0.0;
+                for (int c = a + lane; c < n; c += 64) {
+                    const double u = C[a + (int64_t)c * n], v = C[b + (int64_t)c * n];
+                    C[a + (int64_t)c * n] = cs * u + sn * v;
+                    C[b + (int64_t)c * n] = cs * v - sn * u;
+                }
+                gn_wave_sync();
+                for (int rr = lane; rr <= b; rr += 64) {
+                    const double u = C[rr + (int64_t)a * n], v = C[rr + (int64_t)b * n];
+                    C[rr + (int64_t)a * n] = cs * u + sn * v;
+                    C[rr + (int64_t)b * n] = cs * v - sn * u;
+                }
+                gn_wave_sync();
+                if (lane == 0) {
+                    C[b + (int64_t)a * n] = 0.0;
+                    w.wr[a] = C[a + (int64_t)a * n];
+                    w.wi[a] = 0.0;
+                    w.wr[b] = C[b + (int64_t)b * n];
+                    w.wi[b] = 0.0;
+                }
+                gn_wave_sync();
+                logt(a, 0, cs, sn, 0.0, 0.0);
+            } else if (lane == 0) {
+                w.wr[a] = w.wr[b] = t22 + p;
+                w.wi[a] = sqrt(-q);
+                w.wi[b] = -w.wi[a];
+            }
+            nn -= 2;
+            it = 0;
+            continue;
+        }
+        if (total >= itmax) {
+            fail = 1;
+            break;
+        }
+        ++it;
+        ++total;
+        // shifts: the eigenvalues of the trailing 2 x 2 block (sum s,
+        // product t), or an exceptional pair every tenth iteration
+        double s, t;
+        if (it % 10 == 0) {
+            const double e = fabs(C[nn + (int64_t)(nn - 1) * n]) + fabs(C[(nn - 1) + (int64_t)(nn - 2) * n]);
+            const double h = 0.75 * e + C[nn + (int64_t)nn * n];
+            s = 2.0 * h;
+            t = h * h + 0.4375 * e * e;
+        } else {
+            const double x = C[nn + (int64_t)nn * n], y = C[(nn - 1) + (int64_t)(nn - 1) * n];
+            s = x + y;
+            t = x * y - C[nn + (int64_t)(nn - 1) * n] * C[(nn - 1) + (int64_t)nn * n];
+        }
+        // first column of Hs^2 - s Hs + t I at row l
+        const double h00 = C[l + (int64_t)l * n], h10 = C[(l + 1) + (int64_t)l * n];
+        const double h01 = C[l + (int64_t)(l + 1) * n], h11 = C[(l + 1) + (int64_t)(l + 1) * n];
+        const double h21 = C[(l + 2) + (int64_t)(l + 1) * n];
+        double x = h00 * h00 + h01 * h10 - s * h00 + t;
+        double y = h10 * (h00 + h11 - s);
+        double z = h10 * h21;
+        for (int k = l; k <= nn - 1; ++k) {
+            const int m = (k == nn - 1) ? 2 : 3;
+            if (k > l) {
+                x = C[k + (int64_t)(k - 1) * n];
+                y = C[(k + 1) + (int64_t)(k - 1) * n];
+                z = (m == 3) ? C[(k + 2) + (int64_t)(k - 1) * n] : 0.0;
+            }
+            const double sc = fabs(x) + fabs(y) + fabs(z);
+            if (sc == 0.0) continue;
+            const double xs = x / sc, ys = y / sc, zs = z / sc;
+            const double nr = sqrt(xs * xs + ys * ys + zs * zs);
+            const double alpha = -copysign(nr, xs);
+            const double v0 = xs - alpha, v1 = ys, v2 = zs;
+            const double beta = 1.0 / (alpha * (alpha - xs));
+            const int c0 = (k > l) ? k - 1 : k;
+            const int r1 = (k + 3 < nn) ? k + 3 : nn;
+            for (int c = c0 + lane; c < n; c += 64) {
+                double *p = C + k + (int64_t)c * n;
+                const double a = p[0], b = p[1], cc = m == 3 ? p[2] : 0.0;
+                const double tt = beta * (v0 * a + v1 * b + v2 * cc);
+                p[0] = a - tt * v0;
+                p[1] = b - tt * v1;
+                if (m == 3) p[2] = cc - tt * v2;
+            }
+            gn_wave_sync();
+            for (int r = lane; r <= r1; r += 64) {
+                double *p = C + r + (int64_t)k * n;
+                const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
+                const double tt = beta * (a * v0 + b * v1 + cc * v2);
+                p[0] = a - tt * v0;
+                p[n] = b - tt * v1;
+                if (m == 3) p[2 * n] = cc - tt * v2;
+            }
+            if (k > l && lane == 0) {
+                C[k + (int64_t)(k - 1) * n] = alpha * sc;
+                C[(k + 1) + (int64_t)(k - 1) * n] = 0.0;
+                if (m == 3) C[(k + 2) + (int64_t)(k - 1) * n] = 0.0;
+            }
+            gn_wave_sync();
+            logt(k, m, v0, v1, v2, beta);
+        }
+    }
+    gn_wave_sync();
+    // the rest of the log: every thread applies it after the block barrier
+    if (lane == 0) {
+        status[0] = fail ? 2 : 0;
+        status[1] = total;
+        status[2] = nlog;
+    }
+}
+
+// one thread per real eigenvalue or conjugate pair: the eigenvector of the
+// quasi-triangular T (n x n) into X (packed real, col-major n)
+__device__ void gn_tri_vector(const double *T, int n, const double *wr, const double *wi, int k, double tiny,
+                              double *X) {
+    const bool pair = wi[k] > 0.0;
+    const double lr = wr[k], li = wi[k];
+    double *xr = X + (int64_t)k * n;
+    double *xi = pair ? X + (int64_t)(k + 1) * n : nullptr;
+    int top = k;
+    if (!pair) {
+        xr[k] = 1.0;
+    } else {
+        const int a = k, b = k + 1;
+        const double t11 = T[a + (int64_t)a * n], t12 = T[a + (int64_t)b * n];
+        const double t21 = T[b + (int64_t)a * n], t22 = T[b + (int64_t)b * n];
+        if (fabs(t21) >= fabs(t12)) {
+            // x_b = 1, x_a = (lambda - t22) / t21
+            xr[b] = 1.0;
+            xi[b] = 0.0;
+            xr[a] = (lr - t22) / t21;
+            xi[a] = li / t21;
+        } else {
+            // x_a = 1, x_b = (lambda - t11) / t12
+            xr[a] = 1.0;
+            xi[a] = 0.0;
+            xr[b] = (lr - t11) / t12;
+            xi[b] = li / t12;
+        }
+        top = b;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        const bool blk2 = i >= 1 && wi[i] < 0.0;
+        if (blk2) {
+            const int a = i - 1, b = i;
+            double rar = 0.0, rai = 0.0, rbr = 0.0, rbi = 0.0;
+            for (int j = i + 1; j <= top; ++j) {
+                const double ta = T[a + (int64_t)j * n], tb = T[b + (int64_t)j * n];
+                const double vr = xr[j], vi = pair ? xi[j] : 0.0;
+                rar += ta * vr;
+                rai += ta * vi;
+                rbr += tb * vr;
+                rbi += tb * vi;
+            }
+            // [[m11, m12], [m21, m22]] [xa; xb] = -[ra; rb], m11 = t11 - lambda,
+            // m22 = t22 - lambda (complex), m12, m21 real
+            const double m11r = T[a + (int64_t)a * n] - lr, m11i = -li;
+            const double m22r = T[b + (int64_t)b * n] - lr, m22i = -li;
+            const double m12 = T[a + (int64_t)b * n], m21 = T[b + (int64_t)a * n];
+            double detr = m11r * m22r - m11i * m22i - m12 * m21;
+            double deti = m11r * m22i + m11i * m22r;
+            if (detr == 0.0 && deti == 0.0) detr = tiny;
+            // xa = (-ra m22 + rb m12) / det, xb = (-rb m11 + ra m21) / det
+            const double nar = -(rar * m22r - rai * m22i) + rbr * m12;
+            const double nai = -(rar * m22i + rai * m22r) + rbi * m12;
+            const double nbr = -(rbr * m11r - rbi * m11i) + rar * m21;
+            const double nbi = -(rbr * m11i + rbi * m11r) + rai * m21;
+            const double dd = detr * detr + deti * deti;
+            xr[a] = (nar * detr + nai * deti) / dd;
+            xr[b] = (nbr * detr + nbi * deti) / dd;
+            if (pair) {
+                xi[a] = (nai * detr - nar * deti) / dd;
+                xi[b] = (nbi * detr - nbr * deti) / dd;
+            }
+            --i;
+        } else {
+            double rr = 0.0, ri = 0.0;
+            for (int j = i + 1; j <= top; ++j) {
+                const double ti = T[i + (int64_t)j * n];
+                rr += ti * xr[j];
+                if (pair) ri += ti * xi[j];
+            }
+            double dr = T[i + (int64_t)i * n] - lr, di = -li;
+            if (dr == 0.0 && di == 0.0) dr = tiny;
+            const double dd = dr * dr + di * di;
+            // x_i = -r / d
+            xr[i] = -(rr * dr + ri * di) / dd;
+            if (pair) xi[i] = -(ri * dr - rr * di) / dd;
+        }
+        // growth guard: the new entries (rows lo..i0) above 2^330 scale the
+        // whole partial vector down
+        const int lo = i, i0 = blk2 ? i + 1 : i;
+        double mx = 0.0;
+        for (int j = lo; j <= i0; ++j) mx = fmax(mx, fabs(xr[j]) + (pair ? fabs(xi[j]) : 0.0));
+        if (mx > 0x1p330) {
+            const double f = 1.0 / mx;
+            for (int j = lo; j <= top; ++j) {
+                xr[j] *= f;
+                if (pair) xi[j] *= f;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__restrict__ H,
+                                                               const double *__restrict__ G, int n,
+                                                               double *__restrict__ theta_re,
+                                                               double *__restrict__ theta_im,
+                                                               double *__restrict__ Y, GenWork w, int *status,
+                                                               int use_lds) {
+    extern __shared__ __attribute__((aligned(16))) double smem[];
+    __shared__ double red[16];
+    __shared__ int s_slot[SE_THREADS];
+    const int t = threadIdx.x, T = blockDim.x, wave = t >> 6;
+    double *C = use_lds ? smem : w.C;
+    for (int e = t; e < n * n; e += T) {
+        const int i = e % n, j = e / n;
+        w.L[e] = 0.5 * (G[i + j * n] + G[j + i * n]);
+        C[e] = H[e];
+    }
+    if (t < 4) status[t] = 0;
+    __syncthreads();
+    if (!cholesky(w.L, n, 1)) {
+        if (t == 0) status[0] = 1;
+        for (int i = t; i < n; i += T) {
+            theta_re[i] = 0.0;
+            theta_im[i] = 0.0;
+        }
+        return;
+    }
+    // C <- L^{-1} H L^{-T}: L^{-1} H, transpose, L^{-1} (.), transpose
+    trsm_lower(w.L, n, C, n);
+    transpose_sq(C, n);
+    trsm_lower(w.L, n, C, n);
+    transpose_sq(C, n);
+    // ---- 2. Householder reduction to Hessenberg form, Q accumulated
+    for (int e = t; e < n * n; e += T) w.Q[e] = (e % n == e / n) ? 1.0 : 0.0;
+    double *v = w.wr;  // scratch vector (rows j+1..n-1) until step 3
+    double *tv = w.wi;
+    __syncthreads();
+    for (int j = 0; j + 2 < n; ++j) {
+        double sg = 0.0;
+        for (int i = j + 2 + t; i < n; i += T) sg += C[i + (int64_t)j * n] * C[i + (int64_t)j * n];
+        sg = block_sum(sg, red);
+        if (sg == 0.0) continue;  // uniform: column already reduced
+        const double x0 = C[(j + 1) + (int64_t)j * n];
+        const double alpha = -copysign(sqrt(x0 * x0 + sg), x0);
+        const double beta = 1.0 / (alpha * (alpha - x0));
+        for (int i = j + 1 + t; i < n; i += T) v[i] = (i == j + 1) ? x0 - alpha : C[i + (int64_t)j * n];
+        __syncthreads();
+        // left: columns j+1..n-1, tv[c] = beta v^T C[:, c] (a wavefront per column)
+        const int nw = T >> 6, lane = t & 63;
+        for (int c = j + 1 + wave; c < n; c += nw) {
+            double acc = 0.0;
+            for (int i = j + 1 + lane; i < n; i += 64) acc += v[i] * C[i + (int64_t)c * n];
+            acc = wave_sum_f64(acc);
+            if (lane == 0) tv[c] = beta * acc;
+        }
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int e = t; e < m * m; e += T) {
+            const int i = j + 1 + e % m, c = j + 1 + e / m;
+            C[i + (int64_t)c * n] -= tv[c] * v[i];
+        }
+        __syncthreads();
+        for (int i = j + 1 + t; i < n; i += T) C[i + (int64_t)j * n] = (i == j + 1) ? alpha : 0.0;
+        // right: every row r of C and of Q, tv[r] = beta C[r, :] v
+        for (int r = t; r < 2 * n; r += T) {
+            const double *M = r < n ? C : w.Q;
+            const int rr = r < n ? r : r - n;
+            double acc = 0.0;
+            for (int i = j + 1; i < n; ++i) acc += M[rr + (int64_t)i * n] * v[i];
+            w.X[r] = beta * acc;
+        }
+        __syncthreads();
+        for (int e = t; e < 2 * n * m; e += T) {
+            const int r = e % (2 * n), i = j + 1 + e / (2 * n);
+            double *M = r < n ? C : w.Q;
+            const int rr = r < n ? r : r - n;
+            M[rr + (int64_t)i * n] -= w.X[r] * v[i];
+        }
+        __syncthreads();
+    }
+    // ---- 3. QR iteration (wavefront 0), then Q <- Q Z from the log
+    if (wave == 0) gn_francis(C, n, w, status);
+    __syncthreads();
+    if (status[0] != 0) {
+        for (int i = t; i < n; i += T) {
+            theta_re[i] = 0.0;
+            theta_im[i] = 0.0;
+        }
+        return;
+    }
+    gn_apply_log(w.Q, n, w.lg, w.lcode, status[2], t, T);
+    // ---- 4. eigenvectors of T, V = Q X_T
+    double tn = 0.0;
+    for (int e = t; e < n * n; e += T) tn = fmax(tn, fabs(C[e]));
+    tn = block_maxabs(tn, red);
+    const double tiny = 0x1p-52 * (tn > 0.0 ? tn : 1.0);
+    for (int e = t; e < n * n; e += T) w.X[e] = 0.0;
+    __syncthreads();
+    for (int k = t; k < n; k += T)
+        if (w.wi[k] >= 0.0) gn_tri_vector(C, n, w.wr, w.wi, k, tiny, w.X);
+    __syncthreads();
+    // V = Q X into C's storage... C (T) is no longer needed
+    double *V = w.C;  // global n x n
+    for (int e = t; e < n * n; e += T) {
+        const int r = e % n, c = e / n;
+        const int jmax = (c + 1 < n) ? c + 1 : n - 1;
+        double s = 0.0;
+        for (int j = 0; j <= jmax; ++j) s += w.Q[r + (int64_t)j * n] * w.X[j + (int64_t)c * n];
+        V[e] = s;
+    }
+    __syncthreads();
+    // unit 2-norm per real vector / complex pair
+    for (int k = t; k < n; k += T) {
+        if (w.wi[k] < 0.0) continue;
+        const bool pair = w.wi[k] > 0.0;
+        double s = 0.0;
+        for (int r = 0; r < n; ++r) {
+            const double a = V[r + (int64_t)k * n];
+            s += a * a;
+            if (pair) {
+                const double b = V[r + (int64_t)(k + 1) * n];
+                s += b * b;
+            }
+        }
+        const double f = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        for (int r = 0; r < n; ++r) {
+            V[r + (int64_t)k * n] *= f;
+            if (pair) V[r + (int64_t)(k + 1) * n] *= f;
+        }
+    }
+    __syncthreads();
+    trsm_lower_t(w.L, n, V, n);  // Y = L^{-T} V
+    // ---- 5. order the units (real values and + members of pairs)
+    for (int g = t; g < n; g += T) {
+        int slot = -1;
+        if (w.wi[g] >= 0.0) {
+            const double mg = hypot(w.wr[g], w.wi[g]), rg = w.wr[g], ig = w.wi[g];
+            slot = 0;
+            for (int h = 0; h < n; ++h) {
+                if (w.wi[h] < 0.0 || h == g) continue;
+                const double mh = hypot(w.wr[h], w.wi[h]), rh = w.wr[h], ih = w.wi[h];
+                const bool before = mh > mg || (mh == mg && (rh > rg || (rh == rg && (ih > ig || (ih == ig && h < g)))));
+                if (before) slot += ih > 0.0 ? 2 : 1;
+            }
+        }
+        s_slot[g] = slot;
+    }
+    __syncthreads();
+    for (int g = t; g < n; g += T) {
+        const int s = s_slot[g];
+        if (s < 0) continue;
+        theta_re[s] = w.wr[g];
+        theta_im[s] = w.wi[g];
+        if (w.wi[g] > 0.0) {
+            theta_re[s + 1] = w.wr[g];
+            theta_im[s + 1] = -w.wi[g];
+        }
+    }
+    for (int e = t; e < n * n; e += T) {
+        const int r = e % n, c = e / n;
+        // column c of V goes to slot s_slot[c] (a real value or Re of a pair)
+        // or s_slot[c - 1] + 1 (Im of the pair starting at c - 1)
+        int s;
+        if (w.wi[c] >= 0.0)
+            s = s_slot[c];
+        else
+            s = s_slot[c - 1] + 1;
+        Y[r + (int64_t)s * n] = V[e];
+    }
+}
+
 // Dynamic-LDS limits are per kernel and device; raising them once per
 // device to the largest size the launches below ask for keeps the attribute
 // calls off the per-iteration path.
@@ -1484,6 +1999,8 @@ void pencil_attributes(Context *ctx) {
     OFRR_HIP(hipFuncSetAttribute((const void *)k_fp_back, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)fp_lds_bytes()));
     OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
+    OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_general, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
     done.insert(ctx->device);
 }
@@ -1542,6 +2059,44 @@ int32_t pencil_eig(Context *ctx, int32_t b, const double *H, const double *G, of
     OFRR_HIP(hipMemcpyAsync(host, rank, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     ctx->sync();
     return host[0];
+}
+
+const int32_t *pencil_general_async(Context *ctx, int32_t b, const double *H, const double *G, double *theta_re,
+                                    double *theta_im, double *Y) {
+    OFRR_CHECK_ARG(b >= 1 && b <= SE_THREADS, "general pencil: 1 <= b <= 1024");
+    pencil_attributes(ctx);
+    const size_t nn = (size_t)b * b;
+    GenWork w;
+    double *base = ctx->buf<double>("gpencil_work", 4 * nn + 2 * (size_t)b + 8);
+    w.L = base;
+    w.C = base + nn;
+    w.Q = base + 2 * nn;
+    w.X = base + 3 * nn;
+    w.wr = base + 4 * nn;
+    w.wi = w.wr + b;
+    // transforms logged before Q is updated: about two sweeps of b steps per
+    // eigenvalue are usual; a full log is applied by the chasing wavefront
+    w.cap = (int)std::min<size_t>(4 * nn + 64, (size_t)1 << 22);
+    w.lg = ctx->buf<double>("gpencil_log", (size_t)GN_LOGW * w.cap);
+    w.lcode = ctx->buf<int>("gpencil_lcode", (size_t)w.cap);
+    int *status = ctx->buf<int>("gpencil_status", 4);
+    const int use_lds = b <= SE_LDS_MAX_N ? 1 : 0;
+    const size_t shmem = use_lds ? nn * sizeof(double) : 0;
+    KTimer tm(ctx, "small_eig");
+    hipLaunchKernelGGL(k_pencil_general, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b, theta_re,
+                       theta_im, Y, w, status, use_lds);
+    OFRR_HIP(hipGetLastError());
+    return status;
+}
+
+void pencil_general(Context *ctx, int32_t b, const double *H, const double *G, double *theta_re, double *theta_im,
+                    double *Y) {
+    const int32_t *st = pencil_general_async(ctx, b, H, G, theta_re, theta_im, Y);
+    int32_t *host = ctx->host_stage<int32_t>(2);
+    OFRR_HIP(hipMemcpyAsync(host, st, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    if (host[0] == 1) fail(OFRR_ERR_NUMERIC, "general pencil: G is not positive definite");
+    if (host[0] == 2) fail(OFRR_ERR_NUMERIC, "general pencil: the QR iteration did not converge");
 }
 
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,

@@ -145,7 +145,7 @@ struct EigRun {
             if (ph.sliced)
                 product_i8s(ctx, A_sl, bc, (const double *)Vm, ld, (double *)Wm, ld, defer, i8_digits);
             else
-                product_f64(ctx, A, 1, bc, (const double *)Vm, ld, (double *)Wm, ld);
+                product_f64(ctx, A, atrans, bc, (const double *)Vm, ld, (double *)Wm, ld);
             return;
         }
         if (ph.basis == OFRR_F32) {
@@ -154,7 +154,7 @@ struct EigRun {
             double *v64 = ctx->buf<double>("f32_v64", (size_t)n * ld);
             double *w64 = ctx->buf<double>("f32_w64", (size_t)n * ld);
             cast_matrix(ctx, OFRR_F32, OFRR_F64, ld, n, Vm, ld, v64, ld);
-            product_f64(ctx, A, 1, bc, v64, ld, w64, ld);
+            product_f64(ctx, A, atrans, bc, v64, ld, w64, ld);
             cast_matrix(ctx, OFRR_F64, OFRR_F32, ld, n, w64, ld, Wm, ld);
             return;
         }
@@ -165,7 +165,7 @@ struct EigRun {
         uint16_t *vlo = nullptr;
         if (plan->b_split >= 2 || ph.split) vlo = ctx->buf<uint16_t>("prod_vlo", (size_t)ld * ldt);
         split_block_t(ctx, ph.basis, n, bc, (const float *)Vm, ld, vhi, vlo, ldt);
-        product_lowp_t(ctx, ph.basis, n, n, A_lo, n, 1, bc, vhi, vlo, ldt, (float *)Wm, ld,
+        product_lowp_t(ctx, ph.basis, n, n, A_lo, n, atrans, bc, vhi, vlo, ldt, (float *)Wm, ld,
                        ph.split ? A_lo2 : nullptr, defer);
     }
 
@@ -181,6 +181,9 @@ struct EigRun {
         return true;
     }
 
+    // dense products read A^T (a symmetric A: A^T = A, the K-contiguous
+    // form of the column-major storage) or A itself (a general A)
+    int atrans = 1;
     int64_t b0 = 0;  // leading dimension of every block (the initial basis size)
     // digits per side of the INT8 digit-plane products (sliced FP64 phase)
     int i8_digits = 6;
@@ -607,6 +610,262 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         info->seconds = ms * 1e-3;
         info->gram_t_max = gram_t_max;
         info->grams_f64 = grams_f64;
+    }
+    return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Real non-symmetric A (Sec. 3.1: complex Ritz values; eq. (geig) with the
+// pencil (V^T A V, V^T V) of a non-orthogonal basis).  The same outer
+// iteration with products A V, the power filter, the Hessenberg process,
+// FP64 projections and the non-symmetric pencil; the Ritz block is held
+// packed real (a conjugate pair as Re and Im of its + member), which is
+// also the real restart basis.  The k wanted values are those of largest
+// modulus.
+// ---------------------------------------------------------------------------
+ofrr_status eig_general_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis, const ofrr_plan *plan,
+                             const double *X0, double *evals_re, double *evals_im, double *evecs_re,
+                             double *evecs_im, double *resid, ofrr_info *info) {
+    const int64_t n = A->rows;
+    const int64_t ld = basis;
+    hipEvent_t ev0, ev1;
+    OFRR_HIP(hipEventCreate(&ev0));
+    OFRR_HIP(hipEventCreate(&ev1));
+    OFRR_HIP(hipEventRecord(ev0, ctx->stream));
+
+    EigRun run;
+    run.ctx = ctx;
+    run.A = A;
+    run.plan = plan;
+    run.n = n;
+    run.b = basis;
+    run.k = k;
+    run.which = OFRR_LARGEST;
+    run.b0 = ld;
+    run.atrans = 0;
+
+    const bool dense = A->format == OFRR_DENSE_COLMAJOR;
+    std::vector<Phase> phases;
+    phases.push_back(Phase{plan->basis_dtype});
+    if (plan->refine >= 2 && dense && plan->basis_dtype == OFRR_BF16) {
+        Phase mid{OFRR_BF16};
+        mid.split = true;
+        phases.push_back(mid);
+    }
+    if (plan->refine >= 2 && !dense && (plan->basis_dtype == OFRR_F16 || plan->basis_dtype == OFRR_BF16))
+        phases.push_back(Phase{OFRR_F32});
+    if (plan->refine && plan->basis_dtype != OFRR_F64) {
+        Phase tail{OFRR_F64};
+        tail.sliced = dense && plan->tail_product == OFRR_TAIL_I8_SLICED;
+        phases.push_back(tail);
+    }
+    bool any_split = false, any_sliced = false;
+    for (auto &p : phases) {
+        any_split = any_split || p.split;
+        any_sliced = any_sliced || p.sliced;
+    }
+    if (A->dtype == OFRR_F64) {
+        const double amax = absmax_values(ctx, A);
+        if (!std::isfinite(amax)) fail(OFRR_ERR_NUMERIC, "A holds NaN or infinity");
+        if (amax > 0) {
+            int e = 0;
+            (void)std::frexp(amax, &e);
+            if (e > 300 || e < -300) run.sigma = std::ldexp(1.0, -e);
+        }
+    }
+    // digit planes of A's rows (K-contiguous rows of A) for a sliced phase
+    if (any_sliced) run.A_sl = slice_matrix_i8(ctx, A, 0);
+    if (dense && !phases[0].f64() && phases[0].basis != OFRR_F32) {
+        run.A_lo_t = phases[0].basis;
+        run.A_lo = ctx->buf<uint16_t>("A_lo", (size_t)n * n);
+        const float *Af = nullptr;
+        int64_t lda = A->ld;
+        if (A->dtype == OFRR_F32) {
+            Af = (const float *)A->values;
+        } else {
+            float *tmp = ctx->buf<float>("A_f32", (size_t)n * n);
+            cast_matrix(ctx, OFRR_F64, OFRR_F32, n, n, A->values, A->ld, tmp, n, run.sigma);
+            Af = tmp;
+            lda = n;
+        }
+        if (any_split) {
+            run.A_lo2 = ctx->buf<uint16_t>("A_lo2", (size_t)n * n);
+            cast_f32_to_bf16x2(ctx, n, n, Af, lda, run.A_lo, run.A_lo2);
+        } else {
+            cast_matrix(ctx, OFRR_F32, run.A_lo_t, n, n, Af, lda, run.A_lo, n);
+        }
+    }
+
+    const size_t blk = (size_t)n * ld;
+    void *X = ctx->buf<double>("X", blk);
+    void *AX = ctx->buf<double>("AX", blk);
+    void *Y1 = ctx->buf<double>("Y1", blk);
+    void *Y2 = ctx->buf<double>("Y2", blk);
+    void *V = ctx->buf<double>("V", blk);
+    void *W = ctx->buf<double>("W", blk);
+    float *swork = ctx->buf<float>("scale_work", (size_t)ld * ((n + 4095) / 4096 + 2) + 256);
+    double *G = ctx->buf<double>("G", (size_t)ld * ld);
+    double *H = ctx->buf<double>("H", (size_t)ld * ld);
+    double *Yr = ctx->buf<double>("Yr", (size_t)ld * ld);
+    double *th_re = ctx->buf<double>("theta", (size_t)ld + 8);
+    double *th_im = ctx->buf<double>("theta_im", (size_t)ld + 8);
+    int32_t *piv = ctx->buf<int32_t>("piv", (size_t)ld);
+    int32_t *keep = ctx->buf<int32_t>("keep", (size_t)ld);
+    const int64_t nblk = (n + 63) / 64;
+    double *res2 = ctx->buf<double>("res2", (size_t)nblk * ld);
+    double *xn2 = ctx->buf<double>("xn2", (size_t)nblk * ld);
+    double *rest = ctx->buf<double>("res_est", (size_t)ld + 8);
+    {
+        const double *src = X0;
+        if (!src) {
+            double *gen = ctx->buf<double>("X0_gen", blk);
+            uniform_start(ctx, n, basis, 0x5EEDull, gen);
+            src = gen;
+        }
+        colmajor_to_rowmajor(ctx, n, basis, src, n, phases[0].master(), X, ld);
+    }
+
+    int32_t bc = basis;
+    scale_columns_reset(ctx);
+    bool have_ax = false;
+    int iters = 0, iters_low = 0;
+    StallDetector stall_det{plan->stall_iters};
+    size_t pi = 0;
+    double anorm_used = plan->anorm * run.sigma;
+    double emax_prev = INFINITY;
+    std::vector<double> hre, him;
+    while (iters < plan->max_iters) {
+        const Phase &ph = phases[pi];
+        const ofrr_dtype mt = ph.master();
+        run.i8_digits = !ph.sliced ? 6 : (plan->tail_digits == 0 ? i8_digits_for(emax_prev) : plan->tail_digits);
+        const double tol = plan->drop_tol > 0 ? plan->drop_tol : unit_roundoff(mt);
+        // ---- power filter: Y1 = A^degree X, every block column-scaled
+        if (have_ax)
+            OFRR_HIP(hipMemcpyAsync(Y1, AX, (size_t)n * ld * esize(mt), hipMemcpyDeviceToDevice, ctx->stream));
+        else
+            run.product(ph, X, Y1, bc);
+        for (int d = 2; d <= plan->degree; ++d) {
+            scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
+            if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)Y1);
+            run.product(ph, Y1, Y2, bc);
+            std::swap(Y1, Y2);
+        }
+        scale_columns_pow2(ctx, mt, n, bc, Y1, ld, mt, nullptr, ld, swork);
+        // ---- stabilise
+        const int32_t *hstat = nullptr;
+        hessenberg(ctx, mt, n, bc, Y1, ld, tol, piv, keep, &hstat);
+        std::swap(V, Y1);
+        if (!ph.f64() && !ph.split && plan->b_split < 2) round_block(ctx, ph.basis, n * ld, (float *)V);
+        double *stage = nullptr;
+        for (bool first = true;; first = false) {
+            // ---- project, solve, lift
+            run.product(ph, V, W, bc);
+            project(ctx, n, bc, mt, V, ld, mt, W, ld, OFRR_ACC_F64, G, H);
+            const int32_t *pst = pencil_general_async(ctx, bc, H, G, th_re, th_im, Yr);
+            lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, nullptr, mt, X, AX, ld, nullptr, nullptr);
+            residual_partials_general(ctx, mt, n, bc, X, AX, ld, th_re, th_im, res2, xn2);
+            if (plan->anorm <= 0) {
+                hre.resize((size_t)bc);
+                him.resize((size_t)bc);
+                OFRR_HIP(hipMemcpyAsync(hre.data(), th_re, sizeof(double) * bc, hipMemcpyDeviceToHost, ctx->stream));
+                OFRR_HIP(hipMemcpyAsync(him.data(), th_im, sizeof(double) * bc, hipMemcpyDeviceToHost, ctx->stream));
+                ctx->sync();
+                double m = 0.0;
+                for (int32_t i = 0; i < bc; ++i) m = std::max(m, std::hypot(hre[i], him[i]));
+                anorm_used = m > 0 ? m : 1.0;
+            }
+            // estimates of the k wanted slots, then {pencil status, hessenberg
+            // error flag, kept count}
+            residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, pst, first ? hstat : nullptr);
+            stage = ctx->host_stage<double>((size_t)k + 4);
+            const int nread = k + (first ? 3 : 1);
+            OFRR_HIP(hipMemcpyAsync(stage, rest, sizeof(double) * nread, hipMemcpyDeviceToHost, ctx->stream));
+            ctx->sync();
+            if (first) {
+                // a dropped column leaves G singular: the pencil is redone
+                // on the compacted basis before its status counts
+                if (stage[k + 1] != 0.0) fail(OFRR_ERR_HIP, "hessenberg: wait for the column candidates timed out");
+                const int32_t kept = (int32_t)stage[k + 2];
+                if (kept <= 0) fail(OFRR_ERR_NUMERIC, "every basis column was dropped");
+                if (kept != bc) {
+                    compact_columns_rm(ctx, mt, n, bc, V, ld, keep, Y1, ld);
+                    std::swap(V, Y1);
+                    bc = kept;
+                    if (bc < k) fail(OFRR_ERR_NUMERIC, "basis lost rank below k");
+                    continue;
+                }
+            }
+            if (stage[k] == 1.0) fail(OFRR_ERR_NUMERIC, "projected mass matrix is not positive definite");
+            if (stage[k] == 2.0) fail(OFRR_ERR_NUMERIC, "small non-symmetric eigensolver did not converge");
+            break;
+        }
+        ++iters;
+        if (!ph.f64()) ++iters_low;
+        have_ax = true;
+        double emax = 0.0;
+        for (int i = 0; i < k; ++i) emax = std::max(emax, std::isfinite(stage[i]) ? stage[i] : INFINITY);
+        if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "non-finite residual estimate");
+        emax_prev = emax;
+        const bool last_phase = pi + 1 == phases.size();
+        if (last_phase && plan->tol > 0 && emax <= plan->tol && run.i8_digits == 6) break;
+        if (!last_phase) {
+            const bool stalled = stall_det.push(emax);
+            const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
+            if (stalled || by_value) {
+                if (phases[pi + 1].f64() && !ph.f64()) promote_block(ctx, n * ld, X);
+                ++pi;
+                have_ax = false;
+                stall_det.reset();
+            }
+        }
+    }
+
+    // ---- final FP64 residuals from A as stored; a pair cut at k keeps its
+    // second column
+    const Phase &ph = phases[pi];
+    double cut_im = 0.0;
+    OFRR_HIP(hipMemcpyAsync(&cut_im, th_im + (k - 1), sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    const int32_t kk = (cut_im > 0.0 && k < bc) ? k + 1 : k;
+    double *Xf = ctx->buf<double>("X_final", (size_t)n * kk + 8);
+    double *AXf = ctx->buf<double>("AX_final", (size_t)n * kk + 8);
+    cast_matrix(ctx, ph.master(), OFRR_F64, kk, n, X, ld, Xf, kk);
+    ++run.products;
+    if (A->format == OFRR_CSR)
+        product_csr(ctx, A, kk, OFRR_F64, Xf, kk, AXf, kk);
+    else
+        product_f64(ctx, A, 0, kk, Xf, kk, AXf, kk);
+    if (run.sigma != 1.0) scale_array(ctx, n * kk, AXf, run.sigma);
+    finalize_general(ctx, n, k, Xf, AXf, kk, th_re, th_im, anorm_used, evals_re, evals_im, evecs_re, evecs_im,
+                     resid);
+    if (run.sigma != 1.0) {
+        scale_array(ctx, k, evals_re, 1.0 / run.sigma);
+        scale_array(ctx, k, evals_im, 1.0 / run.sigma);
+    }
+    OFRR_HIP(hipEventRecord(ev1, ctx->stream));
+    std::vector<double> r((size_t)k);
+    OFRR_HIP(hipMemcpyAsync(r.data(), resid, sizeof(double) * k, hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    float ms = 0.f;
+    OFRR_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    OFRR_HIP(hipEventDestroy(ev0));
+    OFRR_HIP(hipEventDestroy(ev1));
+    int nconv = 0;
+    double rmax = 0.0;
+    for (double v : r) {
+        rmax = std::max(rmax, v);
+        if (plan->tol > 0 ? v <= plan->tol : true) ++nconv;
+    }
+    if (info) {
+        info->iters = iters;
+        info->iters_low = iters_low;
+        info->n_converged = nconv;
+        info->basis_eff = bc;
+        info->products = run.products;
+        info->max_resid = rmax;
+        info->seconds = ms * 1e-3;
+        info->gram_t_max = 0.0;
+        info->grams_f64 = 0;
     }
     return (plan->tol > 0 && nconv < k) ? OFRR_NOT_CONVERGED : OFRR_OK;
 }

@@ -40,7 +40,8 @@ EXPORTED = ["ofrr_plan_default", "ofrr_create", "ofrr_destroy", "ofrr_last_error
             "ofrr_quantize",
             "ofrr_quantize_fp8_blocks", "ofrr_block_product", "ofrr_block_product_sliced",
             "ofrr_block_product_fp8", "ofrr_hessenberg", "ofrr_hessenberg_noalloc", "ofrr_basis_generate",
-            "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil"]
+            "ofrr_project", "ofrr_pencil_eig", "ofrr_svd_pencil", "ofrr_eig_general",
+            "ofrr_pencil_eig_general"]
 
 
 class OfrrError(RuntimeError):
@@ -124,6 +125,8 @@ def load_library(path: str = LIB_PATH):
                                  vp, vp]
     lib.ofrr_pencil_eig.argtypes = [vp, i32, vp, vp, ctypes.c_int, vp, vp, P(i32)]
     lib.ofrr_svd_pencil.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.ofrr_eig_general.argtypes = [vp, P(Matrix), i32, i32, P(Plan), vp, vp, vp, vp, vp, vp, P(Info)]
+    lib.ofrr_pencil_eig_general.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("ofrr_plan_default", "ofrr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -232,6 +235,15 @@ class EigResult:
 
 
 @dataclass
+class GeneralResult:
+    evals: torch.Tensor  # complex128, k
+    evecs: torch.Tensor  # complex128, n x k
+    resid: torch.Tensor
+    info: dict
+    status: int
+
+
+@dataclass
 class SvdResult:
     sigma: torch.Tensor
     U: torch.Tensor
@@ -317,6 +329,25 @@ class Context:
                                        _ptr(resid), ctypes.byref(info))
         self._check(st, allow_warning=True)
         return EigResult(evals, evecs, resid, info.as_dict(), st)
+
+    def eig_general(self, A, k: int, basis: int, plan: Plan | None = None, X0=None) -> GeneralResult:
+        """k eigenpairs of largest modulus of a real non-symmetric A (dense
+        column-major or CSR); complex values and vectors."""
+        mat = self._mat(A)
+        n = mat.rows
+        plan = plan or make_plan()
+        X0c = _colmajor_f64(X0, n, basis, self.device)
+        ere = torch.empty(k, dtype=torch.float64, device=self.device)
+        eim = torch.empty(k, dtype=torch.float64, device=self.device)
+        vre = _empty_colmajor(n, k, self.device)
+        vim = _empty_colmajor(n, k, self.device)
+        resid = torch.empty(k, dtype=torch.float64, device=self.device)
+        info = Info()
+        st = self.lib.ofrr_eig_general(self.h, ctypes.byref(mat), k, basis, ctypes.byref(plan), _ptr(X0c),
+                                       _ptr(ere), _ptr(eim), _ptr(vre), _ptr(vim), _ptr(resid),
+                                       ctypes.byref(info))
+        self._check(st, allow_warning=True)
+        return GeneralResult(torch.complex(ere, eim), torch.complex(vre, vim), resid, info.as_dict(), st)
 
     def svd_partial(self, A, k: int, basis: int, plan: Plan | None = None, V0=None) -> SvdResult:
         mat = self._mat(A)
@@ -578,6 +609,20 @@ class Context:
         self._check(self.lib.ofrr_pencil_eig(self.h, b, _ptr(Hc), _ptr(Gc), _WHICH[which],
                                              _ptr(theta), _ptr(Y), ctypes.byref(rank)))
         return theta, Y, rank.value
+
+    def pencil_eig_general(self, H: torch.Tensor, G: torch.Tensor):
+        """Non-symmetric pencil: (theta_re, theta_im, Y packed real)."""
+        self._on_device(H, G)
+        b = H.shape[0]
+        if tuple(H.shape) != (b, b) or tuple(G.shape) != (b, b):
+            raise OfrrError(ERR_INVALID_ARG, "H and G must be square and of the same size")
+        Hc = H.to(torch.float64).t().contiguous().t()
+        Gc = G.to(torch.float64).t().contiguous().t()
+        tre = torch.empty(b, dtype=torch.float64, device=self.device)
+        tim = torch.empty(b, dtype=torch.float64, device=self.device)
+        Y = _empty_colmajor(b, b, self.device)
+        self._check(self.lib.ofrr_pencil_eig_general(self.h, b, _ptr(Hc), _ptr(Gc), _ptr(tre), _ptr(tim), _ptr(Y)))
+        return tre, tim, Y
 
     def svd_pencil(self, B: torch.Tensor, MU: torch.Tensor, MV: torch.Tensor):
         self._on_device(B, MU, MV)

@@ -182,3 +182,21 @@ def test_real_basis_spans_the_ritz_vectors():
     # rank 9 together with the complex vectors: the same complex span
     s = np.linalg.svd(np.concatenate([Xr, Z], axis=1), compute_uv=False)
     assert s[8] > 1e-8 * s[0] and s[9] < 1e-12 * s[0]
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.5])
+def test_convection_diffusion_closed_form(gamma):
+    # the sparse non-symmetric workload: its eigenvalues (LAPACK on the
+    # dense form) are the closed form's, complex for gamma > 1
+    import scipy.sparse as sp
+    N = 9
+    rp, ci, v = W.convection_diffusion_2d_csr(N, gamma)
+    A = sp.csr_matrix((v.astype(np.float64), ci, rp), shape=(N * N, N * N)).toarray()
+    cf = W.convection_diffusion_2d_eigenvalues(N, gamma)
+    _assert_same_values(np.linalg.eigvals(A), cf, 1e-12 * np.abs(cf).max())
+    assert (np.abs(cf.imag).max() > 0.5) == (gamma > 1)
+    # and the oracle's subspace iteration on the CSR form finds the leading
+    # values of the closed form
+    r = O.subspace_eig_general((rp, ci, v), W.uniform_start(N * N, 24, 3), 4, degree=2, tol=1e-11,
+                               basis="hessenberg")
+    _assert_same_values(r.theta, _sorted_c(cf)[:4], 1e-9)

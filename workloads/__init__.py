@@ -11,6 +11,8 @@ from .generators import (  # noqa: F401
     goe_noise,
     svd_prescribed,
     laplacian_2d_csr,
+    convection_diffusion_2d_csr,
+    convection_diffusion_2d_eigenvalues,
     laplacian_2d_eigenvalues,
     uniform_start,
     batched_sizes,

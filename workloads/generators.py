@@ -106,6 +106,43 @@ def laplacian_2d_csr(N: int, dtype=np.float32):
     return row_ptr.astype(np.int32), col_idx, values
 
 
+def convection_diffusion_2d_csr(N: int, gamma: float, dtype=np.float32):
+    """Non-symmetric 5-point convection-diffusion operator on an N x N grid
+    (row = x + N*y): diagonal 4, -1 to the y neighbours, -(1 + gamma) to
+    x - 1 and -(1 - gamma) to x + 1 (central differences of a flow along x
+    with cell Peclet number gamma), CSR with sorted int32 column indices.
+    For gamma > 1 most eigenvalues are complex.  Returns (row_ptr, col_idx,
+    values)."""
+    n = N * N
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % N
+    y = idx // N
+    cols, vals = [], []
+    for dc, ok, v in ((-N, y > 0, -1.0), (-1, x > 0, -(1.0 + gamma)), (0, np.ones(n, bool), 4.0),
+                      (1, x < N - 1, -(1.0 - gamma)), (N, y < N - 1, -1.0)):
+        cols.append(np.where(ok, idx + dc, -1))
+        vals.append(np.where(ok, v, 0.0))
+    cols = np.stack(cols, axis=1)
+    vals = np.stack(vals, axis=1)
+    mask = cols >= 0
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=row_ptr[1:])
+    return row_ptr.astype(np.int32), cols[mask].astype(np.int32), vals[mask].astype(dtype)
+
+
+def convection_diffusion_2d_eigenvalues(N: int, gamma: float) -> np.ndarray:
+    """All eigenvalues of convection_diffusion_2d_csr(N, gamma): the sum of
+    the x part, a tridiagonal Toeplitz matrix (-(1+gamma), 2, -(1-gamma))
+    with eigenvalues 2 + 2 sqrt(1 - gamma^2) cos(p pi/(N+1)) (complex square
+    root), and the y part 2 - 2 cos(q pi/(N+1)) (textbook closed forms).
+    Complex, unsorted."""
+    j = np.arange(1, N + 1)
+    c = np.cos(j * np.pi / (N + 1))
+    ex = 2.0 + 2.0 * np.sqrt(complex(1.0 - gamma * gamma)) * c
+    ey = 2.0 - 2.0 * c
+    return (ex[:, None] + ey[None, :]).ravel()
+
+
 def laplacian_2d_eigenvalues(N: int) -> np.ndarray:
     """All eigenvalues of the N x N-grid Dirichlet 5-point Laplacian
     (textbook closed form 4 - 2 cos(p pi/(N+1)) - 2 cos(q pi/(N+1))),
