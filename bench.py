@@ -289,6 +289,106 @@ def bench_svd(args):
             "roofline": roofline, "cpu_baseline": cpu}
 
 
+def bench_general(args):
+    """Real non-symmetric dense A (n 16384, FP64 storage) = S D S^-1 with
+    moduli j^-1.5, half of the units conjugate pairs; the 64 eigenvalues of
+    largest modulus, basis 128, power filter of degree 2; BF16 basis with
+    the split-BF16 and sliced-INT8 FP64 phases against the FP64 form."""
+    import torch
+    import workloads as W
+    from paper_2505_00281_amd import ofrr
+    from oracle import ofrr_oracle as O
+    n, k, b, deg = 16384, 64, 128, 2
+    t = time.time()
+    reals, pairs, lam = W.general_power_law_spectrum(n, 1006)
+    A = W.general_prescribed(reals, pairs, 1007, nonnormal=0.3, dtype=torch.float64, device="cuda")
+    X0 = torch.from_numpy(W.uniform_start(n, b, 1107))
+    torch.cuda.synchronize()
+    log(f"[bench] general: generated A in {time.time() - t:.1f}s")
+    ctx = ofrr.Context(0)
+    common = dict(degree=deg, tol=TOL * 0.5, anorm=1.0, max_iters=300)
+    mixed_kw = dict(basis_dtype="bf16", refine=args.refine, stall_iters=args.stall_iters, tail=args.tail, **common)
+    steps = max(1, min(args.steps, 5))
+    res, ms = _timed_calls(lambda: ctx.eig_general(A, k, b, plan=ofrr.make_plan(**mixed_kw), X0=X0), steps,
+                           max(1, min(args.warmup, 2)), "general mixed")
+    fres, fms = None, None
+    if not args.no_fp64_form:
+        fres, fms = _timed_calls(lambda: ctx.eig_general(A, k, b, plan=ofrr.make_plan(basis_dtype="f64", **common),
+                                                         X0=X0), 2, 1, "general fp64")
+
+    def count(r):
+        # each returned value matched to the nearest unused prescribed one
+        th = r.evals.cpu().numpy()
+        res_ = r.resid.cpu().numpy()
+        pool = list(lam[:k + 8])
+        errs = []
+        for z in th:
+            d = np.abs(np.array(pool) - z)
+            j = int(np.argmin(d))
+            errs.append(d[j])
+            pool.pop(j)
+        errs = np.array(errs)  # |lambda_1| = 1: absolute = relative to the largest modulus
+        return int(((res_ <= TOL) & (errs <= 1e-10)).sum()), float(errs.max()), float(res_.max())
+
+    acc = [count(r) for r in res]
+    value = sum(a[0] for a in acc) / (ms * 1e-3 * len(res))
+    facc = count(fres[-1]) if fres else None
+    fvalue = facc[0] / (fms * 1e-3) if fres else None
+    ctx.kernel_stats_reset()
+    ctx.eig_general(A, k, b, plan=ofrr.make_plan(profile=True, **mixed_kw), X0=X0)
+    torch.cuda.synchronize()
+    fams = ["product_bf16", "product_bf16x2", "product_i8x", "product_reduce", "product_f64", "hessenberg",
+            "small_eig", "gram", "lift", "scale", "quantize", "residual"]
+    stats = {f: ctx.kernel_stats(f) for f in fams}
+    gemm = 2.0 * n * n * b
+    # method bytes per product: A read once as the phase stores it (BF16 copy;
+    # FP64 as stored for the FP64-class phases) + the basis + the output
+    alg = {"product_bf16": (n * n * 2 + n * b * 2 + n * b * 4, gemm, 2500.0, "bf16",
+                            "k_gemm_lp<bf16> (A V, A column-major read M-contiguous, BF16 MFMA, FP32 accumulate)"),
+           "product_bf16x2": (n * n * 2 + n * b * 2 + n * b * 4, gemm, 2500.0, "bf16",
+                              "k_gemm_lp<bf16, split A and V> (A V)"),
+           "product_i8x": (n * n * 8 + n * b * 16, gemm, 5000.0, "int8",
+                           "k_gemm_i8s (A V from INT8 digit planes of A's rows; FP64-class product)")}
+    dom = max(alg, key=lambda f: stats[f][1])
+    by, ops, pk, dt, kern = alg[dom]
+    roofline = _family_roof(ctx, dom, by, ops, pk, dt, kern)
+    roofline["per_family_ms_one_call"] = {f: round(t_, 3) for f, (n_, t_) in stats.items()}
+    cpu = None
+    if not args.no_oracle:
+        # CPU baseline: one outer iteration of the oracle (two products with
+        # MGS2 after each, classical Rayleigh-Ritz with the library's
+        # non-symmetric solver) on the host copy, scaled to the FP64 form's
+        # iteration count
+        Ah = A.cpu().numpy()
+        t = time.time()
+        O.subspace_eig_general(Ah, X0.numpy(), k, degree=deg, outer=1)
+        per_it = time.time() - t
+        iters_needed = (fres or res)[-1].info["iters"]
+        cpu = {"value": k / (per_it * iters_needed), "unit": "Ritz pairs/s", "cores": int(_cores()),
+               "kind": "oracle",
+               "sample": (f"one outer iteration of the oracle ({deg} products with MGS2 after each, Rayleigh-Ritz "
+                          f"with the library's non-symmetric eigensolver) on the same matrix, {per_it:.1f}s, scaled "
+                          f"to the {iters_needed} iterations the FP64 form needs (projected)")}
+    ctx.close()
+    return {"metric": "Ritz pairs/sec at residual <=1e-8, mixed vs FP64 form, 1 MI355X; % roofline",
+            "value": value, "unit": "Ritz pairs/s", "n_gpus": 1, "steps": len(res), "warmup": 1, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "dense real non-symmetric A = S D S^-1, n 16384 (FP64 storage), moduli j^-1.5 "
+                                   "with half the units conjugate pairs, S = Q (I + 0.3 N); 64 eigenvalues of largest "
+                                   "modulus, basis 128, power filter degree 2, BF16 basis with split-BF16 and "
+                                   "sliced-INT8 FP64 phases",
+                       "n": n, "k": k, "basis": b, "parallelism": "single GPU"},
+            "n_converged": [a[0] for a in acc], "iters": res[-1].info["iters"],
+            "iters_low": res[-1].info["iters_low"],
+            "accuracy": {"max_eval_err_vs_prescribed": max(a[1] for a in acc), "max_resid": max(a[2] for a in acc),
+                         "criterion": "residual <= 1e-8 and eigenvalue within 1e-10 of the prescribed one "
+                                      "(|lambda_1| = 1; A stored in FP64)"},
+            "fp64_form": ({"value": fvalue, "ms_per_step": fms, "iters": fres[-1].info["iters"],
+                           "n_converged": facc[0], "max_eval_err": facc[1]} if fres else None),
+            "speedup_vs_fp64_form": value / fvalue if fvalue else None,
+            "roofline": roofline, "cpu_baseline": cpu}
+
+
 def bench_laplacian(args):
     """CSR Dirichlet 5-point Laplacian on a 1024 x 1024 grid (n = 1,048,576);
     32 smallest eigenpairs, basis 64, degree-20 Chebyshev on [lambda_65, 8],
@@ -588,7 +688,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read + write) three times; "
                          "used to scale rocprofv3 FETCH_SIZE/WRITE_SIZE readings")
-    ap.add_argument("--workload", choices=["dense", "svd", "laplacian", "batched", "t3"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "svd", "laplacian", "batched", "t3", "general"], default="dense",
                     help="dense (default): the n=16384 eigenvalue workload of the headline metric; "
                          "svd: 65536 x 8192 FP8 SVD; laplacian: CSR 2-D Laplacian, 32 smallest; "
                          "batched: 512 problems n in [256, 4096]; t3: basis-generation processes at the "
@@ -614,7 +714,7 @@ def main():
     device = torch.device("cuda", 0)
     if args.workload != "dense":
         out = {"svd": bench_svd, "laplacian": bench_laplacian, "batched": bench_batched,
-               "t3": bench_t3}[args.workload](args)
+               "t3": bench_t3, "general": bench_general}[args.workload](args)
         print(json.dumps(out))
         return
     if args.traffic_probe:

@@ -1502,6 +1502,9 @@ PencilWork make_work(Context *ctx, int n) {
 // ---------------------------------------------------------------------------
 
 constexpr int GN_LOGW = 4;  // doubles per logged transform
+// C kept in LDS up to this size (136^2 FP64 = 145 KiB, with the static
+// arrays below the 160 KiB of a CU)
+constexpr int GN_LDS_MAX_N = 136;
 
 struct GenWork {
     double *L, *C, *Q, *X;  // n x n each (C may be replaced by an LDS copy)
@@ -1519,35 +1522,82 @@ __device__ __forceinline__ void gn_wave_sync() {
 }
 
 // rows r = r0 + i * stride of Q (col-major, n) times the logged transforms
-// [0, count), in order
+// [0, count), in order.  A transform at column k acts on columns k..k+2
+// (k, k+1 for a rotation); a bulge chase logs k, k+1, k+2, ..., so each
+// row keeps its three current columns in registers and slides them: one
+// load and one store per transform, the load of the column after the
+// window issued one transform ahead, the next entry read one ahead.
 __device__ void gn_apply_log(double *Q, int n, const double *lg, const int *lcode, int count, int r0,
                              int stride) {
     for (int r = r0; r < n; r += stride) {
+        double *q = Q + r;
+        int base = -1;
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, pre = 0.0;
+        int code = count > 0 ? lcode[0] : 0;
+        double v0 = count > 0 ? lg[0] : 0.0, v1 = count > 0 ? lg[1] : 0.0;
+        double v2 = count > 0 ? lg[2] : 0.0, beta = count > 0 ? lg[3] : 0.0;
         for (int e = 0; e < count; ++e) {
-            const int code = lcode[e];
+            // the next entry
+            const int en = e + 1 < count ? e + 1 : e;
+            const int code_n = lcode[en];
+            const double n0 = lg[GN_LOGW * en], n1 = lg[GN_LOGW * en + 1];
+            const double n2 = lg[GN_LOGW * en + 2], nb = lg[GN_LOGW * en + 3];
             const int k = code & 0xffff, m = code >> 16;
-            const double v0 = lg[GN_LOGW * e], v1 = lg[GN_LOGW * e + 1];
-            double *q0 = Q + r + (int64_t)k * n;
-            double *q1 = q0 + n;
-            if (m == 0) {
-                const double u = *q0, w = *q1;
-                *q0 = v0 * u + v1 * w;
-                *q1 = v0 * w - v1 * u;
-            } else {
-                const double v2 = lg[GN_LOGW * e + 2], beta = lg[GN_LOGW * e + 3];
-                double *q2 = q1 + n;
-                const double a = *q0, b = *q1, c = m == 3 ? *q2 : 0.0;
-                const double t = beta * (v0 * a + v1 * b + v2 * c);
-                *q0 = a - t * v0;
-                *q1 = b - t * v1;
-                if (m == 3) *q2 = c - t * v2;
+            if (base >= 0 && k == base + 1) {
+                q[(int64_t)base * n] = w0;
+                w0 = w1;
+                w1 = w2;
+                w2 = pre;
+                base = k;
+            } else if (k != base) {
+                if (base >= 0) {
+                    q[(int64_t)base * n] = w0;
+                    q[(int64_t)(base + 1) * n] = w1;
+                    if (base + 2 < n) q[(int64_t)(base + 2) * n] = w2;
+                }
+                base = k;
+                w0 = q[(int64_t)k * n];
+                w1 = q[(int64_t)(k + 1) * n];
+                w2 = k + 2 < n ? q[(int64_t)(k + 2) * n] : 0.0;
             }
+            // the column after the window, for a slide at the next entry
+            // (columns beyond the window are not touched before then)
+            pre = base + 3 < n ? q[(int64_t)(base + 3) * n] : 0.0;
+            if (m == 0) {
+                const double u = w0, w = w1;
+                w0 = v0 * u + v1 * w;
+                w1 = v0 * w - v1 * u;
+            } else {
+                const double t = beta * (v0 * w0 + v1 * w1 + (m == 3 ? v2 * w2 : 0.0));
+                w0 -= t * v0;
+                w1 -= t * v1;
+                if (m == 3) w2 -= t * v2;
+            }
+            code = code_n;
+            v0 = n0;
+            v1 = n1;
+            v2 = n2;
+            beta = nb;
+        }
+        if (base >= 0) {
+            q[(int64_t)base * n] = w0;
+            q[(int64_t)(base + 1) * n] = w1;
+            if (base + 2 < n) q[(int64_t)(base + 2) * n] = w2;
         }
     }
 }
 
+template <bool LDS>
+__device__ __forceinline__ void gn_sync() {
+    if (LDS)
+        wave_lds_sync();  // C in LDS: the wavefront's DS operations in order
+    else
+        gn_wave_sync();
+}
+
 // step 3 for wavefront 0: C (n x n, upper Hessenberg) -> T in place;
 // eigenvalues in diagonal order to w.wr, w.wi
+template <bool LDS>
 __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
     const int lane = threadIdx.x & 63;
     const double eps = 0x1p-52;
@@ -1557,20 +1607,38 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
         if (i <= j + 1) hn = fmax(hn, fabs(C[e]));
     }
     for (int o = 32; o > 0; o >>= 1) hn = fmax(hn, __shfl_xor(hn, o, 64));
-    int nn = n - 1, it = 0, total = 0, nlog = 0, fail = 0;
+    int nn = n - 1, it = 0, total = 0, nlog = 0, nbat = 0, fail = 0;
     const int itmax = 30 * (n > 10 ? n : 10);
-    auto logt = [&](int k, int m, double a0, double a1, double a2, double a3) {
-        if (lane == 0) {
-            double *p = w.lg + (int64_t)GN_LOGW * nlog;
-            p[0] = a0;
-            p[1] = a1;
-            p[2] = a2;
-            p[3] = a3;
-            w.lcode[nlog] = k | (m << 16);
+    // transforms are logged 64 at a time: lane j holds entry j of the batch
+    // in registers until the batch is written out with one store per lane
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    int pc = 0;
+    auto write_batch = [&]() {
+        if (lane < nbat) {
+            const int64_t idx = nlog - nbat + lane;
+            double *p = w.lg + (int64_t)GN_LOGW * idx;
+            p[0] = p0;
+            p[1] = p1;
+            p[2] = p2;
+            p[3] = p3;
+            w.lcode[idx] = pc;
         }
+        nbat = 0;
+    };
+    auto logt = [&](int k, int m, double a0, double a1, double a2, double a3) {
+        if (lane == nbat) {
+            p0 = a0;
+            p1 = a1;
+            p2 = a2;
+            p3 = a3;
+            pc = k | (m << 16);
+        }
+        ++nbat;
         ++nlog;
+        if (nbat == 64) write_batch();
         if (nlog == w.cap) {
             // log full: this wavefront applies it to Q now
+            write_batch();
             gn_wave_sync();
             gn_apply_log(w.Q, n, w.lg, w.lcode, nlog, lane, 64);
             gn_wave_sync();
@@ -1596,7 +1664,7 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
             }
         }
         if (l > 0 && lane == 0) C[l + (int64_t)(l - 1) * n] = 0.0;
-        gn_wave_sync();
+        gn_sync<LDS>();
         if (l == nn) {
             if (lane == 0) {
                 w.wr[nn] = C[nn + (int64_t)nn * n];
@@ -1623,13 +1691,13 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
                     C[a + (int64_t)c * n] = cs * u + sn * v;
                     C[b + (int64_t)c * n] = cs * v - sn * u;
                 }
-                gn_wave_sync();
+                gn_sync<LDS>();
                 for (int rr = lane; rr <= b; rr += 64) {
                     const double u = C[rr + (int64_t)a * n], v = C[rr + (int64_t)b * n];
                     C[rr + (int64_t)a * n] = cs * u + sn * v;
                     C[rr + (int64_t)b * n] = cs * v - sn * u;
                 }
-                gn_wave_sync();
+                gn_sync<LDS>();
                 if (lane == 0) {
                     C[b + (int64_t)a * n] = 0.0;
                     w.wr[a] = C[a + (int64_t)a * n];
@@ -1637,7 +1705,7 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
                     w.wr[b] = C[b + (int64_t)b * n];
                     w.wi[b] = 0.0;
                 }
-                gn_wave_sync();
+                gn_sync<LDS>();
                 logt(a, 0, cs, sn, 0.0, 0.0);
             } else if (lane == 0) {
                 w.wr[a] = w.wr[b] = t22 + p;
@@ -1674,49 +1742,88 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
         double x = h00 * h00 + h01 * h10 - s * h00 + t;
         double y = h10 * (h00 + h11 - s);
         double z = h10 * h21;
+        // with C in LDS (n <= 136: at most three rows per lane) the next
+        // step's x, y, z (column k, rows k+1..k+3 after the right update)
+        // come from the lanes that computed them
+        bool have_next = false;
+        double col0[3] = {0.0, 0.0, 0.0};
         for (int k = l; k <= nn - 1; ++k) {
             const int m = (k == nn - 1) ? 2 : 3;
             if (k > l) {
-                x = C[k + (int64_t)(k - 1) * n];
-                y = C[(k + 1) + (int64_t)(k - 1) * n];
-                z = (m == 3) ? C[(k + 2) + (int64_t)(k - 1) * n] : 0.0;
+                if (LDS && have_next) {
+                    auto pick = [&](int r) {
+                        const int it = r >> 6;
+                        const double v = it == 0 ? col0[0] : (it == 1 ? col0[1] : col0[2]);
+                        return readlane_f64(v, r & 63);
+                    };
+                    x = pick(k);
+                    y = pick(k + 1);
+                    z = (m == 3) ? pick(k + 2) : 0.0;
+                } else {
+                    x = C[k + (int64_t)(k - 1) * n];
+                    y = C[(k + 1) + (int64_t)(k - 1) * n];
+                    z = (m == 3) ? C[(k + 2) + (int64_t)(k - 1) * n] : 0.0;
+                }
             }
+            have_next = false;
             const double sc = fabs(x) + fabs(y) + fabs(z);
             if (sc == 0.0) continue;
-            const double xs = x / sc, ys = y / sc, zs = z / sc;
+            const double rs = 1.0 / sc;
+            const double xs = x * rs, ys = y * rs, zs = z * rs;
             const double nr = sqrt(xs * xs + ys * ys + zs * zs);
             const double alpha = -copysign(nr, xs);
             const double v0 = xs - alpha, v1 = ys, v2 = zs;
             const double beta = 1.0 / (alpha * (alpha - xs));
             const int c0 = (k > l) ? k - 1 : k;
             const int r1 = (k + 3 < nn) ? k + 3 : nn;
+            // left: rows k..k+2 from column c0 on (column k-1 of a chase step
+            // gets its exact result alpha sc, 0, 0)
             for (int c = c0 + lane; c < n; c += 64) {
                 double *p = C + k + (int64_t)c * n;
+                if (k > l && c == k - 1) {
+                    p[0] = alpha * sc;
+                    p[1] = 0.0;
+                    if (m == 3) p[2] = 0.0;
+                    continue;
+                }
                 const double a = p[0], b = p[1], cc = m == 3 ? p[2] : 0.0;
                 const double tt = beta * (v0 * a + v1 * b + v2 * cc);
                 p[0] = a - tt * v0;
                 p[1] = b - tt * v1;
                 if (m == 3) p[2] = cc - tt * v2;
             }
-            gn_wave_sync();
-            for (int r = lane; r <= r1; r += 64) {
-                double *p = C + r + (int64_t)k * n;
-                const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
-                const double tt = beta * (a * v0 + b * v1 + cc * v2);
-                p[0] = a - tt * v0;
-                p[n] = b - tt * v1;
-                if (m == 3) p[2 * n] = cc - tt * v2;
+            gn_sync<LDS>();
+            // right: columns k..k+2 of rows 0..r1
+            if (LDS) {
+#pragma unroll
+                for (int it = 0; it < 3; ++it) {
+                    const int r = lane + 64 * it;
+                    if (r <= r1) {
+                        double *p = C + r + (int64_t)k * n;
+                        const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
+                        const double tt = beta * (a * v0 + b * v1 + cc * v2);
+                        col0[it] = a - tt * v0;
+                        p[0] = col0[it];
+                        p[n] = b - tt * v1;
+                        if (m == 3) p[2 * n] = cc - tt * v2;
+                    }
+                }
+                have_next = true;
+            } else {
+                for (int r = lane; r <= r1; r += 64) {
+                    double *p = C + r + (int64_t)k * n;
+                    const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
+                    const double tt = beta * (a * v0 + b * v1 + cc * v2);
+                    p[0] = a - tt * v0;
+                    p[n] = b - tt * v1;
+                    if (m == 3) p[2 * n] = cc - tt * v2;
+                }
             }
-            if (k > l && lane == 0) {
-                C[k + (int64_t)(k - 1) * n] = alpha * sc;
-                C[(k + 1) + (int64_t)(k - 1) * n] = 0.0;
-                if (m == 3) C[(k + 2) + (int64_t)(k - 1) * n] = 0.0;
-            }
-            gn_wave_sync();
+            gn_sync<LDS>();
             logt(k, m, v0, v1, v2, beta);
         }
     }
-    gn_wave_sync();
+    write_batch();
     // the rest of the log: every thread applies it after the block barrier
     if (lane == 0) {
         status[0] = fail ? 2 : 0;
@@ -1818,17 +1925,18 @@ __device__ void gn_tri_vector(const double *T, int n, const double *wr, const do
     }
 }
 
+template <bool LDS>
 __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__restrict__ H,
                                                                const double *__restrict__ G, int n,
                                                                double *__restrict__ theta_re,
                                                                double *__restrict__ theta_im,
-                                                               double *__restrict__ Y, GenWork w, int *status,
-                                                               int use_lds) {
+                                                               double *__restrict__ Y, GenWork w, int *status) {
     extern __shared__ __attribute__((aligned(16))) double smem[];
     __shared__ double red[16];
     __shared__ int s_slot[SE_THREADS];
     const int t = threadIdx.x, T = blockDim.x, wave = t >> 6;
-    double *C = use_lds ? smem : w.C;
+    // C in LDS (n <= GN_LDS_MAX_N) or in the workspace
+    double *C = LDS ? smem : w.C;
     for (int e = t; e < n * n; e += T) {
         const int i = e % n, j = e / n;
         w.L[e] = 0.5 * (G[i + j * n] + G[j + i * n]);
@@ -1898,7 +2006,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
         __syncthreads();
     }
     // ---- 3. QR iteration (wavefront 0), then Q <- Q Z from the log
-    if (wave == 0) gn_francis(C, n, w, status);
+    if (wave == 0) gn_francis<LDS>(C, n, w, status);
     __syncthreads();
     if (status[0] != 0) {
         for (int i = t; i < n; i += T) {
@@ -2000,8 +2108,8 @@ void pencil_attributes(Context *ctx) {
                                  (int)fp_lds_bytes()));
     OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
-    OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_general, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
+    OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_general<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)((size_t)GN_LDS_MAX_N * GN_LDS_MAX_N * sizeof(double))));
     done.insert(ctx->device);
 }
 
@@ -2080,11 +2188,15 @@ const int32_t *pencil_general_async(Context *ctx, int32_t b, const double *H, co
     w.lg = ctx->buf<double>("gpencil_log", (size_t)GN_LOGW * w.cap);
     w.lcode = ctx->buf<int>("gpencil_lcode", (size_t)w.cap);
     int *status = ctx->buf<int>("gpencil_status", 4);
-    const int use_lds = b <= SE_LDS_MAX_N ? 1 : 0;
+    const int use_lds = b <= GN_LDS_MAX_N ? 1 : 0;
     const size_t shmem = use_lds ? nn * sizeof(double) : 0;
     KTimer tm(ctx, "small_eig");
-    hipLaunchKernelGGL(k_pencil_general, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b, theta_re,
-                       theta_im, Y, w, status, use_lds);
+    if (use_lds)
+        hipLaunchKernelGGL(k_pencil_general<true>, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b, theta_re,
+                           theta_im, Y, w, status);
+    else
+        hipLaunchKernelGGL(k_pencil_general<false>, dim3(1), dim3(SE_THREADS), 0, ctx->stream, H, G, b, theta_re,
+                           theta_im, Y, w, status);
     OFRR_HIP(hipGetLastError());
     return status;
 }

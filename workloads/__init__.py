@@ -17,6 +17,7 @@ from .generators import (  # noqa: F401
     uniform_start,
     batched_sizes,
     general_prescribed,
+    general_power_law_spectrum,
     kernel_points,
     kernel_subset,
     gaussian_kernel,

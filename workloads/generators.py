@@ -153,28 +153,64 @@ def laplacian_2d_eigenvalues(N: int) -> np.ndarray:
 
 def general_prescribed(real_eigs, complex_pairs, seed: int, nonnormal: float = 0.0,
                        dtype=torch.float64, device: str | torch.device = "cpu") -> torch.Tensor:
-    """Real non-symmetric A = S D S^-1 with D block diagonal: the given real
-    eigenvalues, and for each (a, b) in complex_pairs a 2 x 2 block
-    [[a, b], [-b, a]] (eigenvalues a +- ib).  S = Q (I + nonnormal N) with Q
-    Haar orthogonal and N strictly upper triangular N(0,1) / sqrt(n) (S = Q:
-    a normal matrix).  Assembled in FP64, column-major."""
-    reals = np.asarray(real_eigs, dtype=np.float64)
+    """Real non-symmetric A = S D S^-1 with D block diagonal: first, for each
+    (a, b) in complex_pairs, a 2 x 2 block [[a, b], [-b, a]] (eigenvalues
+    a +- ib), then the given real eigenvalues.  S = Q U with Q Haar
+    orthogonal and U = I + nonnormal N, N strictly upper triangular with
+    N(0, 1/n) entries (U = I: a normal matrix).  Assembled in FP64 on
+    `device` as Q (U D U^-1) Q^T and stored column-major in `dtype`."""
+    reals = torch.as_tensor(np.asarray(real_eigs, dtype=np.float64), device=device)
     pairs = np.asarray(complex_pairs, dtype=np.float64).reshape(-1, 2)
-    n = reals.size + 2 * pairs.shape[0]
-    D = np.zeros((n, n))
-    i = 0
-    for a, b in pairs:
-        D[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
-        i += 2
-    D[np.arange(i, n), np.arange(i, n)] = reals
-    q = haar_orthogonal(n, seed).numpy()
+    n = reals.numel() + 2 * pairs.shape[0]
+    q = haar_orthogonal(n, seed, device=device)
     if nonnormal:
-        N = np.triu(_normal((n, n), seed + 1), 1) / np.sqrt(n)
-        S = q @ (np.eye(n) + nonnormal * N)
+        u = torch.from_numpy(np.triu(_normal((n, n), seed + 1), 1)).to(device) * (nonnormal / math.sqrt(n))
+        u.diagonal().add_(1.0)
     else:
-        S = q
-    A = torch.from_numpy(S @ D) @ torch.linalg.inv(torch.from_numpy(S))
-    return A.to(dtype).T.contiguous().T.to(device)
+        u = torch.eye(n, dtype=torch.float64, device=device)
+    # T = U D: column operations
+    t = u.clone()
+    npair = pairs.shape[0]
+    if npair:
+        a = torch.as_tensor(pairs[:, 0], device=device)
+        b = torch.as_tensor(pairs[:, 1], device=device)
+        c0 = u[:, 0:2 * npair:2]
+        c1 = u[:, 1:2 * npair:2]
+        t[:, 0:2 * npair:2] = c0 * a - c1 * b
+        t[:, 1:2 * npair:2] = c0 * b + c1 * a
+    t[:, 2 * npair:] = u[:, 2 * npair:] * reals
+    # T U^-1 (U upper triangular), then Q T Q^T
+    t = torch.linalg.solve_triangular(u, t, upper=True, left=False)
+    del u
+    a_ = q @ t @ q.T
+    del q, t
+    return a_.to(dtype).T.contiguous().T
+
+
+def general_power_law_spectrum(n: int, seed: int, pair_fraction: float = 0.5):
+    """Eigenvalues for general_prescribed with moduli j^-1.5: walking j = 1,
+    2, ..., with probability pair_fraction a conjugate pair of modulus
+    j^-1.5 at an angle drawn from U(0.1 pi, 0.9 pi) (taking j and j + 1),
+    else a real value +-j^-1.5 with a random sign.  Returns (reals, pairs,
+    all n eigenvalues as complex, in the order drawn: moduli non-increasing,
+    a pair's + member first)."""
+    g = rng(seed)
+    reals, pairs, allv = [], [], []
+    j = 1
+    while j <= n:
+        m = float(j) ** -1.5
+        if j < n and g.random() < pair_fraction:
+            th = np.pi * (0.1 + 0.8 * g.random())
+            a, b = m * np.cos(th), m * np.sin(th)
+            pairs.append((a, b))
+            allv += [complex(a, b), complex(a, -b)]
+            j += 2
+        else:
+            v = m if g.random() < 0.5 else -m
+            reals.append(v)
+            allv.append(complex(v, 0.0))
+            j += 1
+    return reals, pairs, np.array(allv)
 
 
 def kernel_points(n: int, seed: int, d: int = 2) -> np.ndarray:
