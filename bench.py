@@ -392,7 +392,7 @@ def bench_general(args):
 def bench_laplacian(args):
     """CSR Dirichlet 5-point Laplacian on a 1024 x 1024 grid (n = 1,048,576);
     32 smallest eigenpairs, basis 64, degree-20 Chebyshev on [lambda_65, 8],
-    FP16 vectors with FP32 and FP64 phases after it; against the FP64 form."""
+    FP32 vectors with an FP64 tail; against the FP64 form."""
     import torch
     import workloads as W
     from paper_2505_00281_amd import ofrr
@@ -405,8 +405,11 @@ def bench_laplacian(args):
     mat = ofrr.csr_matrix(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), torch.from_numpy(v).cuda())
     ctx = ofrr.Context(0)
     common = dict(filter="chebyshev", degree=20, lo=float(ev[b]), hi=8.0, tol=TOL * 0.5, anorm=8.0,
-                  max_iters=3000, stall_iters=10)
-    mixed_kw = dict(basis_dtype="f16", refine=args.refine, **common)
+                  max_iters=3000)
+    # FP32 vectors, then the FP64 tail once the residual reaches the FP32
+    # level (a binary16 phase before it gains nothing here: the CSR steps
+    # read the FP32 master block either way)
+    mixed_kw = dict(basis_dtype="f32", refine=1, stall_iters=100, **common)
     steps = max(1, min(args.steps, 2))
     res, ms = _timed_calls(lambda: ctx.eig_partial(mat, k, b, which="smallest", plan=ofrr.make_plan(**mixed_kw),
                                                    X0=X0), steps, max(0, min(args.warmup, 1)), "laplacian mixed")
@@ -445,14 +448,14 @@ def bench_laplacian(args):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_spmm_cheb_scaled (CSR Chebyshev step with the product, the three-term combine and the "
-                          "column scaling fused; binary16 phase read from its FP32 master, rounded on load)",
+                          "column scaling fused)",
                 "family": "spmm", "avg_launch_ms": tot_ms / max(launches, 1), "launches": launches,
                 "algorithmic_bytes_per_launch": tot_bytes / max(launches, 1),
                 "algorithmic_bytes_per_step_by_storage": {sub[es]: step_bytes[es] for es in sub},
                 "per_storage": {sub[es]: {"launches": per[es][0], "avg_launch_ms": per[es][1] / max(per[es][0], 1),
                                           "GB_s": round(step_bytes[es] * per[es][0] / (per[es][1] * 1e-3) / 1e9, 1)
                                           if per[es][1] > 0 else None} for es in sub},
-                "dtype": "f16/f32/f64 phases"}
+                "dtype": "f32/f64 phases"}
     roofline["per_family_ms_one_call"] = {f: round(t_, 3) for f, (n_, t_) in stats.items()}
     # CPU baseline: a bounded sample, one outer iteration of the oracle with a
     # degree-10 filter (10 CSR products, MGS2 after each, Rayleigh-Ritz),
@@ -472,10 +475,11 @@ def bench_laplacian(args):
     ctx.close()
     return {"metric": "Ritz pairs/sec at residual <=1e-8, mixed vs FP64 form, 1 MI355X; % roofline",
             "value": value, "unit": "Ritz pairs/s", "n_gpus": 1, "steps": len(res), "warmup": 1, "ms_per_step": ms,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "sparse SPD 5-point 2-D Laplacian, 1024 x 1024 grid (n=1,048,576, CSR, FP32 "
-                                   "values); 32 smallest, degree-20 Chebyshev on [lambda_65, 8], basis 64, FP16 vectors",
-                       "n": n, "nnz": nnz, "k": k, "basis": b, "refine": args.refine, "parallelism": "single GPU"},
+                                   "values); 32 smallest, degree-20 Chebyshev on [lambda_65, 8], basis 64, FP32 vectors "
+                                   "with an FP64 tail",
+                       "n": n, "nnz": nnz, "k": k, "basis": b, "refine": 1, "parallelism": "single GPU"},
             "n_converged": [a[0] for a in acc], "iters": res[-1].info["iters"], "iters_low": res[-1].info["iters_low"],
             "products": res[-1].info["products"],
             "accuracy": {"max_rel_eval_err_vs_closed_form": max(a[1] for a in acc),

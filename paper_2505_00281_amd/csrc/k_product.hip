@@ -332,6 +332,38 @@ __global__ __launch_bounds__(256) void k_spmm_v(const int32_t *__restrict__ rp, 
     }
 }
 
+// VW consecutive columns of a row-major block: one 16-byte load (two FP64
+// or four FP32 values); the row's ld is a multiple of VW, so the load stays
+// inside the row even past the last used column
+template <class T, int VW>
+struct VecLd;
+template <>
+struct VecLd<double, 2> {
+    static __device__ __forceinline__ void get(const double *p, double *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLd<float, 2> {
+    static __device__ __forceinline__ void get(const float *p, float *o) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLd<float, 4> {
+    static __device__ __forceinline__ void get(const float *p, float *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
 // One Chebyshev step on CSR A with the recurrence's column scaling folded
 // in.  The scaled iteration brings the newest block Y1 to infinity-norm
 // (1/2, 1] per column by a power of two s (from the merged magnitude keys
@@ -344,7 +376,8 @@ __global__ __launch_bounds__(256) void k_spmm_v(const int32_t *__restrict__ rp, 
 // step's output Y2 = alpha (A Y1 - c Y1) - beta Y0 is written unscaled and
 // its column keys are merged into cmax_out for the next step; workgroup 0
 // records s for that step's p0 and clears the key array two steps ahead.
-template <class T, int RND, class TA>
+// A group of L lanes takes a row, each lane VW adjacent columns.
+template <class T, int RND, class TA, int VW>
 __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const TA *__restrict__ val, int64_t n_rows,
     int64_t n_cols, int64_t nnz, int b, int lanes_log2, const T *__restrict__ Y1, const T *__restrict__ Y0,
@@ -355,18 +388,18 @@ __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
     __shared__ ACC sc[512], pp[512];
     __shared__ unsigned km[512];
     const int t = threadIdx.x;
-    for (int j = t; j < b; j += 256) {
+    for (int j = t; j < 512; j += 256) {
         double f = 1.0;
-        if (cmax_in) {
+        if (j < b && cmax_in) {
             unsigned mb = cmax_in[j];
 #pragma unroll
             for (int q = 1; q < CM_COPIES; ++q) mb = max(mb, cmax_in[q * 512 + j]);
             f = key_scale<T>(mb);
         }
         sc[j] = (ACC)f;
-        pp[j] = p0 ? (ACC)p0[j] : (ACC)1;
+        pp[j] = (j < b && p0) ? (ACC)p0[j] : (ACC)1;
         km[j] = 0u;
-        if (blockIdx.x == 0 && s_out) s_out[j] = f;
+        if (j < b && blockIdx.x == 0 && s_out) s_out[j] = f;
     }
     if (blockIdx.x == 0 && clear)
         for (int e = t; e < CM_COPIES * 512; e += 256) clear[e] = 0u;
@@ -384,9 +417,15 @@ __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
         if (e0 < 0) e0 = 0;
         if (e1 > nnz) e1 = nnz;
         const int64_t cmx = n_cols - 1;
-        for (int j = 2 * li; j < b; j += 2 * L) {
-            const ACC s0 = sc[j], s1 = sc[j + 1 < b ? j + 1 : j];
-            ACC acc0 = (ACC)0, acc1 = (ACC)0;
+        for (int j = VW * li; j < b; j += VW * L) {
+            // (the scale arrays hold 512 entries: j + VW - 1 < 512 since
+            // b <= 512 and VW divides the row's ld)
+            ACC s[VW], acc[VW];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                s[v] = sc[j + v];
+                acc[v] = (ACC)0;
+            }
             int64_t e = e0;
             for (; e + 4 <= e1; e += 4) {
                 int64_t cc[4];
@@ -397,52 +436,44 @@ __global__ __launch_bounds__(256) void k_spmm_cheb_scaled(
                     cc[u] = q < 0 ? 0 : (q > cmx ? cmx : q);
                     a[u] = (ACC)val[e + u];
                 }
-                ACC x0[4], x1[4];
+                ACC x[4][VW];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) Pair<T>::get(Y1 + cc[u] * ld + j, x0[u], x1[u]);
+                for (int u = 0; u < 4; ++u) VecLd<T, VW>::get(Y1 + cc[u] * ld + j, x[u]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    acc0 = fma(a[u], spmm_round<RND>(x0[u] * s0), acc0);
-                    acc1 = fma(a[u], spmm_round<RND>(x1[u] * s1), acc1);
-                }
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) acc[v] = fma(a[u], spmm_round<RND>(x[u][v] * s[v]), acc[v]);
             }
             for (; e < e1; ++e) {
                 const int64_t q = ci[e];
                 const int64_t cc = q < 0 ? 0 : (q > cmx ? cmx : q);
                 const ACC a = (ACC)val[e];
-                ACC x0, x1;
-                Pair<T>::get(Y1 + cc * ld + j, x0, x1);
-                acc0 = fma(a, spmm_round<RND>(x0 * s0), acc0);
-                acc1 = fma(a, spmm_round<RND>(x1 * s1), acc1);
+                ACC x[VW];
+                VecLd<T, VW>::get(Y1 + cc * ld + j, x);
+#pragma unroll
+                for (int v = 0; v < VW; ++v) acc[v] = fma(a, spmm_round<RND>(x[v] * s[v]), acc[v]);
             }
             const int64_t o = row * ld + j;
-            const bool two = j + 1 < b;
-            ACC yc0, yc1, yp0 = (ACC)0, yp1 = (ACC)0;
-            Pair<T>::get(Y1 + o, yc0, yc1);
-            // a scaled step's Y1 is the stored (rounded) block; the first
-            // step's combine reads its input as it is, only the product
-            // reading it rounded
-            if (cmax_in) {
-                yc0 = spmm_round<RND>(yc0 * s0);
-                yc1 = spmm_round<RND>(yc1 * s1);
-            }
-            if (beta != 0.0) {
-                Pair<T>::get(Y0 + o, yp0, yp1);
-                const ACC q0 = yp0 * pp[j], q1 = yp1 * pp[two ? j + 1 : j];
-                yp0 = (round_prev ? spmm_round<RND>(q0) : q0) * s0;
-                yp1 = (round_prev ? spmm_round<RND>(q1) : q1) * s1;
-            }
-            double v0 = alpha * fma(-c, (double)yc0, (double)acc0);
-            if (beta != 0.0) v0 = fma(-beta, (double)yp0, v0);
-            const T w0 = (T)v0;
-            Y2[o] = w0;
-            if (cmax_out) atomicMax(&km[j], mag_key<T>((double)w0));
-            if (two) {
-                double v1 = alpha * fma(-c, (double)yc1, (double)acc1);
-                if (beta != 0.0) v1 = fma(-beta, (double)yp1, v1);
-                const T w1 = (T)v1;
-                Y2[o + 1] = w1;
-                if (cmax_out) atomicMax(&km[j + 1], mag_key<T>((double)w1));
+            ACC yc[VW], yp[VW];
+            VecLd<T, VW>::get(Y1 + o, yc);
+            if (beta != 0.0) VecLd<T, VW>::get(Y0 + o, yp);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                if (j + v >= b) break;
+                // a scaled step's Y1 is the stored (rounded) block; the first
+                // step's combine reads its input as it is, only the product
+                // reading it rounded
+                ACC ycv = yc[v];
+                if (cmax_in) ycv = spmm_round<RND>(ycv * s[v]);
+                double val2 = alpha * fma(-c, (double)ycv, (double)acc[v]);
+                if (beta != 0.0) {
+                    const ACC q = yp[v] * pp[j + v];
+                    const ACC ypv = (round_prev ? spmm_round<RND>(q) : q) * s[v];
+                    val2 = fma(-beta, (double)ypv, val2);
+                }
+                const T w = (T)val2;
+                Y2[o + v] = w;
+                if (cmax_out) atomicMax(&km[j + v], mag_key<T>((double)w));
             }
         }
     }
@@ -642,8 +673,11 @@ bool spmm_cheb_scaled(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype 
     const size_t es = phase == OFRR_F64 ? 8 : 4;
     if (!pair_aligned(Y1, ld, es) || !pair_aligned(Y2, ld, es) || (Y0 && !pair_aligned(Y0, ld, es))) return false;
     if (b > 512) return false;
+    // FP32 blocks: four columns per lane (16-byte loads) when the rows allow it
+    auto quad = [&](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
+    const bool vw4 = es == 4 && ld % 4 == 0 && quad(Y1) && quad(Y2) && quad(Y0);
     KTimer tm(ctx, phase == OFRR_F64 ? "spmm_f64" : phase == OFRR_F32 ? "spmm_f32" : "spmm_f16");
-    const int lg = spmm_lanes_log2(b);
+    const int lg = spmm_lanes_log2(vw4 ? (b + 1) / 2 : b);
     const int64_t rows_per = (int64_t)(256 >> lg) * SPMM_PASSES;
     const int64_t G = (A->rows + rows_per - 1) / rows_per;
     OFRR_CHECK_ARG(G < ((int64_t)1 << 31), "spmm: too many rows");
@@ -652,9 +686,18 @@ bool spmm_cheb_scaled(Context *ctx, const ofrr_matrix *A, int32_t b, ofrr_dtype 
         using T = std::remove_pointer_t<decltype(tag)>;
         using TA = std::remove_pointer_t<decltype(atag)>;
         constexpr int R = decltype(rnd)::value;
-        hipLaunchKernelGGL((k_spmm_cheb_scaled<T, R, TA>), dim3((unsigned)G), dim3(256), 0, ctx->stream, A->row_ptr,
-                           A->col_idx, (const TA *)A->values, A->rows, A->cols, A->nnz, b, lg, (const T *)Y1,
-                           (const T *)Y0, (T *)Y2, ld, alpha, c, beta, cmax_in, p0, rp, s_out, cmax_out, clear);
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(256), 0, ctx->stream, A->row_ptr, A->col_idx,
+                               (const TA *)A->values, A->rows, A->cols, A->nnz, b, lg, (const T *)Y1, (const T *)Y0,
+                               (T *)Y2, ld, alpha, c, beta, cmax_in, p0, rp, s_out, cmax_out, clear);
+        };
+        if constexpr (std::is_same<T, float>::value) {
+            if (vw4) {
+                launch(k_spmm_cheb_scaled<T, R, TA, 4>);
+                return;
+            }
+        }
+        launch(k_spmm_cheb_scaled<T, R, TA, 2>);
     };
     auto by_a = [&](auto *tag, auto rnd) {
         if (A->dtype == OFRR_F32) go(tag, rnd, (float *)nullptr);

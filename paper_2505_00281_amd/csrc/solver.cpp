@@ -189,6 +189,18 @@ struct EigRun {
     int i8_digits = 6;
 };
 
+// Residual level at which a reduced-precision phase hands over to the
+// next: plan.switch_resid when set; otherwise, for an FP32 phase, eight
+// units of FP32 rounding (9.5e-7 on the scale of anorm: its blocks cannot
+// represent a smaller residual), so that a slowly converging problem does
+// not leave it early on a pause of the stall rule.  Other phases leave on
+// the stall rule alone.
+double switch_level(const ofrr_plan *plan, const Phase &ph) {
+    if (plan->switch_resid > 0) return plan->switch_resid;
+    if (ph.basis == OFRR_F32) return 8.0 * std::ldexp(1.0, -23);
+    return -1.0;
+}
+
 // Digits per side for a sliced FP64 iteration, from the largest wanted
 // residual estimate of the iteration before it.  A product with S digits
 // per side is exact up to about 2^-7S of the row and column scales (four:
@@ -553,7 +565,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         if (last_phase && plan->tol > 0 && emax <= plan->tol && run.i8_digits == 6) break;
         if (!last_phase) {
             const bool stalled = stall_det.push(emax);
-            const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
+            const bool by_value = emax <= switch_level(plan, ph);
             if (stalled || by_value) {
                 // next phase: promote X for the FP64 tail; AX is recomputed by a
                 // product of the new phase in every case
@@ -810,7 +822,7 @@ ofrr_status eig_general_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         if (last_phase && plan->tol > 0 && emax <= plan->tol && run.i8_digits == 6) break;
         if (!last_phase) {
             const bool stalled = stall_det.push(emax);
-            const bool by_value = plan->switch_resid > 0 && emax <= plan->switch_resid;
+            const bool by_value = emax <= switch_level(plan, ph);
             if (stalled || by_value) {
                 if (phases[pi + 1].f64() && !ph.f64()) promote_block(ctx, n * ld, X);
                 ++pi;
