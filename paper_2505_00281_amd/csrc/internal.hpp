@@ -382,11 +382,13 @@ void pencil_general(Context *ctx, int32_t b, const double *H, const double *G, d
 
 // k_lift.hip
 // X = V Y[:, :nc], AX = W Y[:, :nc] (n x nc outputs, element type per xt),
-// optional residual partial sums ||AX_i - theta_i X_i||^2, ||X_i||^2.
-void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const void *V,
-          int64_t ldv, ofrr_dtype wt, const void *W, int64_t ldw, const double *Y, int32_t ldy,
-          const double *theta, ofrr_dtype xt, void *X, void *AX, int64_t ldx, double *res2,
-          double *xn2);
+// optional residual partial sums ||AX_i - theta_i X_i||^2, ||X_i||^2:
+// returns the number of partial rows written (row stride nc; at most
+// ceil(n / 64)), for residual_reduce.
+int64_t lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const void *V,
+             int64_t ldv, ofrr_dtype wt, const void *W, int64_t ldw, const double *Y, int32_t ldy,
+             const double *theta, ofrr_dtype xt, void *X, void *AX, int64_t ldx, double *res2,
+             double *xn2);
 // Chebyshev first step from X and AX: Y1 = alpha*(AX - c*X); or Y1 = AX
 // (power); output in type yt.
 void axpby_block(Context *ctx, int64_t n, int32_t b, ofrr_dtype it, const void *AX,

@@ -158,7 +158,7 @@ struct LiftVec<double> {
 
 constexpr int LF_LDK = 129;  // LDS row stride of the coefficients (128 columns + 1)
 
-template <class TI, class TO, bool TWO>
+template <class TI, class TO, bool TWO, int NQ>
 __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, int64_t ld1,
                                                    const TI *__restrict__ In2, int64_t ld2, int64_t n, int b,
                                                    int nc, const double *__restrict__ S, int lds,
@@ -170,14 +170,15 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
     typedef typename LiftVec<TI>::v4 v4;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, cl = lane & 15;
     constexpr bool two = TWO;
+    // NQ 16-column tiles (8 for nc <= 128, 4 for nc <= 64)
     // Y (column-major, leading dimension lds) into LDS as [k][c], zero-padded
-    // to kpad = 16 ceil(b / 16) rows and 128 columns, so every operand read
+    // to kpad = 16 ceil(b / 16) rows and 16 NQ columns, so every operand read
     // below is unconditional: consecutive threads read consecutive k of a
     // column (coalesced), eight loads in flight per thread; the odd row
     // stride spreads both the stores and the MFMA operand reads over the banks
     const int kpad = (b + 15) / 16 * 16;
     {
-        const int tot = kpad * 128;
+        const int tot = kpad * 16 * NQ;
         for (int e0 = 0; e0 < tot; e0 += 256 * 8) {
             double v[8];
 #pragma unroll
@@ -198,25 +199,28 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
     // the workgroup lifts 64-row blocks blockIdx.x, + gridDim.x, ... with the
     // coefficients staged once (a grid of at most a few workgroups per CU)
     const int64_t nblk = (n + 63) / 64;
+    // residual partials of this workgroup's blocks (thread t < nc: column t),
+    // summed over its blocks in order and written once
+    double racc = 0.0, xacc = 0.0;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t rowA = blk * 64 + 16 * wave + cl;  // this lane's operand row
     const bool rok = rowA < n;
     const int ntile = (nc + 15) / 16;
-    lf_f64x4_t acc1[8], acc2[8];
+    lf_f64x4_t acc1[NQ], acc2[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc1[q] = acc2[q] = lf_f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NQ; ++q) acc1[q] = acc2[q] = lf_f64x4_t{0.0, 0.0, 0.0, 0.0};
     // K blocks of 16; lane group g takes the block's entries 4g .. 4g + 3
     auto mfma_block = [&](int k0, const double (&a1)[4], const double (&a2)[4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * g + s;
-            // all eight column tiles (the padding is zero): the operand reads
+            // all NQ column tiles (the padding is zero): the operand reads
             // are static and unconditional, so they are issued together
-            double yq[8];
+            double yq[NQ];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) yq[q] = Ys[k * LF_LDK + 16 * q + cl];
+            for (int q = 0; q < NQ; ++q) yq[q] = Ys[k * LF_LDK + 16 * q + cl];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 acc1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], yq[q], acc1[q], 0, 0, 0);
                 if constexpr (TWO) acc2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], yq[q], acc2[q], 0, 0, 0);
             }
@@ -271,11 +275,11 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
     }
     // outputs, and the residual partials of this 64-row block
     const int64_t rbase = blk * 64 + 16 * wave + g;  // + 4 r
-    double r2[8], x2[8];
+    double r2[NQ], x2[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) r2[q] = x2[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) r2[q] = x2[q] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int c = 16 * q + cl;
         if (q >= ntile || c >= nc) continue;
         const double th = res2 ? theta[c] : 0.0;
@@ -294,7 +298,7 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
     if (res2) {
         // over the four lane groups (fixed butterfly), then the four waves
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             r2[q] += __shfl_xor(r2[q], 16, 64);
             r2[q] += __shfl_xor(r2[q], 32, 64);
             x2[q] += __shfl_xor(x2[q], 16, 64);
@@ -302,20 +306,22 @@ __global__ __launch_bounds__(256) void k_lift_mfma(const TI *__restrict__ In1, i
         }
         if (g == 0) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 red[0][wave][16 * q + cl] = r2[q];
                 red[1][wave][16 * q + cl] = x2[q];
             }
         }
         __syncthreads();
         if (t < nc) {
-            const double a = (red[0][0][t] + red[0][1][t]) + (red[0][2][t] + red[0][3][t]);
-            const double c = (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
-            res2[blk * nc + t] = a;
-            xn2[blk * nc + t] = c;
+            racc += (red[0][0][t] + red[0][1][t]) + (red[0][2][t] + red[0][3][t]);
+            xacc += (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
         }
         __syncthreads();  // red is rewritten by the next block
     }
+    }
+    if (res2 && t < nc) {
+        res2[(int64_t)blockIdx.x * nc + t] = racc;
+        xn2[(int64_t)blockIdx.x * nc + t] = xacc;
     }
 }
 
@@ -550,11 +556,12 @@ inline int grid1(int64_t total) {
 
 }  // namespace
 
-void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const void *V,
-          int64_t ldv, ofrr_dtype wt, const void *W, int64_t ldw, const double *Y, int32_t ldy,
-          const double *theta, ofrr_dtype xt, void *X, void *AX, int64_t ldx, double *res2,
-          double *xn2) {
+int64_t lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const void *V,
+             int64_t ldv, ofrr_dtype wt, const void *W, int64_t ldw, const double *Y, int32_t ldy,
+             const double *theta, ofrr_dtype xt, void *X, void *AX, int64_t ldx, double *res2,
+             double *xn2) {
     KTimer tm(ctx, "lift");
+    int64_t prow = (n + 63) / 64;  // rows of residual partials written
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nc + 63) / 64));
     if (vt != wt && W != nullptr) {
         // mixed input types: lift the two products separately
@@ -563,7 +570,7 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
         lift(ctx, n, b, nc, wt, W, ldw, wt, nullptr, 0, Y, ldy, nullptr, xt, AX, nullptr, ldx,
              nullptr, nullptr);
         OFRR_CHECK_ARG(res2 == nullptr, "lift: residual partials need one input type");
-        return;
+        return 0;
     }
     // FP64 MFMA path when the coefficients fit one LDS stage and the input is
     // FP32 or FP64 (whose residual partials use the same 64-row blocks)
@@ -588,14 +595,22 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
                         const int64_t nblk = (n + 63) / 64;
                         const int64_t cap = 2LL * (ctx->cu_count > 0 ? ctx->cu_count : 256);
                         const unsigned gl = (unsigned)(nblk < cap ? nblk : cap);
+                        prow = gl;
                         hipLaunchKernelGGL(kernel, dim3(gl), dim3(256), shmem, ctx->stream,
                                            (const TI *)V, ldv, (const TI *)W, ldw, n, b, nc, Y, ldy, theta,
                                            (TO *)X, (TO *)AX, ldx, res2, xn2);
                     };
-                    if (W)
-                        launch(k_lift_mfma<TI, TO, true>);
-                    else
-                        launch(k_lift_mfma<TI, TO, false>);
+                    if (nc <= 64) {
+                        if (W)
+                            launch(k_lift_mfma<TI, TO, true, 4>);
+                        else
+                            launch(k_lift_mfma<TI, TO, false, 4>);
+                    } else {
+                        if (W)
+                            launch(k_lift_mfma<TI, TO, true, 8>);
+                        else
+                            launch(k_lift_mfma<TI, TO, false, 8>);
+                    }
                 });
             }
         });
@@ -611,6 +626,7 @@ void lift(Context *ctx, int64_t n, int32_t b, int32_t nc, ofrr_dtype vt, const v
         });
     }
     OFRR_HIP(hipGetLastError());
+    return prow;
 }
 
 void residual_reduce(Context *ctx, const double *res2, const double *xn2, int nblk, int stride,

@@ -516,7 +516,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             const int32_t *rank_dev = pencil_eig_async(ctx, bc, H, G, which, theta, Yr);
             if (f32_gram) gram_condition(ctx, bc, G, Yr, rank_dev, rest + k + 3);
             // ---- lift (X = V Y, AX = W Y) with residual estimates
-            lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
+            const int64_t prow = lift(ctx, n, bc, bc, mt, V, ld, mt, W, ld, Yr, bc, theta, mt, X, AX, ld, res2, xn2);
             // residual estimates of the k wanted pairs
             if (plan->anorm <= 0) {
                 std::vector<double> th((size_t)bc);
@@ -527,7 +527,7 @@ ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                 for (double v : th) m = std::max(m, std::fabs(v));
                 anorm_used = m > 0 ? m : 1.0;
             }
-            residual_reduce(ctx, res2, xn2, (int)nblk, bc, k, anorm_used, rest, rank_dev,
+            residual_reduce(ctx, res2, xn2, (int)prow, bc, k, anorm_used, rest, rank_dev,
                             first ? hstat : nullptr);
             stage = ctx->host_stage<double>((size_t)k + 4);
             const int nread = f32_gram ? k + 4 : k + (first ? 3 : 1);
