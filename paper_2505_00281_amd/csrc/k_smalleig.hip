@@ -11,7 +11,10 @@
 //                C = L_U^{-1} B L_V^{-T}; the positive eigenvalues of
 //                [0 C; C^T 0] are the singular values, with unit eigenvectors
 //                [u; v] / sqrt(2); y = L_U^{-T} u / sqrt(2),
-//                z = L_V^{-T} v / sqrt(2) meet [y; z]^T M [y; z] = 1.
+//                z = L_V^{-T} v / sqrt(2) meet [y; z]^T M [y; z] = 1.  The
+//                SVD of C comes from one-sided Jacobi (relative accuracy of
+//                the singular values; one or two sweeps once C is nearly
+//                diagonal, as it is for a converging subspace).
 //
 // Symmetric eigen-decomposition, organised for one 1024-thread workgroup:
 //   1. Householder reduction to tridiagonal form T = Q^T C Q (the matrix in
@@ -613,6 +616,101 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
     }
 }
 
+// One-sided (Hestenes) Jacobi SVD of M (m x q, column-major, m >= q,
+// m <= 1024): the columns are rotated in pairs until every pair is
+// orthogonal to tol, so that M V = U Sigma with orthogonal V (q x q,
+// accumulated here).  Pairs follow a round-robin tournament (every pair
+// once per sweep, q/2 disjoint pairs per step, a half wavefront per pair
+// with the lanes over rows); a sweep without a rotation ends the iteration.  The
+// singular values come out with high relative accuracy, and a nearly
+// diagonal start (the projected matrix of a converging subspace) needs one
+// or two sweeps.  Returns the number of sweeps.
+// One step of the tournament: pair pr goes to the 32-lane group pr mod 32
+// (a half wavefront; the lanes hold rows l + 32 u), so 32 pairs are in
+// flight at once.
+__device__ __forceinline__ double half_wave_sum(double v) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int MAXR>
+__device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, int step, double tol, int *s_rot) {
+    const int t = threadIdx.x, T = blockDim.x, grp = t >> 5, gl = t & 31, ng = T >> 5;
+    auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + step) % (mm - 1)) + 1; };
+    for (int pr = grp; pr < mm / 2; pr += ng) {
+        int i = pos(pr), j = pos(mm - 1 - pr);
+        if (i > j) {
+            const int x = i;
+            i = j;
+            j = x;
+        }
+        if (j >= q) continue;  // the dummy slot of an odd q
+        double *gi = M + (int64_t)i * m, *gj = M + (int64_t)j * m;
+        double *vi = V + (int64_t)i * q, *vj = V + (int64_t)j * q;
+        double a[MAXR], b[MAXR], c[MAXR], d[MAXR];
+#pragma unroll
+        for (int u = 0; u < MAXR; ++u) {
+            const int r = gl + 32 * u;
+            a[u] = r < m ? gi[r] : 0.0;
+            b[u] = r < m ? gj[r] : 0.0;
+            c[u] = r < q ? vi[r] : 0.0;
+            d[u] = r < q ? vj[r] : 0.0;
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < MAXR; ++u) {
+            al += a[u] * a[u];
+            be += b[u] * b[u];
+            ga += a[u] * b[u];
+        }
+        al = half_wave_sum(al);
+        be = half_wave_sum(be);
+        ga = half_wave_sum(ga);
+        if (!(fabs(ga) > tol * sqrt(al * be))) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+        for (int u = 0; u < MAXR; ++u) {
+            const int r = gl + 32 * u;
+            if (r < m) {
+                gi[r] = cs * a[u] - sn * b[u];
+                gj[r] = sn * a[u] + cs * b[u];
+            }
+            if (r < q) {
+                vi[r] = cs * c[u] - sn * d[u];
+                vj[r] = sn * c[u] + cs * d[u];
+            }
+        }
+        if (gl == 0) atomicAdd(s_rot, 1);
+    }
+}
+
+__device__ int jacobi_svd(double *M, int m, int q, double *V, int *s_rot) {
+    const int t = threadIdx.x, T = blockDim.x;
+    for (int e = t; e < q * q; e += T) V[e] = (e % q == e / q) ? 1.0 : 0.0;
+    const int mm = q + (q & 1);
+    const double tol = 0x1p-52 * sqrt((double)m);
+    int sweep = 0;
+    __syncthreads();
+    for (; sweep < 40; ++sweep) {
+        if (t == 0) *s_rot = 0;
+        __syncthreads();
+        for (int step = 0; step < mm - 1; ++step) {
+            if (m <= 256)
+                jacobi_rotate_pairs<8>(M, m, V, q, mm, step, tol, s_rot);
+            else
+                jacobi_rotate_pairs<32>(M, m, V, q, mm, step, tol, s_rot);
+            __syncthreads();
+        }
+        const int nrot = *s_rot;
+        __syncthreads();
+        if (nrot == 0) break;
+    }
+    return sweep + 1;
+}
+
 __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restrict__ B, int k1,
                                                            int k2, const double *__restrict__ MU,
                                                            const double *__restrict__ MV,
@@ -654,27 +752,51 @@ __global__ __launch_bounds__(SE_THREADS) void k_svd_pencil(const double *__restr
     }
     __syncthreads();
     trsm_lower(LU, k1, w.L, k2);
-    // augmented symmetric [0 Cm; Cm^T 0] (N x N)
-    for (int e = t; e < N * N; e += T) {
-        const int i = e % N, j = e / N;
-        double v = 0.0;
-        if (i < k1 && j >= k1) v = w.L[i + (j - k1) * k1];
-        if (i >= k1 && j < k1) v = w.L[j + (i - k1) * k1];
-        w.C[e] = v;
+    // SVD of Cm = U Sigma V^T (the positive eigenpairs of [0 Cm; Cm^T 0] are
+    // (sigma, [u; v] / sqrt 2)) by one-sided Jacobi on the taller of Cm and
+    // Cm^T
+    const bool swap = k1 < k2;
+    const int m = swap ? k2 : k1, q = swap ? k1 : k2;
+    double *M = w.L;
+    if (swap) {
+        for (int e = t; e < k1 * k2; e += T) {
+            const int i = e % k2, j = e / k2;  // M[i + j*k2] = Cm[j + i*k1]
+            w.T[i + j * k2] = w.L[j + i * k1];
+        }
+        M = w.T;
+    }
+    __shared__ int s_rot;
+    (void)jacobi_svd(M, m, q, w.Z, &s_rot);
+    // column norms = singular values, descending
+    for (int j = t; j < q; j += T) {
+        double s2 = 0.0;
+        for (int r = 0; r < m; ++r) s2 += M[r + (int64_t)j * m] * M[r + (int64_t)j * m];
+        w.w[j] = sqrt(s2);
     }
     __syncthreads();
-    sym_eig(w.C, N, w.w, w.Z, w.ek, red);
-    sort_order(w.w, N, true, w.ord);
-    const int r = k1 < k2 ? k1 : k2;
-    // top r (positive) eigenpairs: u part (k1), v part (k2) of unit eigvecs
+    sort_order(w.w, q, true, w.ord);
+    const int r = q;
     for (int c = t; c < r; c += T) sigma[c] = w.w[w.ord[c]];
-    for (int e = t; e < k1 * r; e += T) {
-        const int row = e % k1, c = e / k1;
-        Yo[row + c * k1] = w.Z[row + w.ord[c] * N];
+    // left singular vectors u = M_j / sigma_j (length m), right v = V_j
+    // (length q); [y; z] = [u; v] / sqrt 2 before the L^{-T} transforms
+    const double h = 0.70710678118654752440;
+    for (int e = t; e < m * r; e += T) {
+        const int row = e % m, c = e / m;
+        const int j = w.ord[c];
+        const double sj = w.w[j];
+        const double uv = sj > 0.0 ? M[row + (int64_t)j * m] / sj * h : 0.0;
+        if (swap)
+            Zo[row + c * k2] = uv;
+        else
+            Yo[row + c * k1] = uv;
     }
-    for (int e = t; e < k2 * r; e += T) {
-        const int row = e % k2, c = e / k2;
-        Zo[row + c * k2] = w.Z[k1 + row + w.ord[c] * N];
+    for (int e = t; e < q * r; e += T) {
+        const int row = e % q, c = e / q;
+        const double vv = w.Z[row + (int64_t)w.ord[c] * q] * h;
+        if (swap)
+            Yo[row + c * k1] = vv;
+        else
+            Zo[row + c * k2] = vv;
     }
     __syncthreads();
     trsm_lower_t(LU, k1, Yo, r);

@@ -493,12 +493,12 @@ def test_pencil_eig_indefinite_mass_falls_back(ctx):
     assert theta[7] == 0.0
 
 
-@pytest.mark.parametrize("k1,k2", [(8, 6), (16, 16), (40, 25)])
+@pytest.mark.parametrize("k1,k2", [(8, 6), (16, 16), (40, 25), (25, 40), (200, 200), (200, 171)])
 def test_svd_pencil(ctx, k1, k2):
     rng = np.random.default_rng(11)
-    A = rng.standard_normal((300, 120))
+    A = rng.standard_normal((300, 240))
     U = rng.standard_normal((300, k1))
-    V = rng.standard_normal((120, k2))
+    V = rng.standard_normal((240, k2))
     B, MU, MV = U.T @ A @ V, U.T @ U, V.T @ V
     print("svd pencil", k1, k2, flush=True)
     s, Y, Z = ctx.svd_pencil(_cuda(B), _cuda(MU), _cuda(MV))
@@ -508,3 +508,5 @@ def test_svd_pencil(ctx, k1, k2):
     Ut, Vt = np.sqrt(2) * U @ Y, np.sqrt(2) * V @ Z
     np.testing.assert_allclose(Ut.T @ Ut, np.eye(min(k1, k2)), atol=1e-9)
     np.testing.assert_allclose(Vt.T @ Vt, np.eye(min(k1, k2)), atol=1e-9)
+    # the left and right vectors belong together: 2 Y^T B Z = diag(sigma)
+    np.testing.assert_allclose(2.0 * Y.T @ B @ Z, np.diag(s), atol=1e-9 * s[0])
