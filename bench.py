@@ -217,7 +217,8 @@ def _family_roof(ctx, fam, bytes_per_launch, ops_per_launch, peak_mfma, dtype, k
 def bench_svd(args):
     """65536 x 8192 FP32 A = U diag(exp(-i/200)) V^T; top 100 singular
     triplets, basis 200; FP8 e4m3 basis build with 32 x 32 block scales,
-    FP64 tail; against the FP64 form of the same method."""
+    FP64-class tail (INT8 digit-plane products by default); against the
+    FP64 form of the same method."""
     import torch
     import workloads as W
     from paper_2505_00281_amd import ofrr
@@ -230,7 +231,7 @@ def bench_svd(args):
     torch.cuda.synchronize()
     log(f"[bench] svd: generated A in {time.time() - t:.1f}s")
     ctx = ofrr.Context(0)
-    mixed_kw = dict(basis_dtype="f8e4m3", refine=1, tol=TOL * 0.5, max_iters=300, stall_iters=3)
+    mixed_kw = dict(basis_dtype="f8e4m3", refine=1, tol=TOL * 0.5, max_iters=300, stall_iters=3, tail=args.tail)
     steps = max(1, min(args.steps, 5))
     res, ms = _timed_calls(lambda: ctx.svd_partial(A, k, b, plan=ofrr.make_plan(**mixed_kw), V0=V0), steps,
                            max(1, min(args.warmup, 2)), "svd mixed")
@@ -258,7 +259,8 @@ def bench_svd(args):
     ctx.kernel_stats_reset()
     ctx.svd_partial(A, k, b, plan=ofrr.make_plan(profile=True, **mixed_kw), V0=V0)
     torch.cuda.synchronize()
-    fams = ["product_f8", "product_f64", "hessenberg", "small_eig", "gram", "lift", "scale", "quantize", "residual"]
+    fams = ["product_f8", "product_i8x", "product_reduce", "product_f64", "hessenberg", "small_eig", "gram", "lift",
+            "scale", "quantize", "residual"]
     stats = {f: ctx.kernel_stats(f) for f in fams}
     f8_bytes = m * n + (m // 32) * (n // 32) * 4 + (m + n) * b + max(m, n) * b * 4
     roofline = _family_roof(ctx, "product_f8", f8_bytes, 2.0 * m * n * b, 5000.0, "fp8",
@@ -283,7 +285,8 @@ def bench_svd(args):
             "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp8",
             "data": "synthetic",
             "config": {"workload": "dense SVD 65536 x 8192, FP32 A = U diag(exp(-i/200)) V^T; top k=100, basis 200, "
-                                   "FP8 e4m3 basis build with 32x32 block scales, FP64 tail",
+                                   "FP8 e4m3 basis build with 32x32 block scales, FP64-class tail "
+                                   f"({'INT8 digit-plane products' if args.tail == 'i8' else 'FP64 products'})",
                        "m": m, "n": n, "k": k, "basis": b, "parallelism": "single GPU"},
             "n_converged": [a[0] for a in acc], "iters": res[-1].info["iters"], "iters_low": res[-1].info["iters_low"],
             "accuracy": {"max_rel_sigma_diff_vs_fp64_form": max(a[1] for a in acc),

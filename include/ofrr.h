@@ -136,8 +136,9 @@ typedef struct {
                                 term split (hi + lo) through the MFMA, 1 rounds it once */
     int32_t profile;         /* nonzero: time every kernel launch with HIP events */
     int32_t tail_product;    /* ofrr_tail: products of the FP64 phase after reduced-precision
-                                phases (refine >= 1, dense A); the FP64 form (basis_dtype F64)
-                                always runs FP64 arithmetic */
+                                phases (refine >= 1, dense A; ofrr_eig_partial,
+                                ofrr_eig_general and ofrr_svd_partial); the FP64 form
+                                (basis_dtype F64) always runs FP64 arithmetic */
     double gram_switch_t;    /* FP32 gram_accum: a projection is accumulated in FP64 instead
                                 when the conditioning statistic of the previous iteration's
                                 mass matrix, t(G) = sum_i G_ii (G^-1)_ii / b (t = 1 for a

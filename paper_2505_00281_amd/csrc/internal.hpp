@@ -298,7 +298,9 @@ struct SlicedA {
     int32_t *ex = nullptr;     // per-row exponent bounds (mpad)
     int64_t m = 0, kdim = 0, mpad = 0, kpad = 0, plane_stride = 0;
 };
-SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans);
+// tag names the workspace buffers of the planes (two slicings of one A,
+// e.g. its rows and its columns, need two tags)
+SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans, const char *tag = "i8_a");
 // digits: signed 7-bit digits per side (6: 21 digit pairs, exact to about
 // 2^-42 of the row and column scales; 5: 15 pairs, 2^-35; 4: 10 pairs, 2^-28)
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,

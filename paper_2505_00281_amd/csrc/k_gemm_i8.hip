@@ -26,6 +26,8 @@
 // MFMA v_mfma_i32_32x32x32_i8: lane l holds A[l%32][16(l/32)..+16] and
 // B[16(l/32)..+16][l%32] (any consistent K order is exact for integers);
 // accumulator register r is D[(r/4)*8 + 4(l/32) + r%4][l%32].
+#include <string>
+
 #include "internal.hpp"
 #include "device_util.hpp"
 
@@ -374,7 +376,7 @@ inline int grid1(int64_t total) {
 
 }  // namespace
 
-SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
+SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans, const char *tag) {
     OFRR_CHECK_ARG(A->format == OFRR_DENSE_COLMAJOR, "sliced product: dense A");
     OFRR_CHECK_ARG(A->dtype == OFRR_F32 || A->dtype == OFRR_F64, "sliced product: A is F32 or F64");
     SlicedA s;
@@ -383,8 +385,8 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans) {
     s.mpad = (s.m + I8_BM - 1) / I8_BM * I8_BM;
     s.kpad = (s.kdim + I8_BK - 1) / I8_BK * I8_BK;
     s.plane_stride = s.mpad * s.kpad;
-    s.planes = ctx->buf<int8_t>("i8_a_planes", (size_t)I8_S * s.plane_stride);
-    s.ex = ctx->buf<int32_t>("i8_a_exp", (size_t)s.mpad);
+    s.planes = ctx->buf<int8_t>(std::string(tag) + "_planes", (size_t)I8_S * s.plane_stride);
+    s.ex = ctx->buf<int32_t>(std::string(tag) + "_exp", (size_t)s.mpad);
     KTimer tm(ctx, "quantize");
     auto go = [&](auto kern, auto p) {
         hipLaunchKernelGGL(kern, dim3((unsigned)s.mpad), dim3(256), 0, ctx->stream, p, A->ld, s.m, s.mpad,

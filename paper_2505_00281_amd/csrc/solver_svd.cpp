@@ -73,6 +73,17 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         }
     }
 
+    // FP64 tail with products from exact INT8 digit planes (six digits per
+    // side, about 2^-42 of the row and column scales): A's rows for A V and
+    // its columns for A^T U, sliced once
+    const bool sliced = plan->tail_product == OFRR_TAIL_I8_SLICED && phases.back() == OFRR_F64 &&
+                        phases.size() > 1 && (A->dtype == OFRR_F32 || A->dtype == OFRR_F64);
+    SlicedA A_rows, A_cols;
+    if (sliced) {
+        A_rows = slice_matrix_i8(ctx, A, 0, "svd_i8_rows");
+        A_cols = slice_matrix_i8(ctx, A, 1, "svd_i8_cols");
+    }
+
     const size_t bm = (size_t)m * ld, bn = (size_t)n * ld;
     void *Ub = ctx->buf<double>("svd_U", bm);
     void *T1 = ctx->buf<double>("svd_T1", bm);
@@ -117,7 +128,10 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         ++products;
         const int64_t rows = trans ? n : m, cols = trans ? m : n;
         if (phases[pi] == OFRR_F64) {
-            product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
+            if (sliced)
+                product_i8s(ctx, trans ? A_cols : A_rows, bc, (const double *)X, ld, (double *)Wout, ld);
+            else
+                product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
         } else if (phases[pi] == OFRR_F8E4M3) {
             // basis quantised per product: one scale per 32 rows of each column
             uint8_t *vc = reinterpret_cast<uint8_t *>(vh);

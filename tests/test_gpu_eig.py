@@ -289,24 +289,26 @@ def test_svd_converged_fp64(ctx):
     assert r.resid.cpu().numpy().max() <= 2e-12
 
 
-@pytest.mark.parametrize("lowp", ["bf16", "f16", "f8e4m3"])
-def test_svd_mixed_refined_converged(ctx, lowp):
+@pytest.mark.parametrize("lowp,tail", [("bf16", "f64"), ("f16", "f64"), ("f8e4m3", "f64"), ("f8e4m3", "i8"),
+                                       ("bf16", "i8")])
+def test_svd_mixed_refined_converged(ctx, lowp, tail):
+    # tail i8: the FP64 phase's A V and A^T U from exact INT8 digit planes
     m, n, b, k = 1500, 400, 24, 10
     sig = np.exp(-np.arange(1, n + 1) / 40.0)
     A = W.svd_prescribed(m, n, sig, 43, dtype=torch.float32)
     Ad = A.double().numpy()
     s_ref = np.linalg.svd(Ad, compute_uv=False)
-    print("svd mixed", lowp, flush=True)
+    print("svd mixed", lowp, tail, flush=True)
     r = ctx.svd_partial(A.cuda(), k, b, plan=_plan(basis_dtype=lowp, refine=True, tol=1e-9,
-                                                    max_iters=400))
+                                                    max_iters=400, tail=tail))
     print("info", r.info, flush=True)
     assert r.info["iters_low"] >= 1
     assert r.resid.cpu().numpy().max() <= 1e-8
     np.testing.assert_allclose(r.sigma.cpu().numpy(), s_ref[:k], rtol=1e-10)
 
 
-@pytest.mark.parametrize("lowp", ["bf16", "f8e4m3"])
-def test_svd_phase_switch_at_iteration_cap(ctx, lowp):
+@pytest.mark.parametrize("lowp,tail", [("bf16", "f64"), ("f8e4m3", "f64"), ("f8e4m3", "i8")])
+def test_svd_phase_switch_at_iteration_cap(ctx, lowp, tail):
     """The iteration cap lands on the switch to the FP64 tail: the left and
     right Ritz blocks are promoted exactly, so U, V, sigma and the final
     residuals equal those of the same run that does not switch, bit for
@@ -316,7 +318,7 @@ def test_svd_phase_switch_at_iteration_cap(ctx, lowp):
     A = W.svd_prescribed(m, n, sig, 44, dtype=torch.float32).cuda()
     V0 = torch.from_numpy(W.uniform_start(n, b, 45))
     print("svd switch at cap", lowp, flush=True)
-    common = dict(basis_dtype=lowp, refine=True, tol=1e-15, max_iters=1)
+    common = dict(basis_dtype=lowp, refine=True, tol=1e-15, max_iters=1, tail=tail)
     sw = ctx.svd_partial(A, k, b, plan=_plan(stall_iters=1, switch_resid=1e3, **common), V0=V0)
     ns = ctx.svd_partial(A, k, b, plan=_plan(stall_iters=50, switch_resid=0.0, **common), V0=V0)
     assert sw.info["iters"] == ns.info["iters"] == 1
