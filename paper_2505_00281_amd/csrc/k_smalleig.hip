@@ -2218,6 +2218,147 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// SVD pencil as a pipeline of launches (k1, k2 <= 256):
+//   k_svdp_chol    two workgroups: MU = L_U L_U^T and MV = L_V L_V^T at once,
+//                  with the reciprocal diagonals and the transposed factors
+//                  (the rows of L as columns, for the backward solves);
+//   k_tri_cols     the triangular solves, one wavefront per right-hand
+//                  column (lanes over rows, the column in registers, the
+//                  factor's next column loaded one step ahead): no barrier;
+//   k_svdp_jacobi  one workgroup: one-sided Jacobi SVD of the reduced matrix,
+//                  singular values in descending order, the unit vectors
+//                  divided by sqrt(2) before the last solves.
+// status[0]: 3 / 4 when MU / MV is not positive definite (later launches
+// return at once).
+// ---------------------------------------------------------------------------
+struct SvdpWork {
+    double *LU, *LV, *LUt, *LVt;  // factors and their transposes
+    double *iu, *iv;              // reciprocal diagonals
+    double *T, *M, *V;            // k1 x k2 / k2 x k1 / q x q scratch
+    double *w;                    // q singular values (unsorted)
+    int *ord;
+};
+
+__global__ __launch_bounds__(SE_THREADS) void k_svdp_chol(const double *__restrict__ MU, int k1,
+                                                          const double *__restrict__ MV, int k2, SvdpWork w,
+                                                          int *status) {
+    const bool u = blockIdx.x == 0;
+    const int k = u ? k1 : k2;
+    const double *Msrc = u ? MU : MV;
+    double *L = u ? w.LU : w.LV, *Lt = u ? w.LUt : w.LVt, *inv = u ? w.iu : w.iv;
+    const int t = threadIdx.x, T = blockDim.x;
+    for (int e = t; e < k * k; e += T) {
+        const int i = e % k, j = e / k;
+        L[e] = 0.5 * (Msrc[i + j * k] + Msrc[j + i * k]);
+    }
+    __syncthreads();
+    if (!cholesky(L, k, 0)) {
+        if (t == 0) atomicMax(status, u ? 3 : 4);
+        return;
+    }
+    for (int e = t; e < k * k; e += T) {
+        const int i = e % k, j = e / k;
+        Lt[e] = L[j + i * k];
+    }
+    for (int i = t; i < k; i += T) inv[i] = 1.0 / L[i + i * k];
+}
+
+// column c of X (n x m, ld n) <- L^{-1} X_c (FWD, L lower, its columns) or
+// L^{-T} X_c (backward, with Lt = L^T: column j of Lt is row j of L); one
+// wavefront per column, n <= 256
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_tri_cols(const double *__restrict__ Lc, const double *__restrict__ inv, int n,
+                                                  double *__restrict__ X, int m, const int *status) {
+    if (status[0] != 0) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= m) return;
+    double *x = X + (int64_t)c * n;
+    double xr[4], lc[4], ln[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = lane + 64 * u;
+        xr[u] = r < n ? x[r] : 0.0;
+    }
+    const int j0 = FWD ? 0 : n - 1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = lane + 64 * u;
+        lc[u] = r < n ? Lc[r + (int64_t)j0 * n] : 0.0;
+    }
+    for (int s = 0; s < n; ++s) {
+        const int j = FWD ? s : n - 1 - s;
+        // the next step's column of the factor, loaded ahead
+        const int jn = FWD ? (j + 1 < n ? j + 1 : j) : (j > 0 ? j - 1 : j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = lane + 64 * u;
+            ln[u] = r < n ? Lc[r + (int64_t)jn * n] : 0.0;
+        }
+        const int ju = j >> 6;
+        const double own = ju == 0 ? xr[0] : (ju == 1 ? xr[1] : (ju == 2 ? xr[2] : xr[3]));
+        const double xj = readlane_f64(own, j & 63) * inv[j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = lane + 64 * u;
+            if (r == j) xr[u] = xj;
+            else if (FWD ? (r > j && r < n) : (r < j)) xr[u] = fma(-lc[u], xj, xr[u]);
+            lc[u] = ln[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = lane + 64 * u;
+        if (r < n) x[r] = xr[u];
+    }
+}
+
+// dst (cols x rows) = src^T (src rows x cols, both column-major)
+__global__ void k_transpose_f64(const double *__restrict__ src, int rows, int cols, double *__restrict__ dst,
+                                const int *status) {
+    if (status[0] != 0) return;
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % cols), j = (int)(e / cols);  // dst[i + j cols] = src[j + i rows]
+        dst[e] = src[j + (int64_t)i * rows];
+    }
+}
+
+// One-sided Jacobi SVD of M (m x q, m >= q) -> sigma (descending), the
+// left vectors (length m) and right vectors (length q) divided by sqrt 2
+// into Lo (ld lo_ld) and Ro (ld ro_ld).
+__global__ __launch_bounds__(SE_THREADS) void k_svdp_jacobi(double *__restrict__ M, int m, int q, SvdpWork w,
+                                                            double *__restrict__ sigma, double *__restrict__ Lo,
+                                                            int lo_ld, double *__restrict__ Ro, int ro_ld,
+                                                            const int *status) {
+    if (status[0] != 0) return;
+    __shared__ int s_rot;
+    const int t = threadIdx.x, T = blockDim.x, wave = t >> 6, lane = t & 63, nw = T >> 6;
+    (void)jacobi_svd(M, m, q, w.V, &s_rot);
+    // column norms: a wavefront per column
+    for (int j = wave; j < q; j += nw) {
+        double s2 = 0.0;
+        for (int r = lane; r < m; r += 64) s2 += M[r + (int64_t)j * m] * M[r + (int64_t)j * m];
+        s2 = wave_sum_f64(s2);
+        if (lane == 0) w.w[j] = sqrt(s2);
+    }
+    __syncthreads();
+    sort_order(w.w, q, true, w.ord);
+    for (int c = t; c < q; c += T) sigma[c] = w.w[w.ord[c]];
+    const double h = 0.70710678118654752440;
+    for (int e = t; e < m * q; e += T) {
+        const int row = e % m, c = e / m;
+        const int j = w.ord[c];
+        const double sj = w.w[j];
+        Lo[row + (int64_t)c * lo_ld] = sj > 0.0 ? M[row + (int64_t)j * m] / sj * h : 0.0;
+    }
+    for (int e = t; e < q * q; e += T) {
+        const int row = e % q, c = e / q;
+        Ro[row + (int64_t)c * ro_ld] = w.V[row + (int64_t)w.ord[c] * q] * h;
+    }
+}
+
 // Dynamic-LDS limits are per kernel and device; raising them once per
 // device to the largest size the launches below ask for keeps the attribute
 // calls off the per-iteration path.
@@ -2336,6 +2477,62 @@ void pencil_general(Context *ctx, int32_t b, const double *H, const double *G, d
 void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const double *MU,
                 const double *MV, double *sigma, double *Y, double *Z) {
     OFRR_CHECK_ARG(k1 >= 1 && k2 >= 1 && k1 + k2 <= 1024, "svd pencil sizes");
+    if (k1 <= 256 && k2 <= 256) {
+        // the pipeline of launches: block Cholesky, C^T = L_V^{-1} (L_U^{-1} B)^T
+        // by column solves, one-sided Jacobi on the taller of C and C^T, the
+        // L^{-T} transforms by column solves
+        const size_t kk = (size_t)256 * 256;
+        double *base = ctx->buf<double>("svdp2_work", 9 * kk + 2 * 256 + 256);
+        SvdpWork w;
+        w.LU = base;
+        w.LV = base + kk;
+        w.LUt = base + 2 * kk;
+        w.LVt = base + 3 * kk;
+        w.T = base + 4 * kk;
+        w.M = base + 5 * kk;
+        w.V = base + 6 * kk;
+        w.iu = base + 9 * kk;
+        w.iv = w.iu + 256;
+        w.w = w.iv + 256;
+        w.ord = ctx->buf<int>("svdp2_ord", 256);
+        int *status = ctx->buf<int>("pencil_status", 4);
+        zero_bytes(ctx, status, 16);
+        KTimer tm(ctx, "small_eig");
+        hipLaunchKernelGGL(k_svdp_chol, dim3(2), dim3(SE_THREADS), 0, ctx->stream, MU, k1, MV, k2, w, status);
+        // T = L_U^{-1} B (k1 x k2: k2 columns)
+        OFRR_HIP(hipMemcpyAsync(w.T, B, sizeof(double) * k1 * k2, hipMemcpyDeviceToDevice, ctx->stream));
+        hipLaunchKernelGGL(k_tri_cols<true>, dim3((k2 + 3) / 4), dim3(256), 0, ctx->stream, w.LU, w.iu, k1, w.T,
+                           k2, status);
+        // C^T = L_V^{-1} T^T (k2 x k1: k1 columns)
+        double *Ct = w.M;
+        hipLaunchKernelGGL(k_transpose_f64, dim3(64), dim3(256), 0, ctx->stream, w.T, k1, k2, Ct, status);
+        hipLaunchKernelGGL(k_tri_cols<true>, dim3((k1 + 3) / 4), dim3(256), 0, ctx->stream, w.LV, w.iv, k2, Ct,
+                           k1, status);
+        const int r = k1 < k2 ? k1 : k2;
+        if (k2 >= k1) {
+            // Jacobi on C^T (k2 x k1): C^T V' = U' S, so C = V' S U'^T: the left
+            // vectors of C are V' (length k1), the right ones U' (length k2)
+            hipLaunchKernelGGL(k_svdp_jacobi, dim3(1), dim3(SE_THREADS), 0, ctx->stream, Ct, k2, k1, w, sigma, Z,
+                               k2, Y, k1, status);
+        } else {
+            double *C = w.T;
+            hipLaunchKernelGGL(k_transpose_f64, dim3(64), dim3(256), 0, ctx->stream, Ct, k2, k1, C, status);
+            hipLaunchKernelGGL(k_svdp_jacobi, dim3(1), dim3(SE_THREADS), 0, ctx->stream, C, k1, k2, w, sigma, Y,
+                               k1, Z, k2, status);
+        }
+        // y = L_U^{-T} (u / sqrt 2), z = L_V^{-T} (v / sqrt 2)
+        hipLaunchKernelGGL(k_tri_cols<false>, dim3((r + 3) / 4), dim3(256), 0, ctx->stream, w.LUt, w.iu, k1, Y, r,
+                           status);
+        hipLaunchKernelGGL(k_tri_cols<false>, dim3((r + 3) / 4), dim3(256), 0, ctx->stream, w.LVt, w.iv, k2, Z, r,
+                           status);
+        OFRR_HIP(hipGetLastError());
+        int host = 0;
+        OFRR_HIP(hipMemcpyAsync(&host, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        ctx->sync();
+        if (host == 3) fail(OFRR_ERR_NUMERIC, "svd pencil: U^T U not positive definite");
+        if (host == 4) fail(OFRR_ERR_NUMERIC, "svd pencil: V^T V not positive definite");
+        return;
+    }
     const int N = k1 + k2;
     PencilWork w = make_work(ctx, N + 1);
     double *LU = ctx->buf<double>("svdp_LU", (size_t)k1 * k1);
