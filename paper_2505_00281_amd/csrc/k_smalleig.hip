@@ -1373,6 +1373,58 @@ __device__ void cluster_vectors(const double *d, const double *e, int n, const d
     }
 }
 
+// The same inverse iteration for one wavefront with the factorisation and
+// the iterate in LDS (f: 5 n, x: n): the recurrences run on lane 0, the
+// Gram-Schmidt steps against the cluster's earlier vectors and the
+// normalisation on all lanes.
+__device__ void cluster_vectors_wave(const double *d, const double *e, int n, const double *lam, int i0, int i1,
+                                     double tiny, double *f, double *x, double *Zt) {
+    const int lane = threadIdx.x & 63;
+    for (int i = i0; i < i1; ++i) {
+        const double lm = lam[i] + (double)(i - i0) * 4.0 * tiny;
+        if (lane == 0) tri_factor(d, e, n, lm, tiny, f);
+        for (int k = lane; k < n; k += 64) {
+            uint32_t h = (uint32_t)(k * 2654435761u) ^ (uint32_t)(i * 40503u + 0x9E37u);
+            h ^= h >> 15;
+            h *= 0x2C1B3C6Du;
+            h ^= h >> 12;
+            x[k] = 0.5 + (double)(h & 0xFFFF) * (1.0 / 65536.0);
+        }
+        wave_lds_sync();
+        for (int it = 0; it < 3; ++it) {
+            if (lane == 0) tri_solve(f, n, x);
+            wave_lds_sync();
+            for (int qv = i0; qv < i; ++qv) {
+                const double *y = Zt + (int64_t)qv * n;
+                double sdot = 0.0;
+                for (int k = lane; k < n; k += 64) sdot += y[k] * x[k];
+                sdot = wave_sum_f64(sdot);
+                for (int k = lane; k < n; k += 64) x[k] -= sdot * y[k];
+                wave_lds_sync();
+            }
+            double mx = 0.0;
+            for (int k = lane; k < n; k += 64) mx = fmax(mx, fabs(x[k]));
+            mx = wave_max_f64(mx);
+            const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+            double nn = 0.0;
+            for (int k = lane; k < n; k += 64) {
+                const double v = x[k] * inv;
+                nn += v * v;
+            }
+            nn = wave_sum_f64(nn);
+            const double rr = inv / sqrt(nn);
+            for (int k = lane; k < n; k += 64) x[k] *= rr;
+            wave_lds_sync();
+        }
+        double *zo = Zt + (int64_t)i * n;
+        for (int k = lane; k < n; k += 64) zo[k] = x[k];
+        // the next member's Gram-Schmidt reads this vector from global memory
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
 // Gershgorin interval of T widened by a few ulps, and the pivot floor;
 // the same values in every lane of every wave.
 __device__ void fp_gershgorin(const double *sd, const double *se, int n, double &lo, double &hi,
@@ -1428,6 +1480,8 @@ __global__ __launch_bounds__(64 * FP_WAVES) void k_fp_bisect(int n, FPWork w, co
 __global__ __launch_bounds__(64 * FP_WAVES) void k_fp_vectors(int n, FPWork w, const int *status) {
     __shared__ double sd[FP_NMAX], se[FP_NMAX], sl[FP_NMAX];
     __shared__ double dpm[FP_WAVES][2][FP_NMAX], zz[FP_WAVES][FP_NMAX];
+    // factorisation of T - lam I for a cluster's inverse iteration, per wave
+    __shared__ double fsc[FP_WAVES][5 * FP_NMAX];
     if (status[0] != 0) return;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int k = t; k < n; k += blockDim.x) {
@@ -1447,7 +1501,7 @@ __global__ __launch_bounds__(64 * FP_WAVES) void k_fp_vectors(int n, FPWork w, c
     int i1 = i + 1;
     while (i1 < n && !(sl[i1] - sl[i1 - 1] > ortol)) ++i1;
     if (i1 > i + 1) {
-        if (lane == 0) cluster_vectors(sd, se, n, sl, i, i1, tiny, w.scr + (size_t)i * 6 * n, w.Zt);
+        cluster_vectors_wave(sd, se, n, sl, i, i1, tiny, fsc[wv], zz[wv], w.Zt);
         return;
     }
     const double lm = sl[i];
