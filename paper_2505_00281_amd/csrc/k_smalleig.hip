@@ -624,7 +624,8 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
 // with the lanes over rows); a sweep without a rotation ends the iteration.  The
 // singular values come out with high relative accuracy, and a nearly
 // diagonal start (the projected matrix of a converging subspace) needs one
-// or two sweeps.  Returns the number of sweeps.
+// or two sweeps; a sweep whose rotations were all tiny is the last.
+// Returns the number of sweeps.
 // One step of the tournament: pair pr goes to the 32-lane group pr mod 32
 // (a half wavefront; the lanes hold rows l + 32 u), so 32 pairs are in
 // flight at once.
@@ -635,7 +636,8 @@ __device__ __forceinline__ double half_wave_sum(double v) {
 }
 
 template <int MAXR>
-__device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, int step, double tol, int *s_rot) {
+__device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, int step, double tol, int *s_rot,
+                                    unsigned *s_cmax) {
     const int t = threadIdx.x, T = blockDim.x, grp = t >> 5, gl = t & 31, ng = T >> 5;
     auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + step) % (mm - 1)) + 1; };
     for (int pr = grp; pr < mm / 2; pr += ng) {
@@ -667,7 +669,11 @@ __device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, 
         al = half_wave_sum(al);
         be = half_wave_sum(be);
         ga = half_wave_sum(ga);
-        if (!(fabs(ga) > tol * sqrt(al * be))) continue;
+        // the largest cosine of the sweep (as FP32 bits: positive values
+        // order as unsigned integers)
+        const double nab = sqrt(al * be);
+        if (gl == 0 && nab > 0.0) atomicMax(s_cmax, __float_as_uint((float)(fabs(ga) / nab)));
+        if (!(fabs(ga) > tol * nab)) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -688,25 +694,33 @@ __device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, 
 }
 
 __device__ int jacobi_svd(double *M, int m, int q, double *V, int *s_rot) {
+    __shared__ unsigned s_cmax;
     const int t = threadIdx.x, T = blockDim.x;
     for (int e = t; e < q * q; e += T) V[e] = (e % q == e / q) ? 1.0 : 0.0;
     const int mm = q + (q & 1);
     const double tol = 0x1p-52 * sqrt((double)m);
+    // a sweep whose largest cosine was below a tenth of sqrt(tol) leaves
+    // cosines of order its square (quadratic convergence): no further sweep
+    const float cfin = (float)(0.1 * sqrt(tol));
     int sweep = 0;
     __syncthreads();
     for (; sweep < 40; ++sweep) {
-        if (t == 0) *s_rot = 0;
+        if (t == 0) {
+            *s_rot = 0;
+            s_cmax = 0u;
+        }
         __syncthreads();
         for (int step = 0; step < mm - 1; ++step) {
             if (m <= 256)
-                jacobi_rotate_pairs<8>(M, m, V, q, mm, step, tol, s_rot);
+                jacobi_rotate_pairs<8>(M, m, V, q, mm, step, tol, s_rot, &s_cmax);
             else
-                jacobi_rotate_pairs<32>(M, m, V, q, mm, step, tol, s_rot);
+                jacobi_rotate_pairs<32>(M, m, V, q, mm, step, tol, s_rot, &s_cmax);
             __syncthreads();
         }
         const int nrot = *s_rot;
+        const float cmax = __uint_as_float(s_cmax);
         __syncthreads();
-        if (nrot == 0) break;
+        if (nrot == 0 || cmax <= cfin) break;
     }
     return sweep + 1;
 }
