@@ -693,6 +693,8 @@ __device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, 
     }
 }
 
+// MAXR = 0 picks the register depth at run time (8 for m <= 256, else 32)
+template <int MAXR = 0>
 __device__ int jacobi_svd(double *M, int m, int q, double *V, int *s_rot) {
     __shared__ unsigned s_cmax;
     const int t = threadIdx.x, T = blockDim.x;
@@ -711,7 +713,7 @@ __device__ int jacobi_svd(double *M, int m, int q, double *V, int *s_rot) {
         }
         __syncthreads();
         for (int step = 0; step < mm - 1; ++step) {
-            if (m <= 256)
+            if (MAXR == 8 || (MAXR == 0 && m <= 256))
                 jacobi_rotate_pairs<8>(M, m, V, q, mm, step, tol, s_rot, &s_cmax);
             else
                 jacobi_rotate_pairs<32>(M, m, V, q, mm, step, tol, s_rot, &s_cmax);
@@ -1692,8 +1694,8 @@ PencilWork make_work(Context *ctx, int n) {
 // ---------------------------------------------------------------------------
 
 constexpr int GN_LOGW = 4;  // doubles per logged transform
-// C kept in LDS up to this size (136^2 FP64 = 145 KiB, with the static
-// arrays below the 160 KiB of a CU)
+// C kept in LDS up to this size (137 x 136 FP64 = 146 KiB with the odd
+// leading dimension; with the static arrays below the 160 KiB of a CU)
 constexpr int GN_LDS_MAX_N = 136;
 
 struct GenWork {
@@ -1788,13 +1790,13 @@ __device__ __forceinline__ void gn_sync() {
 // step 3 for wavefront 0: C (n x n, upper Hessenberg) -> T in place;
 // eigenvalues in diagonal order to w.wr, w.wi
 template <bool LDS>
-__device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
+__device__ void gn_francis(double *C, int n, int ldc, GenWork &w, int *status) {
     const int lane = threadIdx.x & 63;
     const double eps = 0x1p-52;
     double hn = 0.0;
     for (int e = lane; e < n * n; e += 64) {
         const int i = e % n, j = e / n;
-        if (i <= j + 1) hn = fmax(hn, fabs(C[e]));
+        if (i <= j + 1) hn = fmax(hn, fabs(C[i + (int64_t)j * ldc]));
     }
     for (int o = 32; o > 0; o >>= 1) hn = fmax(hn, __shfl_xor(hn, o, 64));
     int nn = n - 1, it = 0, total = 0, nlog = 0, nbat = 0, fail = 0;
@@ -1843,9 +1845,9 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
             const int c = base - lane;
             bool ok = false;
             if (c >= 1) {
-                double s = fabs(C[(c - 1) + (int64_t)(c - 1) * n]) + fabs(C[c + (int64_t)c * n]);
+                double s = fabs(C[(c - 1) + (int64_t)(c - 1) * ldc]) + fabs(C[c + (int64_t)c * ldc]);
                 if (s == 0.0) s = hn;
-                ok = fabs(C[c + (int64_t)(c - 1) * n]) <= eps * s;
+                ok = fabs(C[c + (int64_t)(c - 1) * ldc]) <= eps * s;
             }
             const unsigned long long m = __ballot(ok);
             if (m) {
@@ -1853,11 +1855,11 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
                 break;
             }
         }
-        if (l > 0 && lane == 0) C[l + (int64_t)(l - 1) * n] = 0.0;
+        if (l > 0 && lane == 0) C[l + (int64_t)(l - 1) * ldc] = 0.0;
         gn_sync<LDS>();
         if (l == nn) {
             if (lane == 0) {
-                w.wr[nn] = C[nn + (int64_t)nn * n];
+                w.wr[nn] = C[nn + (int64_t)nn * ldc];
                 w.wi[nn] = 0.0;
             }
             --nn;
@@ -1866,8 +1868,8 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
         }
         if (l == nn - 1) {
             const int a = nn - 1, b = nn;
-            const double t11 = C[a + (int64_t)a * n], t12 = C[a + (int64_t)b * n];
-            const double t21 = C[b + (int64_t)a * n], t22 = C[b + (int64_t)b * n];
+            const double t11 = C[a + (int64_t)a * ldc], t12 = C[a + (int64_t)b * ldc];
+            const double t21 = C[b + (int64_t)a * ldc], t22 = C[b + (int64_t)b * ldc];
             const double p = 0.5 * (t11 - t22);
             const double q = p * p + t12 * t21;
             if (q >= 0.0) {
@@ -1877,22 +1879,22 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
                 const double r = hypot(z, t21);
                 const double cs = r > 0.0 ? z / r : 1.0, sn = r > 0.0 ? t21 / r : 0.0;
                 for (int c = a + lane; c < n; c += 64) {
-                    const double u = C[a + (int64_t)c * n], v = C[b + (int64_t)c * n];
-                    C[a + (int64_t)c * n] = cs * u + sn * v;
-                    C[b + (int64_t)c * n] = cs * v - sn * u;
+                    const double u = C[a + (int64_t)c * ldc], v = C[b + (int64_t)c * ldc];
+                    C[a + (int64_t)c * ldc] = cs * u + sn * v;
+                    C[b + (int64_t)c * ldc] = cs * v - sn * u;
                 }
                 gn_sync<LDS>();
                 for (int rr = lane; rr <= b; rr += 64) {
-                    const double u = C[rr + (int64_t)a * n], v = C[rr + (int64_t)b * n];
-                    C[rr + (int64_t)a * n] = cs * u + sn * v;
-                    C[rr + (int64_t)b * n] = cs * v - sn * u;
+                    const double u = C[rr + (int64_t)a * ldc], v = C[rr + (int64_t)b * ldc];
+                    C[rr + (int64_t)a * ldc] = cs * u + sn * v;
+                    C[rr + (int64_t)b * ldc] = cs * v - sn * u;
                 }
                 gn_sync<LDS>();
                 if (lane == 0) {
-                    C[b + (int64_t)a * n] = 0.0;
-                    w.wr[a] = C[a + (int64_t)a * n];
+                    C[b + (int64_t)a * ldc] = 0.0;
+                    w.wr[a] = C[a + (int64_t)a * ldc];
                     w.wi[a] = 0.0;
-                    w.wr[b] = C[b + (int64_t)b * n];
+                    w.wr[b] = C[b + (int64_t)b * ldc];
                     w.wi[b] = 0.0;
                 }
                 gn_sync<LDS>();
@@ -1916,19 +1918,19 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
         // product t), or an exceptional pair every tenth iteration
         double s, t;
         if (it % 10 == 0) {
-            const double e = fabs(C[nn + (int64_t)(nn - 1) * n]) + fabs(C[(nn - 1) + (int64_t)(nn - 2) * n]);
-            const double h = 0.75 * e + C[nn + (int64_t)nn * n];
+            const double e = fabs(C[nn + (int64_t)(nn - 1) * ldc]) + fabs(C[(nn - 1) + (int64_t)(nn - 2) * ldc]);
+            const double h = 0.75 * e + C[nn + (int64_t)nn * ldc];
             s = 2.0 * h;
             t = h * h + 0.4375 * e * e;
         } else {
-            const double x = C[nn + (int64_t)nn * n], y = C[(nn - 1) + (int64_t)(nn - 1) * n];
+            const double x = C[nn + (int64_t)nn * ldc], y = C[(nn - 1) + (int64_t)(nn - 1) * ldc];
             s = x + y;
-            t = x * y - C[nn + (int64_t)(nn - 1) * n] * C[(nn - 1) + (int64_t)nn * n];
+            t = x * y - C[nn + (int64_t)(nn - 1) * ldc] * C[(nn - 1) + (int64_t)nn * ldc];
         }
         // first column of Hs^2 - s Hs + t I at row l
-        const double h00 = C[l + (int64_t)l * n], h10 = C[(l + 1) + (int64_t)l * n];
-        const double h01 = C[l + (int64_t)(l + 1) * n], h11 = C[(l + 1) + (int64_t)(l + 1) * n];
-        const double h21 = C[(l + 2) + (int64_t)(l + 1) * n];
+        const double h00 = C[l + (int64_t)l * ldc], h10 = C[(l + 1) + (int64_t)l * ldc];
+        const double h01 = C[l + (int64_t)(l + 1) * ldc], h11 = C[(l + 1) + (int64_t)(l + 1) * ldc];
+        const double h21 = C[(l + 2) + (int64_t)(l + 1) * ldc];
         double x = h00 * h00 + h01 * h10 - s * h00 + t;
         double y = h10 * (h00 + h11 - s);
         double z = h10 * h21;
@@ -1936,23 +1938,24 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
         // step's x, y, z (column k, rows k+1..k+3 after the right update)
         // come from the lanes that computed them
         bool have_next = false;
-        double col0[3] = {0.0, 0.0, 0.0};
+        // (named registers, not an array: an array the selects index would
+        // be placed in scratch memory)
+        double c0a = 0.0, c0b = 0.0, c0c = 0.0;
         for (int k = l; k <= nn - 1; ++k) {
             const int m = (k == nn - 1) ? 2 : 3;
             if (k > l) {
                 if (LDS && have_next) {
-                    auto pick = [&](int r) {
-                        const int it = r >> 6;
-                        const double v = it == 0 ? col0[0] : (it == 1 ? col0[1] : col0[2]);
-                        return readlane_f64(v, r & 63);
-                    };
-                    x = pick(k);
-                    y = pick(k + 1);
-                    z = (m == 3) ? pick(k + 2) : 0.0;
+                    const int ix = k >> 6, iy = (k + 1) >> 6, iz = (k + 2) >> 6;
+                    const double vx = ix == 0 ? c0a : (ix == 1 ? c0b : c0c);
+                    const double vy = iy == 0 ? c0a : (iy == 1 ? c0b : c0c);
+                    const double vz = iz == 0 ? c0a : (iz == 1 ? c0b : c0c);
+                    x = readlane_f64(vx, k & 63);
+                    y = readlane_f64(vy, (k + 1) & 63);
+                    z = (m == 3) ? readlane_f64(vz, (k + 2) & 63) : 0.0;
                 } else {
-                    x = C[k + (int64_t)(k - 1) * n];
-                    y = C[(k + 1) + (int64_t)(k - 1) * n];
-                    z = (m == 3) ? C[(k + 2) + (int64_t)(k - 1) * n] : 0.0;
+                    x = C[k + (int64_t)(k - 1) * ldc];
+                    y = C[(k + 1) + (int64_t)(k - 1) * ldc];
+                    z = (m == 3) ? C[(k + 2) + (int64_t)(k - 1) * ldc] : 0.0;
                 }
             }
             have_next = false;
@@ -1968,45 +1971,91 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
             const int r1 = (k + 3 < nn) ? k + 3 : nn;
             // left: rows k..k+2 from column c0 on (column k-1 of a chase step
             // gets its exact result alpha sc, 0, 0)
-            for (int c = c0 + lane; c < n; c += 64) {
-                double *p = C + k + (int64_t)c * n;
-                if (k > l && c == k - 1) {
-                    p[0] = alpha * sc;
-                    p[1] = 0.0;
-                    if (m == 3) p[2] = 0.0;
-                    continue;
+            if (LDS) {
+                // at most three columns per lane (n <= 136): every load first
+                double ra[3], rb[3], rc[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int c = c0 + lane + 64 * q;
+                    const double *p = C + k + (int64_t)(c < n ? c : n - 1) * ldc;
+                    ra[q] = p[0];
+                    rb[q] = p[1];
+                    rc[q] = m == 3 ? p[2] : 0.0;
                 }
-                const double a = p[0], b = p[1], cc = m == 3 ? p[2] : 0.0;
-                const double tt = beta * (v0 * a + v1 * b + v2 * cc);
-                p[0] = a - tt * v0;
-                p[1] = b - tt * v1;
-                if (m == 3) p[2] = cc - tt * v2;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int c = c0 + lane + 64 * q;
+                    if (c >= n) continue;
+                    double *p = C + k + (int64_t)c * ldc;
+                    double n0, n1, n2;
+                    if (k > l && c == k - 1) {
+                        n0 = alpha * sc;
+                        n1 = 0.0;
+                        n2 = 0.0;
+                    } else {
+                        const double tt = beta * (v0 * ra[q] + v1 * rb[q] + v2 * rc[q]);
+                        n0 = ra[q] - tt * v0;
+                        n1 = rb[q] - tt * v1;
+                        n2 = rc[q] - tt * v2;
+                    }
+                    p[0] = n0;
+                    p[1] = n1;
+                    if (m == 3) p[2] = n2;
+                }
+            } else {
+                for (int c = c0 + lane; c < n; c += 64) {
+                    double *p = C + k + (int64_t)c * ldc;
+                    if (k > l && c == k - 1) {
+                        p[0] = alpha * sc;
+                        p[1] = 0.0;
+                        if (m == 3) p[2] = 0.0;
+                        continue;
+                    }
+                    const double a = p[0], b = p[1], cc = m == 3 ? p[2] : 0.0;
+                    const double tt = beta * (v0 * a + v1 * b + v2 * cc);
+                    p[0] = a - tt * v0;
+                    p[1] = b - tt * v1;
+                    if (m == 3) p[2] = cc - tt * v2;
+                }
             }
             gn_sync<LDS>();
             // right: columns k..k+2 of rows 0..r1
             if (LDS) {
+                // rows lane, lane + 64, lane + 128: every load first
+                double ra[3], rb[3], rc[3];
 #pragma unroll
-                for (int it = 0; it < 3; ++it) {
-                    const int r = lane + 64 * it;
+                for (int q = 0; q < 3; ++q) {
+                    const int r = lane + 64 * q;
+                    const double *p = C + (r <= r1 ? r : r1) + (int64_t)k * ldc;
+                    ra[q] = p[0];
+                    rb[q] = p[ldc];
+                    rc[q] = m == 3 ? p[2 * ldc] : 0.0;
+                }
+                double nk[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int r = lane + 64 * q;
+                    const double tt = beta * (ra[q] * v0 + rb[q] * v1 + rc[q] * v2);
+                    nk[q] = ra[q] - tt * v0;
                     if (r <= r1) {
-                        double *p = C + r + (int64_t)k * n;
-                        const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
-                        const double tt = beta * (a * v0 + b * v1 + cc * v2);
-                        col0[it] = a - tt * v0;
-                        p[0] = col0[it];
-                        p[n] = b - tt * v1;
-                        if (m == 3) p[2 * n] = cc - tt * v2;
+                        double *p = C + r + (int64_t)k * ldc;
+                        p[0] = nk[q];
+                        p[ldc] = rb[q] - tt * v1;
+                        if (m == 3) p[2 * ldc] = rc[q] - tt * v2;
                     }
                 }
+                c0a = nk[0];
+                c0b = nk[1];
+                c0c = nk[2];
                 have_next = true;
             } else {
                 for (int r = lane; r <= r1; r += 64) {
-                    double *p = C + r + (int64_t)k * n;
-                    const double a = p[0], b = p[n], cc = m == 3 ? p[2 * n] : 0.0;
+                    double *p = C + r + (int64_t)k * ldc;
+                    const double a = p[0], b = p[ldc], cc = m == 3 ? p[2 * ldc] : 0.0;
                     const double tt = beta * (a * v0 + b * v1 + cc * v2);
                     p[0] = a - tt * v0;
-                    p[n] = b - tt * v1;
-                    if (m == 3) p[2 * n] = cc - tt * v2;
+                    p[ldc] = b - tt * v1;
+                    if (m == 3) p[2 * ldc] = cc - tt * v2;
                 }
             }
             gn_sync<LDS>();
@@ -2024,8 +2073,8 @@ __device__ void gn_francis(double *C, int n, GenWork &w, int *status) {
 
 // one thread per real eigenvalue or conjugate pair: the eigenvector of the
 // quasi-triangular T (n x n) into X (packed real, col-major n)
-__device__ void gn_tri_vector(const double *T, int n, const double *wr, const double *wi, int k, double tiny,
-                              double *X) {
+__device__ void gn_tri_vector(const double *T, int n, int ldt, const double *wr, const double *wi, int k,
+                              double tiny, double *X) {
     const bool pair = wi[k] > 0.0;
     const double lr = wr[k], li = wi[k];
     double *xr = X + (int64_t)k * n;
@@ -2035,8 +2084,8 @@ __device__ void gn_tri_vector(const double *T, int n, const double *wr, const do
         xr[k] = 1.0;
     } else {
         const int a = k, b = k + 1;
-        const double t11 = T[a + (int64_t)a * n], t12 = T[a + (int64_t)b * n];
-        const double t21 = T[b + (int64_t)a * n], t22 = T[b + (int64_t)b * n];
+        const double t11 = T[a + (int64_t)a * ldt], t12 = T[a + (int64_t)b * ldt];
+        const double t21 = T[b + (int64_t)a * ldt], t22 = T[b + (int64_t)b * ldt];
         if (fabs(t21) >= fabs(t12)) {
             // x_b = 1, x_a = (lambda - t22) / t21
             xr[b] = 1.0;
@@ -2058,7 +2107,7 @@ __device__ void gn_tri_vector(const double *T, int n, const double *wr, const do
             const int a = i - 1, b = i;
             double rar = 0.0, rai = 0.0, rbr = 0.0, rbi = 0.0;
             for (int j = i + 1; j <= top; ++j) {
-                const double ta = T[a + (int64_t)j * n], tb = T[b + (int64_t)j * n];
+                const double ta = T[a + (int64_t)j * ldt], tb = T[b + (int64_t)j * ldt];
                 const double vr = xr[j], vi = pair ? xi[j] : 0.0;
                 rar += ta * vr;
                 rai += ta * vi;
@@ -2067,9 +2116,9 @@ __device__ void gn_tri_vector(const double *T, int n, const double *wr, const do
             }
             // [[m11, m12], [m21, m22]] [xa; xb] = -[ra; rb], m11 = t11 - lambda,
             // m22 = t22 - lambda (complex), m12, m21 real
-            const double m11r = T[a + (int64_t)a * n] - lr, m11i = -li;
-            const double m22r = T[b + (int64_t)b * n] - lr, m22i = -li;
-            const double m12 = T[a + (int64_t)b * n], m21 = T[b + (int64_t)a * n];
+            const double m11r = T[a + (int64_t)a * ldt] - lr, m11i = -li;
+            const double m22r = T[b + (int64_t)b * ldt] - lr, m22i = -li;
+            const double m12 = T[a + (int64_t)b * ldt], m21 = T[b + (int64_t)a * ldt];
             double detr = m11r * m22r - m11i * m22i - m12 * m21;
             double deti = m11r * m22i + m11i * m22r;
             if (detr == 0.0 && deti == 0.0) detr = tiny;
@@ -2089,11 +2138,11 @@ __device__ void gn_tri_vector(const double *T, int n, const double *wr, const do
         } else {
             double rr = 0.0, ri = 0.0;
             for (int j = i + 1; j <= top; ++j) {
-                const double ti = T[i + (int64_t)j * n];
+                const double ti = T[i + (int64_t)j * ldt];
                 rr += ti * xr[j];
                 if (pair) ri += ti * xi[j];
             }
-            double dr = T[i + (int64_t)i * n] - lr, di = -li;
+            double dr = T[i + (int64_t)i * ldt] - lr, di = -li;
             if (dr == 0.0 && di == 0.0) dr = tiny;
             const double dd = dr * dr + di * di;
             // x_i = -r / d
@@ -2125,12 +2174,15 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
     __shared__ double red[16];
     __shared__ int s_slot[SE_THREADS];
     const int t = threadIdx.x, T = blockDim.x, wave = t >> 6;
-    // C in LDS (n <= GN_LDS_MAX_N) or in the workspace
-    double *C = LDS ? smem : w.C;
+    // the reduction C = L^{-1} H L^{-T} in the workspace (leading dimension
+    // n), then C in LDS (n <= GN_LDS_MAX_N) with an odd leading dimension,
+    // so that a wavefront reading a row (lanes over columns) spreads over the
+    // banks, or left in the workspace
+    double *Cg = w.C;
     for (int e = t; e < n * n; e += T) {
         const int i = e % n, j = e / n;
         w.L[e] = 0.5 * (G[i + j * n] + G[j + i * n]);
-        C[e] = H[e];
+        Cg[e] = H[e];
     }
     if (t < 4) status[t] = 0;
     __syncthreads();
@@ -2143,10 +2195,19 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
         return;
     }
     // C <- L^{-1} H L^{-T}: L^{-1} H, transpose, L^{-1} (.), transpose
-    trsm_lower(w.L, n, C, n);
-    transpose_sq(C, n);
-    trsm_lower(w.L, n, C, n);
-    transpose_sq(C, n);
+    trsm_lower(w.L, n, Cg, n);
+    transpose_sq(Cg, n);
+    trsm_lower(w.L, n, Cg, n);
+    transpose_sq(Cg, n);
+    const int ldc = LDS ? (n | 1) : n;
+    double *C = LDS ? smem : Cg;
+    if (LDS) {
+        for (int e = t; e < n * n; e += T) {
+            const int i = e % n, j = e / n;
+            C[i + j * ldc] = Cg[e];
+        }
+        __syncthreads();
+    }
     // ---- 2. Householder reduction to Hessenberg form, Q accumulated
     for (int e = t; e < n * n; e += T) w.Q[e] = (e % n == e / n) ? 1.0 : 0.0;
     double *v = w.wr;  // scratch vector (rows j+1..n-1) until step 3
@@ -2154,19 +2215,19 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
     __syncthreads();
     for (int j = 0; j + 2 < n; ++j) {
         double sg = 0.0;
-        for (int i = j + 2 + t; i < n; i += T) sg += C[i + (int64_t)j * n] * C[i + (int64_t)j * n];
+        for (int i = j + 2 + t; i < n; i += T) sg += C[i + (int64_t)j * ldc] * C[i + (int64_t)j * ldc];
         sg = block_sum(sg, red);
         if (sg == 0.0) continue;  // uniform: column already reduced
-        const double x0 = C[(j + 1) + (int64_t)j * n];
+        const double x0 = C[(j + 1) + (int64_t)j * ldc];
         const double alpha = -copysign(sqrt(x0 * x0 + sg), x0);
         const double beta = 1.0 / (alpha * (alpha - x0));
-        for (int i = j + 1 + t; i < n; i += T) v[i] = (i == j + 1) ? x0 - alpha : C[i + (int64_t)j * n];
+        for (int i = j + 1 + t; i < n; i += T) v[i] = (i == j + 1) ? x0 - alpha : C[i + (int64_t)j * ldc];
         __syncthreads();
         // left: columns j+1..n-1, tv[c] = beta v^T C[:, c] (a wavefront per column)
         const int nw = T >> 6, lane = t & 63;
         for (int c = j + 1 + wave; c < n; c += nw) {
             double acc = 0.0;
-            for (int i = j + 1 + lane; i < n; i += 64) acc += v[i] * C[i + (int64_t)c * n];
+            for (int i = j + 1 + lane; i < n; i += 64) acc += v[i] * C[i + (int64_t)c * ldc];
             acc = wave_sum_f64(acc);
             if (lane == 0) tv[c] = beta * acc;
         }
@@ -2174,16 +2235,17 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
         const int m = n - j - 1;
         for (int e = t; e < m * m; e += T) {
             const int i = j + 1 + e % m, c = j + 1 + e / m;
-            C[i + (int64_t)c * n] -= tv[c] * v[i];
+            C[i + (int64_t)c * ldc] -= tv[c] * v[i];
         }
         __syncthreads();
-        for (int i = j + 1 + t; i < n; i += T) C[i + (int64_t)j * n] = (i == j + 1) ? alpha : 0.0;
+        for (int i = j + 1 + t; i < n; i += T) C[i + (int64_t)j * ldc] = (i == j + 1) ? alpha : 0.0;
         // right: every row r of C and of Q, tv[r] = beta C[r, :] v
         for (int r = t; r < 2 * n; r += T) {
             const double *M = r < n ? C : w.Q;
             const int rr = r < n ? r : r - n;
+            const int ldm = r < n ? ldc : n;
             double acc = 0.0;
-            for (int i = j + 1; i < n; ++i) acc += M[rr + (int64_t)i * n] * v[i];
+            for (int i = j + 1; i < n; ++i) acc += M[rr + (int64_t)i * ldm] * v[i];
             w.X[r] = beta * acc;
         }
         __syncthreads();
@@ -2191,12 +2253,13 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
             const int r = e % (2 * n), i = j + 1 + e / (2 * n);
             double *M = r < n ? C : w.Q;
             const int rr = r < n ? r : r - n;
-            M[rr + (int64_t)i * n] -= w.X[r] * v[i];
+            const int ldm = r < n ? ldc : n;
+            M[rr + (int64_t)i * ldm] -= w.X[r] * v[i];
         }
         __syncthreads();
     }
     // ---- 3. QR iteration (wavefront 0), then Q <- Q Z from the log
-    if (wave == 0) gn_francis<LDS>(C, n, w, status);
+    if (wave == 0) gn_francis<LDS>(C, n, ldc, w, status);
     __syncthreads();
     if (status[0] != 0) {
         for (int i = t; i < n; i += T) {
@@ -2208,13 +2271,13 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
     gn_apply_log(w.Q, n, w.lg, w.lcode, status[2], t, T);
     // ---- 4. eigenvectors of T, V = Q X_T
     double tn = 0.0;
-    for (int e = t; e < n * n; e += T) tn = fmax(tn, fabs(C[e]));
+    for (int e = t; e < n * n; e += T) tn = fmax(tn, fabs(C[e % n + (int64_t)(e / n) * ldc]));
     tn = block_maxabs(tn, red);
     const double tiny = 0x1p-52 * (tn > 0.0 ? tn : 1.0);
     for (int e = t; e < n * n; e += T) w.X[e] = 0.0;
     __syncthreads();
     for (int k = t; k < n; k += T)
-        if (w.wi[k] >= 0.0) gn_tri_vector(C, n, w.wr, w.wi, k, tiny, w.X);
+        if (w.wi[k] >= 0.0) gn_tri_vector(C, n, ldc, w.wr, w.wi, k, tiny, w.X);
     __syncthreads();
     // V = Q X into C's storage... C (T) is no longer needed
     double *V = w.C;  // global n x n
@@ -2403,7 +2466,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_svdp_jacobi(double *__restrict__
     if (status[0] != 0) return;
     __shared__ int s_rot;
     const int t = threadIdx.x, T = blockDim.x, wave = t >> 6, lane = t & 63, nw = T >> 6;
-    (void)jacobi_svd(M, m, q, w.V, &s_rot);
+    (void)jacobi_svd<8>(M, m, q, w.V, &s_rot);  // launched for m <= 256 only
     // column norms: a wavefront per column
     for (int j = wave; j < q; j += nw) {
         double s2 = 0.0;
@@ -2440,7 +2503,7 @@ void pencil_attributes(Context *ctx) {
     OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)((size_t)SE_LDS_MAX_N * SE_LDS_MAX_N * sizeof(double))));
     OFRR_HIP(hipFuncSetAttribute((const void *)k_pencil_general<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)((size_t)GN_LDS_MAX_N * GN_LDS_MAX_N * sizeof(double))));
+                                 (int)((size_t)(GN_LDS_MAX_N | 1) * GN_LDS_MAX_N * sizeof(double))));
     done.insert(ctx->device);
 }
 
@@ -2520,7 +2583,7 @@ const int32_t *pencil_general_async(Context *ctx, int32_t b, const double *H, co
     w.lcode = ctx->buf<int>("gpencil_lcode", (size_t)w.cap);
     int *status = ctx->buf<int>("gpencil_status", 4);
     const int use_lds = b <= GN_LDS_MAX_N ? 1 : 0;
-    const size_t shmem = use_lds ? nn * sizeof(double) : 0;
+    const size_t shmem = use_lds ? (size_t)(b | 1) * b * sizeof(double) : 0;
     KTimer tm(ctx, "small_eig");
     if (use_lds)
         hipLaunchKernelGGL(k_pencil_general<true>, dim3(1), dim3(SE_THREADS), shmem, ctx->stream, H, G, b, theta_re,
