@@ -2462,11 +2462,13 @@ __global__ void k_transpose_f64(const double *__restrict__ src, int rows, int co
 __global__ __launch_bounds__(SE_THREADS) void k_svdp_jacobi(double *__restrict__ M, int m, int q, SvdpWork w,
                                                             double *__restrict__ sigma, double *__restrict__ Lo,
                                                             int lo_ld, double *__restrict__ Ro, int ro_ld,
-                                                            const int *status) {
+                                                            int run_jacobi, const int *status) {
     if (status[0] != 0) return;
     __shared__ int s_rot;
     const int t = threadIdx.x, T = blockDim.x, wave = t >> 6, lane = t & 63, nw = T >> 6;
-    (void)jacobi_svd<8>(M, m, q, w.V, &s_rot);  // launched for m <= 256 only
+    // (run_jacobi = 0: the block Jacobi launch before this one left the
+    // rotated M and its V)
+    if (run_jacobi) (void)jacobi_svd<8>(M, m, q, w.V, &s_rot);  // launched for m <= 256 only
     // column norms: a wavefront per column
     for (int j = wave; j < q; j += nw) {
         double s2 = 0.0;
@@ -2487,6 +2489,152 @@ __global__ __launch_bounds__(SE_THREADS) void k_svdp_jacobi(double *__restrict__
     for (int e = t; e < q * q; e += T) {
         const int row = e % q, c = e / q;
         Ro[row + (int64_t)c * ro_ld] = w.V[row + (int64_t)w.ord[c] * q] * h;
+    }
+}
+
+// The same one-sided Jacobi spread over workgroups (q >= BJ_MIN_Q, m <= 256,
+// cooperative launch of nblk / 2 workgroups).  The q columns form nblk
+// blocks of at most BJ_NB (nblk even; a block past q is empty).  A sweep is
+// nblk - 1 rounds: in each round a round-robin tournament pairs the blocks,
+// every workgroup copies the columns of its two blocks (of M and of V) into
+// LDS, rotates every pair among them once (a local tournament, a half
+// wavefront per pair, as in the single-workgroup form) and writes them back,
+// and a grid barrier ends the round.  Every pair of columns meets in some
+// round, so a sweep rotates all pairs (those inside a block more than once).
+// The stopping rule is the single-workgroup one, on the sweep's largest
+// cosine and rotation count, gathered by global atomics into slot `sweep`
+// of cmax / nrot (zeroed by the host with the barrier words) and read by
+// every workgroup after the sweep's last barrier, so all leave together.
+// status[0] = 5 when a barrier wait timed out.
+constexpr int BJ_NB = 7, BJ_THREADS = 256, BJ_MIN_Q = 24, BJ_MAX_SWEEPS = 40;
+
+struct BjSync {
+    unsigned *bar;   // barrier counter
+    int *err;        // barrier time-out flag
+    unsigned *cmax;  // BJ_MAX_SWEEPS slots: largest cosine (FP32 bits)
+    int *nrot;       // BJ_MAX_SWEEPS slots: rotations
+};
+
+__global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict__ M, int m, int q,
+                                                             double *__restrict__ V, int nblk, BjSync sy,
+                                                             int *status) {
+    if (status[0] != 0) return;
+    __shared__ double s_m[2 * BJ_NB * 256], s_v[2 * BJ_NB * 256];
+    __shared__ unsigned s_cmax;
+    __shared__ int s_rot;
+    const int t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
+    const int grp = t >> 5, gl = t & 31, ng = BJ_THREADS >> 5;
+    constexpr int LS = 2 * BJ_NB;  // local slots: BJ_NB of each block
+    unsigned epoch = 0;
+    for (int e = g * BJ_THREADS + t; e < q * q; e += G * BJ_THREADS) V[e] = (e % q == e / q) ? 1.0 : 0.0;
+    if (!grid_barrier(sy.bar, (unsigned)G, epoch, sy.err)) {
+        if (g == 0 && t == 0) status[0] = 5;
+        return;
+    }
+    const double tol = 0x1p-52 * sqrt((double)m);
+    const float cfin = (float)(0.1 * sqrt(tol));
+    for (int sweep = 0; sweep < BJ_MAX_SWEEPS; ++sweep) {
+        for (int round = 0; round < nblk - 1; ++round) {
+            auto bpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (nblk - 1)) + 1; };
+            int bi = bpos(g), bj = bpos(nblk - 1 - g);
+            if (bi > bj) {
+                const int x = bi;
+                bi = bj;
+                bj = x;
+            }
+            const int i0 = bi * BJ_NB, j0 = bj * BJ_NB;
+            const int ci = min(max(q - i0, 0), BJ_NB), cj = min(max(q - j0, 0), BJ_NB);
+            // column of local slot sl, or -1 (slots of block bi come first,
+            // so slot order is column order)
+            auto gcol = [&](int sl) {
+                return sl < BJ_NB ? (sl < ci ? i0 + sl : -1) : (sl - BJ_NB < cj ? j0 + sl - BJ_NB : -1);
+            };
+            if (t == 0) {
+                s_cmax = 0u;
+                s_rot = 0;
+            }
+            for (int e = t; e < LS * m; e += BJ_THREADS) {
+                const int sl = e / m, r = e - sl * m, c = gcol(sl);
+                if (c >= 0) s_m[sl * m + r] = M[(int64_t)c * m + r];
+            }
+            for (int e = t; e < LS * q; e += BJ_THREADS) {
+                const int sl = e / q, r = e - sl * q, c = gcol(sl);
+                if (c >= 0) s_v[sl * q + r] = V[(int64_t)c * q + r];
+            }
+            __syncthreads();
+            for (int step = 0; step < LS - 1; ++step) {
+                auto lpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + step) % (LS - 1)) + 1; };
+                for (int pr = grp; pr < LS / 2; pr += ng) {
+                    int a0 = lpos(pr), b0 = lpos(LS - 1 - pr);
+                    if (a0 > b0) {
+                        const int x = a0;
+                        a0 = b0;
+                        b0 = x;
+                    }
+                    if (gcol(a0) < 0 || gcol(b0) < 0) continue;
+                    double *gi = s_m + a0 * m, *gj = s_m + b0 * m;
+                    double *vi = s_v + a0 * q, *vj = s_v + b0 * q;
+                    double a[8], b[8], c[8], d[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int r = gl + 32 * u;
+                        a[u] = r < m ? gi[r] : 0.0;
+                        b[u] = r < m ? gj[r] : 0.0;
+                        c[u] = r < q ? vi[r] : 0.0;
+                        d[u] = r < q ? vj[r] : 0.0;
+                    }
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        al += a[u] * a[u];
+                        be += b[u] * b[u];
+                        ga += a[u] * b[u];
+                    }
+                    al = half_wave_sum(al);
+                    be = half_wave_sum(be);
+                    ga = half_wave_sum(ga);
+                    const double nab = sqrt(al * be);
+                    if (gl == 0 && nab > 0.0) atomicMax(&s_cmax, __float_as_uint((float)(fabs(ga) / nab)));
+                    if (!(fabs(ga) > tol * nab)) continue;
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int r = gl + 32 * u;
+                        if (r < m) {
+                            gi[r] = cs * a[u] - sn * b[u];
+                            gj[r] = sn * a[u] + cs * b[u];
+                        }
+                        if (r < q) {
+                            vi[r] = cs * c[u] - sn * d[u];
+                            vj[r] = sn * c[u] + cs * d[u];
+                        }
+                    }
+                    if (gl == 0) atomicAdd(&s_rot, 1);
+                }
+                __syncthreads();
+            }
+            for (int e = t; e < LS * m; e += BJ_THREADS) {
+                const int sl = e / m, r = e - sl * m, c = gcol(sl);
+                if (c >= 0) M[(int64_t)c * m + r] = s_m[sl * m + r];
+            }
+            for (int e = t; e < LS * q; e += BJ_THREADS) {
+                const int sl = e / q, r = e - sl * q, c = gcol(sl);
+                if (c >= 0) V[(int64_t)c * q + r] = s_v[sl * q + r];
+            }
+            if (t == 0) {
+                atomicMax(sy.cmax + sweep, s_cmax);
+                atomicAdd(sy.nrot + sweep, s_rot);
+            }
+            if (!grid_barrier(sy.bar, (unsigned)G, epoch, sy.err)) {
+                if (g == 0 && t == 0) status[0] = 5;
+                return;
+            }
+        }
+        const int nrot = __hip_atomic_load(sy.nrot + sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float cm = __uint_as_float(__hip_atomic_load(sy.cmax + sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (nrot == 0 || cm <= cfin) break;
     }
 }
 
@@ -2640,16 +2788,39 @@ void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const dou
         hipLaunchKernelGGL(k_tri_cols<true>, dim3((k1 + 3) / 4), dim3(256), 0, ctx->stream, w.LV, w.iv, k2, Ct,
                            k1, status);
         const int r = k1 < k2 ? k1 : k2;
+        unsigned *bj = ctx->buf<unsigned>("svdp_bj_sync", 2 + 2 * BJ_MAX_SWEEPS);
+        // Jacobi on Mx (mr x qc, mr >= qc): across workgroups when qc is
+        // large enough to pay for the grid barriers, then norms, order and
+        // the scaled vectors in one workgroup
+        auto jacobi = [&](double *Mx, int mr, int qc, double *Lo, int lo_ld, double *Ro, int ro_ld) {
+            int run = 1;
+            if (qc >= BJ_MIN_Q) {
+                int nblk = (qc + BJ_NB - 1) / BJ_NB;
+                nblk += nblk & 1;
+                BjSync sy;
+                sy.bar = bj;
+                sy.err = reinterpret_cast<int *>(bj + 1);
+                sy.cmax = bj + 2;
+                sy.nrot = reinterpret_cast<int *>(bj + 2 + BJ_MAX_SWEEPS);
+                zero_bytes(ctx, bj, sizeof(unsigned) * (2 + 2 * BJ_MAX_SWEEPS));
+                double *Vp = w.V;
+                int *stp = status;
+                void *args[] = {&Mx, &mr, &qc, &Vp, &nblk, &sy, &stp};
+                OFRR_HIP(hipLaunchCooperativeKernel((const void *)k_svdp_bjacobi, dim3(nblk / 2), dim3(BJ_THREADS),
+                                                    args, 0, ctx->stream));
+                run = 0;
+            }
+            hipLaunchKernelGGL(k_svdp_jacobi, dim3(1), dim3(SE_THREADS), 0, ctx->stream, Mx, mr, qc, w, sigma, Lo,
+                               lo_ld, Ro, ro_ld, run, status);
+        };
         if (k2 >= k1) {
             // Jacobi on C^T (k2 x k1): C^T V' = U' S, so C = V' S U'^T: the left
             // vectors of C are V' (length k1), the right ones U' (length k2)
-            hipLaunchKernelGGL(k_svdp_jacobi, dim3(1), dim3(SE_THREADS), 0, ctx->stream, Ct, k2, k1, w, sigma, Z,
-                               k2, Y, k1, status);
+            jacobi(Ct, k2, k1, Z, k2, Y, k1);
         } else {
             double *C = w.T;
             hipLaunchKernelGGL(k_transpose_f64, dim3(64), dim3(256), 0, ctx->stream, Ct, k2, k1, C, status);
-            hipLaunchKernelGGL(k_svdp_jacobi, dim3(1), dim3(SE_THREADS), 0, ctx->stream, C, k1, k2, w, sigma, Y,
-                               k1, Z, k2, status);
+            jacobi(C, k1, k2, Y, k1, Z, k2);
         }
         // y = L_U^{-T} (u / sqrt 2), z = L_V^{-T} (v / sqrt 2)
         hipLaunchKernelGGL(k_tri_cols<false>, dim3((r + 3) / 4), dim3(256), 0, ctx->stream, w.LUt, w.iu, k1, Y, r,
@@ -2662,6 +2833,7 @@ void svd_pencil(Context *ctx, int32_t k1, int32_t k2, const double *B, const dou
         ctx->sync();
         if (host == 3) fail(OFRR_ERR_NUMERIC, "svd pencil: U^T U not positive definite");
         if (host == 4) fail(OFRR_ERR_NUMERIC, "svd pencil: V^T V not positive definite");
+        if (host == 5) fail(OFRR_ERR_HIP, "svd pencil: a grid barrier of the Jacobi sweeps timed out");
         return;
     }
     const int N = k1 + k2;
