@@ -419,9 +419,40 @@ __device__ bool cholesky(double *A, int n, int rel_floor) {
         for (int i = j + t; i < n; i += T) A[i + j * n] = (i == j) ? l : A[i + j * n] / l;
         __syncthreads();
         const int rem = n - j - 1;
-        for (int e = t; e < rem * rem; e += T) {
-            const int ii = j + 1 + e % rem, kk = j + 1 + e / rem;
-            if (kk <= ii) A[ii + kk * n] -= A[ii + j * n] * A[kk + j * n];
+        if (rem <= 256 && T == 1024) {
+            // thread (tr, tc): trailing rows tr + 32 p, columns tc + 32 q; the
+            // thread's entries of column j in registers, and two columns'
+            // loads issued before their stores (independent, in flight together)
+            const int tr = t & 31, tc = t >> 5;
+            double lj[8];
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                const int i0 = tr + 32 * p;
+                lj[p] = i0 < rem ? A[(j + 1 + i0) + (int64_t)j * n] : 0.0;
+            }
+            for (int k0 = tc; k0 < rem; k0 += 64) {
+                const int k1 = k0 + 32;
+                const double lk0 = A[(j + 1 + k0) + (int64_t)j * n];
+                const double lk1 = k1 < rem ? A[(j + 1 + k1) + (int64_t)j * n] : 0.0;
+                double x0[8], x1[8];
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const int i0 = tr + 32 * p;
+                    x0[p] = (i0 < rem && i0 >= k0) ? A[(j + 1 + i0) + (int64_t)(j + 1 + k0) * n] : 0.0;
+                    x1[p] = (i0 < rem && i0 >= k1) ? A[(j + 1 + i0) + (int64_t)(j + 1 + k1) * n] : 0.0;
+                }
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const int i0 = tr + 32 * p;
+                    if (i0 < rem && i0 >= k0) A[(j + 1 + i0) + (int64_t)(j + 1 + k0) * n] = x0[p] - lj[p] * lk0;
+                    if (i0 < rem && i0 >= k1) A[(j + 1 + i0) + (int64_t)(j + 1 + k1) * n] = x1[p] - lj[p] * lk1;
+                }
+            }
+        } else {
+            for (int e = t; e < rem * rem; e += T) {
+                const int ii = j + 1 + e % rem, kk = j + 1 + e / rem;
+                if (kk <= ii) A[ii + kk * n] -= A[ii + j * n] * A[kk + j * n];
+            }
         }
         __syncthreads();
     }
@@ -2553,13 +2584,21 @@ __global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict_
                 s_cmax = 0u;
                 s_rot = 0;
             }
-            for (int e = t; e < LS * m; e += BJ_THREADS) {
-                const int sl = e / m, r = e - sl * m, c = gcol(sl);
-                if (c >= 0) s_m[sl * m + r] = M[(int64_t)c * m + r];
-            }
-            for (int e = t; e < LS * q; e += BJ_THREADS) {
-                const int sl = e / q, r = e - sl * q, c = gcol(sl);
-                if (c >= 0) s_v[sl * q + r] = V[(int64_t)c * q + r];
+            // thread t moves row t of every slot (m, q <= BJ_THREADS): all
+            // global loads issued before the first LDS store
+            {
+                double xm[LS], xv[LS];
+#pragma unroll
+                for (int sl = 0; sl < LS; ++sl) {
+                    const int c = gcol(sl);
+                    xm[sl] = (c >= 0 && t < m) ? M[(int64_t)c * m + t] : 0.0;
+                    xv[sl] = (c >= 0 && t < q) ? V[(int64_t)c * q + t] : 0.0;
+                }
+#pragma unroll
+                for (int sl = 0; sl < LS; ++sl) {
+                    if (t < m) s_m[sl * m + t] = xm[sl];
+                    if (t < q) s_v[sl * q + t] = xv[sl];
+                }
             }
             __syncthreads();
             for (int step = 0; step < LS - 1; ++step) {
@@ -2615,13 +2654,11 @@ __global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict_
                 }
                 __syncthreads();
             }
-            for (int e = t; e < LS * m; e += BJ_THREADS) {
-                const int sl = e / m, r = e - sl * m, c = gcol(sl);
-                if (c >= 0) M[(int64_t)c * m + r] = s_m[sl * m + r];
-            }
-            for (int e = t; e < LS * q; e += BJ_THREADS) {
-                const int sl = e / q, r = e - sl * q, c = gcol(sl);
-                if (c >= 0) V[(int64_t)c * q + r] = s_v[sl * q + r];
+#pragma unroll
+            for (int sl = 0; sl < LS; ++sl) {
+                const int c = gcol(sl);
+                if (c >= 0 && t < m) M[(int64_t)c * m + t] = s_m[sl * m + t];
+                if (c >= 0 && t < q) V[(int64_t)c * q + t] = s_v[sl * q + t];
             }
             if (t == 0) {
                 atomicMax(sy.cmax + sweep, s_cmax);
