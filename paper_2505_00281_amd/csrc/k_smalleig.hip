@@ -29,6 +29,7 @@
 //      equal eigenvalues so degenerate pairs stay independent.
 //   4. Z = Q Z_T by applying the reflectors in reverse order.
 #include <set>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "device_util.hpp"
@@ -660,11 +661,8 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil(const double *__restrict_
 // One step of the tournament: pair pr goes to the 32-lane group pr mod 32
 // (a half wavefront; the lanes hold rows l + 32 u), so 32 pairs are in
 // flight at once.
-__device__ __forceinline__ double half_wave_sum(double v) {
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+
+__device__ double half_wave_sum(double v);  // defined with the DPP helpers below
 
 template <int MAXR>
 __device__ void jacobi_rotate_pairs(double *M, int m, double *V, int q, int mm, int step, double tol, int *s_rot,
@@ -943,6 +941,22 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+// Sum over each 32-lane half of the wave, in every lane of that half: DPP
+// sums inside rows of 16 lanes, then the other row's sum by a swizzle (lane
+// xor 16).  Only lanes of the same half are read, so the other half may be
+// inactive.
+__device__ double half_wave_sum(double v) {
+    v += dpp_f64<DPP_XOR1>(v);
+    v += dpp_f64<DPP_XOR2>(v);
+    v += dpp_f64<DPP_HALF_MIRROR>(v);
+    v += dpp_f64<DPP_MIRROR>(v);
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    constexpr int XOR16 = 0x1F | (0x10 << 10);  // bit mode: and 31, or 0, xor 16
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)u, XOR16);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), XOR16);
+    return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
 // Sum over the 64 lanes with a fixed pattern (rows of 16 lanes, then the
@@ -2526,17 +2540,20 @@ __global__ __launch_bounds__(SE_THREADS) void k_svdp_jacobi(double *__restrict__
 // The same one-sided Jacobi spread over workgroups (q >= BJ_MIN_Q, m <= 256,
 // cooperative launch of nblk / 2 workgroups).  The q columns form nblk
 // blocks of at most BJ_NB (nblk even; a block past q is empty).  A sweep is
-// nblk - 1 rounds: in each round a round-robin tournament pairs the blocks,
-// every workgroup copies the columns of its two blocks (of M and of V) into
-// LDS, rotates every pair among them once (a local tournament, a half
-// wavefront per pair, as in the single-workgroup form) and writes them back,
-// and a grid barrier ends the round.  Every pair of columns meets in some
-// round, so a sweep rotates all pairs (those inside a block more than once).
-// The stopping rule is the single-workgroup one, on the sweep's largest
-// cosine and rotation count, gathered by global atomics into slot `sweep`
-// of cmax / nrot (zeroed by the host with the barrier words) and read by
-// every workgroup after the sweep's last barrier, so all leave together.
-// status[0] = 5 when a barrier wait timed out.
+// one inner round and nblk - 1 cross rounds, each ended by a grid barrier:
+//   inner: workgroup g copies blocks 2g and 2g + 1 (their columns of M and
+//          of V) into LDS and rotates every pair among them once (a local
+//          round-robin tournament, a half wavefront per pair);
+//   cross: a round-robin tournament pairs the blocks; of its pair (I, J)
+//          a workgroup keeps one column of I in each half wavefront's
+//          registers and J in LDS, and in BJ_NB steps every half wavefront
+//          meets every column of J (step s: column (p + s) mod BJ_NB).
+// So every pair of columns is rotated in each sweep.  The stopping rule is
+// the single-workgroup one, on the sweep's largest cosine and rotation
+// count, gathered by global atomics into slot `sweep` of cmax / nrot (zeroed
+// by the host with the barrier words) and read by every workgroup after the
+// sweep's last barrier, so all leave together.  status[0] = 5 when a
+// barrier wait timed out.
 constexpr int BJ_NB = 7, BJ_THREADS = 256, BJ_MIN_Q = 24, BJ_MAX_SWEEPS = 40;
 
 struct BjSync {
@@ -2546,6 +2563,49 @@ struct BjSync {
     int *nrot;       // BJ_MAX_SWEEPS slots: rotations
 };
 
+// One Jacobi rotation of a column pair held by a half wavefront (a, c: the
+// lower-numbered column of M and of V; b, d: the other; row gl + 32 u in
+// slot u).  The cosine of the pair goes to s_cmax, a rotation to s_rot.
+// Reciprocals and square roots are hardware estimates refined by Newton
+// steps (a few ulps: the rotation stays orthogonal to working accuracy).
+__device__ __forceinline__ void bj_rotate(double (&a)[8], double (&b)[8], double (&c)[8], double (&d)[8], double tol,
+                                          int gl, unsigned *s_cmax, int *s_rot) {
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        al = fma(a[u], a[u], al);
+        be = fma(b[u], b[u], be);
+        ga = fma(a[u], b[u], ga);
+    }
+    al = half_wave_sum(al);
+    be = half_wave_sum(be);
+    ga = half_wave_sum(ga);
+    const double pab = al * be;
+    // (columns of norm below 2^-500 are left alone)
+    if (!(pab > 0x1p-1000)) return;
+    const double cosv = fabs(ga) * rsqrt_nr(pab);
+    if (gl == 0) atomicMax(s_cmax, __float_as_uint((float)cosv));
+    if (!(cosv > tol)) return;
+    const double zeta = (be - al) * 0.5 * rcp_nr(ga);
+    double tt;
+    if (fabs(zeta) > 0x1p500) {
+        tt = 0.5 * rcp_nr(zeta);
+    } else {
+        const double z2 = fma(zeta, zeta, 1.0);
+        tt = copysign(rcp_nr(fabs(zeta) + z2 * rsqrt_nr(z2)), zeta);
+    }
+    const double cs = rsqrt_nr(fma(tt, tt, 1.0)), sn = cs * tt;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double x = a[u], y = b[u], z = c[u], w = d[u];
+        a[u] = cs * x - sn * y;
+        b[u] = sn * x + cs * y;
+        c[u] = cs * z - sn * w;
+        d[u] = sn * z + cs * w;
+    }
+    if (gl == 0) atomicAdd(s_rot, 1);
+}
+
 __global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict__ M, int m, int q,
                                                              double *__restrict__ V, int nblk, BjSync sy,
                                                              int *status) {
@@ -2554,8 +2614,8 @@ __global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict_
     __shared__ unsigned s_cmax;
     __shared__ int s_rot;
     const int t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
-    const int grp = t >> 5, gl = t & 31, ng = BJ_THREADS >> 5;
-    constexpr int LS = 2 * BJ_NB;  // local slots: BJ_NB of each block
+    const int grp = t >> 5, gl = t & 31;
+    constexpr int LS = 2 * BJ_NB;  // slots of the inner round: BJ_NB of each block
     unsigned epoch = 0;
     for (int e = g * BJ_THREADS + t; e < q * q; e += G * BJ_THREADS) V[e] = (e % q == e / q) ? 1.0 : 0.0;
     if (!grid_barrier(sy.bar, (unsigned)G, epoch, sy.err)) {
@@ -2564,101 +2624,145 @@ __global__ __launch_bounds__(BJ_THREADS) void k_svdp_bjacobi(double *__restrict_
     }
     const double tol = 0x1p-52 * sqrt((double)m);
     const float cfin = (float)(0.1 * sqrt(tol));
+    // thread t moves row t of slots [0, ns) between the columns col(slot)
+    // and LDS (m, q <= BJ_THREADS); every global load before the first store
+    auto to_lds = [&](auto col, auto ns_tag) {
+        constexpr int NS = decltype(ns_tag)::value;
+        double xm[NS], xv[NS];
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int c = col(sl);
+            xm[sl] = (c >= 0 && t < m) ? M[(int64_t)c * m + t] : 0.0;
+            xv[sl] = (c >= 0 && t < q) ? V[(int64_t)c * q + t] : 0.0;
+        }
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            if (t < m) s_m[sl * m + t] = xm[sl];
+            if (t < q) s_v[sl * q + t] = xv[sl];
+        }
+    };
+    auto from_lds = [&](auto col, auto ns_tag) {
+        constexpr int NS = decltype(ns_tag)::value;
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int c = col(sl);
+            if (c >= 0 && t < m) M[(int64_t)c * m + t] = s_m[sl * m + t];
+            if (c >= 0 && t < q) V[(int64_t)c * q + t] = s_v[sl * q + t];
+        }
+    };
+    using NSInner = std::integral_constant<int, LS>;
+    using NSBlock = std::integral_constant<int, BJ_NB>;
     for (int sweep = 0; sweep < BJ_MAX_SWEEPS; ++sweep) {
-        for (int round = 0; round < nblk - 1; ++round) {
-            auto bpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (nblk - 1)) + 1; };
-            int bi = bpos(g), bj = bpos(nblk - 1 - g);
-            if (bi > bj) {
-                const int x = bi;
-                bi = bj;
-                bj = x;
+        for (int round = -1; round < nblk - 1; ++round) {
+            int bi, bj;
+            if (round < 0) {
+                bi = 2 * g;
+                bj = 2 * g + 1;
+            } else {
+                auto bpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + round) % (nblk - 1)) + 1; };
+                bi = bpos(g);
+                bj = bpos(nblk - 1 - g);
+                if (bi > bj) {
+                    const int x = bi;
+                    bi = bj;
+                    bj = x;
+                }
             }
             const int i0 = bi * BJ_NB, j0 = bj * BJ_NB;
             const int ci = min(max(q - i0, 0), BJ_NB), cj = min(max(q - j0, 0), BJ_NB);
-            // column of local slot sl, or -1 (slots of block bi come first,
-            // so slot order is column order)
-            auto gcol = [&](int sl) {
-                return sl < BJ_NB ? (sl < ci ? i0 + sl : -1) : (sl - BJ_NB < cj ? j0 + sl - BJ_NB : -1);
-            };
             if (t == 0) {
                 s_cmax = 0u;
                 s_rot = 0;
             }
-            // thread t moves row t of every slot (m, q <= BJ_THREADS): all
-            // global loads issued before the first LDS store
-            {
-                double xm[LS], xv[LS];
-#pragma unroll
-                for (int sl = 0; sl < LS; ++sl) {
-                    const int c = gcol(sl);
-                    xm[sl] = (c >= 0 && t < m) ? M[(int64_t)c * m + t] : 0.0;
-                    xv[sl] = (c >= 0 && t < q) ? V[(int64_t)c * q + t] : 0.0;
-                }
-#pragma unroll
-                for (int sl = 0; sl < LS; ++sl) {
-                    if (t < m) s_m[sl * m + t] = xm[sl];
-                    if (t < q) s_v[sl * q + t] = xv[sl];
-                }
-            }
-            __syncthreads();
-            for (int step = 0; step < LS - 1; ++step) {
-                auto lpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + step) % (LS - 1)) + 1; };
-                for (int pr = grp; pr < LS / 2; pr += ng) {
-                    int a0 = lpos(pr), b0 = lpos(LS - 1 - pr);
-                    if (a0 > b0) {
-                        const int x = a0;
-                        a0 = b0;
-                        b0 = x;
-                    }
-                    if (gcol(a0) < 0 || gcol(b0) < 0) continue;
-                    double *gi = s_m + a0 * m, *gj = s_m + b0 * m;
-                    double *vi = s_v + a0 * q, *vj = s_v + b0 * q;
-                    double a[8], b[8], c[8], d[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int r = gl + 32 * u;
-                        a[u] = r < m ? gi[r] : 0.0;
-                        b[u] = r < m ? gj[r] : 0.0;
-                        c[u] = r < q ? vi[r] : 0.0;
-                        d[u] = r < q ? vj[r] : 0.0;
-                    }
-                    double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        al += a[u] * a[u];
-                        be += b[u] * b[u];
-                        ga += a[u] * b[u];
-                    }
-                    al = half_wave_sum(al);
-                    be = half_wave_sum(be);
-                    ga = half_wave_sum(ga);
-                    const double nab = sqrt(al * be);
-                    if (gl == 0 && nab > 0.0) atomicMax(&s_cmax, __float_as_uint((float)(fabs(ga) / nab)));
-                    if (!(fabs(ga) > tol * nab)) continue;
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int r = gl + 32 * u;
-                        if (r < m) {
-                            gi[r] = cs * a[u] - sn * b[u];
-                            gj[r] = sn * a[u] + cs * b[u];
+            if (round < 0) {
+                // inner round: slots of block bi first, so slot order is column order
+                auto gcol = [&](int sl) {
+                    return sl < BJ_NB ? (sl < ci ? i0 + sl : -1) : (sl - BJ_NB < cj ? j0 + sl - BJ_NB : -1);
+                };
+                to_lds(gcol, NSInner{});
+                __syncthreads();
+                for (int step = 0; step < LS - 1; ++step) {
+                    auto lpos = [&](int k) { return k == 0 ? 0 : ((k - 1 + step) % (LS - 1)) + 1; };
+                    if (grp < LS / 2) {
+                        int a0 = lpos(grp), b0 = lpos(LS - 1 - grp);
+                        if (a0 > b0) {
+                            const int x = a0;
+                            a0 = b0;
+                            b0 = x;
                         }
-                        if (r < q) {
-                            vi[r] = cs * c[u] - sn * d[u];
-                            vj[r] = sn * c[u] + cs * d[u];
+                        if (gcol(a0) >= 0 && gcol(b0) >= 0) {
+                            double *gi = s_m + a0 * m, *gj = s_m + b0 * m;
+                            double *vi = s_v + a0 * q, *vj = s_v + b0 * q;
+                            double a[8], b[8], c[8], d[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int r = gl + 32 * u;
+                                a[u] = r < m ? gi[r] : 0.0;
+                                b[u] = r < m ? gj[r] : 0.0;
+                                c[u] = r < q ? vi[r] : 0.0;
+                                d[u] = r < q ? vj[r] : 0.0;
+                            }
+                            bj_rotate(a, b, c, d, tol, gl, &s_cmax, &s_rot);
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int r = gl + 32 * u;
+                                if (r < m) {
+                                    gi[r] = a[u];
+                                    gj[r] = b[u];
+                                }
+                                if (r < q) {
+                                    vi[r] = c[u];
+                                    vj[r] = d[u];
+                                }
+                            }
                         }
                     }
-                    if (gl == 0) atomicAdd(&s_rot, 1);
+                    __syncthreads();
+                }
+                from_lds(gcol, NSInner{});
+            } else {
+                // cross round: J in LDS, column i0 + grp of I in registers
+                auto jcol = [&](int sl) { return sl < cj ? j0 + sl : -1; };
+                to_lds(jcol, NSBlock{});
+                const int ic = (grp < BJ_NB && grp < ci) ? i0 + grp : -1;
+                double a[8], c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int r = gl + 32 * u;
+                    a[u] = (ic >= 0 && r < m) ? M[(int64_t)ic * m + r] : 0.0;
+                    c[u] = (ic >= 0 && r < q) ? V[(int64_t)ic * q + r] : 0.0;
                 }
                 __syncthreads();
-            }
+                for (int step = 0; step < BJ_NB; ++step) {
+                    const int s = (grp + step) % BJ_NB;
+                    if (ic >= 0 && s < cj) {
+                        double *gj = s_m + s * m, *vj = s_v + s * q;
+                        double b[8], d[8];
 #pragma unroll
-            for (int sl = 0; sl < LS; ++sl) {
-                const int c = gcol(sl);
-                if (c >= 0 && t < m) M[(int64_t)c * m + t] = s_m[sl * m + t];
-                if (c >= 0 && t < q) V[(int64_t)c * q + t] = s_v[sl * q + t];
+                        for (int u = 0; u < 8; ++u) {
+                            const int r = gl + 32 * u;
+                            b[u] = r < m ? gj[r] : 0.0;
+                            d[u] = r < q ? vj[r] : 0.0;
+                        }
+                        bj_rotate(a, b, c, d, tol, gl, &s_cmax, &s_rot);
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int r = gl + 32 * u;
+                            if (r < m) gj[r] = b[u];
+                            if (r < q) vj[r] = d[u];
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (ic >= 0) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int r = gl + 32 * u;
+                        if (r < m) M[(int64_t)ic * m + r] = a[u];
+                        if (r < q) V[(int64_t)ic * q + r] = c[u];
+                    }
+                }
+                from_lds(jcol, NSBlock{});
             }
             if (t == 0) {
                 atomicMax(sy.cmax + sweep, s_cmax);
