@@ -2416,6 +2416,85 @@ struct SvdpWork {
     int *ord;
 };
 
+// Blocked right-looking Cholesky for n <= 256 with 1024 threads (positive
+// pivots required): per panel of CP columns, the panel (rows j0..n-1) is
+// factorised in LDS, written back, and the trailing lower triangle takes the
+// panel's rank-CP update in one pass (thread (tr, tc): rows tr + 32 p,
+// columns tc + 32 q of the trailing block), so global memory is visited once
+// per panel instead of once per column.
+constexpr int CP = 8;
+__device__ bool cholesky_panel256(double *A, int n) {
+    __shared__ double P[256 * CP];
+    __shared__ int s_bad;
+    const int t = threadIdx.x, T = blockDim.x;
+    if (t == 0) s_bad = 0;
+    for (int j0 = 0; j0 < n; j0 += CP) {
+        const int nb = min(CP, n - j0), rows = n - j0;
+        for (int e = t; e < rows * nb; e += T) {
+            const int r = e % rows, c = e / rows;
+            P[r + c * 256] = A[(j0 + r) + (int64_t)(j0 + c) * n];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nb; ++jj) {
+            const double d = P[jj + jj * 256];
+            if (!(d > 0.0)) {
+                if (t == 0) s_bad = 1;
+                break;
+            }
+            const double l = sqrt(d);
+            __syncthreads();
+            for (int r = jj + t; r < rows; r += T) P[r + jj * 256] = (r == jj) ? l : P[r + jj * 256] / l;
+            __syncthreads();
+            // rank-1 update of the panel's later columns (rows >= their index)
+            for (int e = t; e < rows * (nb - jj - 1); e += T) {
+                const int r = e % rows, c = jj + 1 + e / rows;
+                if (r >= c) P[r + c * 256] -= P[r + jj * 256] * P[c + jj * 256];
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (s_bad) return false;
+        for (int e = t; e < rows * nb; e += T) {
+            const int r = e % rows, c = e / rows;
+            A[(j0 + r) + (int64_t)(j0 + c) * n] = r >= c ? P[r + c * 256] : 0.0;
+        }
+        // trailing update: rows and columns j0 + nb .. n-1
+        const int k0 = j0 + nb, rem = n - k0;
+        if (rem > 0) {
+            const int tr = t & 31, tc = t >> 5;
+            for (int cq = tc; cq < rem; cq += 32) {
+                double lc[CP];
+#pragma unroll
+                for (int jj = 0; jj < CP; ++jj) lc[jj] = jj < nb ? P[(nb + cq) + jj * 256] : 0.0;
+                double x[8];
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const int rp = tr + 32 * p;
+                    x[p] = (rp < rem && rp >= cq) ? A[(k0 + rp) + (int64_t)(k0 + cq) * n] : 0.0;
+                }
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const int rp = tr + 32 * p;
+                    if (rp < rem && rp >= cq) {
+                        double s = x[p];
+#pragma unroll
+                        for (int jj = 0; jj < CP; ++jj) s -= P[(nb + rp) + jj * 256] * lc[jj];
+                        A[(k0 + rp) + (int64_t)(k0 + cq) * n] = s;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // the strict upper triangle above the panels' diagonal blocks
+    for (int e = t; e < n * n; e += T) {
+        const int i = e % n, j = e / n;
+        if (i < j) A[e] = 0.0;
+    }
+    __syncthreads();
+    return true;
+}
+
 __global__ __launch_bounds__(SE_THREADS) void k_svdp_chol(const double *__restrict__ MU, int k1,
                                                           const double *__restrict__ MV, int k2, SvdpWork w,
                                                           int *status) {
@@ -2429,7 +2508,7 @@ __global__ __launch_bounds__(SE_THREADS) void k_svdp_chol(const double *__restri
         L[e] = 0.5 * (Msrc[i + j * k] + Msrc[j + i * k]);
     }
     __syncthreads();
-    if (!cholesky(L, k, 0)) {
+    if (!cholesky_panel256(L, k)) {
         if (t == 0) atomicMax(status, u ? 3 : 4);
         return;
     }
