@@ -1824,6 +1824,79 @@ __device__ void gn_apply_log(double *Q, int n, const double *lg, const int *lcod
     }
 }
 
+// The same product by the whole workgroup, row t of Q per thread (n <= the
+// workgroup size): the log passes through LDS in chunks of GN_CHUNK entries
+// (each chunk one batch of loads by all threads, read back as broadcasts),
+// and a row holds the GN_PF columns after its window in registers, loaded
+// GN_PF slides before they enter it.  Columns beyond the window are written
+// only after they have entered it, and a jump reloads window and prefetch.
+constexpr int GN_CHUNK = 64, GN_PF = 8;
+__device__ void gn_apply_log_wg(double *Q, int n, const double *lg, const int *lcode, int count) {
+    __shared__ double s_lg[GN_CHUNK * GN_LOGW];
+    __shared__ int s_code[GN_CHUNK];
+    const int t = threadIdx.x, T = blockDim.x;
+    double *q = Q + t;
+    const bool row = t < n;
+    int base = -1;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    double pf[GN_PF];
+#pragma unroll
+    for (int i = 0; i < GN_PF; ++i) pf[i] = 0.0;
+    for (int c0 = 0; c0 < count; c0 += GN_CHUNK) {
+        const int nc = min(GN_CHUNK, count - c0);
+        __syncthreads();  // the previous chunk has been read by every row
+        for (int e = t; e < nc * GN_LOGW; e += T) s_lg[e] = lg[(int64_t)c0 * GN_LOGW + e];
+        for (int e = t; e < nc; e += T) s_code[e] = lcode[c0 + e];
+        __syncthreads();
+        if (!row) continue;
+        for (int e = 0; e < nc; ++e) {
+            const int code = s_code[e];
+            const int k = code & 0xffff, m = code >> 16;
+            const double v0 = s_lg[GN_LOGW * e], v1 = s_lg[GN_LOGW * e + 1];
+            const double v2 = s_lg[GN_LOGW * e + 2], beta = s_lg[GN_LOGW * e + 3];
+            if (base >= 0 && k == base + 1) {
+                q[(int64_t)base * n] = w0;
+                w0 = w1;
+                w1 = w2;
+                w2 = pf[0];
+#pragma unroll
+                for (int i = 0; i + 1 < GN_PF; ++i) pf[i] = pf[i + 1];
+                const int cn = k + 2 + GN_PF;
+                pf[GN_PF - 1] = cn < n ? q[(int64_t)cn * n] : 0.0;
+                base = k;
+            } else if (k != base) {
+                if (base >= 0) {
+                    q[(int64_t)base * n] = w0;
+                    q[(int64_t)(base + 1) * n] = w1;
+                    if (base + 2 < n) q[(int64_t)(base + 2) * n] = w2;
+                }
+                base = k;
+                w0 = q[(int64_t)k * n];
+                w1 = q[(int64_t)(k + 1) * n];
+                w2 = k + 2 < n ? q[(int64_t)(k + 2) * n] : 0.0;
+#pragma unroll
+                for (int i = 0; i < GN_PF; ++i) pf[i] = k + 3 + i < n ? q[(int64_t)(k + 3 + i) * n] : 0.0;
+            }
+            if (m == 0) {
+                const double u = w0, w = w1;
+                w0 = v0 * u + v1 * w;
+                w1 = v0 * w - v1 * u;
+            } else {
+                const double tt = beta * (v0 * w0 + v1 * w1 + (m == 3 ? v2 * w2 : 0.0));
+                w0 -= tt * v0;
+                w1 -= tt * v1;
+                if (m == 3) w2 -= tt * v2;
+            }
+        }
+    }
+    if (row && base >= 0) {
+        q[(int64_t)base * n] = w0;
+        q[(int64_t)(base + 1) * n] = w1;
+        if (base + 2 < n) q[(int64_t)(base + 2) * n] = w2;
+    }
+    __syncthreads();
+}
+
 template <bool LDS>
 __device__ __forceinline__ void gn_sync() {
     if (LDS)
@@ -2313,7 +2386,10 @@ __global__ __launch_bounds__(SE_THREADS) void k_pencil_general(const double *__r
         }
         return;
     }
-    gn_apply_log(w.Q, n, w.lg, w.lcode, status[2], t, T);
+    if (n <= T)
+        gn_apply_log_wg(w.Q, n, w.lg, w.lcode, status[2]);
+    else
+        gn_apply_log(w.Q, n, w.lg, w.lcode, status[2], t, T);
     // ---- 4. eigenvectors of T, V = Q X_T
     double tn = 0.0;
     for (int e = t; e < n * n; e += T) tn = fmax(tn, fabs(C[e % n + (int64_t)(e / n) * ldc]));
