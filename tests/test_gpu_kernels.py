@@ -510,3 +510,25 @@ def test_svd_pencil(ctx, k1, k2):
     np.testing.assert_allclose(Vt.T @ Vt, np.eye(min(k1, k2)), atol=1e-9)
     # the left and right vectors belong together: 2 Y^T B Z = diag(sigma)
     np.testing.assert_allclose(2.0 * Y.T @ B @ Z, np.diag(s), atol=1e-9 * s[0])
+
+
+@pytest.mark.parametrize("k", [30, 200])
+def test_svd_pencil_not_positive_definite(ctx, k):
+    # a mass matrix with a negative pivot is reported (U^T U: status 3,
+    # V^T V: status 4) before the Jacobi launch, on both sizes of the
+    # pipeline; the context then solves a valid pencil as before
+    from paper_2505_00281_amd import ofrr
+    rng = np.random.default_rng(12)
+    U = rng.standard_normal((3 * k, k))
+    V = rng.standard_normal((3 * k, k))
+    B, MU, MV = U.T @ rng.standard_normal((3 * k, 3 * k)) @ V, U.T @ U, V.T @ V
+    bad = np.eye(k)
+    bad[k // 2, k // 2] = -1.0
+    print("svd pencil not positive definite", k, flush=True)
+    for mu, mv, what in ((bad, MV, "U^T U"), (MU, bad, "V^T V")):
+        with pytest.raises(ofrr.OfrrError) as e:
+            ctx.svd_pencil(_cuda(B), _cuda(mu), _cuda(mv))
+        assert e.value.status == ofrr.ERR_NUMERIC and what in str(e.value)
+    s, _, _ = ctx.svd_pencil(_cuda(B), _cuda(MU), _cuda(MV))
+    s_ref, _, _ = O.svd_pencil(B, MU, MV)
+    np.testing.assert_allclose(s.cpu().numpy(), s_ref[:k], rtol=1e-11)
