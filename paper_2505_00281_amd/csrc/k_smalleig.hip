@@ -2079,12 +2079,21 @@ __device__ void gn_francis(double *C, int n, int ldc, GenWork &w, int *status) {
             have_next = false;
             const double sc = fabs(x) + fabs(y) + fabs(z);
             if (sc == 0.0) continue;
-            const double rs = 1.0 / sc;
+            // scaled by the power of two that brings sc to [1/2, 1) (exact;
+            // the exponent clamped so that both factors stay finite): the
+            // sum of squares then lies in [1/12, 1) and alpha (alpha - xs)
+            // in [1/12, 2), where the refined hardware estimates apply (a
+            // few ulps: the reflector stays orthogonal to working accuracy)
+            int se;
+            (void)frexp(sc, &se);
+            se = se < -1020 ? -1020 : (se > 1020 ? 1020 : se);
+            const double rs = ldexp(1.0, -se), sb = ldexp(1.0, se);
             const double xs = x * rs, ys = y * rs, zs = z * rs;
-            const double nr = sqrt(xs * xs + ys * ys + zs * zs);
+            const double s2 = xs * xs + ys * ys + zs * zs;
+            const double nr = s2 * rsqrt_nr(s2);
             const double alpha = -copysign(nr, xs);
             const double v0 = xs - alpha, v1 = ys, v2 = zs;
-            const double beta = 1.0 / (alpha * (alpha - xs));
+            const double beta = rcp_nr(alpha * (alpha - xs));
             const int c0 = (k > l) ? k - 1 : k;
             const int r1 = (k + 3 < nn) ? k + 3 : nn;
             // left: rows k..k+2 from column c0 on (column k-1 of a chase step
@@ -2107,7 +2116,7 @@ __device__ void gn_francis(double *C, int n, int ldc, GenWork &w, int *status) {
                     double *p = C + k + (int64_t)c * ldc;
                     double n0, n1, n2;
                     if (k > l && c == k - 1) {
-                        n0 = alpha * sc;
+                        n0 = alpha * sb;
                         n1 = 0.0;
                         n2 = 0.0;
                     } else {
@@ -2124,7 +2133,7 @@ __device__ void gn_francis(double *C, int n, int ldc, GenWork &w, int *status) {
                 for (int c = c0 + lane; c < n; c += 64) {
                     double *p = C + k + (int64_t)c * ldc;
                     if (k > l && c == k - 1) {
-                        p[0] = alpha * sc;
+                        p[0] = alpha * sb;
                         p[1] = 0.0;
                         if (m == 3) p[2] = 0.0;
                         continue;
