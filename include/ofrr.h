@@ -523,7 +523,10 @@ ofrr_status ofrr_pencil_eig_general(ofrr_ctx ctx, int32_t b, const double *H, co
 /* The SVD pencil of Sec. 3.2 for B (k1 x k2), MU (k1 x k1), MV (k2 x k2):
  * sigma (min(k1,k2), descending, the positive eigenvalues), Y (k1 x
  * min(k1,k2)), Z (k2 x min(k1,k2)) normalised so that [y; z]^T blkdiag(MU,
- * MV) [y; z] = 1. */
+ * MV) [y; z] = 1.  All device pointers, column-major, k1 + k2 <= 1024.
+ * OFRR_ERR_NUMERIC if MU or MV is not positive definite (the message names
+ * which); OFRR_ERR_HIP if a grid barrier of the multi-workgroup Jacobi
+ * sweeps (k1, k2 <= 256) timed out. */
 ofrr_status ofrr_svd_pencil(ofrr_ctx ctx, int32_t k1, int32_t k2, const double *B,
                             const double *MU, const double *MV, double *sigma, double *Y,
                             double *Z);
