@@ -1347,7 +1347,9 @@ template <class T>
 int32_t run_panel(Context *ctx, int64_t n, int32_t b, T *Y, int64_t ldy, double tol, int32_t *piv, int32_t *keep,
                   const int32_t **status, const WordsBuf &wb) {
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    const int G = (int)std::min<int64_t>(cus, (n + HP_NT - 1) / HP_NT);
+    // every CU takes a slice once there are 256 rows per CU (more slices
+    // stream the trailing block with more of the chip's memory paths)
+    const int G = (int)std::min<int64_t>(cus, (n + HP_NT / 2 - 1) / (HP_NT / 2));
     const int64_t per = (n + G - 1) / G;
     const int R = (int)((per + HP_NT - 1) / HP_NT);
     // word buffer: [0] error flag and kept count, then per column parity and
