@@ -176,7 +176,9 @@ typedef struct {
                                 previous largest residual estimate r (4 while r > 1600
                                 2^-28, 5 while r > 1600 2^-35, else 6); 4, 5 or 6: fixed.
                                 S digits are exact to about 2^-7S of the row and column
-                                scales of A and V */
+                                scales of A and V.  The iteration stops at tol only after
+                                an iteration whose products took six digits (eig_partial,
+                                eig_general, svd_partial) */
 } ofrr_plan;
 
 typedef struct {

@@ -305,6 +305,9 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans, const cha
 // 2^-42 of the row and column scales; 5: 15 pairs, 2^-35; 4: 10 pairs, 2^-28)
 void product_i8s(Context *ctx, const SlicedA &sa, int32_t b, const double *V, int64_t ldv, double *W,
                  int64_t ldw, SlabOut *defer = nullptr, int digits = 6);
+// digits per side for a sliced FP64 iteration from the largest residual
+// estimate of the iteration before it (solver.cpp)
+int i8_digits_for(double emax);
 
 // k_hessenberg.hip
 // Returns the kept count (after waiting for the sweep; a timed-out wait

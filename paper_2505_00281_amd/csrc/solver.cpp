@@ -201,6 +201,9 @@ double switch_level(const ofrr_plan *plan, const Phase &ph) {
     return -1.0;
 }
 
+
+}  // namespace
+
 // Digits per side for a sliced FP64 iteration, from the largest wanted
 // residual estimate of the iteration before it.  A product with S digits
 // per side is exact up to about 2^-7S of the row and column scales (four:
@@ -216,8 +219,6 @@ int i8_digits_for(double emax) {
     if (emax > 1600.0 * std::ldexp(1.0, -35)) return 5;
     return 6;
 }
-
-}  // namespace
 
 ofrr_status eig_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int32_t basis,
                              ofrr_which which, const ofrr_plan *plan, const double *X0,

@@ -123,13 +123,22 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
         colmajor_to_rowmajor(ctx, n, basis, src, n, master(), Vb, ld);
     }
 
+    // digits per side of the tail's digit-plane products: chosen at the start
+    // of each tail iteration from the previous largest residual estimate (as
+    // for the eigenproblem), so the first tail iterations take fewer
+    int dig = 6;
+    double emax_prev = INFINITY;
+    auto tail_digits = [&]() {
+        return plan->tail_digits == 0 ? i8_digits_for(emax_prev) : plan->tail_digits;
+    };
     // W (rows x bc) = op(A) * X (cols x bc), phase arithmetic
     auto product = [&](int trans, const void *X, void *Wout, int32_t bc) {
         ++products;
         const int64_t rows = trans ? n : m, cols = trans ? m : n;
         if (phases[pi] == OFRR_F64) {
             if (sliced)
-                product_i8s(ctx, trans ? A_cols : A_rows, bc, (const double *)X, ld, (double *)Wout, ld);
+                product_i8s(ctx, trans ? A_cols : A_rows, bc, (const double *)X, ld, (double *)Wout, ld, nullptr,
+                            dig);
             else
                 product_f64(ctx, A, trans, bc, (const double *)X, ld, (double *)Wout, ld);
         } else if (phases[pi] == OFRR_F8E4M3) {
@@ -178,6 +187,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
     const bool debug = std::getenv("OFRR_DEBUG") != nullptr;
     while (true) {
         ofrr_dtype mt = master();  // refreshed below if the phase changes
+        dig = (sliced && pi + 1 == phases.size()) ? tail_digits() : 6;
         product(0, Vb, T1, bv);
         if (have_prev) {
             col_resid(ctx, mt, m, k, T1, Ut, ld, sig, anorm, est);
@@ -186,8 +196,11 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
             double emax = 0.0;
             for (double v : eh) emax = std::max(emax, std::isfinite(v) ? v : INFINITY);
             if (!std::isfinite(emax)) fail(OFRR_ERR_NUMERIC, "svd: non-finite residual estimate");
+            emax_prev = emax;
             const bool last = pi + 1 == phases.size();
-            if (last && plan->tol > 0 && emax <= plan->tol) break;
+            // (an estimate from products with fewer than six digits is
+            // followed by an iteration with six before the loop may stop)
+            if (last && plan->tol > 0 && emax <= plan->tol && dig == 6) break;
             if (!last) {
                 const bool stalled = stall_det.push(emax);
                 if (stalled || (plan->switch_resid > 0 && emax <= plan->switch_resid)) {
@@ -200,6 +213,7 @@ ofrr_status svd_partial_impl(Context *ctx, const ofrr_matrix *A, int32_t k, int3
                     ++pi;
                     stall_det.reset();
                     mt = master();
+                    dig = sliced && pi + 1 == phases.size() ? tail_digits() : 6;
                     product(0, Vb, T1, bv);
                 }
             }
