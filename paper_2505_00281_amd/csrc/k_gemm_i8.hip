@@ -125,6 +125,55 @@ __global__ __launch_bounds__(256) void k_slice_rows(const TA *__restrict__ A, in
     }
 }
 
+// Row slicing of a column-major A (op(A) = A): one workgroup per 64 rows, a
+// lane per row, so every load of a wavefront is 64 consecutive entries of one
+// column (one row per workgroup would touch a cache line per entry).  The
+// four wavefronts take interleaved 16-column chunks; the row maxima meet in
+// LDS; the planes and exponents are those of k_slice_rows.
+template <class TA>
+__global__ __launch_bounds__(256) void k_slice_rows_cm(const TA *__restrict__ A, int64_t lda, int64_t m,
+                                                       int64_t mpad, int64_t kdim, int64_t kpad,
+                                                       int8_t *__restrict__ planes, int64_t plane_stride,
+                                                       int32_t *__restrict__ ex) {
+    __shared__ double red[4][64];
+    const int t = threadIdx.x, r = t & 63, w = t >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + r;
+    // row i clamped into A and columns clamped into [0, kdim): every load
+    // is unconditional
+    const TA *a = A + (i < m ? i : m - 1);
+    auto at = [&](int64_t k) -> double { return (double)a[(k < kdim ? k : kdim - 1) * lda]; };
+    double amax = 0.0;
+    for (int64_t k0 = (int64_t)w * 16; k0 < kdim; k0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = at(k0 + q);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) amax = fmax(amax, fabs(v[q]));
+    }
+    red[w][r] = i < m ? amax : 0.0;
+    __syncthreads();
+    amax = fmax(fmax(red[0][r], red[1][r]), fmax(red[2][r], red[3][r]));
+    const int e = exp_bound(amax);
+    if (w == 0 && i < mpad) ex[i] = e;
+    if (i >= mpad) return;
+    for (int64_t k0 = (int64_t)w * 16; k0 < kpad; k0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = at(k0 + q);
+        int8_t d[I8_S][16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            int8_t dq[I8_S];
+            digits_of((i < m && k0 + q < kdim) ? v[q] : 0.0, e, dq);
+#pragma unroll
+            for (int s = 0; s < I8_S; ++s) d[s][q] = dq[s];
+        }
+#pragma unroll
+        for (int s = 0; s < I8_S; ++s)
+            *(v4i_t *)(planes + s * plane_stride + plane_off(i, k0, mpad)) = __builtin_bit_cast(v4i_t, d[s]);
+    }
+}
+
 constexpr int VM_COPIES = 4;    // copies of the merged column maxima
 constexpr int VM_STRIDE = 4096;  // entries per copy (b <= 4096)
 
@@ -394,10 +443,16 @@ SlicedA slice_matrix_i8(Context *ctx, const ofrr_matrix *A, int trans, const cha
     };
     const float *af = (const float *)A->values;
     const double *ad = (const double *)A->values;
+    // A's rows (column-major A): 64 rows per workgroup, mpad a multiple of 64
+    static_assert(I8_BM % 64 == 0, "row slicing assumes mpad is a multiple of 64");
+    auto go_cm = [&](auto kern, auto p) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)(s.mpad / 64)), dim3(256), 0, ctx->stream, p, A->ld, s.m, s.mpad,
+                           s.kdim, s.kpad, s.planes, s.plane_stride, s.ex);
+    };
     if (A->dtype == OFRR_F32) {
-        if (trans) go(k_slice_rows<float, true>, af); else go(k_slice_rows<float, false>, af);
+        if (trans) go(k_slice_rows<float, true>, af); else go_cm(k_slice_rows_cm<float>, af);
     } else {
-        if (trans) go(k_slice_rows<double, true>, ad); else go(k_slice_rows<double, false>, ad);
+        if (trans) go(k_slice_rows<double, true>, ad); else go_cm(k_slice_rows_cm<double>, ad);
     }
     OFRR_HIP(hipGetLastError());
     return s;
