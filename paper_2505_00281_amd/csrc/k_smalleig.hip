@@ -2615,37 +2615,46 @@ __global__ __launch_bounds__(256) void k_tri_cols(const double *__restrict__ Lc,
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= m) return;
     double *x = X + (int64_t)c * n;
-    double xr[4], lc[4], ln[4];
+    double xr[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int r = lane + 64 * u;
         xr[u] = r < n ? x[r] : 0.0;
     }
-    const int j0 = FWD ? 0 : n - 1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int r = lane + 64 * u;
-        lc[u] = r < n ? Lc[r + (int64_t)j0 * n] : 0.0;
-    }
-    for (int s = 0; s < n; ++s) {
-        const int j = FWD ? s : n - 1 - s;
-        // the next step's column of the factor, loaded ahead
-        const int jn = FWD ? (j + 1 < n ? j + 1 : j) : (j > 0 ? j - 1 : j);
+    // the factor's columns (and reciprocal diagonals) two steps ahead, loaded
+    // unconditionally from clamped rows (a per-lane guard would wait for
+    // every load); rows past n are never used
+    auto col = [&](int j, double (&d)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r = lane + 64 * u;
-            ln[u] = r < n ? Lc[r + (int64_t)jn * n] : 0.0;
+            d[u] = Lc[(r < n ? r : n - 1) + (int64_t)j * n];
         }
+    };
+    auto ahead = [&](int j, int d) { return FWD ? (j + d < n ? j + d : n - 1) : (j - d > 0 ? j - d : 0); };
+    const int j0 = FWD ? 0 : n - 1;
+    double lc[4], l1[4], l2[4];
+    col(j0, lc);
+    col(ahead(j0, 1), l1);
+    double ic = inv[j0], i1 = inv[ahead(j0, 1)];
+    for (int s = 0; s < n; ++s) {
+        const int j = FWD ? s : n - 1 - s;
+        const int j2 = ahead(j, 2);
+        col(j2, l2);
+        const double i2 = inv[j2];
         const int ju = j >> 6;
         const double own = ju == 0 ? xr[0] : (ju == 1 ? xr[1] : (ju == 2 ? xr[2] : xr[3]));
-        const double xj = readlane_f64(own, j & 63) * inv[j];
+        const double xj = readlane_f64(own, j & 63) * ic;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r = lane + 64 * u;
             if (r == j) xr[u] = xj;
             else if (FWD ? (r > j && r < n) : (r < j)) xr[u] = fma(-lc[u], xj, xr[u]);
-            lc[u] = ln[u];
+            lc[u] = l1[u];
+            l1[u] = l2[u];
         }
+        ic = i1;
+        i1 = i2;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
